@@ -1,0 +1,310 @@
+"""Pins of the CPU oracle against the paper and against mathematics that does not
+come from the oracle's own code (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_02783_amd import workloads as wl
+from tests import oracle_helpers as hp
+
+
+# ---------------------------------------------------------------- FD weights
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10, 12])
+def test_fd_weights_match_taylor_solution(order):
+    """Closed form == the unique symmetric stencil exact on polynomials."""
+    np.testing.assert_allclose(oracle.fd_second_derivative(order), hp.taylor_weights(order),
+                               rtol=1e-12, atol=1e-13)
+
+
+def test_fd_weights_textbook_values():
+    np.testing.assert_allclose(oracle.fd_second_derivative(2), [-2.0, 1.0])
+    np.testing.assert_allclose(oracle.fd_second_derivative(4), [-5 / 2, 4 / 3, -1 / 12])
+
+
+@pytest.mark.parametrize("order", [2, 4, 8, 12])
+def test_fd_dispersion_monotone_and_spectral(order):
+    th = np.linspace(0, math.pi, 2001)
+    s = oracle.fd_dispersion(order, th)
+    assert np.all(np.diff(s) > 0)              # one right-mover per open mode
+    small = np.linspace(1e-3, 0.3, 50)
+    # consistent of order 2M: s(theta) - theta^2 = O(theta^(2M+2))
+    err = np.abs(oracle.fd_dispersion(order, small) - small ** 2)
+    assert np.all(err <= 10.0 * small ** (order + 2) + 1e-14)
+
+
+# ------------------------------------------------- Laplacian + Bloch halos
+
+@pytest.mark.parametrize("na,nb,order,k", [(5, 4, 4, (0.37, -0.81)), (7, 6, 12, (0.2, 0.45)),
+                                            (2, 3, 6, (0.9, -0.4)), (1, 4, 8, (0.3, 0.1))])
+def test_lateral_spectrum_closed_form(na, nb, order, k):
+    """Eigenvalues of -1/2 L_k on one z-periodic plane (kz = 0) are
+    {eps_a(ma) + eps_b(mb)}; covers multi-wrap stencils (radius >= N)."""
+    p = wl.Problem(na, nb, 1, 0.45, 0.55, 0.5, order, np.zeros(na * nb), wl.Projectors.empty(),
+                   np.zeros(1), np.zeros(1), np.zeros((1, 2)), np.zeros(1))
+    h = oracle.hamiltonian_dense(p, k, kz=0.0)
+    np.testing.assert_allclose(h, h.conj().T, atol=1e-13)
+    ev = np.sort(np.linalg.eigvalsh(h))
+    ref = np.sort(hp.lateral_energies(na, nb, p.ha, p.hb, k, order))
+    np.testing.assert_allclose(ev, ref, atol=1e-11 * max(1.0, ref.max()))
+
+
+@pytest.mark.parametrize("case", [dict(na=4, nb=3, nz=20, order=4, k=(0.0, 0.0)),
+                                  dict(na=3, nb=4, nz=16, order=12, k=(0.7, -1.1)),
+                                  dict(na=2, nb=2, nz=14, order=8, k=(1.3, 0.4))])
+def test_free_electron_separable_identity(case):
+    """V = 0, no projectors: T_3D(E,k) = sum over lateral modes of the 1D chain
+    transmission at E - eps_perp (exact for any CAP and any k)."""
+    na, nb, nz, order, k = case["na"], case["nb"], case["nz"], case["order"], case["k"]
+    h = 0.5
+    p = wl.free_electron_slab(na=na, nb=nb, nz=nz, h=h, order=order, ramp=5, peak=0.9)
+    es = np.array([0.11, 0.53, 1.37, 2.9])
+    t3 = oracle.transmission(p, es, k)["T_LR"]
+    ep = hp.lateral_energies(na, nb, h, h, k, order)
+    for e, t in zip(es, t3):
+        ref = sum(hp.t1d(e - x, nz, h, order, p.gamma_l, p.gamma_r) for x in ep)
+        assert abs(t - ref) <= 1e-10 * max(1.0, ref)
+
+
+def test_long_cap_1d_counts_one_channel():
+    """A long gentle CAP absorbs without reflection: T -> 1 inside the band and
+    0 outside it (the factor 4 normalisation and the sign of i Gamma)."""
+    p = wl.free_electron_slab(na=1, nb=1, nz=320, h=0.5, order=4, ramp=80, peak=0.3)
+    top = hp.symbol(4, math.pi) / (2 * 0.25)
+    es = np.array([0.05, 0.3, 1.0, 3.0, top + 0.5])
+    t = oracle.transmission(p, es, (0.0, 0.0))["T_LR"]
+    np.testing.assert_allclose(t[:4], 1.0, atol=3e-2)
+    assert abs(t[1] - 1.0) < 1e-4 and abs(t[2] - 1.0) < 1e-3
+    assert t[4] < 1e-6
+
+
+def test_long_cap_3d_open_mode_count():
+    """T(E,k) approaches the closed-form number of open lateral modes."""
+    na = nb = 2
+    p = wl.free_electron_slab(na=na, nb=nb, nz=320, h=0.5, order=4, ramp=80, peak=0.3)
+    k = (0.31, -0.47)
+    es = np.linspace(0.1, 6.0, 12)
+    t = oracle.transmission(p, es, k)["T_LR"]
+    checked = 0
+    for e, tt in zip(es, t):
+        nopen, ep = hp.open_channels(e, na, nb, 0.5, 0.5, 0.5, k, 4)
+        top = hp.symbol(4, math.pi) / (2 * 0.25)
+        gap = np.min(np.abs(np.concatenate([e - ep, e - ep - top])))
+        if gap < 0.1:
+            continue
+        assert abs(tt - nopen) < 2e-2, (e, tt, nopen)
+        checked += 1
+    assert checked >= 6
+
+
+# ------------------------------------------------------------ invariants
+
+@pytest.fixture(scope="module")
+def rand_prob():
+    return hp.random_problem(np.random.default_rng(7))
+
+
+def test_t_lr_equals_t_rl_and_trace_form(rand_prob):
+    k = (0.9, -0.4)
+    for e in (-0.4, 0.3, 1.7):
+        r = oracle.transmission(rand_prob, [e], k)
+        tf = oracle.trace_forms(rand_prob, e, k)
+        assert r["T_LR"][0] >= 0
+        assert abs(r["T_LR"][0] - r["T_RL"][0]) <= 1e-12 * max(1, r["T_LR"][0])
+        assert abs(r["T_LR"][0] - tf["T"]) <= 1e-12 * max(1, tf["T"])
+
+
+def test_time_reversal_k_minus_k(rand_prob):
+    """H_-k = conj(H_k) makes T(-k) = T(k) with no spatial symmetry assumed
+    (the paper derives the +-k degeneracy perturbatively; for T it is exact)."""
+    k = np.array([0.9, -0.4])
+    h1 = oracle.hamiltonian_dense(rand_prob, k)
+    h2 = oracle.hamiltonian_dense(rand_prob, -k)
+    np.testing.assert_allclose(h2, h1.conj(), atol=1e-14)
+    es = [0.3, 1.1]
+    t1 = oracle.transmission(rand_prob, es, k)["T_LR"]
+    t2 = oracle.transmission(rand_prob, es, -k)["T_LR"]
+    np.testing.assert_allclose(t1, t2, rtol=1e-11, atol=1e-13)
+
+
+def test_reciprocal_lattice_shift(rand_prob):
+    p = rand_prob
+    k = np.array([0.9, -0.4])
+    g = np.array([2 * math.pi / p.la, -2 * math.pi / p.lb])
+    t1 = oracle.transmission(p, [0.3], k)["T_LR"]
+    t2 = oracle.transmission(p, [0.3], k + g)["T_LR"]
+    np.testing.assert_allclose(t1, t2, rtol=1e-11, atol=1e-13)
+
+
+def test_cap_sum_rule(rand_prob):
+    """G - G^+ = -2i G Gamma G^+ gives 4Tr[G_L G G_R G^+] = -4 Im Tr[G_L G] - 4Tr[G_L G G_L G^+]."""
+    for e in (0.2, 0.9):
+        tf = oracle.trace_forms(rand_prob, e, (0.5, 0.2))
+        assert abs(tf["T"] - (tf["minus4_im_tr_GLG"] - tf["T_LL"])) <= 1e-11 * max(1, tf["T"])
+
+
+def test_hamiltonian_hermitian_and_apply_consistent(rand_prob):
+    k = (0.6, 0.25)
+    h = oracle.hamiltonian_dense(rand_prob, k)
+    np.testing.assert_allclose(h, h.conj().T, atol=1e-13)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((rand_prob.n, 3)) + 1j * rng.standard_normal((rand_prob.n, 3))
+    y1 = oracle.system_matrix(rand_prob, k, 0.4) @ x
+    y2 = oracle.apply_system(rand_prob, k, 0.4, x)
+    np.testing.assert_allclose(y1, y2, atol=1e-12)
+
+
+def test_green_columns_solve_the_system(rand_prob):
+    k = (0.6, 0.25)
+    cols = [0, 17, rand_prob.n - 1]
+    g = oracle.green_columns(rand_prob, 0.4, k, cols)
+    b = np.zeros((rand_prob.n, 3), complex)
+    b[cols, np.arange(3)] = 1
+    assert np.max(oracle.residual_norms(rand_prob, k, 0.4, g, b)) < 1e-12
+
+
+# ----------------------------------------------- projectors and images
+
+def test_one_point_projector_is_a_local_potential():
+    """h^3 E_p |beta><beta| with beta = h^-3/2 at one point adds E_p to V there."""
+    rng = np.random.default_rng(11)
+    p = hp.random_problem(rng, nproj=0)
+    h3 = p.ha * p.hb * p.hz
+    i0, ep = 37, 0.77
+    proj = wl.Projectors(np.array([0, 1], np.int32), np.array([i0], np.int32),
+                         np.array([[1, -1]], np.int8), np.array([1 / math.sqrt(h3)]), np.array([ep]))
+    v2 = p.v.copy()
+    v2[i0] += ep
+    k = (0.4, 0.8)
+    t1 = oracle.transmission(p.with_(proj=proj), [0.2, 0.9], k)["T_LR"]
+    t2 = oracle.transmission(p.with_(v=v2), [0.2, 0.9], k)["T_LR"]
+    np.testing.assert_allclose(t1, t2, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("k", [(0.0, 0.0), (0.45, -0.3)])
+def test_supercell_folding(k):
+    """A supercell doubled along a at k carries the small cell's k and k + pi/L_a:
+    T_2(k) = T_1(k) + T_1(k + pi/L_a).  Fixes the sign of the image phases of
+    the projectors relative to the Laplacian wrap."""
+    rng = np.random.default_rng(5)
+    p = hp.random_problem(rng, na=3, nb=2, nz=14, nproj=3, vscale=0.3)
+    p2 = hp.double_along_a(p)
+    e = [0.35, 1.2]
+    t_small = (oracle.transmission(p, e, k)["T_LR"]
+               + oracle.transmission(p, e, (k[0] + math.pi / p.la, k[1]))["T_LR"])
+    t_super = oracle.transmission(p2, e, k)["T_LR"]
+    np.testing.assert_allclose(t_super, t_small, rtol=1e-10, atol=1e-12)
+
+
+def test_supercell_detects_flipped_image_phase():
+    """Negative control: flipping the image sign in the small cell breaks folding."""
+    rng = np.random.default_rng(5)
+    p = hp.random_problem(rng, na=3, nb=2, nz=14, nproj=3, vscale=0.3)
+    p2 = hp.double_along_a(p)
+    bad = wl.Projectors(p.proj.offs, p.proj.pt, (-p.proj.img).astype(np.int8), p.proj.beta,
+                        p.proj.ekb)
+    pb = p.with_(proj=bad)
+    k = (0.45, -0.3)
+    t_small = (oracle.transmission(pb, [0.35], k)["T_LR"]
+               + oracle.transmission(pb, [0.35], (k[0] + math.pi / p.la, k[1]))["T_LR"])
+    t_super = oracle.transmission(p2, [0.35], k)["T_LR"]
+    assert abs(t_super[0] - t_small[0]) > 1e-6
+
+
+# ------------------------------------------------ bulk Bloch-mode counting
+
+def _chain_with_periodic_cell(period, nper, v_cell, ramp, peak, h=0.5, na=1, nb=1, order=4,
+                              proj_cell=None):
+    nz = period * nper
+    v = np.tile(v_cell.reshape(period, -1), (nper, 1)).reshape(-1)
+    gl = np.zeros(nz)
+    gl[:ramp] = peak * ((ramp - np.arange(ramp)) / ramp) ** 2
+    gr = gl[::-1].copy()
+    proj = wl.Projectors.empty()
+    if proj_cell is not None:
+        pc = proj_cell
+        npl = na * nb * period
+        offs = [0]; pts = []; imgs = []; betas = []; ekb = []
+        for c in range(nper):
+            for q in range(pc.nproj):
+                sl = slice(pc.offs[q], pc.offs[q + 1])
+                pts.append(pc.pt[sl] + c * npl); imgs.append(pc.img[sl]); betas.append(pc.beta[sl])
+                ekb.append(pc.ekb[q]); offs.append(offs[-1] + pc.offs[q + 1] - pc.offs[q])
+        proj = wl.Projectors(np.array(offs, np.int32), np.concatenate(pts).astype(np.int32),
+                             np.concatenate(imgs), np.concatenate(betas), np.array(ekb))
+    return wl.Problem(na, nb, nz, h, h, h, order, v, proj, gl, gr, np.zeros((1, 2)), np.zeros(1))
+
+
+def _right_movers(cell, k, e, nkz=4000):
+    """M(E) = (number of crossings of E by the bands eps_n(kz) over the zone)/2."""
+    lz = cell.nz * cell.hz
+    kzs = np.linspace(-math.pi / lz, math.pi / lz, nkz, endpoint=False)
+    bands = np.array([np.linalg.eigvalsh(oracle.hamiltonian_dense(cell, k, kz=kz)) for kz in kzs])
+    s = np.sign(bands - e)
+    crossings = np.sum(s != np.roll(s, -1, axis=0))
+    return crossings / 2.0, bands
+
+
+def test_bulk_mode_count_1d_periodic_potential():
+    period = 8
+    z = np.arange(period)
+    v_cell = 0.6 * np.cos(2 * math.pi * z / period)
+    cell = wl.Problem(1, 1, period, 0.5, 0.5, 0.5, 4, v_cell, wl.Projectors.empty(),
+                      np.zeros(period), np.zeros(period), np.zeros((1, 2)), np.zeros(1))
+    chain = _chain_with_periodic_cell(period, 70, v_cell, ramp=200, peak=0.25)
+    es = np.linspace(-0.2, 1.6, 19)
+    t = oracle.transmission(chain, es, (0.0, 0.0))["T_LR"]
+    _, bands = _right_movers(cell, (0.0, 0.0), 0.0, nkz=400)
+    edges = np.concatenate([bands.min(0), bands.max(0)])
+    n_checked = n_gap = 0
+    for e, tt in zip(es, t):
+        if np.min(np.abs(edges - e)) < 0.03:
+            continue
+        m, _ = _right_movers(cell, (0.0, 0.0), e, nkz=400)
+        assert abs(tt - m) < 2e-3, (e, tt, m)
+        n_checked += 1
+        n_gap += m == 0
+    assert n_checked >= 10 and n_gap >= 1
+
+
+def test_bulk_mode_count_3d_with_projectors():
+    """Periodic chain with a lateral grid, a potential and projectors inside each
+    period: T -> number of right-moving Bloch modes of the same H."""
+    rng = np.random.default_rng(21)
+    na = nb = 2
+    period = 6
+    npl = na * nb * period
+    v_cell = 0.3 * rng.standard_normal(npl)
+    h = 0.5
+    h3 = h ** 3
+    offs = [0]; pts = []; imgs = []; betas = []
+    for q in range(2):
+        # entries in the interior planes 1..4 so no sphere crosses a period boundary
+        cand = np.arange(na * nb, na * nb * (period - 1))
+        pt = rng.choice(cand, size=5, replace=False)
+        b = rng.standard_normal(5)
+        b /= math.sqrt(h3 * np.sum(b * b))
+        pts.append(pt); imgs.append(rng.integers(-1, 2, (5, 2))); betas.append(b)
+        offs.append(offs[-1] + 5)
+    pc = wl.Projectors(np.array(offs, np.int32), np.concatenate(pts).astype(np.int32),
+                       np.concatenate(imgs).astype(np.int8), np.concatenate(betas),
+                       np.array([0.4, -0.3]))
+    k = (0.35, -0.6)
+    cell = wl.Problem(na, nb, period, h, h, h, 4, v_cell, pc, np.zeros(period), np.zeros(period),
+                      np.zeros((1, 2)), np.zeros(1))
+    chain = _chain_with_periodic_cell(period, 60, v_cell, ramp=150, peak=0.25, na=na, nb=nb,
+                                      proj_cell=pc)
+    es = np.linspace(0.2, 2.4, 9)
+    t = oracle.transmission(chain, es, k)["T_LR"]
+    _, bands = _right_movers(cell, k, 0.0, nkz=300)
+    edges = np.concatenate([bands.min(0), bands.max(0)])
+    checked = 0
+    for e, tt in zip(es, t):
+        if np.min(np.abs(edges - e)) < 0.05:
+            continue
+        m, _ = _right_movers(cell, k, e, nkz=300)
+        assert abs(tt - m) < 1e-2 * max(1, m), (e, tt, m)
+        checked += 1
+    assert checked >= 4
