@@ -1,0 +1,145 @@
+/*
+ * rst.h -- C ABI of librst, the MI355X (gfx950) Bloch-CAP transmission library.
+ *
+ * Computes the per-spin transmission of a lateral-periodic real-space structure,
+ *
+ *     T(E, k) = 4 Tr[ Gamma_L G Gamma_R G^+ ],   G = (E - H_k + i(Gamma_L + Gamma_R))^-1,
+ *
+ * (paper Sec. II.A: transmission equation, retarded Green's function and the
+ * Gaussian-CAP equation; the factor 4 makes one open channel count as 1) by
+ * Krylov solves of A x = sqrt(Gamma_R,i) e_i over the grid points i of the
+ * right absorbing region, one solve per column, for one lateral Bloch vector k
+ * (Bloch-form equation) at a time.  The k-average of T (end of Sec. II.A) is
+ * left to the caller.
+ *
+ * Hamiltonian (Hartree atomic units):
+ *     H_k = -1/2 L_k + diag(V) + h^3 sum_p E_p |beta_k,p><beta_k,p|
+ *   L_k : central finite-difference Laplacian of even order 2M (2..12) on an
+ *         orthorhombic grid; a lateral neighbour that leaves the cell across the
+ *         +a face (resp. -a) is the wrapped point times exp(+i k_a L_a)
+ *         (resp. exp(-i k_a L_a)), same for b: phi(r + R) = exp(i k.R) phi(r);
+ *         psi = 0 outside the planes 0..Nz-1 along z (transport axis).
+ *   beta_k,p(r) = sum over table entries e of projector p at r of
+ *         beta_e exp(+i k.R_e), R_e the lateral image the entry comes from.
+ *   Gamma_L, Gamma_R : functions of z only (constant in the lateral plane).
+ *
+ * Grid index i = ia + Na*(ib + Nb*iz) (a fastest, z slowest).  Vectors passed
+ * as device pointers are complex, interleaved (re, im), with the column index
+ * fastest: element (i, c) of an (n x ncol) block is at [2*(i*ncol + c)].
+ *
+ * Conventions
+ *  - Host arrays given to rst_set_* are copied; the caller keeps ownership.
+ *  - Device pointers (names ending in _dev) are borrowed for the duration of
+ *    the call and used on the context's stream; the call returns after the
+ *    stream has finished with them.
+ *  - Outputs are caller-allocated.
+ *  - Status < 0: the call failed and wrote no output.  Status > 0: the call
+ *    completed and wrote its outputs, with the condition recorded in rst_stats.
+ *  - Setters invalidate dependent state: rst_set_grid clears potential,
+ *    projectors, CAPs and k.  Calling out of order returns RST_ESTATE.
+ *  - A context is not thread-safe.  rst_last_error() describes the last failure.
+ */
+#ifndef RST_H
+#define RST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rst_ctx rst_ctx;
+
+typedef enum {
+  RST_OK = 0,
+  RST_ENOCONV = 1,        /* completed; some columns did not reach the tolerance */
+  RST_EINVAL = -1,        /* invalid argument */
+  RST_ESTATE = -2,        /* call out of order (e.g. no grid yet) */
+  RST_ENOMEM = -3,        /* device allocation failed */
+  RST_EDEVICE = -4,       /* HIP runtime error */
+  RST_EUNSUPPORTED = -5   /* valid but not supported by the GPU kernels */
+} rst_status;
+
+typedef enum { RST_BICGSTAB = 0 } rst_method;
+typedef enum { RST_FP64 = 0, RST_FP32_REFINE = 1 } rst_precision;
+typedef enum { RST_DIR_LR = 0, RST_DIR_RL = 1 } rst_direction;
+
+/* Solver options.  rst_default_solver() fills the defaults. */
+typedef struct {
+  int method;        /* rst_method */
+  int precision;     /* rst_precision; RST_FP32_REFINE: FP32 stencil/projector applies inside an FP64 refinement loop */
+  double tol;        /* stop when the FP64 true residual ||b - A x|| <= tol ||b|| per column (default 1e-10) */
+  int max_iter;      /* BiCGSTAB iterations per column (default 20000) */
+  int col_block;     /* columns solved together by one workgroup; 0 = automatic */
+  int threads;       /* workgroup size (multiple of 64, <= 1024); 0 = automatic */
+  int direction;     /* RST_DIR_LR: columns in the right CAP, T accumulated on the left (default);
+                        RST_DIR_RL: the reverse.  Both give the same T (exact identity). */
+  double inner_tol;  /* RST_FP32_REFINE: relative tolerance of each FP32 inner solve (default 1e-5) */
+  int max_outer;     /* RST_FP32_REFINE: refinement steps (default 30) */
+} rst_solver_opts;
+
+/* Statistics of the last rst_transmission / rst_solve_columns call. */
+typedef struct {
+  int64_t columns;          /* column solves performed */
+  int64_t columns_unconverged;
+  int64_t iterations_total; /* BiCGSTAB iterations summed over columns */
+  int32_t iterations_max;
+  int32_t restarts_total;   /* breakdown restarts */
+  double max_rel_residual;  /* largest FP64 true relative residual */
+  double kernel_ms;         /* device time of the solver kernel(s) */
+  double bytes_algorithmic; /* algorithmic HBM bytes of the Krylov sweeps (see DESIGN) */
+} rst_stats;
+
+void rst_default_solver(rst_solver_opts *opts);
+
+/* Creates a context on HIP device `hip_device`.  `hip_stream` (a hipStream_t)
+ * may be NULL, in which case the context creates and owns a stream. */
+rst_status rst_create(rst_ctx **out, int hip_device, void *hip_stream);
+void rst_destroy(rst_ctx *ctx);
+const char *rst_last_error(const rst_ctx *ctx);
+
+/* Grid of na x nb x nz points with spacings ha, hb, hz (bohr); fd_order even
+ * in 2..12.  The GPU kernels require na > fd_order/2 and nb > fd_order/2
+ * (RST_EUNSUPPORTED otherwise). */
+rst_status rst_set_grid(rst_ctx *ctx, int na, int nb, int nz, double ha, double hb, double hz,
+                        int fd_order);
+
+/* Local potential V, n = na*nb*nz doubles (Ha), host memory, copied. */
+rst_status rst_set_potential(rst_ctx *ctx, const double *v);
+
+/* Separable projectors in compressed rows over projectors: entries
+ * offs[p]..offs[p+1]-1 of projector p.  pt[e] is a grid index, img[2e],
+ * img[2e+1] the lateral image (ia, ib) the entry comes from, beta[e] its real
+ * value; e_kb[p] the projector energy (Ha).  nproj may be 0.  Copied. */
+rst_status rst_set_projectors(rst_ctx *ctx, int nproj, const int32_t *offs, const int32_t *pt,
+                              const int8_t *img, const double *beta, const double *e_kb);
+
+/* CAP strengths Gamma_L(iz), Gamma_R(iz) >= 0 (nz doubles each, Ha), copied.
+ * The solve columns of RST_DIR_LR are all grid points of the planes with
+ * Gamma_R > 0 (RST_DIR_RL: Gamma_L > 0). */
+rst_status rst_set_abc(rst_ctx *ctx, const double *gamma_l_z, const double *gamma_r_z);
+
+/* Lateral Bloch vector (bohr^-1) along a and b. */
+rst_status rst_set_k(rst_ctx *ctx, double ka, double kb);
+
+rst_status rst_set_solver(rst_ctx *ctx, const rst_solver_opts *opts);
+
+/* T(E_j, k) for j < n_e into T_out (host, caller-allocated, n_e doubles).
+ * Returns RST_ENOCONV if any column missed the tolerance (T is still written). */
+rst_status rst_transmission(rst_ctx *ctx, int n_e, const double *energies, double *T_out,
+                            rst_stats *stats);
+
+/* Test hook: y = (E - H_k + i Gamma) x for an (n x ncol) complex128 block.
+ * x_dev and y_dev are distinct device buffers of n*ncol*16 bytes. */
+rst_status rst_apply_h(rst_ctx *ctx, double energy, const void *x_dev, void *y_dev, int ncol);
+
+/* Green's function columns: x_dev[:, j] = G e_{col[j]} (complex128, n x ncol,
+ * device).  col holds ncol grid indices (host). */
+rst_status rst_solve_columns(rst_ctx *ctx, double energy, int ncol, const int64_t *col,
+                             void *x_dev, rst_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RST_H */

@@ -1,0 +1,322 @@
+// rst_kernels.hpp -- gfx950 device code of librst.
+//
+// One workgroup owns a block of `cw` solve columns for the whole BiCGSTAB solve
+// of A x = b, A = E - H_k + i Gamma (paper Sec. II.A), and streams the grid
+// plane by plane along z:
+//   * z-neighbours of the order-2M stencil come from a per-thread register
+//     queue of 2M+1 planes (each input value is loaded from HBM once per sweep);
+//   * lateral neighbours come from the current plane staged in LDS with a halo
+//     of M points on each lateral face, written once with the Bloch phase
+//     exp(+-i k_d L_d) already applied (Bloch-form equation: phi(r+R) = e^{ik.R} phi(r));
+//   * the separable projectors use per-plane chunked gathers of the output plane
+//     (deterministic fixed-order sums, no atomics) and a point-centric scatter
+//     fused into the stencil epilogue;
+//   * all BiCGSTAB vector updates are fused into the two stencil sweeps of an
+//     iteration (12 vector streams per iteration), dot products are reduced
+//     inside the workgroup, and the shadow residual is a unit vector so its
+//     inner products are single elements.
+// The column index is fastest in memory, so a wavefront's lanes read
+// consecutive columns / points and every load is a contiguous 16-byte access.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rst {
+
+constexpr int CW_MAX = 8;        // columns per workgroup
+constexpr int NM_MAX = 16;       // projectors per group (atom)
+constexpr int CHUNK = 8;         // entries per gather chunk
+constexpr int MAX_T = 512;       // workgroup size bound
+
+template <class R>
+struct alignas(2 * sizeof(R)) cx {
+  R x, y;
+};
+
+template <class R>
+__device__ __forceinline__ cx<R> mkc(R a, R b) {
+  cx<R> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <class R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return mkc(a.x + b.x, a.y + b.y); }
+template <class R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return mkc(a.x - b.x, a.y - b.y); }
+template <class R>
+__device__ __forceinline__ cx<R> cscale(cx<R> a, R s) { return mkc(a.x * s, a.y * s); }
+template <class R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+  return mkc(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+template <class R>
+__device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {
+  return mkc(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+template <class R>
+__device__ __forceinline__ R cnorm2(cx<R> a) { return a.x * a.x + a.y * a.y; }
+template <class R>
+__device__ __forceinline__ cx<double> to64(cx<R> a) { return mkc<double>((double)a.x, (double)a.y); }
+template <class R>
+__device__ __forceinline__ cx<R> fromd(cx<double> a) { return mkc<R>((R)a.x, (R)a.y); }
+__device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
+  double d = b.x * b.x + b.y * b.y;
+  return mkc((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ bool finite2(cx<double> a) { return isfinite(a.x) && isfinite(a.y); }
+
+// ---------------------------------------------------------------------------
+// Kernel arguments
+// ---------------------------------------------------------------------------
+
+struct Geo {
+  int na, nb, nz, P;     // P = na*nb points per plane
+  int pa, pb;            // padded plane dims na+2M, nb+2M
+  double cz[7], ca[7], cb[7];  // 1/2 c_j / h_d^2 for j = 1..M (index j)
+  double diag0;          // 1/2 c_0 (1/ha^2 + 1/hb^2 + 1/hz^2)
+  double pha_x, pha_y;   // exp(i k_a L_a)
+  double phb_x, phb_y;   // exp(i k_b L_b)
+};
+
+struct Proj {
+  int nproj, ngroup, nm;           // nm: stride of beta rows (max projectors per group)
+  int max_chunks;                  // max gather chunks in one plane
+  double h3;
+  const int* grp_pbase;            // [ngroup] first projector of the group
+  const int* grp_nm;               // [ngroup] projectors in the group
+  const double* ekb;               // [nproj]
+  const double* beta;              // [nent*nm] real projector values per entry
+  const double2* eph;              // [nent] exp(+i k.R_e) of the entry's lateral image
+  const int* ent_p;                // [nent] in-plane point index of the entry
+  const int* zc_offs;              // [nz+1] gather chunks per plane
+  const int4* chunks;              // (group, first entry, count, -)
+  const int* zg_offs;              // [nz+1] groups per plane
+  const int4* zgroups;             // (group, first chunk, end chunk) relative to the plane
+  const int* pe_offs;              // [n+1] entries touching each grid point
+  const int2* pe;                  // (group, entry)
+};
+
+struct SolveArgs {
+  Geo g;
+  Proj pj;
+  const double* V;          // [n]
+  const double* gz;         // [nz] Gamma_L + Gamma_R
+  const double* gdst;       // [nz] Gamma on the side where T is accumulated (nullable)
+  const double* gsrc;       // [nz] Gamma on the column side: rhs = sqrt(gsrc) e_i (null: rhs = e_i)
+  const double* energies;   // [ne]
+  const int64_t* cols;      // [ncols] source grid indices
+  int ncols, ne, cw, nblk, nitems;
+  double tol;
+  int max_iter;
+  void* ws;                 // per-workgroup vectors x, r, p, v, t (each n*cw complex of type R)
+  size_t ws_stride;         // elements of cx<R> per workgroup
+  double2* pws;             // per-workgroup projections: 5 arrays of nproj*cw
+  size_t pws_stride;
+  double* T_col;            // [ne*ncols] 4 sum_dst Gamma |x|^2 per column
+  int* iters;               // [ne*ncols]
+  int* restarts;            // [ne*ncols]
+  double* resid;            // [ne*ncols] final FP64 true relative residual
+  int* status;              // [ne*ncols] 0 converged, 1 not converged, 2 non-finite
+  int* counter;             // work queue head
+  double2* xout;            // optional export of x: (n x ncols) column-fastest
+};
+
+struct ApplyArgs {
+  Geo g;
+  Proj pj;
+  const double* V;
+  const double* gz;
+  double energy;
+  const double2* x;         // (n x ncol) column-fastest
+  double2* y;
+  int ncol, cw, nblk;
+  double2* pws;             // per-workgroup projection scratch (2 arrays nproj*cw)
+  size_t pws_stride;
+};
+
+// ---------------------------------------------------------------------------
+// Sweep modes
+// ---------------------------------------------------------------------------
+
+enum InMode { IN_INIT, IN_A, IN_RESTART, IN_B, IN_X, IN_EXT };
+enum OutMode { OUT_V, OUT_T, OUT_RES, OUT_EXT };
+
+// Per-column scalar state shared by the workgroup.
+struct ColState {
+  cx<double> alpha[CW_MAX], omega[CW_MAX], beta[CW_MAX], rho[CW_MAX], rho_new[CW_MAX];
+  cx<double> vj[CW_MAX], sj[CW_MAX], tj[CW_MAX], rj[CW_MAX];
+  cx<double> ts[CW_MAX];
+  double tt[CW_MAX], rr[CW_MAX], bb[CW_MAX], tacc[CW_MAX], bsc[CW_MAX], energy[CW_MAX];
+  double rmax[CW_MAX];
+  long long src[CW_MAX], j0[CW_MAX], rmax_idx[CW_MAX];
+  int state[CW_MAX];       // 0 active, 1 done, 2 failed, 3 padding
+  int iters[CW_MAX], restarts[CW_MAX];
+  int any_flag;
+  int item;
+};
+
+// Vectors of one workgroup.
+template <class R>
+struct Vecs {
+  cx<R>* x;
+  cx<R>* r;
+  cx<R>* p;
+  cx<R>* v;
+  cx<R>* t;
+};
+
+struct ProjArrays {
+  cx<double>* Pr;
+  cx<double>* Pp;
+  cx<double>* Pv;
+  cx<double>* Pt;
+  cx<double>* Px;
+};
+
+// LDS carve-up (dynamic shared memory)
+template <class R>
+struct Lds {
+  cx<R>* inpl0;        // padded lateral plane, double-buffered
+  cx<R>* inpl1;
+  cx<R>* outpl;        // output plane for the gathers (P*cw)
+  cx<double>* dco;     // scatter coefficients h^3 E_p (B^H u) (nproj*cw)
+  cx<double>* slots;   // gather chunk partials (max_chunks*nm*cw)
+  double* red;         // reduction scratch (blockDim*4)
+};
+
+// Dynamic LDS bytes: the reduction scratch (4 doubles per thread, used only
+// between sweeps) aliases the two lateral plane buffers.
+template <class R>
+__host__ __device__ inline size_t lds_bytes(int pa, int pb, int P, int nproj, int max_chunks, int nm,
+                                            int cw, int nthreads) {
+  size_t planes = 2 * (size_t)pa * pb * cw * sizeof(cx<R>);
+  size_t red = (size_t)nthreads * 4 * sizeof(double);
+  size_t off = planes > red ? planes : red;
+  off = (off + 15) & ~size_t(15);
+  if (nproj) off += (size_t)P * cw * sizeof(cx<R>);
+  off = (off + 15) & ~size_t(15);
+  off += (size_t)nproj * cw * sizeof(cx<double>);
+  off += (size_t)max_chunks * nm * cw * sizeof(cx<double>);
+  return off;
+}
+
+template <class R>
+__device__ __forceinline__ Lds<R> carve_lds(char* smem, const Geo& g, const Proj& pj, int cw,
+                                            int nthreads) {
+  Lds<R> L;
+  size_t plane = (size_t)g.pa * g.pb * cw;
+  L.inpl0 = reinterpret_cast<cx<R>*>(smem);
+  L.inpl1 = reinterpret_cast<cx<R>*>(smem) + plane;
+  L.red = reinterpret_cast<double*>(smem);
+  size_t planes = 2 * plane * sizeof(cx<R>);
+  size_t red = (size_t)nthreads * 4 * sizeof(double);
+  size_t off = planes > red ? planes : red;
+  off = (off + 15) & ~size_t(15);
+  L.outpl = reinterpret_cast<cx<R>*>(smem + off);
+  if (pj.nproj) off += (size_t)g.P * cw * sizeof(cx<R>);
+  off = (off + 15) & ~size_t(15);
+  L.dco = reinterpret_cast<cx<double>*>(smem + off);
+  off += (size_t)pj.nproj * cw * sizeof(cx<double>);
+  L.slots = reinterpret_cast<cx<double>*>(smem + off);
+  return L;
+}
+
+// Per-thread positions in the plane.
+template <int Q>
+struct Pos {
+  int p[Q];      // in-plane point, or -1
+  int li[Q];     // LDS interior index in the padded plane
+  unsigned char hal[Q];  // halo flags: 1 a-low, 2 a-high, 4 b-low, 8 b-high
+};
+
+// ---------------------------------------------------------------------------
+// Gather of the plane staged in L.outpl into the projection accumulator acc.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void plane_gather(int z, const Proj& pj, const Lds<R>& L, int cw,
+                                             cx<double>* acc) {
+  const int tid = threadIdx.x, T = blockDim.x;
+  const int c0 = pj.zc_offs[z], c1 = pj.zc_offs[z + 1];
+  const int nch = c1 - c0;
+  const int nm = pj.nm;
+  if (nch == 0) return;  // uniform across the workgroup
+  // stage 1: chunk partial sums (fixed order inside a chunk)
+  for (int w = tid; w < nch * nm * cw; w += T) {
+    const int c = w % cw;
+    const int m = (w / cw) % nm;
+    const int ci = w / (cw * nm);
+    const int4 ch = pj.chunks[c0 + ci];
+    cx<double> s = mkc(0.0, 0.0);
+    if (m < pj.grp_nm[ch.x]) {
+      for (int e = ch.y; e < ch.y + ch.z; ++e) {
+        const cx<double> yv = to64(L.outpl[pj.ent_p[e] * cw + c]);
+        const double2 ph = pj.eph[e];
+        const cx<double> w2 = cmulc(mkc(ph.x, ph.y), yv);  // conj(phase) * y
+        const double b = pj.beta[(size_t)e * nm + m];
+        s.x += b * w2.x;
+        s.y += b * w2.y;
+      }
+    }
+    L.slots[(ci * nm + m) * cw + c] = s;
+  }
+  __syncthreads();
+  // stage 2: per (group, projector, column), add the plane's chunks in order
+  const int g0 = pj.zg_offs[z], g1 = pj.zg_offs[z + 1];
+  for (int w = tid; w < (g1 - g0) * nm * cw; w += T) {
+    const int c = w % cw;
+    const int m = (w / cw) % nm;
+    const int gi = w / (cw * nm);
+    const int4 zg = pj.zgroups[g0 + gi];
+    if (m < pj.grp_nm[zg.x]) {
+      cx<double> s = mkc(0.0, 0.0);
+      for (int ci = zg.y; ci < zg.z; ++ci) s = s + L.slots[(ci * nm + m) * cw + c];
+      cx<double>* a = &acc[(size_t)(pj.grp_pbase[zg.x] + m) * cw + c];
+      *a = *a + cscale(s, pj.h3);
+    }
+  }
+}
+
+// Scatter contribution -sum_p beta_k,p(i) dco[p] at grid point i for column c.
+template <class R>
+__device__ __forceinline__ cx<double> point_scatter(long long i, int c, const Proj& pj,
+                                                    const Lds<R>& L, int cw) {
+  cx<double> acc = mkc(0.0, 0.0);
+  const int k0 = pj.pe_offs[i], k1 = pj.pe_offs[i + 1];
+  for (int k = k0; k < k1; ++k) {
+    const int2 ge = pj.pe[k];
+    const int nmg = pj.grp_nm[ge.x];
+    const int pb = pj.grp_pbase[ge.x];
+    cx<double> t = mkc(0.0, 0.0);
+    const double* bt = pj.beta + (size_t)ge.y * pj.nm;
+    for (int m = 0; m < nmg; ++m) {
+      const cx<double> d = L.dco[(pb + m) * cw + c];
+      t.x += bt[m] * d.x;
+      t.y += bt[m] * d.y;
+    }
+    const double2 ph = pj.eph[ge.y];
+    acc = acc + cmul(mkc(ph.x, ph.y), t);
+  }
+  return acc;
+}
+
+// Workgroup reduction of four per-thread doubles per column into out[k][c].
+__device__ __forceinline__ void col_reduce4(double* red, int cw, const double (&v)[4],
+                                            double (*out)[CW_MAX]) {
+  const int tid = threadIdx.x, T = blockDim.x;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k * T + tid] = v[k];
+  __syncthreads();
+  if (tid < 4 * cw) {
+    const int k = tid / cw, c = tid % cw;
+    double s = 0.0;
+    for (int i = c; i < T; i += cw) s += red[k * T + i];
+    out[k][c] = s;
+  }
+  __syncthreads();
+}
+
+}  // namespace rst

@@ -1,0 +1,803 @@
+// rst_lib.hip -- host runtime and C ABI of librst (see include/rst.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/rst.h"
+#include "rst_solver.hpp"
+
+using rst::cx;
+
+namespace rst {
+// Fills n ints with v (used to reset the work-queue head without a memset node).
+__global__ void k_fill_int(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+}  // namespace rst
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+}  // namespace
+
+struct rst_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  // grid
+  bool has_grid = false;
+  int na = 0, nb = 0, nz = 0, order = 0, rad = 0;
+  double ha = 0, hb = 0, hz = 0;
+  std::vector<double> fdw;  // c_0..c_M
+  // host copies
+  std::vector<double> v, gl, gr;
+  bool has_v = false, has_abc = false, has_k = false;
+  double ka = 0, kb = 0;
+  // projectors (host plan)
+  int nproj = 0, ngroup = 0, nm = 0, max_chunks = 0;
+  std::vector<int> grp_pbase, grp_nm;
+  std::vector<double> ekb, beta;
+  std::vector<int> ent_p, ent_gi;
+  std::vector<int8_t> ent_img;  // 2 per entry
+  std::vector<int> zc_offs, zg_offs, pe_offs;
+  std::vector<int4> chunks, zgroups;
+  std::vector<int2> pe;
+  // device copies
+  DevBuf d_v, d_gz, d_gl, d_gr;
+  DevBuf d_grp_pbase, d_grp_nm, d_ekb, d_beta, d_eph, d_ent_p, d_zc, d_chunks, d_zg, d_zgroups,
+      d_pe_offs, d_pe;
+  // solver
+  rst_solver_opts opts;
+  // work buffers (grown on demand)
+  DevBuf d_ws, d_pws, d_cols, d_en, d_T, d_it, d_rs, d_res, d_st, d_counter, d_args;
+  // host copies of the last kernel-argument blocks (kept alive for async copies)
+  rst::SolveArgs h_solve;
+  rst::ApplyArgs h_apply;
+};
+
+namespace {
+
+rst_status fail(rst_ctx* c, rst_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                          \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ctx, RST_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+rst_status ensure(rst_ctx* c, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return RST_OK;
+  b.release();
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(c, RST_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return RST_OK;
+}
+
+template <class T>
+rst_status upload(rst_ctx* c, DevBuf& b, const std::vector<T>& h) {
+  rst_status s = ensure(c, b, std::max<size_t>(h.size() * sizeof(T), 16));
+  if (s != RST_OK) return s;
+  if (!h.empty()) HIPCHK(c, hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RST_OK;
+}
+
+// Finite-difference weights by Fornberg's recursion (B. Fornberg, Math. Comp.
+// 51 (1988) 699) for the nodes -M..M, second derivative at 0.  Returns c_0..c_M.
+std::vector<double> fornberg_second_derivative(int m) {
+  const int npts = 2 * m + 1;
+  std::vector<long double> x(npts);
+  for (int i = 0; i < npts; ++i) x[i] = (long double)(i - m);
+  const int md = 2;
+  std::vector<std::vector<long double>> C(npts, std::vector<long double>(md + 1, 0.0L));
+  long double c1 = 1.0L, c4 = x[0];
+  C[0][0] = 1.0L;
+  for (int i = 1; i < npts; ++i) {
+    const int mn = std::min(i, md);
+    long double c2 = 1.0L;
+    const long double c5 = c4;
+    c4 = x[i];
+    for (int j = 0; j < i; ++j) {
+      const long double c3 = x[i] - x[j];
+      c2 *= c3;
+      if (j == i - 1) {
+        for (int k = mn; k >= 1; --k) C[i][k] = c1 * (k * C[i - 1][k - 1] - c5 * C[i - 1][k]) / c2;
+        C[i][0] = -c1 * c5 * C[i - 1][0] / c2;
+      }
+      for (int k = mn; k >= 1; --k) C[j][k] = (c4 * C[j][k] - k * C[j][k - 1]) / c3;
+      C[j][0] = c4 * C[j][0] / c3;
+    }
+    c1 = c2;
+  }
+  std::vector<double> w(m + 1);
+  for (int j = 0; j <= m; ++j) w[j] = (double)C[m + j][2];
+  return w;
+}
+
+rst::Geo make_geo(const rst_ctx* c) {
+  rst::Geo g;
+  std::memset(&g, 0, sizeof(g));
+  g.na = c->na;
+  g.nb = c->nb;
+  g.nz = c->nz;
+  g.P = c->na * c->nb;
+  g.pa = c->na + 2 * c->rad;
+  g.pb = c->nb + 2 * c->rad;
+  for (int j = 1; j <= c->rad; ++j) {
+    g.cz[j] = 0.5 * c->fdw[j] / (c->hz * c->hz);
+    g.ca[j] = 0.5 * c->fdw[j] / (c->ha * c->ha);
+    g.cb[j] = 0.5 * c->fdw[j] / (c->hb * c->hb);
+  }
+  g.diag0 = 0.5 * c->fdw[0] * (1.0 / (c->ha * c->ha) + 1.0 / (c->hb * c->hb) + 1.0 / (c->hz * c->hz));
+  const double la = c->na * c->ha, lb = c->nb * c->hb;
+  g.pha_x = std::cos(c->ka * la);
+  g.pha_y = std::sin(c->ka * la);
+  g.phb_x = std::cos(c->kb * lb);
+  g.phb_y = std::sin(c->kb * lb);
+  return g;
+}
+
+rst::Proj make_proj(const rst_ctx* c) {
+  rst::Proj p;
+  std::memset(&p, 0, sizeof(p));
+  p.nproj = c->nproj;
+  p.ngroup = c->ngroup;
+  p.nm = std::max(1, c->nm);
+  p.max_chunks = c->max_chunks;
+  p.h3 = c->ha * c->hb * c->hz;
+  p.grp_pbase = (const int*)c->d_grp_pbase.p;
+  p.grp_nm = (const int*)c->d_grp_nm.p;
+  p.ekb = (const double*)c->d_ekb.p;
+  p.beta = (const double*)c->d_beta.p;
+  p.eph = (const double2*)c->d_eph.p;
+  p.ent_p = (const int*)c->d_ent_p.p;
+  p.zc_offs = (const int*)c->d_zc.p;
+  p.chunks = (const int4*)c->d_chunks.p;
+  p.zg_offs = (const int*)c->d_zg.p;
+  p.zgroups = (const int4*)c->d_zgroups.p;
+  p.pe_offs = (const int*)c->d_pe_offs.p;
+  p.pe = (const int2*)c->d_pe.p;
+  return p;
+}
+
+// Builds the projector plan: groups of consecutive projectors with identical
+// (point, image) entry lists, entries sorted by plane, per-plane gather chunks,
+// and the point-centric scatter lists.
+rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t* pt, const int8_t* img,
+                      const double* beta, const double* ekb) {
+  const long long n = (long long)c->na * c->nb * c->nz;
+  const int P = c->na * c->nb;
+  c->nproj = nproj;
+  c->grp_pbase.clear();
+  c->grp_nm.clear();
+  c->ekb.assign(ekb, ekb + nproj);
+  // group detection
+  std::vector<std::pair<int, int>> groups;  // (first proj, count)
+  for (int p = 0; p < nproj;) {
+    int q = p + 1;
+    const int len = offs[p + 1] - offs[p];
+    while (q < nproj && q - p < rst::NM_MAX && offs[q + 1] - offs[q] == len) {
+      bool same = true;
+      for (int e = 0; e < len && same; ++e) {
+        const int a = offs[p] + e, b = offs[q] + e;
+        same = pt[a] == pt[b] && img[2 * a] == img[2 * b] && img[2 * a + 1] == img[2 * b + 1];
+      }
+      if (!same) break;
+      ++q;
+    }
+    groups.push_back({p, q - p});
+    p = q;
+  }
+  c->ngroup = (int)groups.size();
+  int nm = 1;
+  for (auto& g : groups) nm = std::max(nm, g.second);
+  c->nm = nm;
+  // entries per group sorted by (plane, in-plane point, image)
+  c->ent_p.clear();
+  c->ent_gi.clear();
+  c->ent_img.clear();
+  c->beta.clear();
+  std::vector<int> grp_e0, grp_ne;
+  for (int gi = 0; gi < c->ngroup; ++gi) {
+    const int p0 = groups[gi].first, cnt = groups[gi].second;
+    const int len = offs[p0 + 1] - offs[p0];
+    std::vector<int> ord(len);
+    for (int e = 0; e < len; ++e) ord[e] = e;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+      const int ia = pt[offs[p0] + a], ib = pt[offs[p0] + b];
+      return ia < ib;
+    });
+    grp_e0.push_back((int)c->ent_p.size());
+    grp_ne.push_back(len);
+    c->grp_pbase.push_back(p0);
+    c->grp_nm.push_back(cnt);
+    for (int e : ord) {
+      const int a = offs[p0] + e;
+      if (pt[a] < 0 || pt[a] >= n) return fail(c, RST_EINVAL, "projector point index out of range");
+      c->ent_gi.push_back(pt[a]);
+      c->ent_p.push_back(pt[a] % P);
+      c->ent_img.push_back(img[2 * a]);
+      c->ent_img.push_back(img[2 * a + 1]);
+      for (int m = 0; m < nm; ++m)
+        c->beta.push_back(m < cnt ? beta[offs[p0 + m] + e] : 0.0);
+    }
+  }
+  const int nent = (int)c->ent_p.size();
+  // per-plane chunks
+  c->zc_offs.assign(c->nz + 1, 0);
+  c->zg_offs.assign(c->nz + 1, 0);
+  c->chunks.clear();
+  c->zgroups.clear();
+  std::vector<std::vector<int4>> zch(c->nz), zgr(c->nz);
+  for (int gi = 0; gi < c->ngroup; ++gi) {
+    int e = grp_e0[gi];
+    const int eend = grp_e0[gi] + grp_ne[gi];
+    while (e < eend) {
+      const int z = c->ent_gi[e] / P;
+      int f = e;
+      while (f < eend && c->ent_gi[f] / P == z) ++f;
+      int4 zg;
+      zg.x = gi;
+      zg.y = (int)zch[z].size();
+      for (int s = e; s < f; s += rst::CHUNK) {
+        int4 ch;
+        ch.x = gi;
+        ch.y = s;
+        ch.z = std::min(rst::CHUNK, f - s);
+        ch.w = 0;
+        zch[z].push_back(ch);
+      }
+      zg.z = (int)zch[z].size();
+      zg.w = 0;
+      zgr[z].push_back(zg);
+      e = f;
+    }
+  }
+  c->max_chunks = 0;
+  for (int z = 0; z < c->nz; ++z) {
+    c->zc_offs[z + 1] = c->zc_offs[z] + (int)zch[z].size();
+    c->zg_offs[z + 1] = c->zg_offs[z] + (int)zgr[z].size();
+    c->max_chunks = std::max(c->max_chunks, (int)zch[z].size());
+    c->chunks.insert(c->chunks.end(), zch[z].begin(), zch[z].end());
+    c->zgroups.insert(c->zgroups.end(), zgr[z].begin(), zgr[z].end());
+  }
+  // point-centric lists
+  std::vector<int> cnt(n + 1, 0);
+  for (int gi = 0; gi < c->ngroup; ++gi)
+    for (int e = grp_e0[gi]; e < grp_e0[gi] + grp_ne[gi]; ++e) cnt[c->ent_gi[e] + 1]++;
+  c->pe_offs.assign(n + 1, 0);
+  for (long long i = 0; i < n; ++i) c->pe_offs[i + 1] = c->pe_offs[i] + cnt[i + 1];
+  c->pe.assign(c->pe_offs[n], int2{0, 0});
+  std::vector<int> fillp(c->pe_offs.begin(), c->pe_offs.end() - 1);
+  for (int gi = 0; gi < c->ngroup; ++gi)
+    for (int e = grp_e0[gi]; e < grp_e0[gi] + grp_ne[gi]; ++e) {
+      int2 v;
+      v.x = gi;
+      v.y = e;
+      c->pe[fillp[c->ent_gi[e]]++] = v;
+    }
+  (void)nent;
+  rst_status s;
+  if ((s = upload(c, c->d_grp_pbase, c->grp_pbase)) != RST_OK) return s;
+  if ((s = upload(c, c->d_grp_nm, c->grp_nm)) != RST_OK) return s;
+  if ((s = upload(c, c->d_ekb, c->ekb)) != RST_OK) return s;
+  if ((s = upload(c, c->d_beta, c->beta)) != RST_OK) return s;
+  if ((s = upload(c, c->d_ent_p, c->ent_p)) != RST_OK) return s;
+  if ((s = upload(c, c->d_zc, c->zc_offs)) != RST_OK) return s;
+  if ((s = upload(c, c->d_chunks, c->chunks)) != RST_OK) return s;
+  if ((s = upload(c, c->d_zg, c->zg_offs)) != RST_OK) return s;
+  if ((s = upload(c, c->d_zgroups, c->zgroups)) != RST_OK) return s;
+  if ((s = upload(c, c->d_pe_offs, c->pe_offs)) != RST_OK) return s;
+  if ((s = upload(c, c->d_pe, c->pe)) != RST_OK) return s;
+  return RST_OK;
+}
+
+rst_status upload_k(rst_ctx* c) {
+  const double la = c->na * c->ha, lb = c->nb * c->hb;
+  std::vector<double2> eph(c->ent_p.size());
+  for (size_t e = 0; e < eph.size(); ++e) {
+    const double ph = c->ka * la * c->ent_img[2 * e] + c->kb * lb * c->ent_img[2 * e + 1];
+    eph[e].x = std::cos(ph);
+    eph[e].y = std::sin(ph);
+  }
+  return upload(c, c->d_eph, eph);
+}
+
+// kernel dispatch ------------------------------------------------------------
+// Instances live in kern_inst.hip (one translation unit per radius / positions).
+extern "C" void* rst_kptr_r2_q1(int);
+extern "C" void* rst_kptr_r2_q2(int);
+extern "C" void* rst_kptr_r2_q4(int);
+extern "C" void* rst_kptr_r6_q1(int);
+extern "C" void* rst_kptr_r6_q2(int);
+
+void* pick_kernel(int rad, int q, bool apply) {
+  const int w = apply ? 1 : 0;
+  if (rad == 2 && q == 1) return rst_kptr_r2_q1(w);
+  if (rad == 2 && q == 2) return rst_kptr_r2_q2(w);
+  if (rad == 2 && q == 4) return rst_kptr_r2_q4(w);
+  if (rad == 6 && q == 1) return rst_kptr_r6_q1(w);
+  if (rad == 6 && q == 2) return rst_kptr_r6_q2(w);
+  return nullptr;
+}
+
+struct LaunchShape {
+  int cw, threads, q;
+};
+
+rst_status choose_shape(rst_ctx* c, int cw_req, int t_req, LaunchShape& ls) {
+  const int P = c->na * c->nb;
+  int cw = cw_req > 0 ? cw_req : 1;
+  if (cw > rst::CW_MAX || (cw & (cw - 1))) return fail(c, RST_EINVAL, "col_block must be a power of two <= 8");
+  const int pos = P * cw;
+  for (int q : {1, 2, 4}) {
+    if (c->rad == 6 && q == 4) continue;
+    int t = t_req > 0 ? t_req : ((pos + q - 1) / q + 63) / 64 * 64;
+    if (t < 64) t = 64;
+    if (t > rst::MAX_T || t % 64 || t % cw) continue;
+    if ((long long)t * q < pos) continue;
+    ls.cw = cw;
+    ls.threads = t;
+    ls.q = q;
+    return RST_OK;
+  }
+  return fail(c, RST_EUNSUPPORTED, "plane of " + std::to_string(P) + " points x " + std::to_string(cw) +
+                                       " columns does not fit one workgroup (max 4 per thread at 512 threads)");
+}
+
+rst_status check_ready(rst_ctx* c) {
+  if (!c) return RST_EINVAL;
+  if (!c->has_grid) return fail(c, RST_ESTATE, "rst_set_grid not called");
+  if (!c->has_v) return fail(c, RST_ESTATE, "rst_set_potential not called");
+  if (!c->has_abc) return fail(c, RST_ESTATE, "rst_set_abc not called");
+  if (!c->has_k) return fail(c, RST_ESTATE, "rst_set_k not called");
+  if (c->rad != 2 && c->rad != 6)
+    return fail(c, RST_EUNSUPPORTED, "GPU kernels are built for FD orders 4 and 12");
+  return RST_OK;
+}
+
+// Runs the persistent solver over ncols columns x ne energies.
+rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
+                      const double* d_gsrc, const double* d_gdst, double2* xout,
+                      std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
+                      std::vector<double>& res, std::vector<int>& st, double& ms) {
+  LaunchShape ls;
+  rst_status s = choose_shape(c, c->opts.col_block, c->opts.threads, ls);
+  if (s != RST_OK) return s;
+  const int ncols = (int)cols.size();
+  const int nblk = (ncols + ls.cw - 1) / ls.cw;
+  const long long nitems = (long long)nblk * ne;
+  if (nitems > 0x7fffffff) return fail(c, RST_EINVAL, "too many column blocks");
+  const size_t n = (size_t)c->na * c->nb * c->nz;
+  void* kern = pick_kernel(c->rad, ls.q, false);
+  if (!kern) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
+  rst::Geo g = make_geo(c);
+  rst::Proj pj = make_proj(c);
+  const size_t lds = rst::lds_bytes<double>(g.pa, g.pb, g.P, pj.nproj, pj.max_chunks, pj.nm, ls.cw, ls.threads);
+  int dev_lds = 0;
+  HIPCHK(c, hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+  if (lds + sizeof(rst::ColState) + 1024 > (size_t)dev_lds)
+    return fail(c, RST_EUNSUPPORTED, "LDS requirement " + std::to_string(lds) + " exceeds the device limit");
+  if (lds > 64 * 1024) HIPCHK(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per_cu = 0;
+  HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, ls.threads, lds));
+  if (per_cu < 1) return fail(c, RST_EUNSUPPORTED, "kernel does not fit on a compute unit");
+  int ncu = 0;
+  HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  long long nwg = std::min<long long>(nitems, (long long)per_cu * ncu);
+  // bound the workspace to a quarter of free memory
+  const size_t ws_stride = 5 * n * ls.cw;  // elements of cx<double>
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
+  const size_t per_wg = ws_stride * sizeof(cx<double>) + 5 * (size_t)c->nproj * ls.cw * 16;
+  const long long cap = std::max<long long>(1, (long long)(free_b / 4 / per_wg));
+  nwg = std::min(nwg, cap);
+  if ((s = ensure(c, c->d_ws, nwg * ws_stride * sizeof(cx<double>))) != RST_OK) return s;
+  const size_t pws_stride = std::max<size_t>(1, 5 * (size_t)c->nproj * ls.cw);
+  if ((s = ensure(c, c->d_pws, nwg * pws_stride * 16)) != RST_OK) return s;
+  std::vector<double> en(energies, energies + ne);
+  if ((s = upload(c, c->d_en, en)) != RST_OK) return s;
+  if ((s = upload(c, c->d_cols, cols)) != RST_OK) return s;
+  const size_t nout = (size_t)ne * ncols;
+  if ((s = ensure(c, c->d_T, nout * 8)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_it, nout * 4)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_rs, nout * 4)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_res, nout * 8)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_st, nout * 4)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_counter, 64)) != RST_OK) return s;
+  rst::SolveArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.g = g;
+  A.pj = pj;
+  A.V = (const double*)c->d_v.p;
+  A.gz = (const double*)c->d_gz.p;
+  A.gdst = d_gdst;
+  A.gsrc = d_gsrc;
+  A.energies = (const double*)c->d_en.p;
+  A.cols = (const int64_t*)c->d_cols.p;
+  A.ncols = ncols;
+  A.ne = ne;
+  A.cw = ls.cw;
+  A.nblk = nblk;
+  A.nitems = (int)nitems;
+  A.tol = c->opts.tol;
+  A.max_iter = c->opts.max_iter;
+  A.ws = c->d_ws.p;
+  A.ws_stride = ws_stride;
+  A.pws = (double2*)c->d_pws.p;
+  A.pws_stride = pws_stride;
+  A.T_col = (double*)c->d_T.p;
+  A.iters = (int*)c->d_it.p;
+  A.restarts = (int*)c->d_rs.p;
+  A.resid = (double*)c->d_res.p;
+  A.status = (int*)c->d_st.p;
+  A.counter = (int*)c->d_counter.p;
+  A.xout = xout;
+  hipLaunchKernelGGL(rst::k_fill_int, dim3(1), dim3(64), 0, c->stream, (int*)c->d_counter.p, 16, 0);
+  HIPCHK(c, hipGetLastError());
+  if ((s = ensure(c, c->d_args, sizeof(A))) != RST_OK) return s;
+  c->h_solve = A;
+  HIPCHK(c, hipMemcpyAsync(c->d_args.p, &c->h_solve, sizeof(A), hipMemcpyHostToDevice, c->stream));
+  void* dargs = c->d_args.p;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  void* args[] = {&dargs};
+  HIPCHK(c, hipLaunchKernel(kern, dim3((unsigned)nwg), dim3(ls.threads), args, lds, c->stream));
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float fms = 0;
+  HIPCHK(c, hipEventElapsedTime(&fms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  ms = fms;
+  Tcol.resize(nout);
+  its.resize(nout);
+  rss.resize(nout);
+  res.resize(nout);
+  st.resize(nout);
+  HIPCHK(c, hipMemcpy(Tcol.data(), c->d_T.p, nout * 8, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(its.data(), c->d_it.p, nout * 4, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(rss.data(), c->d_rs.p, nout * 4, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(res.data(), c->d_res.p, nout * 8, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(st.data(), c->d_st.p, nout * 4, hipMemcpyDeviceToHost));
+  return RST_OK;
+}
+
+void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const std::vector<int>& rss,
+                const std::vector<double>& res, const std::vector<int>& stv, double ms, int& nbad) {
+  nbad = 0;
+  rst_stats s;
+  std::memset(&s, 0, sizeof(s));
+  s.columns = (int64_t)its.size();
+  for (size_t i = 0; i < its.size(); ++i) {
+    s.iterations_total += its[i];
+    s.iterations_max = std::max(s.iterations_max, its[i]);
+    s.restarts_total += rss[i];
+    s.max_rel_residual = std::max(s.max_rel_residual, res[i]);
+    if (stv[i] != 0) ++nbad;
+  }
+  s.columns_unconverged = nbad;
+  s.kernel_ms = ms;
+  const double n = (double)c->na * c->nb * c->nz;
+  s.bytes_algorithmic = (double)s.iterations_total * 12.0 * 16.0 * n;
+  if (st) *st = s;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rst_default_solver(rst_solver_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->method = RST_BICGSTAB;
+  o->precision = RST_FP64;
+  o->tol = 1e-10;
+  o->max_iter = 20000;
+  o->col_block = 0;
+  o->threads = 0;
+  o->direction = RST_DIR_LR;
+  o->inner_tol = 1e-5;
+  o->max_outer = 30;
+}
+
+rst_status rst_create(rst_ctx** out, int hip_device, void* hip_stream) {
+  if (!out) return RST_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return RST_EDEVICE;
+  if (hipSetDevice(hip_device) != hipSuccess) return RST_EDEVICE;
+  rst_ctx* c = new rst_ctx();
+  c->device = hip_device;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      return RST_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  rst_default_solver(&c->opts);
+  *out = c;
+  return RST_OK;
+}
+
+void rst_destroy(rst_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* rst_last_error(const rst_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+rst_status rst_set_grid(rst_ctx* c, int na, int nb, int nz, double ha, double hb, double hz, int order) {
+  if (!c) return RST_EINVAL;
+  if (na < 1 || nb < 1 || nz < 1 || !(ha > 0) || !(hb > 0) || !(hz > 0))
+    return fail(c, RST_EINVAL, "grid dimensions and spacings must be positive");
+  if (order < 2 || order > 12 || order % 2) return fail(c, RST_EINVAL, "fd_order must be even in 2..12");
+  const int rad = order / 2;
+  if (na <= rad || nb <= rad)
+    return fail(c, RST_EUNSUPPORTED, "lateral grid must exceed the stencil radius (na, nb > fd_order/2)");
+  if ((long long)na * nb * nz > 0x7fffffffLL) return fail(c, RST_EINVAL, "grid too large");
+  hipSetDevice(c->device);
+  c->na = na;
+  c->nb = nb;
+  c->nz = nz;
+  c->ha = ha;
+  c->hb = hb;
+  c->hz = hz;
+  c->order = order;
+  c->rad = rad;
+  c->fdw = fornberg_second_derivative(rad);
+  c->has_grid = true;
+  c->has_v = c->has_abc = c->has_k = false;
+  c->nproj = c->ngroup = 0;
+  c->nm = 1;
+  c->max_chunks = 0;
+  c->ent_p.clear();
+  c->ent_img.clear();
+  // empty projector plan
+  const long long n = (long long)na * nb * nz;
+  c->zc_offs.assign(nz + 1, 0);
+  c->zg_offs.assign(nz + 1, 0);
+  c->pe_offs.assign(n + 1, 0);
+  rst_status s;
+  if ((s = upload(c, c->d_zc, c->zc_offs)) != RST_OK) return s;
+  if ((s = upload(c, c->d_zg, c->zg_offs)) != RST_OK) return s;
+  if ((s = upload(c, c->d_pe_offs, c->pe_offs)) != RST_OK) return s;
+  return RST_OK;
+}
+
+rst_status rst_set_potential(rst_ctx* c, const double* v) {
+  if (!c) return RST_EINVAL;
+  if (!c->has_grid) return fail(c, RST_ESTATE, "rst_set_grid not called");
+  if (!v) return fail(c, RST_EINVAL, "null potential");
+  const size_t n = (size_t)c->na * c->nb * c->nz;
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return fail(c, RST_EINVAL, "non-finite potential value");
+  hipSetDevice(c->device);
+  c->v.assign(v, v + n);
+  rst_status s = upload(c, c->d_v, c->v);
+  if (s != RST_OK) return s;
+  c->has_v = true;
+  return RST_OK;
+}
+
+rst_status rst_set_projectors(rst_ctx* c, int nproj, const int32_t* offs, const int32_t* pt, const int8_t* img,
+                              const double* beta, const double* e_kb) {
+  if (!c) return RST_EINVAL;
+  if (!c->has_grid) return fail(c, RST_ESTATE, "rst_set_grid not called");
+  if (nproj < 0) return fail(c, RST_EINVAL, "nproj < 0");
+  hipSetDevice(c->device);
+  if (nproj == 0) {
+    c->nproj = c->ngroup = 0;
+    c->nm = 1;
+    c->max_chunks = 0;
+    c->ent_p.clear();
+    c->ent_img.clear();
+    return RST_OK;
+  }
+  if (!offs || !pt || !img || !beta || !e_kb) return fail(c, RST_EINVAL, "null projector array");
+  if (offs[0] != 0) return fail(c, RST_EINVAL, "offs[0] must be 0");
+  for (int p = 0; p < nproj; ++p) {
+    if (offs[p + 1] < offs[p]) return fail(c, RST_EINVAL, "offs must be non-decreasing");
+    if (!std::isfinite(e_kb[p])) return fail(c, RST_EINVAL, "non-finite projector energy");
+  }
+  for (int e = 0; e < offs[nproj]; ++e)
+    if (!std::isfinite(beta[e])) return fail(c, RST_EINVAL, "non-finite projector value");
+  rst_status s = build_plan(c, nproj, offs, pt, img, beta, e_kb);
+  if (s != RST_OK) return s;
+  if (c->has_k) return upload_k(c);
+  return RST_OK;
+}
+
+rst_status rst_set_abc(rst_ctx* c, const double* gl, const double* gr) {
+  if (!c) return RST_EINVAL;
+  if (!c->has_grid) return fail(c, RST_ESTATE, "rst_set_grid not called");
+  if (!gl || !gr) return fail(c, RST_EINVAL, "null CAP profile");
+  for (int z = 0; z < c->nz; ++z)
+    if (!(gl[z] >= 0) || !(gr[z] >= 0) || !std::isfinite(gl[z]) || !std::isfinite(gr[z]))
+      return fail(c, RST_EINVAL, "CAP values must be finite and >= 0");
+  hipSetDevice(c->device);
+  c->gl.assign(gl, gl + c->nz);
+  c->gr.assign(gr, gr + c->nz);
+  std::vector<double> gz(c->nz);
+  for (int z = 0; z < c->nz; ++z) gz[z] = gl[z] + gr[z];
+  rst_status s;
+  if ((s = upload(c, c->d_gz, gz)) != RST_OK) return s;
+  if ((s = upload(c, c->d_gl, c->gl)) != RST_OK) return s;
+  if ((s = upload(c, c->d_gr, c->gr)) != RST_OK) return s;
+  c->has_abc = true;
+  return RST_OK;
+}
+
+rst_status rst_set_k(rst_ctx* c, double ka, double kb) {
+  if (!c) return RST_EINVAL;
+  if (!c->has_grid) return fail(c, RST_ESTATE, "rst_set_grid not called");
+  if (!std::isfinite(ka) || !std::isfinite(kb)) return fail(c, RST_EINVAL, "non-finite k");
+  hipSetDevice(c->device);
+  c->ka = ka;
+  c->kb = kb;
+  rst_status s = upload_k(c);
+  if (s != RST_OK) return s;
+  c->has_k = true;
+  return RST_OK;
+}
+
+rst_status rst_set_solver(rst_ctx* c, const rst_solver_opts* o) {
+  if (!c || !o) return RST_EINVAL;
+  if (o->method != RST_BICGSTAB) return fail(c, RST_EINVAL, "unknown method");
+  if (o->precision != RST_FP64) return fail(c, RST_EUNSUPPORTED, "only RST_FP64 is implemented");
+  if (!(o->tol > 0) || o->max_iter < 1) return fail(c, RST_EINVAL, "tol must be > 0 and max_iter >= 1");
+  if (o->col_block < 0 || o->col_block > rst::CW_MAX || (o->col_block & (o->col_block - 1)))
+    return fail(c, RST_EINVAL, "col_block must be 0 or a power of two <= 8");
+  if (o->threads < 0 || o->threads > rst::MAX_T || o->threads % 64)
+    return fail(c, RST_EINVAL, "threads must be 0 or a multiple of 64 <= 512");
+  if (o->direction != RST_DIR_LR && o->direction != RST_DIR_RL) return fail(c, RST_EINVAL, "bad direction");
+  c->opts = *o;
+  return RST_OK;
+}
+
+rst_status rst_transmission(rst_ctx* c, int n_e, const double* E, double* T_out, rst_stats* stats) {
+  rst_status s = check_ready(c);
+  if (s != RST_OK) return s;
+  if (n_e < 0 || (n_e > 0 && (!E || !T_out))) return fail(c, RST_EINVAL, "bad energy arguments");
+  for (int i = 0; i < n_e; ++i)
+    if (!std::isfinite(E[i])) return fail(c, RST_EINVAL, "non-finite energy");
+  hipSetDevice(c->device);
+  const bool lr = c->opts.direction == RST_DIR_LR;
+  const std::vector<double>& gsrc = lr ? c->gr : c->gl;
+  const int P = c->na * c->nb;
+  std::vector<int64_t> cols;
+  for (int z = 0; z < c->nz; ++z)
+    if (gsrc[z] > 0)
+      for (int p = 0; p < P; ++p) cols.push_back((int64_t)z * P + p);
+  if (n_e == 0) return RST_OK;
+  if (cols.empty()) {
+    for (int i = 0; i < n_e; ++i) T_out[i] = 0.0;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    return RST_OK;
+  }
+  std::vector<double> Tcol, res;
+  std::vector<int> its, rss, stv;
+  double ms = 0;
+  s = run_solver(c, n_e, E, cols, lr ? (const double*)c->d_gr.p : (const double*)c->d_gl.p,
+                 lr ? (const double*)c->d_gl.p : (const double*)c->d_gr.p, nullptr, Tcol, its, rss, res, stv,
+                 ms);
+  if (s != RST_OK) return s;
+  const size_t nc = cols.size();
+  for (int i = 0; i < n_e; ++i) {
+    double t = 0;
+    for (size_t j = 0; j < nc; ++j) t += Tcol[(size_t)i * nc + j];
+    T_out[i] = t;
+  }
+  int nbad = 0;
+  fill_stats(c, stats, its, rss, res, stv, ms, nbad);
+  return nbad ? RST_ENOCONV : RST_OK;
+}
+
+rst_status rst_solve_columns(rst_ctx* c, double energy, int ncol, const int64_t* col, void* x_dev,
+                             rst_stats* stats) {
+  rst_status s = check_ready(c);
+  if (s != RST_OK) return s;
+  const long long n = (long long)c->na * c->nb * c->nz;
+  if (ncol < 0 || (ncol > 0 && (!col || !x_dev))) return fail(c, RST_EINVAL, "bad column arguments");
+  if (!std::isfinite(energy)) return fail(c, RST_EINVAL, "non-finite energy");
+  for (int j = 0; j < ncol; ++j)
+    if (col[j] < 0 || col[j] >= n) return fail(c, RST_EINVAL, "column index out of range");
+  if (ncol == 0) return RST_OK;
+  hipSetDevice(c->device);
+  std::vector<int64_t> cols(col, col + ncol);
+  std::vector<double> Tcol, res;
+  std::vector<int> its, rss, stv;
+  double ms = 0;
+  s = run_solver(c, 1, &energy, cols, nullptr, nullptr, (double2*)x_dev, Tcol, its, rss, res, stv, ms);
+  if (s != RST_OK) return s;
+  int nbad = 0;
+  fill_stats(c, stats, its, rss, res, stv, ms, nbad);
+  return nbad ? RST_ENOCONV : RST_OK;
+}
+
+rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev, int ncol) {
+  rst_status s = check_ready(c);
+  if (s != RST_OK) return s;
+  if (ncol < 0 || (ncol > 0 && (!x_dev || !y_dev))) return fail(c, RST_EINVAL, "bad apply arguments");
+  if (x_dev == y_dev) return fail(c, RST_EINVAL, "x and y must be distinct buffers");
+  if (!std::isfinite(energy)) return fail(c, RST_EINVAL, "non-finite energy");
+  if (ncol == 0) return RST_OK;
+  hipSetDevice(c->device);
+  LaunchShape ls;
+  int cw_req = c->opts.col_block > 0 ? c->opts.col_block : std::min(rst::CW_MAX, 4);
+  const long long qmax = c->rad == 6 ? 2 : 4;
+  while (cw_req > 1 && (long long)c->na * c->nb * cw_req > qmax * rst::MAX_T) cw_req /= 2;
+  if ((s = choose_shape(c, cw_req, c->opts.threads, ls)) != RST_OK) return s;
+  void* kern = pick_kernel(c->rad, ls.q, true);
+  if (!kern) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
+  rst::ApplyArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.g = make_geo(c);
+  A.pj = make_proj(c);
+  A.V = (const double*)c->d_v.p;
+  A.gz = (const double*)c->d_gz.p;
+  A.energy = energy;
+  A.x = (const double2*)x_dev;
+  A.y = (double2*)y_dev;
+  A.ncol = ncol;
+  A.cw = ls.cw;
+  A.nblk = (ncol + ls.cw - 1) / ls.cw;
+  const size_t pws_stride = std::max<size_t>(1, (size_t)c->nproj * ls.cw);
+  if ((s = ensure(c, c->d_pws, (size_t)A.nblk * pws_stride * 16)) != RST_OK) return s;
+  A.pws = (double2*)c->d_pws.p;
+  A.pws_stride = pws_stride;
+  const size_t lds =
+      rst::lds_bytes<double>(A.g.pa, A.g.pb, A.g.P, A.pj.nproj, A.pj.max_chunks, A.pj.nm, ls.cw, ls.threads);
+  int dev_lds = 0;
+  HIPCHK(c, hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+  if (lds + sizeof(rst::ColState) + 1024 > (size_t)dev_lds)
+    return fail(c, RST_EUNSUPPORTED, "LDS requirement exceeds the device limit");
+  if (lds > 64 * 1024) HIPCHK(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if ((s = ensure(c, c->d_args, sizeof(A))) != RST_OK) return s;
+  c->h_apply = A;
+  HIPCHK(c, hipMemcpyAsync(c->d_args.p, &c->h_apply, sizeof(A), hipMemcpyHostToDevice, c->stream));
+  void* dargs = c->d_args.p;
+  void* args[] = {&dargs};
+  HIPCHK(c, hipLaunchKernel(kern, dim3(A.nblk), dim3(ls.threads), args, lds, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RST_OK;
+}
+
+}  // extern "C"

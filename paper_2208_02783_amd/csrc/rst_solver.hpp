@@ -1,0 +1,413 @@
+// rst_solver.hpp -- persistent BiCGSTAB kernel (one workgroup = one column
+// block, start to finish) and the stand-alone apply kernel.
+//
+// BiCGSTAB (van der Vorst) with the shadow residual r^_0 = e_j0 (a unit vector,
+// initially the column's source point), so (r^_0, w) = w[j0].  Each iteration
+// is two sweeps:
+//   sweep B: s = r - alpha v (formed on load), t = A s, dots (t,s), (t,t);
+//   sweep A: x += alpha p + omega s, r = s - omega t, p = r + beta (p - omega v)
+//            (all formed on load), v = A p, ||r||^2.
+// beta needs rho' = r'[j0] = s[j0] - omega t[j0], which sweep B records, so the
+// x/r/p updates of one iteration and the v = A p of the next share one sweep.
+// Projections B^H w of the Krylov vectors are carried by the same recurrences;
+// those of the apply outputs (v, t, r_true) are gathered from the output planes.
+// Convergence is decided on the FP64 true residual b - A x (a fresh gather of x
+// and a fresh apply); a column whose recursive residual reached tol but whose
+// true residual did not, or a breakdown, restarts the block from the true
+// residual with the shadow moved to argmax |r|.
+#pragma once
+#include "rst_sweep.hpp"
+
+namespace rst {
+
+template <class R>
+__device__ __forceinline__ void zero_acc(cx<double>* a, int count) {
+  for (int w = threadIdx.x; w < count; w += blockDim.x) a[w] = mkc(0.0, 0.0);
+}
+
+// dco = h3 * ekb * Pu  (per projector, per column)
+__device__ __forceinline__ void set_dco(const Proj& pj, int cw, cx<double>* dco, const cx<double>* Pu) {
+  for (int w = threadIdx.x; w < pj.nproj * cw; w += blockDim.x) {
+    const int p = w / cw;
+    dco[w] = cscale(Pu[w], pj.ekb[p]);
+  }
+}
+
+template <int RAD, int Q, class R>
+__device__ __forceinline__ void true_residual_and_restart(const SolveArgs& A, SweepCtx<R>& C, const Pos<Q>& ps,
+                                          const ProjArrays& PA, bool final_check, bool& all_done) {
+  ColState& S = *C.S;
+  const int cw = A.cw;
+  const int tid = threadIdx.x;
+  const int ncw = A.pj.nproj * cw;
+  // (1) gather x -> Px, T accumulator
+  zero_acc<R>(PA.Px, ncw);
+  __syncthreads();
+  double tacc = 0.0;
+  C.acc = PA.Px;
+  gather_sweep<Q, R, false>(C, ps, A.gdst, tacc);
+  {
+    double v4[4] = {tacc, 0, 0, 0};
+    __shared__ double red_out[4][CW_MAX];
+    col_reduce4(C.L.red, cw, v4, red_out);
+    if (tid < cw) S.tacc[tid] = red_out[0][tid];
+  }
+  // (2) r = b - A x, gathered into Pr
+  set_dco(A.pj, cw, C.L.dco, PA.Px);
+  zero_acc<R>(PA.Pr, ncw);
+  __syncthreads();
+  double dots[4] = {0, 0, 0, 0};
+  double rmax = -1.0;
+  long long rmax_idx = 0x7fffffffffffffffLL;
+  C.acc = PA.Pr;
+  sweep<RAD, Q, R, IN_X, OUT_RES>(C, ps, dots, rmax, rmax_idx);
+  {
+    __shared__ double red_out[4][CW_MAX];
+    col_reduce4(C.L.red, cw, dots, red_out);
+    // argmax |r| per column (ties: smaller index); scratch aliases the reduction buffer
+    double* bm = C.L.red;
+    long long* bi = reinterpret_cast<long long*>(C.L.red + blockDim.x);
+    bm[tid] = rmax;
+    bi[tid] = rmax_idx;
+    __syncthreads();
+    if (tid < cw) {
+      double m = -1.0;
+      long long ix = 0x7fffffffffffffffLL;
+      for (int i = tid; i < (int)blockDim.x; i += cw) {
+        if (bm[i] > m || (bm[i] == m && bi[i] < ix)) {
+          m = bm[i];
+          ix = bi[i];
+        }
+      }
+      S.rr[tid] = red_out[0][tid];
+      S.rmax[tid] = m;
+      S.rmax_idx[tid] = ix;
+    }
+    __syncthreads();
+  }
+  // (3) decide
+  if (tid == 0) S.any_flag = 0;
+  __syncthreads();
+  if (tid < cw) {
+    const int c = tid;
+    if (S.state[c] == 0) {
+      const double rr = S.rr[c];
+      if (!isfinite(rr)) {
+        S.state[c] = 2;
+      } else if (rr <= A.tol * A.tol * S.bb[c]) {
+        S.state[c] = 1;
+      } else if (final_check) {
+        S.state[c] = 4;  // out of iterations
+      } else {
+        S.j0[c] = S.rmax_idx[c];
+        S.restarts[c] += 1;
+        atomicOr(&S.any_flag, 1);
+      }
+    }
+  }
+  __syncthreads();
+  all_done = (S.any_flag == 0);
+  if (all_done) return;
+  // (4) restart: p = r, v = A p
+  for (int w = tid; w < ncw; w += blockDim.x) PA.Pp[w] = PA.Pr[w];
+  set_dco(A.pj, cw, C.L.dco, PA.Pr);
+  zero_acc<R>(PA.Pv, ncw);
+  __syncthreads();
+  double d2[4] = {0, 0, 0, 0};
+  C.acc = PA.Pv;
+  sweep<RAD, Q, R, IN_RESTART, OUT_V>(C, ps, d2, rmax, rmax_idx);
+  if (tid < cw) S.rho[tid] = S.rj[tid];
+  __syncthreads();
+}
+
+template <int RAD, int Q, class R>
+__device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, const Pos<Q>& ps,
+                           const ProjArrays& PA, int item) {
+  ColState& S = *C.S;
+  const int cw = A.cw;
+  const int tid = threadIdx.x;
+  const int ncw = A.pj.nproj * cw;
+  const int e_idx = item / A.nblk;
+  const int blk = item % A.nblk;
+  if (tid < cw) {
+    const int c = tid;
+    const int col = blk * cw + c;
+    S.energy[c] = A.energies[e_idx];
+    S.alpha[c] = S.omega[c] = S.beta[c] = mkc(0.0, 0.0);
+    S.iters[c] = 0;
+    S.restarts[c] = 0;
+    S.tacc[c] = 0.0;
+    S.rr[c] = 0.0;
+    if (col < A.ncols) {
+      const long long src = A.cols[col];
+      S.src[c] = src;
+      S.j0[c] = src;
+      const double gs = A.gsrc ? A.gsrc[src / A.g.P] : 1.0;
+      S.bsc[c] = sqrt(gs);
+      S.bb[c] = gs;
+      S.state[c] = 0;
+    } else {
+      S.src[c] = -1;
+      S.j0[c] = -1;
+      S.bsc[c] = 0.0;
+      S.bb[c] = 0.0;
+      S.state[c] = 3;
+    }
+  }
+  __syncthreads();
+  // projections of b: Pr = Pp = h3-free B^H b (only entries at the source point)
+  zero_acc<R>(PA.Pr, ncw);
+  zero_acc<R>(PA.Pv, ncw);
+  __syncthreads();
+  if (A.pj.nproj && tid < cw && S.state[tid] == 0) {
+    const int c = tid;
+    const long long src = S.src[c];
+    for (int k = A.pj.pe_offs[src]; k < A.pj.pe_offs[src + 1]; ++k) {
+      const int2 ge = A.pj.pe[k];
+      const double2 ph = A.pj.eph[ge.y];
+      const cx<double> w = cscale(mkc(ph.x, -ph.y), S.bsc[c]);
+      for (int m = 0; m < A.pj.grp_nm[ge.x]; ++m) {
+        const double b = A.pj.beta[(size_t)ge.y * A.pj.nm + m];
+        cx<double>* a = &PA.Pr[(size_t)(A.pj.grp_pbase[ge.x] + m) * cw + c];
+        *a = *a + cscale(w, b * A.pj.h3);
+      }
+    }
+  }
+  __syncthreads();
+  for (int w = tid; w < ncw; w += blockDim.x) PA.Pp[w] = PA.Pr[w];
+  set_dco(A.pj, cw, C.L.dco, PA.Pr);
+  __syncthreads();
+  double dots[4] = {0, 0, 0, 0};
+  double rmax = 0;
+  long long rmax_idx = 0;
+  C.acc = PA.Pv;
+  sweep<RAD, Q, R, IN_INIT, OUT_V>(C, ps, dots, rmax, rmax_idx);
+  if (tid < cw) S.rho[tid] = mkc(S.bsc[tid], 0.0);
+  __syncthreads();
+
+  bool all_done = false;
+  int it = 0;
+  while (!all_done) {
+    // every pass counts, breakdown passes included, so the loop is bounded
+    if (it >= A.max_iter) {
+      true_residual_and_restart<RAD, Q, R>(A, C, ps, PA, true, all_done);
+      break;
+    }
+    ++it;
+    // alpha = rho / (r^0, v)
+    if (tid == 0) S.any_flag = 0;
+    __syncthreads();
+    if (tid < cw) {
+      const int c = tid;
+      if (S.state[c] == 0) {
+        const cx<double> vj = S.vj[c];
+        if (!(cnorm2(vj) > 0.0) || !finite2(vj) || !finite2(S.rho[c])) {
+          atomicOr(&S.any_flag, 1);
+          S.alpha[c] = mkc(0.0, 0.0);
+        } else {
+          S.alpha[c] = cdiv(S.rho[c], vj);
+        }
+      } else {
+        S.alpha[c] = mkc(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+    if (S.any_flag) {
+      true_residual_and_restart<RAD, Q, R>(A, C, ps, PA, false, all_done);
+      continue;
+    }
+    // sweep B: s = r - alpha v, t = A s
+    for (int w = tid; w < ncw; w += blockDim.x) {
+      const int c = w % cw;
+      const cx<double> ps_ = PA.Pr[w] - cmul(S.alpha[c], PA.Pv[w]);
+      C.L.dco[w] = cscale(ps_, A.pj.ekb[w / cw]);
+    }
+    zero_acc<R>(PA.Pt, ncw);
+    __syncthreads();
+    for (int k = 0; k < 4; ++k) dots[k] = 0;
+    C.acc = PA.Pt;
+    sweep<RAD, Q, R, IN_B, OUT_T>(C, ps, dots, rmax, rmax_idx);
+    {
+      __shared__ double red_out[4][CW_MAX];
+      col_reduce4(C.L.red, cw, dots, red_out);
+      if (tid == 0) S.any_flag = 0;
+      __syncthreads();
+      if (tid < cw) {
+        const int c = tid;
+        S.ts[c] = mkc(red_out[1][c], red_out[2][c]);
+        S.tt[c] = red_out[3][c];
+        if (S.state[c] == 0) {
+          const double tt = S.tt[c];
+          const cx<double> om = (tt > 0.0 && isfinite(tt)) ? cscale(S.ts[c], 1.0 / tt) : mkc(0.0, 0.0);
+          const cx<double> rn = S.sj[c] - cmul(om, S.tj[c]);
+          if (!(cnorm2(om) > 0.0) || !finite2(om) || !(cnorm2(rn) > 0.0) || !finite2(rn)) {
+            atomicOr(&S.any_flag, 1);
+            S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
+          } else {
+            S.omega[c] = om;
+            S.rho_new[c] = rn;
+            S.beta[c] = cmul(cdiv(rn, S.rho[c]), cdiv(S.alpha[c], om));
+          }
+        } else {
+          S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
+        }
+      }
+      __syncthreads();
+    }
+    if (S.any_flag) {
+      true_residual_and_restart<RAD, Q, R>(A, C, ps, PA, false, all_done);
+      continue;
+    }
+    // projections of s, r', p'
+    for (int w = tid; w < ncw; w += blockDim.x) {
+      const int c = w % cw;
+      const cx<double> al = S.alpha[c], om = S.omega[c], be = S.beta[c];
+      const cx<double> Ps = PA.Pr[w] - cmul(al, PA.Pv[w]);
+      const cx<double> Prn = Ps - cmul(om, PA.Pt[w]);
+      const cx<double> Ppn = Prn + cmul(be, PA.Pp[w] - cmul(om, PA.Pv[w]));
+      PA.Pr[w] = Prn;
+      PA.Pp[w] = Ppn;
+      C.L.dco[w] = cscale(Ppn, A.pj.ekb[w / cw]);
+    }
+    __syncthreads();
+    zero_acc<R>(PA.Pv, ncw);
+    __syncthreads();
+    for (int k = 0; k < 4; ++k) dots[k] = 0;
+    C.acc = PA.Pv;
+    sweep<RAD, Q, R, IN_A, OUT_V>(C, ps, dots, rmax, rmax_idx);
+    {
+      __shared__ double red_out[4][CW_MAX];
+      col_reduce4(C.L.red, cw, dots, red_out);
+      if (tid == 0) S.any_flag = 0;
+      __syncthreads();
+      if (tid < cw) {
+        const int c = tid;
+        if (S.state[c] == 0) {
+          S.iters[c] += 1;
+          S.rho[c] = S.rho_new[c];
+          const double rr = red_out[0][c];
+          S.rr[c] = rr;
+          if (!isfinite(rr) || rr <= A.tol * A.tol * S.bb[c]) atomicOr(&S.any_flag, 1);
+        }
+      }
+      __syncthreads();
+    }
+    if (S.any_flag) true_residual_and_restart<RAD, Q, R>(A, C, ps, PA, false, all_done);
+  }
+  // outputs
+  if (tid < cw) {
+    const int c = tid;
+    const int col = blk * cw + c;
+    if (col < A.ncols) {
+      const size_t o = (size_t)e_idx * A.ncols + col;
+      A.T_col[o] = 4.0 * S.tacc[c];
+      A.iters[o] = S.iters[c];
+      A.restarts[o] = S.restarts[c];
+      A.resid[o] = S.bb[c] > 0 ? sqrt(S.rr[c] / S.bb[c]) : 0.0;
+      A.status[o] = S.state[c] == 1 ? 0 : (S.state[c] == 2 ? 2 : 1);
+    }
+  }
+  if (A.xout) {
+    const Geo& g = A.g;
+    const size_t nall = (size_t)g.P * g.nz * cw;
+    for (size_t w = tid; w < nall; w += blockDim.x) {
+      const int c = (int)(w % cw);
+      const size_t gi = w / cw;
+      const int col = blk * cw + c;
+      if (col < A.ncols) {
+        const cx<R> xv = C.vec.x[w];
+        double2 o;
+        o.x = (double)xv.x;
+        o.y = (double)xv.y;
+        A.xout[gi * A.ncols + col] = o;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int RAD, int Q, class R>
+__global__ __launch_bounds__(MAX_T) void k_bicgstab(const SolveArgs* __restrict__ Ap) {
+  const SolveArgs& A = *Ap;
+  extern __shared__ __align__(16) char smem[];
+  __shared__ ColState S;
+  const int cw = A.cw;
+  SweepCtx<R> C;
+  C.g = &A.g;
+  C.pj = &A.pj;
+  C.V = A.V;
+  C.gz = A.gz;
+  C.cw = cw;
+  C.L = carve_lds<R>(smem, A.g, A.pj, cw, blockDim.x);
+  C.S = &S;
+  C.xext = nullptr;
+  C.yext = nullptr;
+  C.ext_ld = C.ext_c0 = C.ext_ncol = 0;
+  const size_t nv = (size_t)A.g.P * A.g.nz * cw;
+  cx<R>* base = reinterpret_cast<cx<R>*>(A.ws) + (size_t)blockIdx.x * A.ws_stride;
+  C.vec.x = base;
+  C.vec.r = base + nv;
+  C.vec.p = base + 2 * nv;
+  C.vec.v = base + 3 * nv;
+  C.vec.t = base + 4 * nv;
+  const size_t np = (size_t)A.pj.nproj * cw;
+  cx<double>* pb = reinterpret_cast<cx<double>*>(A.pws) + (size_t)blockIdx.x * A.pws_stride;
+  ProjArrays PA{pb, pb + np, pb + 2 * np, pb + 3 * np, pb + 4 * np};
+  const Pos<Q> ps = make_pos<Q>(A.g, cw, RAD);
+  for (;;) {
+    if (threadIdx.x == 0) S.item = atomicAdd(A.counter, 1);
+    __syncthreads();
+    const int item = S.item;
+    if (item >= A.nitems) break;
+    solve_item<RAD, Q, R>(A, C, ps, PA, item);
+  }
+}
+
+template <int RAD, int Q, class R>
+__global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ Ap) {
+  const ApplyArgs& A = *Ap;
+  extern __shared__ __align__(16) char smem[];
+  __shared__ ColState S;
+  const int cw = A.cw;
+  SweepCtx<R> C;
+  C.g = &A.g;
+  C.pj = &A.pj;
+  C.V = A.V;
+  C.gz = A.gz;
+  C.cw = cw;
+  C.L = carve_lds<R>(smem, A.g, A.pj, cw, blockDim.x);
+  C.S = &S;
+  C.xext = A.x;
+  C.yext = A.y;
+  C.ext_ld = A.ncol;
+  C.ext_c0 = blockIdx.x * cw;
+  C.ext_ncol = A.ncol;
+  C.vec = Vecs<R>{nullptr, nullptr, nullptr, nullptr, nullptr};
+  const int tid = threadIdx.x;
+  if (tid < cw) {
+    S.energy[tid] = A.energy;
+    S.alpha[tid] = S.omega[tid] = S.beta[tid] = mkc(0.0, 0.0);
+    S.bsc[tid] = 0;
+    S.src[tid] = -1;
+    S.j0[tid] = -1;
+  }
+  const size_t np = (size_t)A.pj.nproj * cw;
+  cx<double>* Px = reinterpret_cast<cx<double>*>(A.pws) + (size_t)blockIdx.x * A.pws_stride;
+  zero_acc<R>(Px, (int)np);
+  __syncthreads();
+  const Pos<Q> ps = make_pos<Q>(A.g, cw, RAD);
+  double tacc = 0;
+  if (A.pj.nproj) {
+    C.acc = Px;
+    gather_sweep<Q, R, true>(C, ps, nullptr, tacc);
+  }
+  set_dco(A.pj, cw, C.L.dco, Px);
+  __syncthreads();
+  double dots[4] = {0, 0, 0, 0};
+  double rmax = 0;
+  long long ri = 0;
+  C.acc = nullptr;
+  sweep<RAD, Q, R, IN_EXT, OUT_EXT>(C, ps, dots, rmax, ri);
+}
+
+}  // namespace rst

@@ -1,0 +1,209 @@
+"""Python binding of librst (ctypes): argument marshalling only.
+
+Every step of the transmission path runs in the HIP library; this module
+converts numpy arrays and torch device tensors into the pointers and sizes the
+C ABI (include/rst.h) takes.  Loading fails loudly if the library is missing:
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librst.so")
+
+RST_OK, RST_ENOCONV = 0, 1
+RST_EINVAL, RST_ESTATE, RST_ENOMEM, RST_EDEVICE, RST_EUNSUPPORTED = -1, -2, -3, -4, -5
+RST_BICGSTAB = 0
+RST_FP64, RST_FP32_REFINE = 0, 1
+RST_DIR_LR, RST_DIR_RL = 0, 1
+
+EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error", "rst_set_grid",
+            "rst_set_potential", "rst_set_projectors", "rst_set_abc", "rst_set_k", "rst_set_solver",
+            "rst_transmission", "rst_apply_h", "rst_solve_columns"]
+
+
+class rst_solver_opts(C.Structure):
+    _fields_ = [("method", C.c_int), ("precision", C.c_int), ("tol", C.c_double),
+                ("max_iter", C.c_int), ("col_block", C.c_int), ("threads", C.c_int),
+                ("direction", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int)]
+
+
+class rst_stats(C.Structure):
+    _fields_ = [("columns", C.c_int64), ("columns_unconverged", C.c_int64),
+                ("iterations_total", C.c_int64), ("iterations_max", C.c_int32),
+                ("restarts_total", C.c_int32), ("max_rel_residual", C.c_double),
+                ("kernel_ms", C.c_double), ("bytes_algorithmic", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RstError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"librst status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Loads librst.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"librst.so not found at {path}: build it with "
+                           "`python -m paper_2208_02783_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.rst_default_solver.argtypes = [C.POINTER(rst_solver_opts)]
+    lib.rst_default_solver.restype = None
+    lib.rst_create.argtypes = [C.POINTER(P), C.c_int, P]
+    lib.rst_destroy.argtypes = [P]
+    lib.rst_destroy.restype = None
+    lib.rst_last_error.argtypes = [P]
+    lib.rst_last_error.restype = C.c_char_p
+    lib.rst_set_grid.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_int]
+    lib.rst_set_potential.argtypes = [P, P]
+    lib.rst_set_projectors.argtypes = [P, C.c_int, P, P, P, P, P]
+    lib.rst_set_abc.argtypes = [P, P, P]
+    lib.rst_set_k.argtypes = [P, C.c_double, C.c_double]
+    lib.rst_set_solver.argtypes = [P, C.POINTER(rst_solver_opts)]
+    lib.rst_transmission.argtypes = [P, C.c_int, P, P, C.POINTER(rst_stats)]
+    lib.rst_apply_h.argtypes = [P, C.c_double, P, P, C.c_int]
+    lib.rst_solve_columns.argtypes = [P, C.c_double, C.c_int, P, P, C.POINTER(rst_stats)]
+    for name in EXPORTED:
+        if name not in ("rst_default_solver", "rst_destroy", "rst_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def default_solver() -> rst_solver_opts:
+    o = rst_solver_opts()
+    load().rst_default_solver(C.byref(o))
+    return o
+
+
+class Context:
+    """One librst context (one device, one stream).  Method names follow the C ABI."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = load()
+        self.h = C.c_void_p()
+        s = self.lib.rst_create(C.byref(self.h), int(device), C.c_void_p(stream) if stream else None)
+        if s != RST_OK:
+            raise RstError(s, "rst_create failed")
+        self._keep = []
+
+    def close(self):
+        if self.h:
+            self.lib.rst_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, s, allow_noconv=False):
+        if s == RST_OK or (allow_noconv and s == RST_ENOCONV):
+            return s
+        raise RstError(s, self.lib.rst_last_error(self.h).decode())
+
+    def last_error(self) -> str:
+        return self.lib.rst_last_error(self.h).decode()
+
+    # -- setters
+    def rst_set_grid(self, na, nb, nz, ha, hb, hz, fd_order):
+        return self._chk(self.lib.rst_set_grid(self.h, na, nb, nz, ha, hb, hz, fd_order))
+
+    def rst_set_potential(self, v):
+        v = np.ascontiguousarray(v, np.float64)
+        return self._chk(self.lib.rst_set_potential(self.h, _ptr(v)))
+
+    def rst_set_projectors(self, offs, pt, img, beta, e_kb):
+        nproj = int(len(e_kb))
+        offs = np.ascontiguousarray(offs, np.int32)
+        pt = np.ascontiguousarray(pt, np.int32)
+        img = np.ascontiguousarray(img, np.int8)
+        beta = np.ascontiguousarray(beta, np.float64)
+        e_kb = np.ascontiguousarray(e_kb, np.float64)
+        return self._chk(self.lib.rst_set_projectors(self.h, nproj, _ptr(offs), _ptr(pt), _ptr(img),
+                                                     _ptr(beta), _ptr(e_kb)))
+
+    def rst_set_abc(self, gamma_l, gamma_r):
+        gl = np.ascontiguousarray(gamma_l, np.float64)
+        gr = np.ascontiguousarray(gamma_r, np.float64)
+        return self._chk(self.lib.rst_set_abc(self.h, _ptr(gl), _ptr(gr)))
+
+    def rst_set_k(self, ka, kb):
+        return self._chk(self.lib.rst_set_k(self.h, float(ka), float(kb)))
+
+    def rst_set_solver(self, opts: rst_solver_opts = None, **kw):
+        o = opts or default_solver()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return self._chk(self.lib.rst_set_solver(self.h, C.byref(o)))
+
+    # -- compute
+    def rst_transmission(self, energies):
+        e = np.ascontiguousarray(np.atleast_1d(energies), np.float64)
+        t = np.zeros(e.size)
+        st = rst_stats()
+        s = self._chk(self.lib.rst_transmission(self.h, e.size, _ptr(e), _ptr(t), C.byref(st)),
+                      allow_noconv=True)
+        return t, st.as_dict(), s
+
+    def rst_apply_h(self, energy, x_dev_ptr: int, y_dev_ptr: int, ncol: int):
+        return self._chk(self.lib.rst_apply_h(self.h, float(energy), C.c_void_p(x_dev_ptr),
+                                              C.c_void_p(y_dev_ptr), int(ncol)))
+
+    def rst_solve_columns(self, energy, cols, x_dev_ptr: int):
+        cols = np.ascontiguousarray(cols, np.int64)
+        st = rst_stats()
+        s = self._chk(self.lib.rst_solve_columns(self.h, float(energy), cols.size, _ptr(cols),
+                                                 C.c_void_p(x_dev_ptr), C.byref(st)), allow_noconv=True)
+        return st.as_dict(), s
+
+    # -- convenience
+    def load_problem(self, prob, k=None):
+        """Sets grid, potential, projectors, CAPs and k from a workloads.Problem."""
+        self.rst_set_grid(prob.na, prob.nb, prob.nz, prob.ha, prob.hb, prob.hz, prob.order)
+        self.rst_set_potential(prob.v)
+        pj = prob.proj
+        if pj.nproj:
+            self.rst_set_projectors(pj.offs, pj.pt, pj.img.reshape(-1), pj.beta, pj.ekb)
+        self.rst_set_abc(prob.gamma_l, prob.gamma_r)
+        kk = prob.kpts[0] if k is None else k
+        self.rst_set_k(kk[0], kk[1])
+
+
+def apply_h(ctx: Context, energy: float, x):
+    """y = (E - H_k + i Gamma) x for a torch complex128 CUDA tensor x of shape (n, ncol)."""
+    import torch
+    assert x.is_cuda and x.dtype == torch.complex128 and x.is_contiguous()
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    ctx.rst_apply_h(energy, x.data_ptr(), y.data_ptr(), x.shape[1])
+    return y
+
+
+def solve_columns(ctx: Context, energy: float, cols, n: int, device="cuda"):
+    """Columns G e_c of the Green's function as a torch complex128 (n, ncol) tensor."""
+    import torch
+    cols = np.asarray(cols, np.int64)
+    x = torch.zeros((n, cols.size), dtype=torch.complex128, device=device)
+    torch.cuda.synchronize()
+    st, s = ctx.rst_solve_columns(energy, cols, x.data_ptr())
+    return x, st, s

@@ -1,0 +1,185 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_02783_amd import rst
+from paper_2208_02783_amd import workloads as wl
+from tests import oracle_helpers as hp
+from tests.gpu_util import make_ctx, n_channels, rand_block, torch_cuda
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ apply
+
+APPLY_CASES = [
+    dict(na=5, nb=4, nz=11, order=4, nproj=3, k=(0.37, -0.81), ncol=5),
+    dict(na=7, nb=8, nz=20, order=12, nproj=4, k=(0.2, 0.45), ncol=3),
+    dict(na=9, nb=7, nz=30, order=12, nproj=0, k=(-0.6, 0.1), ncol=1),
+    dict(na=3, nb=3, nz=5, order=4, nproj=2, k=(1.1, 0.3), ncol=9),
+]
+
+
+@pytest.mark.parametrize("case", APPLY_CASES)
+def test_apply_matches_oracle(case):
+    torch = torch_cuda()
+    _say("apply case", case)
+    rng = np.random.default_rng(13)
+    p = hp.random_problem(rng, na=case["na"], nb=case["nb"], nz=case["nz"], order=case["order"],
+                          nproj=case["nproj"], ramp=3)
+    ctx = make_ctx(torch, p, case["k"])
+    x, xd = rand_block(torch, p.n, case["ncol"], 1)
+    e = 0.731
+    y = rst.apply_h(ctx, e, xd).cpu().numpy()
+    ref = oracle.apply_system(p, case["k"], e, x)
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-13, err
+
+
+def test_apply_full_size_config2_columns():
+    """Config 2 at its full size (17x17x170, order 12, 360 projectors), every
+    output of a few columns against the oracle's factored apply."""
+    torch = torch_cuda()
+    p = wl.config(2)
+    k = p.kpts[5]
+    ctx = make_ctx(torch, p, k)
+    x, xd = rand_block(torch, p.n, 3, 2)
+    e = float(p.energies[100])
+    y = rst.apply_h(ctx, e, xd).cpu().numpy()
+    ref = oracle.apply_system(p, k, e, x)
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-13, err
+
+
+# ----------------------------------------------------------- Green columns
+
+def test_solve_columns_match_oracle():
+    torch = torch_cuda()
+    rng = np.random.default_rng(3)
+    p = hp.random_problem(rng, na=5, nb=4, nz=16, order=4, nproj=3, ramp=4)
+    k = (0.45, -0.2)
+    ctx = make_ctx(torch, p, k, tol=1e-12)
+    cols = np.array([0, 7, p.n // 2, p.n - 1])
+    x, st, s = rst.solve_columns(ctx, 0.42, cols, p.n)
+    assert s == rst.RST_OK, st
+    ref = oracle.green_columns(p, 0.42, k, cols)
+    err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 1e-9, (err, st)
+
+
+# ----------------------------------------------------------- transmission
+
+def test_config1_all_energies_match_oracle():
+    """Config 1 as specified (8x8x40, order 4, 10-plane CAP, k = 0), 32 energies,
+    all 640 right-CAP columns: |dT| <= 1e-6 max(1, N_ch)."""
+    torch = torch_cuda()
+    g = json.load(open(os.path.join(GOLD, "config1_T.json")))
+    p = wl.config(1)
+    ctx = make_ctx(torch, p)
+    t, st, s = ctx.rst_transmission(np.array(g["energies"]))
+    _say("config1 stats", st)
+    assert s == rst.RST_OK
+    for e, tg, tr in zip(g["energies"], g["T_LR"], t):
+        assert abs(tr - tg) <= 1e-6 * max(1, n_channels(p, e, (0, 0))), (e, tr, tg)
+
+
+def test_config1_rl_direction_equals_lr():
+    torch = torch_cuda()
+    g = json.load(open(os.path.join(GOLD, "config1_T.json")))
+    p = wl.config(1)
+    es = np.array(g["energies"][::8])
+    ctx = make_ctx(torch, p, direction=rst.RST_DIR_RL)
+    t, st, s = ctx.rst_transmission(es)
+    assert s == rst.RST_OK
+    np.testing.assert_allclose(t, np.array(g["T_RL"][::8]), atol=1e-6)
+    np.testing.assert_allclose(t, np.array(g["T_LR"][::8]), atol=1e-6)
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_tiny_structures_match_oracle(cfg):
+    """Tiny variants of configs 2 and 3 from the same generator (order 12,
+    Gaussian wells, KB projectors with lateral images, nonzero k)."""
+    torch = torch_cuda()
+    p = wl.config(cfg, tiny=True)
+    k = p.kpts[1]
+    es = p.energies[[0, 3, 7]]
+    _say("tiny cfg", cfg, "n", p.n, "nproj", p.proj.nproj, "k", k)
+    ref = oracle.transmission(p, es, k)
+    ctx = make_ctx(torch, p, k)
+    t, st, s = ctx.rst_transmission(es)
+    _say("stats", st)
+    assert s == rst.RST_OK
+    assert np.max(np.abs(ref["T_LR"] - ref["T_RL"])) < 1e-9  # oracle well conditioned here
+    np.testing.assert_allclose(t, ref["T_LR"], atol=1e-6, rtol=0)
+
+
+def test_gpu_time_reversal_and_zone_shift():
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    k = np.array(p.kpts[1])
+    es = p.energies[[2, 5]]
+    out = []
+    for kk in (k, -k, k + np.array([2 * math.pi / p.la, 0.0])):
+        ctx = make_ctx(torch, p, kk)
+        t, st, s = ctx.rst_transmission(es)
+        assert s == rst.RST_OK
+        out.append(t)
+    np.testing.assert_allclose(out[1], out[0], atol=1e-8)
+    np.testing.assert_allclose(out[2], out[0], atol=1e-8)
+
+
+def test_deterministic_bitwise():
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    es = p.energies[[1, 4]]
+    ctx = make_ctx(torch, p, p.kpts[0])
+    t1, _, _ = ctx.rst_transmission(es)
+    t2, _, _ = ctx.rst_transmission(es)
+    assert np.array_equal(t1, t2)
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_edge_cases():
+    torch = torch_cuda()
+    p = wl.config(1)
+    ctx = make_ctx(torch, p)
+    t, st, s = ctx.rst_transmission(np.zeros(0))
+    assert t.size == 0 and s == rst.RST_OK
+    # no right CAP -> no columns -> T = 0
+    ctx2 = make_ctx(torch, p.with_(gamma_r=np.zeros(p.nz)))
+    t, st, s = ctx2.rst_transmission(np.array([0.3]))
+    assert t[0] == 0.0
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_set_grid(3, 3, 10, 0.5, 0.5, 0.5, 12)  # radius 6 > 3 lateral points
+    assert ei.value.status == rst.RST_EUNSUPPORTED
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_set_grid(8, 8, 10, 0.5, 0.5, 0.5, 5)
+    assert ei.value.status == rst.RST_EINVAL
+    c3 = rst.Context(0)
+    c3.rst_set_grid(8, 8, 10, 0.5, 0.5, 0.5, 4)
+    with pytest.raises(rst.RstError) as ei:
+        c3.rst_transmission(np.array([0.3]))
+    assert ei.value.status == rst.RST_ESTATE
+    with pytest.raises(rst.RstError) as ei:
+        c3.rst_set_abc(-np.ones(10), np.zeros(10))
+    assert ei.value.status == rst.RST_EINVAL
+
+
+def test_iteration_cap_reports_enoconv():
+    torch = torch_cuda()
+    p = wl.config(1)
+    ctx = make_ctx(torch, p, max_iter=2)
+    t, st, s = ctx.rst_transmission(np.array([0.7]))
+    assert s == rst.RST_ENOCONV
+    assert st["columns_unconverged"] > 0
