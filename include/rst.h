@@ -64,6 +64,7 @@ typedef enum {
 typedef enum { RST_BICGSTAB = 0 } rst_method;
 typedef enum { RST_FP64 = 0, RST_FP32_REFINE = 1 } rst_precision;
 typedef enum { RST_DIR_LR = 0, RST_DIR_RL = 1 } rst_direction;
+typedef enum { RST_PRECOND_NONE = 0, RST_PRECOND_FREE_CAP = 1 } rst_precond;
 
 /* Solver options.  rst_default_solver() fills the defaults. */
 typedef struct {
@@ -72,11 +73,16 @@ typedef struct {
   double tol;        /* stop when the FP64 true residual ||b - A x|| <= tol ||b|| per column (default 1e-10) */
   int max_iter;      /* BiCGSTAB iterations per column (default 20000) */
   int col_block;     /* columns solved together by one workgroup; 0 = automatic */
-  int threads;       /* workgroup size (multiple of 64, <= 1024); 0 = automatic */
+  int threads;       /* workgroup size (multiple of 64, <= 512); 0 = automatic */
   int direction;     /* RST_DIR_LR: columns in the right CAP, T accumulated on the left (default);
                         RST_DIR_RL: the reverse.  Both give the same T (exact identity). */
   double inner_tol;  /* RST_FP32_REFINE: relative tolerance of each FP32 inner solve (default 1e-5) */
   int max_outer;     /* RST_FP32_REFINE: refinement steps (default 30) */
+  int precond;       /* rst_precond.  RST_PRECOND_FREE_CAP: right preconditioner
+                        M = E - (-1/2 L_lat - 1/2 D2_z + Vbar) + i Gamma(z) with the exact
+                        lateral FD Laplacian (diagonal in the twisted lateral Fourier basis),
+                        the three-point z Laplacian and Vbar = mean(V); applied by lateral DFTs
+                        and one tridiagonal solve per lateral mode.  Default NONE. */
 } rst_solver_opts;
 
 /* Statistics of the last rst_transmission / rst_solve_columns call. */

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librst.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-INSTANCES = [(2, 1), (2, 2), (2, 4), (6, 1), (6, 2)]
+INSTANCES = [(2, 1), (2, 2), (6, 1), (6, 2)]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

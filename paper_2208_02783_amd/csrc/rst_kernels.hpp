@@ -99,9 +99,20 @@ struct Proj {
   const int2* pe;                  // (group, entry)
 };
 
+// Constants of the free-electron + CAP preconditioner (see rst_precond.hpp).
+struct PcConst {
+  double vbar;           // shift of the reference operator
+  double a;              // 1/2 / hz^2 (three-point z coupling)
+  const double* eps;     // [P] lateral mode energies eps_perp(m)
+  const double2* twa;    // [na*na] exp(-2 pi i ma a / na) exp(-i k_a a h_a), index ma*na + a
+  const double2* twb;    // [nb*nb] exp(-2 pi i mb b / nb) exp(-i k_b b h_b), index mb*nb + b
+};
+
 struct SolveArgs {
   Geo g;
   Proj pj;
+  PcConst pc;
+  size_t pc_lds_off;        // byte offset of the DFT tables in dynamic LDS
   const double* V;          // [n]
   const double* gz;         // [nz] Gamma_L + Gamma_R
   const double* gdst;       // [nz] Gamma on the side where T is accumulated (nullable)
@@ -141,8 +152,8 @@ struct ApplyArgs {
 // Sweep modes
 // ---------------------------------------------------------------------------
 
-enum InMode { IN_INIT, IN_A, IN_RESTART, IN_B, IN_X, IN_EXT };
-enum OutMode { OUT_V, OUT_T, OUT_RES, OUT_EXT };
+enum InMode { IN_INIT, IN_A, IN_RESTART, IN_B, IN_X, IN_EXT, IN_PC };
+enum OutMode { OUT_V, OUT_T, OUT_RES, OUT_EXT, OUT_TS };
 
 // Per-column scalar state shared by the workgroup.
 struct ColState {

@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "../../include/rst.h"
-#include "rst_solver.hpp"
+#include "rst_precond.hpp"
 
 using rst::cx;
 
@@ -64,6 +64,7 @@ struct rst_ctx {
   std::vector<int2> pe;
   // device copies
   DevBuf d_v, d_gz, d_gl, d_gr;
+  DevBuf d_pc_eps, d_pc_twa, d_pc_twb;
   DevBuf d_grp_pbase, d_grp_nm, d_ekb, d_beta, d_eph, d_ent_p, d_zc, d_chunks, d_zg, d_zgroups,
       d_pe_offs, d_pe;
   // solver
@@ -321,6 +322,41 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
   return RST_OK;
 }
 
+// Lateral mode energies and twisted DFT tables of the free-electron + CAP
+// preconditioner for the current grid and k.
+rst_status upload_pc(rst_ctx* c) {
+  const int na = c->na, nb = c->nb;
+  const double la = na * c->ha, lb = nb * c->hb;
+  const double pi = 3.14159265358979323846;
+  auto symbol = [&](double th) {
+    double s = -c->fdw[0];
+    for (int j = 1; j <= c->rad; ++j) s -= 2.0 * c->fdw[j] * std::cos(j * th);
+    return s;
+  };
+  std::vector<double> eps((size_t)na * nb);
+  for (int mb = 0; mb < nb; ++mb)
+    for (int ma = 0; ma < na; ++ma) {
+      const double ta = (c->ka + 2 * pi * ma / la) * c->ha;
+      const double tb = (c->kb + 2 * pi * mb / lb) * c->hb;
+      eps[(size_t)mb * na + ma] = 0.5 * (symbol(ta) / (c->ha * c->ha) + symbol(tb) / (c->hb * c->hb));
+    }
+  std::vector<double2> twa((size_t)na * na), twb((size_t)nb * nb);
+  for (int m = 0; m < na; ++m)
+    for (int a = 0; a < na; ++a) {
+      const double ph = -2 * pi * (double)((m * a) % na) / na - c->ka * a * c->ha;
+      twa[(size_t)m * na + a] = double2{std::cos(ph), std::sin(ph)};
+    }
+  for (int m = 0; m < nb; ++m)
+    for (int b = 0; b < nb; ++b) {
+      const double ph = -2 * pi * (double)((m * b) % nb) / nb - c->kb * b * c->hb;
+      twb[(size_t)m * nb + b] = double2{std::cos(ph), std::sin(ph)};
+    }
+  rst_status s;
+  if ((s = upload(c, c->d_pc_eps, eps)) != RST_OK) return s;
+  if ((s = upload(c, c->d_pc_twa, twa)) != RST_OK) return s;
+  return upload(c, c->d_pc_twb, twb);
+}
+
 rst_status upload_k(rst_ctx* c) {
   const double la = c->na * c->ha, lb = c->nb * c->hb;
   std::vector<double2> eph(c->ent_p.size());
@@ -336,15 +372,12 @@ rst_status upload_k(rst_ctx* c) {
 // Instances live in kern_inst.hip (one translation unit per radius / positions).
 extern "C" void* rst_kptr_r2_q1(int);
 extern "C" void* rst_kptr_r2_q2(int);
-extern "C" void* rst_kptr_r2_q4(int);
 extern "C" void* rst_kptr_r6_q1(int);
 extern "C" void* rst_kptr_r6_q2(int);
 
-void* pick_kernel(int rad, int q, bool apply) {
-  const int w = apply ? 1 : 0;
+void* pick_kernel(int rad, int q, int w) {
   if (rad == 2 && q == 1) return rst_kptr_r2_q1(w);
   if (rad == 2 && q == 2) return rst_kptr_r2_q2(w);
-  if (rad == 2 && q == 4) return rst_kptr_r2_q4(w);
   if (rad == 6 && q == 1) return rst_kptr_r6_q1(w);
   if (rad == 6 && q == 2) return rst_kptr_r6_q2(w);
   return nullptr;
@@ -359,8 +392,7 @@ rst_status choose_shape(rst_ctx* c, int cw_req, int t_req, LaunchShape& ls) {
   int cw = cw_req > 0 ? cw_req : 1;
   if (cw > rst::CW_MAX || (cw & (cw - 1))) return fail(c, RST_EINVAL, "col_block must be a power of two <= 8");
   const int pos = P * cw;
-  for (int q : {1, 2, 4}) {
-    if (c->rad == 6 && q == 4) continue;
+  for (int q : {1, 2}) {
     int t = t_req > 0 ? t_req : ((pos + q - 1) / q + 63) / 64 * 64;
     if (t < 64) t = 64;
     if (t > rst::MAX_T || t % 64 || t % cw) continue;
@@ -371,7 +403,7 @@ rst_status choose_shape(rst_ctx* c, int cw_req, int t_req, LaunchShape& ls) {
     return RST_OK;
   }
   return fail(c, RST_EUNSUPPORTED, "plane of " + std::to_string(P) + " points x " + std::to_string(cw) +
-                                       " columns does not fit one workgroup (max 4 per thread at 512 threads)");
+                                       " columns does not fit one workgroup (max 2 per thread at 512 threads)");
 }
 
 rst_status check_ready(rst_ctx* c) {
@@ -398,11 +430,14 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   const long long nitems = (long long)nblk * ne;
   if (nitems > 0x7fffffff) return fail(c, RST_EINVAL, "too many column blocks");
   const size_t n = (size_t)c->na * c->nb * c->nz;
-  void* kern = pick_kernel(c->rad, ls.q, false);
+  const bool pc = c->opts.precond == RST_PRECOND_FREE_CAP;
+  void* kern = pick_kernel(c->rad, ls.q, pc ? 2 : 0);
   if (!kern) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
   rst::Geo g = make_geo(c);
   rst::Proj pj = make_proj(c);
-  const size_t lds = rst::lds_bytes<double>(g.pa, g.pb, g.P, pj.nproj, pj.max_chunks, pj.nm, ls.cw, ls.threads);
+  size_t lds = rst::lds_bytes<double>(g.pa, g.pb, g.P, pj.nproj, pj.max_chunks, pj.nm, ls.cw, ls.threads);
+  const size_t pc_off = (lds + 15) & ~size_t(15);
+  if (pc) lds = pc_off + (size_t)(c->na * c->na + c->nb * c->nb) * 16;
   int dev_lds = 0;
   HIPCHK(c, hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
   if (lds + sizeof(rst::ColState) + 1024 > (size_t)dev_lds)
@@ -415,7 +450,8 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
   long long nwg = std::min<long long>(nitems, (long long)per_cu * ncu);
   // bound the workspace to a quarter of free memory
-  const size_t ws_stride = 5 * n * ls.cw;  // elements of cx<double>
+  // x r p v t (+ ph sh s w and the item's Thomas pivots with the preconditioner)
+  const size_t ws_stride = pc ? 9 * n * ls.cw + n : 5 * n * ls.cw;  // elements of cx<double>
   size_t free_b = 0, total_b = 0;
   HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
   const size_t per_wg = ws_stride * sizeof(cx<double>) + 5 * (size_t)c->nproj * ls.cw * 16;
@@ -438,6 +474,16 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   std::memset(&A, 0, sizeof(A));
   A.g = g;
   A.pj = pj;
+  A.pc_lds_off = pc_off;
+  if (pc) {
+    double vbar = 0;
+    for (double x : c->v) vbar += x;
+    A.pc.vbar = vbar / (double)c->v.size();
+    A.pc.a = 0.5 / (c->hz * c->hz);
+    A.pc.eps = (const double*)c->d_pc_eps.p;
+    A.pc.twa = (const double2*)c->d_pc_twa.p;
+    A.pc.twb = (const double2*)c->d_pc_twb.p;
+  }
   A.V = (const double*)c->d_v.p;
   A.gz = (const double*)c->d_gz.p;
   A.gdst = d_gdst;
@@ -510,7 +556,8 @@ void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const st
   s.columns_unconverged = nbad;
   s.kernel_ms = ms;
   const double n = (double)c->na * c->nb * c->nz;
-  s.bytes_algorithmic = (double)s.iterations_total * 12.0 * 16.0 * n;
+  const double streams = c->opts.precond == RST_PRECOND_FREE_CAP ? 24.0 : 12.0;
+  s.bytes_algorithmic = (double)s.iterations_total * streams * 16.0 * n;
   if (st) *st = s;
 }
 
@@ -530,6 +577,7 @@ void rst_default_solver(rst_solver_opts* o) {
   o->direction = RST_DIR_LR;
   o->inner_tol = 1e-5;
   o->max_outer = 30;
+  o->precond = RST_PRECOND_NONE;
 }
 
 rst_status rst_create(rst_ctx** out, int hip_device, void* hip_stream) {
@@ -674,6 +722,7 @@ rst_status rst_set_k(rst_ctx* c, double ka, double kb) {
   c->kb = kb;
   rst_status s = upload_k(c);
   if (s != RST_OK) return s;
+  if ((s = upload_pc(c)) != RST_OK) return s;
   c->has_k = true;
   return RST_OK;
 }
@@ -688,6 +737,8 @@ rst_status rst_set_solver(rst_ctx* c, const rst_solver_opts* o) {
   if (o->threads < 0 || o->threads > rst::MAX_T || o->threads % 64)
     return fail(c, RST_EINVAL, "threads must be 0 or a multiple of 64 <= 512");
   if (o->direction != RST_DIR_LR && o->direction != RST_DIR_RL) return fail(c, RST_EINVAL, "bad direction");
+  if (o->precond != RST_PRECOND_NONE && o->precond != RST_PRECOND_FREE_CAP)
+    return fail(c, RST_EINVAL, "unknown preconditioner");
   c->opts = *o;
   return RST_OK;
 }
@@ -762,10 +813,10 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
   hipSetDevice(c->device);
   LaunchShape ls;
   int cw_req = c->opts.col_block > 0 ? c->opts.col_block : std::min(rst::CW_MAX, 4);
-  const long long qmax = c->rad == 6 ? 2 : 4;
+  const long long qmax = 2;
   while (cw_req > 1 && (long long)c->na * c->nb * cw_req > qmax * rst::MAX_T) cw_req /= 2;
   if ((s = choose_shape(c, cw_req, c->opts.threads, ls)) != RST_OK) return s;
-  void* kern = pick_kernel(c->rad, ls.q, true);
+  void* kern = pick_kernel(c->rad, ls.q, 1);
   if (!kern) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
   rst::ApplyArgs A;
   std::memset(&A, 0, sizeof(A));

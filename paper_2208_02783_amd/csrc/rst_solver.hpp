@@ -343,6 +343,7 @@ __global__ __launch_bounds__(MAX_T) void k_bicgstab(const SolveArgs* __restrict_
   C.xext = nullptr;
   C.yext = nullptr;
   C.ext_ld = C.ext_c0 = C.ext_ncol = 0;
+  C.pcsrc = C.pcs = nullptr;
   const size_t nv = (size_t)A.g.P * A.g.nz * cw;
   cx<R>* base = reinterpret_cast<cx<R>*>(A.ws) + (size_t)blockIdx.x * A.ws_stride;
   C.vec.x = base;
@@ -383,6 +384,7 @@ __global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ A
   C.ext_c0 = blockIdx.x * cw;
   C.ext_ncol = A.ncol;
   C.vec = Vecs<R>{nullptr, nullptr, nullptr, nullptr, nullptr};
+  C.pcsrc = C.pcs = nullptr;
   const int tid = threadIdx.x;
   if (tid < cw) {
     S.energy[tid] = A.energy;

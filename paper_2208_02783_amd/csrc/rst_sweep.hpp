@@ -20,6 +20,8 @@ struct SweepCtx {
   Lds<R> L;
   ColState* S;
   cx<double>* acc;       // gather accumulator of the output (nullptr: no gather)
+  cx<R>* pcsrc;          // IN_PC source (preconditioned vector)
+  cx<R>* pcs;            // OUT_TS: s for the (t, s) product
 };
 
 template <int Q>
@@ -88,6 +90,8 @@ __device__ __forceinline__ cx<R> load_in(const SweepCtx<R>& C, int zl, int p, in
     return s;
   } else if constexpr (IN == IN_X) {
     return C.vec.x[off];
+  } else if constexpr (IN == IN_PC) {
+    return C.pcsrc[off];
   } else {  // IN_EXT
     if (C.ext_c0 + c < C.ext_ncol) {
       const double2 v = C.xext[(size_t)gi * C.ext_ld + C.ext_c0 + c];
@@ -138,6 +142,14 @@ __device__ __forceinline__ void store_out(const SweepCtx<R>& C, long long gi, in
       rmax_idx = gi;
     }
     if (do_gather) C.L.outpl[p * cw + c] = rr;
+  } else if constexpr (OUT == OUT_TS) {
+    C.vec.t[off] = y;
+    const cx<double> y64 = to64(y), s64 = to64(C.pcs[off]);
+    const cx<double> ts = cmulc(y64, s64);
+    dots[1] += ts.x;
+    dots[2] += ts.y;
+    dots[3] += cnorm2(y64);
+    if (gi == j0) S->tj[c] = y64;
   } else {  // OUT_EXT
     if (C.ext_c0 + c < C.ext_ncol) {
       double2 o;

@@ -20,6 +20,7 @@ RST_EINVAL, RST_ESTATE, RST_ENOMEM, RST_EDEVICE, RST_EUNSUPPORTED = -1, -2, -3, 
 RST_BICGSTAB = 0
 RST_FP64, RST_FP32_REFINE = 0, 1
 RST_DIR_LR, RST_DIR_RL = 0, 1
+RST_PRECOND_NONE, RST_PRECOND_FREE_CAP = 0, 1
 
 EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error", "rst_set_grid",
             "rst_set_potential", "rst_set_projectors", "rst_set_abc", "rst_set_k", "rst_set_solver",
@@ -29,7 +30,8 @@ EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error",
 class rst_solver_opts(C.Structure):
     _fields_ = [("method", C.c_int), ("precision", C.c_int), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("col_block", C.c_int), ("threads", C.c_int),
-                ("direction", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int)]
+                ("direction", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int),
+                ("precond", C.c_int)]
 
 
 class rst_stats(C.Structure):

@@ -183,3 +183,41 @@ def test_iteration_cap_reports_enoconv():
     t, st, s = ctx.rst_transmission(np.array([0.7]))
     assert s == rst.RST_ENOCONV
     assert st["columns_unconverged"] > 0
+
+
+# ------------------------------------------------- preconditioned solver
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_preconditioned_matches_oracle(cfg):
+    """Right-preconditioned BiCGSTAB (free-electron + CAP preconditioner) gives
+    the same T as the dense oracle."""
+    torch = torch_cuda()
+    if cfg == 1:
+        g = json.load(open(os.path.join(GOLD, "config1_T.json")))
+        p = wl.config(1)
+        es = np.array(g["energies"][::5])
+        ref = np.array(g["T_LR"][::5])
+        k = (0.0, 0.0)
+    else:
+        p = wl.config(cfg, tiny=True)
+        k = p.kpts[1]
+        es = p.energies[[0, 4, 7]]
+        ref = oracle.transmission(p, es, k, both=False)["T_LR"]
+    ctx = make_ctx(torch, p, k, precond=rst.RST_PRECOND_FREE_CAP)
+    t, st, s = ctx.rst_transmission(es)
+    _say("precond cfg", cfg, st)
+    assert s == rst.RST_OK
+    np.testing.assert_allclose(t, ref, atol=1e-6, rtol=0)
+
+
+def test_preconditioned_solve_columns():
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    k = p.kpts[0]
+    ctx = make_ctx(torch, p, k, tol=1e-12, precond=rst.RST_PRECOND_FREE_CAP)
+    cols = np.array([3, p.n // 3, p.n - 5])
+    x, st, s = rst.solve_columns(ctx, float(p.energies[2]), cols, p.n)
+    assert s == rst.RST_OK, st
+    ref = oracle.green_columns(p, float(p.energies[2]), k, cols)
+    err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 1e-9, (err, st)
