@@ -25,20 +25,24 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+def build(verbose: bool = False, jobs: int | None = None, out: str = LIB, defines=()) -> str:
     jobs = jobs or min(8, os.cpu_count() or 4)
     objdir = tempfile.mkdtemp(prefix="rstbuild_")
-    units = [(os.path.join(CSRC, "rst_lib.hip"), os.path.join(objdir, "rst_lib.o"), [])]
-    for rad, q in INSTANCES:
-        units.append((os.path.join(CSRC, "kern_inst.hip"), os.path.join(objdir, f"k_r{rad}_q{q}.o"),
-                      [f"-DRST_RAD={rad}", f"-DRST_Q={q}"]))
+    units = []
+    # heaviest first: the preconditioned solvers, then the plain solvers, then apply
+    for kind in (2, 0, 1):
+        for rad, q in INSTANCES:
+            units.append((os.path.join(CSRC, "kern_inst.hip"),
+                          os.path.join(objdir, f"k{kind}_r{rad}_q{q}.o"),
+                          [f"-DRST_RAD={rad}", f"-DRST_Q={q}", f"-DRST_KIND={kind}"]))
     procs = []
+    units.append((os.path.join(CSRC, "rst_lib.hip"), os.path.join(objdir, "rst_lib.o"), []))
     pending = list(units)
     objs = []
     while pending or procs:
         while pending and len(procs) < jobs:
             src, obj, defs = pending.pop(0)
-            cmd = [HIPCC, *FLAGS, *defs, "-c", "-o", obj, src]
+            cmd = [HIPCC, *FLAGS, *defs, *[f"-D{d}" for d in defines], "-c", "-o", obj, src]
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((subprocess.Popen(cmd), cmd))
@@ -48,16 +52,16 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
             for q, _ in procs:
                 q.wait()
             raise RuntimeError("hipcc failed: " + " ".join(cmd))
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
     os.rmdir(objdir)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

@@ -2,16 +2,21 @@
 // kernels; compiled once per pair so the instances build in parallel.
 #include "rst_precond.hpp"
 
-#if !defined(RST_RAD) || !defined(RST_Q)
-#error "RST_RAD and RST_Q must be defined"
+#if !defined(RST_RAD) || !defined(RST_Q) || !defined(RST_KIND)
+#error "RST_RAD, RST_Q and RST_KIND must be defined"
 #endif
 
 #define RST_CAT2(a, b) a##b
 #define RST_CAT(a, b) RST_CAT2(a, b)
-#define RST_KPTR RST_CAT(RST_CAT(RST_CAT(rst_kptr_r, RST_RAD), _q), RST_Q)
+#define RST_KPTR RST_CAT(RST_CAT(RST_CAT(RST_CAT(RST_CAT(rst_kptr_k, RST_KIND), _r), RST_RAD), _q), RST_Q)
 
-extern "C" __attribute__((visibility("hidden"))) void* RST_KPTR(int which) {
-  if (which == 0) return (void*)rst::k_bicgstab<RST_RAD, RST_Q, double>;
-  if (which == 2) return (void*)rst::k_bicgstab_pc<RST_RAD, RST_Q, double>;
+// RST_KIND: 0 plain solver, 1 apply, 2 preconditioned solver
+extern "C" __attribute__((visibility("hidden"))) void* RST_KPTR() {
+#if RST_KIND == 0
+  return (void*)rst::k_bicgstab<RST_RAD, RST_Q, double>;
+#elif RST_KIND == 1
   return (void*)rst::k_apply<RST_RAD, RST_Q, double>;
+#else
+  return (void*)rst::k_bicgstab_pc<RST_RAD, RST_Q, double>;
+#endif
 }

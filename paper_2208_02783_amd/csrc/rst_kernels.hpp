@@ -27,7 +27,18 @@ namespace rst {
 constexpr int CW_MAX = 8;        // columns per workgroup
 constexpr int NM_MAX = 16;       // projectors per group (atom)
 constexpr int CHUNK = 8;         // entries per gather chunk
+constexpr int SC_SLOTS = 1;      // scatter slots per grid point before the overflow list
 constexpr int MAX_T = 512;       // workgroup size bound
+
+// Minimum waves per SIMD requested for the solver kernels (caps VGPRs at 512/N).
+#ifndef RST_WAVES_PER_EU
+#define RST_WAVES_PER_EU 4
+#endif
+#if RST_WAVES_PER_EU > 0
+#define RST_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(RST_WAVES_PER_EU)))
+#else
+#define RST_WAVES_ATTR
+#endif
 
 template <class R>
 struct alignas(2 * sizeof(R)) cx {
@@ -95,7 +106,12 @@ struct Proj {
   const int4* chunks;              // (group, first entry, count, -)
   const int* zg_offs;              // [nz+1] groups per plane
   const int4* zgroups;             // (group, first chunk, end chunk) relative to the plane
-  const int* pe_offs;              // [n+1] entries touching each grid point
+  // point-major scatter table: SC_SLOTS (group, entry) slots per grid point
+  const int* sc_pb;                // [n*SC_SLOTS] first projector of the slot's group, -1 if empty
+  const double2* sc_eph;           // [n*SC_SLOTS] exp(+i k.R) of the slot's entry
+  const double* sc_beta;           // [n*SC_SLOTS*nm] projector values of the slot (zero-padded)
+  int has_overflow;                // points touched by more than SC_SLOTS entries exist
+  const int* pe_offs;              // [n+1] overflow entries of each grid point
   const int2* pe;                  // (group, entry)
 };
 
@@ -194,6 +210,7 @@ struct Lds {
   cx<R>* inpl1;
   cx<R>* outpl;        // output plane for the gathers (P*cw)
   cx<double>* dco;     // scatter coefficients h^3 E_p (B^H u) (nproj*cw)
+  cx<double>* pacc;    // gather accumulator of the current sweep (nproj*cw)
   cx<double>* slots;   // gather chunk partials (max_chunks*nm*cw)
   double* red;         // reduction scratch (blockDim*4)
 };
@@ -209,7 +226,7 @@ __host__ __device__ inline size_t lds_bytes(int pa, int pb, int P, int nproj, in
   off = (off + 15) & ~size_t(15);
   if (nproj) off += (size_t)P * cw * sizeof(cx<R>);
   off = (off + 15) & ~size_t(15);
-  off += (size_t)nproj * cw * sizeof(cx<double>);
+  off += 2 * (size_t)nproj * cw * sizeof(cx<double>);
   off += (size_t)max_chunks * nm * cw * sizeof(cx<double>);
   return off;
 }
@@ -231,6 +248,8 @@ __device__ __forceinline__ Lds<R> carve_lds(char* smem, const Geo& g, const Proj
   off = (off + 15) & ~size_t(15);
   L.dco = reinterpret_cast<cx<double>*>(smem + off);
   off += (size_t)pj.nproj * cw * sizeof(cx<double>);
+  L.pacc = reinterpret_cast<cx<double>*>(smem + off);
+  off += (size_t)pj.nproj * cw * sizeof(cx<double>);
   L.slots = reinterpret_cast<cx<double>*>(smem + off);
   return L;
 }
@@ -244,11 +263,12 @@ struct Pos {
 };
 
 // ---------------------------------------------------------------------------
-// Gather of the plane staged in L.outpl into the projection accumulator acc.
+// Gather of the plane staged in L.outpl into the LDS accumulator L.pacc.
+// Chunks hold at most CHUNK entries of one group in one plane; the entry loop
+// is unrolled so every chunk issues its loads at once.
 // ---------------------------------------------------------------------------
 template <class R>
-__device__ __forceinline__ void plane_gather(int z, const Proj& pj, const Lds<R>& L, int cw,
-                                             cx<double>* acc) {
+__device__ __forceinline__ void plane_gather(int z, const Proj& pj, const Lds<R>& L, int cw) {
   const int tid = threadIdx.x, T = blockDim.x;
   const int c0 = pj.zc_offs[z], c1 = pj.zc_offs[z + 1];
   const int nch = c1 - c0;
@@ -260,18 +280,20 @@ __device__ __forceinline__ void plane_gather(int z, const Proj& pj, const Lds<R>
     const int m = (w / cw) % nm;
     const int ci = w / (cw * nm);
     const int4 ch = pj.chunks[c0 + ci];
-    cx<double> s = mkc(0.0, 0.0);
-    if (m < pj.grp_nm[ch.x]) {
-      for (int e = ch.y; e < ch.y + ch.z; ++e) {
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int k = 0; k < CHUNK; ++k) {
+      if (k < ch.z) {
+        const int e = ch.y + k;
         const cx<double> yv = to64(L.outpl[pj.ent_p[e] * cw + c]);
         const double2 ph = pj.eph[e];
         const cx<double> w2 = cmulc(mkc(ph.x, ph.y), yv);  // conj(phase) * y
         const double b = pj.beta[(size_t)e * nm + m];
-        s.x += b * w2.x;
-        s.y += b * w2.y;
+        sx += b * w2.x;
+        sy += b * w2.y;
       }
     }
-    L.slots[(ci * nm + m) * cw + c] = s;
+    L.slots[(ci * nm + m) * cw + c] = mkc(sx, sy);
   }
   __syncthreads();
   // stage 2: per (group, projector, column), add the plane's chunks in order
@@ -280,37 +302,71 @@ __device__ __forceinline__ void plane_gather(int z, const Proj& pj, const Lds<R>
     const int c = w % cw;
     const int m = (w / cw) % nm;
     const int gi = w / (cw * nm);
-    const int4 zg = pj.zgroups[g0 + gi];
+    const int4 zg = pj.zgroups[g0 + gi];  // (group, first chunk, end chunk, first projector)
     if (m < pj.grp_nm[zg.x]) {
       cx<double> s = mkc(0.0, 0.0);
       for (int ci = zg.y; ci < zg.z; ++ci) s = s + L.slots[(ci * nm + m) * cw + c];
-      cx<double>* a = &acc[(size_t)(pj.grp_pbase[zg.x] + m) * cw + c];
+      cx<double>* a = &L.pacc[(size_t)(zg.w + m) * cw + c];
       *a = *a + cscale(s, pj.h3);
     }
   }
 }
 
-// Scatter contribution -sum_p beta_k,p(i) dco[p] at grid point i for column c.
+// Scatter contribution sum_p beta_k,p(i) dco[p] at grid point i for column c.
 template <class R>
 __device__ __forceinline__ cx<double> point_scatter(long long i, int c, const Proj& pj,
                                                     const Lds<R>& L, int cw) {
   cx<double> acc = mkc(0.0, 0.0);
-  const int k0 = pj.pe_offs[i], k1 = pj.pe_offs[i + 1];
-  for (int k = k0; k < k1; ++k) {
-    const int2 ge = pj.pe[k];
-    const int nmg = pj.grp_nm[ge.x];
-    const int pb = pj.grp_pbase[ge.x];
-    cx<double> t = mkc(0.0, 0.0);
-    const double* bt = pj.beta + (size_t)ge.y * pj.nm;
-    for (int m = 0; m < nmg; ++m) {
-      const cx<double> d = L.dco[(pb + m) * cw + c];
-      t.x += bt[m] * d.x;
-      t.y += bt[m] * d.y;
+  const int nm = pj.nm;
+  const int plast = pj.nproj - 1;
+#pragma unroll
+  for (int sl = 0; sl < SC_SLOTS; ++sl) {
+    const size_t si = (size_t)i * SC_SLOTS + sl;
+    const int pb = pj.sc_pb[si];
+    if (pb >= 0) {
+      const double* bt = pj.sc_beta + si * nm;
+      double tx = 0.0, ty = 0.0;
+#pragma unroll
+      for (int m = 0; m < NM_MAX; ++m) {
+        if (m < nm) {
+          const int pp = min(pb + m, plast);  // beta is zero past the group's projectors
+          const cx<double> d = L.dco[pp * cw + c];
+          tx += bt[m] * d.x;
+          ty += bt[m] * d.y;
+        }
+      }
+      const double2 ph = pj.sc_eph[si];
+      acc = acc + cmul(mkc(ph.x, ph.y), mkc(tx, ty));
     }
-    const double2 ph = pj.eph[ge.y];
-    acc = acc + cmul(mkc(ph.x, ph.y), t);
+  }
+  if (pj.has_overflow) {
+    const int k0 = pj.pe_offs[i], k1 = pj.pe_offs[i + 1];
+    for (int k = k0; k < k1; ++k) {
+      const int2 ge = pj.pe[k];
+      const int nmg = pj.grp_nm[ge.x];
+      const int pb = pj.grp_pbase[ge.x];
+      cx<double> t = mkc(0.0, 0.0);
+      const double* bt = pj.beta + (size_t)ge.y * nm;
+      for (int m = 0; m < nmg; ++m) {
+        const cx<double> d = L.dco[(pb + m) * cw + c];
+        t.x += bt[m] * d.x;
+        t.y += bt[m] * d.y;
+      }
+      const double2 ph = pj.eph[ge.y];
+      acc = acc + cmul(mkc(ph.x, ph.y), t);
+    }
   }
   return acc;
+}
+
+// Start / end of a sweep that gathers into LDS: zero L.pacc; copy it to dst.
+template <class R>
+__device__ __forceinline__ void pacc_zero(const Proj& pj, const Lds<R>& L, int cw) {
+  for (int w = threadIdx.x; w < pj.nproj * cw; w += blockDim.x) L.pacc[w] = mkc(0.0, 0.0);
+}
+template <class R>
+__device__ __forceinline__ void pacc_flush(const Proj& pj, const Lds<R>& L, int cw, cx<double>* dst) {
+  for (int w = threadIdx.x; w < pj.nproj * cw; w += blockDim.x) dst[w] = L.pacc[w];
 }
 
 // Workgroup reduction of four per-thread doubles per column into out[k][c].

@@ -62,11 +62,14 @@ struct rst_ctx {
   std::vector<int> zc_offs, zg_offs, pe_offs;
   std::vector<int4> chunks, zgroups;
   std::vector<int2> pe;
+  std::vector<int> sc_pb, sc_ent;  // scatter slots: first projector and entry (-1 empty)
+  std::vector<double> sc_beta;
+  int has_overflow = 0;
   // device copies
   DevBuf d_v, d_gz, d_gl, d_gr;
   DevBuf d_pc_eps, d_pc_twa, d_pc_twb;
   DevBuf d_grp_pbase, d_grp_nm, d_ekb, d_beta, d_eph, d_ent_p, d_zc, d_chunks, d_zg, d_zgroups,
-      d_pe_offs, d_pe;
+      d_pe_offs, d_pe, d_sc_pb, d_sc_eph, d_sc_beta;
   // solver
   rst_solver_opts opts;
   // work buffers (grown on demand)
@@ -187,6 +190,10 @@ rst::Proj make_proj(const rst_ctx* c) {
   p.zgroups = (const int4*)c->d_zgroups.p;
   p.pe_offs = (const int*)c->d_pe_offs.p;
   p.pe = (const int2*)c->d_pe.p;
+  p.sc_pb = (const int*)c->d_sc_pb.p;
+  p.sc_eph = (const double2*)c->d_sc_eph.p;
+  p.sc_beta = (const double*)c->d_sc_beta.p;
+  p.has_overflow = c->has_overflow;
   return p;
 }
 
@@ -278,7 +285,7 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
         zch[z].push_back(ch);
       }
       zg.z = (int)zch[z].size();
-      zg.w = 0;
+      zg.w = groups[gi].first;
       zgr[z].push_back(zg);
       e = f;
     }
@@ -291,21 +298,38 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
     c->chunks.insert(c->chunks.end(), zch[z].begin(), zch[z].end());
     c->zgroups.insert(c->zgroups.end(), zgr[z].begin(), zgr[z].end());
   }
-  // point-centric lists
+  // point-centric scatter: the first SC_SLOTS entries of each point go to the
+  // slot table (group order), further ones to the overflow lists
+  const int K = rst::SC_SLOTS;
+  c->sc_pb.assign((size_t)n * K, -1);
+  c->sc_ent.assign((size_t)n * K, -1);
+  c->sc_beta.assign((size_t)n * K * nm, 0.0);
+  std::vector<int> used(n, 0);
   std::vector<int> cnt(n + 1, 0);
-  for (int gi = 0; gi < c->ngroup; ++gi)
-    for (int e = grp_e0[gi]; e < grp_e0[gi] + grp_ne[gi]; ++e) cnt[c->ent_gi[e] + 1]++;
-  c->pe_offs.assign(n + 1, 0);
-  for (long long i = 0; i < n; ++i) c->pe_offs[i + 1] = c->pe_offs[i] + cnt[i + 1];
-  c->pe.assign(c->pe_offs[n], int2{0, 0});
-  std::vector<int> fillp(c->pe_offs.begin(), c->pe_offs.end() - 1);
+  std::vector<std::pair<long long, int2>> ovf;
   for (int gi = 0; gi < c->ngroup; ++gi)
     for (int e = grp_e0[gi]; e < grp_e0[gi] + grp_ne[gi]; ++e) {
-      int2 v;
-      v.x = gi;
-      v.y = e;
-      c->pe[fillp[c->ent_gi[e]]++] = v;
+      const long long i = c->ent_gi[e];
+      if (used[i] < K) {
+        const size_t si = (size_t)i * K + used[i];
+        c->sc_pb[si] = c->grp_pbase[gi];
+        c->sc_ent[si] = e;
+        for (int m = 0; m < nm; ++m) c->sc_beta[si * nm + m] = c->beta[(size_t)e * nm + m];
+        used[i]++;
+      } else {
+        int2 v;
+        v.x = gi;
+        v.y = e;
+        ovf.push_back({i, v});
+        cnt[i + 1]++;
+      }
     }
+  c->has_overflow = ovf.empty() ? 0 : 1;
+  c->pe_offs.assign(n + 1, 0);
+  for (long long i = 0; i < n; ++i) c->pe_offs[i + 1] = c->pe_offs[i] + cnt[i + 1];
+  c->pe.assign(std::max<size_t>(1, c->pe_offs[n]), int2{0, 0});
+  std::vector<int> fillp(c->pe_offs.begin(), c->pe_offs.end() - 1);
+  for (auto& o : ovf) c->pe[fillp[o.first]++] = o.second;
   (void)nent;
   rst_status s;
   if ((s = upload(c, c->d_grp_pbase, c->grp_pbase)) != RST_OK) return s;
@@ -319,6 +343,8 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
   if ((s = upload(c, c->d_zgroups, c->zgroups)) != RST_OK) return s;
   if ((s = upload(c, c->d_pe_offs, c->pe_offs)) != RST_OK) return s;
   if ((s = upload(c, c->d_pe, c->pe)) != RST_OK) return s;
+  if ((s = upload(c, c->d_sc_pb, c->sc_pb)) != RST_OK) return s;
+  if ((s = upload(c, c->d_sc_beta, c->sc_beta)) != RST_OK) return s;
   return RST_OK;
 }
 
@@ -365,21 +391,44 @@ rst_status upload_k(rst_ctx* c) {
     eph[e].x = std::cos(ph);
     eph[e].y = std::sin(ph);
   }
-  return upload(c, c->d_eph, eph);
+  rst_status s = upload(c, c->d_eph, eph);
+  if (s != RST_OK) return s;
+  std::vector<double2> sce(c->sc_ent.size());
+  for (size_t i = 0; i < sce.size(); ++i) {
+    const int e = c->sc_ent[i];
+    sce[i] = e >= 0 ? eph[e] : double2{0.0, 0.0};
+  }
+  return upload(c, c->d_sc_eph, sce);
 }
 
 // kernel dispatch ------------------------------------------------------------
 // Instances live in kern_inst.hip (one translation unit per radius / positions).
-extern "C" void* rst_kptr_r2_q1(int);
-extern "C" void* rst_kptr_r2_q2(int);
-extern "C" void* rst_kptr_r6_q1(int);
-extern "C" void* rst_kptr_r6_q2(int);
+extern "C" void* rst_kptr_k0_r2_q1();
+extern "C" void* rst_kptr_k0_r2_q2();
+extern "C" void* rst_kptr_k0_r6_q1();
+extern "C" void* rst_kptr_k0_r6_q2();
+extern "C" void* rst_kptr_k1_r2_q1();
+extern "C" void* rst_kptr_k1_r2_q2();
+extern "C" void* rst_kptr_k1_r6_q1();
+extern "C" void* rst_kptr_k1_r6_q2();
+extern "C" void* rst_kptr_k2_r2_q1();
+extern "C" void* rst_kptr_k2_r2_q2();
+extern "C" void* rst_kptr_k2_r6_q1();
+extern "C" void* rst_kptr_k2_r6_q2();
 
 void* pick_kernel(int rad, int q, int w) {
-  if (rad == 2 && q == 1) return rst_kptr_r2_q1(w);
-  if (rad == 2 && q == 2) return rst_kptr_r2_q2(w);
-  if (rad == 6 && q == 1) return rst_kptr_r6_q1(w);
-  if (rad == 6 && q == 2) return rst_kptr_r6_q2(w);
+  if (w == 0 && rad == 2 && q == 1) return rst_kptr_k0_r2_q1();
+  if (w == 0 && rad == 2 && q == 2) return rst_kptr_k0_r2_q2();
+  if (w == 0 && rad == 6 && q == 1) return rst_kptr_k0_r6_q1();
+  if (w == 0 && rad == 6 && q == 2) return rst_kptr_k0_r6_q2();
+  if (w == 1 && rad == 2 && q == 1) return rst_kptr_k1_r2_q1();
+  if (w == 1 && rad == 2 && q == 2) return rst_kptr_k1_r2_q2();
+  if (w == 1 && rad == 6 && q == 1) return rst_kptr_k1_r6_q1();
+  if (w == 1 && rad == 6 && q == 2) return rst_kptr_k1_r6_q2();
+  if (w == 2 && rad == 2 && q == 1) return rst_kptr_k2_r2_q1();
+  if (w == 2 && rad == 2 && q == 2) return rst_kptr_k2_r2_q2();
+  if (w == 2 && rad == 6 && q == 1) return rst_kptr_k2_r6_q1();
+  if (w == 2 && rad == 6 && q == 2) return rst_kptr_k2_r6_q2();
   return nullptr;
 }
 
@@ -636,8 +685,10 @@ rst_status rst_set_grid(rst_ctx* c, int na, int nb, int nz, double ha, double hb
   c->nproj = c->ngroup = 0;
   c->nm = 1;
   c->max_chunks = 0;
+  c->has_overflow = 0;
   c->ent_p.clear();
   c->ent_img.clear();
+  c->sc_ent.clear();
   // empty projector plan
   const long long n = (long long)na * nb * nz;
   c->zc_offs.assign(nz + 1, 0);
@@ -675,8 +726,10 @@ rst_status rst_set_projectors(rst_ctx* c, int nproj, const int32_t* offs, const 
     c->nproj = c->ngroup = 0;
     c->nm = 1;
     c->max_chunks = 0;
+    c->has_overflow = 0;
     c->ent_p.clear();
     c->ent_img.clear();
+    c->sc_ent.clear();
     return RST_OK;
   }
   if (!offs || !pt || !img || !beta || !e_kb) return fail(c, RST_EINVAL, "null projector array");

@@ -105,10 +105,10 @@ __device__ __forceinline__ void lateral_dft(const Geo& g, const Pos<Q>& ps, int 
 
 // Forward sweep: form the input plane by plane (per mode), lateral DFT, Thomas
 // elimination into pv.w.
-template <int Q, class R, int IN>
+template <int Q, class R>
 __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, const Pos<Q>& ps,
                                            const PcConst& K, const cx<double>* twa, const cx<double>* twb,
-                                           double (&dots)[4]) {
+                                           int IN, double (&dots)[4]) {
   const Geo& g = *C.g;
   const int cw = C.cw;
   const int c = threadIdx.x % cw;
@@ -131,13 +131,13 @@ __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, 
       if (ps.p[k] < 0) continue;
       const long long gi = (long long)z * g.P + ps.p[k];
       const size_t off = (size_t)gi * cw + c;
-      if constexpr (IN == PC_INIT) {
+      if (IN == PC_INIT) {
         const cx<R> bb = (gi == src) ? mkc<R>(bsc, (R)0) : mkc<R>((R)0, (R)0);
         C.vec.x[off] = mkc<R>((R)0, (R)0);
         C.vec.r[off] = bb;
         C.vec.p[off] = bb;
         u[k] = bb;
-      } else if constexpr (IN == PC_MERGED) {
+      } else if (IN == PC_MERGED) {
         const cx<R> xv = C.vec.x[off], phv = pv.ph[off], shv = pv.sh[off], sv = pv.s[off];
         const cx<R> tv = C.vec.t[off], pvv = C.vec.p[off], vv = C.vec.v[off];
         const cx<R> xn = xv + cmul(al, phv) + cmul(om, shv);
@@ -148,7 +148,7 @@ __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, 
         C.vec.p[off] = pn;
         dots[0] += (double)cnorm2(rn);
         u[k] = pn;
-      } else if constexpr (IN == PC_RESTART) {
+      } else if (IN == PC_RESTART) {
         const cx<R> rv = C.vec.r[off];
         C.vec.p[off] = rv;
         if (gi == j0) S->rj[c] = to64(rv);
@@ -185,6 +185,7 @@ __device__ __forceinline__ void pc_backward(SweepCtx<R>& C, const PcVecs<R>& pv,
   const int c = threadIdx.x % cw;
   const R a = (R)K.a;
   const bool do_gather = pj.nproj > 0 && C.acc != nullptr;
+  if (do_gather) pacc_zero<R>(pj, C.L, cw);
   cx<R> xnext[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) xnext[k] = mkc<R>((R)0, (R)0);
@@ -211,11 +212,15 @@ __device__ __forceinline__ void pc_backward(SweepCtx<R>& C, const PcVecs<R>& pv,
     }
     if (do_gather) {
       __syncthreads();
-      plane_gather<R>(z, pj, C.L, cw, C.acc);
+      plane_gather<R>(z, pj, C.L, cw);
       __syncthreads();
     }
   }
   __syncthreads();
+  if (do_gather) {
+    pacc_flush<R>(pj, C.L, cw, C.acc);
+    __syncthreads();
+  }
 }
 
 // Apply sweep of the preconditioned path: y = A u with u = ph (-> v) or sh (-> t).
@@ -228,9 +233,9 @@ __device__ __forceinline__ void pc_apply(SweepCtx<R>& C, const PcVecs<R>& pv, co
   C.pcsrc = TS ? pv.sh : pv.ph;
   C.pcs = pv.s;
   if constexpr (TS)
-    sweep<RAD, Q, R, IN_PC, OUT_TS>(C, ps, dots, rmax, ri);
+    sweep<RAD, Q, R>(C, ps, IN_PC, OUT_TS, dots, rmax, ri);
   else
-    sweep<RAD, Q, R, IN_PC, OUT_V>(C, ps, dots, rmax, ri);
+    sweep<RAD, Q, R>(C, ps, IN_PC, OUT_V, dots, rmax, ri);
 }
 
 template <int RAD, int Q, class R>
@@ -260,7 +265,7 @@ __device__ __forceinline__ void pc_true_residual_and_restart(const SolveArgs& A,
   double rmax = -1.0;
   long long rmax_idx = 0x7fffffffffffffffLL;
   C.acc = nullptr;
-  sweep<RAD, Q, R, IN_X, OUT_RES>(C, ps, dots, rmax, rmax_idx);
+  sweep<RAD, Q, R>(C, ps, IN_X, OUT_RES, dots, rmax, rmax_idx);
   {
     __shared__ double red_out[4][CW_MAX];
     col_reduce4(C.L.red, cw, dots, red_out);
@@ -307,7 +312,7 @@ __device__ __forceinline__ void pc_true_residual_and_restart(const SolveArgs& A,
   if (all_done) return;
   // restart: p = r, ph = M^-1 p, v = A ph
   double d2[4] = {0, 0, 0, 0};
-  pc_forward<Q, R, PC_RESTART>(C, pv, ps, K, twa, twb, d2);
+  pc_forward<Q, R>(C, pv, ps, K, twa, twb, PC_RESTART, d2);
   zero_acc<R>(PA.Pr, ncw);
   __syncthreads();
   C.acc = PA.Pr;
@@ -372,7 +377,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
   }
   __syncthreads();
   double dots[4] = {0, 0, 0, 0};
-  pc_forward<Q, R, PC_INIT>(C, pv, ps, K, twa, twb, dots);
+  pc_forward<Q, R>(C, pv, ps, K, twa, twb, PC_INIT, dots);
   zero_acc<R>(PA.Pr, ncw);
   __syncthreads();
   C.acc = PA.Pr;
@@ -414,7 +419,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
     }
     // s = r - alpha v, sh = M^-1 s, t = A sh
     for (int k = 0; k < 4; ++k) dots[k] = 0;
-    pc_forward<Q, R, PC_S>(C, pv, ps, K, twa, twb, dots);
+    pc_forward<Q, R>(C, pv, ps, K, twa, twb, PC_S, dots);
     zero_acc<R>(PA.Pp, ncw);
     __syncthreads();
     C.acc = PA.Pp;
@@ -456,7 +461,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
     }
     // x += alpha ph + omega sh, r = s - omega t, p = r + beta (p - omega v); ph = M^-1 p; v = A ph
     for (int k = 0; k < 4; ++k) dots[k] = 0;
-    pc_forward<Q, R, PC_MERGED>(C, pv, ps, K, twa, twb, dots);
+    pc_forward<Q, R>(C, pv, ps, K, twa, twb, PC_MERGED, dots);
     zero_acc<R>(PA.Pr, ncw);
     __syncthreads();
     C.acc = PA.Pr;
@@ -516,7 +521,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
 }
 
 template <int RAD, int Q, class R>
-__global__ __launch_bounds__(MAX_T) void k_bicgstab_pc(const SolveArgs* __restrict__ Ap) {
+__global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab_pc(const SolveArgs* __restrict__ Ap) {
   const SolveArgs& A = *Ap;
   extern __shared__ __align__(16) char smem[];
   __shared__ ColState S;

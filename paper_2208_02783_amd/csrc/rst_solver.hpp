@@ -60,7 +60,7 @@ __device__ __forceinline__ void true_residual_and_restart(const SolveArgs& A, Sw
   double rmax = -1.0;
   long long rmax_idx = 0x7fffffffffffffffLL;
   C.acc = PA.Pr;
-  sweep<RAD, Q, R, IN_X, OUT_RES>(C, ps, dots, rmax, rmax_idx);
+  sweep<RAD, Q, R>(C, ps, IN_X, OUT_RES, dots, rmax, rmax_idx);
   {
     __shared__ double red_out[4][CW_MAX];
     col_reduce4(C.L.red, cw, dots, red_out);
@@ -115,7 +115,7 @@ __device__ __forceinline__ void true_residual_and_restart(const SolveArgs& A, Sw
   __syncthreads();
   double d2[4] = {0, 0, 0, 0};
   C.acc = PA.Pv;
-  sweep<RAD, Q, R, IN_RESTART, OUT_V>(C, ps, d2, rmax, rmax_idx);
+  sweep<RAD, Q, R>(C, ps, IN_RESTART, OUT_V, d2, rmax, rmax_idx);
   if (tid < cw) S.rho[tid] = S.rj[tid];
   __syncthreads();
 }
@@ -162,6 +162,20 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, c
   if (A.pj.nproj && tid < cw && S.state[tid] == 0) {
     const int c = tid;
     const long long src = S.src[c];
+    // slot-table entries of the source point
+    for (int sl = 0; sl < SC_SLOTS; ++sl) {
+      const size_t si = (size_t)src * SC_SLOTS + sl;
+      const int pb = A.pj.sc_pb[si];
+      if (pb < 0) continue;
+      const double2 ph = A.pj.sc_eph[si];
+      const cx<double> w = cscale(mkc(ph.x, -ph.y), S.bsc[c]);
+      for (int m = 0; m < A.pj.nm && pb + m < A.pj.nproj; ++m) {
+        const double b = A.pj.sc_beta[si * A.pj.nm + m];  // zero past the group's projectors
+        cx<double>* a = &PA.Pr[(size_t)(pb + m) * cw + c];
+        *a = *a + cscale(w, b * A.pj.h3);
+      }
+    }
+    // overflow entries
     for (int k = A.pj.pe_offs[src]; k < A.pj.pe_offs[src + 1]; ++k) {
       const int2 ge = A.pj.pe[k];
       const double2 ph = A.pj.eph[ge.y];
@@ -181,7 +195,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, c
   double rmax = 0;
   long long rmax_idx = 0;
   C.acc = PA.Pv;
-  sweep<RAD, Q, R, IN_INIT, OUT_V>(C, ps, dots, rmax, rmax_idx);
+  sweep<RAD, Q, R>(C, ps, IN_INIT, OUT_V, dots, rmax, rmax_idx);
   if (tid < cw) S.rho[tid] = mkc(S.bsc[tid], 0.0);
   __syncthreads();
 
@@ -226,7 +240,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, c
     __syncthreads();
     for (int k = 0; k < 4; ++k) dots[k] = 0;
     C.acc = PA.Pt;
-    sweep<RAD, Q, R, IN_B, OUT_T>(C, ps, dots, rmax, rmax_idx);
+    sweep<RAD, Q, R>(C, ps, IN_B, OUT_T, dots, rmax, rmax_idx);
     {
       __shared__ double red_out[4][CW_MAX];
       col_reduce4(C.L.red, cw, dots, red_out);
@@ -274,7 +288,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, c
     __syncthreads();
     for (int k = 0; k < 4; ++k) dots[k] = 0;
     C.acc = PA.Pv;
-    sweep<RAD, Q, R, IN_A, OUT_V>(C, ps, dots, rmax, rmax_idx);
+    sweep<RAD, Q, R>(C, ps, IN_A, OUT_V, dots, rmax, rmax_idx);
     {
       __shared__ double red_out[4][CW_MAX];
       col_reduce4(C.L.red, cw, dots, red_out);
@@ -327,7 +341,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, c
 }
 
 template <int RAD, int Q, class R>
-__global__ __launch_bounds__(MAX_T) void k_bicgstab(const SolveArgs* __restrict__ Ap) {
+__global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab(const SolveArgs* __restrict__ Ap) {
   const SolveArgs& A = *Ap;
   extern __shared__ __align__(16) char smem[];
   __shared__ ColState S;
@@ -409,7 +423,7 @@ __global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ A
   double rmax = 0;
   long long ri = 0;
   C.acc = nullptr;
-  sweep<RAD, Q, R, IN_EXT, OUT_EXT>(C, ps, dots, rmax, ri);
+  sweep<RAD, Q, R>(C, ps, IN_EXT, OUT_EXT, dots, rmax, ri);
 }
 
 }  // namespace rst

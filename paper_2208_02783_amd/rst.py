@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librst.so")
+LIB_PATH = os.environ.get("RST_LIB") or os.path.join(_HERE, "librst.so")
 
 RST_OK, RST_ENOCONV = 0, 1
 RST_EINVAL, RST_ESTATE, RST_ENOMEM, RST_EDEVICE, RST_EUNSUPPORTED = -1, -2, -3, -4, -5
