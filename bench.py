@@ -28,6 +28,27 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "T(E,k) points/sec at |ΔT|≤1e-6 vs FP64 oracle; stencil HBM GB/s; plain vs batched"
 
 
+def src_hash():
+    import hashlib
+    import glob
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2208_02783_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(bytes_alg_per_launch, precond):
+    """HBM traffic per launch from the committed counter profile, only if the
+    kernel sources are unchanged since it was taken (else None)."""
+    f = os.path.join(ROOT, "profiles", "k_bicgstab_pc_cfg2_traffic.json")
+    if not precond or not os.path.exists(f):
+        return None
+    d = json.load(open(f))
+    if d.get("src_sha256") != src_hash():
+        return None
+    return d["traffic_over_algorithmic"] * bytes_alg_per_launch
+
+
 def step_points(prob, i):
     k = prob.kpts[(7 * i + 9) % len(prob.kpts)]
     e = float(prob.energies[(97 * i + 400) % len(prob.energies)])
@@ -69,6 +90,9 @@ def main():
     ap.add_argument("--precond", type=int, default=1, help="1: free-electron + CAP, 0: none")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="before the run, copy this many GiB device-to-device (a reference "
+                         "kernel of known traffic for hardware-counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the transmission path here runs on a single "
@@ -81,6 +105,13 @@ def main():
     from paper_2208_02783_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration_gib > 0:
+        nel = int(args.copy_calibration_gib * (1 << 30) // 8)
+        a = torch.ones(nel, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     prob = wl.config(2)
     ctx = rst.Context(0)
     ctx.load_problem(prob, prob.kpts[0])
@@ -139,7 +170,7 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(bytes_alg / args.steps, args.precond),
         },
     }
     if not args.no_cpu_baseline:

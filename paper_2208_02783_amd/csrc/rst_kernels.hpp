@@ -120,8 +120,7 @@ struct PcConst {
   double vbar;           // shift of the reference operator
   double a;              // 1/2 / hz^2 (three-point z coupling)
   const double* eps;     // [P] lateral mode energies eps_perp(m)
-  const double2* twa;    // [na*na] exp(-2 pi i ma a / na) exp(-i k_a a h_a), index ma*na + a
-  const double2* twb;    // [nb*nb] exp(-2 pi i mb b / nb) exp(-i k_b b h_b), index mb*nb + b
+  const double2* steps;  // [3(na+nb)] DFT recurrence steps fa, fb, ia, ib and phases pa, pb
 };
 
 struct SolveArgs {

@@ -366,21 +366,19 @@ rst_status upload_pc(rst_ctx* c) {
       const double tb = (c->kb + 2 * pi * mb / lb) * c->hb;
       eps[(size_t)mb * na + ma] = 0.5 * (symbol(ta) / (c->ha * c->ha) + symbol(tb) / (c->hb * c->hb));
     }
-  std::vector<double2> twa((size_t)na * na), twb((size_t)nb * nb);
-  for (int m = 0; m < na; ++m)
-    for (int a = 0; a < na; ++a) {
-      const double ph = -2 * pi * (double)((m * a) % na) / na - c->ka * a * c->ha;
-      twa[(size_t)m * na + a] = double2{std::cos(ph), std::sin(ph)};
-    }
-  for (int m = 0; m < nb; ++m)
-    for (int b = 0; b < nb; ++b) {
-      const double ph = -2 * pi * (double)((m * b) % nb) / nb - c->kb * b * c->hb;
-      twb[(size_t)m * nb + b] = double2{std::cos(ph), std::sin(ph)};
-    }
+  // DFT recurrence steps: fa[m] = exp(-i(2 pi m/na + k_a h_a)), ia[a] = exp(+2 pi i a/na),
+  // pa[a] = exp(+i k_a a h_a) (same for b)
+  std::vector<double2> steps;
+  auto push = [&](double ph) { steps.push_back(double2{std::cos(ph), std::sin(ph)}); };
+  for (int m = 0; m < na; ++m) push(-(2 * pi * m / na + c->ka * c->ha));
+  for (int m = 0; m < nb; ++m) push(-(2 * pi * m / nb + c->kb * c->hb));
+  for (int a = 0; a < na; ++a) push(2 * pi * a / na);
+  for (int b = 0; b < nb; ++b) push(2 * pi * b / nb);
+  for (int a = 0; a < na; ++a) push(c->ka * a * c->ha);
+  for (int b = 0; b < nb; ++b) push(c->kb * b * c->hb);
   rst_status s;
   if ((s = upload(c, c->d_pc_eps, eps)) != RST_OK) return s;
-  if ((s = upload(c, c->d_pc_twa, twa)) != RST_OK) return s;
-  return upload(c, c->d_pc_twb, twb);
+  return upload(c, c->d_pc_twa, steps);
 }
 
 rst_status upload_k(rst_ctx* c) {
@@ -486,7 +484,7 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   rst::Proj pj = make_proj(c);
   size_t lds = rst::lds_bytes<double>(g.pa, g.pb, g.P, pj.nproj, pj.max_chunks, pj.nm, ls.cw, ls.threads);
   const size_t pc_off = (lds + 15) & ~size_t(15);
-  if (pc) lds = pc_off + (size_t)(c->na * c->na + c->nb * c->nb) * 16;
+  if (pc) lds = pc_off + (size_t)3 * (c->na + c->nb) * 16;
   int dev_lds = 0;
   HIPCHK(c, hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
   if (lds + sizeof(rst::ColState) + 1024 > (size_t)dev_lds)
@@ -530,8 +528,7 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
     A.pc.vbar = vbar / (double)c->v.size();
     A.pc.a = 0.5 / (c->hz * c->hz);
     A.pc.eps = (const double*)c->d_pc_eps.p;
-    A.pc.twa = (const double2*)c->d_pc_twa.p;
-    A.pc.twb = (const double2*)c->d_pc_twb.p;
+    A.pc.steps = (const double2*)c->d_pc_twa.p;
   }
   A.V = (const double*)c->d_v.p;
   A.gz = (const double*)c->d_gz.p;

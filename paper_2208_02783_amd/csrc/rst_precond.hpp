@@ -28,75 +28,97 @@ struct PcVecs {
 };
 
 // Lateral DFT of the plane held in the positions' values u[k] -> modes out[k].
-// dir = -1: forward (twisted, unnormalised); dir = +1: inverse (with 1/P).
+// Forward kernel exp(-2 pi i m a / N) exp(-i k a h): for the sum over a at
+// fixed m it is the a-th power of w_m = exp(-i (2 pi m / N + k h)); the inverse
+// sum over m at fixed a uses conj(exp(-2 pi i m a / N)) = v_a^m with
+// v_a = exp(+2 pi i a / N), times exp(+i k a h).  Every sum therefore runs a
+// register recurrence t <- t * step instead of reading twiddles.
+// step tables (LDS): fa[ma] = w_ma, fb[mb] = w_mb, ia[a] = v_a, ib[b] = v_b,
+// pa[a] = exp(+i k_a a h_a), pb[b] = exp(+i k_b b h_b).
+// Forward: unnormalised; inverse: with 1/(Na Nb).
+struct DftSteps {
+  const cx<double>* fa;
+  const cx<double>* fb;
+  const cx<double>* ia;
+  const cx<double>* ib;
+  const cx<double>* pa;
+  const cx<double>* pb;
+};
+
 template <int Q, class R>
 __device__ __forceinline__ void lateral_dft(const Geo& g, const Pos<Q>& ps, int cw, cx<R>* b0, cx<R>* b1,
-                                            const cx<double>* twa, const cx<double>* twb, bool inverse,
-                                            const cx<R> (&u)[Q], cx<R> (&out)[Q]) {
+                                            const DftSteps& st, bool inverse, const cx<R> (&u)[Q],
+                                            cx<R> (&out)[Q]) {
   const int na = g.na, nb = g.nb;
   const int c = threadIdx.x % cw;
+  const size_t rs = (size_t)na * cw;  // row stride of the plane buffers
 #pragma unroll
   for (int k = 0; k < Q; ++k)
     if (ps.p[k] >= 0) b0[ps.p[k] * cw + c] = u[k];
   __syncthreads();
   if (!inverse) {
-    // pass A along a: g(ma, b) = sum_a twa(ma, a) f(a, b)
+    // pass A along a: g(ma, b) = sum_a w_ma^a f(a, b)
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       if (ps.p[k] >= 0) {
         const int ma = ps.p[k] % na, b = ps.p[k] / na;
-        cx<double> s = mkc(0.0, 0.0);
+        const cx<double> w = st.fa[ma];
+        cx<double> t = mkc(1.0, 0.0), s = mkc(0.0, 0.0);
+        const cx<R>* row = b0 + b * rs + c;
         for (int a = 0; a < na; ++a) {
-          const cx<double> f = to64(b0[(b * na + a) * cw + c]);
-          const cx<double> t = twa[ma * na + a];
-          s = s + cmul(t, f);
+          s = s + cmul(t, to64(row[a * cw]));
+          t = cmul(t, w);
         }
         b1[ps.p[k] * cw + c] = fromd<R>(s);
       }
     }
     __syncthreads();
-    // pass B along b
+    // pass B along b: F(ma, mb) = sum_b w_mb^b g(ma, b)
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       if (ps.p[k] >= 0) {
         const int ma = ps.p[k] % na, mb = ps.p[k] / na;
-        cx<double> s = mkc(0.0, 0.0);
+        const cx<double> w = st.fb[mb];
+        cx<double> t = mkc(1.0, 0.0), s = mkc(0.0, 0.0);
+        const cx<R>* col = b1 + ma * cw + c;
         for (int b = 0; b < nb; ++b) {
-          const cx<double> f = to64(b1[(b * na + ma) * cw + c]);
-          const cx<double> t = twb[mb * nb + b];
-          s = s + cmul(t, f);
+          s = s + cmul(t, to64(col[b * rs]));
+          t = cmul(t, w);
         }
         out[k] = fromd<R>(s);
       }
     }
   } else {
-    // pass A' along ma: h(a, mb) = sum_ma conj(twa(ma, a)) F(ma, mb)
+    // pass A' along ma: h(a, mb) = exp(i k_a a h) sum_ma v_a^ma F(ma, mb)
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       if (ps.p[k] >= 0) {
         const int a = ps.p[k] % na, mb = ps.p[k] / na;
-        cx<double> s = mkc(0.0, 0.0);
+        const cx<double> v = st.ia[a];
+        cx<double> t = mkc(1.0, 0.0), s = mkc(0.0, 0.0);
+        const cx<R>* row = b0 + mb * rs + c;
         for (int ma = 0; ma < na; ++ma) {
-          const cx<double> f = to64(b0[(mb * na + ma) * cw + c]);
-          const cx<double> t = twa[ma * na + a];
-          s = s + cmulc(t, f);
+          s = s + cmul(t, to64(row[ma * cw]));
+          t = cmul(t, v);
         }
-        b1[ps.p[k] * cw + c] = fromd<R>(s);
+        b1[ps.p[k] * cw + c] = fromd<R>(cmul(st.pa[a], s));
       }
     }
     __syncthreads();
+    // pass B' along mb: f(a, b) = exp(i k_b b h) / (Na Nb) sum_mb v_b^mb h(a, mb)
     const double inv_p = 1.0 / (double)(na * nb);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       if (ps.p[k] >= 0) {
         const int a = ps.p[k] % na, b = ps.p[k] / na;
-        cx<double> s = mkc(0.0, 0.0);
+        const cx<double> v = st.ib[b];
+        cx<double> t = mkc(1.0, 0.0), s = mkc(0.0, 0.0);
+        const cx<R>* col = b1 + a * cw + c;
         for (int mb = 0; mb < nb; ++mb) {
-          const cx<double> f = to64(b1[(mb * na + a) * cw + c]);
-          const cx<double> t = twb[mb * nb + b];
-          s = s + cmulc(t, f);
+          s = s + cmul(t, to64(col[mb * rs]));
+          t = cmul(t, v);
         }
-        out[k] = fromd<R>(cscale(s, inv_p));
+        out[k] = fromd<R>(cscale(cmul(st.pb[b], s), inv_p));
       }
     }
   }
@@ -107,7 +129,7 @@ __device__ __forceinline__ void lateral_dft(const Geo& g, const Pos<Q>& ps, int 
 // elimination into pv.w.
 template <int Q, class R>
 __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, const Pos<Q>& ps,
-                                           const PcConst& K, const cx<double>* twa, const cx<double>* twb,
+                                           const PcConst& K, const DftSteps& dst_,
                                            int IN, double (&dots)[4]) {
   const Geo& g = *C.g;
   const int cw = C.cw;
@@ -160,7 +182,7 @@ __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, 
         u[k] = sv;
       }
     }
-    lateral_dft<Q, R>(g, ps, cw, C.L.inpl0, C.L.inpl1, twa, twb, false, u, f);
+    lateral_dft<Q, R>(g, ps, cw, C.L.inpl0, C.L.inpl1, dst_, false, u, f);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       if (ps.p[k] < 0) continue;
@@ -177,7 +199,7 @@ __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, 
 // Backward sweep: back substitution, inverse DFT, write dst, gather into acc.
 template <int Q, class R>
 __device__ __forceinline__ void pc_backward(SweepCtx<R>& C, const PcVecs<R>& pv, const Pos<Q>& ps,
-                                            const PcConst& K, const cx<double>* twa, const cx<double>* twb,
+                                            const PcConst& K, const DftSteps& dst_,
                                             cx<R>* dst) {
   const Geo& g = *C.g;
   const Proj& pj = *C.pj;
@@ -202,7 +224,7 @@ __device__ __forceinline__ void pc_backward(SweepCtx<R>& C, const PcVecs<R>& pv,
       xnext[k] = xv;
       m[k] = xv;
     }
-    lateral_dft<Q, R>(g, ps, cw, C.L.inpl0, C.L.inpl1, twa, twb, true, m, u);
+    lateral_dft<Q, R>(g, ps, cw, C.L.inpl0, C.L.inpl1, dst_, true, m, u);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       if (ps.p[k] < 0) continue;
@@ -242,8 +264,8 @@ template <int RAD, int Q, class R>
 __device__ __forceinline__ void pc_true_residual_and_restart(const SolveArgs& A, SweepCtx<R>& C,
                                                              const PcVecs<R>& pv, const Pos<Q>& ps,
                                                              const ProjArrays& PA, const PcConst& K,
-                                                             const cx<double>* twa, const cx<double>* twb,
-                                                             bool final_check, bool& all_done) {
+                                                             const DftSteps& dst_, bool final_check,
+                                                             bool& all_done) {
   ColState& S = *C.S;
   const int cw = A.cw;
   const int tid = threadIdx.x;
@@ -312,11 +334,11 @@ __device__ __forceinline__ void pc_true_residual_and_restart(const SolveArgs& A,
   if (all_done) return;
   // restart: p = r, ph = M^-1 p, v = A ph
   double d2[4] = {0, 0, 0, 0};
-  pc_forward<Q, R>(C, pv, ps, K, twa, twb, PC_RESTART, d2);
+  pc_forward<Q, R>(C, pv, ps, K, dst_, PC_RESTART, d2);
   zero_acc<R>(PA.Pr, ncw);
   __syncthreads();
   C.acc = PA.Pr;
-  pc_backward<Q, R>(C, pv, ps, K, twa, twb, pv.ph);
+  pc_backward<Q, R>(C, pv, ps, K, dst_, pv.ph);
   set_dco(A.pj, cw, C.L.dco, PA.Pr);
   __syncthreads();
   pc_apply<RAD, Q, R, false>(C, pv, ps, d2);
@@ -327,7 +349,7 @@ __device__ __forceinline__ void pc_true_residual_and_restart(const SolveArgs& A,
 template <int RAD, int Q, class R>
 __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C, const PcVecs<R>& pv,
                                               const Pos<Q>& ps, const ProjArrays& PA, const PcConst& K,
-                                              const cx<double>* twa, const cx<double>* twb, int item) {
+                                              const DftSteps& dst_, int item) {
   ColState& S = *C.S;
   const Geo& g = A.g;
   const int cw = A.cw;
@@ -377,11 +399,11 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
   }
   __syncthreads();
   double dots[4] = {0, 0, 0, 0};
-  pc_forward<Q, R>(C, pv, ps, K, twa, twb, PC_INIT, dots);
+  pc_forward<Q, R>(C, pv, ps, K, dst_, PC_INIT, dots);
   zero_acc<R>(PA.Pr, ncw);
   __syncthreads();
   C.acc = PA.Pr;
-  pc_backward<Q, R>(C, pv, ps, K, twa, twb, pv.ph);
+  pc_backward<Q, R>(C, pv, ps, K, dst_, pv.ph);
   set_dco(A.pj, cw, C.L.dco, PA.Pr);
   __syncthreads();
   pc_apply<RAD, Q, R, false>(C, pv, ps, dots);
@@ -392,7 +414,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
   int it = 0;
   while (!all_done) {
     if (it >= A.max_iter) {
-      pc_true_residual_and_restart<RAD, Q, R>(A, C, pv, ps, PA, K, twa, twb, true, all_done);
+      pc_true_residual_and_restart<RAD, Q, R>(A, C, pv, ps, PA, K, dst_, true, all_done);
       break;
     }
     ++it;
@@ -414,16 +436,16 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
     }
     __syncthreads();
     if (S.any_flag) {
-      pc_true_residual_and_restart<RAD, Q, R>(A, C, pv, ps, PA, K, twa, twb, false, all_done);
+      pc_true_residual_and_restart<RAD, Q, R>(A, C, pv, ps, PA, K, dst_, false, all_done);
       continue;
     }
     // s = r - alpha v, sh = M^-1 s, t = A sh
     for (int k = 0; k < 4; ++k) dots[k] = 0;
-    pc_forward<Q, R>(C, pv, ps, K, twa, twb, PC_S, dots);
+    pc_forward<Q, R>(C, pv, ps, K, dst_, PC_S, dots);
     zero_acc<R>(PA.Pp, ncw);
     __syncthreads();
     C.acc = PA.Pp;
-    pc_backward<Q, R>(C, pv, ps, K, twa, twb, pv.sh);
+    pc_backward<Q, R>(C, pv, ps, K, dst_, pv.sh);
     set_dco(A.pj, cw, C.L.dco, PA.Pp);
     __syncthreads();
     for (int k = 0; k < 4; ++k) dots[k] = 0;
@@ -456,16 +478,16 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
       __syncthreads();
     }
     if (S.any_flag) {
-      pc_true_residual_and_restart<RAD, Q, R>(A, C, pv, ps, PA, K, twa, twb, false, all_done);
+      pc_true_residual_and_restart<RAD, Q, R>(A, C, pv, ps, PA, K, dst_, false, all_done);
       continue;
     }
     // x += alpha ph + omega sh, r = s - omega t, p = r + beta (p - omega v); ph = M^-1 p; v = A ph
     for (int k = 0; k < 4; ++k) dots[k] = 0;
-    pc_forward<Q, R>(C, pv, ps, K, twa, twb, PC_MERGED, dots);
+    pc_forward<Q, R>(C, pv, ps, K, dst_, PC_MERGED, dots);
     zero_acc<R>(PA.Pr, ncw);
     __syncthreads();
     C.acc = PA.Pr;
-    pc_backward<Q, R>(C, pv, ps, K, twa, twb, pv.ph);
+    pc_backward<Q, R>(C, pv, ps, K, dst_, pv.ph);
     set_dco(A.pj, cw, C.L.dco, PA.Pr);
     __syncthreads();
     double d2[4] = {0, 0, 0, 0};
@@ -488,7 +510,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
       __syncthreads();
     }
     if (S.any_flag)
-      pc_true_residual_and_restart<RAD, Q, R>(A, C, pv, ps, PA, K, twa, twb, false, all_done);
+      pc_true_residual_and_restart<RAD, Q, R>(A, C, pv, ps, PA, K, dst_, false, all_done);
   }
   if (tid < cw) {
     const int c = tid;
@@ -554,17 +576,20 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab_pc(const Solv
   const size_t np = (size_t)A.pj.nproj * cw;
   cx<double>* pb = reinterpret_cast<cx<double>*>(A.pws) + (size_t)blockIdx.x * A.pws_stride;
   ProjArrays PA{pb, pb + np, pb + 2 * np, pb + 3 * np, pb + 4 * np};
-  // DFT tables in LDS after the solver's regions
-  cx<double>* twa = reinterpret_cast<cx<double>*>(smem + A.pc_lds_off);
-  cx<double>* twb = twa + A.g.na * A.g.na;
-  for (int w = threadIdx.x; w < A.g.na * A.g.na; w += blockDim.x) {
-    const double2 t = A.pc.twa[w];
-    twa[w] = mkc(t.x, t.y);
+  // DFT step tables in LDS after the solver's regions: fa[na] fb[nb] ia[na] ib[nb] pa[na] pb[nb]
+  cx<double>* tab = reinterpret_cast<cx<double>*>(smem + A.pc_lds_off);
+  const int ntab = 3 * (A.g.na + A.g.nb);
+  for (int w = threadIdx.x; w < ntab; w += blockDim.x) {
+    const double2 t = A.pc.steps[w];
+    tab[w] = mkc(t.x, t.y);
   }
-  for (int w = threadIdx.x; w < A.g.nb * A.g.nb; w += blockDim.x) {
-    const double2 t = A.pc.twb[w];
-    twb[w] = mkc(t.x, t.y);
-  }
+  DftSteps dst_;
+  dst_.fa = tab;
+  dst_.fb = tab + A.g.na;
+  dst_.ia = tab + A.g.na + A.g.nb;
+  dst_.ib = tab + 2 * A.g.na + A.g.nb;
+  dst_.pa = tab + 2 * A.g.na + 2 * A.g.nb;
+  dst_.pb = tab + 3 * A.g.na + 2 * A.g.nb;
   __syncthreads();
   const Pos<Q> ps = make_pos<Q>(A.g, cw, RAD);
   for (;;) {
@@ -572,7 +597,7 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab_pc(const Solv
     __syncthreads();
     const int item = S.item;
     if (item >= A.nitems) break;
-    pc_solve_item<RAD, Q, R>(A, C, pv, ps, PA, A.pc, twa, twb, item);
+    pc_solve_item<RAD, Q, R>(A, C, pv, ps, PA, A.pc, dst_, item);
   }
 }
 
