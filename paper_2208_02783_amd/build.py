@@ -45,13 +45,18 @@ def build(verbose: bool = False, jobs: int | None = None, out: str = LIB, define
             cmd = [HIPCC, *FLAGS, *defs, *[f"-D{d}" for d in defines], "-c", "-o", obj, src]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            procs.append((subprocess.Popen(cmd), cmd))
+            procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT), cmd))
             objs.append(obj)
         p, cmd = procs.pop(0)
-        if p.wait() != 0:
+        text = p.communicate()[0].decode(errors="replace")
+        # hipcc's host pass warns that it does not know the device-only feature flag
+        msgs = [l for l in text.splitlines() if "packed-fp32-ops" not in l]
+        if p.returncode != 0:
             for q, _ in procs:
                 q.wait()
-            raise RuntimeError("hipcc failed: " + " ".join(cmd))
+            raise RuntimeError("hipcc failed: " + " ".join(cmd) + "\n" + "\n".join(msgs))
+        if verbose and msgs:
+            print("\n".join(msgs), flush=True)
     tmp = out + ".tmp"
     link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

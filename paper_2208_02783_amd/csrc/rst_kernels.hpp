@@ -79,6 +79,50 @@ __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
 }
 __device__ __forceinline__ bool finite2(cx<double> a) { return isfinite(a.x) && isfinite(a.y); }
 
+// Streaming (non-temporal) access to the Krylov vectors: they are touched once
+// per sweep, so they should not evict the shared tables from L2.
+#ifndef RST_NT
+#define RST_NT 1
+#endif
+typedef double rst_d2 __attribute__((ext_vector_type(2)));
+typedef float rst_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cx<double> ldv(const cx<double>* p) {
+#if RST_NT
+  const rst_d2 v = __builtin_nontemporal_load(reinterpret_cast<const rst_d2*>(p));
+  return mkc(v.x, v.y);
+#else
+  return *p;
+#endif
+}
+__device__ __forceinline__ cx<float> ldv(const cx<float>* p) {
+#if RST_NT
+  const rst_f2 v = __builtin_nontemporal_load(reinterpret_cast<const rst_f2*>(p));
+  return mkc(v.x, v.y);
+#else
+  return *p;
+#endif
+}
+__device__ __forceinline__ void stv(cx<double>* p, const cx<double>& v) {
+#if RST_NT
+  rst_d2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<rst_d2*>(p));
+#else
+  *p = v;
+#endif
+}
+__device__ __forceinline__ void stv(cx<float>* p, const cx<float>& v) {
+#if RST_NT
+  rst_f2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<rst_f2*>(p));
+#else
+  *p = v;
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // Kernel arguments
 // ---------------------------------------------------------------------------
@@ -121,6 +165,7 @@ struct PcConst {
   double a;              // 1/2 / hz^2 (three-point z coupling)
   const double* eps;     // [P] lateral mode energies eps_perp(m)
   const double2* steps;  // [3(na+nb)] DFT recurrence steps fa, fb, ia, ib and phases pa, pb
+  const double2* inv;    // [ne*nz*P] reciprocal Thomas pivots per energy, plane, lateral mode
 };
 
 struct SolveArgs {

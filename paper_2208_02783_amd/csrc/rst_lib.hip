@@ -21,6 +21,31 @@ __global__ void k_fill_int(int* p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
+
+// Reciprocal Thomas pivots of the preconditioner for every (energy, lateral
+// mode): den_0 = b_0, den_z = b_z - a^2 / den_{z-1}, with
+// b_z = E - Vbar - eps_perp(m) - 2a + i Gamma(z).  One thread per (E, m).
+__global__ void k_pc_pivots(const SolveArgs* __restrict__ Ap) {
+  const SolveArgs& A = *Ap;
+  const int P = A.g.P, nz = A.g.nz;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)A.ne * P) return;
+  const int e = (int)(t / P), m = (int)(t % P);
+  const double a = A.pc.a, a2 = a * a;
+  const double re0 = A.energies[e] - A.pc.vbar - A.pc.eps[m] - 2.0 * a;
+  double2* inv = const_cast<double2*>(A.pc.inv) + (size_t)e * nz * P;
+  cx<double> iv = mkc(0.0, 0.0);
+  for (int z = 0; z < nz; ++z) {
+    cx<double> den = mkc(re0, A.gz[z]);
+    if (z > 0) den = den - cscale(iv, a2);
+    iv = cdiv(mkc(1.0, 0.0), den);
+    double2 o;
+    o.x = iv.x;
+    o.y = iv.y;
+    inv[(size_t)z * P + m] = o;
+  }
+}
+
 }  // namespace rst
 
 namespace {
@@ -73,7 +98,7 @@ struct rst_ctx {
   // solver
   rst_solver_opts opts;
   // work buffers (grown on demand)
-  DevBuf d_ws, d_pws, d_cols, d_en, d_T, d_it, d_rs, d_res, d_st, d_counter, d_args;
+  DevBuf d_ws, d_pws, d_cols, d_en, d_T, d_it, d_rs, d_res, d_st, d_counter, d_args, d_pc_inv;
   // host copies of the last kernel-argument blocks (kept alive for async copies)
   rst::SolveArgs h_solve;
   rst::ApplyArgs h_apply;
@@ -497,8 +522,8 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
   long long nwg = std::min<long long>(nitems, (long long)per_cu * ncu);
   // bound the workspace to a quarter of free memory
-  // x r p v t (+ ph sh s w and the item's Thomas pivots with the preconditioner)
-  const size_t ws_stride = pc ? 9 * n * ls.cw + n : 5 * n * ls.cw;  // elements of cx<double>
+  // x r p v t (+ ph sh s w with the preconditioner)
+  const size_t ws_stride = pc ? 9 * n * ls.cw : 5 * n * ls.cw;  // elements of cx<double>
   size_t free_b = 0, total_b = 0;
   HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
   const size_t per_wg = ws_stride * sizeof(cx<double>) + 5 * (size_t)c->nproj * ls.cw * 16;
@@ -529,6 +554,8 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
     A.pc.a = 0.5 / (c->hz * c->hz);
     A.pc.eps = (const double*)c->d_pc_eps.p;
     A.pc.steps = (const double2*)c->d_pc_twa.p;
+    if ((s = ensure(c, c->d_pc_inv, (size_t)ne * n * 16)) != RST_OK) return s;
+    A.pc.inv = (const double2*)c->d_pc_inv.p;
   }
   A.V = (const double*)c->d_v.p;
   A.gz = (const double*)c->d_gz.p;
@@ -559,6 +586,12 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   if ((s = ensure(c, c->d_args, sizeof(A))) != RST_OK) return s;
   c->h_solve = A;
   HIPCHK(c, hipMemcpyAsync(c->d_args.p, &c->h_solve, sizeof(A), hipMemcpyHostToDevice, c->stream));
+  if (pc) {
+    const long long nt = (long long)ne * c->na * c->nb;
+    hipLaunchKernelGGL(rst::k_pc_pivots, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
+                       (const rst::SolveArgs*)c->d_args.p);
+    HIPCHK(c, hipGetLastError());
+  }
   void* dargs = c->d_args.p;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));

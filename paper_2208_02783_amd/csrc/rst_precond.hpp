@@ -24,7 +24,7 @@ struct PcVecs {
   cx<R>* sh;   // M^-1 s
   cx<R>* s;
   cx<R>* w;    // forward-eliminated values in mode space
-  cx<double>* inv;  // [nz*P] reciprocal Thomas pivots of this item
+  const cx<double>* inv;  // [nz*P] reciprocal Thomas pivots of the current item's energy
 };
 
 // Lateral DFT of the plane held in the positions' values u[k] -> modes out[k].
@@ -155,29 +155,30 @@ __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, 
       const size_t off = (size_t)gi * cw + c;
       if (IN == PC_INIT) {
         const cx<R> bb = (gi == src) ? mkc<R>(bsc, (R)0) : mkc<R>((R)0, (R)0);
-        C.vec.x[off] = mkc<R>((R)0, (R)0);
-        C.vec.r[off] = bb;
-        C.vec.p[off] = bb;
+        stv(&C.vec.x[off], mkc<R>((R)0, (R)0));
+        stv(&C.vec.r[off], bb);
+        stv(&C.vec.p[off], bb);
         u[k] = bb;
       } else if (IN == PC_MERGED) {
-        const cx<R> xv = C.vec.x[off], phv = pv.ph[off], shv = pv.sh[off], sv = pv.s[off];
-        const cx<R> tv = C.vec.t[off], pvv = C.vec.p[off], vv = C.vec.v[off];
+        const cx<R> xv = ldv(&C.vec.x[off]), phv = ldv(&pv.ph[off]), shv = ldv(&pv.sh[off]),
+                    sv = ldv(&pv.s[off]);
+        const cx<R> tv = ldv(&C.vec.t[off]), pvv = ldv(&C.vec.p[off]), vv = ldv(&C.vec.v[off]);
         const cx<R> xn = xv + cmul(al, phv) + cmul(om, shv);
         const cx<R> rn = sv - cmul(om, tv);
         const cx<R> pn = rn + cmul(be, pvv - cmul(om, vv));
-        C.vec.x[off] = xn;
-        C.vec.r[off] = rn;
-        C.vec.p[off] = pn;
+        stv(&C.vec.x[off], xn);
+        stv(&C.vec.r[off], rn);
+        stv(&C.vec.p[off], pn);
         dots[0] += (double)cnorm2(rn);
         u[k] = pn;
       } else if (IN == PC_RESTART) {
-        const cx<R> rv = C.vec.r[off];
-        C.vec.p[off] = rv;
+        const cx<R> rv = ldv(&C.vec.r[off]);
+        stv(&C.vec.p[off], rv);
         if (gi == j0) S->rj[c] = to64(rv);
         u[k] = rv;
       } else {  // PC_S
-        const cx<R> sv = C.vec.r[off] - cmul(al, C.vec.v[off]);
-        pv.s[off] = sv;
+        const cx<R> sv = ldv(&C.vec.r[off]) - cmul(al, ldv(&C.vec.v[off]));
+        stv(&pv.s[off], sv);
         if (gi == j0) S->sj[c] = to64(sv);
         u[k] = sv;
       }
@@ -189,7 +190,7 @@ __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, 
       const size_t mi = (size_t)z * g.P + ps.p[k];
       const cx<R> iv = fromd<R>(pv.inv[mi]);
       const cx<R> d = cmul(f[k] - cscale(dprev[k], a), iv);
-      pv.w[mi * cw + c] = d;
+      stv(&pv.w[mi * cw + c], d);
       dprev[k] = d;
     }
   }
@@ -218,7 +219,7 @@ __device__ __forceinline__ void pc_backward(SweepCtx<R>& C, const PcVecs<R>& pv,
       m[k] = mkc<R>((R)0, (R)0);
       if (ps.p[k] < 0) continue;
       const size_t mi = (size_t)z * g.P + ps.p[k];
-      const cx<R> d = pv.w[mi * cw + c];
+      const cx<R> d = ldv(&pv.w[mi * cw + c]);
       const cx<R> iv = fromd<R>(pv.inv[mi]);
       const cx<R> xv = d - cscale(cmul(iv, xnext[k]), a);
       xnext[k] = xv;
@@ -229,7 +230,7 @@ __device__ __forceinline__ void pc_backward(SweepCtx<R>& C, const PcVecs<R>& pv,
     for (int k = 0; k < Q; ++k) {
       if (ps.p[k] < 0) continue;
       const size_t off = ((size_t)z * g.P + ps.p[k]) * cw + c;
-      dst[off] = u[k];
+      stv(&dst[off], u[k]);
       if (do_gather) C.L.outpl[ps.p[k] * cw + c] = u[k];
     }
     if (do_gather) {
@@ -347,7 +348,7 @@ __device__ __forceinline__ void pc_true_residual_and_restart(const SolveArgs& A,
 }
 
 template <int RAD, int Q, class R>
-__device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C, const PcVecs<R>& pv,
+__device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C, PcVecs<R>& pv,
                                               const Pos<Q>& ps, const ProjArrays& PA, const PcConst& K,
                                               const DftSteps& dst_, int item) {
   ColState& S = *C.S;
@@ -382,21 +383,8 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
       S.state[c] = 3;
     }
   }
-  // Thomas pivots of this item's energy, one recursion per lateral mode
-  {
-    const double en = A.energies[e_idx];
-    const double a2 = K.a * K.a;
-    for (int m = tid; m < g.P; m += blockDim.x) {
-      const double re0 = en - K.vbar - K.eps[m] - 2.0 * K.a;
-      cx<double> inv = mkc(0.0, 0.0);
-      for (int z = 0; z < g.nz; ++z) {
-        cx<double> den = mkc(re0, A.gz[z]);
-        if (z > 0) den = den - cscale(inv, a2);
-        inv = cdiv(mkc(1.0, 0.0), den);
-        pv.inv[(size_t)z * g.P + m] = inv;
-      }
-    }
-  }
+  // this item's energy selects its slice of the shared Thomas pivots
+  pv.inv = reinterpret_cast<const cx<double>*>(K.inv) + (size_t)e_idx * g.nz * g.P;
   __syncthreads();
   double dots[4] = {0, 0, 0, 0};
   pc_forward<Q, R>(C, pv, ps, K, dst_, PC_INIT, dots);
@@ -572,7 +560,7 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab_pc(const Solv
   pv.sh = base + 6 * nv;
   pv.s = base + 7 * nv;
   pv.w = base + 8 * nv;
-  pv.inv = reinterpret_cast<cx<double>*>(base + 9 * nv);
+  pv.inv = nullptr;
   const size_t np = (size_t)A.pj.nproj * cw;
   cx<double>* pb = reinterpret_cast<cx<double>*>(A.pws) + (size_t)blockIdx.x * A.pws_stride;
   ProjArrays PA{pb, pb + np, pb + 2 * np, pb + 3 * np, pb + 4 * np};

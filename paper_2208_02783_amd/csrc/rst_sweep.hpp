@@ -60,44 +60,44 @@ __device__ __forceinline__ cx<R> load_in(const SweepCtx<R>& C, int mode, int zl,
   switch (mode) {
     case IN_INIT: {
       const cx<R> u = (gi == S->src[c]) ? mkc<R>((R)S->bsc[c], (R)0) : mkc<R>((R)0, (R)0);
-      C.vec.x[off] = mkc<R>((R)0, (R)0);
-      C.vec.r[off] = u;
-      C.vec.p[off] = u;
+      stv(&C.vec.x[off], mkc<R>((R)0, (R)0));
+      stv(&C.vec.r[off], u);
+      stv(&C.vec.p[off], u);
       return u;
     }
     case IN_A: {
-      const cx<R> rv = C.vec.r[off];
-      const cx<R> vv = C.vec.v[off];
-      const cx<R> tv = C.vec.t[off];
-      const cx<R> pv = C.vec.p[off];
-      const cx<R> xv = C.vec.x[off];
+      const cx<R> rv = ldv(&C.vec.r[off]);
+      const cx<R> vv = ldv(&C.vec.v[off]);
+      const cx<R> tv = ldv(&C.vec.t[off]);
+      const cx<R> pv = ldv(&C.vec.p[off]);
+      const cx<R> xv = ldv(&C.vec.x[off]);
       const cx<R> s = rv - cmul(al, vv);
       const cx<R> xn = xv + cmul(al, pv) + cmul(om, s);
       const cx<R> rn = s - cmul(om, tv);
       const cx<R> pn = rn + cmul(be, pv - cmul(om, vv));
-      C.vec.x[off] = xn;
-      C.vec.r[off] = rn;
-      C.vec.p[off] = pn;
+      stv(&C.vec.x[off], xn);
+      stv(&C.vec.r[off], rn);
+      stv(&C.vec.p[off], pn);
       d0 += (double)cnorm2(rn);
       return pn;
     }
     case IN_RESTART: {
-      const cx<R> rv = C.vec.r[off];
-      C.vec.p[off] = rv;
+      const cx<R> rv = ldv(&C.vec.r[off]);
+      stv(&C.vec.p[off], rv);
       if (gi == S->j0[c]) S->rj[c] = to64(rv);
       return rv;
     }
     case IN_B: {
-      const cx<R> rv = C.vec.r[off];
-      const cx<R> vv = C.vec.v[off];
+      const cx<R> rv = ldv(&C.vec.r[off]);
+      const cx<R> vv = ldv(&C.vec.v[off]);
       const cx<R> s = rv - cmul(al, vv);
       if (gi == S->j0[c]) S->sj[c] = to64(s);
       return s;
     }
     case IN_X:
-      return C.vec.x[off];
+      return ldv(&C.vec.x[off]);
     case IN_PC:
-      return C.pcsrc[off];
+      return ldv(&C.pcsrc[off]);
     default: {  // IN_EXT
       if (C.ext_c0 + c < C.ext_ncol) {
         const double2 v = C.xext[(size_t)gi * C.ext_ld + C.ext_c0 + c];
@@ -119,12 +119,12 @@ __device__ __forceinline__ void store_out(const SweepCtx<R>& C, int mode, long l
   const size_t off = (size_t)gi * cw + c;
   switch (mode) {
     case OUT_V:
-      C.vec.v[off] = y;
+      stv(&C.vec.v[off], y);
       if (gi == j0) S->vj[c] = to64(y);
       if (do_gather) C.L.outpl[p * cw + c] = y;
       break;
     case OUT_T: {
-      C.vec.t[off] = y;
+      stv(&C.vec.t[off], y);
       const cx<double> y64 = to64(y), u64 = to64(u);
       const cx<double> ts = cmulc(y64, u64);
       dots[1] += ts.x;
@@ -135,8 +135,8 @@ __device__ __forceinline__ void store_out(const SweepCtx<R>& C, int mode, long l
       break;
     }
     case OUT_TS: {
-      C.vec.t[off] = y;
-      const cx<double> y64 = to64(y), s64 = to64(C.pcs[off]);
+      stv(&C.vec.t[off], y);
+      const cx<double> y64 = to64(y), s64 = to64(ldv(&C.pcs[off]));
       const cx<double> ts = cmulc(y64, s64);
       dots[1] += ts.x;
       dots[2] += ts.y;
@@ -147,7 +147,7 @@ __device__ __forceinline__ void store_out(const SweepCtx<R>& C, int mode, long l
     case OUT_RES: {
       cx<R> rr = mkc<R>(-y.x, -y.y);
       if (gi == src) rr.x += (R)bsc;
-      C.vec.r[off] = rr;
+      stv(&C.vec.r[off], rr);
       const double n2 = (double)cnorm2(rr);
       dots[0] += n2;
       if (n2 > rmax || (n2 == rmax && gi < rmax_idx)) {
@@ -317,7 +317,7 @@ __device__ __forceinline__ void gather_sweep(SweepCtx<R>& C, const Pos<Q>& ps, c
             xv = mkc<R>((R)0, (R)0);
           }
         } else {
-          xv = C.vec.x[(size_t)gi * cw + c];
+          xv = ldv(&C.vec.x[(size_t)gi * cw + c]);
         }
         tacc += gd * (double)cnorm2(xv);
         if (need_g) C.L.outpl[ps.p[k] * cw + c] = xv;
