@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precond", type=int, default=1, help="1: free-electron + CAP, 0: none")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="fp64: FP64 throughout; mixed: FP32 applies inside FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="before the run, copy this many GiB device-to-device (a reference "
@@ -115,12 +117,16 @@ def main():
     prob = wl.config(2)
     ctx = rst.Context(0)
     ctx.load_problem(prob, prob.kpts[0])
-    ctx.rst_set_solver(tol=args.tol, precond=args.precond, max_iter=20000)
+    ctx.rst_set_solver(tol=args.tol, precond=args.precond, max_iter=20000,
+                       precision=rst.RST_FP32_REFINE if args.precision == "mixed" else rst.RST_FP64)
 
     def one(i):
         k, e = step_points(prob, i)
         ctx.rst_set_k(k[0], k[1])
         t, st, s = ctx.rst_transmission(np.array([e]))
+        print(f"step {i}: E={e:.4f} T={t[0]:.6f} status={s} iters/col="
+              f"{st['iterations_total'] / max(st['columns'], 1):.1f} kernel {st['kernel_ms']:.0f} ms",
+              file=sys.stderr, flush=True)
         return t[0], st, s, k, e
 
     for i in range(args.warmup):
@@ -149,7 +155,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": "FCC bulk slab 17x17x170 (h=0.401 bohr, a=6.82, 10 cells), 12th-order FD, "
@@ -158,6 +164,9 @@ def main():
             "solver": ("right-preconditioned BiCGSTAB, free-electron + CAP preconditioner"
                        if args.precond else "BiCGSTAB, no preconditioner"),
             "tol_true_rel_residual": args.tol,
+            "precision": ("FP64 throughout" if args.precision == "fp64" else
+                          "FP32 stencil/projector/preconditioner applies, FP64 refinement, "
+                          "inner products and true residual"),
             "points": [{"k": [float(r[3][0]), float(r[3][1])], "E": r[4], "T": r[0],
                         "status": int(r[2])} for r in res],
             "iterations_per_column_avg": iters / max(cols, 1),
@@ -170,7 +179,8 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": measured_traffic(bytes_alg / args.steps, args.precond),
+            "traffic": (measured_traffic(bytes_alg / args.steps, args.precond)
+                        if args.precision == "fp64" else None),
         },
     }
     if not args.no_cpu_baseline:

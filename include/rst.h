@@ -76,7 +76,9 @@ typedef struct {
   int threads;       /* workgroup size (multiple of 64, <= 512); 0 = automatic */
   int direction;     /* RST_DIR_LR: columns in the right CAP, T accumulated on the left (default);
                         RST_DIR_RL: the reverse.  Both give the same T (exact identity). */
-  double inner_tol;  /* RST_FP32_REFINE: relative tolerance of each FP32 inner solve (default 1e-5) */
+  double inner_tol;  /* RST_FP32_REFINE: relative tolerance of each FP32 inner solve (default 1e-4);
+                        an inner solve also ends after max_iter iterations or when its residual
+                        has not halved for 40 iterations (FP32 stagnation) */
   int max_outer;     /* RST_FP32_REFINE: refinement steps (default 30) */
   int precond;       /* rst_precond.  RST_PRECOND_FREE_CAP: right preconditioner
                         M = E - (-1/2 L_lat - 1/2 D2_z + Vbar) + i Gamma(z) with the exact
@@ -94,7 +96,11 @@ typedef struct {
   int32_t restarts_total;   /* breakdown restarts */
   double max_rel_residual;  /* largest FP64 true relative residual */
   double kernel_ms;         /* device time of the solver kernel(s) */
-  double bytes_algorithmic; /* algorithmic HBM bytes of the Krylov sweeps (see DESIGN) */
+  double bytes_algorithmic; /* algorithmic HBM bytes of the Krylov sweeps: FP64 BiCGSTAB 12 (plain) or
+                               24 (preconditioned) complex128 streams per grid point, iteration and
+                               column; RST_FP32_REFINE the same counts of complex64 streams plus
+                               14 complex128-equivalent streams per refinement step */
+  int64_t refinements_total; /* RST_FP32_REFINE: FP64 refinement steps summed over columns */
 } rst_stats;
 
 void rst_default_solver(rst_solver_opts *opts);

@@ -30,7 +30,7 @@ def build(verbose: bool = False, jobs: int | None = None, out: str = LIB, define
     objdir = tempfile.mkdtemp(prefix="rstbuild_")
     units = []
     # heaviest first: the preconditioned solvers, then the plain solvers, then apply
-    for kind in (2, 0, 1):
+    for kind in (4, 2, 3, 0, 1):
         for rad, q in INSTANCES:
             units.append((os.path.join(CSRC, "kern_inst.hip"),
                           os.path.join(objdir, f"k{kind}_r{rad}_q{q}.o"),

@@ -1,6 +1,6 @@
 // One (stencil radius, positions per thread) instance of the solver and apply
 // kernels; compiled once per pair so the instances build in parallel.
-#include "rst_precond.hpp"
+#include "rst_mixed.hpp"
 
 #if !defined(RST_RAD) || !defined(RST_Q) || !defined(RST_KIND)
 #error "RST_RAD, RST_Q and RST_KIND must be defined"
@@ -10,13 +10,18 @@
 #define RST_CAT(a, b) RST_CAT2(a, b)
 #define RST_KPTR RST_CAT(RST_CAT(RST_CAT(RST_CAT(RST_CAT(rst_kptr_k, RST_KIND), _r), RST_RAD), _q), RST_Q)
 
-// RST_KIND: 0 plain solver, 1 apply, 2 preconditioned solver
+// RST_KIND: 0 plain solver, 1 apply, 2 preconditioned solver,
+//           3 mixed-precision plain solver, 4 mixed-precision preconditioned solver
 extern "C" __attribute__((visibility("hidden"))) void* RST_KPTR() {
 #if RST_KIND == 0
   return (void*)rst::k_bicgstab<RST_RAD, RST_Q, double>;
 #elif RST_KIND == 1
   return (void*)rst::k_apply<RST_RAD, RST_Q, double>;
-#else
+#elif RST_KIND == 2
   return (void*)rst::k_bicgstab_pc<RST_RAD, RST_Q, double>;
+#elif RST_KIND == 3
+  return (void*)rst::k_mixed<RST_RAD, RST_Q, false>;
+#else
+  return (void*)rst::k_mixed<RST_RAD, RST_Q, true>;
 #endif
 }

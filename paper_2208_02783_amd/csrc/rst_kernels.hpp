@@ -172,6 +172,9 @@ struct SolveArgs {
   Geo g;
   Proj pj;
   PcConst pc;
+  double inner_tol;         // mixed precision: relative tolerance of each FP32 inner solve
+  int inner_max;            // mixed precision: iterations per inner solve
+  int max_outer;            // mixed precision: refinement steps
   size_t pc_lds_off;        // byte offset of the DFT tables in dynamic LDS
   const double* V;          // [n]
   const double* gz;         // [nz] Gamma_L + Gamma_R
@@ -212,7 +215,7 @@ struct ApplyArgs {
 // Sweep modes
 // ---------------------------------------------------------------------------
 
-enum InMode { IN_INIT, IN_A, IN_RESTART, IN_B, IN_X, IN_EXT, IN_PC };
+enum InMode { IN_INIT, IN_A, IN_RESTART, IN_B, IN_X, IN_EXT, IN_PC, IN_INIT_VEC };
 enum OutMode { OUT_V, OUT_T, OUT_RES, OUT_EXT, OUT_TS };
 
 // Per-column scalar state shared by the workgroup.
@@ -225,6 +228,10 @@ struct ColState {
   long long src[CW_MAX], j0[CW_MAX], rmax_idx[CW_MAX];
   int state[CW_MAX];       // 0 active, 1 done, 2 failed, 3 padding
   int iters[CW_MAX], restarts[CW_MAX];
+  // mixed precision: scale of the inner right-hand side r64 (1/||r64||), the
+  // inner solve's own state (0 running, 1 stopped) and the refinement steps
+  double rscale[CW_MAX], uscale[CW_MAX], ibest[CW_MAX];
+  int istate[CW_MAX], outer[CW_MAX], istall[CW_MAX];
   int any_flag;
   int item;
 };

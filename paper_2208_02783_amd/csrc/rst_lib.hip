@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "../../include/rst.h"
-#include "rst_precond.hpp"
+#include "rst_mixed.hpp"
 
 using rst::cx;
 
@@ -438,6 +438,14 @@ extern "C" void* rst_kptr_k2_r2_q1();
 extern "C" void* rst_kptr_k2_r2_q2();
 extern "C" void* rst_kptr_k2_r6_q1();
 extern "C" void* rst_kptr_k2_r6_q2();
+extern "C" void* rst_kptr_k3_r2_q1();
+extern "C" void* rst_kptr_k3_r2_q2();
+extern "C" void* rst_kptr_k3_r6_q1();
+extern "C" void* rst_kptr_k3_r6_q2();
+extern "C" void* rst_kptr_k4_r2_q1();
+extern "C" void* rst_kptr_k4_r2_q2();
+extern "C" void* rst_kptr_k4_r6_q1();
+extern "C" void* rst_kptr_k4_r6_q2();
 
 void* pick_kernel(int rad, int q, int w) {
   if (w == 0 && rad == 2 && q == 1) return rst_kptr_k0_r2_q1();
@@ -452,6 +460,14 @@ void* pick_kernel(int rad, int q, int w) {
   if (w == 2 && rad == 2 && q == 2) return rst_kptr_k2_r2_q2();
   if (w == 2 && rad == 6 && q == 1) return rst_kptr_k2_r6_q1();
   if (w == 2 && rad == 6 && q == 2) return rst_kptr_k2_r6_q2();
+  if (w == 3 && rad == 2 && q == 1) return rst_kptr_k3_r2_q1();
+  if (w == 3 && rad == 2 && q == 2) return rst_kptr_k3_r2_q2();
+  if (w == 3 && rad == 6 && q == 1) return rst_kptr_k3_r6_q1();
+  if (w == 3 && rad == 6 && q == 2) return rst_kptr_k3_r6_q2();
+  if (w == 4 && rad == 2 && q == 1) return rst_kptr_k4_r2_q1();
+  if (w == 4 && rad == 2 && q == 2) return rst_kptr_k4_r2_q2();
+  if (w == 4 && rad == 6 && q == 1) return rst_kptr_k4_r6_q1();
+  if (w == 4 && rad == 6 && q == 2) return rst_kptr_k4_r6_q2();
   return nullptr;
 }
 
@@ -503,7 +519,8 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   if (nitems > 0x7fffffff) return fail(c, RST_EINVAL, "too many column blocks");
   const size_t n = (size_t)c->na * c->nb * c->nz;
   const bool pc = c->opts.precond == RST_PRECOND_FREE_CAP;
-  void* kern = pick_kernel(c->rad, ls.q, pc ? 2 : 0);
+  const bool mixed = c->opts.precision == RST_FP32_REFINE;
+  void* kern = pick_kernel(c->rad, ls.q, mixed ? (pc ? 4 : 3) : (pc ? 2 : 0));
   if (!kern) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
   rst::Geo g = make_geo(c);
   rst::Proj pj = make_proj(c);
@@ -522,8 +539,10 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
   long long nwg = std::min<long long>(nitems, (long long)per_cu * ncu);
   // bound the workspace to a quarter of free memory
-  // x r p v t (+ ph sh s w with the preconditioner)
-  const size_t ws_stride = pc ? 9 * n * ls.cw : 5 * n * ls.cw;  // elements of cx<double>
+  // x r p v t (+ ph sh s w with the preconditioner); mixed: FP64 x, r and FP32 inner vectors
+  const size_t nfv = pc ? 9 : 5;
+  const size_t ws_stride = mixed ? 2 * n * ls.cw + (nfv * n * ls.cw + 1) / 2
+                                 : nfv * n * ls.cw;  // elements of cx<double>
   size_t free_b = 0, total_b = 0;
   HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
   const size_t per_wg = ws_stride * sizeof(cx<double>) + 5 * (size_t)c->nproj * ls.cw * 16;
@@ -570,6 +589,9 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   A.nitems = (int)nitems;
   A.tol = c->opts.tol;
   A.max_iter = c->opts.max_iter;
+  A.inner_tol = c->opts.inner_tol;
+  A.inner_max = c->opts.max_iter;
+  A.max_outer = c->opts.max_outer;
   A.ws = c->d_ws.p;
   A.ws_stride = ws_stride;
   A.pws = (double2*)c->d_pws.p;
@@ -628,7 +650,10 @@ void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const st
   for (size_t i = 0; i < its.size(); ++i) {
     s.iterations_total += its[i];
     s.iterations_max = std::max(s.iterations_max, its[i]);
-    s.restarts_total += rss[i];
+    if (c->opts.precision == RST_FP32_REFINE)
+      s.refinements_total += rss[i];
+    else
+      s.restarts_total += rss[i];
     s.max_rel_residual = std::max(s.max_rel_residual, res[i]);
     if (stv[i] != 0) ++nbad;
   }
@@ -636,7 +661,13 @@ void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const st
   s.kernel_ms = ms;
   const double n = (double)c->na * c->nb * c->nz;
   const double streams = c->opts.precond == RST_PRECOND_FREE_CAP ? 24.0 : 12.0;
-  s.bytes_algorithmic = (double)s.iterations_total * streams * 16.0 * n;
+  if (c->opts.precision == RST_FP32_REFINE)
+    // inner iterations on FP32 vectors; per refinement step: x64 update (read x64, d, write x64),
+    // FP64 residual (read x64, write r64) and the inner start (read r64, write x, r, p)
+    s.bytes_algorithmic = (double)s.iterations_total * streams * 8.0 * n +
+                          (double)s.refinements_total * (40.0 + 32.0 + 40.0) * n;
+  else
+    s.bytes_algorithmic = (double)s.iterations_total * streams * 16.0 * n;
   if (st) *st = s;
 }
 
@@ -654,7 +685,7 @@ void rst_default_solver(rst_solver_opts* o) {
   o->col_block = 0;
   o->threads = 0;
   o->direction = RST_DIR_LR;
-  o->inner_tol = 1e-5;
+  o->inner_tol = 1e-4;
   o->max_outer = 30;
   o->precond = RST_PRECOND_NONE;
 }
@@ -813,7 +844,9 @@ rst_status rst_set_k(rst_ctx* c, double ka, double kb) {
 rst_status rst_set_solver(rst_ctx* c, const rst_solver_opts* o) {
   if (!c || !o) return RST_EINVAL;
   if (o->method != RST_BICGSTAB) return fail(c, RST_EINVAL, "unknown method");
-  if (o->precision != RST_FP64) return fail(c, RST_EUNSUPPORTED, "only RST_FP64 is implemented");
+  if (o->precision != RST_FP64 && o->precision != RST_FP32_REFINE) return fail(c, RST_EINVAL, "unknown precision");
+  if (o->precision == RST_FP32_REFINE && (!(o->inner_tol > 0) || o->inner_tol >= 1 || o->max_outer < 1))
+    return fail(c, RST_EINVAL, "inner_tol must be in (0, 1) and max_outer >= 1");
   if (!(o->tol > 0) || o->max_iter < 1) return fail(c, RST_EINVAL, "tol must be > 0 and max_iter >= 1");
   if (o->col_block < 0 || o->col_block > rst::CW_MAX || (o->col_block & (o->col_block - 1)))
     return fail(c, RST_EINVAL, "col_block must be 0 or a power of two <= 8");

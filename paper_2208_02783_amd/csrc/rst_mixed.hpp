@@ -1,0 +1,547 @@
+// rst_mixed.hpp -- FP32 applies inside an FP64 iterative refinement.
+//
+// Per column: x = 0, r = b; repeat { d ~ A^-1 (r / ||r||) by BiCGSTAB with FP32
+// vectors and FP32 stencil / projector / preconditioner applies (inner
+// products, scalars and projections in FP64), stopped at a loose recursive
+// tolerance; x += ||r|| d in FP64; r = b - A x with an FP64 apply } until the
+// FP64 true residual ||r|| <= tol ||b||.  An inner breakdown just ends that
+// inner solve: the next refinement step restarts from the FP64 residual.
+#pragma once
+#include "rst_precond.hpp"
+
+namespace rst {
+
+constexpr int STALL_ITERS = 40;  // inner solve stops after this many iterations without progress
+
+// Inner FP32 BiCGSTAB without preconditioner; PA.Pr must hold B^H (rhs).
+template <int RAD, int Q>
+__device__ __forceinline__ void inner_plain(const SolveArgs& A, SweepCtx<float>& C, const Pos<Q>& ps,
+                                            const ProjArrays& PA) {
+  ColState& S = *C.S;
+  const int cw = A.cw;
+  const int tid = threadIdx.x;
+  const int ncw = A.pj.nproj * cw;
+  const double itol2 = A.inner_tol * A.inner_tol;  // the right-hand side has unit norm
+  if (tid < cw) {
+    S.alpha[tid] = S.omega[tid] = S.beta[tid] = mkc(0.0, 0.0);
+    S.ibest[tid] = 1.0;  // the right-hand side has unit norm
+    S.istall[tid] = 0;
+  }
+  for (int w = tid; w < ncw; w += blockDim.x) PA.Pp[w] = PA.Pr[w];
+  set_dco(A.pj, cw, C.L.dco, PA.Pr);
+  __syncthreads();
+  double dots[4] = {0, 0, 0, 0};
+  double rmax = 0;
+  long long ri = 0;
+  C.acc = PA.Pv;
+  sweep<RAD, Q, float>(C, ps, IN_INIT_VEC, OUT_V, dots, rmax, ri);
+  if (tid < cw) S.rho[tid] = S.rj[tid];
+  __syncthreads();
+  for (int it = 0; it < A.inner_max; ++it) {
+    if (tid == 0) S.any_flag = 0;
+    __syncthreads();
+    if (tid < cw) {
+      const int c = tid;
+      S.alpha[c] = mkc(0.0, 0.0);
+      if (S.istate[c] == 0) {
+        const cx<double> vj = S.vj[c];
+        if (!(cnorm2(vj) > 0.0) || !finite2(vj) || !finite2(S.rho[c]) || !(cnorm2(S.rho[c]) > 0.0)) {
+          S.istate[c] = 1;
+        } else {
+          S.alpha[c] = cdiv(S.rho[c], vj);
+          atomicOr(&S.any_flag, 1);
+        }
+      }
+    }
+    __syncthreads();
+    if (!S.any_flag) break;
+    for (int w = tid; w < ncw; w += blockDim.x) {
+      const int c = w % cw;
+      C.L.dco[w] = cscale(PA.Pr[w] - cmul(S.alpha[c], PA.Pv[w]), A.pj.ekb[w / cw]);
+    }
+    __syncthreads();
+    for (int k = 0; k < 4; ++k) dots[k] = 0;
+    C.acc = PA.Pt;
+    sweep<RAD, Q, float>(C, ps, IN_B, OUT_T, dots, rmax, ri);
+    {
+      __shared__ double red_out[4][CW_MAX];
+      col_reduce4(C.L.red, cw, dots, red_out);
+      if (tid < cw) {
+        const int c = tid;
+        const cx<double> ts = mkc(red_out[1][c], red_out[2][c]);
+        const double tt = red_out[3][c];
+        if (S.istate[c] == 0) {
+          const cx<double> om = (tt > 0.0 && isfinite(tt)) ? cscale(ts, 1.0 / tt) : mkc(0.0, 0.0);
+          const cx<double> rn = S.sj[c] - cmul(om, S.tj[c]);
+          if (!(cnorm2(om) > 0.0) || !finite2(om) || !(cnorm2(rn) > 0.0) || !finite2(rn)) {
+            S.istate[c] = 1;
+            S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
+          } else {
+            S.omega[c] = om;
+            S.rho_new[c] = rn;
+            S.beta[c] = cmul(cdiv(rn, S.rho[c]), cdiv(S.alpha[c], om));
+          }
+        } else {
+          S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
+        }
+      }
+      __syncthreads();
+    }
+    for (int w = tid; w < ncw; w += blockDim.x) {
+      const int c = w % cw;
+      const cx<double> al = S.alpha[c], om = S.omega[c], be = S.beta[c];
+      const cx<double> Ps = PA.Pr[w] - cmul(al, PA.Pv[w]);
+      const cx<double> Prn = Ps - cmul(om, PA.Pt[w]);
+      const cx<double> Ppn = Prn + cmul(be, PA.Pp[w] - cmul(om, PA.Pv[w]));
+      PA.Pr[w] = Prn;
+      PA.Pp[w] = Ppn;
+      C.L.dco[w] = cscale(Ppn, A.pj.ekb[w / cw]);
+    }
+    __syncthreads();
+    for (int k = 0; k < 4; ++k) dots[k] = 0;
+    C.acc = PA.Pv;
+    sweep<RAD, Q, float>(C, ps, IN_A, OUT_V, dots, rmax, ri);
+    {
+      __shared__ double red_out[4][CW_MAX];
+      col_reduce4(C.L.red, cw, dots, red_out);
+      if (tid < cw) {
+        const int c = tid;
+        if (S.istate[c] == 0) {
+          S.iters[c] += 1;
+          S.rho[c] = S.rho_new[c];
+          const double rr = red_out[0][c];
+          if (!isfinite(rr) || rr <= itol2) S.istate[c] = 1;
+          // stagnation: no halving of the best residual norm for STALL_ITERS iterations
+          if (rr < 0.25 * S.ibest[c]) {
+            S.ibest[c] = rr;
+            S.istall[c] = 0;
+          } else if (++S.istall[c] >= STALL_ITERS) {
+            S.istate[c] = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Inner FP32 right-preconditioned BiCGSTAB.
+template <int RAD, int Q>
+__device__ __forceinline__ void inner_pc(const SolveArgs& A, SweepCtx<float>& C, const PcVecs<float>& pv,
+                                         const Pos<Q>& ps, const ProjArrays& PA, const PcConst& K,
+                                         const DftSteps& dst_) {
+  ColState& S = *C.S;
+  const int cw = A.cw;
+  const int tid = threadIdx.x;
+  const double itol2 = A.inner_tol * A.inner_tol;
+  if (tid < cw) {
+    S.alpha[tid] = S.omega[tid] = S.beta[tid] = mkc(0.0, 0.0);
+    S.ibest[tid] = 1.0;  // the right-hand side has unit norm
+    S.istall[tid] = 0;
+  }
+  __syncthreads();
+  double dots[4] = {0, 0, 0, 0};
+  pc_forward<Q, float>(C, pv, ps, K, dst_, PC_INIT_VEC, dots);
+  C.acc = PA.Pr;
+  pc_backward<Q, float>(C, pv, ps, K, dst_, pv.ph);
+  set_dco(A.pj, cw, C.L.dco, PA.Pr);
+  __syncthreads();
+  pc_apply<RAD, Q, float, false>(C, pv, ps, dots);
+  if (tid < cw) S.rho[tid] = S.rj[tid];
+  __syncthreads();
+  for (int it = 0; it < A.inner_max; ++it) {
+    if (tid == 0) S.any_flag = 0;
+    __syncthreads();
+    if (tid < cw) {
+      const int c = tid;
+      S.alpha[c] = mkc(0.0, 0.0);
+      if (S.istate[c] == 0) {
+        const cx<double> vj = S.vj[c];
+        if (!(cnorm2(vj) > 0.0) || !finite2(vj) || !finite2(S.rho[c]) || !(cnorm2(S.rho[c]) > 0.0)) {
+          S.istate[c] = 1;
+        } else {
+          S.alpha[c] = cdiv(S.rho[c], vj);
+          atomicOr(&S.any_flag, 1);
+        }
+      }
+    }
+    __syncthreads();
+    if (!S.any_flag) break;
+    for (int k = 0; k < 4; ++k) dots[k] = 0;
+    pc_forward<Q, float>(C, pv, ps, K, dst_, PC_S, dots);
+    C.acc = PA.Pp;
+    pc_backward<Q, float>(C, pv, ps, K, dst_, pv.sh);
+    set_dco(A.pj, cw, C.L.dco, PA.Pp);
+    __syncthreads();
+    for (int k = 0; k < 4; ++k) dots[k] = 0;
+    pc_apply<RAD, Q, float, true>(C, pv, ps, dots);
+    {
+      __shared__ double red_out[4][CW_MAX];
+      col_reduce4(C.L.red, cw, dots, red_out);
+      if (tid < cw) {
+        const int c = tid;
+        const cx<double> ts = mkc(red_out[1][c], red_out[2][c]);
+        const double tt = red_out[3][c];
+        if (S.istate[c] == 0) {
+          const cx<double> om = (tt > 0.0 && isfinite(tt)) ? cscale(ts, 1.0 / tt) : mkc(0.0, 0.0);
+          const cx<double> rn = S.sj[c] - cmul(om, S.tj[c]);
+          if (!(cnorm2(om) > 0.0) || !finite2(om) || !(cnorm2(rn) > 0.0) || !finite2(rn)) {
+            // keep x as it is: the merged update below leaves it unchanged
+            S.istate[c] = 1;
+            S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
+          } else {
+            S.omega[c] = om;
+            S.rho_new[c] = rn;
+            S.beta[c] = cmul(cdiv(rn, S.rho[c]), cdiv(S.alpha[c], om));
+          }
+        } else {
+          S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
+        }
+      }
+      __syncthreads();
+    }
+    for (int k = 0; k < 4; ++k) dots[k] = 0;
+    pc_forward<Q, float>(C, pv, ps, K, dst_, PC_MERGED, dots);
+    C.acc = PA.Pr;
+    pc_backward<Q, float>(C, pv, ps, K, dst_, pv.ph);
+    set_dco(A.pj, cw, C.L.dco, PA.Pr);
+    __syncthreads();
+    double d2[4] = {0, 0, 0, 0};
+    pc_apply<RAD, Q, float, false>(C, pv, ps, d2);
+    {
+      __shared__ double red_out[4][CW_MAX];
+      col_reduce4(C.L.red, cw, dots, red_out);
+      if (tid < cw) {
+        const int c = tid;
+        if (S.istate[c] == 0) {
+          S.iters[c] += 1;
+          S.rho[c] = S.rho_new[c];
+          const double rr = red_out[0][c];
+          if (!isfinite(rr) || rr <= itol2) S.istate[c] = 1;
+          // stagnation: no halving of the best residual norm for STALL_ITERS iterations
+          if (rr < 0.25 * S.ibest[c]) {
+            S.ibest[c] = rr;
+            S.istall[c] = 0;
+          } else if (++S.istall[c] >= STALL_ITERS) {
+            S.istate[c] = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// x64 += uscale * d32 over all planes, with the gathers of the new x64 into
+// C.acc and the transmission accumulator sum_z gdst(z) |x64|^2.
+template <int Q>
+__device__ __forceinline__ void update_gather_sweep(SweepCtx<double>& C, const Pos<Q>& ps,
+                                                    const cx<float>* d32, const double* gdst,
+                                                    double& tacc) {
+  const Geo& g = *C.g;
+  const Proj& pj = *C.pj;
+  const int cw = C.cw;
+  const int c = threadIdx.x % cw;
+  const double us = C.S->uscale[c];
+  const bool any_g = pj.nproj > 0 && C.acc != nullptr;
+  if (any_g) pacc_zero<double>(pj, C.L, cw);
+  __syncthreads();
+  for (int z = 0; z < g.nz; ++z) {
+    const bool need_g = any_g && pj.zc_offs[z + 1] > pj.zc_offs[z];
+    const double gd = gdst ? gdst[z] : 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (ps.p[k] >= 0) {
+        const size_t off = ((size_t)z * g.P + ps.p[k]) * cw + c;
+        const cx<double> xv = ldv(&C.vec.x[off]) + cscale(to64(ldv(&d32[off])), us);
+        stv(&C.vec.x[off], xv);
+        tacc += gd * cnorm2(xv);
+        if (need_g) C.L.outpl[ps.p[k] * cw + c] = xv;
+      }
+    }
+    if (need_g) {
+      __syncthreads();
+      plane_gather<double>(z, pj, C.L, cw);
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (any_g) {
+    pacc_flush<double>(pj, C.L, cw, C.acc);
+    __syncthreads();
+  }
+}
+
+template <int RAD, int Q, bool PC>
+__device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<double>& C64,
+                                                 SweepCtx<float>& C32, PcVecs<float>& pv, const Pos<Q>& ps,
+                                                 const ProjArrays& PA, const DftSteps& dst_, int item) {
+  ColState& S = *C64.S;
+  const Geo& g = A.g;
+  const int cw = A.cw;
+  const int tid = threadIdx.x;
+  const int ncw = A.pj.nproj * cw;
+  const int e_idx = item / A.nblk;
+  const int blk = item % A.nblk;
+  if (tid < cw) {
+    const int c = tid;
+    const int col = blk * cw + c;
+    S.energy[c] = A.energies[e_idx];
+    S.alpha[c] = S.omega[c] = S.beta[c] = mkc(0.0, 0.0);
+    S.iters[c] = 0;
+    S.restarts[c] = 0;
+    S.outer[c] = 0;
+    S.tacc[c] = 0.0;
+    if (col < A.ncols) {
+      const long long src = A.cols[col];
+      S.src[c] = src;
+      S.j0[c] = src;
+      const double gs = A.gsrc ? A.gsrc[src / g.P] : 1.0;
+      S.bsc[c] = sqrt(gs);
+      S.bb[c] = gs;
+      S.rr[c] = gs;
+      S.state[c] = 0;
+    } else {
+      S.src[c] = -1;
+      S.j0[c] = -1;
+      S.bsc[c] = 0.0;
+      S.bb[c] = 0.0;
+      S.rr[c] = 0.0;
+      S.state[c] = 3;
+    }
+  }
+  if constexpr (PC) pv.inv = reinterpret_cast<const cx<double>*>(A.pc.inv) + (size_t)e_idx * g.nz * g.P;
+  __syncthreads();
+  // x64 = 0, r64 = b, each element by the thread that owns it in every sweep
+  const size_t nall = (size_t)g.P * g.nz * cw;
+  {
+    const int c = tid % cw;
+    for (int z = 0; z < g.nz; ++z) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (ps.p[k] < 0) continue;
+        const long long gi = (long long)z * g.P + ps.p[k];
+        const size_t off = (size_t)gi * cw + c;
+        stv(&C64.vec.x[off], mkc(0.0, 0.0));
+        stv(&C64.vec.r[off], gi == S.src[c] ? mkc(S.bsc[c], 0.0) : mkc(0.0, 0.0));
+      }
+    }
+  }
+  // projections of b into Pt (kept as the FP64 right-hand-side projections)
+  zero_acc<double>(PA.Pt, ncw);
+  __syncthreads();
+  if (A.pj.nproj && tid < cw && S.state[tid] == 0) {
+    const int c = tid;
+    const long long src = S.src[c];
+    for (int sl = 0; sl < SC_SLOTS; ++sl) {
+      const size_t si = (size_t)src * SC_SLOTS + sl;
+      const int pb = A.pj.sc_pb[si];
+      if (pb < 0) continue;
+      const double2 ph = A.pj.sc_eph[si];
+      const cx<double> w = cscale(mkc(ph.x, -ph.y), S.bsc[c]);
+      for (int m = 0; m < A.pj.nm && pb + m < A.pj.nproj; ++m) {
+        const double b = A.pj.sc_beta[si * A.pj.nm + m];
+        cx<double>* a = &PA.Pt[(size_t)(pb + m) * cw + c];
+        *a = *a + cscale(w, b * A.pj.h3);
+      }
+    }
+    for (int k = A.pj.pe_offs[src]; k < A.pj.pe_offs[src + 1]; ++k) {
+      const int2 ge = A.pj.pe[k];
+      const double2 ph = A.pj.eph[ge.y];
+      const cx<double> w = cscale(mkc(ph.x, -ph.y), S.bsc[c]);
+      for (int m = 0; m < A.pj.grp_nm[ge.x]; ++m) {
+        const double b = A.pj.beta[(size_t)ge.y * A.pj.nm + m];
+        cx<double>* a = &PA.Pt[(size_t)(A.pj.grp_pbase[ge.x] + m) * cw + c];
+        *a = *a + cscale(w, b * A.pj.h3);
+      }
+    }
+  }
+  __syncthreads();
+  for (int outer = 0; outer < A.max_outer; ++outer) {
+    if (tid == 0) S.any_flag = 0;
+    __syncthreads();
+    if (tid < cw) {
+      const int c = tid;
+      if (S.state[c] == 0 && S.rr[c] > 0.0) {
+        S.rscale[c] = 1.0 / sqrt(S.rr[c]);
+        S.uscale[c] = sqrt(S.rr[c]);
+        S.istate[c] = 0;
+        S.outer[c] += 1;
+        atomicOr(&S.any_flag, 1);
+      } else {
+        S.rscale[c] = 0.0;
+        S.uscale[c] = 0.0;
+        S.istate[c] = 1;
+      }
+    }
+    __syncthreads();
+    if (!S.any_flag) break;
+    // inner FP32 solve of A d = r64 / ||r64||
+    for (int w = tid; w < ncw; w += blockDim.x) PA.Pr[w] = cscale(PA.Pt[w], S.rscale[w % cw]);
+    __syncthreads();
+    C32.rhs64 = C64.vec.r;
+    if constexpr (PC)
+      inner_pc<RAD, Q>(A, C32, pv, ps, PA, A.pc, dst_);
+    else
+      inner_plain<RAD, Q>(A, C32, ps, PA);
+    // x64 += ||r64|| d, gathered into Px
+    double tacc = 0.0;
+    C64.acc = PA.Px;
+    update_gather_sweep<Q>(C64, ps, C32.vec.x, A.gdst, tacc);
+    {
+      double v4[4] = {tacc, 0, 0, 0};
+      __shared__ double red_out[4][CW_MAX];
+      col_reduce4(C64.L.red, cw, v4, red_out);
+      if (tid < cw) S.tacc[tid] = red_out[0][tid];
+    }
+    // r64 = b - A x64 (FP64), gathered into Pt
+    set_dco(A.pj, cw, C64.L.dco, PA.Px);
+    __syncthreads();
+    double dots[4] = {0, 0, 0, 0};
+    double rmax = -1.0;
+    long long rmax_idx = 0x7fffffffffffffffLL;
+    C64.acc = PA.Pt;
+    sweep<RAD, Q, double>(C64, ps, IN_X, OUT_RES, dots, rmax, rmax_idx);
+    {
+      __shared__ double red_out[4][CW_MAX];
+      col_reduce4(C64.L.red, cw, dots, red_out);
+      double* bm = C64.L.red;
+      long long* bi = reinterpret_cast<long long*>(C64.L.red + blockDim.x);
+      bm[tid] = rmax;
+      bi[tid] = rmax_idx;
+      __syncthreads();
+      if (tid < cw) {
+        const int c = tid;
+        double m = -1.0;
+        long long ix = 0x7fffffffffffffffLL;
+        for (int i = c; i < (int)blockDim.x; i += cw) {
+          if (bm[i] > m || (bm[i] == m && bi[i] < ix)) {
+            m = bm[i];
+            ix = bi[i];
+          }
+        }
+        if (S.state[c] == 0) {
+          const double rr = red_out[0][c];
+          S.rr[c] = rr;
+          S.j0[c] = ix;
+          if (!isfinite(rr))
+            S.state[c] = 2;
+          else if (rr <= A.tol * A.tol * S.bb[c])
+            S.state[c] = 1;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid < cw) {
+    const int c = tid;
+    if (S.state[c] == 0) S.state[c] = 4;
+    const int col = blk * cw + c;
+    if (col < A.ncols) {
+      const size_t o = (size_t)e_idx * A.ncols + col;
+      A.T_col[o] = 4.0 * S.tacc[c];
+      A.iters[o] = S.iters[c];
+      A.restarts[o] = S.outer[c];
+      A.resid[o] = S.bb[c] > 0 ? sqrt(S.rr[c] / S.bb[c]) : 0.0;
+      A.status[o] = S.state[c] == 1 ? 0 : (S.state[c] == 2 ? 2 : 1);
+    }
+  }
+  if (A.xout) {
+    __threadfence();  // x was stored by the position-owning threads; read here by another mapping
+    __syncthreads();
+    for (size_t w = tid; w < nall; w += blockDim.x) {
+      const int c = (int)(w % cw);
+      const size_t gi = w / cw;
+      const int col = blk * cw + c;
+      if (col < A.ncols) {
+        const cx<double> xv = C64.vec.x[w];
+        double2 o;
+        o.x = xv.x;
+        o.y = xv.y;
+        A.xout[gi * A.ncols + col] = o;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int RAD, int Q, bool PC>
+__global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_mixed(const SolveArgs* __restrict__ Ap) {
+  const SolveArgs& A = *Ap;
+  extern __shared__ __align__(16) char smem[];
+  __shared__ ColState S;
+  const int cw = A.cw;
+  SweepCtx<double> C64;
+  C64.g = &A.g;
+  C64.pj = &A.pj;
+  C64.V = A.V;
+  C64.gz = A.gz;
+  C64.cw = cw;
+  C64.L = carve_lds<double>(smem, A.g, A.pj, cw, blockDim.x);
+  C64.S = &S;
+  C64.xext = nullptr;
+  C64.yext = nullptr;
+  C64.ext_ld = C64.ext_c0 = C64.ext_ncol = 0;
+  C64.pcsrc = C64.pcs = nullptr;
+  C64.rhs64 = nullptr;
+  SweepCtx<float> C32;
+  C32.g = &A.g;
+  C32.pj = &A.pj;
+  C32.V = A.V;
+  C32.gz = A.gz;
+  C32.cw = cw;
+  C32.L = carve_lds<float>(smem, A.g, A.pj, cw, blockDim.x);
+  C32.S = &S;
+  C32.xext = nullptr;
+  C32.yext = nullptr;
+  C32.ext_ld = C32.ext_c0 = C32.ext_ncol = 0;
+  C32.pcsrc = C32.pcs = nullptr;
+  C32.rhs64 = nullptr;
+  const size_t nv = (size_t)A.g.P * A.g.nz * cw;
+  cx<double>* b64 = reinterpret_cast<cx<double>*>(A.ws) + (size_t)blockIdx.x * A.ws_stride;
+  C64.vec.x = b64;
+  C64.vec.r = b64 + nv;
+  C64.vec.p = C64.vec.v = C64.vec.t = nullptr;
+  cx<float>* b32 = reinterpret_cast<cx<float>*>(b64 + 2 * nv);
+  C32.vec.x = b32;
+  C32.vec.r = b32 + nv;
+  C32.vec.p = b32 + 2 * nv;
+  C32.vec.v = b32 + 3 * nv;
+  C32.vec.t = b32 + 4 * nv;
+  PcVecs<float> pv;
+  pv.ph = b32 + 5 * nv;
+  pv.sh = b32 + 6 * nv;
+  pv.s = b32 + 7 * nv;
+  pv.w = b32 + 8 * nv;
+  pv.inv = nullptr;
+  const size_t np = (size_t)A.pj.nproj * cw;
+  cx<double>* pb = reinterpret_cast<cx<double>*>(A.pws) + (size_t)blockIdx.x * A.pws_stride;
+  ProjArrays PA{pb, pb + np, pb + 2 * np, pb + 3 * np, pb + 4 * np};
+  DftSteps dst_;
+  dst_.fa = dst_.fb = dst_.ia = dst_.ib = dst_.pa = dst_.pb = nullptr;
+  if constexpr (PC) {
+    cx<double>* tab = reinterpret_cast<cx<double>*>(smem + A.pc_lds_off);
+    const int ntab = 3 * (A.g.na + A.g.nb);
+    for (int w = threadIdx.x; w < ntab; w += blockDim.x) {
+      const double2 t = A.pc.steps[w];
+      tab[w] = mkc(t.x, t.y);
+    }
+    dst_.fa = tab;
+    dst_.fb = tab + A.g.na;
+    dst_.ia = tab + A.g.na + A.g.nb;
+    dst_.ib = tab + 2 * A.g.na + A.g.nb;
+    dst_.pa = tab + 2 * A.g.na + 2 * A.g.nb;
+    dst_.pb = tab + 3 * A.g.na + 2 * A.g.nb;
+  }
+  __syncthreads();
+  const Pos<Q> ps = make_pos<Q>(A.g, cw, RAD);
+  for (;;) {
+    if (threadIdx.x == 0) S.item = atomicAdd(A.counter, 1);
+    __syncthreads();
+    const int item = S.item;
+    if (item >= A.nitems) break;
+    mixed_solve_item<RAD, Q, PC>(A, C64, C32, pv, ps, PA, dst_, item);
+  }
+}
+
+}  // namespace rst

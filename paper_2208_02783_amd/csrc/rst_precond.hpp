@@ -16,7 +16,7 @@
 
 namespace rst {
 
-enum PcIn { PC_INIT, PC_MERGED, PC_RESTART, PC_S };
+enum PcIn { PC_INIT, PC_MERGED, PC_RESTART, PC_S, PC_INIT_VEC };
 
 template <class R>
 struct PcVecs {
@@ -158,6 +158,13 @@ __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, 
         stv(&C.vec.x[off], mkc<R>((R)0, (R)0));
         stv(&C.vec.r[off], bb);
         stv(&C.vec.p[off], bb);
+        u[k] = bb;
+      } else if (IN == PC_INIT_VEC) {
+        const cx<R> bb = fromd<R>(cscale(ldv(&C.rhs64[off]), S->rscale[c]));
+        stv(&C.vec.x[off], mkc<R>((R)0, (R)0));
+        stv(&C.vec.r[off], bb);
+        stv(&C.vec.p[off], bb);
+        if (gi == j0) S->rj[c] = to64(bb);
         u[k] = bb;
       } else if (IN == PC_MERGED) {
         const cx<R> xv = ldv(&C.vec.x[off]), phv = ldv(&pv.ph[off]), shv = ldv(&pv.sh[off]),
@@ -513,6 +520,8 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
     }
   }
   if (A.xout) {
+    __threadfence();  // x was stored by the position-owning threads; read here by another mapping
+    __syncthreads();
     const size_t nall = (size_t)g.P * g.nz * cw;
     for (size_t w = tid; w < nall; w += blockDim.x) {
       const int c = (int)(w % cw);
@@ -548,6 +557,7 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab_pc(const Solv
   C.yext = nullptr;
   C.ext_ld = C.ext_c0 = C.ext_ncol = 0;
   C.pcsrc = C.pcs = nullptr;
+  C.rhs64 = nullptr;
   const size_t nv = (size_t)A.g.P * A.g.nz * cw;
   cx<R>* base = reinterpret_cast<cx<R>*>(A.ws) + (size_t)blockIdx.x * A.ws_stride;
   C.vec.x = base;

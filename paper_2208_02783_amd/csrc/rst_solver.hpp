@@ -322,6 +322,8 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, c
     }
   }
   if (A.xout) {
+    __threadfence();  // x was stored by the position-owning threads; read here by another mapping
+    __syncthreads();
     const Geo& g = A.g;
     const size_t nall = (size_t)g.P * g.nz * cw;
     for (size_t w = tid; w < nall; w += blockDim.x) {
@@ -358,6 +360,7 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab(const SolveAr
   C.yext = nullptr;
   C.ext_ld = C.ext_c0 = C.ext_ncol = 0;
   C.pcsrc = C.pcs = nullptr;
+  C.rhs64 = nullptr;
   const size_t nv = (size_t)A.g.P * A.g.nz * cw;
   cx<R>* base = reinterpret_cast<cx<R>*>(A.ws) + (size_t)blockIdx.x * A.ws_stride;
   C.vec.x = base;
@@ -399,6 +402,7 @@ __global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ A
   C.ext_ncol = A.ncol;
   C.vec = Vecs<R>{nullptr, nullptr, nullptr, nullptr, nullptr};
   C.pcsrc = C.pcs = nullptr;
+  C.rhs64 = nullptr;
   const int tid = threadIdx.x;
   if (tid < cw) {
     S.energy[tid] = A.energy;

@@ -22,6 +22,7 @@ struct SweepCtx {
   cx<double>* acc;       // gather accumulator of the output (nullptr: no gather)
   cx<R>* pcsrc;          // IN_PC source (preconditioned vector)
   cx<R>* pcs;            // OUT_TS: s for the (t, s) product
+  const cx<double>* rhs64;  // IN_INIT_VEC: FP64 right-hand side, scaled by S->rscale
 };
 
 template <int Q>
@@ -63,6 +64,15 @@ __device__ __forceinline__ cx<R> load_in(const SweepCtx<R>& C, int mode, int zl,
       stv(&C.vec.x[off], mkc<R>((R)0, (R)0));
       stv(&C.vec.r[off], u);
       stv(&C.vec.p[off], u);
+      return u;
+    }
+    case IN_INIT_VEC: {
+      const cx<double> b64 = cscale(ldv(&C.rhs64[off]), S->rscale[c]);
+      const cx<R> u = fromd<R>(b64);
+      stv(&C.vec.x[off], mkc<R>((R)0, (R)0));
+      stv(&C.vec.r[off], u);
+      stv(&C.vec.p[off], u);
+      if (gi == S->j0[c]) S->rj[c] = to64(u);
       return u;
     }
     case IN_A: {

@@ -38,7 +38,8 @@ class rst_stats(C.Structure):
     _fields_ = [("columns", C.c_int64), ("columns_unconverged", C.c_int64),
                 ("iterations_total", C.c_int64), ("iterations_max", C.c_int32),
                 ("restarts_total", C.c_int32), ("max_rel_residual", C.c_double),
-                ("kernel_ms", C.c_double), ("bytes_algorithmic", C.c_double)]
+                ("kernel_ms", C.c_double), ("bytes_algorithmic", C.c_double),
+                ("refinements_total", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -100,6 +101,15 @@ class Context:
     """One librst context (one device, one stream).  Method names follow the C ABI."""
 
     def __init__(self, device: int = 0, stream=None):
+        # torch brings its own HIP runtime; it must initialise before librst's
+        # (the other order leaves torch without devices).  Device buffers from
+        # torch are then used by the library's kernels on the same GPU.
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         self.lib = load()
         self.h = C.c_void_p()
         s = self.lib.rst_create(C.byref(self.h), int(device), C.c_void_p(stream) if stream else None)

@@ -221,3 +221,43 @@ def test_preconditioned_solve_columns():
     ref = oracle.green_columns(p, float(p.energies[2]), k, cols)
     err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
     assert err <= 1e-9, (err, st)
+
+
+# ------------------------------------------------------ mixed precision
+
+@pytest.mark.parametrize("cfg,pc", [(1, 0), (1, 1), (2, 1), (3, 1), (2, 0)])
+def test_mixed_precision_matches_oracle(cfg, pc):
+    """FP32 stencil/projector/preconditioner applies inside FP64 refinement reach
+    the FP64 tolerance: T matches the dense FP64 oracle to 1e-6."""
+    torch = torch_cuda()
+    if cfg == 1:
+        g = json.load(open(os.path.join(GOLD, "config1_T.json")))
+        p = wl.config(1)
+        es = np.array(g["energies"][1::6])
+        ref = np.array(g["T_LR"][1::6])
+        k = (0.0, 0.0)
+    else:
+        p = wl.config(cfg, tiny=True)
+        k = p.kpts[1]
+        es = p.energies[[1, 5]]
+        ref = oracle.transmission(p, es, k, both=False)["T_LR"]
+    ctx = make_ctx(torch, p, k, precision=rst.RST_FP32_REFINE, precond=pc)
+    t, st, s = ctx.rst_transmission(es)
+    _say("mixed cfg", cfg, "pc", pc, st)
+    assert s == rst.RST_OK
+    assert st["refinements_total"] >= st["columns"]
+    assert st["max_rel_residual"] <= 1e-10
+    np.testing.assert_allclose(t, ref, atol=1e-6, rtol=0)
+
+
+def test_mixed_solve_columns():
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    k = p.kpts[0]
+    ctx = make_ctx(torch, p, k, tol=1e-12, precision=rst.RST_FP32_REFINE, precond=rst.RST_PRECOND_FREE_CAP)
+    cols = np.array([3, p.n // 3, p.n - 5])
+    x, st, s = rst.solve_columns(ctx, float(p.energies[2]), cols, p.n)
+    assert s == rst.RST_OK, st
+    ref = oracle.green_columns(p, float(p.energies[2]), k, cols)
+    err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 1e-9, (err, st)
