@@ -82,6 +82,53 @@ def cpu_baseline(seconds_budget=20.0):
                       f"~{per_point * (n_full / n_tiny) ** 3 / 3600:.2f} h per point"}
 
 
+def batched_comparison(n_slabs=96, ne=2):
+    """Config 4 subset: 96 uneven free-electron slabs (8x8x{48..160}, order 4,
+    10-plane CAPs, random k), `ne` energies each.  Plain: one rst_transmission
+    call per slab; batched: one persistent launch over every (slab, energy,
+    column) item (autotuned column block, HIP-graph replay)."""
+    import torch
+    from paper_2208_02783_amd import rst
+    from paper_2208_02783_amd import workloads as wl
+    slabs = wl.batch_slabs(n_slabs=n_slabs, ne=128)
+    pick = np.linspace(0, 127, ne).round().astype(int)
+    p0 = slabs[0]
+    # plain: per-slab launches
+    ctx = rst.Context(0)
+    ctx.rst_set_grid(p0.na, p0.nb, p0.nz, p0.ha, p0.hb, p0.hz, p0.order)
+    ctx.rst_set_solver()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_plain, ok_plain, cols = [], True, 0
+    for p in slabs:
+        ctx.load_problem(p, p.kpts[0])
+        t, st, s = ctx.rst_transmission(p.energies[pick])
+        t_plain.append(t)
+        ok_plain &= s == rst.RST_OK
+        cols += st["columns"]
+    wall_plain = time.perf_counter() - t0
+    # batched: one launch (first run tunes and captures the graph; the second is timed)
+    cb = rst.Context(0)
+    cb.rst_set_grid(p0.na, p0.nb, p0.nz, p0.ha, p0.hb, p0.hz, p0.order)
+    cb.rst_set_solver()
+    for p in slabs:
+        cb.rst_batch_add(p.nz, p.v, p.gamma_l, p.gamma_r, p.kpts[0][0], p.kpts[0][1], p.energies[pick])
+    cb.rst_batch_run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_b, st_b, s_b = cb.rst_batch_run()
+    wall_b = time.perf_counter() - t0
+    npts = n_slabs * ne
+    dmax = float(np.max(np.abs(np.concatenate(t_plain) - t_b)))
+    print(f"batched comparison: plain {npts / wall_plain:.1f} pts/s, batched {npts / wall_b:.1f} pts/s",
+          file=sys.stderr, flush=True)
+    return {"workload": f"{n_slabs} free-electron slabs 8x8x(48..160), h=0.5, order 4, 10-plane CAPs, "
+                        f"random k, {ne} energies each ({npts} T(E,k) points, {cols} column solves)",
+            "plain_points_per_s": npts / wall_plain, "batched_points_per_s": npts / wall_b,
+            "batched_col_block": st_b["col_block"], "batched_threads": st_b["threads"],
+            "max_abs_dT_plain_vs_batched": dmax, "all_converged": bool(ok_plain and s_b == rst.RST_OK)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +139,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="fp64: FP64 throughout; mixed: FP32 applies inside FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the plain-vs-batched comparison")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="before the run, copy this many GiB device-to-device (a reference "
                          "kernel of known traffic for hardware-counter scaling)")
@@ -183,6 +231,8 @@ def main():
                         if args.precision == "fp64" else None),
         },
     }
+    if not args.no_batched:
+        line["batched"] = batched_comparison()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -101,7 +101,23 @@ typedef struct {
                                column; RST_FP32_REFINE the same counts of complex64 streams plus
                                14 complex128-equivalent streams per refinement step */
   int64_t refinements_total; /* RST_FP32_REFINE: FP64 refinement steps summed over columns */
+  int32_t col_block;         /* columns per workgroup used by the launch */
+  int32_t threads;           /* workgroup size used by the launch */
 } rst_stats;
+
+/* One structure of a batch (rst_batch_add).  The lateral grid, spacings and
+ * FD order are the context's (rst_set_grid; its nz is ignored here); each
+ * structure has its own plane count, potential, CAPs, lateral k and energies.
+ * Host arrays are copied by rst_batch_add. */
+typedef struct {
+  int nz;                  /* planes of this structure (>= 1) */
+  const double *v;         /* na*nb*nz potential (Ha) */
+  const double *gamma_l;   /* nz left CAP (Ha, >= 0) */
+  const double *gamma_r;   /* nz right CAP (Ha, >= 0) */
+  double ka, kb;           /* lateral Bloch vector (bohr^-1) */
+  int n_e;                 /* energies of this structure */
+  const double *energies;  /* n_e (Ha) */
+} rst_problem;
 
 void rst_default_solver(rst_solver_opts *opts);
 
@@ -150,6 +166,21 @@ rst_status rst_apply_h(rst_ctx *ctx, double energy, const void *x_dev, void *y_d
  * device).  col holds ncol grid indices (host). */
 rst_status rst_solve_columns(rst_ctx *ctx, double energy, int ncol, const int64_t *col,
                              void *x_dev, rst_stats *stats);
+
+/* Batched transmission (paper Appendix: the (k, spin) calculations are
+ * independent; here every (structure, energy, column block) is a work item of
+ * one persistent launch).  rst_batch_clear empties the batch; rst_batch_add
+ * appends a structure (RST_EUNSUPPORTED if the context has projectors: the
+ * batch path carries local potentials only); rst_batch_run computes T for
+ * every (structure, energy) into T_out (host, sum of n_e doubles, in the order
+ * the structures were added) with the context's solver options (FP64 BiCGSTAB
+ * without preconditioner).  With col_block = 0 the columns per workgroup are
+ * chosen by timing the candidates on a sample of the batch (cached per lateral
+ * shape); the launch is captured in a HIP graph and replayed while the batch is
+ * unchanged. */
+rst_status rst_batch_clear(rst_ctx *ctx);
+rst_status rst_batch_add(rst_ctx *ctx, const rst_problem *prob);
+rst_status rst_batch_run(rst_ctx *ctx, double *T_out, rst_stats *stats);
 
 #ifdef __cplusplus
 }

@@ -168,7 +168,22 @@ struct PcConst {
   const double2* inv;    // [ne*nz*P] reciprocal Thomas pivots per energy, plane, lateral mode
 };
 
+// One structure of a batched launch (same lateral grid, order and spacings;
+// own plane count, potential, CAPs, k, energies and columns).
+struct BatchProb {
+  long long item0;    // first work item of this structure
+  long long v_off;    // offset of its potential in V
+  long long col_off;  // offset of its columns in cols
+  long long out_off;  // offset of its (energy x column) outputs
+  int nz, ne, ncols, nblk;
+  int gz_off;         // offset of its CAP profiles (gz, gdst, gsrc)
+  int e_off;          // offset of its energies
+  double pha_x, pha_y, phb_x, phb_y;
+};
+
 struct SolveArgs {
+  const BatchProb* batch;  // nullptr: a single structure
+  int nprob;
   Geo g;
   Proj pj;
   PcConst pc;

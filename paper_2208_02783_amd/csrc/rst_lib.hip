@@ -99,6 +99,19 @@ struct rst_ctx {
   rst_solver_opts opts;
   // work buffers (grown on demand)
   DevBuf d_ws, d_pws, d_cols, d_en, d_T, d_it, d_rs, d_res, d_st, d_counter, d_args, d_pc_inv;
+  // batch of structures (rst_batch_add)
+  struct HostProb {
+    int nz;
+    std::vector<double> v, gl, gr, en;
+    double ka, kb;
+  };
+  std::vector<HostProb> batch;
+  int batch_version = 0;
+  std::map<long long, int> tuned_cw;  // (lateral shape, order, direction) -> columns per workgroup
+  hipGraphExec_t gexec = nullptr;
+  long long gexec_key = -1;
+  DevBuf d_bprob, d_bv, d_bgz, d_bgl, d_bgr, d_ben, d_bcols;
+  int last_cw = 0, last_threads = 0;
   // host copies of the last kernel-argument blocks (kept alive for async copies)
   rst::SolveArgs h_solve;
   rst::ApplyArgs h_apply;
@@ -515,6 +528,8 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   if (s != RST_OK) return s;
   const int ncols = (int)cols.size();
   const int nblk = (ncols + ls.cw - 1) / ls.cw;
+  c->last_cw = ls.cw;
+  c->last_threads = ls.threads;
   const long long nitems = (long long)nblk * ne;
   if (nitems > 0x7fffffff) return fail(c, RST_EINVAL, "too many column blocks");
   const size_t n = (size_t)c->na * c->nb * c->nz;
@@ -642,7 +657,8 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
 }
 
 void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const std::vector<int>& rss,
-                const std::vector<double>& res, const std::vector<int>& stv, double ms, int& nbad) {
+                const std::vector<double>& res, const std::vector<int>& stv, double ms, int& nbad,
+                int cw = 0, int threads = 0, double n_override = 0.0) {
   nbad = 0;
   rst_stats s;
   std::memset(&s, 0, sizeof(s));
@@ -659,7 +675,9 @@ void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const st
   }
   s.columns_unconverged = nbad;
   s.kernel_ms = ms;
-  const double n = (double)c->na * c->nb * c->nz;
+  s.col_block = cw;
+  s.threads = threads;
+  const double n = n_override > 0 ? n_override : (double)c->na * c->nb * c->nz;
   const double streams = c->opts.precond == RST_PRECOND_FREE_CAP ? 24.0 : 12.0;
   if (c->opts.precision == RST_FP32_REFINE)
     // inner iterations on FP32 vectors; per refinement step: x64 update (read x64, d, write x64),
@@ -671,9 +689,303 @@ void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const st
   if (st) *st = s;
 }
 
+// Launches the batched solver over the structures `sel` of the batch (all
+// energies of each, or the first `ne_cap` if > 0) with cw columns per
+// workgroup.  Returns per-structure, per-energy T and the per-column stats.
+struct BatchOut {
+  std::vector<std::vector<double>> T;  // [structure in sel order][energy]
+  std::vector<int> its, rss, stv;
+  std::vector<double> res;
+  double ms = 0;
+  double points_n = 0;  // sum over columns of the structure's grid size (bytes bookkeeping)
+  int cw = 0, threads = 0;
+};
+
+rst_status run_batch(rst_ctx* c, const std::vector<int>& sel, int ne_cap, int cw, bool use_graph,
+                     BatchOut& out) {
+  LaunchShape ls;
+  rst_status s = choose_shape(c, cw, c->opts.threads, ls);
+  if (s != RST_OK) return s;
+  const int P = c->na * c->nb;
+  const bool lr = c->opts.direction == RST_DIR_LR;
+  // order the work by decreasing cost so the long structures start first
+  std::vector<int> order(sel.size());
+  std::vector<double> cost(sel.size());
+  std::vector<std::vector<int64_t>> pcols(sel.size());
+  for (size_t i = 0; i < sel.size(); ++i) {
+    const auto& hp = c->batch[sel[i]];
+    const std::vector<double>& gs = lr ? hp.gr : hp.gl;
+    for (int z = 0; z < hp.nz; ++z)
+      if (gs[z] > 0)
+        for (int p = 0; p < P; ++p) pcols[i].push_back((int64_t)z * P + p);
+    const int ne = ne_cap > 0 ? std::min<int>(ne_cap, (int)hp.en.size()) : (int)hp.en.size();
+    cost[i] = (double)hp.nz * pcols[i].size() * ne;
+    order[i] = (int)i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<rst::BatchProb> bp(sel.size());
+  std::vector<double> v, gz, gl, gr, en;
+  std::vector<int64_t> cols;
+  long long items = 0, outs = 0;
+  int nz_max = 1;
+  std::vector<long long> out_off(sel.size());
+  std::vector<int> ne_of(sel.size());
+  for (int oi : order) {
+    const auto& hp = c->batch[sel[oi]];
+    const int ne = ne_cap > 0 ? std::min<int>(ne_cap, (int)hp.en.size()) : (int)hp.en.size();
+    const int ncols = (int)pcols[oi].size();
+    rst::BatchProb& b = bp[oi];
+    std::memset(&b, 0, sizeof(b));
+    b.nz = hp.nz;
+    b.ne = ne;
+    b.ncols = ncols;
+    b.nblk = (ncols + ls.cw - 1) / ls.cw;
+    b.item0 = items;
+    b.v_off = (long long)v.size();
+    b.gz_off = (int)gz.size();
+    b.e_off = (int)en.size();
+    b.col_off = (long long)cols.size();
+    b.out_off = outs;
+    const double la = c->na * c->ha, lb = c->nb * c->hb;
+    b.pha_x = std::cos(hp.ka * la);
+    b.pha_y = std::sin(hp.ka * la);
+    b.phb_x = std::cos(hp.kb * lb);
+    b.phb_y = std::sin(hp.kb * lb);
+    items += ncols > 0 ? (long long)b.nblk * ne : 0;
+    outs += (long long)ne * ncols;
+    out_off[oi] = b.out_off;
+    ne_of[oi] = ne;
+    nz_max = std::max(nz_max, hp.nz);
+    v.insert(v.end(), hp.v.begin(), hp.v.end());
+    for (int z = 0; z < hp.nz; ++z) gz.push_back(hp.gl[z] + hp.gr[z]);
+    gl.insert(gl.end(), hp.gl.begin(), hp.gl.end());
+    gr.insert(gr.end(), hp.gr.begin(), hp.gr.end());
+    en.insert(en.end(), hp.en.begin(), hp.en.begin() + ne);
+    cols.insert(cols.end(), pcols[oi].begin(), pcols[oi].end());
+  }
+  // the structures in item order (binary search by item0)
+  std::vector<rst::BatchProb> bsorted;
+  for (int oi : order) bsorted.push_back(bp[oi]);
+  out.T.assign(sel.size(), {});
+  for (size_t i = 0; i < sel.size(); ++i) out.T[i].assign(ne_of[i], 0.0);
+  out.cw = ls.cw;
+  out.threads = ls.threads;
+  if (items == 0) return RST_OK;
+  if (items > 0x7fffffff) return fail(c, RST_EINVAL, "too many work items in the batch");
+  if ((s = upload(c, c->d_bprob, bsorted)) != RST_OK) return s;
+  if ((s = upload(c, c->d_bv, v)) != RST_OK) return s;
+  if ((s = upload(c, c->d_bgz, gz)) != RST_OK) return s;
+  if ((s = upload(c, c->d_bgl, gl)) != RST_OK) return s;
+  if ((s = upload(c, c->d_bgr, gr)) != RST_OK) return s;
+  if ((s = upload(c, c->d_ben, en)) != RST_OK) return s;
+  if ((s = upload(c, c->d_bcols, cols)) != RST_OK) return s;
+  void* kern = pick_kernel(c->rad, ls.q, 0);
+  if (!kern) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
+  rst::Geo g = make_geo(c);
+  g.nz = nz_max;
+  rst::Proj pj = make_proj(c);
+  pj.nproj = 0;
+  const size_t lds = rst::lds_bytes<double>(g.pa, g.pb, g.P, 0, 0, pj.nm, ls.cw, ls.threads);
+  int per_cu = 0, ncu = 0;
+  HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, ls.threads, lds));
+  HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  if (per_cu < 1) return fail(c, RST_EUNSUPPORTED, "kernel does not fit on a compute unit");
+  const size_t n_max = (size_t)P * nz_max;
+  const size_t ws_stride = 5 * n_max * ls.cw;
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
+  long long nwg = std::min<long long>(items, (long long)per_cu * ncu);
+  nwg = std::min<long long>(nwg, std::max<long long>(1, (long long)(free_b / 4 / (ws_stride * 16))));
+  if ((s = ensure(c, c->d_ws, nwg * ws_stride * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_pws, 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_T, outs * 8)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_it, outs * 4)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_rs, outs * 4)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_res, outs * 8)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_st, outs * 4)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_counter, 64)) != RST_OK) return s;
+  rst::SolveArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.batch = (const rst::BatchProb*)c->d_bprob.p;
+  A.nprob = (int)bsorted.size();
+  A.g = g;
+  A.pj = pj;
+  A.V = (const double*)c->d_bv.p;
+  A.gz = (const double*)c->d_bgz.p;
+  A.gdst = lr ? (const double*)c->d_bgl.p : (const double*)c->d_bgr.p;
+  A.gsrc = lr ? (const double*)c->d_bgr.p : (const double*)c->d_bgl.p;
+  A.energies = (const double*)c->d_ben.p;
+  A.cols = (const int64_t*)c->d_bcols.p;
+  A.cw = ls.cw;
+  A.nitems = (int)items;
+  A.tol = c->opts.tol;
+  A.max_iter = c->opts.max_iter;
+  A.ws = c->d_ws.p;
+  A.ws_stride = ws_stride;
+  A.pws = (double2*)c->d_pws.p;
+  A.pws_stride = 1;
+  A.T_col = (double*)c->d_T.p;
+  A.iters = (int*)c->d_it.p;
+  A.restarts = (int*)c->d_rs.p;
+  A.resid = (double*)c->d_res.p;
+  A.status = (int*)c->d_st.p;
+  A.counter = (int*)c->d_counter.p;
+  if ((s = ensure(c, c->d_args, sizeof(A))) != RST_OK) return s;
+  c->h_solve = A;
+  HIPCHK(c, hipMemcpyAsync(c->d_args.p, &c->h_solve, sizeof(A), hipMemcpyHostToDevice, c->stream));
+  void* dargs = c->d_args.p;
+  void* args[] = {&dargs};
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  // graph key: batch contents, launch shape and buffers
+  const long long key = ((long long)c->batch_version << 32) ^ ((long long)ls.cw << 24) ^ (nwg << 1) ^
+                        (long long)(uintptr_t)c->d_ws.p ^ (long long)lds;
+  if (use_graph && (c->gexec == nullptr || c->gexec_key != key)) {
+    if (c->gexec) {
+      HIPCHK(c, hipGraphExecDestroy(c->gexec));
+      c->gexec = nullptr;
+    }
+    hipGraph_t graph;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipLaunchKernelGGL(rst::k_fill_int, dim3(1), dim3(64), 0, c->stream, (int*)c->d_counter.p, 16, 0);
+    hipLaunchKernel(kern, dim3((unsigned)nwg), dim3(ls.threads), args, lds, c->stream);
+    HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
+    HIPCHK(c, hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0));
+    HIPCHK(c, hipGraphDestroy(graph));
+    c->gexec_key = key;
+  }
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  if (use_graph) {
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+  } else {
+    hipLaunchKernelGGL(rst::k_fill_int, dim3(1), dim3(64), 0, c->stream, (int*)c->d_counter.p, 16, 0);
+    HIPCHK(c, hipLaunchKernel(kern, dim3((unsigned)nwg), dim3(ls.threads), args, lds, c->stream));
+  }
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float fms = 0;
+  HIPCHK(c, hipEventElapsedTime(&fms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  out.ms = fms;
+  std::vector<double> Tcol(outs);
+  out.its.resize(outs);
+  out.rss.resize(outs);
+  out.res.resize(outs);
+  out.stv.resize(outs);
+  HIPCHK(c, hipMemcpy(Tcol.data(), c->d_T.p, outs * 8, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(out.its.data(), c->d_it.p, outs * 4, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(out.rss.data(), c->d_rs.p, outs * 4, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(out.res.data(), c->d_res.p, outs * 8, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(out.stv.data(), c->d_st.p, outs * 4, hipMemcpyDeviceToHost));
+  out.points_n = 0;
+  for (size_t i = 0; i < sel.size(); ++i) {
+    const int ncols = (int)pcols[i].size();
+    const double n_i = (double)P * c->batch[sel[i]].nz;
+    for (int e = 0; e < ne_of[i]; ++e) {
+      double t = 0;
+      for (int j = 0; j < ncols; ++j) {
+        const size_t o = out_off[i] + (size_t)e * ncols + j;
+        t += Tcol[o];
+        out.points_n += n_i * out.its[o];
+      }
+      out.T[i][e] = t;
+    }
+  }
+  return RST_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+rst_status rst_batch_clear(rst_ctx* c) {
+  if (!c) return RST_EINVAL;
+  c->batch.clear();
+  c->batch_version++;
+  return RST_OK;
+}
+
+rst_status rst_batch_add(rst_ctx* c, const rst_problem* p) {
+  if (!c || !p) return RST_EINVAL;
+  if (!c->has_grid) return fail(c, RST_ESTATE, "rst_set_grid not called");
+  if (c->nproj > 0) return fail(c, RST_EUNSUPPORTED, "batched structures carry local potentials only");
+  if (p->nz < 1 || !p->v || !p->gamma_l || !p->gamma_r || p->n_e < 0 || (p->n_e > 0 && !p->energies))
+    return fail(c, RST_EINVAL, "bad rst_problem");
+  if (!std::isfinite(p->ka) || !std::isfinite(p->kb)) return fail(c, RST_EINVAL, "non-finite k");
+  const size_t n = (size_t)c->na * c->nb * p->nz;
+  rst_ctx::HostProb hp;
+  hp.nz = p->nz;
+  hp.v.assign(p->v, p->v + n);
+  hp.gl.assign(p->gamma_l, p->gamma_l + p->nz);
+  hp.gr.assign(p->gamma_r, p->gamma_r + p->nz);
+  hp.en.assign(p->energies, p->energies + p->n_e);
+  hp.ka = p->ka;
+  hp.kb = p->kb;
+  for (double x : hp.v)
+    if (!std::isfinite(x)) return fail(c, RST_EINVAL, "non-finite potential value");
+  for (int z = 0; z < p->nz; ++z)
+    if (!(hp.gl[z] >= 0) || !(hp.gr[z] >= 0) || !std::isfinite(hp.gl[z]) || !std::isfinite(hp.gr[z]))
+      return fail(c, RST_EINVAL, "CAP values must be finite and >= 0");
+  for (double e : hp.en)
+    if (!std::isfinite(e)) return fail(c, RST_EINVAL, "non-finite energy");
+  c->batch.push_back(std::move(hp));
+  c->batch_version++;
+  return RST_OK;
+}
+
+rst_status rst_batch_run(rst_ctx* c, double* T_out, rst_stats* stats) {
+  if (!c) return RST_EINVAL;
+  if (!c->has_grid) return fail(c, RST_ESTATE, "rst_set_grid not called");
+  if (c->rad != 2 && c->rad != 6) return fail(c, RST_EUNSUPPORTED, "GPU kernels are built for FD orders 4 and 12");
+  if (c->opts.precision != RST_FP64 || c->opts.precond != RST_PRECOND_NONE)
+    return fail(c, RST_EUNSUPPORTED, "the batched launch runs FP64 BiCGSTAB without preconditioner");
+  if (c->batch.empty()) return RST_OK;
+  if (!T_out) return fail(c, RST_EINVAL, "null T_out");
+  hipSetDevice(c->device);
+  std::vector<int> all(c->batch.size());
+  for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
+  int cw = c->opts.col_block;
+  rst_status s;
+  if (cw == 0) {
+    // autotune: time every candidate on the costliest structure (2 energies)
+    const long long key = ((long long)c->na << 40) ^ ((long long)c->nb << 24) ^ ((long long)c->rad << 8) ^
+                          c->opts.direction;
+    auto it = c->tuned_cw.find(key);
+    if (it != c->tuned_cw.end()) {
+      cw = it->second;
+    } else {
+      int best = 1;
+      double best_t = 1e300;
+      int worst = 0;
+      double cost = -1;
+      for (size_t i = 0; i < c->batch.size(); ++i) {
+        const double ci = (double)c->batch[i].nz * c->batch[i].en.size();
+        if (ci > cost) { cost = ci; worst = (int)i; }
+      }
+      for (int cand : {1, 2, 4, 8}) {
+        LaunchShape ls;
+        if (choose_shape(c, cand, c->opts.threads, ls) != RST_OK) continue;
+        BatchOut o;
+        if ((s = run_batch(c, {worst}, 2, cand, false, o)) != RST_OK) return s;
+        const double per = o.ms / std::max<size_t>(1, o.its.size());
+        if (per < best_t) { best_t = per; best = cand; }
+      }
+      c->tuned_cw[key] = best;
+      cw = best;
+    }
+  }
+  BatchOut o;
+  if ((s = run_batch(c, all, 0, cw, true, o)) != RST_OK) return s;
+  size_t k = 0;
+  for (size_t i = 0; i < all.size(); ++i)
+    for (double t : o.T[i]) T_out[k++] = t;
+  int nbad = 0;
+  fill_stats(c, stats, o.its, o.rss, o.res, o.stv, o.ms, nbad, o.cw, o.threads, 0.0);
+  if (stats) stats->bytes_algorithmic = o.points_n * 12.0 * 16.0;
+  return nbad ? RST_ENOCONV : RST_OK;
+}
 
 void rst_default_solver(rst_solver_opts* o) {
   if (!o) return;
@@ -716,6 +1028,7 @@ void rst_destroy(rst_ctx* c) {
   if (!c) return;
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -893,7 +1206,7 @@ rst_status rst_transmission(rst_ctx* c, int n_e, const double* E, double* T_out,
     T_out[i] = t;
   }
   int nbad = 0;
-  fill_stats(c, stats, its, rss, res, stv, ms, nbad);
+  fill_stats(c, stats, its, rss, res, stv, ms, nbad, c->last_cw, c->last_threads);
   return nbad ? RST_ENOCONV : RST_OK;
 }
 
@@ -915,7 +1228,7 @@ rst_status rst_solve_columns(rst_ctx* c, double energy, int ncol, const int64_t*
   s = run_solver(c, 1, &energy, cols, nullptr, nullptr, (double2*)x_dev, Tcol, its, rss, res, stv, ms);
   if (s != RST_OK) return s;
   int nbad = 0;
-  fill_stats(c, stats, its, rss, res, stv, ms, nbad);
+  fill_stats(c, stats, its, rss, res, stv, ms, nbad, c->last_cw, c->last_threads);
   return nbad ? RST_ENOCONV : RST_OK;
 }
 

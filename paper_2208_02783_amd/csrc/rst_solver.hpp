@@ -372,12 +372,51 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab(const SolveAr
   cx<double>* pb = reinterpret_cast<cx<double>*>(A.pws) + (size_t)blockIdx.x * A.pws_stride;
   ProjArrays PA{pb, pb + np, pb + 2 * np, pb + 3 * np, pb + 4 * np};
   const Pos<Q> ps = make_pos<Q>(A.g, cw, RAD);
+  __shared__ SolveArgs Ai;  // per-item arguments of a batched launch
+  __shared__ int local_item;
   for (;;) {
     if (threadIdx.x == 0) S.item = atomicAdd(A.counter, 1);
     __syncthreads();
     const int item = S.item;
     if (item >= A.nitems) break;
-    solve_item<RAD, Q, R>(A, C, ps, PA, item);
+    if (A.nprob > 0) {
+      if (threadIdx.x == 0) {
+        int lo = 0, hi = A.nprob - 1;  // last structure whose first item <= item
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) / 2;
+          if (A.batch[mid].item0 <= item) lo = mid; else hi = mid - 1;
+        }
+        const BatchProb bp = A.batch[lo];
+        Ai = A;
+        Ai.g.nz = bp.nz;
+        Ai.g.pha_x = bp.pha_x;
+        Ai.g.pha_y = bp.pha_y;
+        Ai.g.phb_x = bp.phb_x;
+        Ai.g.phb_y = bp.phb_y;
+        Ai.V = A.V + bp.v_off;
+        Ai.gz = A.gz + bp.gz_off;
+        Ai.gdst = A.gdst + bp.gz_off;
+        Ai.gsrc = A.gsrc + bp.gz_off;
+        Ai.energies = A.energies + bp.e_off;
+        Ai.cols = A.cols + bp.col_off;
+        Ai.ncols = bp.ncols;
+        Ai.nblk = bp.nblk;
+        Ai.ne = bp.ne;
+        Ai.T_col = A.T_col + bp.out_off;
+        Ai.iters = A.iters + bp.out_off;
+        Ai.restarts = A.restarts + bp.out_off;
+        Ai.resid = A.resid + bp.out_off;
+        Ai.status = A.status + bp.out_off;
+        local_item = (int)(item - bp.item0);
+      }
+      __syncthreads();
+      C.g = &Ai.g;
+      C.V = Ai.V;
+      C.gz = Ai.gz;
+      solve_item<RAD, Q, R>(Ai, C, ps, PA, local_item);
+    } else {
+      solve_item<RAD, Q, R>(A, C, ps, PA, item);
+    }
   }
 }
 

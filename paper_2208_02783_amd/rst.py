@@ -24,7 +24,8 @@ RST_PRECOND_NONE, RST_PRECOND_FREE_CAP = 0, 1
 
 EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error", "rst_set_grid",
             "rst_set_potential", "rst_set_projectors", "rst_set_abc", "rst_set_k", "rst_set_solver",
-            "rst_transmission", "rst_apply_h", "rst_solve_columns"]
+            "rst_transmission", "rst_apply_h", "rst_solve_columns", "rst_batch_clear",
+            "rst_batch_add", "rst_batch_run"]
 
 
 class rst_solver_opts(C.Structure):
@@ -39,10 +40,17 @@ class rst_stats(C.Structure):
                 ("iterations_total", C.c_int64), ("iterations_max", C.c_int32),
                 ("restarts_total", C.c_int32), ("max_rel_residual", C.c_double),
                 ("kernel_ms", C.c_double), ("bytes_algorithmic", C.c_double),
-                ("refinements_total", C.c_int64)]
+                ("refinements_total", C.c_int64), ("col_block", C.c_int32),
+                ("threads", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rst_problem(C.Structure):
+    _fields_ = [("nz", C.c_int), ("v", C.c_void_p), ("gamma_l", C.c_void_p),
+                ("gamma_r", C.c_void_p), ("ka", C.c_double), ("kb", C.c_double),
+                ("n_e", C.c_int), ("energies", C.c_void_p)]
 
 
 class RstError(RuntimeError):
@@ -80,6 +88,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.rst_transmission.argtypes = [P, C.c_int, P, P, C.POINTER(rst_stats)]
     lib.rst_apply_h.argtypes = [P, C.c_double, P, P, C.c_int]
     lib.rst_solve_columns.argtypes = [P, C.c_double, C.c_int, P, P, C.POINTER(rst_stats)]
+    lib.rst_batch_clear.argtypes = [P]
+    lib.rst_batch_add.argtypes = [P, C.POINTER(rst_problem)]
+    lib.rst_batch_run.argtypes = [P, P, C.POINTER(rst_stats)]
     for name in EXPORTED:
         if name not in ("rst_default_solver", "rst_destroy", "rst_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -187,6 +198,25 @@ class Context:
         s = self._chk(self.lib.rst_solve_columns(self.h, float(energy), cols.size, _ptr(cols),
                                                  C.c_void_p(x_dev_ptr), C.byref(st)), allow_noconv=True)
         return st.as_dict(), s
+
+    # -- batches
+    def rst_batch_clear(self):
+        self._batch_ne = 0
+        return self._chk(self.lib.rst_batch_clear(self.h))
+
+    def rst_batch_add(self, nz, v, gamma_l, gamma_r, ka, kb, energies):
+        arrs = [np.ascontiguousarray(a, np.float64) for a in (v, gamma_l, gamma_r, energies)]
+        pr = rst_problem(int(nz), _ptr(arrs[0]).value, _ptr(arrs[1]).value, _ptr(arrs[2]).value,
+                         float(ka), float(kb), int(arrs[3].size), _ptr(arrs[3]).value)
+        self._batch_ne = getattr(self, "_batch_ne", 0) + arrs[3].size
+        return self._chk(self.lib.rst_batch_add(self.h, C.byref(pr)))
+
+    def rst_batch_run(self, total_energies=None):
+        n = int(total_energies if total_energies is not None else getattr(self, "_batch_ne", 0))
+        t = np.zeros(max(n, 1))
+        st = rst_stats()
+        s = self._chk(self.lib.rst_batch_run(self.h, _ptr(t), C.byref(st)), allow_noconv=True)
+        return t[:n], st.as_dict(), s
 
     # -- convenience
     def load_problem(self, prob, k=None):

@@ -261,3 +261,71 @@ def test_mixed_solve_columns():
     ref = oracle.green_columns(p, float(p.energies[2]), k, cols)
     err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
     assert err <= 1e-9, (err, st)
+
+
+# ------------------------------------------------------------- batching
+
+def _batch_ctx(slabs, **solver):
+    p0 = slabs[0]
+    ctx = rst.Context(0)
+    ctx.rst_set_grid(p0.na, p0.nb, p0.nz, p0.ha, p0.hb, p0.hz, p0.order)
+    ctx.rst_set_solver(**solver)
+    for p in slabs:
+        ctx.rst_batch_add(p.nz, p.v, p.gamma_l, p.gamma_r, p.kpts[0][0], p.kpts[0][1], p.energies)
+    return ctx
+
+
+def test_batch_equals_individual_launches():
+    """Uneven slabs (config-4 generator) in one persistent launch give the same T
+    as one launch per slab; with the same column block the results are bitwise
+    identical, since each item is computed by one workgroup in a fixed order."""
+    torch = torch_cuda()
+    slabs = wl.batch_slabs(n_slabs=6, ne=3, cells=(6, 10))
+    ctx = _batch_ctx(slabs, col_block=1)
+    tb, st, s = ctx.rst_batch_run()
+    _say("batch stats", st)
+    assert s == rst.RST_OK and st["col_block"] == 1
+    ti = []
+    for p in slabs:
+        c1 = make_ctx(torch, p, p.kpts[0], col_block=1)
+        t, _, s1 = c1.rst_transmission(p.energies)
+        assert s1 == rst.RST_OK
+        ti.append(t)
+    assert np.array_equal(tb, np.concatenate(ti))
+    # autotuned column block: same T to rounding
+    ctx2 = _batch_ctx(slabs)
+    tb2, st2, s2 = ctx2.rst_batch_run()
+    _say("autotuned col_block", st2["col_block"], "threads", st2["threads"])
+    assert s2 == rst.RST_OK
+    np.testing.assert_allclose(tb2, tb, rtol=0, atol=1e-9)
+
+
+def test_batch_matches_oracle_and_graph_replay():
+    torch = torch_cuda()
+    slabs = wl.batch_slabs(n_slabs=3, ne=2, cells=(6, 8), replica=1)
+    ctx = _batch_ctx(slabs)
+    t1, st, s = ctx.rst_batch_run()
+    x = torch.ones(1 << 20, device="cuda")
+    x.mul_(2.0)  # eager work between graph replays
+    torch.cuda.synchronize()
+    t2, _, _ = ctx.rst_batch_run()
+    assert np.array_equal(t1, t2)
+    ref = np.concatenate([oracle.transmission(p, p.energies, p.kpts[0], both=False)["T_LR"]
+                          for p in slabs])
+    for p, tt, rr in zip([p for p in slabs for _ in p.energies], t1, ref):
+        assert abs(tt - rr) <= 1e-6 * max(1, n_channels(p, 0.5, p.kpts[0]) + 4), (tt, rr)
+
+
+def test_batch_edge_cases():
+    torch = torch_cuda()
+    slabs = wl.batch_slabs(n_slabs=1, ne=1)
+    p = slabs[0]
+    c = rst.Context(0)
+    c.rst_set_grid(p.na, p.nb, p.nz, p.ha, p.hb, p.hz, p.order)
+    t, st, s = c.rst_batch_run(0)
+    assert s == rst.RST_OK and t.size == 0
+    q = wl.config(2, tiny=True)
+    c2 = make_ctx(torch, q, q.kpts[0])
+    with pytest.raises(rst.RstError) as ei:
+        c2.rst_batch_add(q.nz, q.v, q.gamma_l, q.gamma_r, 0.0, 0.0, q.energies[:1])
+    assert ei.value.status == rst.RST_EUNSUPPORTED
