@@ -82,7 +82,7 @@ def cpu_baseline(seconds_budget=20.0):
                       f"~{per_point * (n_full / n_tiny) ** 3 / 3600:.2f} h per point"}
 
 
-def batched_comparison(n_slabs=96, ne=2):
+def batched_comparison(n_slabs=96, ne=2, precond=1):
     """Config 4 subset: 96 uneven free-electron slabs (8x8x{48..160}, order 4,
     10-plane CAPs, random k), `ne` energies each.  Plain: one rst_transmission
     call per slab; batched: one persistent launch over every (slab, energy,
@@ -96,12 +96,13 @@ def batched_comparison(n_slabs=96, ne=2):
     # plain: per-slab launches
     ctx = rst.Context(0)
     ctx.rst_set_grid(p0.na, p0.nb, p0.nz, p0.ha, p0.hb, p0.hz, p0.order)
-    ctx.rst_set_solver()
+    ctx.rst_set_solver(precond=precond)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t_plain, ok_plain, cols = [], True, 0
     for p in slabs:
         ctx.load_problem(p, p.kpts[0])
+        ctx.rst_set_solver(precond=precond)
         t, st, s = ctx.rst_transmission(p.energies[pick])
         t_plain.append(t)
         ok_plain &= s == rst.RST_OK
@@ -110,7 +111,7 @@ def batched_comparison(n_slabs=96, ne=2):
     # batched: one launch (first run tunes and captures the graph; the second is timed)
     cb = rst.Context(0)
     cb.rst_set_grid(p0.na, p0.nb, p0.nz, p0.ha, p0.hb, p0.hz, p0.order)
-    cb.rst_set_solver()
+    cb.rst_set_solver(precond=precond)
     for p in slabs:
         cb.rst_batch_add(p.nz, p.v, p.gamma_l, p.gamma_r, p.kpts[0][0], p.kpts[0][1], p.energies[pick])
     cb.rst_batch_run()
@@ -123,7 +124,8 @@ def batched_comparison(n_slabs=96, ne=2):
     print(f"batched comparison: plain {npts / wall_plain:.1f} pts/s, batched {npts / wall_b:.1f} pts/s",
           file=sys.stderr, flush=True)
     return {"workload": f"{n_slabs} free-electron slabs 8x8x(48..160), h=0.5, order 4, 10-plane CAPs, "
-                        f"random k, {ne} energies each ({npts} T(E,k) points, {cols} column solves)",
+                        f"random k, {ne} energies each ({npts} T(E,k) points, {cols} column solves), "
+                        f"{'free-electron + CAP preconditioned' if precond else 'plain'} BiCGSTAB",
             "plain_points_per_s": npts / wall_plain, "batched_points_per_s": npts / wall_b,
             "batched_col_block": st_b["col_block"], "batched_threads": st_b["threads"],
             "max_abs_dT_plain_vs_batched": dmax, "all_converged": bool(ok_plain and s_b == rst.RST_OK)}

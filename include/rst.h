@@ -61,30 +61,42 @@ typedef enum {
   RST_EUNSUPPORTED = -5   /* valid but not supported by the GPU kernels */
 } rst_status;
 
-typedef enum { RST_BICGSTAB = 0 } rst_method;
+typedef enum { RST_BICGSTAB = 0, RST_FGMRES = 1 } rst_method;
 typedef enum { RST_FP64 = 0, RST_FP32_REFINE = 1 } rst_precision;
 typedef enum { RST_DIR_LR = 0, RST_DIR_RL = 1 } rst_direction;
-typedef enum { RST_PRECOND_NONE = 0, RST_PRECOND_FREE_CAP = 1 } rst_precond;
+typedef enum { RST_PRECOND_NONE = 0, RST_PRECOND_FREE_CAP = 1, RST_PRECOND_LEARNED = 2 } rst_precond;
 
 /* Solver options.  rst_default_solver() fills the defaults. */
 typedef struct {
-  int method;        /* rst_method */
-  int precision;     /* rst_precision; RST_FP32_REFINE: FP32 stencil/projector applies inside an FP64 refinement loop */
+  int method;        /* rst_method.  RST_BICGSTAB: the persistent fused BiCGSTAB kernels (every precision
+                        and preconditioner except RST_PRECOND_LEARNED).  RST_FGMRES: restarted flexible
+                        GMRES(restart) in FP64 over chunks of columns (classical Gram-Schmidt twice),
+                        convergence on the FP64 true residual after each cycle; precision FP64 only */
+  int precision;     /* rst_precision; RST_FP32_REFINE: BiCGSTAB on complex64 vectors with FP32 stencil,
+                        projector and preconditioner applies (inner products, scalars and projections
+                        FP64), the solution kept as x64 + x32 and the recursive residual replaced by the
+                        FP64 true residual b - A x64 whenever it has fallen by update_delta (reliable
+                        updates, Sleijpen and van der Vorst 1996); convergence is decided on the FP64
+                        true residual */
   double tol;        /* stop when the FP64 true residual ||b - A x|| <= tol ||b|| per column (default 1e-10) */
   int max_iter;      /* BiCGSTAB iterations per column (default 20000) */
   int col_block;     /* columns solved together by one workgroup; 0 = automatic */
   int threads;       /* workgroup size (multiple of 64, <= 512); 0 = automatic */
   int direction;     /* RST_DIR_LR: columns in the right CAP, T accumulated on the left (default);
                         RST_DIR_RL: the reverse.  Both give the same T (exact identity). */
-  double inner_tol;  /* RST_FP32_REFINE: relative tolerance of each FP32 inner solve (default 1e-4);
-                        an inner solve also ends after max_iter iterations or when its residual
-                        has not halved for 40 iterations (FP32 stagnation) */
-  int max_outer;     /* RST_FP32_REFINE: refinement steps (default 30) */
+  double update_delta; /* RST_FP32_REFINE: the residual is replaced once its norm is below update_delta
+                          times the largest since the last replacement (default 0.1, in (0, 1)) */
   int precond;       /* rst_precond.  RST_PRECOND_FREE_CAP: right preconditioner
                         M = E - (-1/2 L_lat - 1/2 D2_z + Vbar) + i Gamma(z) with the exact
                         lateral FD Laplacian (diagonal in the twisted lateral Fourier basis),
                         the three-point z Laplacian and Vbar = mean(V); applied by lateral DFTs
-                        and one tridiagonal solve per lateral mode.  Default NONE. */
+                        and one tridiagonal solve per lateral mode.  RST_PRECOND_LEARNED (RST_FGMRES
+                        only): z = M^-1 r + f(r, M^-1 r) with the context's network f (rst_cnn_*).
+                        Default NONE. */
+  int restart;       /* RST_FGMRES: Krylov steps per cycle (default 30, 1..200) */
+  double fallback_ratio; /* RST_PRECOND_LEARNED: a column whose true residual after a cycle is above
+                            fallback_ratio times the previous cycle's continues with M^-1 alone
+                            (default 0.5, in (0, 1]) */
 } rst_solver_opts;
 
 /* Statistics of the last rst_transmission / rst_solve_columns call. */
@@ -92,17 +104,19 @@ typedef struct {
   int64_t columns;          /* column solves performed */
   int64_t columns_unconverged;
   int64_t iterations_total; /* BiCGSTAB iterations summed over columns */
-  int32_t iterations_max;
+  int32_t iterations_max;   /* RST_FGMRES: Arnoldi steps; restarts_total then counts cycles */
   int32_t restarts_total;   /* breakdown restarts */
   double max_rel_residual;  /* largest FP64 true relative residual */
   double kernel_ms;         /* device time of the solver kernel(s) */
   double bytes_algorithmic; /* algorithmic HBM bytes of the Krylov sweeps: FP64 BiCGSTAB 12 (plain) or
                                24 (preconditioned) complex128 streams per grid point, iteration and
                                column; RST_FP32_REFINE the same counts of complex64 streams plus
-                               14 complex128-equivalent streams per refinement step */
-  int64_t refinements_total; /* RST_FP32_REFINE: FP64 refinement steps summed over columns */
+                               72 B per grid point and reliable update */
+  int64_t updates_total;     /* RST_FP32_REFINE: FP64 residual replacements summed over columns */
   int32_t col_block;         /* columns per workgroup used by the launch */
   int32_t threads;           /* workgroup size used by the launch */
+  int64_t fallback_columns;  /* RST_PRECOND_LEARNED: columns switched to M^-1 alone */
+  double cnn_flop;           /* RST_PRECOND_LEARNED: network flops (2 per multiply-add) */
 } rst_stats;
 
 /* One structure of a batch (rst_batch_add).  The lateral grid, spacings and
@@ -173,14 +187,68 @@ rst_status rst_solve_columns(rst_ctx *ctx, double energy, int ncol, const int64_
  * appends a structure (RST_EUNSUPPORTED if the context has projectors: the
  * batch path carries local potentials only); rst_batch_run computes T for
  * every (structure, energy) into T_out (host, sum of n_e doubles, in the order
- * the structures were added) with the context's solver options (FP64 BiCGSTAB
- * without preconditioner).  With col_block = 0 the columns per workgroup are
+ * the structures were added) with the context's solver options (FP64
+ * BiCGSTAB, with or without the free-electron + CAP preconditioner).  With col_block = 0 the columns per workgroup are
  * chosen by timing the candidates on a sample of the batch (cached per lateral
  * shape); the launch is captured in a HIP graph and replayed while the batch is
  * unchanged. */
 rst_status rst_batch_clear(rst_ctx *ctx);
 rst_status rst_batch_add(rst_ctx *ctx, const rst_problem *prob);
 rst_status rst_batch_run(rst_ctx *ctx, double *T_out, rst_stats *stats);
+
+/* ---- Learned correction network of the learned preconditioner ----------------
+ * A three-level 3D U-Net f (16 channels, 3x3x3 convolutions without biases,
+ * ReLU, 2x2x2 mean pooling over the existing children, nearest upsampling with
+ * additive skips; layers W0..W8) maps the four channels (Re r, Im r, Re m, Im m)
+ * of a residual r and m = M^-1 r (M the free-electron + CAP preconditioner) to
+ * a two-channel correction: the learned preconditioner is z = m + f(r, m).
+ * Convolutions are cross-correlations, periodic laterally and zero beyond the
+ * end planes along z.  Tensors are FP32 channel-last device arrays:
+ * element (column c, grid point p, channel ch) at (c*n + p)*C + ch with
+ * p = (iz*nb + ib)*na + ia.  Weights (host, FP32) are the layers W0..W8 one
+ * after another, each (cout, cin, 3, 3, 3) row-major, taps (dz, db, da) with
+ * dz slowest; (cout, cin) = (16, 4), (16, 16) x 7, (2, 16).
+ * The GPU evaluates the convolutions on FP32 matrix cores. */
+int64_t rst_cnn_weight_count(void);
+/* He-normal weights from `seed` (last layer scaled by 0.1); resets Adam. */
+rst_status rst_cnn_seed(rst_ctx *ctx, uint64_t seed);
+rst_status rst_cnn_set_weights(rst_ctx *ctx, const float *w, int64_t count);
+rst_status rst_cnn_get_weights(rst_ctx *ctx, float *w, int64_t count);
+/* out_dev [ncol][n][2] = f(x_dev [ncol][n][4]) on an nz x nb x na grid (n = nz*nb*na). */
+rst_status rst_cnn_forward(rst_ctx *ctx, int ncol, int nz, int nb, int na, const float *x_dev, float *out_dev);
+/* grad (host, rst_cnn_weight_count() floats, weight layout) = d<gout, f(x)>/dW for
+ * gout_dev [ncol][n][2]. */
+rst_status rst_cnn_gradient(rst_ctx *ctx, int ncol, int nz, int nb, int na, const float *x_dev,
+                            const float *gout_dev, float *grad);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) on L = (1/ncol) sum_c ||f(x_c) - target_c||^2;
+ * *loss = L before the step.  target_dev [ncol][n][2]. */
+rst_status rst_cnn_train_step(rst_ctx *ctx, int ncol, int nz, int nb, int na, const float *x_dev,
+                              const float *target_dev, float lr, double *loss);
+
+/* Training of the network (Adam on FP32 weights).  Each step draws one energy
+ * from `energies` and one lateral k from `kpts` (n_k pairs (ka, kb)), then
+ * `batch` pairs: xi complex normal (SplitMix64 counter-based, Box-Muller),
+ * e = M^-1 xi, r = A e with A = E - H_k + i Gamma, both scaled so that
+ * ||r|| = 1; input (r, M^-1 r), target e - M^-1 r.  steps = ceil(pairs / batch).
+ * Starts from the context's weights (seeded from `seed` if it has none); the
+ * context's k is restored on return. */
+typedef struct {
+  int pairs;               /* training pairs */
+  int batch;               /* pairs per Adam step, 1..64 */
+  float lr;                /* Adam step size */
+  uint64_t seed;
+  int n_e;
+  const double *energies;  /* host, n_e (Ha) */
+  int n_k;
+  const double *kpts;      /* host, 2*n_k (bohr^-1) */
+} rst_train_opts;
+typedef struct {
+  int steps;
+  double loss_first;       /* mean loss of the first min(10, steps/4) steps */
+  double loss_last;        /* mean loss of the last min(10, steps/4) steps */
+  double ms;               /* device time */
+} rst_train_stats;
+rst_status rst_precond_train(rst_ctx *ctx, const rst_train_opts *opts, rst_train_stats *stats);
 
 #ifdef __cplusplus
 }

@@ -30,12 +30,13 @@ def build(verbose: bool = False, jobs: int | None = None, out: str = LIB, define
     objdir = tempfile.mkdtemp(prefix="rstbuild_")
     units = []
     # heaviest first: the preconditioned solvers, then the plain solvers, then apply
-    for kind in (4, 2, 3, 0, 1):
+    for kind in (4, 2, 6, 3, 0, 5, 1, 7):
         for rad, q in INSTANCES:
             units.append((os.path.join(CSRC, "kern_inst.hip"),
                           os.path.join(objdir, f"k{kind}_r{rad}_q{q}.o"),
                           [f"-DRST_RAD={rad}", f"-DRST_Q={q}", f"-DRST_KIND={kind}"]))
     procs = []
+    units.append((os.path.join(CSRC, "rst_cnn.hip"), os.path.join(objdir, "rst_cnn.o"), []))
     units.append((os.path.join(CSRC, "rst_lib.hip"), os.path.join(objdir, "rst_lib.o"), []))
     pending = list(units)
     objs = []

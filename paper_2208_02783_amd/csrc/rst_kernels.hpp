@@ -179,6 +179,9 @@ struct BatchProb {
   int gz_off;         // offset of its CAP profiles (gz, gdst, gsrc)
   int e_off;          // offset of its energies
   double pha_x, pha_y, phb_x, phb_y;
+  // preconditioner: lateral mode energies, DFT steps and Thomas pivots of this structure
+  long long eps_off, steps_off, inv_off;
+  double vbar;
 };
 
 struct SolveArgs {
@@ -187,9 +190,8 @@ struct SolveArgs {
   Geo g;
   Proj pj;
   PcConst pc;
-  double inner_tol;         // mixed precision: relative tolerance of each FP32 inner solve
-  int inner_max;            // mixed precision: iterations per inner solve
-  int max_outer;            // mixed precision: refinement steps
+  double delta;             // mixed precision: reliable-update factor (see rst_mixed.hpp)
+  int* updates;             // mixed precision: [ne*ncols] FP64 residual replacements per column
   size_t pc_lds_off;        // byte offset of the DFT tables in dynamic LDS
   const double* V;          // [n]
   const double* gz;         // [nz] Gamma_L + Gamma_R
@@ -224,14 +226,15 @@ struct ApplyArgs {
   int ncol, cw, nblk;
   double2* pws;             // per-workgroup projection scratch (2 arrays nproj*cw)
   size_t pws_stride;
+  int blocked;              // 1: x, y in blocked layout (block b: n x cw column-fastest at b*n*cw)
 };
 
 // ---------------------------------------------------------------------------
 // Sweep modes
 // ---------------------------------------------------------------------------
 
-enum InMode { IN_INIT, IN_A, IN_RESTART, IN_B, IN_X, IN_EXT, IN_PC, IN_INIT_VEC };
-enum OutMode { OUT_V, OUT_T, OUT_RES, OUT_EXT, OUT_TS };
+enum InMode { IN_INIT, IN_A, IN_RESTART, IN_B, IN_X, IN_EXT, IN_PC };
+enum OutMode { OUT_V, OUT_T, OUT_RES, OUT_EXT, OUT_TS, OUT_RES32 };
 
 // Per-column scalar state shared by the workgroup.
 struct ColState {
@@ -243,10 +246,11 @@ struct ColState {
   long long src[CW_MAX], j0[CW_MAX], rmax_idx[CW_MAX];
   int state[CW_MAX];       // 0 active, 1 done, 2 failed, 3 padding
   int iters[CW_MAX], restarts[CW_MAX];
-  // mixed precision: scale of the inner right-hand side r64 (1/||r64||), the
-  // inner solve's own state (0 running, 1 stopped) and the refinement steps
-  double rscale[CW_MAX], uscale[CW_MAX], ibest[CW_MAX];
-  int istate[CW_MAX], outer[CW_MAX], istall[CW_MAX];
+  // mixed precision: largest recursive ||r||^2 since the last FP64 residual
+  // replacement, the replacements so far, and the block's replacement request
+  double maxrr[CW_MAX];
+  int updates[CW_MAX];
+  int upd_flag;
   int any_flag;
   int item;
 };

@@ -7,10 +7,13 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <random>
 #include <string>
 #include <vector>
 
 #include "../../include/rst.h"
+#include "rst_cnn_api.hpp"
+#include "rst_fgmres.hpp"
 #include "rst_mixed.hpp"
 
 using rst::cx;
@@ -65,6 +68,7 @@ struct DevBuf {
 
 struct rst_ctx {
   int device = 0;
+  rst::cnn::Engine* cnn = nullptr;  // learned correction network (created on first use)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
@@ -98,7 +102,14 @@ struct rst_ctx {
   // solver
   rst_solver_opts opts;
   // work buffers (grown on demand)
-  DevBuf d_ws, d_pws, d_cols, d_en, d_T, d_it, d_rs, d_res, d_st, d_counter, d_args, d_pc_inv;
+  DevBuf d_ws, d_pws, d_cols, d_en, d_T, d_it, d_rs, d_res, d_st, d_counter, d_args, d_pc_inv, d_up;
+  std::vector<int> last_updates;  // mixed precision: FP64 residual replacements per column of the last solve
+  long long last_fallbacks = 0;   // FGMRES: columns whose learned correction was switched off
+  double last_cnn_flop = 0.0;     // FGMRES: network flops of the last solve
+  double last_fg_bytes = 0.0;     // FGMRES: algorithmic vector bytes of the last solve
+  // flexible GMRES chunk buffers
+  DevBuf d_fgV, d_fgZ, d_fgX, d_fgW, d_fgM, d_fgwb, d_fgx0, d_fgf, d_fgH, d_fgcs, d_fgsn, d_fgg, d_fginv, d_fgest,
+      d_fgact, d_fgit, d_fguse, d_fgh1, d_fgh2, d_fgn2, d_fgy, d_fgsrc, d_fgbsc, d_fgt, d_fgaa, d_fgpa, d_fgsa;
   // batch of structures (rst_batch_add)
   struct HostProb {
     int nz;
@@ -110,7 +121,7 @@ struct rst_ctx {
   std::map<long long, int> tuned_cw;  // (lateral shape, order, direction) -> columns per workgroup
   hipGraphExec_t gexec = nullptr;
   long long gexec_key = -1;
-  DevBuf d_bprob, d_bv, d_bgz, d_bgl, d_bgr, d_ben, d_bcols;
+  DevBuf d_bprob, d_bv, d_bgz, d_bgl, d_bgr, d_ben, d_bcols, d_bpc_eps, d_bpc_steps, d_bpargs;
   int last_cw = 0, last_threads = 0;
   // host copies of the last kernel-argument blocks (kept alive for async copies)
   rst::SolveArgs h_solve;
@@ -386,9 +397,7 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
   return RST_OK;
 }
 
-// Lateral mode energies and twisted DFT tables of the free-electron + CAP
-// preconditioner for the current grid and k.
-rst_status upload_pc(rst_ctx* c) {
+void pc_tables(const rst_ctx* c, double ka, double kb, std::vector<double>& eps, std::vector<double2>& steps) {
   const int na = c->na, nb = c->nb;
   const double la = na * c->ha, lb = nb * c->hb;
   const double pi = 3.14159265358979323846;
@@ -397,23 +406,31 @@ rst_status upload_pc(rst_ctx* c) {
     for (int j = 1; j <= c->rad; ++j) s -= 2.0 * c->fdw[j] * std::cos(j * th);
     return s;
   };
-  std::vector<double> eps((size_t)na * nb);
+  eps.assign((size_t)na * nb, 0.0);
   for (int mb = 0; mb < nb; ++mb)
     for (int ma = 0; ma < na; ++ma) {
-      const double ta = (c->ka + 2 * pi * ma / la) * c->ha;
-      const double tb = (c->kb + 2 * pi * mb / lb) * c->hb;
+      const double ta = (ka + 2 * pi * ma / la) * c->ha;
+      const double tb = (kb + 2 * pi * mb / lb) * c->hb;
       eps[(size_t)mb * na + ma] = 0.5 * (symbol(ta) / (c->ha * c->ha) + symbol(tb) / (c->hb * c->hb));
     }
   // DFT recurrence steps: fa[m] = exp(-i(2 pi m/na + k_a h_a)), ia[a] = exp(+2 pi i a/na),
   // pa[a] = exp(+i k_a a h_a) (same for b)
-  std::vector<double2> steps;
+  steps.clear();
   auto push = [&](double ph) { steps.push_back(double2{std::cos(ph), std::sin(ph)}); };
-  for (int m = 0; m < na; ++m) push(-(2 * pi * m / na + c->ka * c->ha));
-  for (int m = 0; m < nb; ++m) push(-(2 * pi * m / nb + c->kb * c->hb));
+  for (int m = 0; m < na; ++m) push(-(2 * pi * m / na + ka * c->ha));
+  for (int m = 0; m < nb; ++m) push(-(2 * pi * m / nb + kb * c->hb));
   for (int a = 0; a < na; ++a) push(2 * pi * a / na);
   for (int b = 0; b < nb; ++b) push(2 * pi * b / nb);
-  for (int a = 0; a < na; ++a) push(c->ka * a * c->ha);
-  for (int b = 0; b < nb; ++b) push(c->kb * b * c->hb);
+  for (int a = 0; a < na; ++a) push(ka * a * c->ha);
+  for (int b = 0; b < nb; ++b) push(kb * b * c->hb);
+}
+
+// Lateral mode energies and DFT steps of the free-electron + CAP
+// preconditioner for the current grid and k.
+rst_status upload_pc(rst_ctx* c) {
+  std::vector<double> eps;
+  std::vector<double2> steps;
+  pc_tables(c, c->ka, c->kb, eps, steps);
   rst_status s;
   if ((s = upload(c, c->d_pc_eps, eps)) != RST_OK) return s;
   return upload(c, c->d_pc_twa, steps);
@@ -439,48 +456,40 @@ rst_status upload_k(rst_ctx* c) {
 
 // kernel dispatch ------------------------------------------------------------
 // Instances live in kern_inst.hip (one translation unit per radius / positions).
-extern "C" void* rst_kptr_k0_r2_q1();
-extern "C" void* rst_kptr_k0_r2_q2();
-extern "C" void* rst_kptr_k0_r6_q1();
-extern "C" void* rst_kptr_k0_r6_q2();
-extern "C" void* rst_kptr_k1_r2_q1();
-extern "C" void* rst_kptr_k1_r2_q2();
-extern "C" void* rst_kptr_k1_r6_q1();
-extern "C" void* rst_kptr_k1_r6_q2();
-extern "C" void* rst_kptr_k2_r2_q1();
-extern "C" void* rst_kptr_k2_r2_q2();
-extern "C" void* rst_kptr_k2_r6_q1();
-extern "C" void* rst_kptr_k2_r6_q2();
-extern "C" void* rst_kptr_k3_r2_q1();
-extern "C" void* rst_kptr_k3_r2_q2();
-extern "C" void* rst_kptr_k3_r6_q1();
-extern "C" void* rst_kptr_k3_r6_q2();
-extern "C" void* rst_kptr_k4_r2_q1();
-extern "C" void* rst_kptr_k4_r2_q2();
-extern "C" void* rst_kptr_k4_r6_q1();
-extern "C" void* rst_kptr_k4_r6_q2();
+// Kinds: 0 plain solver, 1 apply, 2 preconditioned solver, 3/4 mixed-precision
+// plain/preconditioned solvers, 5/6 batched plain/preconditioned solvers.
+#define RST_KINST(K)                       \
+  extern "C" void* rst_kptr_k##K##_r2_q1(); \
+  extern "C" void* rst_kptr_k##K##_r2_q2(); \
+  extern "C" void* rst_kptr_k##K##_r6_q1(); \
+  extern "C" void* rst_kptr_k##K##_r6_q2();
+RST_KINST(0)
+RST_KINST(1)
+RST_KINST(2)
+RST_KINST(3)
+RST_KINST(4)
+RST_KINST(5)
+RST_KINST(6)
+RST_KINST(7)
+#undef RST_KINST
 
 void* pick_kernel(int rad, int q, int w) {
-  if (w == 0 && rad == 2 && q == 1) return rst_kptr_k0_r2_q1();
-  if (w == 0 && rad == 2 && q == 2) return rst_kptr_k0_r2_q2();
-  if (w == 0 && rad == 6 && q == 1) return rst_kptr_k0_r6_q1();
-  if (w == 0 && rad == 6 && q == 2) return rst_kptr_k0_r6_q2();
-  if (w == 1 && rad == 2 && q == 1) return rst_kptr_k1_r2_q1();
-  if (w == 1 && rad == 2 && q == 2) return rst_kptr_k1_r2_q2();
-  if (w == 1 && rad == 6 && q == 1) return rst_kptr_k1_r6_q1();
-  if (w == 1 && rad == 6 && q == 2) return rst_kptr_k1_r6_q2();
-  if (w == 2 && rad == 2 && q == 1) return rst_kptr_k2_r2_q1();
-  if (w == 2 && rad == 2 && q == 2) return rst_kptr_k2_r2_q2();
-  if (w == 2 && rad == 6 && q == 1) return rst_kptr_k2_r6_q1();
-  if (w == 2 && rad == 6 && q == 2) return rst_kptr_k2_r6_q2();
-  if (w == 3 && rad == 2 && q == 1) return rst_kptr_k3_r2_q1();
-  if (w == 3 && rad == 2 && q == 2) return rst_kptr_k3_r2_q2();
-  if (w == 3 && rad == 6 && q == 1) return rst_kptr_k3_r6_q1();
-  if (w == 3 && rad == 6 && q == 2) return rst_kptr_k3_r6_q2();
-  if (w == 4 && rad == 2 && q == 1) return rst_kptr_k4_r2_q1();
-  if (w == 4 && rad == 2 && q == 2) return rst_kptr_k4_r2_q2();
-  if (w == 4 && rad == 6 && q == 1) return rst_kptr_k4_r6_q1();
-  if (w == 4 && rad == 6 && q == 2) return rst_kptr_k4_r6_q2();
+#define RST_KPICK(K)                                                \
+  if (w == K) {                                                     \
+    if (rad == 2) return q == 1 ? rst_kptr_k##K##_r2_q1() : rst_kptr_k##K##_r2_q2(); \
+    if (rad == 6) return q == 1 ? rst_kptr_k##K##_r6_q1() : rst_kptr_k##K##_r6_q2(); \
+    return nullptr;                                                 \
+  }
+  if (q != 1 && q != 2) return nullptr;
+  RST_KPICK(0)
+  RST_KPICK(1)
+  RST_KPICK(2)
+  RST_KPICK(3)
+  RST_KPICK(4)
+  RST_KPICK(5)
+  RST_KPICK(6)
+  RST_KPICK(7)
+#undef RST_KPICK
   return nullptr;
 }
 
@@ -519,10 +528,19 @@ rst_status check_ready(rst_ctx* c) {
 }
 
 // Runs the persistent solver over ncols columns x ne energies.
+rst_status run_fgmres(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
+                      const double* d_gdst, const std::vector<double>* hsrc, double2* xout,
+                      std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
+                      std::vector<double>& res, std::vector<int>& st, double& ms);
+
 rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
                       const double* d_gsrc, const double* d_gdst, double2* xout,
                       std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
                       std::vector<double>& res, std::vector<int>& st, double& ms) {
+  if (c->opts.method == RST_FGMRES) {
+    const std::vector<double>* hsrc = d_gsrc == nullptr ? nullptr : (d_gsrc == c->d_gr.p ? &c->gr : &c->gl);
+    return run_fgmres(c, ne, energies, cols, d_gdst, hsrc, xout, Tcol, its, rss, res, st, ms);
+  }
   LaunchShape ls;
   rst_status s = choose_shape(c, c->opts.col_block, c->opts.threads, ls);
   if (s != RST_OK) return s;
@@ -554,9 +572,9 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
   long long nwg = std::min<long long>(nitems, (long long)per_cu * ncu);
   // bound the workspace to a quarter of free memory
-  // x r p v t (+ ph sh s w with the preconditioner); mixed: FP64 x, r and FP32 inner vectors
+  // x r p v t (+ ph sh s w with the preconditioner); mixed: FP64 x and the FP32 vectors
   const size_t nfv = pc ? 9 : 5;
-  const size_t ws_stride = mixed ? 2 * n * ls.cw + (nfv * n * ls.cw + 1) / 2
+  const size_t ws_stride = mixed ? n * ls.cw + (nfv * n * ls.cw + 1) / 2
                                  : nfv * n * ls.cw;  // elements of cx<double>
   size_t free_b = 0, total_b = 0;
   HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
@@ -576,6 +594,7 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   if ((s = ensure(c, c->d_res, nout * 8)) != RST_OK) return s;
   if ((s = ensure(c, c->d_st, nout * 4)) != RST_OK) return s;
   if ((s = ensure(c, c->d_counter, 64)) != RST_OK) return s;
+  if (mixed && (s = ensure(c, c->d_up, nout * 4)) != RST_OK) return s;
   rst::SolveArgs A;
   std::memset(&A, 0, sizeof(A));
   A.g = g;
@@ -604,9 +623,8 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   A.nitems = (int)nitems;
   A.tol = c->opts.tol;
   A.max_iter = c->opts.max_iter;
-  A.inner_tol = c->opts.inner_tol;
-  A.inner_max = c->opts.max_iter;
-  A.max_outer = c->opts.max_outer;
+  A.delta = c->opts.update_delta;
+  A.updates = mixed ? (int*)c->d_up.p : nullptr;
   A.ws = c->d_ws.p;
   A.ws_stride = ws_stride;
   A.pws = (double2*)c->d_pws.p;
@@ -653,6 +671,8 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   HIPCHK(c, hipMemcpy(rss.data(), c->d_rs.p, nout * 4, hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemcpy(res.data(), c->d_res.p, nout * 8, hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemcpy(st.data(), c->d_st.p, nout * 4, hipMemcpyDeviceToHost));
+  c->last_updates.assign(mixed ? nout : 0, 0);
+  if (mixed) HIPCHK(c, hipMemcpy(c->last_updates.data(), c->d_up.p, nout * 4, hipMemcpyDeviceToHost));
   return RST_OK;
 }
 
@@ -666,27 +686,398 @@ void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const st
   for (size_t i = 0; i < its.size(); ++i) {
     s.iterations_total += its[i];
     s.iterations_max = std::max(s.iterations_max, its[i]);
-    if (c->opts.precision == RST_FP32_REFINE)
-      s.refinements_total += rss[i];
-    else
-      s.restarts_total += rss[i];
+    s.restarts_total += rss[i];
     s.max_rel_residual = std::max(s.max_rel_residual, res[i]);
     if (stv[i] != 0) ++nbad;
   }
   s.columns_unconverged = nbad;
+  const bool mixed = c->opts.precision == RST_FP32_REFINE && c->last_updates.size() == its.size();
+  if (mixed)
+    for (int u : c->last_updates) s.updates_total += u;
+  const bool fgm = c->opts.method == RST_FGMRES && n_override == 0.0;
+  if (fgm) {
+    s.fallback_columns = c->last_fallbacks;
+    s.cnn_flop = c->last_cnn_flop;
+  }
   s.kernel_ms = ms;
   s.col_block = cw;
   s.threads = threads;
   const double n = n_override > 0 ? n_override : (double)c->na * c->nb * c->nz;
   const double streams = c->opts.precond == RST_PRECOND_FREE_CAP ? 24.0 : 12.0;
-  if (c->opts.precision == RST_FP32_REFINE)
-    // inner iterations on FP32 vectors; per refinement step: x64 update (read x64, d, write x64),
-    // FP64 residual (read x64, write r64) and the inner start (read r64, write x, r, p)
+  if (mixed)
+    // iterations on FP32 vectors; per reliable update: the fold (read x64 and x32,
+    // write x64 and x32 = 0: 48 B) and the FP64 residual (read x64, write r32: 24 B)
     s.bytes_algorithmic = (double)s.iterations_total * streams * 8.0 * n +
-                          (double)s.refinements_total * (40.0 + 32.0 + 40.0) * n;
+                          (double)s.updates_total * 72.0 * n;
+  else if (fgm)
+    s.bytes_algorithmic = c->last_fg_bytes;
   else
     s.bytes_algorithmic = (double)s.iterations_total * streams * 16.0 * n;
   if (st) *st = s;
+}
+
+
+// Flexible GMRES(m) over chunks of columns (host-driven; every vector
+// operation is one of the fg kernels, the stencil apply or the preconditioner
+// kernel).  Preconditioner per column: z = v (NONE), z = M^-1 v (FREE_CAP) or
+// z = M^-1 v + f(v, M^-1 v) (LEARNED).  A column whose true residual did not
+// fall below fallback_ratio times its previous cycle's value while the
+// learned correction was on continues with M^-1 alone.
+rst_status run_fgmres(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
+                      const double* d_gdst, const std::vector<double>* hsrc, double2* xout,
+                      std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
+                      std::vector<double>& res, std::vector<int>& st, double& ms) {
+  const bool learned = c->opts.precond == RST_PRECOND_LEARNED;
+  const bool usepc = c->opts.precond != RST_PRECOND_NONE;
+  if (learned && (!c->cnn || !rst::cnn::engine_has_weights(c->cnn)))
+    return fail(c, RST_ESTATE, "the learned preconditioner has no network weights");
+  const int m = c->opts.restart;
+  const int P = c->na * c->nb;
+  const long long n = (long long)P * c->nz;
+  const int ncols = (int)cols.size();
+  // launch shape shared by the apply and preconditioner kernels
+  LaunchShape ls;
+  int cw_req = c->opts.col_block > 0 ? c->opts.col_block : std::min(rst::CW_MAX, 8);
+  while (cw_req > 1 && (long long)P * cw_req > 2LL * rst::MAX_T) cw_req /= 2;
+  rst_status s = choose_shape(c, cw_req, c->opts.threads, ls);
+  if (s != RST_OK) return s;
+  const int cw = ls.cw;
+  c->last_cw = cw;
+  c->last_threads = ls.threads;
+  void* kapply = pick_kernel(c->rad, ls.q, 1);
+  void* kpc = pick_kernel(c->rad, ls.q, 7);
+  if (!kapply || !kpc) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
+  // chunk of columns: bounded by a quarter of free memory
+  const size_t per_col = (size_t)(2 * m + 6) * n * 16 + (size_t)(learned ? 11 * 64 + 24 : 0) * n;
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
+  long long chunk = std::min<long long>(512, std::max<long long>(cw, (long long)(free_b / 4 / per_col)));
+  chunk = std::max<long long>(cw, chunk / cw * cw);
+  chunk = std::min<long long>(chunk, ((long long)ncols + cw - 1) / cw * cw);
+  const int ncolp = (int)chunk;
+  const int nblk = ncolp / cw;
+  const size_t vlen = (size_t)nblk * n * cw;  // elements of one chunk vector
+  rst_status e;
+  if ((e = ensure(c, c->d_fgV, (size_t)(m + 1) * vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgZ, (size_t)m * vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgX, vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgW, vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgM, vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgwb, vlen * 16)) != RST_OK) return e;
+  if (learned) {
+    if ((e = ensure(c, c->d_fgx0, (size_t)ncolp * n * 16)) != RST_OK) return e;
+    if ((e = ensure(c, c->d_fgf, (size_t)ncolp * n * 8)) != RST_OK) return e;
+  }
+  const size_t m1 = (size_t)m + 1;
+  if ((e = ensure(c, c->d_fgH, (size_t)ncolp * m1 * m * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgcs, (size_t)ncolp * m * 8)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgsn, (size_t)ncolp * m * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgg, (size_t)ncolp * m1 * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fginv, (size_t)ncolp * 8)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgest, (size_t)ncolp * 8)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgact, (size_t)ncolp * 4)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgit, (size_t)ncolp * 4)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fguse, (size_t)ncolp * 4)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgh1, m1 * ncolp * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgh2, m1 * ncolp * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgn2, (size_t)ncolp * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgy, (size_t)m * ncolp * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgsrc, (size_t)ncolp * 8)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgbsc, (size_t)ncolp * 8)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgt, (size_t)ncolp * 8)) != RST_OK) return e;
+  // kernel arguments: apply slots j < m (Z_j -> W) and m (X -> W); preconditioner slots j <= m (V_j -> M or Z_j)
+  rst::Geo g = make_geo(c);
+  rst::Proj pj = make_proj(c);
+  const size_t pws_stride = std::max<size_t>(1, (size_t)c->nproj * cw);
+  if ((e = ensure(c, c->d_pws, (size_t)nblk * pws_stride * 16)) != RST_OK) return e;
+  const size_t lds_apply =
+      rst::lds_bytes<double>(g.pa, g.pb, g.P, pj.nproj, pj.max_chunks, pj.nm, cw, ls.threads);
+  size_t lds_pc = rst::lds_bytes<double>(g.pa, g.pb, g.P, 0, 0, pj.nm, cw, ls.threads);
+  const size_t pc_off = (lds_pc + 15) & ~size_t(15);
+  lds_pc = pc_off + (size_t)3 * (c->na + c->nb) * 16;
+  int dev_lds = 0;
+  HIPCHK(c, hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+  if (std::max(lds_apply, lds_pc) + sizeof(rst::ColState) + 1024 > (size_t)dev_lds)
+    return fail(c, RST_EUNSUPPORTED, "LDS requirement exceeds the device limit");
+  if (lds_apply > 64 * 1024)
+    HIPCHK(c, hipFuncSetAttribute(kapply, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_apply));
+  if (lds_pc > 64 * 1024) HIPCHK(c, hipFuncSetAttribute(kpc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_pc));
+  double2* V = (double2*)c->d_fgV.p;
+  double2* Z = (double2*)c->d_fgZ.p;
+  double2* X = (double2*)c->d_fgX.p;
+  double2* W = (double2*)c->d_fgW.p;
+  double2* Mb = (double2*)c->d_fgM.p;
+  rst::fg::Shape S{n, cw, nblk, 0, m};
+  rst::fg::Hess Hs{(double2*)c->d_fgH.p, (double*)c->d_fgcs.p, (double2*)c->d_fgsn.p, (double2*)c->d_fgg.p,
+                   (double*)c->d_fginv.p, (double*)c->d_fgest.p, (const int*)c->d_fgact.p, (int*)c->d_fgit.p};
+  std::vector<double> en(energies, energies + ne);
+  if ((e = upload(c, c->d_en, en)) != RST_OK) return e;
+  double vbar = 0;
+  for (double x : c->v) vbar += x;
+  vbar /= (double)c->v.size();
+  if (usepc && (e = ensure(c, c->d_pc_inv, (size_t)n * 16)) != RST_OK) return e;
+  const size_t nout = (size_t)ne * ncols;
+  Tcol.assign(nout, 0.0);
+  its.assign(nout, 0);
+  rss.assign(nout, 0);
+  res.assign(nout, 0.0);
+  st.assign(nout, 1);
+  c->last_fallbacks = 0;
+  c->last_cnn_flop = 0.0;
+  c->last_updates.clear();
+  double bytes = 0.0;
+  const double cnn_flop_col = [&]() {
+    // 2 * 27 * cin * cout flops per point and layer, at the level of the layer
+    const double n0 = (double)n;
+    const double n1 = (double)((c->nz + 1) / 2) * ((c->nb + 1) / 2) * ((c->na + 1) / 2);
+    const double n2 = (double)((c->nz + 3) / 4) * ((c->nb + 3) / 4) * ((c->na + 3) / 4);
+    const double k16 = 2.0 * 27 * 16 * 16;
+    return n0 * (2.0 * 27 * 4 * 16 + k16 + k16 + 2.0 * 27 * 16 * 2) + n1 * 3 * k16 + n2 * 2 * k16;
+  }();
+  const unsigned gv = (unsigned)((vlen + 255) / 256);
+  const unsigned gc = (unsigned)((ncolp + 63) / 64);
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  const int max_cycles = std::max(1, (c->opts.max_iter + m - 1) / m);
+  for (int ie = 0; ie < ne; ++ie) {
+    const double energy = energies[ie];
+    // kernel arguments of this energy
+    std::vector<rst::ApplyArgs> aa(m + 1);
+    for (int j = 0; j <= m; ++j) {
+      rst::ApplyArgs& A = aa[j];
+      std::memset(&A, 0, sizeof(A));
+      A.g = g;
+      A.pj = pj;
+      A.V = (const double*)c->d_v.p;
+      A.gz = (const double*)c->d_gz.p;
+      A.energy = energy;
+      A.x = j < m ? Z + (size_t)j * vlen : X;
+      A.y = W;
+      A.ncol = ncolp;
+      A.cw = cw;
+      A.nblk = nblk;
+      A.pws = (double2*)c->d_pws.p;
+      A.pws_stride = pws_stride;
+      A.blocked = 1;
+    }
+    if ((e = upload(c, c->d_fgaa, aa)) != RST_OK) return e;
+    if (usepc) {
+      // Thomas pivots of this energy
+      rst::SolveArgs A;
+      std::memset(&A, 0, sizeof(A));
+      A.g = g;
+      A.gz = (const double*)c->d_gz.p;
+      A.energies = (const double*)c->d_en.p + ie;
+      A.ne = 1;
+      A.pc.vbar = vbar;
+      A.pc.a = 0.5 / (c->hz * c->hz);
+      A.pc.eps = (const double*)c->d_pc_eps.p;
+      A.pc.steps = (const double2*)c->d_pc_twa.p;
+      A.pc.inv = (const double2*)c->d_pc_inv.p;
+      std::vector<rst::SolveArgs> sa(1, A);
+      if ((e = upload(c, c->d_fgsa, sa)) != RST_OK) return e;
+      hipLaunchKernelGGL(rst::k_pc_pivots, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c->stream,
+                         (const rst::SolveArgs*)c->d_fgsa.p);
+      HIPCHK(c, hipGetLastError());
+      std::vector<rst::PcApplyArgs> pa(m + 1);
+      for (int j = 0; j <= m; ++j) {
+        rst::PcApplyArgs& B = pa[j];
+        std::memset(&B, 0, sizeof(B));
+        B.g = g;
+        B.pc = A.pc;
+        B.in = V + (size_t)j * vlen;
+        B.out = (learned || j == m) ? Mb : Z + (size_t)j * vlen;
+        B.wbuf = (double2*)c->d_fgwb.p;
+        B.cw = cw;
+        B.nblk = nblk;
+        B.pc_lds_off = pc_off;
+      }
+      if ((e = upload(c, c->d_fgpa, pa)) != RST_OK) return e;
+    }
+    for (int c0 = 0; c0 < ncols; c0 += ncolp) {
+      const int nc = std::min(ncolp, ncols - c0);
+      S.ncol = nc;
+      std::vector<long long> src(ncolp, -1);
+      std::vector<double> bsc(ncolp, 0.0), bnorm(ncolp, 0.0), prev(ncolp, 1.0);
+      std::vector<int> act(ncolp, 0), use(ncolp, 0), cyc(ncolp, 0), fb(ncolp, 0);
+      for (int j = 0; j < nc; ++j) {
+        src[j] = cols[c0 + j];
+        const double gs = hsrc ? (*hsrc)[cols[c0 + j] / P] : 1.0;
+        bsc[j] = std::sqrt(gs);
+        bnorm[j] = bsc[j];
+        act[j] = 1;
+        use[j] = learned ? 1 : 0;
+      }
+      std::vector<int> zero(ncolp, 0);
+      if ((e = upload(c, c->d_fgsrc, src)) != RST_OK) return e;
+      if ((e = upload(c, c->d_fgbsc, bsc)) != RST_OK) return e;
+      if ((e = upload(c, c->d_fgact, act)) != RST_OK) return e;
+      if ((e = upload(c, c->d_fguse, use)) != RST_OK) return e;
+      if ((e = upload(c, c->d_fgit, zero)) != RST_OK) return e;
+      hipLaunchKernelGGL(rst::fg::k_fg_init, dim3(gv), dim3(256), 0, c->stream, S, (const long long*)c->d_fgsrc.p,
+                         (const double*)c->d_fgbsc.p, X, W);
+      HIPCHK(c, hipGetLastError());
+      std::vector<double2> n2(ncolp);
+      std::vector<double> est(ncolp);
+      for (int cy = 0; cy < max_cycles; ++cy) {
+        // start: V0 = R / ||R|| (R is in W)
+        hipLaunchKernelGGL(rst::fg::k_fg_dots, dim3(nblk, 1), dim3(256), 0, c->stream, S, (const double2*)W,
+                           (long long)vlen, 1, (const double2*)W, (double2*)c->d_fgn2.p, ncolp);
+        hipLaunchKernelGGL(rst::fg::k_fg_start, dim3(gc), dim3(64), 0, c->stream, S, (const double2*)c->d_fgn2.p,
+                           Hs, ncolp);
+        hipLaunchKernelGGL(rst::fg::k_fg_scale, dim3(gv), dim3(256), 0, c->stream, S, V, (const double2*)W,
+                           (const double*)c->d_fginv.p);
+        HIPCHK(c, hipGetLastError());
+        int k = 0;
+        int nact = 0;
+        for (int j = 0; j < nc; ++j) nact += act[j];
+        for (int j = 0; j < m; ++j) {
+          double2* Vj = V + (size_t)j * vlen;
+          double2* Zj = Z + (size_t)j * vlen;
+          // Z_j = precondition(V_j)
+          if (usepc) {
+            void* pargs = (char*)c->d_fgpa.p + (size_t)j * sizeof(rst::PcApplyArgs);
+            void* args[] = {&pargs};
+            HIPCHK(c, hipLaunchKernel(kpc, dim3(nblk), dim3(ls.threads), args, lds_pc, c->stream));
+            bytes += (double)nact * n * 16.0 * 4;
+            if (learned) {
+              const long long tot = (long long)nc * n;
+              hipLaunchKernelGGL(rst::fg::k_fg_features, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                                 c->stream, S, (const double2*)Vj, (const double2*)Mb, (float*)c->d_fgx0.p);
+              HIPCHK(c, hipGetLastError());
+              hipError_t he = rst::cnn::engine_forward(c->cnn, (const float*)c->d_fgx0.p, (float*)c->d_fgf.p, nc,
+                                                       c->nz, c->nb, c->na, false);
+              if (he != hipSuccess) return fail(c, RST_EDEVICE, std::string("network: ") + hipGetErrorString(he));
+              hipLaunchKernelGGL(rst::fg::k_fg_combine, dim3(gv), dim3(256), 0, c->stream, S, (const double2*)Mb,
+                                 (const float*)c->d_fgf.p, (const int*)c->d_fguse.p, Zj);
+              HIPCHK(c, hipGetLastError());
+              c->last_cnn_flop += cnn_flop_col * nc;
+            }
+          } else {
+            HIPCHK(c, hipMemcpyAsync(Zj, Vj, vlen * 16, hipMemcpyDeviceToDevice, c->stream));
+          }
+          // W = A Z_j
+          {
+            void* aargs = (char*)c->d_fgaa.p + (size_t)j * sizeof(rst::ApplyArgs);
+            void* args[] = {&aargs};
+            HIPCHK(c, hipLaunchKernel(kapply, dim3(nblk), dim3(ls.threads), args, lds_apply, c->stream));
+          }
+          // CGS2 against V_0..V_j, then ||W||, the Hessenberg column and V_{j+1}
+          double2* h1 = (double2*)c->d_fgh1.p;
+          double2* h2 = (double2*)c->d_fgh2.p;
+          hipLaunchKernelGGL(rst::fg::k_fg_dots, dim3(nblk, j + 1), dim3(256), 0, c->stream, S, (const double2*)V,
+                             (long long)vlen, j + 1, (const double2*)W, h1, ncolp);
+          hipLaunchKernelGGL(rst::fg::k_fg_update, dim3(gv), dim3(256), 0, c->stream, S, W, (const double2*)V,
+                             (long long)vlen, j + 1, (const double2*)h1, ncolp, -1.0);
+          hipLaunchKernelGGL(rst::fg::k_fg_dots, dim3(nblk, j + 1), dim3(256), 0, c->stream, S, (const double2*)V,
+                             (long long)vlen, j + 1, (const double2*)W, h2, ncolp);
+          hipLaunchKernelGGL(rst::fg::k_fg_update, dim3(gv), dim3(256), 0, c->stream, S, W, (const double2*)V,
+                             (long long)vlen, j + 1, (const double2*)h2, ncolp, -1.0);
+          hipLaunchKernelGGL(rst::fg::k_fg_dots, dim3(nblk, 1), dim3(256), 0, c->stream, S, (const double2*)W,
+                             (long long)vlen, 1, (const double2*)W, (double2*)c->d_fgn2.p, ncolp);
+          hipLaunchKernelGGL(rst::fg::k_fg_arnoldi, dim3(gc), dim3(64), 0, c->stream, S, j, (const double2*)h1,
+                             (const double2*)h2, (const double2*)c->d_fgn2.p, Hs, ncolp);
+          hipLaunchKernelGGL(rst::fg::k_fg_scale, dim3(gv), dim3(256), 0, c->stream, S, V + (size_t)(j + 1) * vlen,
+                             (const double2*)W, (const double*)c->d_fginv.p);
+          HIPCHK(c, hipGetLastError());
+          bytes += (double)nact * n * 16.0 * (4.0 * (j + 1) + 10.0);
+          k = j + 1;
+          HIPCHK(c, hipMemcpyAsync(est.data(), c->d_fgest.p, (size_t)ncolp * 8, hipMemcpyDeviceToHost, c->stream));
+          HIPCHK(c, hipStreamSynchronize(c->stream));
+          bool all = true;
+          for (int q = 0; q < nc; ++q)
+            if (act[q] && !(est[q] <= 0.5 * c->opts.tol * bnorm[q])) all = false;
+          if (all) break;
+        }
+        // X += sum_{i<k} Z_i y_i
+        hipLaunchKernelGGL(rst::fg::k_fg_trisolve, dim3(gc), dim3(64), 0, c->stream, S, k, Hs, (double2*)c->d_fgy.p,
+                           ncolp);
+        hipLaunchKernelGGL(rst::fg::k_fg_update, dim3(gv), dim3(256), 0, c->stream, S, X, (const double2*)Z,
+                           (long long)vlen, k, (const double2*)c->d_fgy.p, ncolp, 1.0);
+        HIPCHK(c, hipGetLastError());
+        // true residual R = b - A X (into W)
+        {
+          void* aargs = (char*)c->d_fgaa.p + (size_t)m * sizeof(rst::ApplyArgs);
+          void* args[] = {&aargs};
+          HIPCHK(c, hipLaunchKernel(kapply, dim3(nblk), dim3(ls.threads), args, lds_apply, c->stream));
+        }
+        hipLaunchKernelGGL(rst::fg::k_fg_resid, dim3(gv), dim3(256), 0, c->stream, S, (const long long*)c->d_fgsrc.p,
+                           (const double*)c->d_fgbsc.p, (const double2*)X, W);
+        hipLaunchKernelGGL(rst::fg::k_fg_dots, dim3(nblk, 1), dim3(256), 0, c->stream, S, (const double2*)W,
+                           (long long)vlen, 1, (const double2*)W, (double2*)c->d_fgn2.p, ncolp);
+        HIPCHK(c, hipGetLastError());
+        bytes += (double)nact * n * 16.0 * (k + 6.0);
+        HIPCHK(c, hipMemcpyAsync(n2.data(), c->d_fgn2.p, (size_t)ncolp * 16, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        bool any = false, use_changed = false;
+        for (int q = 0; q < nc; ++q) {
+          if (!act[q]) continue;
+          cyc[q] += 1;
+          const double rel = std::sqrt(n2[q].x) / bnorm[q];
+          res[(size_t)ie * ncols + c0 + q] = rel;
+          if (!std::isfinite(rel)) {
+            act[q] = 0;
+            st[(size_t)ie * ncols + c0 + q] = 2;
+          } else if (rel <= c->opts.tol) {
+            act[q] = 0;
+            st[(size_t)ie * ncols + c0 + q] = 0;
+          } else {
+            if (use[q] && rel > c->opts.fallback_ratio * prev[q]) {
+              use[q] = 0;
+              fb[q] = 1;
+              use_changed = true;
+            }
+            any = true;
+          }
+          prev[q] = rel;
+        }
+        if (!any) break;
+        if ((e = upload(c, c->d_fgact, act)) != RST_OK) return e;
+        if (use_changed && (e = upload(c, c->d_fguse, use)) != RST_OK) return e;
+      }
+      // T accumulation, per-column results, optional export of x
+      if (d_gdst) {
+        hipLaunchKernelGGL(rst::fg::k_fg_tacc, dim3(nblk), dim3(256), 0, c->stream, S, (const double2*)X, d_gdst,
+                           (long long)P, (double*)c->d_fgt.p);
+        HIPCHK(c, hipGetLastError());
+        std::vector<double> ta(ncolp);
+        HIPCHK(c, hipMemcpyAsync(ta.data(), c->d_fgt.p, (size_t)ncolp * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int q = 0; q < nc; ++q) Tcol[(size_t)ie * ncols + c0 + q] = 4.0 * ta[q];
+      }
+      std::vector<int> itv(ncolp);
+      HIPCHK(c, hipMemcpyAsync(itv.data(), c->d_fgit.p, (size_t)ncolp * 4, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      for (int q = 0; q < nc; ++q) {
+        its[(size_t)ie * ncols + c0 + q] = itv[q];
+        rss[(size_t)ie * ncols + c0 + q] = cyc[q];
+        c->last_fallbacks += fb[q];
+        if (st[(size_t)ie * ncols + c0 + q] != 0 && st[(size_t)ie * ncols + c0 + q] != 2)
+          st[(size_t)ie * ncols + c0 + q] = 1;
+      }
+      if (xout) {
+        // x (n x ncols, column fastest) from the blocked X (a test-sized export through the host)
+        std::vector<double2> hx(vlen), rows((size_t)n * nc);
+        HIPCHK(c, hipMemcpyAsync(hx.data(), X, vlen * 16, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int q = 0; q < nc; ++q)
+          for (long long p = 0; p < n; ++p) rows[(size_t)p * nc + q] = hx[((size_t)(q / cw) * n + p) * cw + q % cw];
+        HIPCHK(c, hipMemcpy2D(xout + c0, (size_t)ncols * 16, rows.data(), (size_t)nc * 16, (size_t)nc * 16, (size_t)n,
+                              hipMemcpyHostToDevice));
+      }
+    }
+  }
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float fms = 0;
+  HIPCHK(c, hipEventElapsedTime(&fms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  ms = fms;
+  c->last_fg_bytes = bytes;
+  return RST_OK;
 }
 
 // Launches the batched solver over the structures `sel` of the batch (all
@@ -723,6 +1114,10 @@ rst_status run_batch(rst_ctx* c, const std::vector<int>& sel, int ne_cap, int cw
     order[i] = (int)i;
   }
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  const bool pc = c->opts.precond == RST_PRECOND_FREE_CAP;
+  std::vector<double> pc_eps;
+  std::vector<double2> pc_steps;
+  long long inv_total = 0;
   std::vector<rst::BatchProb> bp(sel.size());
   std::vector<double> v, gz, gl, gr, en;
   std::vector<int64_t> cols;
@@ -751,6 +1146,20 @@ rst_status run_batch(rst_ctx* c, const std::vector<int>& sel, int ne_cap, int cw
     b.pha_y = std::sin(hp.ka * la);
     b.phb_x = std::cos(hp.kb * lb);
     b.phb_y = std::sin(hp.kb * lb);
+    if (pc) {
+      std::vector<double> eps;
+      std::vector<double2> steps;
+      pc_tables(c, hp.ka, hp.kb, eps, steps);
+      b.eps_off = (long long)pc_eps.size();
+      b.steps_off = (long long)pc_steps.size();
+      b.inv_off = inv_total;
+      double vb = 0;
+      for (double x : hp.v) vb += x;
+      b.vbar = vb / (double)hp.v.size();
+      pc_eps.insert(pc_eps.end(), eps.begin(), eps.end());
+      pc_steps.insert(pc_steps.end(), steps.begin(), steps.end());
+      inv_total += (long long)ne * hp.nz * P;
+    }
     items += ncols > 0 ? (long long)b.nblk * ne : 0;
     outs += (long long)ne * ncols;
     out_off[oi] = b.out_off;
@@ -779,19 +1188,21 @@ rst_status run_batch(rst_ctx* c, const std::vector<int>& sel, int ne_cap, int cw
   if ((s = upload(c, c->d_bgr, gr)) != RST_OK) return s;
   if ((s = upload(c, c->d_ben, en)) != RST_OK) return s;
   if ((s = upload(c, c->d_bcols, cols)) != RST_OK) return s;
-  void* kern = pick_kernel(c->rad, ls.q, 0);
+  void* kern = pick_kernel(c->rad, ls.q, pc ? 6 : 5);
   if (!kern) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
   rst::Geo g = make_geo(c);
   g.nz = nz_max;
   rst::Proj pj = make_proj(c);
   pj.nproj = 0;
-  const size_t lds = rst::lds_bytes<double>(g.pa, g.pb, g.P, 0, 0, pj.nm, ls.cw, ls.threads);
+  size_t lds = rst::lds_bytes<double>(g.pa, g.pb, g.P, 0, 0, pj.nm, ls.cw, ls.threads);
+  const size_t pc_off = (lds + 15) & ~size_t(15);
+  if (pc) lds = pc_off + (size_t)3 * (c->na + c->nb) * 16;
   int per_cu = 0, ncu = 0;
   HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, ls.threads, lds));
   HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
   if (per_cu < 1) return fail(c, RST_EUNSUPPORTED, "kernel does not fit on a compute unit");
   const size_t n_max = (size_t)P * nz_max;
-  const size_t ws_stride = 5 * n_max * ls.cw;
+  const size_t ws_stride = (pc ? 9 : 5) * n_max * ls.cw;
   size_t free_b = 0, total_b = 0;
   HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
   long long nwg = std::min<long long>(items, (long long)per_cu * ncu);
@@ -830,6 +1241,39 @@ rst_status run_batch(rst_ctx* c, const std::vector<int>& sel, int ne_cap, int cw
   A.resid = (double*)c->d_res.p;
   A.status = (int*)c->d_st.p;
   A.counter = (int*)c->d_counter.p;
+  A.pc_lds_off = pc_off;
+  if (pc) {
+    if ((s = upload(c, c->d_bpc_eps, pc_eps)) != RST_OK) return s;
+    if ((s = upload(c, c->d_bpc_steps, pc_steps)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_pc_inv, (size_t)inv_total * 16)) != RST_OK) return s;
+    A.pc.a = 0.5 / (c->hz * c->hz);
+    A.pc.eps = (const double*)c->d_bpc_eps.p;
+    A.pc.steps = (const double2*)c->d_bpc_steps.p;
+    A.pc.inv = (const double2*)c->d_pc_inv.p;
+    // Thomas pivots of every (structure, energy): one pivot launch per structure
+    std::vector<rst::SolveArgs> pargs(bsorted.size(), A);
+    for (size_t i = 0; i < bsorted.size(); ++i) {
+      const rst::BatchProb& b = bsorted[i];
+      rst::SolveArgs& q = pargs[i];
+      q.batch = nullptr;
+      q.nprob = 0;
+      q.g.nz = b.nz;
+      q.ne = b.ne;
+      q.energies = A.energies + b.e_off;
+      q.gz = A.gz + b.gz_off;
+      q.pc.vbar = b.vbar;
+      q.pc.eps = A.pc.eps + b.eps_off;
+      q.pc.inv = A.pc.inv + b.inv_off;
+    }
+    if ((s = upload(c, c->d_bpargs, pargs)) != RST_OK) return s;
+    for (size_t i = 0; i < bsorted.size(); ++i) {
+      const long long nt = (long long)bsorted[i].ne * P;
+      if (nt == 0) continue;
+      hipLaunchKernelGGL(rst::k_pc_pivots, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
+                         (const rst::SolveArgs*)c->d_bpargs.p + i);
+    }
+    HIPCHK(c, hipGetLastError());
+  }
   if ((s = ensure(c, c->d_args, sizeof(A))) != RST_OK) return s;
   c->h_solve = A;
   HIPCHK(c, hipMemcpyAsync(c->d_args.p, &c->h_solve, sizeof(A), hipMemcpyHostToDevice, c->stream));
@@ -840,7 +1284,7 @@ rst_status run_batch(rst_ctx* c, const std::vector<int>& sel, int ne_cap, int cw
   HIPCHK(c, hipEventCreate(&e1));
   // graph key: batch contents, launch shape and buffers
   const long long key = ((long long)c->batch_version << 32) ^ ((long long)ls.cw << 24) ^ (nwg << 1) ^
-                        (long long)(uintptr_t)c->d_ws.p ^ (long long)lds;
+                        (long long)(uintptr_t)c->d_ws.p ^ (long long)lds ^ ((long long)pc << 20);
   if (use_graph && (c->gexec == nullptr || c->gexec_key != key)) {
     if (c->gexec) {
       HIPCHK(c, hipGraphExecDestroy(c->gexec));
@@ -939,8 +1383,8 @@ rst_status rst_batch_run(rst_ctx* c, double* T_out, rst_stats* stats) {
   if (!c) return RST_EINVAL;
   if (!c->has_grid) return fail(c, RST_ESTATE, "rst_set_grid not called");
   if (c->rad != 2 && c->rad != 6) return fail(c, RST_EUNSUPPORTED, "GPU kernels are built for FD orders 4 and 12");
-  if (c->opts.precision != RST_FP64 || c->opts.precond != RST_PRECOND_NONE)
-    return fail(c, RST_EUNSUPPORTED, "the batched launch runs FP64 BiCGSTAB without preconditioner");
+  if (c->opts.precision != RST_FP64 || c->opts.method != RST_BICGSTAB)
+    return fail(c, RST_EUNSUPPORTED, "the batched launch runs FP64 BiCGSTAB");
   if (c->batch.empty()) return RST_OK;
   if (!T_out) return fail(c, RST_EINVAL, "null T_out");
   hipSetDevice(c->device);
@@ -951,7 +1395,7 @@ rst_status rst_batch_run(rst_ctx* c, double* T_out, rst_stats* stats) {
   if (cw == 0) {
     // autotune: time every candidate on the costliest structure (2 energies)
     const long long key = ((long long)c->na << 40) ^ ((long long)c->nb << 24) ^ ((long long)c->rad << 8) ^
-                          c->opts.direction;
+                          ((long long)c->opts.precond << 4) ^ c->opts.direction;
     auto it = c->tuned_cw.find(key);
     if (it != c->tuned_cw.end()) {
       cw = it->second;
@@ -983,7 +1427,8 @@ rst_status rst_batch_run(rst_ctx* c, double* T_out, rst_stats* stats) {
     for (double t : o.T[i]) T_out[k++] = t;
   int nbad = 0;
   fill_stats(c, stats, o.its, o.rss, o.res, o.stv, o.ms, nbad, o.cw, o.threads, 0.0);
-  if (stats) stats->bytes_algorithmic = o.points_n * 12.0 * 16.0;
+  if (stats)
+    stats->bytes_algorithmic = o.points_n * (c->opts.precond == RST_PRECOND_FREE_CAP ? 24.0 : 12.0) * 16.0;
   return nbad ? RST_ENOCONV : RST_OK;
 }
 
@@ -997,8 +1442,9 @@ void rst_default_solver(rst_solver_opts* o) {
   o->col_block = 0;
   o->threads = 0;
   o->direction = RST_DIR_LR;
-  o->inner_tol = 1e-4;
-  o->max_outer = 30;
+  o->update_delta = 0.1;
+  o->restart = 30;
+  o->fallback_ratio = 0.5;
   o->precond = RST_PRECOND_NONE;
 }
 
@@ -1029,6 +1475,7 @@ void rst_destroy(rst_ctx* c) {
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
   if (c->gexec) hipGraphExecDestroy(c->gexec);
+  rst::cnn::engine_destroy(c->cnn);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1156,17 +1603,26 @@ rst_status rst_set_k(rst_ctx* c, double ka, double kb) {
 
 rst_status rst_set_solver(rst_ctx* c, const rst_solver_opts* o) {
   if (!c || !o) return RST_EINVAL;
-  if (o->method != RST_BICGSTAB) return fail(c, RST_EINVAL, "unknown method");
+  if (o->method != RST_BICGSTAB && o->method != RST_FGMRES) return fail(c, RST_EINVAL, "unknown method");
+  if (o->method == RST_FGMRES) {
+    if (o->restart < 1 || o->restart > 200) return fail(c, RST_EINVAL, "restart must be in 1..200");
+    if (o->precision != RST_FP64) return fail(c, RST_EUNSUPPORTED, "FGMRES runs in FP64 only");
+  }
+  if (o->precond == RST_PRECOND_LEARNED) {
+    if (o->method != RST_FGMRES)
+      return fail(c, RST_EINVAL, "the learned preconditioner needs method RST_FGMRES");
+    if (!(o->fallback_ratio > 0) || o->fallback_ratio > 1) return fail(c, RST_EINVAL, "fallback_ratio must be in (0, 1]");
+  }
   if (o->precision != RST_FP64 && o->precision != RST_FP32_REFINE) return fail(c, RST_EINVAL, "unknown precision");
-  if (o->precision == RST_FP32_REFINE && (!(o->inner_tol > 0) || o->inner_tol >= 1 || o->max_outer < 1))
-    return fail(c, RST_EINVAL, "inner_tol must be in (0, 1) and max_outer >= 1");
+  if (o->precision == RST_FP32_REFINE && (!(o->update_delta > 0) || o->update_delta >= 1))
+    return fail(c, RST_EINVAL, "update_delta must be in (0, 1)");
   if (!(o->tol > 0) || o->max_iter < 1) return fail(c, RST_EINVAL, "tol must be > 0 and max_iter >= 1");
   if (o->col_block < 0 || o->col_block > rst::CW_MAX || (o->col_block & (o->col_block - 1)))
     return fail(c, RST_EINVAL, "col_block must be 0 or a power of two <= 8");
   if (o->threads < 0 || o->threads > rst::MAX_T || o->threads % 64)
     return fail(c, RST_EINVAL, "threads must be 0 or a multiple of 64 <= 512");
   if (o->direction != RST_DIR_LR && o->direction != RST_DIR_RL) return fail(c, RST_EINVAL, "bad direction");
-  if (o->precond != RST_PRECOND_NONE && o->precond != RST_PRECOND_FREE_CAP)
+  if (o->precond != RST_PRECOND_NONE && o->precond != RST_PRECOND_FREE_CAP && o->precond != RST_PRECOND_LEARNED)
     return fail(c, RST_EINVAL, "unknown preconditioner");
   c->opts = *o;
   return RST_OK;
@@ -1277,6 +1733,278 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
   void* args[] = {&dargs};
   HIPCHK(c, hipLaunchKernel(kern, dim3(A.nblk), dim3(ls.threads), args, lds, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RST_OK;
+}
+
+}  // extern "C"
+
+// learned correction network ---------------------------------------------------
+
+static rst_status cnn_engine(rst_ctx* c, bool need_weights) {
+  if (!c->cnn) c->cnn = rst::cnn::engine_create(c->stream);
+  if (need_weights && !rst::cnn::engine_has_weights(c->cnn))
+    return fail(c, RST_ESTATE, "the network has no weights (rst_cnn_seed or rst_cnn_set_weights)");
+  return RST_OK;
+}
+
+#define CNN_HIP(c, x)                                                             \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess) {                                                       \
+      if (e_ == hipErrorOutOfMemory) return fail(c, RST_ENOMEM, "network buffers"); \
+      return fail(c, RST_EDEVICE, std::string("network: ") + hipGetErrorString(e_)); \
+    }                                                                             \
+  } while (0)
+
+static rst_status cnn_shape(rst_ctx* c, int ncol, int nz, int nb, int na) {
+  if (ncol < 1 || nz < 1 || nb < 1 || na < 1 || (long long)ncol * nz * nb * na > (1LL << 31))
+    return fail(c, RST_EINVAL, "network shape must be positive and ncol*nz*nb*na <= 2^31");
+  return RST_OK;
+}
+
+extern "C" {
+
+int64_t rst_cnn_weight_count(void) { return (int64_t)rst::cnn::natural_count(); }
+
+rst_status rst_cnn_seed(rst_ctx* c, uint64_t seed) {
+  if (!c) return RST_EINVAL;
+  hipSetDevice(c->device);
+  rst_status s = cnn_engine(c, false);
+  if (s != RST_OK) return s;
+  CNN_HIP(c, rst::cnn::engine_seed(c->cnn, seed));
+  return RST_OK;
+}
+
+rst_status rst_cnn_set_weights(rst_ctx* c, const float* w, int64_t count) {
+  if (!c || !w) return RST_EINVAL;
+  if (count != rst_cnn_weight_count()) return fail(c, RST_EINVAL, "weight count mismatch");
+  for (int64_t i = 0; i < count; ++i)
+    if (!std::isfinite(w[i])) return fail(c, RST_EINVAL, "non-finite weight");
+  hipSetDevice(c->device);
+  rst_status s = cnn_engine(c, false);
+  if (s != RST_OK) return s;
+  CNN_HIP(c, rst::cnn::engine_set_weights(c->cnn, w));
+  return RST_OK;
+}
+
+rst_status rst_cnn_get_weights(rst_ctx* c, float* w, int64_t count) {
+  if (!c || !w) return RST_EINVAL;
+  if (count != rst_cnn_weight_count()) return fail(c, RST_EINVAL, "weight count mismatch");
+  hipSetDevice(c->device);
+  rst_status s = cnn_engine(c, true);
+  if (s != RST_OK) return s;
+  CNN_HIP(c, rst::cnn::engine_get_weights(c->cnn, w));
+  return RST_OK;
+}
+
+rst_status rst_cnn_forward(rst_ctx* c, int ncol, int nz, int nb, int na, const float* x_dev, float* out_dev) {
+  if (!c || !x_dev || !out_dev) return RST_EINVAL;
+  rst_status s = cnn_shape(c, ncol, nz, nb, na);
+  if (s != RST_OK) return s;
+  hipSetDevice(c->device);
+  if ((s = cnn_engine(c, true)) != RST_OK) return s;
+  CNN_HIP(c, rst::cnn::engine_forward(c->cnn, x_dev, out_dev, ncol, nz, nb, na, false));
+  CNN_HIP(c, hipStreamSynchronize(c->stream));
+  return RST_OK;
+}
+
+rst_status rst_cnn_gradient(rst_ctx* c, int ncol, int nz, int nb, int na, const float* x_dev,
+                            const float* gout_dev, float* grad) {
+  if (!c || !x_dev || !gout_dev || !grad) return RST_EINVAL;
+  rst_status s = cnn_shape(c, ncol, nz, nb, na);
+  if (s != RST_OK) return s;
+  hipSetDevice(c->device);
+  if ((s = cnn_engine(c, true)) != RST_OK) return s;
+  CNN_HIP(c, rst::cnn::engine_gradient(c->cnn, x_dev, gout_dev, ncol, nz, nb, na));
+  CNN_HIP(c, rst::cnn::engine_get_grad(c->cnn, grad));
+  return RST_OK;
+}
+
+rst_status rst_cnn_train_step(rst_ctx* c, int ncol, int nz, int nb, int na, const float* x_dev,
+                              const float* target_dev, float lr, double* loss) {
+  if (!c || !x_dev || !target_dev || !loss) return RST_EINVAL;
+  if (!(lr > 0.f)) return fail(c, RST_EINVAL, "lr must be > 0");
+  rst_status s = cnn_shape(c, ncol, nz, nb, na);
+  if (s != RST_OK) return s;
+  hipSetDevice(c->device);
+  if ((s = cnn_engine(c, true)) != RST_OK) return s;
+  CNN_HIP(c, rst::cnn::engine_train_step(c->cnn, x_dev, target_dev, ncol, nz, nb, na, lr, loss));
+  CNN_HIP(c, hipStreamSynchronize(c->stream));
+  return RST_OK;
+}
+
+rst_status rst_precond_train(rst_ctx* c, const rst_train_opts* o, rst_train_stats* ts) {
+  rst_status s = check_ready(c);
+  if (s != RST_OK) return s;
+  if (!o || o->pairs < 1 || o->batch < 1 || o->batch > 64 || !(o->lr > 0.f) || o->n_e < 1 || !o->energies ||
+      o->n_k < 1 || !o->kpts)
+    return fail(c, RST_EINVAL, "bad training options");
+  for (int i = 0; i < o->n_e; ++i)
+    if (!std::isfinite(o->energies[i])) return fail(c, RST_EINVAL, "non-finite energy");
+  for (int i = 0; i < 2 * o->n_k; ++i)
+    if (!std::isfinite(o->kpts[i])) return fail(c, RST_EINVAL, "non-finite k");
+  hipSetDevice(c->device);
+  if ((s = cnn_engine(c, false)) != RST_OK) return s;
+  if (!rst::cnn::engine_has_weights(c->cnn)) CNN_HIP(c, rst::cnn::engine_seed(c->cnn, o->seed));
+  const int P = c->na * c->nb;
+  const long long n = (long long)P * c->nz;
+  LaunchShape ls;
+  int cw_req = std::min(rst::CW_MAX, 8);
+  while (cw_req > 1 && (long long)P * cw_req > 2LL * rst::MAX_T) cw_req /= 2;
+  if ((s = choose_shape(c, cw_req, 0, ls)) != RST_OK) return s;
+  const int cw = ls.cw, B = o->batch;
+  const int ncolp = (B + cw - 1) / cw * cw, nblk = ncolp / cw;
+  const size_t vlen = (size_t)nblk * n * cw;
+  void* kapply = pick_kernel(c->rad, ls.q, 1);
+  void* kpc = pick_kernel(c->rad, ls.q, 7);
+  if (!kapply || !kpc) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
+  if ((s = ensure(c, c->d_fgV, 3 * vlen * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_fgM, vlen * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_fgwb, vlen * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_fgx0, (size_t)B * n * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_fgf, (size_t)B * n * 8)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_fginv, (size_t)ncolp * 8)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_fgn2, (size_t)ncolp * 16)) != RST_OK) return s;
+  double2* Xi = (double2*)c->d_fgV.p;
+  double2* Ev = Xi + vlen;
+  double2* Rv = Ev + vlen;
+  double2* Mv = (double2*)c->d_fgM.p;
+  rst::Proj pj = make_proj(c);
+  const size_t pws_stride = std::max<size_t>(1, (size_t)c->nproj * cw);
+  if ((s = ensure(c, c->d_pws, (size_t)nblk * pws_stride * 16)) != RST_OK) return s;
+  const double ka0 = c->ka, kb0 = c->kb;
+  std::vector<double> en(o->energies, o->energies + o->n_e);
+  if ((s = upload(c, c->d_en, en)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_pc_inv, (size_t)n * 16)) != RST_OK) return s;
+  double vbar = 0;
+  for (double x : c->v) vbar += x;
+  vbar /= (double)c->v.size();
+  std::mt19937_64 gen(o->seed);
+  const int steps = (o->pairs + B - 1) / B;
+  std::vector<double> losses;
+  losses.reserve(steps);
+  rst::fg::Shape S{n, cw, nblk, B, 1};
+  const unsigned gv = (unsigned)((vlen + 255) / 256);
+  const unsigned gf = (unsigned)(((long long)B * n + 255) / 256);
+  int cur_k = -1;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  for (int st = 0; st < steps; ++st) {
+    const int ie = (int)(gen() % (uint64_t)o->n_e);
+    const int ik = (int)(gen() % (uint64_t)o->n_k);
+    if (ik != cur_k) {
+      c->ka = o->kpts[2 * ik];
+      c->kb = o->kpts[2 * ik + 1];
+      if ((s = upload_k(c)) != RST_OK) return s;
+      if ((s = upload_pc(c)) != RST_OK) return s;
+      cur_k = ik;
+    }
+    rst::Geo g = make_geo(c);
+    size_t lds_apply = rst::lds_bytes<double>(g.pa, g.pb, g.P, pj.nproj, pj.max_chunks, pj.nm, cw, ls.threads);
+    size_t lds_pc = rst::lds_bytes<double>(g.pa, g.pb, g.P, 0, 0, pj.nm, cw, ls.threads);
+    const size_t pc_off = (lds_pc + 15) & ~size_t(15);
+    lds_pc = pc_off + (size_t)3 * (c->na + c->nb) * 16;
+    if (lds_apply > 64 * 1024)
+      HIPCHK(c, hipFuncSetAttribute(kapply, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_apply));
+    if (lds_pc > 64 * 1024)
+      HIPCHK(c, hipFuncSetAttribute(kpc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_pc));
+    rst::SolveArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.g = g;
+    A.gz = (const double*)c->d_gz.p;
+    A.energies = (const double*)c->d_en.p + ie;
+    A.ne = 1;
+    A.pc.vbar = vbar;
+    A.pc.a = 0.5 / (c->hz * c->hz);
+    A.pc.eps = (const double*)c->d_pc_eps.p;
+    A.pc.steps = (const double2*)c->d_pc_twa.p;
+    A.pc.inv = (const double2*)c->d_pc_inv.p;
+    std::vector<rst::SolveArgs> sa(1, A);
+    if ((s = upload(c, c->d_fgsa, sa)) != RST_OK) return s;
+    hipLaunchKernelGGL(rst::k_pc_pivots, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c->stream,
+                       (const rst::SolveArgs*)c->d_fgsa.p);
+    std::vector<rst::PcApplyArgs> pa(2);
+    for (int j = 0; j < 2; ++j) {
+      std::memset(&pa[j], 0, sizeof(pa[j]));
+      pa[j].g = g;
+      pa[j].pc = A.pc;
+      pa[j].in = j == 0 ? Xi : Rv;
+      pa[j].out = j == 0 ? Ev : Mv;
+      pa[j].wbuf = (double2*)c->d_fgwb.p;
+      pa[j].cw = cw;
+      pa[j].nblk = nblk;
+      pa[j].pc_lds_off = pc_off;
+    }
+    if ((s = upload(c, c->d_fgpa, pa)) != RST_OK) return s;
+    std::vector<rst::ApplyArgs> aa(1);
+    std::memset(&aa[0], 0, sizeof(aa[0]));
+    aa[0].g = g;
+    aa[0].pj = pj;
+    aa[0].V = (const double*)c->d_v.p;
+    aa[0].gz = (const double*)c->d_gz.p;
+    aa[0].energy = o->energies[ie];
+    aa[0].x = Ev;
+    aa[0].y = Rv;
+    aa[0].ncol = ncolp;
+    aa[0].cw = cw;
+    aa[0].nblk = nblk;
+    aa[0].pws = (double2*)c->d_pws.p;
+    aa[0].pws_stride = pws_stride;
+    aa[0].blocked = 1;
+    if ((s = upload(c, c->d_fgaa, aa)) != RST_OK) return s;
+    // xi -> e = M^-1 xi -> r = A e; scale to ||r|| = 1; m = M^-1 r; (features, target)
+    hipLaunchKernelGGL(rst::fg::k_fg_randn, dim3(gv), dim3(256), 0, c->stream, S,
+                       (unsigned long long)(o->seed * 0x9E3779B97F4A7C15ULL + (uint64_t)st), Xi);
+    void* p0 = c->d_fgpa.p;
+    void* p1 = (char*)c->d_fgpa.p + sizeof(rst::PcApplyArgs);
+    void* a0 = c->d_fgaa.p;
+    void* args0[] = {&p0};
+    HIPCHK(c, hipLaunchKernel(kpc, dim3(nblk), dim3(ls.threads), args0, lds_pc, c->stream));
+    void* argsa[] = {&a0};
+    HIPCHK(c, hipLaunchKernel(kapply, dim3(nblk), dim3(ls.threads), argsa, lds_apply, c->stream));
+    hipLaunchKernelGGL(rst::fg::k_fg_dots, dim3(nblk, 1), dim3(256), 0, c->stream, S, (const double2*)Rv,
+                       (long long)vlen, 1, (const double2*)Rv, (double2*)c->d_fgn2.p, ncolp);
+    hipLaunchKernelGGL(rst::fg::k_fg_rsqrt, dim3((ncolp + 63) / 64), dim3(64), 0, c->stream,
+                       (const double2*)c->d_fgn2.p, (double*)c->d_fginv.p, ncolp);
+    hipLaunchKernelGGL(rst::fg::k_fg_scale, dim3(gv), dim3(256), 0, c->stream, S, Rv, (const double2*)Rv,
+                       (const double*)c->d_fginv.p);
+    void* args1[] = {&p1};
+    HIPCHK(c, hipLaunchKernel(kpc, dim3(nblk), dim3(ls.threads), args1, lds_pc, c->stream));
+    hipLaunchKernelGGL(rst::fg::k_fg_features, dim3(gf), dim3(256), 0, c->stream, S, (const double2*)Rv,
+                       (const double2*)Mv, (float*)c->d_fgx0.p);
+    hipLaunchKernelGGL(rst::fg::k_fg_target, dim3(gf), dim3(256), 0, c->stream, S, (const double2*)Ev,
+                       (const double2*)Mv, (const double*)c->d_fginv.p, (float*)c->d_fgf.p);
+    HIPCHK(c, hipGetLastError());
+    double loss = 0;
+    CNN_HIP(c, rst::cnn::engine_train_step(c->cnn, (const float*)c->d_fgx0.p, (const float*)c->d_fgf.p, B, c->nz,
+                                           c->nb, c->na, o->lr, &loss));
+    losses.push_back(loss);
+  }
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float fms = 0;
+  HIPCHK(c, hipEventElapsedTime(&fms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  // restore the context's k
+  c->ka = ka0;
+  c->kb = kb0;
+  if ((s = upload_k(c)) != RST_OK) return s;
+  if ((s = upload_pc(c)) != RST_OK) return s;
+  if (ts) {
+    const int w = std::max(1, std::min<int>(10, (int)losses.size() / 4));
+    double f = 0, l = 0;
+    for (int i = 0; i < w; ++i) {
+      f += losses[i];
+      l += losses[losses.size() - 1 - i];
+    }
+    ts->steps = steps;
+    ts->loss_first = f / w;
+    ts->loss_last = l / w;
+    ts->ms = fms;
+  }
   return RST_OK;
 }
 

@@ -1,248 +1,34 @@
-// rst_mixed.hpp -- FP32 applies inside an FP64 iterative refinement.
+// rst_mixed.hpp -- BiCGSTAB on FP32 vectors with FP64 reliable updates.
 //
-// Per column: x = 0, r = b; repeat { d ~ A^-1 (r / ||r||) by BiCGSTAB with FP32
-// vectors and FP32 stencil / projector / preconditioner applies (inner
-// products, scalars and projections in FP64), stopped at a loose recursive
-// tolerance; x += ||r|| d in FP64; r = b - A x with an FP64 apply } until the
-// FP64 true residual ||r|| <= tol ||b||.  An inner breakdown just ends that
-// inner solve: the next refinement step restarts from the FP64 residual.
+// The Krylov recurrences (plain or right-preconditioned: the same fused sweeps
+// as the FP64 solvers) run on complex64 vectors with FP32 stencil, projector
+// and preconditioner applies; inner products, scalars and projections stay
+// FP64.  The solution is held as x64 + x32.  Whenever the recursive residual
+// has fallen by the factor delta below the largest one seen since the last
+// replacement (or has reached the tolerance, or the recurrence broke down),
+// x32 is folded into x64 and the recursive residual is replaced by the FP64
+// true residual b - A x64 (reliable updates: Sleijpen and van der Vorst,
+// "Reliable updated residuals in hybrid Bi-CG methods", Computing 56, 1996).
+// The direction p and v = A p are kept, so the Krylov process runs on across
+// replacements; only a breakdown restarts it (p = r, shadow e_j0 moved to
+// argmax |r|).  Convergence is decided on the FP64 true residual alone.  The
+// drift between the recursive and the true residual grows like eps32 times
+// the largest residual since the last replacement, which the replacement rule
+// keeps within eps32 / delta of the current residual.
 #pragma once
 #include "rst_precond.hpp"
 
 namespace rst {
 
-constexpr int STALL_ITERS = 40;  // inner solve stops after this many iterations without progress
-
-// Inner FP32 BiCGSTAB without preconditioner; PA.Pr must hold B^H (rhs).
-template <int RAD, int Q>
-__device__ __forceinline__ void inner_plain(const SolveArgs& A, SweepCtx<float>& C, const Pos<Q>& ps,
-                                            const ProjArrays& PA) {
-  ColState& S = *C.S;
-  const int cw = A.cw;
-  const int tid = threadIdx.x;
-  const int ncw = A.pj.nproj * cw;
-  const double itol2 = A.inner_tol * A.inner_tol;  // the right-hand side has unit norm
-  if (tid < cw) {
-    S.alpha[tid] = S.omega[tid] = S.beta[tid] = mkc(0.0, 0.0);
-    S.ibest[tid] = 1.0;  // the right-hand side has unit norm
-    S.istall[tid] = 0;
-  }
-  for (int w = tid; w < ncw; w += blockDim.x) PA.Pp[w] = PA.Pr[w];
-  set_dco(A.pj, cw, C.L.dco, PA.Pr);
-  __syncthreads();
-  double dots[4] = {0, 0, 0, 0};
-  double rmax = 0;
-  long long ri = 0;
-  C.acc = PA.Pv;
-  sweep<RAD, Q, float>(C, ps, IN_INIT_VEC, OUT_V, dots, rmax, ri);
-  if (tid < cw) S.rho[tid] = S.rj[tid];
-  __syncthreads();
-  for (int it = 0; it < A.inner_max; ++it) {
-    if (tid == 0) S.any_flag = 0;
-    __syncthreads();
-    if (tid < cw) {
-      const int c = tid;
-      S.alpha[c] = mkc(0.0, 0.0);
-      if (S.istate[c] == 0) {
-        const cx<double> vj = S.vj[c];
-        if (!(cnorm2(vj) > 0.0) || !finite2(vj) || !finite2(S.rho[c]) || !(cnorm2(S.rho[c]) > 0.0)) {
-          S.istate[c] = 1;
-        } else {
-          S.alpha[c] = cdiv(S.rho[c], vj);
-          atomicOr(&S.any_flag, 1);
-        }
-      }
-    }
-    __syncthreads();
-    if (!S.any_flag) break;
-    for (int w = tid; w < ncw; w += blockDim.x) {
-      const int c = w % cw;
-      C.L.dco[w] = cscale(PA.Pr[w] - cmul(S.alpha[c], PA.Pv[w]), A.pj.ekb[w / cw]);
-    }
-    __syncthreads();
-    for (int k = 0; k < 4; ++k) dots[k] = 0;
-    C.acc = PA.Pt;
-    sweep<RAD, Q, float>(C, ps, IN_B, OUT_T, dots, rmax, ri);
-    {
-      __shared__ double red_out[4][CW_MAX];
-      col_reduce4(C.L.red, cw, dots, red_out);
-      if (tid < cw) {
-        const int c = tid;
-        const cx<double> ts = mkc(red_out[1][c], red_out[2][c]);
-        const double tt = red_out[3][c];
-        if (S.istate[c] == 0) {
-          const cx<double> om = (tt > 0.0 && isfinite(tt)) ? cscale(ts, 1.0 / tt) : mkc(0.0, 0.0);
-          const cx<double> rn = S.sj[c] - cmul(om, S.tj[c]);
-          if (!(cnorm2(om) > 0.0) || !finite2(om) || !(cnorm2(rn) > 0.0) || !finite2(rn)) {
-            S.istate[c] = 1;
-            S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
-          } else {
-            S.omega[c] = om;
-            S.rho_new[c] = rn;
-            S.beta[c] = cmul(cdiv(rn, S.rho[c]), cdiv(S.alpha[c], om));
-          }
-        } else {
-          S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
-        }
-      }
-      __syncthreads();
-    }
-    for (int w = tid; w < ncw; w += blockDim.x) {
-      const int c = w % cw;
-      const cx<double> al = S.alpha[c], om = S.omega[c], be = S.beta[c];
-      const cx<double> Ps = PA.Pr[w] - cmul(al, PA.Pv[w]);
-      const cx<double> Prn = Ps - cmul(om, PA.Pt[w]);
-      const cx<double> Ppn = Prn + cmul(be, PA.Pp[w] - cmul(om, PA.Pv[w]));
-      PA.Pr[w] = Prn;
-      PA.Pp[w] = Ppn;
-      C.L.dco[w] = cscale(Ppn, A.pj.ekb[w / cw]);
-    }
-    __syncthreads();
-    for (int k = 0; k < 4; ++k) dots[k] = 0;
-    C.acc = PA.Pv;
-    sweep<RAD, Q, float>(C, ps, IN_A, OUT_V, dots, rmax, ri);
-    {
-      __shared__ double red_out[4][CW_MAX];
-      col_reduce4(C.L.red, cw, dots, red_out);
-      if (tid < cw) {
-        const int c = tid;
-        if (S.istate[c] == 0) {
-          S.iters[c] += 1;
-          S.rho[c] = S.rho_new[c];
-          const double rr = red_out[0][c];
-          if (!isfinite(rr) || rr <= itol2) S.istate[c] = 1;
-          // stagnation: no halving of the best residual norm for STALL_ITERS iterations
-          if (rr < 0.25 * S.ibest[c]) {
-            S.ibest[c] = rr;
-            S.istall[c] = 0;
-          } else if (++S.istall[c] >= STALL_ITERS) {
-            S.istate[c] = 1;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Inner FP32 right-preconditioned BiCGSTAB.
-template <int RAD, int Q>
-__device__ __forceinline__ void inner_pc(const SolveArgs& A, SweepCtx<float>& C, const PcVecs<float>& pv,
-                                         const Pos<Q>& ps, const ProjArrays& PA, const PcConst& K,
-                                         const DftSteps& dst_) {
-  ColState& S = *C.S;
-  const int cw = A.cw;
-  const int tid = threadIdx.x;
-  const double itol2 = A.inner_tol * A.inner_tol;
-  if (tid < cw) {
-    S.alpha[tid] = S.omega[tid] = S.beta[tid] = mkc(0.0, 0.0);
-    S.ibest[tid] = 1.0;  // the right-hand side has unit norm
-    S.istall[tid] = 0;
-  }
-  __syncthreads();
-  double dots[4] = {0, 0, 0, 0};
-  pc_forward<Q, float>(C, pv, ps, K, dst_, PC_INIT_VEC, dots);
-  C.acc = PA.Pr;
-  pc_backward<Q, float>(C, pv, ps, K, dst_, pv.ph);
-  set_dco(A.pj, cw, C.L.dco, PA.Pr);
-  __syncthreads();
-  pc_apply<RAD, Q, float, false>(C, pv, ps, dots);
-  if (tid < cw) S.rho[tid] = S.rj[tid];
-  __syncthreads();
-  for (int it = 0; it < A.inner_max; ++it) {
-    if (tid == 0) S.any_flag = 0;
-    __syncthreads();
-    if (tid < cw) {
-      const int c = tid;
-      S.alpha[c] = mkc(0.0, 0.0);
-      if (S.istate[c] == 0) {
-        const cx<double> vj = S.vj[c];
-        if (!(cnorm2(vj) > 0.0) || !finite2(vj) || !finite2(S.rho[c]) || !(cnorm2(S.rho[c]) > 0.0)) {
-          S.istate[c] = 1;
-        } else {
-          S.alpha[c] = cdiv(S.rho[c], vj);
-          atomicOr(&S.any_flag, 1);
-        }
-      }
-    }
-    __syncthreads();
-    if (!S.any_flag) break;
-    for (int k = 0; k < 4; ++k) dots[k] = 0;
-    pc_forward<Q, float>(C, pv, ps, K, dst_, PC_S, dots);
-    C.acc = PA.Pp;
-    pc_backward<Q, float>(C, pv, ps, K, dst_, pv.sh);
-    set_dco(A.pj, cw, C.L.dco, PA.Pp);
-    __syncthreads();
-    for (int k = 0; k < 4; ++k) dots[k] = 0;
-    pc_apply<RAD, Q, float, true>(C, pv, ps, dots);
-    {
-      __shared__ double red_out[4][CW_MAX];
-      col_reduce4(C.L.red, cw, dots, red_out);
-      if (tid < cw) {
-        const int c = tid;
-        const cx<double> ts = mkc(red_out[1][c], red_out[2][c]);
-        const double tt = red_out[3][c];
-        if (S.istate[c] == 0) {
-          const cx<double> om = (tt > 0.0 && isfinite(tt)) ? cscale(ts, 1.0 / tt) : mkc(0.0, 0.0);
-          const cx<double> rn = S.sj[c] - cmul(om, S.tj[c]);
-          if (!(cnorm2(om) > 0.0) || !finite2(om) || !(cnorm2(rn) > 0.0) || !finite2(rn)) {
-            // keep x as it is: the merged update below leaves it unchanged
-            S.istate[c] = 1;
-            S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
-          } else {
-            S.omega[c] = om;
-            S.rho_new[c] = rn;
-            S.beta[c] = cmul(cdiv(rn, S.rho[c]), cdiv(S.alpha[c], om));
-          }
-        } else {
-          S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
-        }
-      }
-      __syncthreads();
-    }
-    for (int k = 0; k < 4; ++k) dots[k] = 0;
-    pc_forward<Q, float>(C, pv, ps, K, dst_, PC_MERGED, dots);
-    C.acc = PA.Pr;
-    pc_backward<Q, float>(C, pv, ps, K, dst_, pv.ph);
-    set_dco(A.pj, cw, C.L.dco, PA.Pr);
-    __syncthreads();
-    double d2[4] = {0, 0, 0, 0};
-    pc_apply<RAD, Q, float, false>(C, pv, ps, d2);
-    {
-      __shared__ double red_out[4][CW_MAX];
-      col_reduce4(C.L.red, cw, dots, red_out);
-      if (tid < cw) {
-        const int c = tid;
-        if (S.istate[c] == 0) {
-          S.iters[c] += 1;
-          S.rho[c] = S.rho_new[c];
-          const double rr = red_out[0][c];
-          if (!isfinite(rr) || rr <= itol2) S.istate[c] = 1;
-          // stagnation: no halving of the best residual norm for STALL_ITERS iterations
-          if (rr < 0.25 * S.ibest[c]) {
-            S.ibest[c] = rr;
-            S.istall[c] = 0;
-          } else if (++S.istall[c] >= STALL_ITERS) {
-            S.istate[c] = 1;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// x64 += uscale * d32 over all planes, with the gathers of the new x64 into
+// x64 += x32 and x32 = 0 over all planes, with the gather of the new x64 into
 // C.acc and the transmission accumulator sum_z gdst(z) |x64|^2.
 template <int Q>
-__device__ __forceinline__ void update_gather_sweep(SweepCtx<double>& C, const Pos<Q>& ps,
-                                                    const cx<float>* d32, const double* gdst,
-                                                    double& tacc) {
+__device__ __forceinline__ void fold_gather_sweep(SweepCtx<double>& C, const Pos<Q>& ps, cx<float>* x32,
+                                                  const double* gdst, double& tacc) {
   const Geo& g = *C.g;
   const Proj& pj = *C.pj;
   const int cw = C.cw;
   const int c = threadIdx.x % cw;
-  const double us = C.S->uscale[c];
   const bool any_g = pj.nproj > 0 && C.acc != nullptr;
   if (any_g) pacc_zero<double>(pj, C.L, cw);
   __syncthreads();
@@ -253,8 +39,9 @@ __device__ __forceinline__ void update_gather_sweep(SweepCtx<double>& C, const P
     for (int k = 0; k < Q; ++k) {
       if (ps.p[k] >= 0) {
         const size_t off = ((size_t)z * g.P + ps.p[k]) * cw + c;
-        const cx<double> xv = ldv(&C.vec.x[off]) + cscale(to64(ldv(&d32[off])), us);
+        const cx<double> xv = ldv(&C.vec.x[off]) + to64(ldv(&x32[off]));
         stv(&C.vec.x[off], xv);
+        stv(&x32[off], mkc<float>(0.0f, 0.0f));
         tacc += gd * cnorm2(xv);
         if (need_g) C.L.outpl[ps.p[k] * cw + c] = xv;
       }
@@ -270,6 +57,110 @@ __device__ __forceinline__ void update_gather_sweep(SweepCtx<double>& C, const P
     pacc_flush<double>(pj, C.L, cw, C.acc);
     __syncthreads();
   }
+}
+
+// One reliable update of the block: fold x32 into x64, r32 = b - A x64
+// (FP64 apply), decide every active column on its FP64 true residual, and
+// restart the Krylov process of the block if `restart` (a breakdown) asks.
+template <int RAD, int Q, bool PC>
+__device__ __forceinline__ void reliable_update(const SolveArgs& A, SweepCtx<double>& C64, SweepCtx<float>& C32,
+                                                const PcVecs<float>& pv, const Pos<Q>& ps,
+                                                const ProjArrays& PA, const DftSteps& dst_, bool final_check,
+                                                bool restart, bool& all_done) {
+  ColState& S = *C64.S;
+  const int cw = A.cw;
+  const int tid = threadIdx.x;
+  // (1) x64 += x32, x32 = 0; B^H x64 -> Px; T accumulator
+  double tacc = 0.0;
+  C64.acc = PA.Px;
+  fold_gather_sweep<Q>(C64, ps, C32.vec.x, A.gdst, tacc);
+  {
+    double v4[4] = {tacc, 0, 0, 0};
+    __shared__ double red_out[4][CW_MAX];
+    col_reduce4(C64.L.red, cw, v4, red_out);
+    if (tid < cw) S.tacc[tid] = red_out[0][tid];
+  }
+  // (2) r32 = b - A x64 (FP64 sweep; the plain recurrences take B^H r into Pr)
+  set_dco(A.pj, cw, C64.L.dco, PA.Px);
+  __syncthreads();
+  double dots[4] = {0, 0, 0, 0};
+  double rmax = -1.0;
+  long long rmax_idx = 0x7fffffffffffffffLL;
+  C64.acc = PC ? nullptr : PA.Pr;
+  C64.r32 = C32.vec.r;
+  sweep<RAD, Q, double>(C64, ps, IN_X, OUT_RES32, dots, rmax, rmax_idx);
+  {
+    __shared__ double red_out[4][CW_MAX];
+    col_reduce4(C64.L.red, cw, dots, red_out);
+    double* bm = C64.L.red;
+    long long* bi = reinterpret_cast<long long*>(C64.L.red + blockDim.x);
+    bm[tid] = rmax;
+    bi[tid] = rmax_idx;
+    __syncthreads();
+    if (tid < cw) {
+      double m = -1.0;
+      long long ix = 0x7fffffffffffffffLL;
+      for (int i = tid; i < (int)blockDim.x; i += cw) {
+        if (bm[i] > m || (bm[i] == m && bi[i] < ix)) {
+          m = bm[i];
+          ix = bi[i];
+        }
+      }
+      S.rr[tid] = red_out[0][tid];
+      S.rmax_idx[tid] = ix;
+    }
+    __syncthreads();
+  }
+  // (3) decide: converged, failed, out of iterations, or go on from the true residual
+  if (tid == 0) S.any_flag = 0;
+  __syncthreads();
+  if (tid < cw) {
+    const int c = tid;
+    if (S.state[c] == 0) {
+      const double rr = S.rr[c];
+      S.updates[c] += 1;
+      if (!isfinite(rr)) {
+        S.state[c] = 2;
+      } else if (rr <= A.tol * A.tol * S.bb[c]) {
+        S.state[c] = 1;
+      } else if (final_check) {
+        S.state[c] = 4;
+      } else {
+        S.maxrr[c] = rr;
+        if (restart) {
+          S.j0[c] = S.rmax_idx[c];
+          S.restarts[c] += 1;
+        } else {
+          S.rho[c] = S.rj[c];  // (r^0, r) of the replaced residual
+        }
+        atomicOr(&S.any_flag, 1);
+      }
+    }
+  }
+  __syncthreads();
+  all_done = (S.any_flag == 0);
+  if (all_done || !restart) return;
+  // (4) restart: p = r, v = A p (with the preconditioner: ph = M^-1 p, v = A ph)
+  const int ncw = A.pj.nproj * cw;
+  double d2[4] = {0, 0, 0, 0};
+  if constexpr (PC) {
+    pc_forward<Q, float>(C32, pv, ps, A.pc, dst_, PC_RESTART, d2);
+    C32.acc = PA.Pr;
+    pc_backward<Q, float>(C32, pv, ps, A.pc, dst_, pv.ph);
+    set_dco(A.pj, cw, C32.L.dco, PA.Pr);
+    __syncthreads();
+    pc_apply<RAD, Q, float, false>(C32, pv, ps, d2);
+  } else {
+    for (int w = tid; w < ncw; w += blockDim.x) PA.Pp[w] = PA.Pr[w];
+    set_dco(A.pj, cw, C32.L.dco, PA.Pr);
+    __syncthreads();
+    C32.acc = PA.Pv;
+    double rm = 0;
+    long long ri = 0;
+    sweep<RAD, Q, float>(C32, ps, IN_RESTART, OUT_V, d2, rm, ri);
+  }
+  if (tid < cw) S.rho[tid] = S.rj[tid];
+  __syncthreads();
 }
 
 template <int RAD, int Q, bool PC>
@@ -290,8 +181,9 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
     S.alpha[c] = S.omega[c] = S.beta[c] = mkc(0.0, 0.0);
     S.iters[c] = 0;
     S.restarts[c] = 0;
-    S.outer[c] = 0;
+    S.updates[c] = 0;
     S.tacc[c] = 0.0;
+    S.rr[c] = 0.0;
     if (col < A.ncols) {
       const long long src = A.cols[col];
       S.src[c] = src;
@@ -299,149 +191,217 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
       const double gs = A.gsrc ? A.gsrc[src / g.P] : 1.0;
       S.bsc[c] = sqrt(gs);
       S.bb[c] = gs;
-      S.rr[c] = gs;
+      S.maxrr[c] = gs;
       S.state[c] = 0;
     } else {
       S.src[c] = -1;
       S.j0[c] = -1;
       S.bsc[c] = 0.0;
       S.bb[c] = 0.0;
-      S.rr[c] = 0.0;
+      S.maxrr[c] = 0.0;
       S.state[c] = 3;
     }
   }
   if constexpr (PC) pv.inv = reinterpret_cast<const cx<double>*>(A.pc.inv) + (size_t)e_idx * g.nz * g.P;
   __syncthreads();
-  // x64 = 0, r64 = b, each element by the thread that owns it in every sweep
-  const size_t nall = (size_t)g.P * g.nz * cw;
+  // x64 = 0, each element by the thread that owns it in every sweep
   {
     const int c = tid % cw;
     for (int z = 0; z < g.nz; ++z) {
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         if (ps.p[k] < 0) continue;
-        const long long gi = (long long)z * g.P + ps.p[k];
-        const size_t off = (size_t)gi * cw + c;
-        stv(&C64.vec.x[off], mkc(0.0, 0.0));
-        stv(&C64.vec.r[off], gi == S.src[c] ? mkc(S.bsc[c], 0.0) : mkc(0.0, 0.0));
+        stv(&C64.vec.x[((size_t)z * g.P + ps.p[k]) * cw + c], mkc(0.0, 0.0));
       }
     }
   }
-  // projections of b into Pt (kept as the FP64 right-hand-side projections)
-  zero_acc<double>(PA.Pt, ncw);
-  __syncthreads();
-  if (A.pj.nproj && tid < cw && S.state[tid] == 0) {
-    const int c = tid;
-    const long long src = S.src[c];
-    for (int sl = 0; sl < SC_SLOTS; ++sl) {
-      const size_t si = (size_t)src * SC_SLOTS + sl;
-      const int pb = A.pj.sc_pb[si];
-      if (pb < 0) continue;
-      const double2 ph = A.pj.sc_eph[si];
-      const cx<double> w = cscale(mkc(ph.x, -ph.y), S.bsc[c]);
-      for (int m = 0; m < A.pj.nm && pb + m < A.pj.nproj; ++m) {
-        const double b = A.pj.sc_beta[si * A.pj.nm + m];
-        cx<double>* a = &PA.Pt[(size_t)(pb + m) * cw + c];
-        *a = *a + cscale(w, b * A.pj.h3);
+  // x32 = 0, r32 = p32 = b, v = A p (preconditioned: ph = M^-1 p, v = A ph)
+  double dots[4] = {0, 0, 0, 0};
+  double rmax = 0;
+  long long rmax_idx = 0;
+  if constexpr (PC) {
+    pc_forward<Q, float>(C32, pv, ps, A.pc, dst_, PC_INIT, dots);
+    C32.acc = PA.Pr;
+    pc_backward<Q, float>(C32, pv, ps, A.pc, dst_, pv.ph);
+    set_dco(A.pj, cw, C32.L.dco, PA.Pr);
+    __syncthreads();
+    pc_apply<RAD, Q, float, false>(C32, pv, ps, dots);
+  } else {
+    // projections of b (entries at the source point only): Pr = Pp = B^H b
+    zero_acc<double>(PA.Pr, ncw);
+    __syncthreads();
+    if (A.pj.nproj && tid < cw && S.state[tid] == 0) {
+      const int c = tid;
+      const long long src = S.src[c];
+      for (int sl = 0; sl < SC_SLOTS; ++sl) {
+        const size_t si = (size_t)src * SC_SLOTS + sl;
+        const int pb = A.pj.sc_pb[si];
+        if (pb < 0) continue;
+        const double2 ph = A.pj.sc_eph[si];
+        const cx<double> w = cscale(mkc(ph.x, -ph.y), S.bsc[c]);
+        for (int m = 0; m < A.pj.nm && pb + m < A.pj.nproj; ++m) {
+          const double b = A.pj.sc_beta[si * A.pj.nm + m];
+          cx<double>* a = &PA.Pr[(size_t)(pb + m) * cw + c];
+          *a = *a + cscale(w, b * A.pj.h3);
+        }
+      }
+      for (int k = A.pj.pe_offs[src]; k < A.pj.pe_offs[src + 1]; ++k) {
+        const int2 ge = A.pj.pe[k];
+        const double2 ph = A.pj.eph[ge.y];
+        const cx<double> w = cscale(mkc(ph.x, -ph.y), S.bsc[c]);
+        for (int m = 0; m < A.pj.grp_nm[ge.x]; ++m) {
+          const double b = A.pj.beta[(size_t)ge.y * A.pj.nm + m];
+          cx<double>* a = &PA.Pr[(size_t)(A.pj.grp_pbase[ge.x] + m) * cw + c];
+          *a = *a + cscale(w, b * A.pj.h3);
+        }
       }
     }
-    for (int k = A.pj.pe_offs[src]; k < A.pj.pe_offs[src + 1]; ++k) {
-      const int2 ge = A.pj.pe[k];
-      const double2 ph = A.pj.eph[ge.y];
-      const cx<double> w = cscale(mkc(ph.x, -ph.y), S.bsc[c]);
-      for (int m = 0; m < A.pj.grp_nm[ge.x]; ++m) {
-        const double b = A.pj.beta[(size_t)ge.y * A.pj.nm + m];
-        cx<double>* a = &PA.Pt[(size_t)(A.pj.grp_pbase[ge.x] + m) * cw + c];
-        *a = *a + cscale(w, b * A.pj.h3);
-      }
-    }
+    __syncthreads();
+    for (int w = tid; w < ncw; w += blockDim.x) PA.Pp[w] = PA.Pr[w];
+    set_dco(A.pj, cw, C32.L.dco, PA.Pr);
+    __syncthreads();
+    C32.acc = PA.Pv;
+    sweep<RAD, Q, float>(C32, ps, IN_INIT, OUT_V, dots, rmax, rmax_idx);
   }
+  if (tid < cw) S.rho[tid] = mkc(S.bsc[tid], 0.0);
   __syncthreads();
-  for (int outer = 0; outer < A.max_outer; ++outer) {
+
+  const double d2max = A.delta * A.delta;
+  bool all_done = false;
+  int it = 0;
+  while (!all_done) {
+    // every pass counts, breakdown passes included, so the loop is bounded
+    if (it >= A.max_iter) {
+      reliable_update<RAD, Q, PC>(A, C64, C32, pv, ps, PA, dst_, true, false, all_done);
+      break;
+    }
+    ++it;
+    // alpha = rho / (r^0, v)
     if (tid == 0) S.any_flag = 0;
     __syncthreads();
     if (tid < cw) {
       const int c = tid;
-      if (S.state[c] == 0 && S.rr[c] > 0.0) {
-        S.rscale[c] = 1.0 / sqrt(S.rr[c]);
-        S.uscale[c] = sqrt(S.rr[c]);
-        S.istate[c] = 0;
-        S.outer[c] += 1;
-        atomicOr(&S.any_flag, 1);
-      } else {
-        S.rscale[c] = 0.0;
-        S.uscale[c] = 0.0;
-        S.istate[c] = 1;
+      S.alpha[c] = mkc(0.0, 0.0);
+      if (S.state[c] == 0) {
+        const cx<double> vj = S.vj[c];
+        if (!(cnorm2(vj) > 0.0) || !finite2(vj) || !finite2(S.rho[c]))
+          atomicOr(&S.any_flag, 1);
+        else
+          S.alpha[c] = cdiv(S.rho[c], vj);
       }
     }
     __syncthreads();
-    if (!S.any_flag) break;
-    // inner FP32 solve of A d = r64 / ||r64||
-    for (int w = tid; w < ncw; w += blockDim.x) PA.Pr[w] = cscale(PA.Pt[w], S.rscale[w % cw]);
-    __syncthreads();
-    C32.rhs64 = C64.vec.r;
-    if constexpr (PC)
-      inner_pc<RAD, Q>(A, C32, pv, ps, PA, A.pc, dst_);
-    else
-      inner_plain<RAD, Q>(A, C32, ps, PA);
-    // x64 += ||r64|| d, gathered into Px
-    double tacc = 0.0;
-    C64.acc = PA.Px;
-    update_gather_sweep<Q>(C64, ps, C32.vec.x, A.gdst, tacc);
-    {
-      double v4[4] = {tacc, 0, 0, 0};
-      __shared__ double red_out[4][CW_MAX];
-      col_reduce4(C64.L.red, cw, v4, red_out);
-      if (tid < cw) S.tacc[tid] = red_out[0][tid];
+    if (S.any_flag) {
+      reliable_update<RAD, Q, PC>(A, C64, C32, pv, ps, PA, dst_, false, true, all_done);
+      continue;
     }
-    // r64 = b - A x64 (FP64), gathered into Pt
-    set_dco(A.pj, cw, C64.L.dco, PA.Px);
-    __syncthreads();
-    double dots[4] = {0, 0, 0, 0};
-    double rmax = -1.0;
-    long long rmax_idx = 0x7fffffffffffffffLL;
-    C64.acc = PA.Pt;
-    sweep<RAD, Q, double>(C64, ps, IN_X, OUT_RES, dots, rmax, rmax_idx);
+    // s = r - alpha v, t = A s (preconditioned: sh = M^-1 s, t = A sh); dots (t,s), (t,t)
+    for (int k = 0; k < 4; ++k) dots[k] = 0;
+    if constexpr (PC) {
+      pc_forward<Q, float>(C32, pv, ps, A.pc, dst_, PC_S, dots);
+      C32.acc = PA.Pp;
+      pc_backward<Q, float>(C32, pv, ps, A.pc, dst_, pv.sh);
+      set_dco(A.pj, cw, C32.L.dco, PA.Pp);
+      __syncthreads();
+      for (int k = 0; k < 4; ++k) dots[k] = 0;
+      pc_apply<RAD, Q, float, true>(C32, pv, ps, dots);
+    } else {
+      for (int w = tid; w < ncw; w += blockDim.x) {
+        const int c = w % cw;
+        C32.L.dco[w] = cscale(PA.Pr[w] - cmul(S.alpha[c], PA.Pv[w]), A.pj.ekb[w / cw]);
+      }
+      __syncthreads();
+      C32.acc = PA.Pt;
+      sweep<RAD, Q, float>(C32, ps, IN_B, OUT_T, dots, rmax, rmax_idx);
+    }
     {
       __shared__ double red_out[4][CW_MAX];
-      col_reduce4(C64.L.red, cw, dots, red_out);
-      double* bm = C64.L.red;
-      long long* bi = reinterpret_cast<long long*>(C64.L.red + blockDim.x);
-      bm[tid] = rmax;
-      bi[tid] = rmax_idx;
+      col_reduce4(C32.L.red, cw, dots, red_out);
+      if (tid == 0) S.any_flag = 0;
       __syncthreads();
       if (tid < cw) {
         const int c = tid;
-        double m = -1.0;
-        long long ix = 0x7fffffffffffffffLL;
-        for (int i = c; i < (int)blockDim.x; i += cw) {
-          if (bm[i] > m || (bm[i] == m && bi[i] < ix)) {
-            m = bm[i];
-            ix = bi[i];
-          }
-        }
         if (S.state[c] == 0) {
-          const double rr = red_out[0][c];
-          S.rr[c] = rr;
-          S.j0[c] = ix;
-          if (!isfinite(rr))
-            S.state[c] = 2;
-          else if (rr <= A.tol * A.tol * S.bb[c])
-            S.state[c] = 1;
+          const cx<double> ts = mkc(red_out[1][c], red_out[2][c]);
+          const double tt = red_out[3][c];
+          const cx<double> om = (tt > 0.0 && isfinite(tt)) ? cscale(ts, 1.0 / tt) : mkc(0.0, 0.0);
+          const cx<double> rn = S.sj[c] - cmul(om, S.tj[c]);
+          if (!(cnorm2(om) > 0.0) || !finite2(om) || !(cnorm2(rn) > 0.0) || !finite2(rn)) {
+            atomicOr(&S.any_flag, 1);
+            S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
+          } else {
+            S.omega[c] = om;
+            S.rho_new[c] = rn;
+            S.beta[c] = cmul(cdiv(rn, S.rho[c]), cdiv(S.alpha[c], om));
+          }
+        } else {
+          S.omega[c] = S.beta[c] = S.alpha[c] = mkc(0.0, 0.0);
         }
       }
       __syncthreads();
     }
+    if (S.any_flag) {
+      reliable_update<RAD, Q, PC>(A, C64, C32, pv, ps, PA, dst_, false, true, all_done);
+      continue;
+    }
+    // x += alpha p + omega s, r = s - omega t, p = r + beta (p - omega v), v = A p
+    // (preconditioned: x += alpha ph + omega sh, v = A ph with ph = M^-1 p); ||r||^2
+    for (int k = 0; k < 4; ++k) dots[k] = 0;
+    if constexpr (PC) {
+      pc_forward<Q, float>(C32, pv, ps, A.pc, dst_, PC_MERGED, dots);
+      C32.acc = PA.Pr;
+      pc_backward<Q, float>(C32, pv, ps, A.pc, dst_, pv.ph);
+      set_dco(A.pj, cw, C32.L.dco, PA.Pr);
+      __syncthreads();
+      double d2[4] = {0, 0, 0, 0};
+      pc_apply<RAD, Q, float, false>(C32, pv, ps, d2);
+    } else {
+      for (int w = tid; w < ncw; w += blockDim.x) {
+        const int c = w % cw;
+        const cx<double> al = S.alpha[c], om = S.omega[c], be = S.beta[c];
+        const cx<double> Ps = PA.Pr[w] - cmul(al, PA.Pv[w]);
+        const cx<double> Prn = Ps - cmul(om, PA.Pt[w]);
+        const cx<double> Ppn = Prn + cmul(be, PA.Pp[w] - cmul(om, PA.Pv[w]));
+        PA.Pr[w] = Prn;
+        PA.Pp[w] = Ppn;
+        C32.L.dco[w] = cscale(Ppn, A.pj.ekb[w / cw]);
+      }
+      __syncthreads();
+      C32.acc = PA.Pv;
+      sweep<RAD, Q, float>(C32, ps, IN_A, OUT_V, dots, rmax, rmax_idx);
+    }
+    {
+      __shared__ double red_out[4][CW_MAX];
+      col_reduce4(C32.L.red, cw, dots, red_out);
+      if (tid == 0) S.any_flag = 0;
+      __syncthreads();
+      if (tid < cw) {
+        const int c = tid;
+        if (S.state[c] == 0) {
+          S.iters[c] += 1;
+          S.rho[c] = S.rho_new[c];
+          const double rr = red_out[0][c];
+          // replace the residual once it has fallen by delta below the largest
+          // since the last replacement, or reached the tolerance
+          if (!isfinite(rr) || rr <= A.tol * A.tol * S.bb[c] || rr < d2max * S.maxrr[c])
+            atomicOr(&S.any_flag, 1);
+          else if (rr > S.maxrr[c])
+            S.maxrr[c] = rr;
+        }
+      }
+      __syncthreads();
+    }
+    if (S.any_flag) reliable_update<RAD, Q, PC>(A, C64, C32, pv, ps, PA, dst_, false, false, all_done);
   }
   if (tid < cw) {
     const int c = tid;
-    if (S.state[c] == 0) S.state[c] = 4;
     const int col = blk * cw + c;
     if (col < A.ncols) {
       const size_t o = (size_t)e_idx * A.ncols + col;
       A.T_col[o] = 4.0 * S.tacc[c];
       A.iters[o] = S.iters[c];
-      A.restarts[o] = S.outer[c];
+      A.restarts[o] = S.restarts[c];
+      if (A.updates) A.updates[o] = S.updates[c];
       A.resid[o] = S.bb[c] > 0 ? sqrt(S.rr[c] / S.bb[c]) : 0.0;
       A.status[o] = S.state[c] == 1 ? 0 : (S.state[c] == 2 ? 2 : 1);
     }
@@ -449,6 +409,7 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
   if (A.xout) {
     __threadfence();  // x was stored by the position-owning threads; read here by another mapping
     __syncthreads();
+    const size_t nall = (size_t)g.P * g.nz * cw;
     for (size_t w = tid; w < nall; w += blockDim.x) {
       const int c = (int)(w % cw);
       const size_t gi = w / cw;
@@ -483,7 +444,7 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_mixed(const SolveArgs*
   C64.yext = nullptr;
   C64.ext_ld = C64.ext_c0 = C64.ext_ncol = 0;
   C64.pcsrc = C64.pcs = nullptr;
-  C64.rhs64 = nullptr;
+  C64.r32 = nullptr;
   SweepCtx<float> C32;
   C32.g = &A.g;
   C32.pj = &A.pj;
@@ -496,13 +457,13 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_mixed(const SolveArgs*
   C32.yext = nullptr;
   C32.ext_ld = C32.ext_c0 = C32.ext_ncol = 0;
   C32.pcsrc = C32.pcs = nullptr;
-  C32.rhs64 = nullptr;
+  C32.r32 = nullptr;
+  // workspace: FP64 x, then the FP32 vectors x r p v t (+ ph sh s w)
   const size_t nv = (size_t)A.g.P * A.g.nz * cw;
   cx<double>* b64 = reinterpret_cast<cx<double>*>(A.ws) + (size_t)blockIdx.x * A.ws_stride;
   C64.vec.x = b64;
-  C64.vec.r = b64 + nv;
-  C64.vec.p = C64.vec.v = C64.vec.t = nullptr;
-  cx<float>* b32 = reinterpret_cast<cx<float>*>(b64 + 2 * nv);
+  C64.vec.r = C64.vec.p = C64.vec.v = C64.vec.t = nullptr;
+  cx<float>* b32 = reinterpret_cast<cx<float>*>(b64 + nv);
   C32.vec.x = b32;
   C32.vec.r = b32 + nv;
   C32.vec.p = b32 + 2 * nv;

@@ -16,7 +16,7 @@
 
 namespace rst {
 
-enum PcIn { PC_INIT, PC_MERGED, PC_RESTART, PC_S, PC_INIT_VEC };
+enum PcIn { PC_INIT, PC_MERGED, PC_RESTART, PC_S, PC_IN };
 
 template <class R>
 struct PcVecs {
@@ -159,13 +159,6 @@ __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, 
         stv(&C.vec.r[off], bb);
         stv(&C.vec.p[off], bb);
         u[k] = bb;
-      } else if (IN == PC_INIT_VEC) {
-        const cx<R> bb = fromd<R>(cscale(ldv(&C.rhs64[off]), S->rscale[c]));
-        stv(&C.vec.x[off], mkc<R>((R)0, (R)0));
-        stv(&C.vec.r[off], bb);
-        stv(&C.vec.p[off], bb);
-        if (gi == j0) S->rj[c] = to64(bb);
-        u[k] = bb;
       } else if (IN == PC_MERGED) {
         const cx<R> xv = ldv(&C.vec.x[off]), phv = ldv(&pv.ph[off]), shv = ldv(&pv.sh[off]),
                     sv = ldv(&pv.s[off]);
@@ -183,6 +176,8 @@ __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, 
         stv(&C.vec.p[off], rv);
         if (gi == j0) S->rj[c] = to64(rv);
         u[k] = rv;
+      } else if (IN == PC_IN) {
+        u[k] = ldv(&C.vec.r[off]);
       } else {  // PC_S
         const cx<R> sv = ldv(&C.vec.r[off]) - cmul(al, ldv(&C.vec.v[off]));
         stv(&pv.s[off], sv);
@@ -539,7 +534,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
   __syncthreads();
 }
 
-template <int RAD, int Q, class R>
+template <int RAD, int Q, class R, bool BATCH>
 __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab_pc(const SolveArgs* __restrict__ Ap) {
   const SolveArgs& A = *Ap;
   extern __shared__ __align__(16) char smem[];
@@ -557,7 +552,7 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab_pc(const Solv
   C.yext = nullptr;
   C.ext_ld = C.ext_c0 = C.ext_ncol = 0;
   C.pcsrc = C.pcs = nullptr;
-  C.rhs64 = nullptr;
+  C.r32 = nullptr;
   const size_t nv = (size_t)A.g.P * A.g.nz * cw;
   cx<R>* base = reinterpret_cast<cx<R>*>(A.ws) + (size_t)blockIdx.x * A.ws_stride;
   C.vec.x = base;
@@ -595,8 +590,93 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab_pc(const Solv
     __syncthreads();
     const int item = S.item;
     if (item >= A.nitems) break;
-    pc_solve_item<RAD, Q, R>(A, C, pv, ps, PA, A.pc, dst_, item);
+    if constexpr (BATCH) {
+      __shared__ SolveArgs Ai;  // per-item arguments of a batched launch
+      __shared__ int local_item;
+      if (threadIdx.x == 0) local_item = batch_item_args<true>(A, item, Ai);
+      __syncthreads();
+      for (int w = threadIdx.x; w < ntab; w += blockDim.x) {
+        const double2 t = Ai.pc.steps[w];
+        tab[w] = mkc(t.x, t.y);
+      }
+      __syncthreads();
+      C.g = &Ai.g;
+      C.V = Ai.V;
+      C.gz = Ai.gz;
+      pc_solve_item<RAD, Q, R>(Ai, C, pv, ps, PA, Ai.pc, dst_, local_item);
+    } else {
+      pc_solve_item<RAD, Q, R>(A, C, pv, ps, PA, A.pc, dst_, item);
+    }
   }
+}
+
+// Stand-alone M^-1 on blocked vectors (the layout of the flexible-GMRES
+// chunk): workgroup b maps block b of `in` (n x cw, column fastest) to block b
+// of `out`, with `wbuf` as its mode-space scratch.  Energy: the pivots pc.inv.
+struct PcApplyArgs {
+  Geo g;
+  PcConst pc;
+  const double2* in;
+  double2* out;
+  double2* wbuf;
+  int cw, nblk;
+  size_t pc_lds_off;
+};
+
+template <int Q>
+__global__ __launch_bounds__(MAX_T) void k_pc_apply(const PcApplyArgs* __restrict__ Ap) {
+  const PcApplyArgs& A = *Ap;
+  extern __shared__ __align__(16) char smem[];
+  __shared__ ColState S;
+  const int cw = A.cw;
+  Proj pj0 = {};
+  SweepCtx<double> C;
+  C.g = &A.g;
+  C.pj = &pj0;
+  C.V = nullptr;
+  C.gz = nullptr;
+  C.cw = cw;
+  C.L = carve_lds<double>(smem, A.g, pj0, cw, blockDim.x);
+  C.S = &S;
+  C.xext = nullptr;
+  C.yext = nullptr;
+  C.ext_ld = C.ext_c0 = C.ext_ncol = 0;
+  C.pcsrc = C.pcs = nullptr;
+  C.r32 = nullptr;
+  C.acc = nullptr;
+  const size_t nv = (size_t)A.g.P * A.g.nz * cw;
+  const size_t boff = (size_t)blockIdx.x * nv;
+  C.vec = Vecs<double>{nullptr, reinterpret_cast<cx<double>*>(const_cast<double2*>(A.in)) + boff, nullptr,
+                       nullptr, nullptr};
+  PcVecs<double> pv;
+  pv.ph = pv.sh = pv.s = nullptr;
+  pv.w = reinterpret_cast<cx<double>*>(A.wbuf) + boff;
+  pv.inv = reinterpret_cast<const cx<double>*>(A.pc.inv);
+  if (threadIdx.x < CW_MAX) {
+    const int c = threadIdx.x;
+    S.alpha[c] = S.omega[c] = S.beta[c] = mkc(0.0, 0.0);
+    S.j0[c] = -1;
+    S.src[c] = -1;
+    S.bsc[c] = 0.0;
+  }
+  cx<double>* tab = reinterpret_cast<cx<double>*>(smem + A.pc_lds_off);
+  const int ntab = 3 * (A.g.na + A.g.nb);
+  for (int w = threadIdx.x; w < ntab; w += blockDim.x) {
+    const double2 t = A.pc.steps[w];
+    tab[w] = mkc(t.x, t.y);
+  }
+  DftSteps dst_;
+  dst_.fa = tab;
+  dst_.fb = tab + A.g.na;
+  dst_.ia = tab + A.g.na + A.g.nb;
+  dst_.ib = tab + 2 * A.g.na + A.g.nb;
+  dst_.pa = tab + 2 * A.g.na + 2 * A.g.nb;
+  dst_.pb = tab + 3 * A.g.na + 2 * A.g.nb;
+  __syncthreads();
+  const Pos<Q> ps = make_pos<Q>(A.g, cw, 0);
+  double dots[4] = {0, 0, 0, 0};
+  pc_forward<Q, double>(C, pv, ps, A.pc, dst_, PC_IN, dots);
+  pc_backward<Q, double>(C, pv, ps, A.pc, dst_, reinterpret_cast<cx<double>*>(A.out) + boff);
 }
 
 }  // namespace rst

@@ -342,7 +342,50 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, c
   __syncthreads();
 }
 
-template <int RAD, int Q, class R>
+// Arguments of one item of a batched launch: the structure that owns `item`
+// (the last whose first item is <= item), its grid depth, Bloch phases,
+// potential, CAPs, energies, columns and output slices (and, with PC, its
+// preconditioner tables).  Returns the item's index within its structure.
+template <bool PC>
+__device__ inline int batch_item_args(const SolveArgs& A, int item, SolveArgs& Ai) {
+  int lo = 0, hi = A.nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (A.batch[mid].item0 <= item) lo = mid; else hi = mid - 1;
+  }
+  const BatchProb bp = A.batch[lo];
+  Ai = A;
+  Ai.g.nz = bp.nz;
+  Ai.g.pha_x = bp.pha_x;
+  Ai.g.pha_y = bp.pha_y;
+  Ai.g.phb_x = bp.phb_x;
+  Ai.g.phb_y = bp.phb_y;
+  Ai.V = A.V + bp.v_off;
+  Ai.gz = A.gz + bp.gz_off;
+  Ai.gdst = A.gdst + bp.gz_off;
+  Ai.gsrc = A.gsrc + bp.gz_off;
+  Ai.energies = A.energies + bp.e_off;
+  Ai.cols = A.cols + bp.col_off;
+  Ai.ncols = bp.ncols;
+  Ai.nblk = bp.nblk;
+  Ai.ne = bp.ne;
+  Ai.T_col = A.T_col + bp.out_off;
+  Ai.iters = A.iters + bp.out_off;
+  Ai.restarts = A.restarts + bp.out_off;
+  Ai.resid = A.resid + bp.out_off;
+  Ai.status = A.status + bp.out_off;
+  if constexpr (PC) {
+    Ai.pc.vbar = bp.vbar;
+    Ai.pc.eps = A.pc.eps + bp.eps_off;
+    Ai.pc.steps = A.pc.steps + bp.steps_off;
+    Ai.pc.inv = A.pc.inv + bp.inv_off;
+  }
+  return item - bp.item0;
+}
+
+// BATCH: items belong to the structures of A.batch (a separate instance, so
+// the single-structure kernel carries one copy of the solve body).
+template <int RAD, int Q, class R, bool BATCH>
 __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab(const SolveArgs* __restrict__ Ap) {
   const SolveArgs& A = *Ap;
   extern __shared__ __align__(16) char smem[];
@@ -360,7 +403,7 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab(const SolveAr
   C.yext = nullptr;
   C.ext_ld = C.ext_c0 = C.ext_ncol = 0;
   C.pcsrc = C.pcs = nullptr;
-  C.rhs64 = nullptr;
+  C.r32 = nullptr;
   const size_t nv = (size_t)A.g.P * A.g.nz * cw;
   cx<R>* base = reinterpret_cast<cx<R>*>(A.ws) + (size_t)blockIdx.x * A.ws_stride;
   C.vec.x = base;
@@ -372,43 +415,15 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab(const SolveAr
   cx<double>* pb = reinterpret_cast<cx<double>*>(A.pws) + (size_t)blockIdx.x * A.pws_stride;
   ProjArrays PA{pb, pb + np, pb + 2 * np, pb + 3 * np, pb + 4 * np};
   const Pos<Q> ps = make_pos<Q>(A.g, cw, RAD);
-  __shared__ SolveArgs Ai;  // per-item arguments of a batched launch
-  __shared__ int local_item;
   for (;;) {
     if (threadIdx.x == 0) S.item = atomicAdd(A.counter, 1);
     __syncthreads();
     const int item = S.item;
     if (item >= A.nitems) break;
-    if (A.nprob > 0) {
-      if (threadIdx.x == 0) {
-        int lo = 0, hi = A.nprob - 1;  // last structure whose first item <= item
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) / 2;
-          if (A.batch[mid].item0 <= item) lo = mid; else hi = mid - 1;
-        }
-        const BatchProb bp = A.batch[lo];
-        Ai = A;
-        Ai.g.nz = bp.nz;
-        Ai.g.pha_x = bp.pha_x;
-        Ai.g.pha_y = bp.pha_y;
-        Ai.g.phb_x = bp.phb_x;
-        Ai.g.phb_y = bp.phb_y;
-        Ai.V = A.V + bp.v_off;
-        Ai.gz = A.gz + bp.gz_off;
-        Ai.gdst = A.gdst + bp.gz_off;
-        Ai.gsrc = A.gsrc + bp.gz_off;
-        Ai.energies = A.energies + bp.e_off;
-        Ai.cols = A.cols + bp.col_off;
-        Ai.ncols = bp.ncols;
-        Ai.nblk = bp.nblk;
-        Ai.ne = bp.ne;
-        Ai.T_col = A.T_col + bp.out_off;
-        Ai.iters = A.iters + bp.out_off;
-        Ai.restarts = A.restarts + bp.out_off;
-        Ai.resid = A.resid + bp.out_off;
-        Ai.status = A.status + bp.out_off;
-        local_item = (int)(item - bp.item0);
-      }
+    if constexpr (BATCH) {
+      __shared__ SolveArgs Ai;  // per-item arguments of a batched launch
+      __shared__ int local_item;
+      if (threadIdx.x == 0) local_item = batch_item_args<false>(A, item, Ai);
       __syncthreads();
       C.g = &Ai.g;
       C.V = Ai.V;
@@ -434,14 +449,23 @@ __global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ A
   C.cw = cw;
   C.L = carve_lds<R>(smem, A.g, A.pj, cw, blockDim.x);
   C.S = &S;
-  C.xext = A.x;
-  C.yext = A.y;
-  C.ext_ld = A.ncol;
-  C.ext_c0 = blockIdx.x * cw;
-  C.ext_ncol = A.ncol;
+  if (A.blocked) {
+    const size_t boff = (size_t)blockIdx.x * A.g.P * A.g.nz * cw;
+    C.xext = A.x + boff;
+    C.yext = A.y + boff;
+    C.ext_ld = cw;
+    C.ext_c0 = 0;
+    C.ext_ncol = cw;
+  } else {
+    C.xext = A.x;
+    C.yext = A.y;
+    C.ext_ld = A.ncol;
+    C.ext_c0 = blockIdx.x * cw;
+    C.ext_ncol = A.ncol;
+  }
   C.vec = Vecs<R>{nullptr, nullptr, nullptr, nullptr, nullptr};
   C.pcsrc = C.pcs = nullptr;
-  C.rhs64 = nullptr;
+  C.r32 = nullptr;
   const int tid = threadIdx.x;
   if (tid < cw) {
     S.energy[tid] = A.energy;

@@ -22,7 +22,7 @@ struct SweepCtx {
   cx<double>* acc;       // gather accumulator of the output (nullptr: no gather)
   cx<R>* pcsrc;          // IN_PC source (preconditioned vector)
   cx<R>* pcs;            // OUT_TS: s for the (t, s) product
-  const cx<double>* rhs64;  // IN_INIT_VEC: FP64 right-hand side, scaled by S->rscale
+  cx<float>* r32;        // OUT_RES32 destination (FP32 copy of the FP64 residual)
 };
 
 template <int Q>
@@ -64,15 +64,6 @@ __device__ __forceinline__ cx<R> load_in(const SweepCtx<R>& C, int mode, int zl,
       stv(&C.vec.x[off], mkc<R>((R)0, (R)0));
       stv(&C.vec.r[off], u);
       stv(&C.vec.p[off], u);
-      return u;
-    }
-    case IN_INIT_VEC: {
-      const cx<double> b64 = cscale(ldv(&C.rhs64[off]), S->rscale[c]);
-      const cx<R> u = fromd<R>(b64);
-      stv(&C.vec.x[off], mkc<R>((R)0, (R)0));
-      stv(&C.vec.r[off], u);
-      stv(&C.vec.p[off], u);
-      if (gi == S->j0[c]) S->rj[c] = to64(u);
       return u;
     }
     case IN_A: {
@@ -158,6 +149,23 @@ __device__ __forceinline__ void store_out(const SweepCtx<R>& C, int mode, long l
       cx<R> rr = mkc<R>(-y.x, -y.y);
       if (gi == src) rr.x += (R)bsc;
       stv(&C.vec.r[off], rr);
+      const double n2 = (double)cnorm2(rr);
+      dots[0] += n2;
+      if (n2 > rmax || (n2 == rmax && gi < rmax_idx)) {
+        rmax = n2;
+        rmax_idx = gi;
+      }
+      if (do_gather) C.L.outpl[p * cw + c] = rr;
+      break;
+    }
+    case OUT_RES32: {
+      // r = b - A x in FP64, stored as the FP32 recursive residual of the
+      // mixed-precision solver; r[j0] of the stored value and the FP64 gather
+      cx<R> rr = mkc<R>(-y.x, -y.y);
+      if (gi == src) rr.x += (R)bsc;
+      const cx<float> r32 = mkc<float>((float)rr.x, (float)rr.y);
+      stv(&C.r32[off], r32);
+      if (gi == j0) S->rj[c] = to64(r32);
       const double n2 = (double)cnorm2(rr);
       dots[0] += n2;
       if (n2 > rmax || (n2 == rmax && gi < rmax_idx)) {

@@ -17,22 +17,24 @@ LIB_PATH = os.environ.get("RST_LIB") or os.path.join(_HERE, "librst.so")
 
 RST_OK, RST_ENOCONV = 0, 1
 RST_EINVAL, RST_ESTATE, RST_ENOMEM, RST_EDEVICE, RST_EUNSUPPORTED = -1, -2, -3, -4, -5
-RST_BICGSTAB = 0
+RST_BICGSTAB, RST_FGMRES = 0, 1
 RST_FP64, RST_FP32_REFINE = 0, 1
 RST_DIR_LR, RST_DIR_RL = 0, 1
-RST_PRECOND_NONE, RST_PRECOND_FREE_CAP = 0, 1
+RST_PRECOND_NONE, RST_PRECOND_FREE_CAP, RST_PRECOND_LEARNED = 0, 1, 2
 
 EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error", "rst_set_grid",
             "rst_set_potential", "rst_set_projectors", "rst_set_abc", "rst_set_k", "rst_set_solver",
             "rst_transmission", "rst_apply_h", "rst_solve_columns", "rst_batch_clear",
-            "rst_batch_add", "rst_batch_run"]
+            "rst_batch_add", "rst_batch_run", "rst_cnn_weight_count", "rst_cnn_seed",
+            "rst_cnn_set_weights", "rst_cnn_get_weights", "rst_cnn_forward", "rst_cnn_gradient",
+            "rst_cnn_train_step", "rst_precond_train"]
 
 
 class rst_solver_opts(C.Structure):
     _fields_ = [("method", C.c_int), ("precision", C.c_int), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("col_block", C.c_int), ("threads", C.c_int),
-                ("direction", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int),
-                ("precond", C.c_int)]
+                ("direction", C.c_int), ("update_delta", C.c_double), ("precond", C.c_int),
+                ("restart", C.c_int), ("fallback_ratio", C.c_double)]
 
 
 class rst_stats(C.Structure):
@@ -40,8 +42,21 @@ class rst_stats(C.Structure):
                 ("iterations_total", C.c_int64), ("iterations_max", C.c_int32),
                 ("restarts_total", C.c_int32), ("max_rel_residual", C.c_double),
                 ("kernel_ms", C.c_double), ("bytes_algorithmic", C.c_double),
-                ("refinements_total", C.c_int64), ("col_block", C.c_int32),
-                ("threads", C.c_int32)]
+                ("updates_total", C.c_int64), ("col_block", C.c_int32),
+                ("threads", C.c_int32), ("fallback_columns", C.c_int64), ("cnn_flop", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rst_train_opts(C.Structure):
+    _fields_ = [("pairs", C.c_int), ("batch", C.c_int), ("lr", C.c_float), ("seed", C.c_uint64),
+                ("n_e", C.c_int), ("energies", C.c_void_p), ("n_k", C.c_int), ("kpts", C.c_void_p)]
+
+
+class rst_train_stats(C.Structure):
+    _fields_ = [("steps", C.c_int), ("loss_first", C.c_double), ("loss_last", C.c_double),
+                ("ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,9 +106,19 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.rst_batch_clear.argtypes = [P]
     lib.rst_batch_add.argtypes = [P, C.POINTER(rst_problem)]
     lib.rst_batch_run.argtypes = [P, P, C.POINTER(rst_stats)]
+    lib.rst_cnn_weight_count.argtypes = []
+    lib.rst_precond_train.argtypes = [P, C.POINTER(rst_train_opts), C.POINTER(rst_train_stats)]
+    lib.rst_cnn_seed.argtypes = [P, C.c_uint64]
+    lib.rst_cnn_set_weights.argtypes = [P, P, C.c_int64]
+    lib.rst_cnn_get_weights.argtypes = [P, P, C.c_int64]
+    lib.rst_cnn_forward.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P, P]
+    lib.rst_cnn_gradient.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P, P, P]
+    lib.rst_cnn_train_step.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P, P, C.c_float,
+                                       C.POINTER(C.c_double)]
     for name in EXPORTED:
         if name not in ("rst_default_solver", "rst_destroy", "rst_last_error"):
             getattr(lib, name).restype = C.c_int
+    lib.rst_cnn_weight_count.restype = C.c_int64
     _lib = lib
     return lib
 
@@ -218,6 +243,45 @@ class Context:
         s = self._chk(self.lib.rst_batch_run(self.h, _ptr(t), C.byref(st)), allow_noconv=True)
         return t[:n], st.as_dict(), s
 
+    # -- learned correction network
+    def rst_cnn_seed(self, seed: int):
+        return self._chk(self.lib.rst_cnn_seed(self.h, int(seed)))
+
+    def rst_cnn_set_weights(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        return self._chk(self.lib.rst_cnn_set_weights(self.h, _ptr(w), w.size))
+
+    def rst_cnn_get_weights(self):
+        w = np.zeros(self.lib.rst_cnn_weight_count(), np.float32)
+        self._chk(self.lib.rst_cnn_get_weights(self.h, _ptr(w), w.size))
+        return w
+
+    def rst_cnn_forward(self, x_dev_ptr: int, out_dev_ptr: int, ncol, nz, nb, na):
+        return self._chk(self.lib.rst_cnn_forward(self.h, int(ncol), int(nz), int(nb), int(na),
+                                                  C.c_void_p(x_dev_ptr), C.c_void_p(out_dev_ptr)))
+
+    def rst_cnn_gradient(self, x_dev_ptr: int, gout_dev_ptr: int, ncol, nz, nb, na):
+        g = np.zeros(self.lib.rst_cnn_weight_count(), np.float32)
+        self._chk(self.lib.rst_cnn_gradient(self.h, int(ncol), int(nz), int(nb), int(na),
+                                            C.c_void_p(x_dev_ptr), C.c_void_p(gout_dev_ptr), _ptr(g)))
+        return g
+
+    def rst_cnn_train_step(self, x_dev_ptr: int, tgt_dev_ptr: int, ncol, nz, nb, na, lr):
+        loss = C.c_double(0.0)
+        self._chk(self.lib.rst_cnn_train_step(self.h, int(ncol), int(nz), int(nb), int(na),
+                                              C.c_void_p(x_dev_ptr), C.c_void_p(tgt_dev_ptr),
+                                              float(lr), C.byref(loss)))
+        return loss.value
+
+    def rst_precond_train(self, energies, kpts, pairs, batch=8, lr=1e-3, seed=0):
+        e = np.ascontiguousarray(np.atleast_1d(energies), np.float64)
+        k = np.ascontiguousarray(np.asarray(kpts, np.float64).reshape(-1, 2))
+        o = rst_train_opts(int(pairs), int(batch), float(lr), int(seed), e.size, _ptr(e).value,
+                           k.shape[0], _ptr(k).value)
+        st = rst_train_stats()
+        self._chk(self.lib.rst_precond_train(self.h, C.byref(o), C.byref(st)))
+        return st.as_dict()
+
     # -- convenience
     def load_problem(self, prob, k=None):
         """Sets grid, potential, projectors, CAPs and k from a workloads.Problem."""
@@ -249,3 +313,29 @@ def solve_columns(ctx: Context, energy: float, cols, n: int, device="cuda"):
     torch.cuda.synchronize()
     st, s = ctx.rst_solve_columns(energy, cols, x.data_ptr())
     return x, st, s
+
+
+def cnn_forward(ctx: Context, x):
+    """f(x) for a torch float32 CUDA tensor x of shape (ncol, nz, nb, na, 4) -> (ncol, nz, nb, na, 2)."""
+    import torch
+    assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.shape[-1] == 4
+    out = torch.empty(x.shape[:-1] + (2,), dtype=torch.float32, device=x.device)
+    torch.cuda.synchronize()
+    ctx.rst_cnn_forward(x.data_ptr(), out.data_ptr(), x.shape[0], x.shape[1], x.shape[2], x.shape[3])
+    return out
+
+
+def cnn_gradient(ctx: Context, x, gout):
+    """Weight gradient of <gout, f(x)> (weight layout, float32 numpy)."""
+    import torch
+    assert x.is_contiguous() and gout.is_contiguous() and gout.dtype == torch.float32
+    torch.cuda.synchronize()
+    return ctx.rst_cnn_gradient(x.data_ptr(), gout.data_ptr(), x.shape[0], x.shape[1], x.shape[2], x.shape[3])
+
+
+def cnn_train_step(ctx: Context, x, tgt, lr):
+    import torch
+    assert x.is_contiguous() and tgt.is_contiguous()
+    torch.cuda.synchronize()
+    return ctx.rst_cnn_train_step(x.data_ptr(), tgt.data_ptr(), x.shape[0], x.shape[1], x.shape[2],
+                                  x.shape[3], lr)

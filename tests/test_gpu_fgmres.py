@@ -1,0 +1,122 @@
+"""Flexible GMRES (the outer solver of the learned preconditioner) against the
+FP64 oracle: T to 1e-6 and Green's-function columns to 1e-9 relative, for the
+three preconditioners (none, free-electron + CAP, learned correction)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_02783_amd import rst
+from paper_2208_02783_amd import workloads as wl
+from tests.gpu_util import make_ctx, torch_cuda
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("pc", [rst.RST_PRECOND_NONE, rst.RST_PRECOND_FREE_CAP])
+def test_fgmres_config1_matches_oracle(pc):
+    torch = torch_cuda()
+    g = json.load(open(os.path.join(GOLD, "config1_T.json")))
+    p = wl.config(1)
+    es = np.array(g["energies"][2::7])
+    ref = np.array(g["T_LR"][2::7])
+    ctx = make_ctx(torch, p, (0.0, 0.0), method=rst.RST_FGMRES, precond=pc, restart=20)
+    t, st, s = ctx.rst_transmission(es)
+    _say("fgmres cfg1 pc", pc, st)
+    assert s == rst.RST_OK
+    assert st["max_rel_residual"] <= 1e-10
+    np.testing.assert_allclose(t, ref, atol=1e-6, rtol=0)
+
+
+def test_fgmres_tiny_fcc_slab_matches_oracle():
+    """Projectors, wells, k != 0, 12th order: FGMRES with M^-1 against the dense oracle."""
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    k = p.kpts[3]
+    es = p.energies[[0, 7]]
+    ref = oracle.transmission(p, es, k, both=False)["T_LR"]
+    ctx = make_ctx(torch, p, k, method=rst.RST_FGMRES, precond=rst.RST_PRECOND_FREE_CAP, restart=30)
+    t, st, s = ctx.rst_transmission(es)
+    _say("fgmres tiny cfg2", st)
+    assert s == rst.RST_OK
+    np.testing.assert_allclose(t, ref, atol=1e-6, rtol=0)
+
+
+def test_fgmres_solve_columns_matches_oracle():
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    k = p.kpts[1]
+    e = float(p.energies[3])
+    cols = np.array([0, 17, p.n // 2, p.n - 1])
+    ctx = make_ctx(torch, p, k, method=rst.RST_FGMRES, precond=rst.RST_PRECOND_FREE_CAP, tol=1e-12)
+    x, st, s = rst.solve_columns(ctx, e, cols, p.n)
+    assert s == rst.RST_OK, st
+    ref = oracle.green_columns(p, e, k, cols)
+    err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 1e-9, err
+
+
+def test_learned_preconditioner_untrained_still_converges():
+    """With seeded, untrained weights the learned correction may hurt; the
+    per-column fallback to M^-1 keeps FGMRES convergent and T exact."""
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    k = p.kpts[2]
+    es = p.energies[[4]]
+    ref = oracle.transmission(p, es, k, both=False)["T_LR"]
+    ctx = make_ctx(torch, p, k, method=rst.RST_FGMRES, precond=rst.RST_PRECOND_LEARNED, restart=20)
+    ctx.rst_cnn_seed(7)
+    t, st, s = ctx.rst_transmission(es)
+    _say("learned (untrained)", st)
+    assert s == rst.RST_OK
+    assert st["cnn_flop"] > 0
+    np.testing.assert_allclose(t, ref, atol=1e-6, rtol=0)
+
+
+def test_fgmres_option_errors():
+    torch = torch_cuda()
+    p = wl.config(1)
+    ctx = make_ctx(torch, p, (0.0, 0.0))
+    with pytest.raises(RuntimeError, match="FGMRES"):
+        ctx.rst_set_solver(precond=rst.RST_PRECOND_LEARNED)
+    with pytest.raises(RuntimeError, match="FP64"):
+        ctx.rst_set_solver(method=rst.RST_FGMRES, precision=rst.RST_FP32_REFINE)
+    with pytest.raises(RuntimeError, match="restart"):
+        ctx.rst_set_solver(method=rst.RST_FGMRES, restart=0)
+    ctx.rst_set_solver(method=rst.RST_FGMRES, precond=rst.RST_PRECOND_LEARNED)
+    with pytest.raises(RuntimeError, match="weights"):
+        ctx.rst_transmission(np.array([0.5]))
+
+
+def test_training_lowers_the_loss_and_learned_fgmres_is_exact():
+    """Training on pairs from the structure's own operator lowers the loss; the
+    trained correction inside FGMRES gives the oracle's T.  The iteration
+    counts with and without the correction are reported (the gain)."""
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    es = p.energies[::37]
+    ctx = make_ctx(torch, p, p.kpts[0], method=rst.RST_FGMRES, precond=rst.RST_PRECOND_LEARNED, restart=30)
+    ctx.rst_cnn_seed(3)
+    ts = ctx.rst_precond_train(es, p.kpts[:8], pairs=640, batch=8, lr=2e-3, seed=11)
+    _say("training", ts)
+    assert ts["steps"] == 80
+    assert ts["loss_last"] < 0.7 * ts["loss_first"], ts
+    k = p.kpts[5]
+    e_test = p.energies[[10, 200]]
+    ref = oracle.transmission(p, e_test, k, both=False)["T_LR"]
+    ctx.rst_set_k(k[0], k[1])
+    t, st, s = ctx.rst_transmission(e_test)
+    assert s == rst.RST_OK
+    np.testing.assert_allclose(t, ref, atol=1e-6, rtol=0)
+    ctx.rst_set_solver(method=rst.RST_FGMRES, precond=rst.RST_PRECOND_FREE_CAP, restart=30)
+    t2, st2, s2 = ctx.rst_transmission(e_test)
+    assert s2 == rst.RST_OK
+    _say("gain: learned", st["iterations_total"], "its, fallbacks", st["fallback_columns"],
+         "| free-electron only", st2["iterations_total"], "its")
