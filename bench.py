@@ -131,6 +131,66 @@ def batched_comparison(n_slabs=96, ne=2, precond=1):
             "max_abs_dT_plain_vs_batched": dmax, "all_converged": bool(ok_plain and s_b == rst.RST_OK)}
 
 
+def mixed_point(prob, k, e, t_ref):
+    """One T(E,k) point of the same slab with FP32 BiCGSTAB and FP64 reliable
+    updates (free-electron + CAP preconditioner), against the FP64 point."""
+    from paper_2208_02783_amd import rst
+    ctx = rst.Context(0)
+    ctx.load_problem(prob, k)
+    ctx.rst_set_solver(precond=1, precision=rst.RST_FP32_REFINE, max_iter=20000)
+    t0 = time.perf_counter()
+    t, st, s = ctx.rst_transmission(np.array([e]))
+    wall = time.perf_counter() - t0
+    print(f"mixed precision point: {wall:.1f} s, T={t[0]:.6f}, iters/col="
+          f"{st['iterations_total'] / max(st['columns'], 1):.1f}", file=sys.stderr, flush=True)
+    return {"points_per_s": (1.0 if s == rst.RST_OK else 0.0) / wall, "status": int(s), "T": float(t[0]),
+            "abs_dT_vs_fp64": abs(float(t[0]) - t_ref), "iterations_per_column": st["iterations_total"] / st["columns"],
+            "fp64_residual_replacements_per_column": st["updates_total"] / st["columns"],
+            "max_rel_residual": st["max_rel_residual"], "kernel_ms": st["kernel_ms"],
+            "algorithmic_GBps": st["bytes_algorithmic"] / (st["kernel_ms"] * 1e-3) / 1e9}
+
+
+def learned_comparison(prob, ncols=32, pairs=4000, tol=1e-8):
+    """Learned preconditioner on the slab's geometry: the network is trained on
+    generated pairs (r = A M^-1 xi, e = M^-1 xi over the slab's energies and k
+    points), then a bounded sample of right-CAP columns at one (E, k) is solved
+    to `tol` by BiCGSTAB with M^-1, FGMRES(30) with M^-1 and FGMRES(30) with the
+    learned correction."""
+    from paper_2208_02783_amd import rst
+    k = prob.kpts[9]
+    e = float(prob.energies[400])
+    rc = prob.r_columns()
+    cols = rc[np.linspace(0, rc.size - 1, ncols).round().astype(np.int64)]
+    ctx = rst.Context(0)
+    ctx.load_problem(prob, k)
+    ctx.rst_cnn_seed(1)
+    ts = ctx.rst_precond_train(prob.energies[::16], prob.kpts, pairs=pairs, batch=8, lr=1e-3, seed=2)
+    print(f"learned: trained {ts['steps']} steps in {ts['ms'] / 1e3:.1f} s, loss {ts['loss_first']:.3g} -> "
+          f"{ts['loss_last']:.3g}", file=sys.stderr, flush=True)
+    res, xs = {}, {}
+    runs = [("bicgstab_free_cap", dict(method=rst.RST_BICGSTAB, precond=rst.RST_PRECOND_FREE_CAP)),
+            ("fgmres_free_cap", dict(method=rst.RST_FGMRES, precond=rst.RST_PRECOND_FREE_CAP, restart=30)),
+            ("fgmres_learned", dict(method=rst.RST_FGMRES, precond=rst.RST_PRECOND_LEARNED, restart=30))]
+    for name, kw in runs:
+        ctx.rst_set_solver(tol=tol, max_iter=6000, **kw)
+        x, st, s = rst.solve_columns(ctx, e, cols, prob.n)
+        xs[name] = x.cpu().numpy()
+        res[name] = {"status": int(s), "iterations_per_column": st["iterations_total"] / ncols,
+                     "ms": st["kernel_ms"], "max_rel_residual": st["max_rel_residual"],
+                     "fallback_columns": st["fallback_columns"], "network_tflop": st["cnn_flop"] / 1e12}
+        print(f"learned comparison {name}: {st['kernel_ms']:.0f} ms, "
+              f"{st['iterations_total'] / ncols:.1f} its/col", file=sys.stderr, flush=True)
+    ref = xs["bicgstab_free_cap"]
+    for name in res:
+        d = np.linalg.norm(xs[name] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        res[name]["max_rel_dx_vs_bicgstab"] = float(np.max(d))
+    return {"workload": f"config-2 slab geometry, {ncols} right-CAP columns at E={e:.4f}, k={list(map(float, k))}, "
+                        f"to true relative residual {tol:g}",
+            "training": {"pairs": pairs, "batch": 8, "steps": ts["steps"], "seconds": ts["ms"] / 1e3,
+                         "loss_first": ts["loss_first"], "loss_last": ts["loss_last"]},
+            "solvers": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +202,8 @@ def main():
                     help="fp64: FP64 throughout; mixed: FP32 applies inside FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the plain-vs-batched comparison")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision point")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="before the run, copy this many GiB device-to-device (a reference "
                          "kernel of known traffic for hardware-counter scaling)")
@@ -235,6 +297,10 @@ def main():
     }
     if not args.no_batched:
         line["batched"] = batched_comparison()
+    if not args.no_mixed and args.precision == "fp64":
+        line["mixed"] = mixed_point(prob, res[0][3], res[0][4], res[0][0])
+    if not args.no_learned:
+        line["learned"] = learned_comparison(prob)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

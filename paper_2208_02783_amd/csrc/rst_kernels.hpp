@@ -247,9 +247,11 @@ struct ColState {
   int state[CW_MAX];       // 0 active, 1 done, 2 failed, 3 padding
   int iters[CW_MAX], restarts[CW_MAX];
   // mixed precision: largest recursive ||r||^2 since the last FP64 residual
-  // replacement, the replacements so far, and the block's replacement request
-  double maxrr[CW_MAX];
-  int updates[CW_MAX];
+  // replacement, ||r||^2 at it and the latest recursive ||r||^2, the
+  // replacements so far, how the next replacement treats x32 (1 fold, 0
+  // discard, -1 take a fold back), the block's request
+  double maxrr[CW_MAX], rr_upd[CW_MAX], rr_rec[CW_MAX];
+  int updates[CW_MAX], fold[CW_MAX];
   int upd_flag;
   int any_flag;
   int item;

@@ -14,14 +14,23 @@
 // argmax |r|).  Convergence is decided on the FP64 true residual alone.  The
 // drift between the recursive and the true residual grows like eps32 times
 // the largest residual since the last replacement, which the replacement rule
-// keeps within eps32 / delta of the current residual.
+// keeps within eps32 / delta of the current residual.  A column whose
+// recursive residual norm has grown by more than 1e5 since the last
+// replacement (a near-breakdown the FP32 recurrence cannot follow: x32 then has
+// no correct digits) has x32 discarded instead of folded, and the block
+// restarts from the FP64 residual of the unchanged x64.  Likewise a fold after
+// which the true residual norm exceeds the recursive one tenfold is taken back
+// (the FP32 increment was not reliable) and the block restarts.
 #pragma once
 #include "rst_precond.hpp"
 
 namespace rst {
 
-// x64 += x32 and x32 = 0 over all planes, with the gather of the new x64 into
-// C.acc and the transmission accumulator sum_z gdst(z) |x64|^2.
+constexpr double DIVERGE2 = 1e10;  // squared-norm growth that discards x32
+constexpr double GAP2 = 100.0;     // ||r_true||^2 / ||r_rec||^2 that takes a fold back
+
+// x64 += fold[c] * x32 (fold 1, 0 or -1) over all planes, with the gather of
+// the new x64 into C.acc and the transmission accumulator sum_z gdst(z) |x64|^2.
 template <int Q>
 __device__ __forceinline__ void fold_gather_sweep(SweepCtx<double>& C, const Pos<Q>& ps, cx<float>* x32,
                                                   const double* gdst, double& tacc) {
@@ -29,6 +38,7 @@ __device__ __forceinline__ void fold_gather_sweep(SweepCtx<double>& C, const Pos
   const Proj& pj = *C.pj;
   const int cw = C.cw;
   const int c = threadIdx.x % cw;
+  const double fold = (double)C.S->fold[c];
   const bool any_g = pj.nproj > 0 && C.acc != nullptr;
   if (any_g) pacc_zero<double>(pj, C.L, cw);
   __syncthreads();
@@ -39,9 +49,11 @@ __device__ __forceinline__ void fold_gather_sweep(SweepCtx<double>& C, const Pos
     for (int k = 0; k < Q; ++k) {
       if (ps.p[k] >= 0) {
         const size_t off = ((size_t)z * g.P + ps.p[k]) * cw + c;
-        const cx<double> xv = ldv(&C.vec.x[off]) + to64(ldv(&x32[off]));
-        stv(&C.vec.x[off], xv);
-        stv(&x32[off], mkc<float>(0.0f, 0.0f));
+        cx<double> xv = ldv(&C.vec.x[off]);
+        if (fold != 0.0) {
+          xv = xv + cscale(to64(ldv(&x32[off])), fold);
+          stv(&C.vec.x[off], xv);
+        }
         tacc += gd * cnorm2(xv);
         if (need_g) C.L.outpl[ps.p[k] * cw + c] = xv;
       }
@@ -59,18 +71,25 @@ __device__ __forceinline__ void fold_gather_sweep(SweepCtx<double>& C, const Pos
   }
 }
 
-// One reliable update of the block: fold x32 into x64, r32 = b - A x64
-// (FP64 apply), decide every active column on its FP64 true residual, and
-// restart the Krylov process of the block if `restart` (a breakdown) asks.
+// x32 = 0 over all planes.
+template <int Q>
+__device__ __forceinline__ void zero_sweep(const Geo& g, const Pos<Q>& ps, int cw, cx<float>* x32) {
+  const int c = threadIdx.x % cw;
+  for (int z = 0; z < g.nz; ++z) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (ps.p[k] >= 0) stv(&x32[((size_t)z * g.P + ps.p[k]) * cw + c], mkc<float>(0.0f, 0.0f));
+  }
+}
+
+// r32 = b - A x64 (FP64 sweep; the plain recurrences take B^H r into Pr) after
+// the fold sweep: S.rr, S.rmax_idx, S.tacc per column.
 template <int RAD, int Q, bool PC>
-__device__ __forceinline__ void reliable_update(const SolveArgs& A, SweepCtx<double>& C64, SweepCtx<float>& C32,
-                                                const PcVecs<float>& pv, const Pos<Q>& ps,
-                                                const ProjArrays& PA, const DftSteps& dst_, bool final_check,
-                                                bool restart, bool& all_done) {
+__device__ __forceinline__ void fold_and_residual(const SolveArgs& A, SweepCtx<double>& C64, SweepCtx<float>& C32,
+                                                  const Pos<Q>& ps, const ProjArrays& PA) {
   ColState& S = *C64.S;
   const int cw = A.cw;
   const int tid = threadIdx.x;
-  // (1) x64 += x32, x32 = 0; B^H x64 -> Px; T accumulator
   double tacc = 0.0;
   C64.acc = PA.Px;
   fold_gather_sweep<Q>(C64, ps, C32.vec.x, A.gdst, tacc);
@@ -80,7 +99,6 @@ __device__ __forceinline__ void reliable_update(const SolveArgs& A, SweepCtx<dou
     col_reduce4(C64.L.red, cw, v4, red_out);
     if (tid < cw) S.tacc[tid] = red_out[0][tid];
   }
-  // (2) r32 = b - A x64 (FP64 sweep; the plain recurrences take B^H r into Pr)
   set_dco(A.pj, cw, C64.L.dco, PA.Px);
   __syncthreads();
   double dots[4] = {0, 0, 0, 0};
@@ -111,6 +129,40 @@ __device__ __forceinline__ void reliable_update(const SolveArgs& A, SweepCtx<dou
     }
     __syncthreads();
   }
+}
+
+// One reliable update of the block: fold x32 into x64, r32 = b - A x64
+// (FP64 apply), decide every active column on its FP64 true residual, and
+// restart the Krylov process of the block if `restart` (a breakdown or a
+// discarded x32) asks.
+template <int RAD, int Q, bool PC>
+__device__ __forceinline__ void reliable_update(const SolveArgs& A, SweepCtx<double>& C64, SweepCtx<float>& C32,
+                                                const PcVecs<float>& pv, const Pos<Q>& ps,
+                                                const ProjArrays& PA, const DftSteps& dst_, bool final_check,
+                                                bool restart, bool& all_done) {
+  ColState& S = *C64.S;
+  const int cw = A.cw;
+  const int tid = threadIdx.x;
+  // (1) x64 += x32 (or x32 discarded); r32 = b - A x64 in FP64
+  fold_and_residual<RAD, Q, PC>(A, C64, C32, ps, PA);
+  // (2) a fold whose true residual disagrees with the recursive one is taken back
+  if (tid == 0) S.any_flag = 0;
+  __syncthreads();
+  if (tid < cw) {
+    const int c = tid;
+    const bool back = S.state[c] == 0 && S.fold[c] == 1 && !(S.rr[c] <= A.tol * A.tol * S.bb[c]) &&
+                      !(S.rr[c] <= GAP2 * S.rr_rec[c]);
+    S.fold[c] = back ? -1 : 0;
+    if (back) atomicOr(&S.any_flag, 1);
+  }
+  __syncthreads();
+  if (S.any_flag) {
+    fold_and_residual<RAD, Q, PC>(A, C64, C32, ps, PA);
+    restart = true;
+  }
+  zero_sweep<Q>(A.g, ps, cw, C32.vec.x);
+  if (tid < cw) S.fold[tid] = 1;
+  __syncthreads();
   // (3) decide: converged, failed, out of iterations, or go on from the true residual
   if (tid == 0) S.any_flag = 0;
   __syncthreads();
@@ -127,6 +179,7 @@ __device__ __forceinline__ void reliable_update(const SolveArgs& A, SweepCtx<dou
         S.state[c] = 4;
       } else {
         S.maxrr[c] = rr;
+        S.rr_upd[c] = rr;
         if (restart) {
           S.j0[c] = S.rmax_idx[c];
           S.restarts[c] += 1;
@@ -182,6 +235,7 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
     S.iters[c] = 0;
     S.restarts[c] = 0;
     S.updates[c] = 0;
+    S.fold[c] = 1;
     S.tacc[c] = 0.0;
     S.rr[c] = 0.0;
     if (col < A.ncols) {
@@ -192,6 +246,8 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
       S.bsc[c] = sqrt(gs);
       S.bb[c] = gs;
       S.maxrr[c] = gs;
+      S.rr_upd[c] = gs;
+      S.rr_rec[c] = gs;
       S.state[c] = 0;
     } else {
       S.src[c] = -1;
@@ -199,6 +255,8 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
       S.bsc[c] = 0.0;
       S.bb[c] = 0.0;
       S.maxrr[c] = 0.0;
+      S.rr_upd[c] = 0.0;
+      S.rr_rec[c] = 0.0;
       S.state[c] = 3;
     }
   }
@@ -381,17 +439,26 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
           S.iters[c] += 1;
           S.rho[c] = S.rho_new[c];
           const double rr = red_out[0][c];
+          S.rr_rec[c] = rr;
           // replace the residual once it has fallen by delta below the largest
-          // since the last replacement, or reached the tolerance
-          if (!isfinite(rr) || rr <= A.tol * A.tol * S.bb[c] || rr < d2max * S.maxrr[c])
+          // since the last replacement, or reached the tolerance; discard x32
+          // and restart once it has diverged
+          if (!isfinite(rr) || rr > DIVERGE2 * S.rr_upd[c]) {
+            S.fold[c] = 0;
+            atomicOr(&S.any_flag, 2);
+          } else if (rr <= A.tol * A.tol * S.bb[c] || rr < d2max * S.maxrr[c]) {
             atomicOr(&S.any_flag, 1);
-          else if (rr > S.maxrr[c])
+          } else if (rr > S.maxrr[c]) {
             S.maxrr[c] = rr;
+          }
         }
       }
       __syncthreads();
     }
-    if (S.any_flag) reliable_update<RAD, Q, PC>(A, C64, C32, pv, ps, PA, dst_, false, false, all_done);
+    if (S.any_flag) {
+      const bool rs = (S.any_flag & 2) != 0;
+      reliable_update<RAD, Q, PC>(A, C64, C32, pv, ps, PA, dst_, false, rs, all_done);
+    }
   }
   if (tid < cw) {
     const int c = tid;

@@ -77,6 +77,17 @@ class RstError(RuntimeError):
 _lib = None
 
 
+def _torch_runtime_first():
+    """torch brings its own HIP runtime; it must initialise before the one
+    librst links (the other order leaves torch without devices)."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def load(path: str = LIB_PATH) -> C.CDLL:
     """Loads librst.so (raises if it is not built)."""
     global _lib
@@ -85,6 +96,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"librst.so not found at {path}: build it with "
                            "`python -m paper_2208_02783_amd.build` (no CPU fallback exists)")
+    _torch_runtime_first()
     lib = C.CDLL(path)
     P = C.c_void_p
     lib.rst_default_solver.argtypes = [C.POINTER(rst_solver_opts)]
