@@ -77,7 +77,8 @@ typedef struct {
                         FP64), the solution kept as x64 + x32 and the recursive residual replaced by the
                         FP64 true residual b - A x64 whenever it has fallen by update_delta (reliable
                         updates, Sleijpen and van der Vorst 1996); convergence is decided on the FP64
-                        true residual */
+                        true residual.  A column whose best FP64 residual has not fallen tenfold over
+                        30 replacements is solved again in FP64 (stats.fallback_columns) */
   double tol;        /* stop when the FP64 true residual ||b - A x|| <= tol ||b|| per column (default 1e-10) */
   int max_iter;      /* BiCGSTAB iterations per column (default 20000) */
   int col_block;     /* columns solved together by one workgroup; 0 = automatic */
@@ -115,7 +116,9 @@ typedef struct {
   int64_t updates_total;     /* RST_FP32_REFINE: FP64 residual replacements summed over columns */
   int32_t col_block;         /* columns per workgroup used by the launch */
   int32_t threads;           /* workgroup size used by the launch */
-  int64_t fallback_columns;  /* RST_PRECOND_LEARNED: columns switched to M^-1 alone */
+  int64_t fallback_columns;  /* RST_PRECOND_LEARNED: columns switched to M^-1 alone;
+                                RST_FP32_REFINE: columns solved again by the FP64 kernel because the
+                                FP32 recurrences stopped making progress */
   double cnn_flop;           /* RST_PRECOND_LEARNED: network flops (2 per multiply-add) */
 } rst_stats;
 

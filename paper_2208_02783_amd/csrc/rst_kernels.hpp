@@ -146,6 +146,11 @@ struct Proj {
   const double* beta;              // [nent*nm] real projector values per entry
   const double2* eph;              // [nent] exp(+i k.R_e) of the entry's lateral image
   const int* ent_p;                // [nent] in-plane point index of the entry
+  // gather order: chunk j (chunks numbered plane by plane) is entries
+  // j*CHUNK..j*CHUNK+CHUNK-1, padding entries with zero beta and phase
+  const int* g_ent_p;
+  const double2* g_eph;
+  const double* g_beta;
   const int* zc_offs;              // [nz+1] gather chunks per plane
   const int4* chunks;              // (group, first entry, count, -)
   const int* zg_offs;              // [nz+1] groups per plane
@@ -249,9 +254,10 @@ struct ColState {
   // mixed precision: largest recursive ||r||^2 since the last FP64 residual
   // replacement, ||r||^2 at it and the latest recursive ||r||^2, the
   // replacements so far, how the next replacement treats x32 (1 fold, 0
-  // discard, -1 take a fold back), the block's request
-  double maxrr[CW_MAX], rr_upd[CW_MAX], rr_rec[CW_MAX];
-  int updates[CW_MAX], fold[CW_MAX];
+  // discard, -1 take a fold back), the best true ||r||^2 and the replacements
+  // since it last fell tenfold, the block's request
+  double maxrr[CW_MAX], rr_upd[CW_MAX], rr_rec[CW_MAX], best_rr[CW_MAX];
+  int updates[CW_MAX], fold[CW_MAX], stall[CW_MAX];
   int upd_flag;
   int any_flag;
   int item;
@@ -346,24 +352,23 @@ __device__ __forceinline__ void plane_gather(int z, const Proj& pj, const Lds<R>
   const int nch = c1 - c0;
   const int nm = pj.nm;
   if (nch == 0) return;  // uniform across the workgroup
-  // stage 1: chunk partial sums (fixed order inside a chunk)
+  // stage 1: chunk partial sums (fixed order inside a chunk); the chunk's
+  // entries sit at a position known from the plane alone (no lookup chain)
   for (int w = tid; w < nch * nm * cw; w += T) {
     const int c = w % cw;
     const int m = (w / cw) % nm;
     const int ci = w / (cw * nm);
-    const int4 ch = pj.chunks[c0 + ci];
+    const int e0 = (c0 + ci) * CHUNK;
     double sx = 0.0, sy = 0.0;
 #pragma unroll
     for (int k = 0; k < CHUNK; ++k) {
-      if (k < ch.z) {
-        const int e = ch.y + k;
-        const cx<double> yv = to64(L.outpl[pj.ent_p[e] * cw + c]);
-        const double2 ph = pj.eph[e];
-        const cx<double> w2 = cmulc(mkc(ph.x, ph.y), yv);  // conj(phase) * y
-        const double b = pj.beta[(size_t)e * nm + m];
-        sx += b * w2.x;
-        sy += b * w2.y;
-      }
+      const int e = e0 + k;
+      const cx<double> yv = to64(L.outpl[pj.g_ent_p[e] * cw + c]);
+      const double2 ph = pj.g_eph[e];
+      const cx<double> w2 = cmulc(mkc(ph.x, ph.y), yv);  // conj(phase) * y; zero for padding
+      const double b = pj.g_beta[(size_t)e * nm + m];
+      sx += b * w2.x;
+      sy += b * w2.y;
     }
     L.slots[(ci * nm + m) * cw + c] = mkc(sx, sy);
   }
@@ -391,25 +396,26 @@ __device__ __forceinline__ cx<double> point_scatter(long long i, int c, const Pr
   cx<double> acc = mkc(0.0, 0.0);
   const int nm = pj.nm;
   const int plast = pj.nproj - 1;
+  // the slot's projector index, phase and values are loaded together (an empty
+  // slot has zero values and phase, so it adds exactly zero): one memory
+  // latency instead of a dependent chain
 #pragma unroll
   for (int sl = 0; sl < SC_SLOTS; ++sl) {
     const size_t si = (size_t)i * SC_SLOTS + sl;
-    const int pb = pj.sc_pb[si];
-    if (pb >= 0) {
-      const double* bt = pj.sc_beta + si * nm;
-      double tx = 0.0, ty = 0.0;
+    const int pb = max(pj.sc_pb[si], 0);
+    const double* bt = pj.sc_beta + si * nm;
+    const double2 ph = pj.sc_eph[si];
+    double tx = 0.0, ty = 0.0;
 #pragma unroll
-      for (int m = 0; m < NM_MAX; ++m) {
-        if (m < nm) {
-          const int pp = min(pb + m, plast);  // beta is zero past the group's projectors
-          const cx<double> d = L.dco[pp * cw + c];
-          tx += bt[m] * d.x;
-          ty += bt[m] * d.y;
-        }
+    for (int m = 0; m < NM_MAX; ++m) {
+      if (m < nm) {
+        const int pp = min(pb + m, plast);  // beta is zero past the group's projectors
+        const cx<double> d = L.dco[pp * cw + c];
+        tx += bt[m] * d.x;
+        ty += bt[m] * d.y;
       }
-      const double2 ph = pj.sc_eph[si];
-      acc = acc + cmul(mkc(ph.x, ph.y), mkc(tx, ty));
     }
+    acc = acc + cmul(mkc(ph.x, ph.y), mkc(tx, ty));
   }
   if (pj.has_overflow) {
     const int k0 = pj.pe_offs[i], k1 = pj.pe_offs[i + 1];

@@ -93,13 +93,16 @@ struct rst_ctx {
   std::vector<int4> chunks, zgroups;
   std::vector<int2> pe;
   std::vector<int> sc_pb, sc_ent;  // scatter slots: first projector and entry (-1 empty)
+  // gather order: plane-major, each (plane, group) run padded to whole chunks
+  std::vector<int> g_ent_p, g_src;  // in-plane point and source entry (-1: padding)
+  std::vector<double> g_beta;
   std::vector<double> sc_beta;
   int has_overflow = 0;
   // device copies
   DevBuf d_v, d_gz, d_gl, d_gr;
   DevBuf d_pc_eps, d_pc_twa, d_pc_twb;
   DevBuf d_grp_pbase, d_grp_nm, d_ekb, d_beta, d_eph, d_ent_p, d_zc, d_chunks, d_zg, d_zgroups,
-      d_pe_offs, d_pe, d_sc_pb, d_sc_eph, d_sc_beta;
+      d_pe_offs, d_pe, d_sc_pb, d_sc_eph, d_sc_beta, d_g_ent_p, d_g_eph, d_g_beta;
   // solver
   rst_solver_opts opts;
   // work buffers (grown on demand)
@@ -108,6 +111,7 @@ struct rst_ctx {
   long long last_fallbacks = 0;   // FGMRES: columns whose learned correction was switched off
   double last_cnn_flop = 0.0;     // FGMRES: network flops of the last solve
   double last_fg_bytes = 0.0;     // FGMRES: algorithmic vector bytes of the last solve
+  double last_extra_bytes = 0.0;  // mixed precision: bytes of the FP64 re-solves
   // flexible GMRES chunk buffers
   DevBuf d_fgV, d_fgZ, d_fgX, d_fgW, d_fgM, d_fgwb, d_fgx0, d_fgf, d_fgH, d_fgcs, d_fgsn, d_fgg, d_fginv, d_fgest,
       d_fgact, d_fgit, d_fguse, d_fgh1, d_fgh2, d_fgn2, d_fgy, d_fgsrc, d_fgbsc, d_fgt, d_fgaa, d_fgpa, d_fgsa;
@@ -242,6 +246,9 @@ rst::Proj make_proj(const rst_ctx* c) {
   p.pe = (const int2*)c->d_pe.p;
   p.sc_pb = (const int*)c->d_sc_pb.p;
   p.sc_eph = (const double2*)c->d_sc_eph.p;
+  p.g_ent_p = (const int*)c->d_g_ent_p.p;
+  p.g_eph = (const double2*)c->d_g_eph.p;
+  p.g_beta = (const double*)c->d_g_beta.p;
   p.sc_beta = (const double*)c->d_sc_beta.p;
   p.has_overflow = c->has_overflow;
   return p;
@@ -348,6 +355,20 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
     c->chunks.insert(c->chunks.end(), zch[z].begin(), zch[z].end());
     c->zgroups.insert(c->zgroups.end(), zgr[z].begin(), zgr[z].end());
   }
+  // gather-order copies: chunk j (over all planes) holds entries j*CHUNK .. j*CHUNK+CHUNK-1
+  c->g_ent_p.assign(c->chunks.size() * rst::CHUNK, 0);
+  c->g_src.assign(c->chunks.size() * rst::CHUNK, -1);
+  c->g_beta.assign(c->chunks.size() * rst::CHUNK * nm, 0.0);
+  for (size_t j = 0; j < c->chunks.size(); ++j) {
+    const int4 ch = c->chunks[j];
+    for (int k = 0; k < ch.z; ++k) {
+      const size_t g = j * rst::CHUNK + k;
+      const int e = ch.y + k;
+      c->g_ent_p[g] = c->ent_p[e];
+      c->g_src[g] = e;
+      for (int m = 0; m < nm; ++m) c->g_beta[g * nm + m] = c->beta[(size_t)e * nm + m];
+    }
+  }
   // point-centric scatter: the first SC_SLOTS entries of each point go to the
   // slot table (group order), further ones to the overflow lists
   const int K = rst::SC_SLOTS;
@@ -387,6 +408,8 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
   if ((s = upload(c, c->d_ekb, c->ekb)) != RST_OK) return s;
   if ((s = upload(c, c->d_beta, c->beta)) != RST_OK) return s;
   if ((s = upload(c, c->d_ent_p, c->ent_p)) != RST_OK) return s;
+  if ((s = upload(c, c->d_g_ent_p, c->g_ent_p)) != RST_OK) return s;
+  if ((s = upload(c, c->d_g_beta, c->g_beta)) != RST_OK) return s;
   if ((s = upload(c, c->d_zc, c->zc_offs)) != RST_OK) return s;
   if ((s = upload(c, c->d_chunks, c->chunks)) != RST_OK) return s;
   if ((s = upload(c, c->d_zg, c->zg_offs)) != RST_OK) return s;
@@ -447,6 +470,12 @@ rst_status upload_k(rst_ctx* c) {
   }
   rst_status s = upload(c, c->d_eph, eph);
   if (s != RST_OK) return s;
+  std::vector<double2> gph(c->g_src.size());
+  for (size_t g = 0; g < gph.size(); ++g) {
+    const int e = c->g_src[g];
+    gph[g] = e >= 0 ? eph[e] : double2{0.0, 0.0};
+  }
+  if ((s = upload(c, c->d_g_eph, gph)) != RST_OK) return s;
   std::vector<double2> sce(c->sc_ent.size());
   for (size_t i = 0; i < sce.size(); ++i) {
     const int e = c->sc_ent[i];
@@ -677,6 +706,57 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   return RST_OK;
 }
 
+// Mixed precision: columns the FP32 recurrences did not converge are solved
+// again with the FP64 kernel (per energy, only those columns); their results
+// replace the mixed ones.  With an x export the whole set is solved again.
+rst_status mixed_fp64_fallback(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
+                               const double* d_gsrc, const double* d_gdst, double2* xout, std::vector<double>& Tcol,
+                               std::vector<int>& its, std::vector<int>& rss, std::vector<double>& res,
+                               std::vector<int>& stv, double& ms) {
+  if (c->opts.precision != RST_FP32_REFINE) return RST_OK;
+  c->last_fallbacks = 0;
+  c->last_extra_bytes = 0.0;
+  const size_t ncols = cols.size();
+  bool any = false;
+  for (int v : stv) any = any || v != 0;
+  if (!any) return RST_OK;
+  const int saved = c->opts.precision;
+  const std::vector<int> ups = c->last_updates;
+  c->opts.precision = RST_FP64;
+  const double streams = c->opts.precond == RST_PRECOND_FREE_CAP ? 24.0 : 12.0;
+  const double n = (double)c->na * c->nb * c->nz;
+  rst_status s = RST_OK;
+  for (int ie = 0; ie < ne && s == RST_OK; ++ie) {
+    std::vector<int64_t> sub;
+    std::vector<size_t> where;
+    for (size_t j = 0; j < ncols; ++j)
+      if (xout || stv[(size_t)ie * ncols + j] != 0) {
+        sub.push_back(cols[j]);
+        where.push_back((size_t)ie * ncols + j);
+      }
+    if (sub.empty()) continue;
+    std::vector<double> T2, r2;
+    std::vector<int> i2, s2, st2;
+    double ms2 = 0;
+    s = run_solver(c, 1, energies + ie, sub, d_gsrc, d_gdst, xout, T2, i2, s2, r2, st2, ms2);
+    if (s != RST_OK) break;
+    ms += ms2;
+    for (size_t q = 0; q < sub.size(); ++q) {
+      const size_t o = where[q];
+      if (stv[o] != 0) c->last_fallbacks += 1;
+      Tcol[o] = T2[q];
+      its[o] += i2[q];
+      c->last_extra_bytes += (double)i2[q] * streams * 16.0 * n;
+      rss[o] = s2[q];
+      res[o] = r2[q];
+      stv[o] = st2[q];
+    }
+  }
+  c->opts.precision = saved;
+  c->last_updates = ups;
+  return s;
+}
+
 void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const std::vector<int>& rss,
                 const std::vector<double>& res, const std::vector<int>& stv, double ms, int& nbad,
                 int cw = 0, int threads = 0, double n_override = 0.0) {
@@ -700,6 +780,7 @@ void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const st
     s.fallback_columns = c->last_fallbacks;
     s.cnn_flop = c->last_cnn_flop;
   }
+  if (mixed) s.fallback_columns = c->last_fallbacks;
   s.kernel_ms = ms;
   s.col_block = cw;
   s.threads = threads;
@@ -709,7 +790,7 @@ void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const st
     // iterations on FP32 vectors; per reliable update: the fold (read x64 and x32,
     // write x64 and x32 = 0: 48 B) and the FP64 residual (read x64, write r32: 24 B)
     s.bytes_algorithmic = (double)s.iterations_total * streams * 8.0 * n +
-                          (double)s.updates_total * 72.0 * n;
+                          (double)s.updates_total * 72.0 * n + c->last_extra_bytes;
   else if (fgm)
     s.bytes_algorithmic = c->last_fg_bytes;
   else
@@ -1539,6 +1620,9 @@ rst_status rst_set_grid(rst_ctx* c, int na, int nb, int nz, double ha, double hb
   c->ent_p.clear();
   c->ent_img.clear();
   c->sc_ent.clear();
+  c->g_ent_p.clear();
+  c->g_src.clear();
+  c->g_beta.clear();
   // empty projector plan
   const long long n = (long long)na * nb * nz;
   c->zc_offs.assign(nz + 1, 0);
@@ -1580,6 +1664,9 @@ rst_status rst_set_projectors(rst_ctx* c, int nproj, const int32_t* offs, const 
     c->ent_p.clear();
     c->ent_img.clear();
     c->sc_ent.clear();
+    c->g_ent_p.clear();
+    c->g_src.clear();
+    c->g_beta.clear();
     return RST_OK;
   }
   if (!offs || !pt || !img || !beta || !e_kb) return fail(c, RST_EINVAL, "null projector array");
@@ -1684,6 +1771,10 @@ rst_status rst_transmission(rst_ctx* c, int n_e, const double* E, double* T_out,
                  lr ? (const double*)c->d_gl.p : (const double*)c->d_gr.p, nullptr, Tcol, its, rss, res, stv,
                  ms);
   if (s != RST_OK) return s;
+  s = mixed_fp64_fallback(c, n_e, E, cols, lr ? (const double*)c->d_gr.p : (const double*)c->d_gl.p,
+                          lr ? (const double*)c->d_gl.p : (const double*)c->d_gr.p, nullptr, Tcol, its, rss, res,
+                          stv, ms);
+  if (s != RST_OK) return s;
   const size_t nc = cols.size();
   for (int i = 0; i < n_e; ++i) {
     double t = 0;
@@ -1711,6 +1802,8 @@ rst_status rst_solve_columns(rst_ctx* c, double energy, int ncol, const int64_t*
   std::vector<int> its, rss, stv;
   double ms = 0;
   s = run_solver(c, 1, &energy, cols, nullptr, nullptr, (double2*)x_dev, Tcol, its, rss, res, stv, ms);
+  if (s != RST_OK) return s;
+  s = mixed_fp64_fallback(c, 1, &energy, cols, nullptr, nullptr, (double2*)x_dev, Tcol, its, rss, res, stv, ms);
   if (s != RST_OK) return s;
   int nbad = 0;
   fill_stats(c, stats, its, rss, res, stv, ms, nbad, c->last_cw, c->last_threads);

@@ -20,7 +20,10 @@
 // no correct digits) has x32 discarded instead of folded, and the block
 // restarts from the FP64 residual of the unchanged x64.  Likewise a fold after
 // which the true residual norm exceeds the recursive one tenfold is taken back
-// (the FP32 increment was not reliable) and the block restarts.
+// (the FP32 increment was not reliable) and the block restarts.  A column
+// whose best true residual norm has not fallen tenfold over STALL_UPDATES
+// replacements is given up (status not converged): the library then solves it
+// again with the FP64 kernel.
 #pragma once
 #include "rst_precond.hpp"
 
@@ -28,6 +31,7 @@ namespace rst {
 
 constexpr double DIVERGE2 = 1e10;  // squared-norm growth that discards x32
 constexpr double GAP2 = 100.0;     // ||r_true||^2 / ||r_rec||^2 that takes a fold back
+constexpr int STALL_UPDATES = 30;  // replacements without a tenfold fall of the best residual
 
 // x64 += fold[c] * x32 (fold 1, 0 or -1) over all planes, with the gather of
 // the new x64 into C.acc and the transmission accumulator sum_z gdst(z) |x64|^2.
@@ -177,7 +181,13 @@ __device__ __forceinline__ void reliable_update(const SolveArgs& A, SweepCtx<dou
         S.state[c] = 1;
       } else if (final_check) {
         S.state[c] = 4;
+      } else if (!(rr < 0.01 * S.best_rr[c]) && ++S.stall[c] >= STALL_UPDATES) {
+        S.state[c] = 4;  // the FP32 recurrences make no progress on this column
       } else {
+        if (rr < 0.01 * S.best_rr[c]) {
+          S.best_rr[c] = rr;
+          S.stall[c] = 0;
+        }
         S.maxrr[c] = rr;
         S.rr_upd[c] = rr;
         if (restart) {
@@ -236,6 +246,7 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
     S.restarts[c] = 0;
     S.updates[c] = 0;
     S.fold[c] = 1;
+    S.stall[c] = 0;
     S.tacc[c] = 0.0;
     S.rr[c] = 0.0;
     if (col < A.ncols) {
@@ -248,6 +259,7 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
       S.maxrr[c] = gs;
       S.rr_upd[c] = gs;
       S.rr_rec[c] = gs;
+      S.best_rr[c] = gs;
       S.state[c] = 0;
     } else {
       S.src[c] = -1;
@@ -257,6 +269,7 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
       S.maxrr[c] = 0.0;
       S.rr_upd[c] = 0.0;
       S.rr_rec[c] = 0.0;
+      S.best_rr[c] = 0.0;
       S.state[c] = 3;
     }
   }

@@ -243,6 +243,7 @@ __device__ __forceinline__ void sweep(SweepCtx<R>& C, const Pos<Q>& ps, int in_m
       nxt[k] = mkc<R>((R)0, (R)0);
       if (zl < nz && ps.p[k] >= 0) nxt[k] = load_in<R>(C, in_mode, zl, ps.p[k], c, al, om, be, d0);
     }
+
     // 2. stage plane z (with phase-premultiplied halos) into LDS
     cx<R>* buf = (z & 1) ? C.L.inpl1 : C.L.inpl0;
 #pragma unroll
