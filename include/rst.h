@@ -184,6 +184,16 @@ rst_status rst_apply_h(rst_ctx *ctx, double energy, const void *x_dev, void *y_d
 rst_status rst_solve_columns(rst_ctx *ctx, double energy, int ncol, const int64_t *col,
                              void *x_dev, rst_stats *stats);
 
+/* General right-hand sides: for every energy e < n_e and column j < ncol,
+ * x_dev[gi, e, j] = (G(E_e) b_{e,j})[gi] with b_{e,j}[gi] = rhs_dev[gi, e*rhs_estride + j]
+ * (complex128 device arrays; rhs_dev has ld = ncol if rhs_estride = 0, i.e. the same
+ * right-hand sides for every energy, else ld = n_e*ncol with rhs_estride = ncol;
+ * x_dev is (n x n_e*ncol), element (gi, e, j) at gi*(n_e*ncol) + e*ncol + j).
+ * FP64 BiCGSTAB only (RST_EUNSUPPORTED otherwise); the shadow residual is
+ * e_j0 with j0 = argmax |b|. */
+rst_status rst_solve_rhs(rst_ctx *ctx, int n_e, const double *energies, int ncol, const void *rhs_dev,
+                         int64_t rhs_estride, void *x_dev, rst_stats *stats);
+
 /* Batched transmission (paper Appendix: the (k, spin) calculations are
  * independent; here every (structure, energy, column block) is a work item of
  * one persistent launch).  rst_batch_clear empties the batch; rst_batch_add

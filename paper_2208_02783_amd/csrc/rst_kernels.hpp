@@ -217,7 +217,11 @@ struct SolveArgs {
   double* resid;            // [ne*ncols] final FP64 true relative residual
   int* status;              // [ne*ncols] 0 converged, 1 not converged, 2 non-finite
   int* counter;             // work queue head
-  double2* xout;            // optional export of x: (n x ncols) column-fastest
+  double2* xout;            // optional export of x: element (gi, energy e, column j) at
+                            // gi*(ne*ncols) + e*ncols + j
+  const double2* rhs;       // optional dense right-hand sides: element (gi, e, j) at
+                            // gi*rhs_ld + e*rhs_estride + j (null: point sources)
+  long long rhs_ld, rhs_estride;
 };
 
 struct ApplyArgs {

@@ -566,7 +566,8 @@ rst_status run_fgmres(rst_ctx* c, int ne, const double* energies, const std::vec
 rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
                       const double* d_gsrc, const double* d_gdst, double2* xout,
                       std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
-                      std::vector<double>& res, std::vector<int>& st, double& ms) {
+                      std::vector<double>& res, std::vector<int>& st, double& ms,
+                      const double2* rhs = nullptr, long long rhs_ld = 0, long long rhs_estride = 0) {
   if (c->opts.method == RST_FGMRES) {
     const std::vector<double>* hsrc = d_gsrc == nullptr ? nullptr : (d_gsrc == c->d_gr.p ? &c->gr : &c->gl);
     return run_fgmres(c, ne, energies, cols, d_gdst, hsrc, xout, Tcol, its, rss, res, st, ms);
@@ -666,6 +667,9 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   A.status = (int*)c->d_st.p;
   A.counter = (int*)c->d_counter.p;
   A.xout = xout;
+  A.rhs = rhs;
+  A.rhs_ld = rhs_ld;
+  A.rhs_estride = rhs_estride;
   hipLaunchKernelGGL(rst::k_fill_int, dim3(1), dim3(64), 0, c->stream, (int*)c->d_counter.p, 16, 0);
   HIPCHK(c, hipGetLastError());
   if ((s = ensure(c, c->d_args, sizeof(A))) != RST_OK) return s;
@@ -1804,6 +1808,32 @@ rst_status rst_solve_columns(rst_ctx* c, double energy, int ncol, const int64_t*
   s = run_solver(c, 1, &energy, cols, nullptr, nullptr, (double2*)x_dev, Tcol, its, rss, res, stv, ms);
   if (s != RST_OK) return s;
   s = mixed_fp64_fallback(c, 1, &energy, cols, nullptr, nullptr, (double2*)x_dev, Tcol, its, rss, res, stv, ms);
+  if (s != RST_OK) return s;
+  int nbad = 0;
+  fill_stats(c, stats, its, rss, res, stv, ms, nbad, c->last_cw, c->last_threads);
+  return nbad ? RST_ENOCONV : RST_OK;
+}
+
+rst_status rst_solve_rhs(rst_ctx* c, int n_e, const double* energies, int ncol, const void* rhs_dev,
+                         int64_t rhs_estride, void* x_dev, rst_stats* stats) {
+  rst_status s = check_ready(c);
+  if (s != RST_OK) return s;
+  if (n_e < 0 || ncol < 0 || ((n_e > 0 && ncol > 0) && (!energies || !rhs_dev || !x_dev)))
+    return fail(c, RST_EINVAL, "bad right-hand-side arguments");
+  if (rhs_estride != 0 && rhs_estride != ncol) return fail(c, RST_EINVAL, "rhs_estride must be 0 or ncol");
+  for (int i = 0; i < n_e; ++i)
+    if (!std::isfinite(energies[i])) return fail(c, RST_EINVAL, "non-finite energy");
+  if (c->opts.method != RST_BICGSTAB || c->opts.precision != RST_FP64)
+    return fail(c, RST_EUNSUPPORTED, "dense right-hand sides are solved by FP64 BiCGSTAB");
+  if (n_e == 0 || ncol == 0) return RST_OK;
+  hipSetDevice(c->device);
+  std::vector<int64_t> cols(ncol, 0);
+  std::vector<double> Tcol, res;
+  std::vector<int> its, rss, stv;
+  double ms = 0;
+  const long long ld = rhs_estride ? (long long)n_e * ncol : ncol;
+  s = run_solver(c, n_e, energies, cols, nullptr, nullptr, (double2*)x_dev, Tcol, its, rss, res, stv, ms,
+                 (const double2*)rhs_dev, ld, rhs_estride);
   if (s != RST_OK) return s;
   int nbad = 0;
   fill_stats(c, stats, its, rss, res, stv, ms, nbad, c->last_cw, c->last_threads);

@@ -499,7 +499,7 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
         double2 o;
         o.x = xv.x;
         o.y = xv.y;
-        A.xout[gi * A.ncols + col] = o;
+        A.xout[gi * ((size_t)A.ne * A.ncols) + (size_t)e_idx * A.ncols + col] = o;
       }
     }
   }
@@ -525,6 +525,9 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_mixed(const SolveArgs*
   C64.ext_ld = C64.ext_c0 = C64.ext_ncol = 0;
   C64.pcsrc = C64.pcs = nullptr;
   C64.r32 = nullptr;
+  C64.rhs = nullptr;
+  C64.rhs_ld = C64.rhs_c0 = 0;
+  C64.rhs_nc = 0;
   SweepCtx<float> C32;
   C32.g = &A.g;
   C32.pj = &A.pj;
@@ -538,6 +541,9 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_mixed(const SolveArgs*
   C32.ext_ld = C32.ext_c0 = C32.ext_ncol = 0;
   C32.pcsrc = C32.pcs = nullptr;
   C32.r32 = nullptr;
+  C32.rhs = nullptr;
+  C32.rhs_ld = C32.rhs_c0 = 0;
+  C32.rhs_nc = 0;
   // workspace: FP64 x, then the FP32 vectors x r p v t (+ ph sh s w)
   const size_t nv = (size_t)A.g.P * A.g.nz * cw;
   cx<double>* b64 = reinterpret_cast<cx<double>*>(A.ws) + (size_t)blockIdx.x * A.ws_stride;

@@ -139,8 +139,6 @@ __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, 
   const cx<R> om = fromd<R>(S->omega[c]);
   const cx<R> be = fromd<R>(S->beta[c]);
   const long long j0 = S->j0[c];
-  const long long src = S->src[c];
-  const R bsc = (R)S->bsc[c];
   const R a = (R)K.a;
   cx<R> dprev[Q];
 #pragma unroll
@@ -154,7 +152,7 @@ __device__ __forceinline__ void pc_forward(SweepCtx<R>& C, const PcVecs<R>& pv, 
       const long long gi = (long long)z * g.P + ps.p[k];
       const size_t off = (size_t)gi * cw + c;
       if (IN == PC_INIT) {
-        const cx<R> bb = (gi == src) ? mkc<R>(bsc, (R)0) : mkc<R>((R)0, (R)0);
+        const cx<R> bb = rhs_at<R>(C, gi, c);
         stv(&C.vec.x[off], mkc<R>((R)0, (R)0));
         stv(&C.vec.r[off], bb);
         stv(&C.vec.p[off], bb);
@@ -388,6 +386,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
   // this item's energy selects its slice of the shared Thomas pivots
   pv.inv = reinterpret_cast<const cx<double>*>(K.inv) + (size_t)e_idx * g.nz * g.P;
   __syncthreads();
+  if (A.rhs) rhs_scan<Q, R>(A, C, ps, e_idx, blk, nullptr);
   double dots[4] = {0, 0, 0, 0};
   pc_forward<Q, R>(C, pv, ps, K, dst_, PC_INIT, dots);
   zero_acc<R>(PA.Pr, ncw);
@@ -397,7 +396,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
   set_dco(A.pj, cw, C.L.dco, PA.Pr);
   __syncthreads();
   pc_apply<RAD, Q, R, false>(C, pv, ps, dots);
-  if (tid < cw) S.rho[tid] = mkc(S.bsc[tid], 0.0);
+  if (tid < cw) S.rho[tid] = A.rhs ? S.rj[tid] : mkc(S.bsc[tid], 0.0);
   __syncthreads();
 
   bool all_done = false;
@@ -527,7 +526,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
         double2 o;
         o.x = (double)xv.x;
         o.y = (double)xv.y;
-        A.xout[gi * A.ncols + col] = o;
+        A.xout[gi * ((size_t)A.ne * A.ncols) + (size_t)e_idx * A.ncols + col] = o;
       }
     }
   }
@@ -553,6 +552,9 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab_pc(const Solv
   C.ext_ld = C.ext_c0 = C.ext_ncol = 0;
   C.pcsrc = C.pcs = nullptr;
   C.r32 = nullptr;
+  C.rhs = nullptr;
+  C.rhs_ld = C.rhs_c0 = 0;
+  C.rhs_nc = 0;
   const size_t nv = (size_t)A.g.P * A.g.nz * cw;
   cx<R>* base = reinterpret_cast<cx<R>*>(A.ws) + (size_t)blockIdx.x * A.ws_stride;
   C.vec.x = base;
@@ -643,6 +645,9 @@ __global__ __launch_bounds__(MAX_T) void k_pc_apply(const PcApplyArgs* __restric
   C.ext_ld = C.ext_c0 = C.ext_ncol = 0;
   C.pcsrc = C.pcs = nullptr;
   C.r32 = nullptr;
+  C.rhs = nullptr;
+  C.rhs_ld = C.rhs_c0 = 0;
+  C.rhs_nc = 0;
   C.acc = nullptr;
   const size_t nv = (size_t)A.g.P * A.g.nz * cw;
   const size_t boff = (size_t)blockIdx.x * nv;

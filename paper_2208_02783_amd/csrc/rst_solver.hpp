@@ -33,6 +33,80 @@ __device__ __forceinline__ void set_dco(const Proj& pj, int cw, cx<double>* dco,
   }
 }
 
+// Dense right-hand side of an item: point C at the item's columns, then one
+// pass over b for ||b||^2, the shadow index j0 = argmax |b| (ties: smaller
+// index), rho = b[j0] and, when `acc` is given, the projections B^H b.
+template <int Q, class R>
+__device__ __forceinline__ void rhs_scan(const SolveArgs& A, SweepCtx<R>& C, const Pos<Q>& ps, int e_idx, int blk,
+                                         cx<double>* acc) {
+  const Geo& g = *C.g;
+  const Proj& pj = *C.pj;
+  const int cw = C.cw;
+  const int tid = threadIdx.x;
+  const int c = tid % cw;
+  ColState& S = *C.S;
+  C.rhs = A.rhs;
+  C.rhs_ld = A.rhs_ld;
+  C.rhs_c0 = (long long)e_idx * A.rhs_estride + (long long)blk * cw;
+  C.rhs_nc = min(cw, A.ncols - blk * cw);
+  const bool any_g = pj.nproj > 0 && acc != nullptr;
+  if (any_g) pacc_zero<R>(pj, C.L, cw);
+  __syncthreads();
+  double n2 = 0.0, bmax = -1.0;
+  long long bidx = 0x7fffffffffffffffLL;
+  for (int z = 0; z < g.nz; ++z) {
+    const bool need_g = any_g && pj.zc_offs[z + 1] > pj.zc_offs[z];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (ps.p[k] < 0) continue;
+      const long long gi = (long long)z * g.P + ps.p[k];
+      const cx<R> b = rhs_at<R>(C, gi, c);
+      const double a2 = (double)cnorm2(b);
+      n2 += a2;
+      if (a2 > bmax || (a2 == bmax && gi < bidx)) {
+        bmax = a2;
+        bidx = gi;
+      }
+      if (need_g) C.L.outpl[ps.p[k] * cw + c] = b;
+    }
+    if (need_g) {
+      __syncthreads();
+      plane_gather<R>(z, pj, C.L, cw);
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (any_g) {
+    pacc_flush<R>(pj, C.L, cw, acc);
+    __syncthreads();
+  }
+  double v4[4] = {n2, 0, 0, 0};
+  __shared__ double red_out[4][CW_MAX];
+  col_reduce4(C.L.red, cw, v4, red_out);
+  double* bm = C.L.red;
+  long long* bi = reinterpret_cast<long long*>(C.L.red + blockDim.x);
+  bm[tid] = bmax;
+  bi[tid] = bidx;
+  __syncthreads();
+  if (tid < cw) {
+    double m = -1.0;
+    long long ix = 0x7fffffffffffffffLL;
+    for (int i = tid; i < (int)blockDim.x; i += cw) {
+      if (bm[i] > m || (bm[i] == m && bi[i] < ix)) {
+        m = bm[i];
+        ix = bi[i];
+      }
+    }
+    S.src[tid] = -1;
+    S.bb[tid] = red_out[0][tid];
+    S.j0[tid] = ix;
+    S.rj[tid] = (tid < C.rhs_nc && ix >= 0 && ix < (long long)g.P * g.nz) ? to64(rhs_at<R>(C, ix, tid))
+                                                                          : mkc(0.0, 0.0);
+    if (tid < C.rhs_nc && !(red_out[0][tid] > 0.0)) S.state[tid] = 1;  // b = 0: x = 0 is exact
+  }
+  __syncthreads();
+}
+
 template <int RAD, int Q, class R>
 __device__ __forceinline__ void true_residual_and_restart(const SolveArgs& A, SweepCtx<R>& C, const Pos<Q>& ps,
                                           const ProjArrays& PA, bool final_check, bool& all_done) {
@@ -159,7 +233,8 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, c
   zero_acc<R>(PA.Pr, ncw);
   zero_acc<R>(PA.Pv, ncw);
   __syncthreads();
-  if (A.pj.nproj && tid < cw && S.state[tid] == 0) {
+  if (A.rhs) rhs_scan<Q, R>(A, C, ps, e_idx, blk, PA.Pr);
+  if (A.pj.nproj && tid < cw && S.state[tid] == 0 && !A.rhs) {
     const int c = tid;
     const long long src = S.src[c];
     // slot-table entries of the source point
@@ -196,7 +271,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, c
   long long rmax_idx = 0;
   C.acc = PA.Pv;
   sweep<RAD, Q, R>(C, ps, IN_INIT, OUT_V, dots, rmax, rmax_idx);
-  if (tid < cw) S.rho[tid] = mkc(S.bsc[tid], 0.0);
+  if (tid < cw) S.rho[tid] = A.rhs ? S.rj[tid] : mkc(S.bsc[tid], 0.0);
   __syncthreads();
 
   bool all_done = false;
@@ -335,7 +410,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, c
         double2 o;
         o.x = (double)xv.x;
         o.y = (double)xv.y;
-        A.xout[gi * A.ncols + col] = o;
+        A.xout[gi * ((size_t)A.ne * A.ncols) + (size_t)e_idx * A.ncols + col] = o;
       }
     }
   }
@@ -404,6 +479,9 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab(const SolveAr
   C.ext_ld = C.ext_c0 = C.ext_ncol = 0;
   C.pcsrc = C.pcs = nullptr;
   C.r32 = nullptr;
+  C.rhs = nullptr;
+  C.rhs_ld = C.rhs_c0 = 0;
+  C.rhs_nc = 0;
   const size_t nv = (size_t)A.g.P * A.g.nz * cw;
   cx<R>* base = reinterpret_cast<cx<R>*>(A.ws) + (size_t)blockIdx.x * A.ws_stride;
   C.vec.x = base;
@@ -466,6 +544,9 @@ __global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ A
   C.vec = Vecs<R>{nullptr, nullptr, nullptr, nullptr, nullptr};
   C.pcsrc = C.pcs = nullptr;
   C.r32 = nullptr;
+  C.rhs = nullptr;
+  C.rhs_ld = C.rhs_c0 = 0;
+  C.rhs_nc = 0;
   const int tid = threadIdx.x;
   if (tid < cw) {
     S.energy[tid] = A.energy;

@@ -23,7 +23,24 @@ struct SweepCtx {
   cx<R>* pcsrc;          // IN_PC source (preconditioned vector)
   cx<R>* pcs;            // OUT_TS: s for the (t, s) product
   cx<float>* r32;        // OUT_RES32 destination (FP32 copy of the FP64 residual)
+  // dense right-hand side: column c of the block is rhs[gi*rhs_ld + rhs_c0 + c]
+  // (null: the point source bsc e_src of the column)
+  const double2* rhs;
+  long long rhs_ld;
+  long long rhs_c0;
+  int rhs_nc;            // valid columns of the block
 };
+
+// Right-hand side b(gi) of column c.
+template <class R>
+__device__ __forceinline__ cx<R> rhs_at(const SweepCtx<R>& C, long long gi, int c) {
+  if (C.rhs) {
+    if (c >= C.rhs_nc) return mkc<R>((R)0, (R)0);
+    const double2 v = C.rhs[gi * C.rhs_ld + C.rhs_c0 + c];
+    return mkc<R>((R)v.x, (R)v.y);
+  }
+  return (gi == C.S->src[c]) ? mkc<R>((R)C.S->bsc[c], (R)0) : mkc<R>((R)0, (R)0);
+}
 
 template <int Q>
 __device__ __forceinline__ Pos<Q> make_pos(const Geo& g, int cw, int rad) {
@@ -60,7 +77,7 @@ __device__ __forceinline__ cx<R> load_in(const SweepCtx<R>& C, int mode, int zl,
   ColState* S = C.S;
   switch (mode) {
     case IN_INIT: {
-      const cx<R> u = (gi == S->src[c]) ? mkc<R>((R)S->bsc[c], (R)0) : mkc<R>((R)0, (R)0);
+      const cx<R> u = rhs_at<R>(C, gi, c);
       stv(&C.vec.x[off], mkc<R>((R)0, (R)0));
       stv(&C.vec.r[off], u);
       stv(&C.vec.p[off], u);
@@ -146,8 +163,7 @@ __device__ __forceinline__ void store_out(const SweepCtx<R>& C, int mode, long l
       break;
     }
     case OUT_RES: {
-      cx<R> rr = mkc<R>(-y.x, -y.y);
-      if (gi == src) rr.x += (R)bsc;
+      const cx<R> rr = rhs_at<R>(C, gi, c) - y;
       stv(&C.vec.r[off], rr);
       const double n2 = (double)cnorm2(rr);
       dots[0] += n2;

@@ -27,7 +27,7 @@ EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error",
             "rst_transmission", "rst_apply_h", "rst_solve_columns", "rst_batch_clear",
             "rst_batch_add", "rst_batch_run", "rst_cnn_weight_count", "rst_cnn_seed",
             "rst_cnn_set_weights", "rst_cnn_get_weights", "rst_cnn_forward", "rst_cnn_gradient",
-            "rst_cnn_train_step", "rst_precond_train"]
+            "rst_cnn_train_step", "rst_precond_train", "rst_solve_rhs"]
 
 
 class rst_solver_opts(C.Structure):
@@ -119,6 +119,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.rst_batch_add.argtypes = [P, C.POINTER(rst_problem)]
     lib.rst_batch_run.argtypes = [P, P, C.POINTER(rst_stats)]
     lib.rst_cnn_weight_count.argtypes = []
+    lib.rst_solve_rhs.argtypes = [P, C.c_int, P, C.c_int, P, C.c_int64, P, C.POINTER(rst_stats)]
     lib.rst_precond_train.argtypes = [P, C.POINTER(rst_train_opts), C.POINTER(rst_train_stats)]
     lib.rst_cnn_seed.argtypes = [P, C.c_uint64]
     lib.rst_cnn_set_weights.argtypes = [P, P, C.c_int64]
@@ -236,6 +237,14 @@ class Context:
                                                  C.c_void_p(x_dev_ptr), C.byref(st)), allow_noconv=True)
         return st.as_dict(), s
 
+    def rst_solve_rhs(self, energies, ncol, rhs_dev_ptr: int, rhs_estride: int, x_dev_ptr: int):
+        e = np.ascontiguousarray(np.atleast_1d(energies), np.float64)
+        st = rst_stats()
+        s = self._chk(self.lib.rst_solve_rhs(self.h, e.size, _ptr(e), int(ncol), C.c_void_p(rhs_dev_ptr),
+                                             int(rhs_estride), C.c_void_p(x_dev_ptr), C.byref(st)),
+                      allow_noconv=True)
+        return st.as_dict(), s
+
     # -- batches
     def rst_batch_clear(self):
         self._batch_ne = 0
@@ -351,3 +360,17 @@ def cnn_train_step(ctx: Context, x, tgt, lr):
     torch.cuda.synchronize()
     return ctx.rst_cnn_train_step(x.data_ptr(), tgt.data_ptr(), x.shape[0], x.shape[1], x.shape[2],
                                   x.shape[3], lr)
+
+
+def solve_rhs(ctx: Context, energies, b, per_energy=False):
+    """x = G(E) b for a torch complex128 CUDA tensor b of shape (n, ncol) (the same
+    right-hand sides for every energy) or (n, n_e*ncol) with per_energy; returns
+    x of shape (n, n_e*ncol), column e*ncol + j for energy e."""
+    import torch
+    e = np.atleast_1d(np.asarray(energies, np.float64))
+    assert b.is_cuda and b.dtype == torch.complex128 and b.is_contiguous()
+    ncol = b.shape[1] // (e.size if per_energy else 1)
+    x = torch.zeros((b.shape[0], e.size * ncol), dtype=torch.complex128, device=b.device)
+    torch.cuda.synchronize()
+    st, s = ctx.rst_solve_rhs(e, ncol, b.data_ptr(), ncol if per_energy else 0, x.data_ptr())
+    return x, st, s
