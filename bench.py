@@ -191,6 +191,33 @@ def learned_comparison(prob, ncols=32, pairs=4000, tol=1e-8):
             "solvers": res}
 
 
+def lowrank_comparison(prob, k, e_ref, t_ref, n_e=16):
+    """Low-rank transmission on the same slab and k: a randomised range finder
+    over the CAP blocks (probes + held-out solves, then adjoint solves at -k)
+    instead of one solve per right-CAP column.  n_e energies (the timed step's
+    energy among them) in one call; T at the step's energy is compared with the
+    full-column FP64 value."""
+    from paper_2208_02783_amd import rst
+    es = np.unique(np.concatenate([[e_ref], prob.energies[np.linspace(0, len(prob.energies) - 1, n_e - 1)
+                                                           .round().astype(int)]]))
+    ctx = rst.Context(0)
+    ctx.load_problem(prob, k)
+    ctx.rst_set_solver(precond=1, tol=1e-10, max_iter=20000)
+    t0 = time.perf_counter()
+    t, terr, st, s = ctx.rst_transmission_lowrank(es, probes=16, heldout=8, tail_tol=1e-7)
+    wall = time.perf_counter() - t0
+    i = int(np.argmin(np.abs(es - e_ref)))
+    ok = int(np.sum(terr <= 1e-7)) if s in (rst.RST_OK, rst.RST_ENOCONV) else 0
+    print(f"low-rank: {len(es)} points in {wall:.1f} s ({ok / wall:.2f} pts/s), {st['columns']} solves, "
+          f"|dT| at the step point {abs(t[i] - t_ref):.2e}", file=sys.stderr, flush=True)
+    return {"workload": f"same slab and k, {len(es)} energies in one call, probes 16 + 8 held out, doubling "
+                        f"while the tail estimate exceeds 1e-7",
+            "points_per_s": ok / wall, "status": int(s), "solves": st["columns"],
+            "solves_full_column_equivalent": len(es) * prob.r_columns().size,
+            "max_tail_estimate": float(np.max(terr)), "abs_dT_vs_full_column_fp64": float(abs(t[i] - t_ref)),
+            "iterations_per_solve": st["iterations_total"] / max(st["columns"], 1), "kernel_ms": st["kernel_ms"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +231,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the plain-vs-batched comparison")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision point")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
+    ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank transmission comparison")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="before the run, copy this many GiB device-to-device (a reference "
                          "kernel of known traffic for hardware-counter scaling)")
@@ -301,6 +329,8 @@ def main():
         line["mixed"] = mixed_point(prob, res[0][3], res[0][4], res[0][0])
     if not args.no_learned:
         line["learned"] = learned_comparison(prob)
+    if not args.no_lowrank and args.precision == "fp64":
+        line["lowrank"] = lowrank_comparison(prob, res[0][3], res[0][4], res[0][0])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

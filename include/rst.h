@@ -194,6 +194,28 @@ rst_status rst_solve_columns(rst_ctx *ctx, double energy, int ncol, const int64_
 rst_status rst_solve_rhs(rst_ctx *ctx, int n_e, const double *energies, int ncol, const void *rhs_dev,
                          int64_t rhs_estride, void *x_dev, rst_stats *stats);
 
+/* Low-rank transmission: T = 4 ||M||_F^2 with M = Gamma_L^1/2 G Gamma_R^1/2 on the
+ * left-CAP rows and right-CAP columns (the transmission equation written as a
+ * Frobenius norm), by a randomised range finder instead of one solve per
+ * right-CAP column: Y = M Omega from probes + heldout solves with complex
+ * Gaussian right-hand sides on the right CAP; Q = orth(first probes columns of Y)
+ * (Cholesky QR twice); T = 4 ||Q^H M||_F^2 from probes solves at -k
+ * (G_k^H = conj(G_{-k})).  T_err[e] = 4 mean ||(I - QQ^H) y||^2 over the held-out
+ * probes, an estimate of the neglected part (T_true = T + neglected >= T); while
+ * it exceeds tail_tol the probe count doubles (up to max_probes).  Returns
+ * RST_ENOCONV when a solve missed the tolerance or an energy ended above tail_tol.
+ * FP64 BiCGSTAB, direction LR. */
+typedef struct {
+  int probes;        /* initial probe count s (default 32) */
+  int heldout;       /* held-out probes p for the tail estimate (default 8) */
+  int max_probes;    /* largest s (default 256) */
+  double tail_tol;   /* accepted 4 ||(I - QQ^H) M||_F^2 estimate (default 1e-7) */
+  uint64_t seed;
+} rst_lowrank_opts;
+void rst_default_lowrank(rst_lowrank_opts *opts);
+rst_status rst_transmission_lowrank(rst_ctx *ctx, int n_e, const double *energies, const rst_lowrank_opts *opts,
+                                    double *T_out, double *T_err, rst_stats *stats);
+
 /* Batched transmission (paper Appendix: the (k, spin) calculations are
  * independent; here every (structure, energy, column block) is a work item of
  * one persistent launch).  rst_batch_clear empties the batch; rst_batch_add

@@ -15,6 +15,7 @@
 #include "../../include/rst.h"
 #include "rst_cnn_api.hpp"
 #include "rst_fgmres.hpp"
+#include "rst_lowrank.hpp"
 #include "rst_mixed.hpp"
 
 using rst::cx;
@@ -103,6 +104,8 @@ struct rst_ctx {
   DevBuf d_pc_eps, d_pc_twa, d_pc_twb;
   DevBuf d_grp_pbase, d_grp_nm, d_ekb, d_beta, d_eph, d_ent_p, d_zc, d_chunks, d_zg, d_zgroups,
       d_pe_offs, d_pe, d_sc_pb, d_sc_eph, d_sc_beta, d_g_ent_p, d_g_eph, d_g_beta;
+  // low-rank transmission buffers
+  DevBuf d_lrB, d_lrX, d_lrY, d_lrQ, d_lrQ2, d_lrG, d_lrR, d_lrW, d_lrL, d_lrRc, d_lrT;
   // solver
   rst_solver_opts opts;
   // work buffers (grown on demand)
@@ -2154,6 +2157,203 @@ rst_status rst_precond_train(rst_ctx* c, const rst_train_opts* o, rst_train_stat
     ts->ms = fms;
   }
   return RST_OK;
+}
+
+static rst_status lr_solve(rst_ctx* c, int ne, const double* E, int ncol, const double2* rhs, long long estride,
+                           double2* x, rst_stats& acc) {
+  std::vector<int64_t> cols(ncol, 0);
+  std::vector<double> Tcol, res;
+  std::vector<int> its, rss, stv;
+  double ms = 0;
+  const long long ld = estride ? (long long)ne * ncol : ncol;
+  rst_status s = run_solver(c, ne, E, cols, nullptr, nullptr, x, Tcol, its, rss, res, stv, ms, rhs, ld, estride);
+  if (s != RST_OK) return s;
+  int nbad = 0;
+  rst_stats st;
+  fill_stats(c, &st, its, rss, res, stv, ms, nbad, c->last_cw, c->last_threads);
+  acc.columns += st.columns;
+  acc.columns_unconverged += st.columns_unconverged;
+  acc.iterations_total += st.iterations_total;
+  acc.iterations_max = std::max(acc.iterations_max, st.iterations_max);
+  acc.restarts_total += st.restarts_total;
+  acc.max_rel_residual = std::max(acc.max_rel_residual, st.max_rel_residual);
+  acc.kernel_ms += st.kernel_ms;
+  acc.bytes_algorithmic += st.bytes_algorithmic;
+  acc.col_block = st.col_block;
+  acc.threads = st.threads;
+  return RST_OK;
+}
+
+void rst_default_lowrank(rst_lowrank_opts* o) {
+  if (!o) return;
+  o->probes = 32;
+  o->heldout = 8;
+  o->max_probes = 256;
+  o->tail_tol = 1e-7;
+  o->seed = 0x5eed;
+}
+
+rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const rst_lowrank_opts* o, double* T_out,
+                                    double* T_err, rst_stats* stats) {
+  rst_status s = check_ready(c);
+  if (s != RST_OK) return s;
+  if (!o || n_e < 0 || (n_e > 0 && (!E || !T_out))) return fail(c, RST_EINVAL, "bad low-rank arguments");
+  if (o->probes < 1 || o->heldout < 1 || o->max_probes < o->probes || !(o->tail_tol > 0))
+    return fail(c, RST_EINVAL, "bad low-rank options");
+  for (int i = 0; i < n_e; ++i)
+    if (!std::isfinite(E[i])) return fail(c, RST_EINVAL, "non-finite energy");
+  if (c->opts.method != RST_BICGSTAB || c->opts.precision != RST_FP64 || c->opts.direction != RST_DIR_LR)
+    return fail(c, RST_EUNSUPPORTED, "the low-rank transmission uses FP64 BiCGSTAB, direction LR");
+  if (n_e == 0) return RST_OK;
+  hipSetDevice(c->device);
+  const int P = c->na * c->nb;
+  const long long n = (long long)P * c->nz;
+  std::vector<long long> Lh, Rh;
+  for (int z = 0; z < c->nz; ++z)
+    for (int p = 0; p < P; ++p) {
+      if (c->gl[z] > 0) Lh.push_back((long long)z * P + p);
+      if (c->gr[z] > 0) Rh.push_back((long long)z * P + p);
+    }
+  rst_stats acc;
+  std::memset(&acc, 0, sizeof(acc));
+  if (Lh.empty() || Rh.empty()) {
+    for (int i = 0; i < n_e; ++i) {
+      T_out[i] = 0.0;
+      if (T_err) T_err[i] = 0.0;
+    }
+    if (stats) *stats = acc;
+    return RST_OK;
+  }
+  const int nL = (int)Lh.size(), nR = (int)Rh.size();
+  if ((s = upload(c, c->d_lrL, Lh)) != RST_OK) return s;
+  if ((s = upload(c, c->d_lrRc, Rh)) != RST_OK) return s;
+  const double* d_gl = (const double*)c->d_gl.p;
+  const double* d_gr = (const double*)c->d_gr.p;
+  const long long* dL = (const long long*)c->d_lrL.p;
+  const long long* dR = (const long long*)c->d_lrRc.p;
+  std::vector<int> done(n_e, 0);
+  std::vector<double> Tq(n_e, 0.0), tail(n_e, 0.0);
+  int sprobe = std::min(o->probes, nR);
+  const int hp = o->heldout;
+  uint64_t seed = o->seed;
+  const double ka0 = c->ka, kb0 = c->kb;
+  for (;;) {
+    // energies still open
+    std::vector<double> Eo;
+    std::vector<int> idx;
+    for (int i = 0; i < n_e; ++i)
+      if (!done[i]) {
+        Eo.push_back(E[i]);
+        idx.push_back(i);
+      }
+    const int ne = (int)Eo.size();
+    const int sc = sprobe + hp;
+    // (1) probes and forward solves
+    if ((s = ensure(c, c->d_lrB, (size_t)n * sc * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_lrX, (size_t)n * ne * sc * 16)) != RST_OK) return s;
+    hipLaunchKernelGGL(rst::lr::k_lr_probes, dim3((unsigned)((n * sc + 255) / 256)), dim3(256), 0, c->stream, n, P, sc,
+                       d_gr, (unsigned long long)seed, (double2*)c->d_lrB.p);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemsetAsync(c->d_lrX.p, 0, (size_t)n * ne * sc * 16, c->stream));
+    if ((s = lr_solve(c, ne, Eo.data(), sc, (const double2*)c->d_lrB.p, 0, (double2*)c->d_lrX.p, acc)) != RST_OK)
+      return s;
+    // (2) Y = Gamma_L^1/2 X on the left CAP; Q = orth(Y[:, :s]) by Cholesky QR twice
+    const size_t ylen = (size_t)ne * sc * nL;
+    if ((s = ensure(c, c->d_lrY, ylen * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_lrQ, (size_t)ne * sprobe * nL * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_lrQ2, (size_t)ne * sprobe * nL * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_lrG, (size_t)ne * sc * sc * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_lrR, (size_t)ne * sprobe * sprobe * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_lrW, (size_t)ne * sprobe * sprobe * 16)) != RST_OK) return s;
+    hipLaunchKernelGGL(rst::lr::k_lr_gather_left, dim3((unsigned)((ylen + 255) / 256)), dim3(256), 0, c->stream,
+                       (const double2*)c->d_lrX.p, ne, sc, dL, nL, P, d_gl, (double2*)c->d_lrY.p);
+    const double2* Y = (const double2*)c->d_lrY.p;
+    double2* Q = (double2*)c->d_lrQ.p;
+    double2* Q2 = (double2*)c->d_lrQ2.p;
+    const long long sy = (long long)sc * nL, sq = (long long)sprobe * nL;
+    const unsigned gq = (unsigned)(((size_t)ne * sprobe * nL + 255) / 256);
+    for (int pass = 0; pass < 2; ++pass) {
+      const double2* src = pass == 0 ? Y : Q;
+      const long long ss = pass == 0 ? sy : sq;
+      double2* dst = pass == 0 ? Q : Q2;
+      hipLaunchKernelGGL(rst::lr::k_lr_gram, dim3(sprobe, sprobe, ne), dim3(256), 0, c->stream, src, ss, src, ss, nL,
+                         sprobe, sprobe, (double2*)c->d_lrG.p);
+      hipLaunchKernelGGL(rst::lr::k_lr_chol_inv, dim3((ne + 63) / 64), dim3(64), 0, c->stream,
+                         (const double2*)c->d_lrG.p, sprobe, ne, (double2*)c->d_lrR.p, (double2*)c->d_lrW.p);
+      hipLaunchKernelGGL(rst::lr::k_lr_right_mul, dim3(gq), dim3(256), 0, c->stream, src, ss,
+                         (const double2*)c->d_lrW.p, sprobe, nL, ne, dst);
+      HIPCHK(c, hipGetLastError());
+    }
+    // (3) tail of the held-out probes: ||y||^2 - ||Q^H y||^2
+    const double2* Yh = Y + (long long)sprobe * nL;
+    std::vector<double2> cq((size_t)ne * sprobe * hp), yy((size_t)ne * hp * hp);
+    hipLaunchKernelGGL(rst::lr::k_lr_gram, dim3(sprobe, hp, ne), dim3(256), 0, c->stream, (const double2*)Q2, sq, Yh,
+                       sy, nL, sprobe, hp, (double2*)c->d_lrG.p);
+    HIPCHK(c, hipMemcpyAsync(cq.data(), c->d_lrG.p, cq.size() * 16, hipMemcpyDeviceToHost, c->stream));
+    hipLaunchKernelGGL(rst::lr::k_lr_gram, dim3(hp, hp, ne), dim3(256), 0, c->stream, Yh, sy, Yh, sy, nL, hp, hp,
+                       (double2*)c->d_lrG.p);
+    HIPCHK(c, hipMemcpyAsync(yy.data(), c->d_lrG.p, yy.size() * 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<double> tl(ne, 0.0);
+    for (int e = 0; e < ne; ++e) {
+      double t = 0.0;
+      for (int b = 0; b < hp; ++b) {
+        double r = yy[((size_t)e * hp + b) * hp + b].x;
+        for (int a = 0; a < sprobe; ++a) {
+          const double2 v = cq[((size_t)e * sprobe + a) * hp + b];
+          r -= v.x * v.x + v.y * v.y;
+        }
+        t += std::max(r, 0.0);
+      }
+      tl[e] = t / hp;
+    }
+    // (4) adjoint solves at -k: Z = G_{-k} Gamma_L^1/2 conj(Q); T_Q = 4 ||Gamma_R^1/2 Z|_R||_F^2
+    if ((s = ensure(c, c->d_lrB, (size_t)n * ne * sprobe * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_lrX, (size_t)n * ne * sprobe * 16)) != RST_OK) return s;
+    HIPCHK(c, hipMemsetAsync(c->d_lrB.p, 0, (size_t)n * ne * sprobe * 16, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_lrX.p, 0, (size_t)n * ne * sprobe * 16, c->stream));
+    hipLaunchKernelGGL(rst::lr::k_lr_adjoint_rhs, dim3(gq), dim3(256), 0, c->stream, (const double2*)Q2, ne, sprobe, dL,
+                       nL, P, d_gl, n, (double2*)c->d_lrB.p);
+    HIPCHK(c, hipGetLastError());
+    c->ka = -ka0;
+    c->kb = -kb0;
+    if ((s = upload_k(c)) != RST_OK) return s;
+    if ((s = upload_pc(c)) != RST_OK) return s;
+    s = lr_solve(c, ne, Eo.data(), sprobe, (const double2*)c->d_lrB.p, sprobe, (double2*)c->d_lrX.p, acc);
+    c->ka = ka0;
+    c->kb = kb0;
+    rst_status s2 = upload_k(c);
+    if (s2 == RST_OK) s2 = upload_pc(c);
+    if (s != RST_OK) return s;
+    if (s2 != RST_OK) return s2;
+    if ((s = ensure(c, c->d_lrT, (size_t)ne * 8)) != RST_OK) return s;
+    hipLaunchKernelGGL(rst::lr::k_lr_tq, dim3(ne), dim3(256), 0, c->stream, (const double2*)c->d_lrX.p, ne, sprobe, dR,
+                       nR, P, d_gr, (double*)c->d_lrT.p);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> tq(ne);
+    HIPCHK(c, hipMemcpyAsync(tq.data(), c->d_lrT.p, (size_t)ne * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool more = false;
+    for (int e = 0; e < ne; ++e) {
+      Tq[idx[e]] = tq[e];
+      tail[idx[e]] = 4.0 * tl[e];
+      if (4.0 * tl[e] <= o->tail_tol || sprobe >= std::min(o->max_probes, nR))
+        done[idx[e]] = 1;
+      else
+        more = true;
+    }
+    if (!more) break;
+    sprobe = std::min(2 * sprobe, std::min(o->max_probes, nR));
+    seed = seed * 0x9E3779B97F4A7C15ULL + 1;
+  }
+  bool within = true;
+  for (int i = 0; i < n_e; ++i) {
+    T_out[i] = Tq[i];
+    if (T_err) T_err[i] = tail[i];
+    within = within && tail[i] <= o->tail_tol;
+  }
+  if (stats) *stats = acc;
+  return (acc.columns_unconverged || !within) ? RST_ENOCONV : RST_OK;
 }
 
 }  // extern "C"

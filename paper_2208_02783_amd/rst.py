@@ -27,7 +27,8 @@ EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error",
             "rst_transmission", "rst_apply_h", "rst_solve_columns", "rst_batch_clear",
             "rst_batch_add", "rst_batch_run", "rst_cnn_weight_count", "rst_cnn_seed",
             "rst_cnn_set_weights", "rst_cnn_get_weights", "rst_cnn_forward", "rst_cnn_gradient",
-            "rst_cnn_train_step", "rst_precond_train", "rst_solve_rhs"]
+            "rst_cnn_train_step", "rst_precond_train", "rst_solve_rhs", "rst_default_lowrank",
+            "rst_transmission_lowrank"]
 
 
 class rst_solver_opts(C.Structure):
@@ -60,6 +61,11 @@ class rst_train_stats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rst_lowrank_opts(C.Structure):
+    _fields_ = [("probes", C.c_int), ("heldout", C.c_int), ("max_probes", C.c_int), ("tail_tol", C.c_double),
+                ("seed", C.c_uint64)]
 
 
 class rst_problem(C.Structure):
@@ -120,6 +126,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.rst_batch_run.argtypes = [P, P, C.POINTER(rst_stats)]
     lib.rst_cnn_weight_count.argtypes = []
     lib.rst_solve_rhs.argtypes = [P, C.c_int, P, C.c_int, P, C.c_int64, P, C.POINTER(rst_stats)]
+    lib.rst_default_lowrank.argtypes = [C.POINTER(rst_lowrank_opts)]
+    lib.rst_transmission_lowrank.argtypes = [P, C.c_int, P, C.POINTER(rst_lowrank_opts), P, P,
+                                             C.POINTER(rst_stats)]
     lib.rst_precond_train.argtypes = [P, C.POINTER(rst_train_opts), C.POINTER(rst_train_stats)]
     lib.rst_cnn_seed.argtypes = [P, C.c_uint64]
     lib.rst_cnn_set_weights.argtypes = [P, P, C.c_int64]
@@ -129,9 +138,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.rst_cnn_train_step.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P, P, C.c_float,
                                        C.POINTER(C.c_double)]
     for name in EXPORTED:
-        if name not in ("rst_default_solver", "rst_destroy", "rst_last_error"):
+        if name not in ("rst_default_solver", "rst_destroy", "rst_last_error", "rst_default_lowrank"):
             getattr(lib, name).restype = C.c_int
     lib.rst_cnn_weight_count.restype = C.c_int64
+    lib.rst_default_lowrank.restype = None
     _lib = lib
     return lib
 
@@ -244,6 +254,19 @@ class Context:
                                              int(rhs_estride), C.c_void_p(x_dev_ptr), C.byref(st)),
                       allow_noconv=True)
         return st.as_dict(), s
+
+    def rst_transmission_lowrank(self, energies, **kw):
+        e = np.ascontiguousarray(np.atleast_1d(energies), np.float64)
+        o = rst_lowrank_opts()
+        self.lib.rst_default_lowrank(C.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        t = np.zeros(e.size)
+        terr = np.zeros(e.size)
+        st = rst_stats()
+        s = self._chk(self.lib.rst_transmission_lowrank(self.h, e.size, _ptr(e), C.byref(o), _ptr(t), _ptr(terr),
+                                                        C.byref(st)), allow_noconv=True)
+        return t, terr, st.as_dict(), s
 
     # -- batches
     def rst_batch_clear(self):

@@ -370,3 +370,31 @@ def test_solve_rhs_matches_oracle(pc):
         ref = sla.solve(oracle.system_matrix(p, k, e), b2[:, 2 * ie:2 * ie + 2])
         err = np.linalg.norm(x2h[:, 2 * ie:2 * ie + 2] - ref) / np.linalg.norm(ref)
         assert err <= 1e-9, (ie, err)
+
+
+# ------------------------------------------------- low-rank transmission
+
+@pytest.mark.parametrize("cfg,pc", [(1, 1), (2, 1), (2, 0)])
+def test_lowrank_transmission_matches_oracle(cfg, pc):
+    """The randomised range finder over the CAP blocks gives T to the oracle's
+    1e-6 bar with far fewer solves than one per right-CAP column; its tail
+    estimate bounds the neglected part."""
+    torch = torch_cuda()
+    if cfg == 1:
+        g = json.load(open(os.path.join(GOLD, "config1_T.json")))
+        p = wl.config(1)
+        es = np.array(g["energies"][3::9])
+        ref = np.array(g["T_LR"][3::9])
+        k = (0.0, 0.0)
+    else:
+        p = wl.config(2, tiny=True)
+        k = p.kpts[1]
+        es = p.energies[[0, 3, 7]]
+        ref = oracle.transmission(p, es, k, both=False)["T_LR"]
+    ctx = make_ctx(torch, p, k, precond=pc, tol=1e-12)
+    t, terr, st, s = ctx.rst_transmission_lowrank(es, probes=16, heldout=8, tail_tol=1e-8)
+    _say("lowrank cfg", cfg, "T", t, "err", terr, "solves", st["columns"], "of", len(es) * p.r_columns().size)
+    assert s == rst.RST_OK
+    assert np.all(terr <= 1e-8)
+    np.testing.assert_allclose(t, ref, atol=1e-6, rtol=0)
+    assert np.all(t <= ref + 1e-9)  # T_Q is a lower bound up to solver error
