@@ -341,6 +341,7 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
   bool all_done = false;
   int it = 0;
   while (!all_done) {
+    if (!any_active(S, cw)) break;
     // every pass counts, breakdown passes included, so the loop is bounded
     if (it >= A.max_iter) {
       reliable_update<RAD, Q, PC>(A, C64, C32, pv, ps, PA, dst_, true, false, all_done);

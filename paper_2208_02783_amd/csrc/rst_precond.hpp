@@ -402,6 +402,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
   bool all_done = false;
   int it = 0;
   while (!all_done) {
+    if (!any_active(S, cw)) break;
     if (it >= A.max_iter) {
       pc_true_residual_and_restart<RAD, Q, R>(A, C, pv, ps, PA, K, dst_, true, all_done);
       break;

@@ -33,6 +33,17 @@ __device__ __forceinline__ void set_dco(const Proj& pj, int cw, cx<double>* dco,
   }
 }
 
+// True while some column of the block still iterates (state 0); a block whose
+// columns are all finished (e.g. every right-hand side zero) leaves its loop.
+__device__ __forceinline__ bool any_active(ColState& S, int cw) {
+  __syncthreads();
+  if (threadIdx.x == 0) S.upd_flag = 0;
+  __syncthreads();
+  if ((int)threadIdx.x < cw && S.state[threadIdx.x] == 0) atomicOr(&S.upd_flag, 1);
+  __syncthreads();
+  return S.upd_flag != 0;
+}
+
 // Dense right-hand side of an item: point C at the item's columns, then one
 // pass over b for ||b||^2, the shadow index j0 = argmax |b| (ties: smaller
 // index), rho = b[j0] and, when `acc` is given, the projections B^H b.
@@ -277,6 +288,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs& A, SweepCtx<R>& C, c
   bool all_done = false;
   int it = 0;
   while (!all_done) {
+    if (!any_active(S, cw)) break;
     // every pass counts, breakdown passes included, so the loop is bounded
     if (it >= A.max_iter) {
       true_residual_and_restart<RAD, Q, R>(A, C, ps, PA, true, all_done);
