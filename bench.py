@@ -191,7 +191,7 @@ def learned_comparison(prob, ncols=32, pairs=4000, tol=1e-8):
             "solvers": res}
 
 
-def lowrank_comparison(prob, k, e_ref, t_ref, n_e=16):
+def lowrank_comparison(prob, k, e_ref, t_ref, n_e=32):
     """Low-rank transmission on the same slab and k: a randomised range finder
     over the CAP blocks (probes + held-out solves, then adjoint solves at -k)
     instead of one solve per right-CAP column.  n_e energies (the timed step's

@@ -398,3 +398,27 @@ def test_lowrank_transmission_matches_oracle(cfg, pc):
     assert np.all(terr <= 1e-8)
     np.testing.assert_allclose(t, ref, atol=1e-6, rtol=0)
     assert np.all(t <= ref + 1e-9)  # T_Q is a lower bound up to solver error
+
+
+def test_lowrank_and_rhs_edge_cases():
+    """No right CAP: T = 0 with no solves; option errors; dense right-hand sides
+    need FP64 BiCGSTAB; a block of zero right-hand sides returns x = 0 at once."""
+    torch = torch_cuda()
+    p = wl.config(1)
+    ctx = make_ctx(torch, p, (0.0, 0.0), precond=1)
+    ctx.rst_set_abc(p.gamma_l, np.zeros_like(p.gamma_r))
+    t, terr, st, s = ctx.rst_transmission_lowrank(p.energies[:2])
+    assert s == rst.RST_OK and np.all(t == 0) and st["columns"] == 0
+    ctx.rst_set_abc(p.gamma_l, p.gamma_r)
+    with pytest.raises(RuntimeError, match="options"):
+        ctx.rst_transmission_lowrank(p.energies[:1], probes=0)
+    ctx.rst_set_solver(precision=rst.RST_FP32_REFINE)
+    with pytest.raises(RuntimeError, match="FP64"):
+        ctx.rst_transmission_lowrank(p.energies[:1])
+    b = torch.zeros((p.n, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(RuntimeError, match="FP64"):
+        rst.solve_rhs(ctx, p.energies[:1], b)
+    ctx.rst_set_solver(precond=1)
+    x, st, s = rst.solve_rhs(ctx, p.energies[:2], b)
+    assert s == rst.RST_OK and torch.count_nonzero(x).item() == 0
+    assert st["iterations_total"] == 0
