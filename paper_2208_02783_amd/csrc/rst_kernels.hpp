@@ -236,6 +236,7 @@ struct ApplyArgs {
   double2* pws;             // per-workgroup projection scratch (2 arrays nproj*cw)
   size_t pws_stride;
   int blocked;              // 1: x, y in blocked layout (block b: n x cw column-fastest at b*n*cw)
+  const double2* proj_pre;  // projections B^H x computed beforehand (nproj x ncol), or null
 };
 
 // ---------------------------------------------------------------------------

@@ -16,6 +16,7 @@
 #include "rst_cnn_api.hpp"
 #include "rst_fgmres.hpp"
 #include "rst_lowrank.hpp"
+#include "rst_projmm.hpp"
 #include "rst_mixed.hpp"
 
 using rst::cx;
@@ -104,6 +105,9 @@ struct rst_ctx {
   DevBuf d_pc_eps, d_pc_twa, d_pc_twb;
   DevBuf d_grp_pbase, d_grp_nm, d_ekb, d_beta, d_eph, d_ent_p, d_zc, d_chunks, d_zg, d_zgroups,
       d_pe_offs, d_pe, d_sc_pb, d_sc_eph, d_sc_beta, d_g_ent_p, d_g_eph, d_g_beta;
+  // batched projector gather (many-column apply): group entry ranges, entry grid indices, projections
+  std::vector<int> grp_e0, grp_ne;
+  DevBuf d_grp_e0, d_grp_ne, d_ent_gi, d_projP;
   // low-rank transmission buffers
   DevBuf d_lrB, d_lrX, d_lrY, d_lrQ, d_lrQ2, d_lrG, d_lrR, d_lrW, d_lrL, d_lrRc, d_lrT;
   // solver
@@ -267,6 +271,8 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
   c->nproj = nproj;
   c->grp_pbase.clear();
   c->grp_nm.clear();
+  c->grp_e0.clear();
+  c->grp_ne.clear();
   c->ekb.assign(ekb, ekb + nproj);
   // group detection
   std::vector<std::pair<int, int>> groups;  // (first proj, count)
@@ -306,6 +312,8 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
     });
     grp_e0.push_back((int)c->ent_p.size());
     grp_ne.push_back(len);
+    c->grp_e0.push_back((int)c->ent_p.size());
+    c->grp_ne.push_back(len);
     c->grp_pbase.push_back(p0);
     c->grp_nm.push_back(cnt);
     for (int e : ord) {
@@ -412,6 +420,9 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
   if ((s = upload(c, c->d_beta, c->beta)) != RST_OK) return s;
   if ((s = upload(c, c->d_ent_p, c->ent_p)) != RST_OK) return s;
   if ((s = upload(c, c->d_g_ent_p, c->g_ent_p)) != RST_OK) return s;
+  if ((s = upload(c, c->d_grp_e0, c->grp_e0)) != RST_OK) return s;
+  if ((s = upload(c, c->d_grp_ne, c->grp_ne)) != RST_OK) return s;
+  if ((s = upload(c, c->d_ent_gi, c->ent_gi)) != RST_OK) return s;
   if ((s = upload(c, c->d_g_beta, c->g_beta)) != RST_OK) return s;
   if ((s = upload(c, c->d_zc, c->zc_offs)) != RST_OK) return s;
   if ((s = upload(c, c->d_chunks, c->chunks)) != RST_OK) return s;
@@ -1874,6 +1885,28 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
   if ((s = ensure(c, c->d_pws, (size_t)A.nblk * pws_stride * 16)) != RST_OK) return s;
   A.pws = (double2*)c->d_pws.p;
   A.pws_stride = pws_stride;
+  if (c->nproj > 0) {
+    // all projections B^H x at once on the matrix cores; the stencil sweep then only scatters
+    if ((s = ensure(c, c->d_projP, (size_t)c->nproj * ncol * 16)) != RST_OK) return s;
+    rst::ProjMMArgs M;
+    M.X = (const double2*)x_dev;
+    M.P = (double2*)c->d_projP.p;
+    M.grp_e0 = (const int*)c->d_grp_e0.p;
+    M.grp_ne = (const int*)c->d_grp_ne.p;
+    M.grp_pbase = (const int*)c->d_grp_pbase.p;
+    M.grp_nm = (const int*)c->d_grp_nm.p;
+    M.ent_gi = (const int*)c->d_ent_gi.p;
+    M.eph = (const double2*)c->d_eph.p;
+    M.beta = (const double*)c->d_beta.p;
+    M.nm = c->nm;
+    M.ngroup = c->ngroup;
+    M.ncol = ncol;
+    M.h3 = c->ha * c->hb * c->hz;
+    const long long waves = (long long)c->ngroup * ((ncol + 63) / 64);
+    hipLaunchKernelGGL(rst::k_proj_mm, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, c->stream, M);
+    HIPCHK(c, hipGetLastError());
+    A.proj_pre = (const double2*)c->d_projP.p;
+  }
   const size_t lds =
       rst::lds_bytes<double>(A.g.pa, A.g.pb, A.g.P, A.pj.nproj, A.pj.max_chunks, A.pj.nm, ls.cw, ls.threads);
   int dev_lds = 0;

@@ -1,0 +1,87 @@
+// rst_projmm.hpp -- batched projector gather on FP64 matrix cores.
+//
+// For many columns X (n x ncol, column fastest) the projections of one group
+// of projectors sharing their sphere entries (one atom: 9 projectors, about a
+// thousand grid points) form a dense product
+//     P_g (nm x ncol) = h^3 * beta_g^T (nm x E_g) * Xt_g (E_g x ncol),
+//     Xt_g[e][c] = conj(exp(i k.R_e)) X[gi_e][c],
+// with real beta.  One wave computes a group for 64 columns with
+// v_mfma_f64_16x16x4f64 (M = 16 projector rows, nm <= 16 valid; N = 16
+// columns per block, four blocks; K = 4 entries per step), the real and the
+// imaginary part of Xt as two products sharing the beta operand.  Lane l holds
+// A element (row l%16, k = l/16), B element (k = l/16, column l%16) and the
+// accumulator D(row 4*r + l/16, column l%16), r = 0..3 (the FP64 layout,
+// measured on the device; it differs from the FP32 instruction's).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace rst {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+struct ProjMMArgs {
+  const double2* X;       // n x ncol
+  double2* P;             // nproj x ncol: P[p*ncol + c]
+  const int* grp_e0;      // [ngroup] first entry of the group (group-major entry order)
+  const int* grp_ne;      // [ngroup] entries of the group
+  const int* grp_pbase;   // [ngroup] first projector
+  const int* grp_nm;      // [ngroup] projectors
+  const int* ent_gi;      // [nent] grid index of the entry
+  const double2* eph;     // [nent] exp(+i k.R_e)
+  const double* beta;     // [nent*nm] beta[e*nm + m]
+  int nm, ngroup, ncol;
+  double h3;
+};
+
+__global__ __launch_bounds__(256) void k_proj_mm(ProjMMArgs A) {
+  const int lane = threadIdx.x & 63;
+  const long long w = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int ntile = (A.ncol + 63) / 64;
+  if (w >= (long long)A.ngroup * ntile) return;  // whole wave exits together
+  const int g = (int)(w / ntile);
+  const int c0 = (int)(w % ntile) * 64;
+  const int e0 = A.grp_e0[g], ne = A.grp_ne[g], nmg = A.grp_nm[g];
+  const int i16 = lane & 15, kq = lane >> 4;
+  v4d re[4], im[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    re[b] = v4d{0.0, 0.0, 0.0, 0.0};
+    im[b] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  for (int k0 = 0; k0 < ne; k0 += 4) {
+    const int k = k0 + kq;
+    double a = 0.0;
+    double2 ph = make_double2(0.0, 0.0);
+    long long gi = 0;
+    if (k < ne) {
+      const int e = e0 + k;
+      if (i16 < nmg) a = A.beta[(size_t)e * A.nm + i16];
+      ph = A.eph[e];
+      gi = A.ent_gi[e];
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int col = c0 + 16 * b + i16;
+      double xr = 0.0, xi = 0.0;
+      if (k < ne && col < A.ncol) {
+        const double2 x = A.X[gi * A.ncol + col];
+        xr = ph.x * x.x + ph.y * x.y;  // conj(ph) * x
+        xi = ph.x * x.y - ph.y * x.x;
+      }
+      re[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xr, re[b], 0, 0, 0);
+      im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xi, im[b], 0, 0, 0);
+    }
+  }
+  const int pb = A.grp_pbase[g];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int col = c0 + 16 * b + i16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 4 * r + kq;
+      if (m < nmg && col < A.ncol) A.P[(size_t)(pb + m) * A.ncol + col] = make_double2(A.h3 * re[b][r], A.h3 * im[b][r]);
+    }
+  }
+}
+
+}  // namespace rst

@@ -573,7 +573,14 @@ __global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ A
   __syncthreads();
   const Pos<Q> ps = make_pos<Q>(A.g, cw, RAD);
   double tacc = 0;
-  if (A.pj.nproj) {
+  if (A.pj.nproj && A.proj_pre && !A.blocked) {
+    for (int w = tid; w < (int)np; w += blockDim.x) {
+      const int col = blockIdx.x * cw + w % cw;
+      const double2 v = col < A.ncol ? A.proj_pre[(size_t)(w / cw) * A.ncol + col] : make_double2(0.0, 0.0);
+      Px[w] = mkc(v.x, v.y);
+    }
+    __syncthreads();
+  } else if (A.pj.nproj) {
     C.acc = Px;
     gather_sweep<Q, R, true>(C, ps, nullptr, tacc);
   }
