@@ -224,6 +224,56 @@ def lowrank_comparison(prob, k, e_ref, t_ref, n_e=32):
             "iterations_per_solve": st["iterations_total"] / max(st["columns"], 1), "kernel_ms": st["kernel_ms"]}
 
 
+def stencil_apply(prob, k, e, ncol=1024, reps=5):
+    """Stand-alone y = (E - H_k + i Gamma) x on ncol random columns of the slab
+    (FD Laplacian with Bloch-phase lateral wraps, V, CAP, KB projectors), in the
+    two layouts the library takes: column-fastest (n x ncol; the projector
+    gather B^H x runs first on the FP64 matrix cores, then the stencil sweep)
+    and blocked (the solvers' layout: each block of col_block columns
+    contiguous, one workgroup streaming z through it, gather fused into the
+    sweep).  Kernel times from HIP events on the library's stream; algorithmic
+    bytes = read x and write y, 32 B per point per column (V and the projector
+    tables, a few MB read once per launch, are not counted)."""
+    import torch
+    from paper_2208_02783_amd import rst
+    ctx = rst.Context(0)
+    ctx.load_problem(prob, k)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    x = torch.randn((prob.n, ncol), dtype=torch.complex128, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    alg = 32.0 * prob.n * ncol
+
+    def timed(call):
+        call()  # first call sizes the buffers
+        pm, sm = [], []
+        for _ in range(reps):
+            call()
+            a, b = ctx.rst_apply_timing()
+            pm.append(a)
+            sm.append(b)
+        return float(np.mean(pm)), float(np.mean(sm))
+
+    pm, sm = timed(lambda: ctx.rst_apply_h(e, x.data_ptr(), y.data_ptr(), ncol))
+    cw = ctx.rst_apply_block_width()
+    xb = rst.to_blocked(x, cw)
+    yb = torch.empty_like(xb)
+    _, bm = timed(lambda: ctx.rst_apply_h_blocked(e, xb.data_ptr(), yb.data_ptr(), ncol, cw))
+    dif = (torch.max(torch.abs(rst.from_blocked(yb) - y)) / torch.max(torch.abs(y))).item()
+    gbs = alg / ((pm + sm) * 1e-3) / 1e9
+    gbb = alg / (bm * 1e-3) / 1e9
+    print(f"stencil apply, {ncol} columns: column-fastest gather {pm:.3f} ms + sweep {sm:.3f} ms -> "
+          f"{gbs:.0f} GB/s; blocked ({cw} columns per block) {bm:.3f} ms -> {gbb:.0f} GB/s; "
+          f"max rel difference {dif:.1e}", file=sys.stderr, flush=True)
+    del x, y, xb, yb
+    return {"workload": f"config-2 slab, {ncol} random columns, one apply of E - H_k + i Gamma",
+            "columns": ncol, "algorithmic_bytes": alg,
+            "column_fastest": {"projector_gather_ms": pm, "stencil_sweep_ms": sm, "achieved_GBps": gbs,
+                               "frac_of_hbm_peak": gbs / PEAK_HBM_GBS},
+            "blocked": {"col_block": cw, "kernel_ms": bm, "achieved_GBps": gbb,
+                        "frac_of_hbm_peak": gbb / PEAK_HBM_GBS},
+            "max_rel_difference_between_layouts": dif}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +288,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision point")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank transmission comparison")
+    ap.add_argument("--no-stencil", action="store_true", help="skip the stand-alone operator apply")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="before the run, copy this many GiB device-to-device (a reference "
                          "kernel of known traffic for hardware-counter scaling)")
@@ -329,6 +380,8 @@ def main():
                         if args.precision == "fp64" else None),
         },
     }
+    if not args.no_stencil:
+        line["stencil"] = stencil_apply(prob, res[0][3], res[0][4])
     if not args.no_batched:
         line["batched"] = batched_comparison()
     if not args.no_mixed and args.precision == "fp64":

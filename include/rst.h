@@ -179,6 +179,32 @@ rst_status rst_transmission(rst_ctx *ctx, int n_e, const double *energies, doubl
  * x_dev and y_dev are distinct device buffers of n*ncol*16 bytes. */
 rst_status rst_apply_h(rst_ctx *ctx, double energy, const void *x_dev, void *y_dev, int ncol);
 
+/* Widest column block the blocked apply supports on the current grid (a power
+ * of two <= 8: a lateral plane of col_block columns must fit one workgroup at
+ * two positions per thread, its padded copy the LDS).  RST_ESTATE before the
+ * problem is set. */
+rst_status rst_apply_block_width(rst_ctx *ctx, int *col_block);
+
+/* y = (E - H_k + i Gamma) x in the blocked layout the solvers keep their
+ * vectors in: ncol columns in ncol/col_block blocks of col_block columns; block
+ * j occupies elements [j*n*col_block, (j+1)*n*col_block) and holds column
+ * j*col_block + c of grid point gi at j*n*col_block + gi*col_block + c
+ * (complex128, device).  One workgroup streams z through each block, the
+ * projector gather B^H x included (the operator of the transmission equation's
+ * G, with H_k the FD Laplacian with Bloch-phase lateral wraps, V and the KB
+ * projectors).  RST_EINVAL if ncol is not a multiple of col_block, col_block is
+ * not a power of two <= 8 or x == y; RST_EUNSUPPORTED if col_block exceeds
+ * rst_apply_block_width. */
+rst_status rst_apply_h_blocked(rst_ctx *ctx, double energy, const void *x_dev, void *y_dev, int ncol,
+                               int col_block);
+
+/* Kernel durations of the last rst_apply_h or rst_apply_h_blocked on this context, measured with HIP
+ * events on the context's stream: the separate projector gather B^H x (0
+ * without projectors and for the blocked apply, whose sweep gathers itself) and
+ * the stencil sweep.
+ * Both 0 before the first apply.  RST_EINVAL for a null argument. */
+rst_status rst_apply_timing(const rst_ctx *ctx, double *proj_ms, double *stencil_ms);
+
 /* Green's function columns: x_dev[:, j] = G e_{col[j]} (complex128, n x ncol,
  * device).  col holds ncol grid indices (host). */
 rst_status rst_solve_columns(rst_ctx *ctx, double energy, int ncol, const int64_t *col,

@@ -75,6 +75,8 @@ struct rst_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
+  hipEvent_t ev_apply[3] = {nullptr, nullptr, nullptr};  // apply timing (created on first use)
+  double apply_ms[2] = {0.0, 0.0};                      // last apply: projector gather, stencil sweep
 
   // grid
   bool has_grid = false;
@@ -1603,6 +1605,8 @@ void rst_destroy(rst_ctx* c) {
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
   if (c->gexec) hipGraphExecDestroy(c->gexec);
+  for (hipEvent_t& e : c->ev_apply)
+    if (e) hipEventDestroy(e);
   rst::cnn::engine_destroy(c->cnn);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
@@ -1885,6 +1889,9 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
   if ((s = ensure(c, c->d_pws, (size_t)A.nblk * pws_stride * 16)) != RST_OK) return s;
   A.pws = (double2*)c->d_pws.p;
   A.pws_stride = pws_stride;
+  for (hipEvent_t& e : c->ev_apply)
+    if (!e) HIPCHK(c, hipEventCreate(&e));
+  HIPCHK(c, hipEventRecord(c->ev_apply[0], c->stream));
   if (c->nproj > 0) {
     // all projections B^H x at once on the matrix cores; the stencil sweep then only scatters
     if ((s = ensure(c, c->d_projP, (size_t)c->nproj * ncol * 16)) != RST_OK) return s;
@@ -1902,8 +1909,8 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
     M.ngroup = c->ngroup;
     M.ncol = ncol;
     M.h3 = c->ha * c->hb * c->hz;
-    const long long waves = (long long)c->ngroup * ((ncol + 63) / 64);
-    hipLaunchKernelGGL(rst::k_proj_mm, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, c->stream, M);
+    const long long tiles = (long long)c->ngroup * ((ncol + 63) / 64);  // one workgroup per (group, 64 columns)
+    hipLaunchKernelGGL(rst::k_proj_mm, dim3((unsigned)tiles), dim3(256), 0, c->stream, M);
     HIPCHK(c, hipGetLastError());
     A.proj_pre = (const double2*)c->d_projP.p;
   }
@@ -1919,8 +1926,90 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
   HIPCHK(c, hipMemcpyAsync(c->d_args.p, &c->h_apply, sizeof(A), hipMemcpyHostToDevice, c->stream));
   void* dargs = c->d_args.p;
   void* args[] = {&dargs};
+  HIPCHK(c, hipEventRecord(c->ev_apply[1], c->stream));
   HIPCHK(c, hipLaunchKernel(kern, dim3(A.nblk), dim3(ls.threads), args, lds, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev_apply[2], c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  float f0 = 0.f, f1 = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&f0, c->ev_apply[0], c->ev_apply[1]));
+  HIPCHK(c, hipEventElapsedTime(&f1, c->ev_apply[1], c->ev_apply[2]));
+  c->apply_ms[0] = f0;
+  c->apply_ms[1] = f1;
+  return RST_OK;
+}
+
+rst_status rst_apply_block_width(rst_ctx* c, int* col_block) {
+  if (!col_block) return RST_EINVAL;
+  rst_status s = check_ready(c);
+  if (s != RST_OK) return s;
+  hipSetDevice(c->device);
+  BlockedShape bs;
+  if ((s = blocked_shape(c, rst::CW_MAX, c->opts.threads, bs)) != RST_OK) return s;
+  *col_block = bs.ls.cw;
+  return RST_OK;
+}
+
+rst_status rst_apply_h_blocked(rst_ctx* c, double energy, const void* x_dev, void* y_dev, int ncol,
+                               int col_block) {
+  rst_status s = check_ready(c);
+  if (s != RST_OK) return s;
+  if (ncol < 0 || (ncol > 0 && (!x_dev || !y_dev))) return fail(c, RST_EINVAL, "bad apply arguments");
+  if (col_block < 1 || col_block > rst::CW_MAX || (col_block & (col_block - 1)))
+    return fail(c, RST_EINVAL, "col_block must be a power of two <= 8");
+  if (ncol % col_block) return fail(c, RST_EINVAL, "ncol must be a multiple of col_block");
+  if (x_dev == y_dev) return fail(c, RST_EINVAL, "x and y must be distinct buffers");
+  if (!std::isfinite(energy)) return fail(c, RST_EINVAL, "non-finite energy");
+  if (ncol == 0) return RST_OK;
+  hipSetDevice(c->device);
+  BlockedShape bs;
+  if ((s = blocked_shape(c, col_block, c->opts.threads, bs)) != RST_OK) return s;
+  if (bs.ls.cw != col_block)
+    return fail(c, RST_EUNSUPPORTED, "column block of " + std::to_string(col_block) +
+                                         " does not fit one workgroup on this grid (widest: " +
+                                         std::to_string(bs.ls.cw) + ")");
+  void* kern = pick_kernel(c->rad, bs.ls.q, 1);
+  if (!kern) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
+  rst::ApplyArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.g = make_geo(c);
+  A.pj = make_proj(c);
+  A.V = (const double*)c->d_v.p;
+  A.gz = (const double*)c->d_gz.p;
+  A.energy = energy;
+  A.x = (const double2*)x_dev;
+  A.y = (double2*)y_dev;
+  A.ncol = ncol;
+  A.cw = col_block;
+  A.nblk = ncol / col_block;
+  A.blocked = 1;
+  const size_t pws_stride = std::max<size_t>(1, (size_t)c->nproj * col_block);
+  if ((s = ensure(c, c->d_pws, (size_t)A.nblk * pws_stride * 16)) != RST_OK) return s;
+  A.pws = (double2*)c->d_pws.p;
+  A.pws_stride = pws_stride;
+  if (bs.lds_apply > 64 * 1024)
+    HIPCHK(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bs.lds_apply));
+  if ((s = ensure(c, c->d_args, sizeof(A))) != RST_OK) return s;
+  c->h_apply = A;
+  HIPCHK(c, hipMemcpyAsync(c->d_args.p, &c->h_apply, sizeof(A), hipMemcpyHostToDevice, c->stream));
+  for (hipEvent_t& e : c->ev_apply)
+    if (!e) HIPCHK(c, hipEventCreate(&e));
+  void* dargs = c->d_args.p;
+  void* args[] = {&dargs};
+  HIPCHK(c, hipEventRecord(c->ev_apply[1], c->stream));
+  HIPCHK(c, hipLaunchKernel(kern, dim3(A.nblk), dim3(bs.ls.threads), args, bs.lds_apply, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev_apply[2], c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float f1 = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&f1, c->ev_apply[1], c->ev_apply[2]));
+  c->apply_ms[0] = 0.0;  // the projector gather runs inside the sweep
+  c->apply_ms[1] = f1;
+  return RST_OK;
+}
+
+rst_status rst_apply_timing(const rst_ctx* c, double* proj_ms, double* stencil_ms) {
+  if (!c || !proj_ms || !stencil_ms) return RST_EINVAL;
+  *proj_ms = c->apply_ms[0];
+  *stencil_ms = c->apply_ms[1];
   return RST_OK;
 }
 

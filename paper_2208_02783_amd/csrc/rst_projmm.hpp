@@ -5,13 +5,17 @@
 // thousand grid points) form a dense product
 //     P_g (nm x ncol) = h^3 * beta_g^T (nm x E_g) * Xt_g (E_g x ncol),
 //     Xt_g[e][c] = conj(exp(i k.R_e)) X[gi_e][c],
-// with real beta.  One wave computes a group for 64 columns with
+// with real beta.  Products for 64 columns are formed with
 // v_mfma_f64_16x16x4f64 (M = 16 projector rows, nm <= 16 valid; N = 16
 // columns per block, four blocks; K = 4 entries per step), the real and the
 // imaginary part of Xt as two products sharing the beta operand.  Lane l holds
 // A element (row l%16, k = l/16), B element (k = l/16, column l%16) and the
 // accumulator D(row 4*r + l/16, column l%16), r = 0..3 (the FP64 layout,
-// measured on the device; it differs from the FP32 instruction's).
+// measured on the device; it differs from the FP32 instruction's).  A
+// workgroup of four waves takes one (group, 64 columns) tile and splits the
+// entries between its waves (wave w takes the steps k0 = 4w, 4w + 16, ...); the
+// four partial products are summed in LDS in wave order, so the result does not
+// depend on scheduling.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -34,12 +38,11 @@ struct ProjMMArgs {
 };
 
 __global__ __launch_bounds__(256) void k_proj_mm(ProjMMArgs A) {
-  const int lane = threadIdx.x & 63;
-  const long long w = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  __shared__ double red[3][32][64];  // partial products of waves 1..3: [wave-1][slot][lane]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int ntile = (A.ncol + 63) / 64;
-  if (w >= (long long)A.ngroup * ntile) return;  // whole wave exits together
-  const int g = (int)(w / ntile);
-  const int c0 = (int)(w % ntile) * 64;
+  const int g = (int)(blockIdx.x / ntile);
+  const int c0 = (int)(blockIdx.x % ntile) * 64;
   const int e0 = A.grp_e0[g], ne = A.grp_ne[g], nmg = A.grp_nm[g];
   const int i16 = lane & 15, kq = lane >> 4;
   v4d re[4], im[4];
@@ -48,7 +51,7 @@ __global__ __launch_bounds__(256) void k_proj_mm(ProjMMArgs A) {
     re[b] = v4d{0.0, 0.0, 0.0, 0.0};
     im[b] = v4d{0.0, 0.0, 0.0, 0.0};
   }
-  for (int k0 = 0; k0 < ne; k0 += 4) {
+  for (int k0 = 4 * wv; k0 < ne; k0 += 16) {
     const int k = k0 + kq;
     double a = 0.0;
     double2 ph = make_double2(0.0, 0.0);
@@ -72,14 +75,31 @@ __global__ __launch_bounds__(256) void k_proj_mm(ProjMMArgs A) {
       im[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xi, im[b], 0, 0, 0);
     }
   }
+  if (wv > 0) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        red[wv - 1][4 * b + r][lane] = re[b][r];
+        red[wv - 1][16 + 4 * b + r][lane] = im[b][r];
+      }
+  }
+  __syncthreads();
+  if (wv != 0) return;
   const int pb = A.grp_pbase[g];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const int col = c0 + 16 * b + i16;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+      double sr = re[b][r], si = im[b][r];
+#pragma unroll
+      for (int w = 0; w < 3; ++w) {
+        sr += red[w][4 * b + r][lane];
+        si += red[w][16 + 4 * b + r][lane];
+      }
       const int m = 4 * r + kq;
-      if (m < nmg && col < A.ncol) A.P[(size_t)(pb + m) * A.ncol + col] = make_double2(A.h3 * re[b][r], A.h3 * im[b][r]);
+      if (m < nmg && col < A.ncol) A.P[(size_t)(pb + m) * A.ncol + col] = make_double2(A.h3 * sr, A.h3 * si);
     }
   }
 }

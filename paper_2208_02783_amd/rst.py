@@ -24,7 +24,7 @@ RST_PRECOND_NONE, RST_PRECOND_FREE_CAP, RST_PRECOND_LEARNED = 0, 1, 2
 
 EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error", "rst_set_grid",
             "rst_set_potential", "rst_set_projectors", "rst_set_abc", "rst_set_k", "rst_set_solver",
-            "rst_transmission", "rst_apply_h", "rst_solve_columns", "rst_batch_clear",
+            "rst_transmission", "rst_apply_h", "rst_apply_timing", "rst_apply_block_width", "rst_apply_h_blocked", "rst_solve_columns", "rst_batch_clear",
             "rst_batch_add", "rst_batch_run", "rst_cnn_weight_count", "rst_cnn_seed",
             "rst_cnn_set_weights", "rst_cnn_get_weights", "rst_cnn_forward", "rst_cnn_gradient",
             "rst_cnn_train_step", "rst_precond_train", "rst_solve_rhs", "rst_default_lowrank",
@@ -120,6 +120,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.rst_set_solver.argtypes = [P, C.POINTER(rst_solver_opts)]
     lib.rst_transmission.argtypes = [P, C.c_int, P, P, C.POINTER(rst_stats)]
     lib.rst_apply_h.argtypes = [P, C.c_double, P, P, C.c_int]
+    lib.rst_apply_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.rst_apply_block_width.argtypes = [P, C.POINTER(C.c_int)]
+    lib.rst_apply_h_blocked.argtypes = [P, C.c_double, P, P, C.c_int, C.c_int]
     lib.rst_solve_columns.argtypes = [P, C.c_double, C.c_int, P, P, C.POINTER(rst_stats)]
     lib.rst_batch_clear.argtypes = [P]
     lib.rst_batch_add.argtypes = [P, C.POINTER(rst_problem)]
@@ -240,6 +243,21 @@ class Context:
         return self._chk(self.lib.rst_apply_h(self.h, float(energy), C.c_void_p(x_dev_ptr),
                                               C.c_void_p(y_dev_ptr), int(ncol)))
 
+    def rst_apply_block_width(self):
+        cw = C.c_int()
+        self._chk(self.lib.rst_apply_block_width(self.h, C.byref(cw)))
+        return cw.value
+
+    def rst_apply_h_blocked(self, energy, x_dev_ptr: int, y_dev_ptr: int, ncol: int, col_block: int):
+        return self._chk(self.lib.rst_apply_h_blocked(self.h, float(energy), C.c_void_p(x_dev_ptr),
+                                                      C.c_void_p(y_dev_ptr), int(ncol), int(col_block)))
+
+    def rst_apply_timing(self):
+        """(projector gather ms, stencil sweep ms) of the last rst_apply_h."""
+        a, b = C.c_double(), C.c_double()
+        self._chk(self.lib.rst_apply_timing(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def rst_solve_columns(self, energy, cols, x_dev_ptr: int):
         cols = np.ascontiguousarray(cols, np.int64)
         st = rst_stats()
@@ -347,6 +365,29 @@ def apply_h(ctx: Context, energy: float, x):
     torch.cuda.synchronize()
     ctx.rst_apply_h(energy, x.data_ptr(), y.data_ptr(), x.shape[1])
     return y
+
+
+def to_blocked(x, col_block: int):
+    """(n, ncol) column-fastest -> the blocked layout (ncol/col_block, n, col_block)."""
+    n, ncol = x.shape
+    return x.reshape(n, ncol // col_block, col_block).permute(1, 0, 2).contiguous()
+
+
+def from_blocked(xb):
+    """Blocked (nblk, n, col_block) -> (n, nblk*col_block) column-fastest."""
+    nblk, n, cw = xb.shape
+    return xb.permute(1, 0, 2).reshape(n, nblk * cw)
+
+
+def apply_h_blocked(ctx: Context, energy: float, xb):
+    """y = (E - H_k + i Gamma) x for x in the blocked layout, a torch complex128
+    CUDA tensor of shape (nblk, n, col_block)."""
+    import torch
+    assert xb.is_cuda and xb.dtype == torch.complex128 and xb.is_contiguous() and xb.dim() == 3
+    yb = torch.empty_like(xb)
+    torch.cuda.synchronize()
+    ctx.rst_apply_h_blocked(energy, xb.data_ptr(), yb.data_ptr(), xb.shape[0] * xb.shape[2], xb.shape[2])
+    return yb
 
 
 def solve_columns(ctx: Context, energy: float, cols, n: int, device="cuda"):

@@ -61,6 +61,67 @@ def test_apply_full_size_config2_columns():
     assert err <= 1e-13, err
 
 
+@pytest.mark.parametrize("case", APPLY_CASES)
+def test_apply_blocked_matches_oracle(case):
+    """The blocked-layout apply (the layout the solvers keep their vectors in),
+    every output against the oracle, at the widest and at a one-column block."""
+    torch = torch_cuda()
+    _say("blocked apply case", case)
+    rng = np.random.default_rng(17)
+    p = hp.random_problem(rng, na=case["na"], nb=case["nb"], nz=case["nz"], order=case["order"],
+                          nproj=case["nproj"], ramp=3)
+    ctx = make_ctx(torch, p, case["k"])
+    cwmax = ctx.rst_apply_block_width()
+    assert cwmax in (1, 2, 4, 8)
+    e = -0.217
+    for cw in sorted({1, cwmax}):
+        ncol = cw * 3
+        x, xd = rand_block(torch, p.n, ncol, 5)
+        y = rst.from_blocked(rst.apply_h_blocked(ctx, e, rst.to_blocked(xd, cw))).cpu().numpy()
+        ref = oracle.apply_system(p, case["k"], e, x)
+        err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+        assert err <= 1e-13, (cw, err)
+
+
+def test_apply_blocked_full_size_config2():
+    """Config 2 at full size: the blocked apply over 16 columns equals the
+    column-fastest apply (same operator, other kernels for the projector
+    gather), and two of its columns match the oracle."""
+    torch = torch_cuda()
+    p = wl.config(2)
+    k = p.kpts[9]
+    ctx = make_ctx(torch, p, k)
+    cw = ctx.rst_apply_block_width()
+    assert cw == 2  # 17 x 17 plane: two columns per workgroup at two positions per thread
+    x, xd = rand_block(torch, p.n, 16, 8)
+    e = float(p.energies[300])
+    yb = rst.from_blocked(rst.apply_h_blocked(ctx, e, rst.to_blocked(xd, cw)))
+    yc = rst.apply_h(ctx, e, xd)
+    d = (torch.max(torch.abs(yb - yc)) / torch.max(torch.abs(yc))).item()
+    assert d <= 1e-13, d
+    ref = oracle.apply_system(p, k, e, x[:, :2])
+    err = np.max(np.abs(yb[:, :2].cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-13, err
+    pm, sm = ctx.rst_apply_timing()
+    assert pm > 0.0 and sm > 0.0  # the column-fastest apply ran last: gather and sweep timed
+
+
+def test_apply_blocked_errors():
+    torch = torch_cuda()
+    p = wl.config(2)
+    ctx = make_ctx(torch, p, p.kpts[0])
+    x = torch.zeros((8, p.n, 1), dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    for ncol, cw, want in ((6, 4, rst.RST_EINVAL), (6, 3, rst.RST_EINVAL), (8, 8, rst.RST_EUNSUPPORTED)):
+        with pytest.raises(rst.RstError) as ei:
+            ctx.rst_apply_h_blocked(0.5, x.data_ptr(), y.data_ptr(), ncol, cw)
+        assert ei.value.status == want
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_apply_h_blocked(0.5, x.data_ptr(), x.data_ptr(), 8, 1)
+    assert ei.value.status == rst.RST_EINVAL
+    ctx.rst_apply_h_blocked(0.5, x.data_ptr(), y.data_ptr(), 0, 1)  # empty: nothing to do
+
+
 # ----------------------------------------------------------- Green columns
 
 def test_solve_columns_match_oracle():
