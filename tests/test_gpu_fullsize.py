@@ -1,0 +1,79 @@
+"""Config 2 at its full size (17x17x170, order 12, 40 wells, 360 KB projectors,
+9826 right-CAP columns) in the launch configuration the benchmark times:
+right-preconditioned FP64 BiCGSTAB to a true relative residual of 1e-10 with
+the default column block, at the benchmark's first timed (k, E).
+
+The dense oracle cannot factor n = 49,130, so the checks are ones that hold at
+any size: sampled Green's columns are verified with the oracle's own apply (the
+true residual recomputed in FP64 on the CPU), and T(E,k) over all 9826 columns
+against the independent low-rank route (random probes, Cholesky QR, adjoint
+solves at -k), against the left-CAP direction (T_LR = T_RL for any Hermitian
+H_k and real CAPs, transmission equation) and for positivity."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_02783_amd import rst
+from paper_2208_02783_amd import workloads as wl
+from tests.gpu_util import make_ctx, torch_cuda
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _problem():
+    p = wl.config(2)
+    return p, p.kpts[9], float(p.energies[400])
+
+
+def _ctx(torch, p, k, **kw):
+    return make_ctx(torch, p, k, precond=rst.RST_PRECOND_FREE_CAP, tol=TOL, max_iter=20000, **kw)
+
+
+def test_full_size_sampled_columns_true_residual_by_oracle():
+    torch = torch_cuda()
+    p, k, e = _problem()
+    ctx = _ctx(torch, p, k)
+    rc = p.r_columns()
+    cols = rc[np.linspace(0, rc.size - 1, 8).round().astype(int)]
+    _say("full-size columns", cols.tolist(), "E", e, "k", k)
+    x, st, s = rst.solve_columns(ctx, e, cols, p.n)
+    assert s == rst.RST_OK, st
+    x = x.cpu().numpy()
+    b = np.zeros_like(x)
+    b[cols, np.arange(cols.size)] = 1.0
+    res = oracle.residual_norms(p, k, e, x, b)
+    _say("oracle-recomputed true residuals", res)
+    assert np.all(res <= 2 * TOL), res
+    # every column carries current into the left CAP (nonzero there) and decays nowhere to NaN
+    assert np.all(np.isfinite(x))
+    lz = np.repeat(p.gamma_l > 0, p.na * p.nb)
+    assert np.all(np.linalg.norm(x[lz], axis=0) > 0)
+
+
+def test_full_size_point_lowrank_and_rl_agree():
+    torch = torch_cuda()
+    p, k, e = _problem()
+    ctx = _ctx(torch, p, k)
+    t, st, s = ctx.rst_transmission(np.array([e]))
+    _say("full-size T_LR", t[0], "iterations/column", st["iterations_total"] / st["columns"])
+    assert s == rst.RST_OK, st
+    assert st["columns"] == p.r_columns().size == 9826
+    assert st["columns_unconverged"] == 0
+    assert st["max_rel_residual"] <= TOL
+    assert t[0] >= 0.0
+    bar = 1e-6 * max(1.0, t[0])
+    tl, terr, stl, sl = ctx.rst_transmission_lowrank(np.array([e]), probes=16, heldout=8, tail_tol=1e-7)
+    _say("low-rank T", tl[0], "tail estimate", terr[0], "solves", stl["columns"])
+    assert sl == rst.RST_OK
+    assert abs(tl[0] - t[0]) <= bar, (tl[0], t[0])
+    ctx_rl = _ctx(torch, p, k, direction=rst.RST_DIR_RL)
+    trl, strl, srl = ctx_rl.rst_transmission(np.array([e]))
+    _say("full-size T_RL", trl[0])
+    assert srl == rst.RST_OK, strl
+    assert strl["columns"] == p.l_columns().size
+    assert abs(trl[0] - t[0]) <= bar, (trl[0], t[0])
