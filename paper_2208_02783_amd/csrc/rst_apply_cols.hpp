@@ -1,0 +1,153 @@
+// rst_apply_cols.hpp -- y = (E - H_k + i Gamma) x for many columns in the
+// column-fastest layout (x, y: n x ncol, element (gi, c) at gi*ncol + c).
+//
+// H_k is the order-2M finite-difference Laplacian with Bloch-phase lateral
+// wraps, the local potential and the KB projectors (Bloch-form equation,
+// Kleinman-Bylander form); Gamma is the z-only CAP.  One wave owns one lateral
+// grid point and 64 consecutive columns (one lane per column), so every load
+// and store of a grid point's row is 1 KB contiguous.  The wave streams z:
+// its own rows sit in a (2M+1)-deep register queue (the z part of the
+// stencil), the 4M lateral neighbours of the current plane are read from the
+// rows other waves of the same column chunk stream at the same time (L2), and
+// the projector part uses the projections P = h^3 B^H x of all columns
+// computed beforehand (k_proj_mm).  The point is uniform across the wave, so
+// neighbour indices, wrap phases, V and the projector tables are scalar.
+//
+// Workgroup b takes (chunk, point); the eight XCDs receive workgroups round
+// robin (b mod 8) and each has its own L2, so every point of a chunk is placed
+// on one XCD (whole groups of eight chunks; a remainder keeps plain order).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "rst_kernels.hpp"
+
+namespace rst {
+
+struct ColApplyArgs {
+  const double2* x;
+  double2* y;
+  int ncol;
+  Geo g;
+  const double* V;    // [n]
+  const double* gz;   // [nz] Gamma_L + Gamma_R
+  double energy;
+  // projector part: y -= sum_p beta_p (E_p P_p), P from k_proj_mm (h^3 included)
+  Proj pj;
+  const double2* P;   // [nproj*ncol]
+};
+
+__device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <int RAD>
+__global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
+  constexpr int NQ = 2 * RAD + 1;
+  const Geo& g = A.g;
+  const int P = g.P, na = g.na, nb = g.nb, nz = g.nz, ncol = A.ncol;
+  const int nchunk = (ncol + 63) / 64;
+  // (chunk, point) of this workgroup
+  const long long b = blockIdx.x;
+  const long long full8 = (long long)(nchunk / 8) * 8;
+  int chunk, p;
+  if (b < full8 * P) {
+    const long long i = b / 8;
+    chunk = (int)((i / P) * 8 + b % 8);
+    p = (int)(i % P);
+  } else {
+    const long long r = b - full8 * P;
+    chunk = (int)(full8 + r / P);
+    p = (int)(r % P);
+  }
+  const int c = chunk * 64 + (int)threadIdx.x;
+  const bool ok = c < ncol;
+  const int ia = p % na, ib = p / na;
+  const double2 pha = make_double2(g.pha_x, g.pha_y), phac = make_double2(g.pha_x, -g.pha_y);
+  const double2 phb = make_double2(g.phb_x, g.phb_y), phbc = make_double2(g.phb_x, -g.phb_y);
+  const double2 zero = make_double2(0.0, 0.0);
+
+  auto row = [&](long long gi) -> double2 { return ok ? A.x[gi * ncol + c] : zero; };
+
+  double2 q[NQ];
+#pragma unroll
+  for (int s = 0; s < NQ; ++s) q[s] = zero;
+#pragma unroll
+  for (int s = 0; s <= RAD; ++s)
+    if (s < nz) q[RAD + s] = row((long long)s * P + p);
+
+  for (int z = 0; z < nz; ++z) {
+    const int zl = z + RAD + 1;
+    const double2 nxt = zl < nz ? row((long long)zl * P + p) : zero;
+    const long long base = (long long)z * P;
+    const long long gi = base + p;
+    const double2 u = q[RAD];
+    const double dr = A.energy - A.V[gi] + g.diag0;
+    const double gzz = A.gz[z];
+    double2 y = make_double2(dr * u.x - gzz * u.y, dr * u.y + gzz * u.x);
+#pragma unroll
+    for (int j = 1; j <= RAD; ++j) {
+      // lateral neighbours: a wrap across the +face carries exp(+i k L), across the -face its conjugate
+      int ap = ia + j, am = ia - j, bp = ib + j, bm = ib - j;
+      double2 xap = row(base + (long long)ib * na + (ap >= na ? ap - na : ap));
+      double2 xam = row(base + (long long)ib * na + (am < 0 ? am + na : am));
+      double2 xbp = row(base + (long long)(bp >= nb ? bp - nb : bp) * na + ia);
+      double2 xbm = row(base + (long long)(bm < 0 ? bm + nb : bm) * na + ia);
+      if (ap >= na) xap = cmul2(xap, pha);
+      if (am < 0) xam = cmul2(xam, phac);
+      if (bp >= nb) xbp = cmul2(xbp, phb);
+      if (bm < 0) xbm = cmul2(xbm, phbc);
+      const double2 zz = make_double2(q[RAD + j].x + q[RAD - j].x, q[RAD + j].y + q[RAD - j].y);
+      const double2 aa = make_double2(xap.x + xam.x, xap.y + xam.y);
+      const double2 bb = make_double2(xbp.x + xbm.x, xbp.y + xbm.y);
+      y.x += g.cz[j] * zz.x + g.ca[j] * aa.x + g.cb[j] * bb.x;
+      y.y += g.cz[j] * zz.y + g.ca[j] * aa.y + g.cb[j] * bb.y;
+    }
+    if (A.pj.nproj) {
+      // sum over the point's (group, entry) pairs of exp(+i k.R_e) sum_m beta_e,m E_p P_p, p = first + m
+      const Proj& pj = A.pj;
+      double sx = 0.0, sy = 0.0;
+      for (int sl = 0; sl < SC_SLOTS; ++sl) {
+        const size_t si = (size_t)gi * SC_SLOTS + sl;
+        const int pb = pj.sc_pb[si];
+        if (pb < 0) continue;
+        const double2 ph = pj.sc_eph[si];
+        double tx = 0.0, ty = 0.0;
+        for (int m = 0; m < pj.nm && pb + m < pj.nproj; ++m) {
+          const double bt = pj.sc_beta[si * pj.nm + m];
+          const double w = bt * pj.ekb[pb + m];
+          const double2 pv = ok ? A.P[(size_t)(pb + m) * ncol + c] : zero;
+          tx += w * pv.x;
+          ty += w * pv.y;
+        }
+        sx += ph.x * tx - ph.y * ty;
+        sy += ph.x * ty + ph.y * tx;
+      }
+      if (pj.has_overflow) {
+        const int k0 = pj.pe_offs[gi], k1 = pj.pe_offs[gi + 1];
+        for (int k = k0; k < k1; ++k) {
+          const int2 ge = pj.pe[k];
+          const int nmg = pj.grp_nm[ge.x];
+          const int pb = pj.grp_pbase[ge.x];
+          const double2 ph = pj.eph[ge.y];
+          double tx = 0.0, ty = 0.0;
+          for (int m = 0; m < nmg; ++m) {
+            const double w = pj.beta[(size_t)ge.y * pj.nm + m] * pj.ekb[pb + m];
+            const double2 pv = ok ? A.P[(size_t)(pb + m) * ncol + c] : zero;
+            tx += w * pv.x;
+            ty += w * pv.y;
+          }
+          sx += ph.x * tx - ph.y * ty;
+          sy += ph.x * ty + ph.y * tx;
+        }
+      }
+      y.x -= sx;
+      y.y -= sy;
+    }
+    if (ok) A.y[gi * ncol + c] = y;
+#pragma unroll
+    for (int s = 0; s < NQ - 1; ++s) q[s] = q[s + 1];
+    q[NQ - 1] = nxt;
+  }
+}
+
+}  // namespace rst

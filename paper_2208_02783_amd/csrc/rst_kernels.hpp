@@ -230,13 +230,11 @@ struct ApplyArgs {
   const double* V;
   const double* gz;
   double energy;
-  const double2* x;         // (n x ncol) column-fastest
+  const double2* x;         // blocked layout: block b (columns b*cw ..) is n x cw column-fastest at b*n*cw
   double2* y;
   int ncol, cw, nblk;
   double2* pws;             // per-workgroup projection scratch (2 arrays nproj*cw)
   size_t pws_stride;
-  int blocked;              // 1: x, y in blocked layout (block b: n x cw column-fastest at b*n*cw)
-  const double2* proj_pre;  // projections B^H x computed beforehand (nproj x ncol), or null
 };
 
 // ---------------------------------------------------------------------------

@@ -17,6 +17,7 @@
 #include "rst_fgmres.hpp"
 #include "rst_lowrank.hpp"
 #include "rst_projmm.hpp"
+#include "rst_apply_cols.hpp"
 #include "rst_mixed.hpp"
 
 using rst::cx;
@@ -987,7 +988,6 @@ rst_status run_fgmres(rst_ctx* c, int ne, const double* energies, const std::vec
       A.nblk = nblk;
       A.pws = (double2*)c->d_pws.p;
       A.pws_stride = pws_stride;
-      A.blocked = 1;
     }
     if ((e = upload(c, c->d_fgaa, aa)) != RST_OK) return e;
     if (usepc) {
@@ -1866,34 +1866,24 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
   if (!std::isfinite(energy)) return fail(c, RST_EINVAL, "non-finite energy");
   if (ncol == 0) return RST_OK;
   hipSetDevice(c->device);
-  LaunchShape ls;
-  int cw_req = c->opts.col_block > 0 ? c->opts.col_block : std::min(rst::CW_MAX, 4);
-  const long long qmax = 2;
-  while (cw_req > 1 && (long long)c->na * c->nb * cw_req > qmax * rst::MAX_T) cw_req /= 2;
-  if ((s = choose_shape(c, cw_req, c->opts.threads, ls)) != RST_OK) return s;
-  void* kern = pick_kernel(c->rad, ls.q, 1);
-  if (!kern) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
-  rst::ApplyArgs A;
+  const int P = c->na * c->nb;  // rst_set_grid guarantees na, nb > rad: one wrap at most
+  const long long nwg = (long long)((ncol + 63) / 64) * P;  // one wave per (64 columns, lateral point)
+  if (nwg > 0x7fffffffLL) return fail(c, RST_EINVAL, "too many columns for one launch");
+  rst::ColApplyArgs A;
   std::memset(&A, 0, sizeof(A));
-  A.g = make_geo(c);
-  A.pj = make_proj(c);
-  A.V = (const double*)c->d_v.p;
-  A.gz = (const double*)c->d_gz.p;
-  A.energy = energy;
   A.x = (const double2*)x_dev;
   A.y = (double2*)y_dev;
   A.ncol = ncol;
-  A.cw = ls.cw;
-  A.nblk = (ncol + ls.cw - 1) / ls.cw;
-  const size_t pws_stride = std::max<size_t>(1, (size_t)c->nproj * ls.cw);
-  if ((s = ensure(c, c->d_pws, (size_t)A.nblk * pws_stride * 16)) != RST_OK) return s;
-  A.pws = (double2*)c->d_pws.p;
-  A.pws_stride = pws_stride;
+  A.g = make_geo(c);
+  A.V = (const double*)c->d_v.p;
+  A.gz = (const double*)c->d_gz.p;
+  A.energy = energy;
+  A.pj = make_proj(c);
   for (hipEvent_t& e : c->ev_apply)
     if (!e) HIPCHK(c, hipEventCreate(&e));
   HIPCHK(c, hipEventRecord(c->ev_apply[0], c->stream));
   if (c->nproj > 0) {
-    // all projections B^H x at once on the matrix cores; the stencil sweep then only scatters
+    // all projections P = h^3 B^H x at once on the matrix cores; the apply kernel then scatters B E P
     if ((s = ensure(c, c->d_projP, (size_t)c->nproj * ncol * 16)) != RST_OK) return s;
     rst::ProjMMArgs M;
     M.X = (const double2*)x_dev;
@@ -1912,22 +1902,14 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
     const long long tiles = (long long)c->ngroup * ((ncol + 63) / 64);  // one workgroup per (group, 64 columns)
     hipLaunchKernelGGL(rst::k_proj_mm, dim3((unsigned)tiles), dim3(256), 0, c->stream, M);
     HIPCHK(c, hipGetLastError());
-    A.proj_pre = (const double2*)c->d_projP.p;
+    A.P = (const double2*)c->d_projP.p;
   }
-  const size_t lds =
-      rst::lds_bytes<double>(A.g.pa, A.g.pb, A.g.P, A.pj.nproj, A.pj.max_chunks, A.pj.nm, ls.cw, ls.threads);
-  int dev_lds = 0;
-  HIPCHK(c, hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-  if (lds + sizeof(rst::ColState) + 1024 > (size_t)dev_lds)
-    return fail(c, RST_EUNSUPPORTED, "LDS requirement exceeds the device limit");
-  if (lds > 64 * 1024) HIPCHK(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  if ((s = ensure(c, c->d_args, sizeof(A))) != RST_OK) return s;
-  c->h_apply = A;
-  HIPCHK(c, hipMemcpyAsync(c->d_args.p, &c->h_apply, sizeof(A), hipMemcpyHostToDevice, c->stream));
-  void* dargs = c->d_args.p;
-  void* args[] = {&dargs};
   HIPCHK(c, hipEventRecord(c->ev_apply[1], c->stream));
-  HIPCHK(c, hipLaunchKernel(kern, dim3(A.nblk), dim3(ls.threads), args, lds, c->stream));
+  if (c->rad == 6)
+    hipLaunchKernelGGL(rst::k_apply_cols<6>, dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
+  else
+    hipLaunchKernelGGL(rst::k_apply_cols<2>, dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
+  HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->ev_apply[2], c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   float f0 = 0.f, f1 = 0.f;
@@ -1981,7 +1963,6 @@ rst_status rst_apply_h_blocked(rst_ctx* c, double energy, const void* x_dev, voi
   A.ncol = ncol;
   A.cw = col_block;
   A.nblk = ncol / col_block;
-  A.blocked = 1;
   const size_t pws_stride = std::max<size_t>(1, (size_t)c->nproj * col_block);
   if ((s = ensure(c, c->d_pws, (size_t)A.nblk * pws_stride * 16)) != RST_OK) return s;
   A.pws = (double2*)c->d_pws.p;
@@ -2225,7 +2206,6 @@ rst_status rst_precond_train(rst_ctx* c, const rst_train_opts* o, rst_train_stat
     aa[0].nblk = nblk;
     aa[0].pws = (double2*)c->d_pws.p;
     aa[0].pws_stride = pws_stride;
-    aa[0].blocked = 1;
     if ((s = upload(c, c->d_fgaa, aa)) != RST_OK) return s;
     // xi -> e = M^-1 xi -> r = A e; scale to ||r|| = 1; m = M^-1 r; (features, target)
     hipLaunchKernelGGL(rst::fg::k_fg_randn, dim3(gv), dim3(256), 0, c->stream, S,

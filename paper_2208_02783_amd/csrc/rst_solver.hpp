@@ -525,17 +525,9 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab(const SolveAr
   }
 }
 
-// Column block of workgroup b for the column-fastest layout.  A workgroup owns
-// cw columns, a 16*cw-byte piece of each 128-byte row segment; workgroups are
-// handed to the eight XCDs round robin (b mod 8), each XCD with its own L2.
-// Within every run of 32 workgroups the four that share a segment are placed on
-// one XCD (b, b+8, b+16, b+24 take adjacent blocks), so the segment is fetched
-// from HBM once instead of once per XCD.  The partial last run keeps b.
-__device__ __forceinline__ int xcd_col_block(int b, int nblk) {
-  if (b >= (nblk / 32) * 32) return b;
-  return (b / 32) * 32 + (b % 8) * 4 + (b / 8) % 4;
-}
-
+// y = (E - H_k + i Gamma) x on blocked vectors (the solvers' layout), one
+// workgroup per column block: a gather sweep forms B^H x of the block, then
+// the stencil sweep applies the rest and scatters the projector part.
 template <int RAD, int Q, class R>
 __global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ Ap) {
   const ApplyArgs& A = *Ap;
@@ -550,20 +542,12 @@ __global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ A
   C.cw = cw;
   C.L = carve_lds<R>(smem, A.g, A.pj, cw, blockDim.x);
   C.S = &S;
-  if (A.blocked) {
-    const size_t boff = (size_t)blockIdx.x * A.g.P * A.g.nz * cw;
-    C.xext = A.x + boff;
-    C.yext = A.y + boff;
-    C.ext_ld = cw;
-    C.ext_c0 = 0;
-    C.ext_ncol = cw;
-  } else {
-    C.xext = A.x;
-    C.yext = A.y;
-    C.ext_ld = A.ncol;
-    C.ext_c0 = xcd_col_block(blockIdx.x, gridDim.x) * cw;
-    C.ext_ncol = A.ncol;
-  }
+  const size_t boff = (size_t)blockIdx.x * A.g.P * A.g.nz * cw;
+  C.xext = A.x + boff;
+  C.yext = A.y + boff;
+  C.ext_ld = cw;
+  C.ext_c0 = 0;
+  C.ext_ncol = cw;
   C.vec = Vecs<R>{nullptr, nullptr, nullptr, nullptr, nullptr};
   C.pcsrc = C.pcs = nullptr;
   C.r32 = nullptr;
@@ -584,14 +568,7 @@ __global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ A
   __syncthreads();
   const Pos<Q> ps = make_pos<Q>(A.g, cw, RAD);
   double tacc = 0;
-  if (A.pj.nproj && A.proj_pre && !A.blocked) {
-    for (int w = tid; w < (int)np; w += blockDim.x) {
-      const int col = C.ext_c0 + w % cw;
-      const double2 v = col < A.ncol ? A.proj_pre[(size_t)(w / cw) * A.ncol + col] : make_double2(0.0, 0.0);
-      Px[w] = mkc(v.x, v.y);
-    }
-    __syncthreads();
-  } else if (A.pj.nproj) {
+  if (A.pj.nproj) {
     C.acc = Px;
     gather_sweep<Q, R, true>(C, ps, nullptr, tacc);
   }

@@ -61,6 +61,27 @@ def test_apply_full_size_config2_columns():
     assert err <= 1e-13, err
 
 
+def test_apply_full_size_config3_columns():
+    """Config 3 at its full size (54x54x252 point contact, n = 734,832, 3420
+    projectors): the column-fastest apply has no per-plane workgroup limit, so
+    every output of a few columns is checked against the oracle's factored
+    apply.  The solvers hold one lateral plane per workgroup and refuse this
+    grid with a clear status."""
+    torch = torch_cuda()
+    p = wl.config(3)
+    k = p.kpts[5]
+    ctx = make_ctx(torch, p, k, precond=rst.RST_PRECOND_FREE_CAP)
+    x, xd = rand_block(torch, p.n, 3, 4)
+    e = float(p.energies[40])
+    y = rst.apply_h(ctx, e, xd).cpu().numpy()
+    ref = oracle.apply_system(p, k, e, x)
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-13, err
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_transmission(np.array([e]))
+    assert ei.value.status == rst.RST_EUNSUPPORTED
+
+
 @pytest.mark.parametrize("case", APPLY_CASES)
 def test_apply_blocked_matches_oracle(case):
     """The blocked-layout apply (the layout the solvers keep their vectors in),
