@@ -40,7 +40,9 @@ __device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-template <int RAD>
+// NMU: compile-time bound on the projectors per group (9 for l <= 2, else 16),
+// so a point's projection rows are all requested before the first is used.
+template <int RAD, int NMU>
 __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
   constexpr int NQ = 2 * RAD + 1;
   const Geo& g = A.g;
@@ -111,13 +113,21 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
         const int pb = pj.sc_pb[si];
         if (pb < 0) continue;
         const double2 ph = pj.sc_eph[si];
+        const int nv = min(pj.nm, pj.nproj - pb);  // values past the group's projectors are zero
+        double w[NMU];
+        double2 pv[NMU];
+#pragma unroll
+        for (int m = 0; m < NMU; ++m) {
+          const int mm = min(m, nv - 1);  // clamped: every load in bounds, the extra weights zero
+          const double bw = pj.sc_beta[si * pj.nm + mm] * pj.ekb[pb + mm];
+          w[m] = m < nv ? bw : 0.0;
+          pv[m] = ok ? A.P[(size_t)(pb + mm) * ncol + c] : zero;
+        }
         double tx = 0.0, ty = 0.0;
-        for (int m = 0; m < pj.nm && pb + m < pj.nproj; ++m) {
-          const double bt = pj.sc_beta[si * pj.nm + m];
-          const double w = bt * pj.ekb[pb + m];
-          const double2 pv = ok ? A.P[(size_t)(pb + m) * ncol + c] : zero;
-          tx += w * pv.x;
-          ty += w * pv.y;
+#pragma unroll
+        for (int m = 0; m < NMU; ++m) {
+          tx += w[m] * pv[m].x;
+          ty += w[m] * pv[m].y;
         }
         sx += ph.x * tx - ph.y * ty;
         sy += ph.x * ty + ph.y * tx;

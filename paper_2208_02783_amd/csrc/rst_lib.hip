@@ -1905,10 +1905,15 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
     A.P = (const double2*)c->d_projP.p;
   }
   HIPCHK(c, hipEventRecord(c->ev_apply[1], c->stream));
-  if (c->rad == 6)
-    hipLaunchKernelGGL(rst::k_apply_cols<6>, dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
+  const bool nm9 = c->nm <= 9;
+  if (c->rad == 6 && nm9)
+    hipLaunchKernelGGL((rst::k_apply_cols<6, 9>), dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
+  else if (c->rad == 6)
+    hipLaunchKernelGGL((rst::k_apply_cols<6, 16>), dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
+  else if (nm9)
+    hipLaunchKernelGGL((rst::k_apply_cols<2, 9>), dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
   else
-    hipLaunchKernelGGL(rst::k_apply_cols<2>, dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
+    hipLaunchKernelGGL((rst::k_apply_cols<2, 16>), dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->ev_apply[2], c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
