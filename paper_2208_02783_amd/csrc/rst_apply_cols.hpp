@@ -13,15 +13,23 @@
 // computed beforehand (k_proj_mm).  The point is uniform across the wave, so
 // neighbour indices, wrap phases, V and the projector tables are scalar.
 //
-// Workgroup b takes (chunk, point); the eight XCDs receive workgroups round
-// robin (b mod 8) and each has its own L2, so every point of a chunk is placed
-// on one XCD (whole groups of eight chunks; a remainder keeps plain order).
+// A wave covers one segment of zseg planes (its queue starts from the rows
+// below and above the segment), so the waves that share lateral rows stay
+// within a few planes of each other.  Workgroup b takes (chunk, segment,
+// point); the eight XCDs receive workgroups round robin (b mod 8) and each has
+// its own L2, so chunk c runs on XCD c mod 8 with all points of a segment
+// dispatched together and its segments in increasing z (whole groups of eight
+// chunks; a remainder keeps plain order).
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "rst_kernels.hpp"
 
 namespace rst {
+
+// Planes per wave (measured on config 2 at 1024-4096 columns: 8 and 16 best,
+// 32 slightly and 170 (whole columns) 20-30% slower).
+constexpr int APPLY_ZSEG = 16;
 
 struct ColApplyArgs {
   const double2* x;
@@ -34,6 +42,7 @@ struct ColApplyArgs {
   // projector part: y -= sum_p beta_p (E_p P_p), P from k_proj_mm (h^3 included)
   Proj pj;
   const double2* P;   // [nproj*ncol]
+  int zseg;           // planes per wave (>= 1)
 };
 
 __device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
@@ -48,19 +57,24 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
   const Geo& g = A.g;
   const int P = g.P, na = g.na, nb = g.nb, nz = g.nz, ncol = A.ncol;
   const int nchunk = (ncol + 63) / 64;
-  // (chunk, point) of this workgroup
+  const int nseg = (nz + A.zseg - 1) / A.zseg;
+  // (chunk, segment, point) of this workgroup
   const long long b = blockIdx.x;
   const long long full8 = (long long)(nchunk / 8) * 8;
-  int chunk, p;
-  if (b < full8 * P) {
-    const long long i = b / 8;
-    chunk = (int)((i / P) * 8 + b % 8);
+  int chunk, seg, p;
+  if (b < full8 * nseg * P) {
+    const long long i = b / 8;   // position in this XCD's sequence
+    const long long gl = i / P;  // (chunk on this XCD, segment), segment fastest
+    chunk = (int)((gl / nseg) * 8 + b % 8);
+    seg = (int)(gl % nseg);
     p = (int)(i % P);
   } else {
-    const long long r = b - full8 * P;
-    chunk = (int)(full8 + r / P);
+    const long long r = b - full8 * nseg * P;
+    chunk = (int)(full8 + r / ((long long)nseg * P));
+    seg = (int)((r / P) % nseg);
     p = (int)(r % P);
   }
+  const int z0 = seg * A.zseg, z1 = min(nz, z0 + A.zseg);
   const int c = chunk * 64 + (int)threadIdx.x;
   const bool ok = c < ncol;
   const int ia = p % na, ib = p / na;
@@ -70,14 +84,14 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
 
   auto row = [&](long long gi) -> double2 { return ok ? A.x[gi * ncol + c] : zero; };
 
-  double2 q[NQ];
+  double2 q[NQ];  // q[RAD + d] = row of plane z + d
 #pragma unroll
-  for (int s = 0; s < NQ; ++s) q[s] = zero;
-#pragma unroll
-  for (int s = 0; s <= RAD; ++s)
-    if (s < nz) q[RAD + s] = row((long long)s * P + p);
+  for (int s = 0; s < NQ; ++s) {
+    const int zs = z0 - RAD + s;
+    q[s] = (zs >= 0 && zs < nz) ? row((long long)zs * P + p) : zero;
+  }
 
-  for (int z = 0; z < nz; ++z) {
+  for (int z = z0; z < z1; ++z) {
     const int zl = z + RAD + 1;
     const double2 nxt = zl < nz ? row((long long)zl * P + p) : zero;
     const long long base = (long long)z * P;

@@ -1867,7 +1867,10 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
   if (ncol == 0) return RST_OK;
   hipSetDevice(c->device);
   const int P = c->na * c->nb;  // rst_set_grid guarantees na, nb > rad: one wrap at most
-  const long long nwg = (long long)((ncol + 63) / 64) * P;  // one wave per (64 columns, lateral point)
+  // planes per wave: short segments keep the waves that share lateral rows close in z
+  const int zseg = std::min(c->nz, rst::APPLY_ZSEG);
+  const long long nseg = (c->nz + zseg - 1) / zseg;
+  const long long nwg = (long long)((ncol + 63) / 64) * nseg * P;  // one wave per (64 columns, segment, point)
   if (nwg > 0x7fffffffLL) return fail(c, RST_EINVAL, "too many columns for one launch");
   rst::ColApplyArgs A;
   std::memset(&A, 0, sizeof(A));
@@ -1879,6 +1882,7 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
   A.gz = (const double*)c->d_gz.p;
   A.energy = energy;
   A.pj = make_proj(c);
+  A.zseg = zseg;
   for (hipEvent_t& e : c->ev_apply)
     if (!e) HIPCHK(c, hipEventCreate(&e));
   HIPCHK(c, hipEventRecord(c->ev_apply[0], c->stream));
