@@ -259,6 +259,8 @@ def stencil_apply(prob, k, e, ncol=1024, reps=5):
     yb = torch.empty_like(xb)
     _, bm = timed(lambda: ctx.rst_apply_h_blocked(e, xb.data_ptr(), yb.data_ptr(), ncol, cw))
     dif = (torch.max(torch.abs(rst.from_blocked(yb) - y)) / torch.max(torch.abs(y))).item()
+    # the two layouts run different kernels for the same operator: they must agree to rounding
+    assert dif <= 1e-13, f"column-fastest and blocked applies differ by {dif:.2e}"
     gbs = alg / ((pm + sm) * 1e-3) / 1e9
     gbb = alg / (bm * 1e-3) / 1e9
     print(f"stencil apply, {ncol} columns: column-fastest gather {pm:.3f} ms + apply {sm:.3f} ms -> "

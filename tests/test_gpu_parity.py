@@ -61,6 +61,24 @@ def test_apply_full_size_config2_columns():
     assert err <= 1e-13, err
 
 
+@pytest.mark.parametrize("order,nproj", [(4, 3), (12, 4)])
+def test_apply_many_columns_matches_oracle(order, nproj):
+    """549 columns (eight full 64-column chunks placed per XCD plus a ragged
+    ninth) over 40 planes (z segments of 16, 16 and 8): every output against
+    the oracle."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(29)
+    p = hp.random_problem(rng, na=7, nb=8, nz=40, order=order, nproj=nproj, ramp=5)
+    k = (0.31, -0.52)
+    ctx = make_ctx(torch, p, k)
+    x, xd = rand_block(torch, p.n, 549, 6)
+    e = 0.413
+    y = rst.apply_h(ctx, e, xd).cpu().numpy()
+    ref = oracle.apply_system(p, k, e, x)
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-13, err
+
+
 def test_apply_full_size_config3_columns():
     """Config 3 at its full size (54x54x252 point contact, n = 734,832, 3420
     projectors): the column-fastest apply has no per-plane workgroup limit, so
