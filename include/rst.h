@@ -175,6 +175,23 @@ rst_status rst_set_solver(rst_ctx *ctx, const rst_solver_opts *opts);
 rst_status rst_transmission(rst_ctx *ctx, int n_e, const double *energies, double *T_out,
                             rst_stats *stats);
 
+/* k-averaged transmission T(E) = (1/n_k) sum_k T(E, k) over the lateral k-points
+ * kpts (host, n_k pairs (ka, kb) in bohr^-1), each T(E, k) by rst_transmission
+ * (the k-point average of the paper's transmission over the lateral Brillouin
+ * zone).  With fold != 0 a k-point equal to an earlier one, or to its negative,
+ * modulo a reciprocal lattice vector 2 pi / L is not solved again: T(k + G) =
+ * T(k) (Bloch periodicity) and T(-k) = T(k) (H_-k = conj(H_k) for real V,
+ * beta and E_KB, so G_-k = G_k^T and the trace is unchanged) make this exact.
+ * T_out (n_e) gets the average; T_k (nullable, n_k x n_e, row per k-point) the
+ * per-k values; n_solved (nullable) the number of k-points actually solved;
+ * stats (nullable) sums columns, iterations, kernel time and bytes over them.
+ * The caller's k is restored.  Grid, potential and CAPs must be set; k need
+ * not be.  RST_EINVAL for n_k < 1, a null or non-finite input; RST_ENOCONV if
+ * any column hit the iteration cap (all outputs written). */
+rst_status rst_transmission_kavg(rst_ctx *ctx, int n_k, const double *kpts, int fold, int n_e,
+                                 const double *E, double *T_out, double *T_k, int *n_solved,
+                                 rst_stats *stats);
+
 /* Test hook: y = (E - H_k + i Gamma) x for an (n x ncol) complex128 block.
  * x_dev and y_dev are distinct device buffers of n*ncol*16 bytes. */
 rst_status rst_apply_h(rst_ctx *ctx, double energy, const void *x_dev, void *y_dev, int ncol);

@@ -1858,6 +1858,94 @@ rst_status rst_solve_rhs(rst_ctx* c, int n_e, const double* energies, int ncol, 
   return nbad ? RST_ENOCONV : RST_OK;
 }
 
+rst_status rst_transmission_kavg(rst_ctx* c, int n_k, const double* kpts, int fold, int n_e, const double* E,
+                                 double* T_out, double* T_k, int* n_solved, rst_stats* stats) {
+  if (!c) return RST_EINVAL;
+  if (!c->has_grid) return fail(c, RST_ESTATE, "rst_set_grid not called");
+  if (!c->has_v) return fail(c, RST_ESTATE, "rst_set_potential not called");
+  if (!c->has_abc) return fail(c, RST_ESTATE, "rst_set_abc not called");
+  if (n_k < 1 || !kpts) return fail(c, RST_EINVAL, "at least one k-point is needed");
+  if (n_e < 0 || (n_e > 0 && (!E || !T_out))) return fail(c, RST_EINVAL, "bad energy arguments");
+  for (int i = 0; i < 2 * n_k; ++i)
+    if (!std::isfinite(kpts[i])) return fail(c, RST_EINVAL, "non-finite k");
+  for (int i = 0; i < n_e; ++i)
+    if (!std::isfinite(E[i])) return fail(c, RST_EINVAL, "non-finite energy");
+  // representative of each k: itself, or an earlier k equal to it or to its
+  // negative modulo a reciprocal lattice vector (T(k + G) = T(k) = T(-k))
+  const double two_pi = 6.283185307179586;
+  const double ga = two_pi / (c->na * c->ha), gb = two_pi / (c->nb * c->hb);
+  auto integral = [](double x) { return std::fabs(x - std::nearbyint(x)) <= 1e-9; };
+  std::vector<int> rep(n_k);
+  for (int i = 0; i < n_k; ++i) {
+    rep[i] = i;
+    if (!fold) continue;
+    for (int j = 0; j < i; ++j) {
+      if (rep[j] != j) continue;
+      const double ka = kpts[2 * i], kb = kpts[2 * i + 1], ja = kpts[2 * j], jb = kpts[2 * j + 1];
+      const bool same = integral((ka - ja) / ga) && integral((kb - jb) / gb);
+      const bool neg = integral((ka + ja) / ga) && integral((kb + jb) / gb);
+      if (same || neg) {
+        rep[i] = j;
+        break;
+      }
+    }
+  }
+  const bool had_k = c->has_k;
+  const double ka0 = c->ka, kb0 = c->kb;
+  std::vector<double> tk((size_t)n_k * n_e, 0.0);
+  rst_stats acc;
+  std::memset(&acc, 0, sizeof(acc));
+  rst_status worst = RST_OK;
+  int solved = 0;
+  rst_status s = RST_OK;
+  for (int i = 0; i < n_k && s >= 0; ++i) {
+    if (rep[i] != i) continue;
+    if ((s = rst_set_k(c, kpts[2 * i], kpts[2 * i + 1])) != RST_OK) break;
+    rst_stats st;
+    std::memset(&st, 0, sizeof(st));
+    s = rst_transmission(c, n_e, E, tk.data() + (size_t)i * n_e, &st);
+    if (s < 0) break;
+    if (s == RST_ENOCONV) worst = RST_ENOCONV;
+    ++solved;
+    acc.columns += st.columns;
+    acc.columns_unconverged += st.columns_unconverged;
+    acc.iterations_total += st.iterations_total;
+    acc.iterations_max = std::max(acc.iterations_max, st.iterations_max);
+    acc.restarts_total += st.restarts_total;
+    acc.max_rel_residual = std::max(acc.max_rel_residual, st.max_rel_residual);
+    acc.kernel_ms += st.kernel_ms;
+    acc.bytes_algorithmic += st.bytes_algorithmic;
+    acc.updates_total += st.updates_total;
+    acc.fallback_columns += st.fallback_columns;
+    acc.cnn_flop += st.cnn_flop;
+    acc.col_block = st.col_block;
+    acc.threads = st.threads;
+  }
+  // put the caller's k back (or leave none set if there was none)
+  if (had_k) {
+    const std::string err = c->err;
+    const rst_status r = rst_set_k(c, ka0, kb0);
+    if (s >= 0 && r != RST_OK) s = r;
+    if (s < 0 && r == RST_OK) c->err = err;
+  } else {
+    c->has_k = false;
+  }
+  if (s < 0) return s;
+  for (int i = 0; i < n_k; ++i)
+    if (rep[i] != i)
+      std::copy(tk.begin() + (size_t)rep[i] * n_e, tk.begin() + (size_t)(rep[i] + 1) * n_e,
+                tk.begin() + (size_t)i * n_e);
+  for (int e = 0; e < n_e; ++e) {
+    double t = 0.0;
+    for (int i = 0; i < n_k; ++i) t += tk[(size_t)i * n_e + e];
+    T_out[e] = t / n_k;
+  }
+  if (T_k) std::copy(tk.begin(), tk.end(), T_k);
+  if (n_solved) *n_solved = solved;
+  if (stats) *stats = acc;
+  return worst;
+}
+
 rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev, int ncol) {
   rst_status s = check_ready(c);
   if (s != RST_OK) return s;

@@ -24,7 +24,8 @@ RST_PRECOND_NONE, RST_PRECOND_FREE_CAP, RST_PRECOND_LEARNED = 0, 1, 2
 
 EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error", "rst_set_grid",
             "rst_set_potential", "rst_set_projectors", "rst_set_abc", "rst_set_k", "rst_set_solver",
-            "rst_transmission", "rst_apply_h", "rst_apply_timing", "rst_apply_block_width", "rst_apply_h_blocked", "rst_solve_columns", "rst_batch_clear",
+            "rst_transmission", "rst_transmission_kavg", "rst_apply_h", "rst_apply_timing",
+            "rst_apply_block_width", "rst_apply_h_blocked", "rst_solve_columns", "rst_batch_clear",
             "rst_batch_add", "rst_batch_run", "rst_cnn_weight_count", "rst_cnn_seed",
             "rst_cnn_set_weights", "rst_cnn_get_weights", "rst_cnn_forward", "rst_cnn_gradient",
             "rst_cnn_train_step", "rst_precond_train", "rst_solve_rhs", "rst_default_lowrank",
@@ -120,6 +121,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.rst_set_solver.argtypes = [P, C.POINTER(rst_solver_opts)]
     lib.rst_transmission.argtypes = [P, C.c_int, P, P, C.POINTER(rst_stats)]
     lib.rst_apply_h.argtypes = [P, C.c_double, P, P, C.c_int]
+    lib.rst_transmission_kavg.argtypes = [P, C.c_int, P, C.c_int, C.c_int, P, P, P, C.POINTER(C.c_int),
+                                          C.POINTER(rst_stats)]
     lib.rst_apply_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.rst_apply_block_width.argtypes = [P, C.POINTER(C.c_int)]
     lib.rst_apply_h_blocked.argtypes = [P, C.c_double, P, P, C.c_int, C.c_int]
@@ -238,6 +241,19 @@ class Context:
         s = self._chk(self.lib.rst_transmission(self.h, e.size, _ptr(e), _ptr(t), C.byref(st)),
                       allow_noconv=True)
         return t, st.as_dict(), s
+
+    def rst_transmission_kavg(self, kpts, energies, fold=True):
+        """(T(E) averaged over kpts, per-k T (n_k x n_e), k-points solved, stats, status)."""
+        k = np.ascontiguousarray(np.asarray(kpts, np.float64).reshape(-1, 2))
+        e = np.ascontiguousarray(np.atleast_1d(energies), np.float64)
+        t = np.zeros(e.size)
+        tk = np.zeros((k.shape[0], e.size))
+        ns = C.c_int()
+        st = rst_stats()
+        s = self._chk(self.lib.rst_transmission_kavg(self.h, k.shape[0], _ptr(k), int(bool(fold)), e.size, _ptr(e),
+                                                     _ptr(t), _ptr(tk), C.byref(ns), C.byref(st)),
+                      allow_noconv=True)
+        return t, tk, ns.value, st.as_dict(), s
 
     def rst_apply_h(self, energy, x_dev_ptr: int, y_dev_ptr: int, ncol: int):
         return self._chk(self.lib.rst_apply_h(self.h, float(energy), C.c_void_p(x_dev_ptr),

@@ -238,6 +238,40 @@ def test_gpu_time_reversal_and_zone_shift():
     np.testing.assert_allclose(out[2], out[0], atol=1e-8)
 
 
+def test_kpoint_average_with_folding_matches_oracle():
+    """T(E) = mean_k T(E,k) over the tiny config-2 slab's 2x2 Monkhorst-Pack
+    grid: the +-k folding solves two k-points instead of four and still matches
+    the oracle's average (and every per-k value); k + G is folded too; the
+    caller's k is restored."""
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    es = p.energies[[1, 5]]
+    ctx = make_ctx(torch, p, precond=rst.RST_PRECOND_FREE_CAP, tol=1e-10, max_iter=20000)
+    t, tk, ns, st, s = ctx.rst_transmission_kavg(p.kpts, es, fold=True)
+    assert s == rst.RST_OK, st
+    assert ns == 2 and len(p.kpts) == 4
+    ref_k = np.array([oracle.transmission(p, es, k, both=False)["T_LR"] for k in p.kpts])
+    bar = 1e-6 * max(1.0, float(ref_k.max()))
+    np.testing.assert_allclose(tk, ref_k, rtol=0, atol=bar)
+    np.testing.assert_allclose(t, ref_k.mean(axis=0), rtol=0, atol=bar)
+    t2, tk2, ns2, st2, s2 = ctx.rst_transmission_kavg(p.kpts, es, fold=False)
+    assert s2 == rst.RST_OK and ns2 == 4
+    np.testing.assert_allclose(t2, t, rtol=0, atol=bar)
+    assert st2["columns"] == 2 * st["columns"]
+    # the context's own k (the first k-point) is back in place: same launch, same bits
+    t0, _, _ = ctx.rst_transmission(es)
+    np.testing.assert_array_equal(t0, tk[0])
+    # a copy shifted by a reciprocal lattice vector is not solved again
+    ga = 2 * math.pi / (p.na * p.ha)
+    kk = np.array([p.kpts[0], p.kpts[0] + np.array([ga, 0.0])])
+    t3, tk3, ns3, _, _ = ctx.rst_transmission_kavg(kk, es, fold=True)
+    assert ns3 == 1
+    np.testing.assert_array_equal(tk3[0], tk3[1])
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_transmission_kavg(np.zeros((0, 2)), es)
+    assert ei.value.status == rst.RST_EINVAL
+
+
 def test_deterministic_bitwise():
     torch = torch_cuda()
     p = wl.config(2, tiny=True)
