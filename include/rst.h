@@ -61,7 +61,7 @@ typedef enum {
   RST_EUNSUPPORTED = -5   /* valid but not supported by the GPU kernels */
 } rst_status;
 
-typedef enum { RST_BICGSTAB = 0, RST_FGMRES = 1 } rst_method;
+typedef enum { RST_BICGSTAB = 0, RST_FGMRES = 1, RST_COCG = 2 } rst_method;
 typedef enum { RST_FP64 = 0, RST_FP32_REFINE = 1 } rst_precision;
 typedef enum { RST_DIR_LR = 0, RST_DIR_RL = 1 } rst_direction;
 typedef enum { RST_PRECOND_NONE = 0, RST_PRECOND_FREE_CAP = 1, RST_PRECOND_LEARNED = 2 } rst_precond;
@@ -71,7 +71,13 @@ typedef struct {
   int method;        /* rst_method.  RST_BICGSTAB: the persistent fused BiCGSTAB kernels (every precision
                         and preconditioner except RST_PRECOND_LEARNED).  RST_FGMRES: restarted flexible
                         GMRES(restart) in FP64 over chunks of columns (classical Gram-Schmidt twice),
-                        convergence on the FP64 true residual after each cycle; precision FP64 only */
+                        convergence on the FP64 true residual after each cycle; precision FP64 only.
+                        RST_COCG: conjugate orthogonal conjugate gradients (van der Vorst and Melissen
+                        1990) for a real H_k (k_a L_a and k_b L_b multiples of pi, e.g. the Gamma
+                        point: A = E - H_k + i Gamma is then complex symmetric), one operator apply per
+                        step, preconditioner NONE or FREE_CAP, FP64 only, convergence on the FP64 true
+                        residual; a transmission or column solve at any other k returns
+                        RST_EUNSUPPORTED */
   int precision;     /* rst_precision; RST_FP32_REFINE: BiCGSTAB on complex64 vectors with FP32 stencil,
                         projector and preconditioner applies (inner products, scalars and projections
                         FP64), the solution kept as x64 + x32 and the recursive residual replaced by the

@@ -15,6 +15,7 @@
 #include "../../include/rst.h"
 #include "rst_cnn_api.hpp"
 #include "rst_fgmres.hpp"
+#include "rst_cocg.hpp"
 #include "rst_lowrank.hpp"
 #include "rst_projmm.hpp"
 #include "rst_apply_cols.hpp"
@@ -122,6 +123,8 @@ struct rst_ctx {
   double last_cnn_flop = 0.0;     // FGMRES: network flops of the last solve
   double last_fg_bytes = 0.0;     // FGMRES: algorithmic vector bytes of the last solve
   double last_extra_bytes = 0.0;  // mixed precision: bytes of the FP64 re-solves
+  // COCG chunk buffers: R, P, Q vectors; per-column scalars and flags
+  DevBuf d_cgR, d_cgP, d_cgQ, d_cgs, d_cgi;
   // flexible GMRES chunk buffers
   DevBuf d_fgV, d_fgZ, d_fgX, d_fgW, d_fgM, d_fgwb, d_fgx0, d_fgf, d_fgH, d_fgcs, d_fgsn, d_fgg, d_fginv, d_fgest,
       d_fgact, d_fgit, d_fguse, d_fgh1, d_fgh2, d_fgn2, d_fgy, d_fgsrc, d_fgbsc, d_fgt, d_fgaa, d_fgpa, d_fgsa;
@@ -580,6 +583,11 @@ rst_status run_fgmres(rst_ctx* c, int ne, const double* energies, const std::vec
                       std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
                       std::vector<double>& res, std::vector<int>& st, double& ms);
 
+rst_status run_cocg(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
+                    const double* d_gdst, const std::vector<double>* hsrc, double2* xout,
+                    std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
+                    std::vector<double>& res, std::vector<int>& st, double& ms);
+
 rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
                       const double* d_gsrc, const double* d_gdst, double2* xout,
                       std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
@@ -588,6 +596,10 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   if (c->opts.method == RST_FGMRES) {
     const std::vector<double>* hsrc = d_gsrc == nullptr ? nullptr : (d_gsrc == c->d_gr.p ? &c->gr : &c->gl);
     return run_fgmres(c, ne, energies, cols, d_gdst, hsrc, xout, Tcol, its, rss, res, st, ms);
+  }
+  if (c->opts.method == RST_COCG) {
+    const std::vector<double>* hsrc = d_gsrc == nullptr ? nullptr : (d_gsrc == c->d_gr.p ? &c->gr : &c->gl);
+    return run_cocg(c, ne, energies, cols, d_gdst, hsrc, xout, Tcol, its, rss, res, st, ms);
   }
   LaunchShape ls;
   rst_status s = choose_shape(c, c->opts.col_block, c->opts.threads, ls);
@@ -796,7 +808,7 @@ void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const st
   const bool mixed = c->opts.precision == RST_FP32_REFINE && c->last_updates.size() == its.size();
   if (mixed)
     for (int u : c->last_updates) s.updates_total += u;
-  const bool fgm = c->opts.method == RST_FGMRES && n_override == 0.0;
+  const bool fgm = (c->opts.method == RST_FGMRES || c->opts.method == RST_COCG) && n_override == 0.0;
   if (fgm) {
     s.fallback_columns = c->last_fallbacks;
     s.cnn_flop = c->last_cnn_flop;
@@ -1183,6 +1195,341 @@ rst_status run_fgmres(rst_ctx* c, int ne, const double* energies, const std::vec
         c->last_fallbacks += fb[q];
         if (st[(size_t)ie * ncols + c0 + q] != 0 && st[(size_t)ie * ncols + c0 + q] != 2)
           st[(size_t)ie * ncols + c0 + q] = 1;
+      }
+      if (xout) {
+        // x (n x ncols, column fastest) from the blocked X (a test-sized export through the
+        // host, kept out of the reported time)
+        const auto t_exp = std::chrono::steady_clock::now();
+        std::vector<double2> hx(vlen), rows((size_t)n * nc);
+        HIPCHK(c, hipMemcpyAsync(hx.data(), X, vlen * 16, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int q = 0; q < nc; ++q)
+          for (long long p = 0; p < n; ++p) rows[(size_t)p * nc + q] = hx[((size_t)(q / cw) * n + p) * cw + q % cw];
+        HIPCHK(c, hipMemcpy2D(xout + c0, (size_t)ncols * 16, rows.data(), (size_t)nc * 16, (size_t)nc * 16, (size_t)n,
+                              hipMemcpyHostToDevice));
+        export_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_exp).count();
+      }
+    }
+  }
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float fms = 0;
+  HIPCHK(c, hipEventElapsedTime(&fms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  ms = std::max(0.0, (double)fms - export_ms);
+  c->last_fg_bytes = bytes;
+  return RST_OK;
+}
+
+// Preconditioned COCG over chunks of columns (host-driven like FGMRES; every
+// vector operation is a kernel of rst_cocg.hpp, the blocked stencil apply or
+// the M^-1 kernel).  Needs a real H_k: complex symmetric A and M.  The
+// recursive residual norm is read every CHECK steps; a column whose estimate
+// fell below tol, or whose recurrence broke down (p^T A p or rho zero), has
+// its FP64 true residual computed: below tol it is done, otherwise the
+// chunk's residual is replaced by the true one and that column restarts with
+// p = M^-1 r.  Columns still running at max_iter end unconverged.
+rst_status run_cocg(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
+                    const double* d_gdst, const std::vector<double>* hsrc, double2* xout,
+                    std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
+                    std::vector<double>& res, std::vector<int>& st, double& ms) {
+  constexpr int CHECK = 4;
+  const bool usepc = c->opts.precond == RST_PRECOND_FREE_CAP;
+  {
+    const rst::Geo g0 = make_geo(c);
+    if (std::fabs(g0.pha_y) > 1e-12 || std::fabs(g0.phb_y) > 1e-12)
+      return fail(c, RST_EUNSUPPORTED, "COCG needs a real H_k: k_a L_a and k_b L_b must be multiples of pi");
+  }
+  const int P = c->na * c->nb;
+  const long long n = (long long)P * c->nz;
+  const int ncols = (int)cols.size();
+  BlockedShape bs;
+  rst_status s = blocked_shape(c, c->opts.col_block > 0 ? c->opts.col_block : 8, c->opts.threads, bs);
+  if (s != RST_OK) return s;
+  const LaunchShape ls = bs.ls;
+  const int cw = ls.cw;
+  c->last_cw = cw;
+  c->last_threads = ls.threads;
+  void* kapply = pick_kernel(c->rad, ls.q, 1);
+  void* kpc = pick_kernel(c->rad, ls.q, 7);
+  if (!kapply || !kpc) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
+  // chunk of columns: X, R, Z, P, Q, W and the M^-1 work buffer, bounded by a quarter of free memory
+  const size_t per_col = (size_t)7 * n * 16;
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
+  long long chunk = std::min<long long>(512, std::max<long long>(cw, (long long)(free_b / 4 / per_col)));
+  chunk = std::max<long long>(cw, chunk / cw * cw);
+  chunk = std::min<long long>(chunk, ((long long)ncols + cw - 1) / cw * cw);
+  const int ncolp = (int)chunk;
+  const int nblk = ncolp / cw;
+  const size_t vlen = (size_t)nblk * n * cw;
+  rst_status e;
+  if ((e = ensure(c, c->d_fgX, vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgW, vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgM, vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgwb, vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_cgR, vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_cgP, vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_cgQ, vlen * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_cgs, (size_t)6 * ncolp * 16)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_cgi, (size_t)3 * ncolp * 4)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgsrc, (size_t)ncolp * 8)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgbsc, (size_t)ncolp * 8)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_fgt, (size_t)ncolp * 8)) != RST_OK) return e;
+  double2* X = (double2*)c->d_fgX.p;
+  double2* W = (double2*)c->d_fgW.p;
+  double2* Z = (double2*)c->d_fgM.p;
+  double2* R = (double2*)c->d_cgR.p;
+  double2* Pv = (double2*)c->d_cgP.p;
+  double2* Q = (double2*)c->d_cgQ.p;
+  double2* rho = (double2*)c->d_cgs.p;
+  double2* pq = rho + ncolp;
+  double2* rhon = pq + ncolp;
+  double2* n2 = rhon + ncolp;
+  double2* alpha = n2 + ncolp;
+  double2* beta = alpha + ncolp;
+  int* actd = (int*)c->d_cgi.p;
+  int* brkd = actd + ncolp;
+  int* markd = brkd + ncolp;
+  rst::Geo g = make_geo(c);
+  rst::Proj pj = make_proj(c);
+  const size_t pws_stride = std::max<size_t>(1, (size_t)c->nproj * cw);
+  if ((e = ensure(c, c->d_pws, (size_t)nblk * pws_stride * 16)) != RST_OK) return e;
+  if (bs.lds_apply > 64 * 1024)
+    HIPCHK(c, hipFuncSetAttribute(kapply, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bs.lds_apply));
+  if (bs.lds_pc > 64 * 1024)
+    HIPCHK(c, hipFuncSetAttribute(kpc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bs.lds_pc));
+  rst::fg::Shape S{n, cw, nblk, 0, 0};
+  std::vector<double> en(energies, energies + ne);
+  if ((e = upload(c, c->d_en, en)) != RST_OK) return e;
+  double vbar = 0;
+  for (double x : c->v) vbar += x;
+  vbar /= (double)c->v.size();
+  if (usepc && (e = ensure(c, c->d_pc_inv, (size_t)n * 16)) != RST_OK) return e;
+  const size_t nout = (size_t)ne * ncols;
+  Tcol.assign(nout, 0.0);
+  its.assign(nout, 0);
+  rss.assign(nout, 0);
+  res.assign(nout, 0.0);
+  st.assign(nout, 1);
+  c->last_fallbacks = 0;
+  c->last_cnn_flop = 0.0;
+  c->last_updates.clear();
+  double bytes = 0.0;
+  const unsigned gv = (unsigned)((vlen + 255) / 256);
+  const unsigned gc = (unsigned)((ncolp + 63) / 64);
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  double export_ms = 0.0;
+  for (int ie = 0; ie < ne; ++ie) {
+    // operator slots: 0 applies P -> Q, 1 applies X -> W (true residual)
+    std::vector<rst::ApplyArgs> aa(2);
+    for (int j = 0; j < 2; ++j) {
+      rst::ApplyArgs& A = aa[j];
+      std::memset(&A, 0, sizeof(A));
+      A.g = g;
+      A.pj = pj;
+      A.V = (const double*)c->d_v.p;
+      A.gz = (const double*)c->d_gz.p;
+      A.energy = energies[ie];
+      A.x = j == 0 ? Pv : X;
+      A.y = j == 0 ? Q : W;
+      A.ncol = ncolp;
+      A.cw = cw;
+      A.nblk = nblk;
+      A.pws = (double2*)c->d_pws.p;
+      A.pws_stride = pws_stride;
+    }
+    if ((e = upload(c, c->d_fgaa, aa)) != RST_OK) return e;
+    if (usepc) {
+      rst::SolveArgs A;
+      std::memset(&A, 0, sizeof(A));
+      A.g = g;
+      A.gz = (const double*)c->d_gz.p;
+      A.energies = (const double*)c->d_en.p + ie;
+      A.ne = 1;
+      A.pc.vbar = vbar;
+      A.pc.a = 0.5 / (c->hz * c->hz);
+      A.pc.eps = (const double*)c->d_pc_eps.p;
+      A.pc.steps = (const double2*)c->d_pc_twa.p;
+      A.pc.inv = (const double2*)c->d_pc_inv.p;
+      std::vector<rst::SolveArgs> sa(1, A);
+      if ((e = upload(c, c->d_fgsa, sa)) != RST_OK) return e;
+      hipLaunchKernelGGL(rst::k_pc_pivots, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, c->stream,
+                         (const rst::SolveArgs*)c->d_fgsa.p);
+      HIPCHK(c, hipGetLastError());
+      std::vector<rst::PcApplyArgs> pa(1);
+      std::memset(&pa[0], 0, sizeof(pa[0]));
+      pa[0].g = g;
+      pa[0].pc = A.pc;
+      pa[0].in = R;
+      pa[0].out = Z;
+      pa[0].wbuf = (double2*)c->d_fgwb.p;
+      pa[0].cw = cw;
+      pa[0].nblk = nblk;
+      pa[0].pc_lds_off = bs.pc_off;
+      if ((e = upload(c, c->d_fgpa, pa)) != RST_OK) return e;
+    }
+    void* aarg0 = c->d_fgaa.p;
+    void* aarg1 = (char*)c->d_fgaa.p + sizeof(rst::ApplyArgs);
+    void* parg = c->d_fgpa.p;
+    auto apply_pq = [&]() -> rst_status {
+      void* args[] = {&aarg0};
+      HIPCHK(c, hipLaunchKernel(kapply, dim3(nblk), dim3(ls.threads), args, bs.lds_apply, c->stream));
+      return RST_OK;
+    };
+    auto precondition = [&]() -> rst_status {  // Z = M^-1 R (or R)
+      if (usepc) {
+        void* args[] = {&parg};
+        HIPCHK(c, hipLaunchKernel(kpc, dim3(nblk), dim3(ls.threads), args, bs.lds_pc, c->stream));
+      } else {
+        HIPCHK(c, hipMemcpyAsync(Z, R, vlen * 16, hipMemcpyDeviceToDevice, c->stream));
+      }
+      return RST_OK;
+    };
+    // true residual W = b - A X and its squared norms into n2
+    auto true_residual = [&]() -> rst_status {
+      void* args[] = {&aarg1};
+      HIPCHK(c, hipLaunchKernel(kapply, dim3(nblk), dim3(ls.threads), args, bs.lds_apply, c->stream));
+      hipLaunchKernelGGL(rst::fg::k_fg_resid, dim3(gv), dim3(256), 0, c->stream, S, (const long long*)c->d_fgsrc.p,
+                         (const double*)c->d_fgbsc.p, (const double2*)W, W);
+      hipLaunchKernelGGL(rst::cg::k_cg_dot, dim3(nblk), dim3(256), 0, c->stream, S, (const double2*)W,
+                         (const double2*)W, 1, n2, ncolp);
+      HIPCHK(c, hipGetLastError());
+      return RST_OK;
+    };
+    for (int c0 = 0; c0 < ncols; c0 += ncolp) {
+      const int nc = std::min(ncolp, ncols - c0);
+      S.ncol = nc;
+      std::vector<long long> src(ncolp, -1);
+      std::vector<double> bsc(ncolp, 0.0), bnorm(ncolp, 1.0);
+      std::vector<int> act(ncolp, 0), itc(ncolp, 0), rst_n(ncolp, 0), mark(ncolp, 0), need(ncolp, 0);
+      for (int j = 0; j < nc; ++j) {
+        src[j] = cols[c0 + j];
+        const double gs = hsrc ? (*hsrc)[cols[c0 + j] / P] : 1.0;
+        bsc[j] = std::sqrt(gs);
+        bnorm[j] = bsc[j];
+        act[j] = bsc[j] > 0 ? 1 : 0;
+        if (!act[j]) st[(size_t)ie * ncols + c0 + j] = 0;  // zero right-hand side: x = 0
+      }
+      if ((e = upload(c, c->d_fgsrc, src)) != RST_OK) return e;
+      if ((e = upload(c, c->d_fgbsc, bsc)) != RST_OK) return e;
+      HIPCHK(c, hipMemcpyAsync(actd, act.data(), (size_t)ncolp * 4, hipMemcpyHostToDevice, c->stream));
+      std::vector<int> zeros(ncolp, 0), ones(ncolp, 1);
+      HIPCHK(c, hipMemcpyAsync(brkd, zeros.data(), (size_t)ncolp * 4, hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(markd, ones.data(), (size_t)ncolp * 4, hipMemcpyHostToDevice, c->stream));
+      // x = 0, r = b, z = M^-1 r, p = z, rho = r^T z
+      hipLaunchKernelGGL(rst::fg::k_fg_init, dim3(gv), dim3(256), 0, c->stream, S, (const long long*)c->d_fgsrc.p,
+                         (const double*)c->d_fgbsc.p, X, R);
+      HIPCHK(c, hipGetLastError());
+      if ((e = precondition()) != RST_OK) return e;
+      hipLaunchKernelGGL(rst::cg::k_cg_copy_marked, dim3(gv), dim3(256), 0, c->stream, S, Pv, (const double2*)Z,
+                         (const int*)markd);
+      hipLaunchKernelGGL(rst::cg::k_cg_dot, dim3(nblk), dim3(256), 0, c->stream, S, (const double2*)R,
+                         (const double2*)Z, 0, rhon, ncolp);
+      hipLaunchKernelGGL(rst::cg::k_cg_rho_set, dim3(gc), dim3(64), 0, c->stream, ncolp, rho, (const double2*)rhon,
+                         (const int*)markd);
+      HIPCHK(c, hipGetLastError());
+      std::vector<double2> hn2(ncolp);
+      std::vector<int> hbrk(ncolp);
+      int nact = 0;
+      for (int q = 0; q < nc; ++q) nact += act[q];
+      for (int it = 0; it < c->opts.max_iter && nact > 0; ++it) {
+        if ((e = apply_pq()) != RST_OK) return e;
+        hipLaunchKernelGGL(rst::cg::k_cg_dot, dim3(nblk), dim3(256), 0, c->stream, S, (const double2*)Pv,
+                           (const double2*)Q, 0, pq, ncolp);
+        hipLaunchKernelGGL(rst::cg::k_cg_alpha, dim3(gc), dim3(64), 0, c->stream, ncolp, (const double2*)rho,
+                           (const double2*)pq, (const int*)actd, alpha, brkd);
+        hipLaunchKernelGGL(rst::cg::k_cg_xr, dim3(gv), dim3(256), 0, c->stream, S, X, R, (const double2*)Pv,
+                           (const double2*)Q, (const double2*)alpha);
+        HIPCHK(c, hipGetLastError());
+        if ((e = precondition()) != RST_OK) return e;
+        hipLaunchKernelGGL(rst::cg::k_cg_dot, dim3(nblk), dim3(256), 0, c->stream, S, (const double2*)R,
+                           (const double2*)Z, 0, rhon, ncolp);
+        hipLaunchKernelGGL(rst::cg::k_cg_dot, dim3(nblk), dim3(256), 0, c->stream, S, (const double2*)R,
+                           (const double2*)R, 1, n2, ncolp);
+        hipLaunchKernelGGL(rst::cg::k_cg_beta, dim3(gc), dim3(64), 0, c->stream, ncolp, rho, (const double2*)rhon,
+                           (const int*)actd, beta, brkd);
+        hipLaunchKernelGGL(rst::cg::k_cg_p, dim3(gv), dim3(256), 0, c->stream, S, Pv, (const double2*)Z,
+                           (const double2*)beta);
+        HIPCHK(c, hipGetLastError());
+        for (int q = 0; q < nc; ++q) itc[q] += act[q];
+        // apply 48, pq 32, x/r update 96, M^-1 64 (or copy 32), two dots 48, p update 48 B per point
+        bytes += (double)nact * n * (48.0 + 32.0 + 96.0 + (usepc ? 64.0 : 32.0) + 48.0 + 48.0);
+        const bool last = it + 1 == c->opts.max_iter;
+        if ((it + 1) % CHECK != 0 && !last) continue;
+        HIPCHK(c, hipMemcpyAsync(hn2.data(), n2, (size_t)ncolp * 16, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(hbrk.data(), brkd, (size_t)ncolp * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        bool check = last;
+        for (int q = 0; q < nc; ++q) {
+          need[q] = 0;
+          if (!act[q]) continue;
+          const double est = std::sqrt(hn2[q].x) / bnorm[q];
+          if (hbrk[q] || !std::isfinite(est) || est <= c->opts.tol) need[q] = 1;
+          check = check || need[q];
+        }
+        if (!check) continue;
+        // FP64 true residual of the chunk
+        if ((e = true_residual()) != RST_OK) return e;
+        bytes += (double)nact * n * (48.0 + 32.0 + 16.0);
+        HIPCHK(c, hipMemcpyAsync(hn2.data(), n2, (size_t)ncolp * 16, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        bool restart = false;
+        for (int q = 0; q < nc; ++q) {
+          mark[q] = 0;
+          if (!act[q]) continue;
+          const double rel = std::sqrt(hn2[q].x) / bnorm[q];
+          res[(size_t)ie * ncols + c0 + q] = rel;
+          if (rel <= c->opts.tol) {
+            act[q] = 0;
+            st[(size_t)ie * ncols + c0 + q] = 0;
+          } else if (!std::isfinite(rel)) {
+            act[q] = 0;
+            st[(size_t)ie * ncols + c0 + q] = 2;
+          } else if (last) {
+            act[q] = 0;  // iteration cap: unconverged (status 1)
+          } else if (need[q]) {
+            // the estimate fell below tol but the true residual did not, or a breakdown: restart
+            mark[q] = 1;
+            ++rst_n[q];
+            restart = true;
+          }
+        }
+        nact = 0;
+        for (int q = 0; q < nc; ++q) nact += act[q];
+        HIPCHK(c, hipMemcpyAsync(actd, act.data(), (size_t)ncolp * 4, hipMemcpyHostToDevice, c->stream));
+        if (restart && nact > 0) {
+          // marked columns: r = b - A x, z = M^-1 r, p = z, rho = r^T z (the others keep their recurrences)
+          HIPCHK(c, hipMemcpyAsync(markd, mark.data(), (size_t)ncolp * 4, hipMemcpyHostToDevice, c->stream));
+          hipLaunchKernelGGL(rst::cg::k_cg_copy_marked, dim3(gv), dim3(256), 0, c->stream, S, R, (const double2*)W,
+                             (const int*)markd);
+          HIPCHK(c, hipMemcpyAsync(brkd, zeros.data(), (size_t)ncolp * 4, hipMemcpyHostToDevice, c->stream));
+          if ((e = precondition()) != RST_OK) return e;
+          hipLaunchKernelGGL(rst::cg::k_cg_dot, dim3(nblk), dim3(256), 0, c->stream, S, (const double2*)R,
+                             (const double2*)Z, 0, rhon, ncolp);
+          hipLaunchKernelGGL(rst::cg::k_cg_copy_marked, dim3(gv), dim3(256), 0, c->stream, S, Pv, (const double2*)Z,
+                             (const int*)markd);
+          hipLaunchKernelGGL(rst::cg::k_cg_rho_set, dim3(gc), dim3(64), 0, c->stream, ncolp, rho,
+                             (const double2*)rhon, (const int*)markd);
+          HIPCHK(c, hipGetLastError());
+        }
+      }
+      if (d_gdst) {
+        hipLaunchKernelGGL(rst::fg::k_fg_tacc, dim3(nblk), dim3(256), 0, c->stream, S, (const double2*)X, d_gdst,
+                           (long long)P, (double*)c->d_fgt.p);
+        HIPCHK(c, hipGetLastError());
+        std::vector<double> ta(ncolp);
+        HIPCHK(c, hipMemcpyAsync(ta.data(), c->d_fgt.p, (size_t)ncolp * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int q = 0; q < nc; ++q) Tcol[(size_t)ie * ncols + c0 + q] = 4.0 * ta[q];
+      }
+      for (int q = 0; q < nc; ++q) {
+        its[(size_t)ie * ncols + c0 + q] = itc[q];
+        rss[(size_t)ie * ncols + c0 + q] = rst_n[q];
       }
       if (xout) {
         // x (n x ncols, column fastest) from the blocked X (a test-sized export through the
@@ -1741,7 +2088,9 @@ rst_status rst_set_k(rst_ctx* c, double ka, double kb) {
 
 rst_status rst_set_solver(rst_ctx* c, const rst_solver_opts* o) {
   if (!c || !o) return RST_EINVAL;
-  if (o->method != RST_BICGSTAB && o->method != RST_FGMRES) return fail(c, RST_EINVAL, "unknown method");
+  if (o->method != RST_BICGSTAB && o->method != RST_FGMRES && o->method != RST_COCG)
+    return fail(c, RST_EINVAL, "unknown method");
+  if (o->method == RST_COCG && o->precision != RST_FP64) return fail(c, RST_EUNSUPPORTED, "COCG runs in FP64 only");
   if (o->method == RST_FGMRES) {
     if (o->restart < 1 || o->restart > 200) return fail(c, RST_EINVAL, "restart must be in 1..200");
     if (o->precision != RST_FP64) return fail(c, RST_EUNSUPPORTED, "FGMRES runs in FP64 only");

@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("RST_LIB") or os.path.join(_HERE, "librst.so")
 
 RST_OK, RST_ENOCONV = 0, 1
 RST_EINVAL, RST_ESTATE, RST_ENOMEM, RST_EDEVICE, RST_EUNSUPPORTED = -1, -2, -3, -4, -5
-RST_BICGSTAB, RST_FGMRES = 0, 1
+RST_BICGSTAB, RST_FGMRES, RST_COCG = 0, 1, 2
 RST_FP64, RST_FP32_REFINE = 0, 1
 RST_DIR_LR, RST_DIR_RL = 0, 1
 RST_PRECOND_NONE, RST_PRECOND_FREE_CAP, RST_PRECOND_LEARNED = 0, 1, 2

@@ -1,0 +1,101 @@
+"""COCG (method RST_COCG) for real H_k, where A = E - H_k + i Gamma is complex
+symmetric: the Gamma point and the lateral zone boundary.  Parity against the
+CPU oracle through the C ABI, with and without the free-electron + CAP
+preconditioner, plus the option and k errors."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_02783_amd import rst
+from paper_2208_02783_amd import workloads as wl
+from tests import oracle_helpers as hp
+from tests.gpu_util import make_ctx, n_channels, torch_cuda
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("pc", [rst.RST_PRECOND_NONE, rst.RST_PRECOND_FREE_CAP])
+def test_cocg_config1_matches_oracle(pc):
+    """Config 1 (8x8x40 free-electron slab at k = 0) at every fourth stored energy."""
+    torch = torch_cuda()
+    g = json.load(open(os.path.join(GOLD, "config1_T.json")))
+    p = wl.config(1)
+    es = np.array(g["energies"][::4])
+    ref = np.array(g["T_LR"][::4])
+    ctx = make_ctx(torch, p, method=rst.RST_COCG, precond=pc, tol=1e-10, max_iter=20000)
+    t, st, s = ctx.rst_transmission(es)
+    _say("cocg config1 pc", pc, "its/col", st["iterations_total"] / st["columns"], "restarts", st["restarts_total"])
+    assert s == rst.RST_OK, st
+    assert st["max_rel_residual"] <= 1e-10
+    for e, a, b in zip(es, t, ref):
+        assert abs(a - b) <= 1e-6 * max(1, n_channels(p, e, (0.0, 0.0))), (e, a, b)
+
+
+@pytest.mark.parametrize("kind", ["gamma", "zone_boundary"])
+def test_cocg_tiny_fcc_slab_matches_oracle(kind):
+    """Tiny config-2 slab (wells and KB projectors with lateral images) at a real
+    H_k: k = 0, and k_a = pi / L_a where every Bloch phase is -1 or +1."""
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    k = (0.0, 0.0) if kind == "gamma" else (math.pi / (p.na * p.ha), 0.0)
+    es = p.energies[[0, 3, 6]]
+    ctx = make_ctx(torch, p, k, method=rst.RST_COCG, precond=rst.RST_PRECOND_FREE_CAP, tol=1e-10, max_iter=20000)
+    t, st, s = ctx.rst_transmission(es)
+    _say("cocg tiny", kind, "its/col", st["iterations_total"] / st["columns"], "restarts", st["restarts_total"])
+    assert s == rst.RST_OK, st
+    ref = oracle.transmission(p, es, k, both=False)["T_LR"]
+    np.testing.assert_allclose(t, ref, rtol=0, atol=1e-6 * max(1.0, float(ref.max())))
+    if kind == "gamma":
+        # same T as the persistent BiCGSTAB path (at the zone boundary that path leaves
+        # a column of this slab unconverged after 20000 iterations; COCG needs ~80)
+        ctx.rst_set_solver(method=rst.RST_BICGSTAB, precond=rst.RST_PRECOND_FREE_CAP, tol=1e-10, max_iter=20000)
+        tb, _, sb = ctx.rst_transmission(es)
+        assert sb == rst.RST_OK
+        np.testing.assert_allclose(t, tb, rtol=0, atol=1e-6 * max(1.0, float(ref.max())))
+
+
+def test_cocg_solve_columns_match_oracle():
+    torch = torch_cuda()
+    rng = np.random.default_rng(41)
+    p = hp.random_problem(rng, na=5, nb=4, nz=16, order=4, nproj=3, ramp=4)
+    k = (0.0, 0.0)
+    cols = np.array([0, 9, p.n // 2, p.n - 1])
+    for pc in (rst.RST_PRECOND_NONE, rst.RST_PRECOND_FREE_CAP):
+        ctx = make_ctx(torch, p, k, method=rst.RST_COCG, precond=pc, tol=1e-12, max_iter=20000)
+        x, st, s = rst.solve_columns(ctx, 0.37, cols, p.n)
+        assert s == rst.RST_OK, st
+        ref = oracle.green_columns(p, 0.37, k, cols)
+        err = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+        assert err <= 1e-9, (pc, err, st)
+
+
+def test_cocg_option_and_k_errors():
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    ctx = make_ctx(torch, p, p.kpts[0])  # a generic k: H_k complex
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_set_solver(method=rst.RST_COCG, precision=rst.RST_FP32_REFINE)
+    assert ei.value.status == rst.RST_EUNSUPPORTED
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_set_solver(method=rst.RST_COCG, precond=rst.RST_PRECOND_LEARNED)
+    assert ei.value.status == rst.RST_EINVAL
+    ctx.rst_set_solver(method=rst.RST_COCG)
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_transmission(p.energies[:1])
+    assert ei.value.status == rst.RST_EUNSUPPORTED
+    # the batched launch and the dense right-hand sides stay BiCGSTAB-only
+    ctx.rst_set_k(0.0, 0.0)
+    b = torch.zeros((p.n, 1), dtype=torch.complex128, device="cuda")
+    b[0, 0] = 1.0
+    with pytest.raises(rst.RstError) as ei:
+        rst.solve_rhs(ctx, p.energies[:1], b)
+    assert ei.value.status == rst.RST_EUNSUPPORTED
