@@ -276,6 +276,51 @@ def stencil_apply(prob, k, e, ncol=1024, reps=5):
             "max_rel_difference_between_layouts": dif}
 
 
+def cocg_comparison(prob2):
+    """COCG against the persistent BiCGSTAB where H_k is real (k = 0), both with
+    the free-electron + CAP preconditioner to a true relative residual of 1e-10:
+    config 1 (32 energies, all 640 right-CAP columns per energy) and one
+    T(E, k = 0) point of the config-2 slab (all 9826 columns)."""
+    import torch
+    from paper_2208_02783_amd import rst
+    from paper_2208_02783_amd import workloads as wl
+    out = {}
+    p1 = wl.config(1)
+    ctx = rst.Context(0)
+    ctx.load_problem(p1, (0.0, 0.0))
+    r1 = {}
+    for name, m in (("bicgstab", rst.RST_BICGSTAB), ("cocg", rst.RST_COCG)):
+        ctx.rst_set_solver(method=m, precond=1, tol=1e-10, max_iter=20000)
+        t0 = time.perf_counter()
+        t, st, s = ctx.rst_transmission(p1.energies)
+        wall = time.perf_counter() - t0
+        r1[name] = {"points_per_s": len(p1.energies) / wall if s == rst.RST_OK else 0.0, "kernel_ms": st["kernel_ms"],
+                    "iterations_per_column": st["iterations_total"] / st["columns"], "T": t}
+    dt = float(np.max(np.abs(r1["cocg"]["T"] - r1["bicgstab"]["T"])))
+    for v in r1.values():
+        del v["T"]
+    out["config1_32_energies"] = dict(r1, max_abs_dT=dt)
+    ctx2 = rst.Context(0)
+    ctx2.load_problem(prob2, (0.0, 0.0))
+    e = float(prob2.energies[400])
+    r2 = {}
+    for name, m in (("bicgstab", rst.RST_BICGSTAB), ("cocg", rst.RST_COCG)):
+        ctx2.rst_set_solver(method=m, precond=1, tol=1e-10, max_iter=20000)
+        t0 = time.perf_counter()
+        t, st, s = ctx2.rst_transmission(np.array([e]))
+        wall = time.perf_counter() - t0
+        r2[name] = {"seconds": wall, "kernel_ms": st["kernel_ms"], "status": int(s), "T": float(t[0]),
+                    "iterations_per_column": st["iterations_total"] / st["columns"],
+                    "achieved_GBps": st["bytes_algorithmic"] / (st["kernel_ms"] * 1e-3) / 1e9}
+    out["config2_gamma_point"] = dict(r2, abs_dT=abs(r2["cocg"]["T"] - r2["bicgstab"]["T"]),
+                                      workload=f"config-2 slab at k = 0, E = {e:.4f}, all 9826 right-CAP columns")
+    print(f"cocg vs bicgstab: config 1 {r1['cocg']['kernel_ms']:.0f} vs {r1['bicgstab']['kernel_ms']:.0f} ms; "
+          f"config-2 point at Gamma {r2['cocg']['seconds']:.1f} vs {r2['bicgstab']['seconds']:.1f} s "
+          f"({r2['cocg']['iterations_per_column']:.0f} vs {r2['bicgstab']['iterations_per_column']:.0f} its/col)",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,6 +336,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank transmission comparison")
     ap.add_argument("--no-stencil", action="store_true", help="skip the stand-alone operator apply")
+    ap.add_argument("--no-cocg", action="store_true", help="skip the COCG comparison at k = 0")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="before the run, copy this many GiB device-to-device (a reference "
                          "kernel of known traffic for hardware-counter scaling)")
@@ -386,6 +432,8 @@ def main():
         line["stencil"] = stencil_apply(prob, res[0][3], res[0][4])
     if not args.no_batched:
         line["batched"] = batched_comparison()
+    if not args.no_cocg:
+        line["cocg"] = cocg_comparison(prob)
     if not args.no_mixed and args.precision == "fp64":
         line["mixed"] = mixed_point(prob, res[0][3], res[0][4], res[0][0])
     if not args.no_learned:

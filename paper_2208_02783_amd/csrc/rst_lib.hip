@@ -1254,11 +1254,12 @@ rst_status run_cocg(rst_ctx* c, int ne, const double* energies, const std::vecto
   void* kapply = pick_kernel(c->rad, ls.q, 1);
   void* kpc = pick_kernel(c->rad, ls.q, 7);
   if (!kapply || !kpc) return fail(c, RST_EUNSUPPORTED, "no kernel instance");
-  // chunk of columns: X, R, Z, P, Q, W and the M^-1 work buffer, bounded by a quarter of free memory
+  // chunk of columns: X, R, Z, P, Q, W and the M^-1 work buffer, bounded by a quarter of free memory;
+  // wide chunks give the blocked kernels enough workgroups (4096 columns of config 2: 22 GB)
   const size_t per_col = (size_t)7 * n * 16;
   size_t free_b = 0, total_b = 0;
   HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
-  long long chunk = std::min<long long>(512, std::max<long long>(cw, (long long)(free_b / 4 / per_col)));
+  long long chunk = std::min<long long>(4096, std::max<long long>(cw, (long long)(free_b / 4 / per_col)));
   chunk = std::max<long long>(cw, chunk / cw * cw);
   chunk = std::min<long long>(chunk, ((long long)ncols + cw - 1) / cw * cw);
   const int ncolp = (int)chunk;
