@@ -198,8 +198,13 @@ rst_status rst_transmission_kavg(rst_ctx *ctx, int n_k, const double *kpts, int 
                                  const double *E, double *T_out, double *T_k, int *n_solved,
                                  rst_stats *stats);
 
-/* Test hook: y = (E - H_k + i Gamma) x for an (n x ncol) complex128 block.
- * x_dev and y_dev are distinct device buffers of n*ncol*16 bytes. */
+/* y = (E - H_k + i Gamma) x for an (n x ncol) complex128 block, column fastest
+ * (element (gi, c) at gi*ncol + c): the FD Laplacian with Bloch-phase lateral
+ * wraps, V, the CAPs and the KB projectors (Bloch-form and transmission
+ * equations).  x_dev and y_dev are distinct device buffers of n*ncol*16 bytes;
+ * a projection buffer of nproj*ncol*16 bytes is grown on demand.  Any lateral
+ * size (one wavefront per grid point and 64 columns).  RST_EINVAL for x == y,
+ * a negative ncol or a non-finite energy. */
 rst_status rst_apply_h(rst_ctx *ctx, double energy, const void *x_dev, void *y_dev, int ncol);
 
 /* Widest column block the blocked apply supports on the current grid (a power
