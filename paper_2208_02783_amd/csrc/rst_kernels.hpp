@@ -254,6 +254,8 @@ struct ColState {
   long long src[CW_MAX], j0[CW_MAX], rmax_idx[CW_MAX];
   int state[CW_MAX];       // 0 active, 1 done, 2 failed, 3 padding
   int iters[CW_MAX], restarts[CW_MAX];
+  // smallest recursive ||r||^2 since the last restart (divergence guard)
+  double rrmin[CW_MAX];
   // mixed precision: largest recursive ||r||^2 since the last FP64 residual
   // replacement, ||r||^2 at it and the latest recursive ||r||^2, the
   // replacements so far, how the next replacement treats x32 (1 fold, 0
@@ -265,6 +267,22 @@ struct ColState {
   int any_flag;
   int item;
 };
+
+// Restart guards of the preconditioned fused BiCGSTAB loop.  With the unit
+// shadow vector e_j0, rho = r[j0] is one residual element: once it is tiny
+// next to ||r|| the next alpha and beta carry no information (near-breakdown),
+// and a recursion that has grown far above its best residual is diverging.
+// Either sends the column to the FP64 true residual and a restart with
+// j0 = argmax |r|.  (Measured: without them the preconditioned solver diverged
+// on a few columns at the lateral zone boundary, k_a L_a = pi; the
+// unpreconditioned solver, whose residual history spikes far more, converges
+// there without them and is slowed down twofold by them, so it does not use them.)
+constexpr double NEAR_BREAKDOWN2 = 1e-28;  // |rho|^2 <= this * ||r||^2
+constexpr double DIVERGENCE2 = 1e10;       // ||r||^2 > this * min ||r||^2 since the restart
+
+__device__ __forceinline__ bool needs_restart(const ColState& S, int c, double rr) {
+  return rr > DIVERGENCE2 * S.rrmin[c] || (S.rho[c].x * S.rho[c].x + S.rho[c].y * S.rho[c].y) <= NEAR_BREAKDOWN2 * rr;
+}
 
 // Vectors of one workgroup.
 template <class R>

@@ -326,6 +326,7 @@ __device__ __forceinline__ void pc_true_residual_and_restart(const SolveArgs& A,
       } else {
         S.j0[c] = S.rmax_idx[c];
         S.restarts[c] += 1;
+        S.rrmin[c] = rr;
         atomicOr(&S.any_flag, 1);
       }
     }
@@ -365,6 +366,7 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
     S.alpha[c] = S.omega[c] = S.beta[c] = mkc(0.0, 0.0);
     S.iters[c] = 0;
     S.restarts[c] = 0;
+    S.rrmin[c] = HUGE_VAL;
     S.tacc[c] = 0.0;
     S.rr[c] = 0.0;
     if (col < A.ncols) {
@@ -494,7 +496,8 @@ __device__ __forceinline__ void pc_solve_item(const SolveArgs& A, SweepCtx<R>& C
           S.rho[c] = S.rho_new[c];
           const double rr = red_out[0][c];
           S.rr[c] = rr;
-          if (!isfinite(rr) || rr <= A.tol * A.tol * S.bb[c]) atomicOr(&S.any_flag, 1);
+          S.rrmin[c] = fmin(S.rrmin[c], rr);
+          if (!isfinite(rr) || rr <= A.tol * A.tol * S.bb[c] || needs_restart(S, c, rr)) atomicOr(&S.any_flag, 1);
         }
       }
       __syncthreads();

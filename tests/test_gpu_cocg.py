@@ -54,13 +54,13 @@ def test_cocg_tiny_fcc_slab_matches_oracle(kind):
     assert s == rst.RST_OK, st
     ref = oracle.transmission(p, es, k, both=False)["T_LR"]
     np.testing.assert_allclose(t, ref, rtol=0, atol=1e-6 * max(1.0, float(ref.max())))
-    if kind == "gamma":
-        # same T as the persistent BiCGSTAB path (at the zone boundary that path leaves
-        # a column of this slab unconverged after 20000 iterations; COCG needs ~80)
-        ctx.rst_set_solver(method=rst.RST_BICGSTAB, precond=rst.RST_PRECOND_FREE_CAP, tol=1e-10, max_iter=20000)
-        tb, _, sb = ctx.rst_transmission(es)
-        assert sb == rst.RST_OK
-        np.testing.assert_allclose(t, tb, rtol=0, atol=1e-6 * max(1.0, float(ref.max())))
+    # same T as the persistent preconditioned BiCGSTAB (at the zone boundary a few columns of
+    # this slab need its near-breakdown / divergence restarts to converge)
+    ctx.rst_set_solver(method=rst.RST_BICGSTAB, precond=rst.RST_PRECOND_FREE_CAP, tol=1e-10, max_iter=20000)
+    tb, stb, sb = ctx.rst_transmission(es)
+    _say("bicgstab", kind, "its/col", stb["iterations_total"] / stb["columns"], "restarts", stb["restarts_total"])
+    assert sb == rst.RST_OK, stb
+    np.testing.assert_allclose(tb, ref, rtol=0, atol=1e-6 * max(1.0, float(ref.max())))
 
 
 def test_cocg_solve_columns_match_oracle():
