@@ -154,8 +154,9 @@ def learned_comparison(prob, ncols=32, pairs=4000, tol=1e-8):
     """Learned preconditioner on the slab's geometry: the network is trained on
     generated pairs (r = A M^-1 xi, e = M^-1 xi over the slab's energies and k
     points), then a bounded sample of right-CAP columns at one (E, k) is solved
-    to `tol` by BiCGSTAB with M^-1, FGMRES(30) with M^-1 and FGMRES(30) with the
-    learned correction."""
+    to `tol` by BiCGSTAB with M^-1, the unpreconditioned BiCGSTAB and FGMRES(30),
+    FGMRES(30) with M^-1 and FGMRES(30) with the learned correction (every solver
+    capped at 6000 iterations; its status says whether it converged)."""
     from paper_2208_02783_amd import rst
     k = prob.kpts[9]
     e = float(prob.energies[400])
@@ -169,6 +170,8 @@ def learned_comparison(prob, ncols=32, pairs=4000, tol=1e-8):
           f"{ts['loss_last']:.3g}", file=sys.stderr, flush=True)
     res, xs = {}, {}
     runs = [("bicgstab_free_cap", dict(method=rst.RST_BICGSTAB, precond=rst.RST_PRECOND_FREE_CAP)),
+            ("bicgstab_none", dict(method=rst.RST_BICGSTAB, precond=rst.RST_PRECOND_NONE)),
+            ("fgmres_none", dict(method=rst.RST_FGMRES, precond=rst.RST_PRECOND_NONE, restart=30)),
             ("fgmres_free_cap", dict(method=rst.RST_FGMRES, precond=rst.RST_PRECOND_FREE_CAP, restart=30)),
             ("fgmres_learned", dict(method=rst.RST_FGMRES, precond=rst.RST_PRECOND_LEARNED, restart=30))]
     for name, kw in runs:
