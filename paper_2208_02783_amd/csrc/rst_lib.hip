@@ -1871,7 +1871,9 @@ rst_status rst_batch_run(rst_ctx* c, double* T_out, rst_stats* stats) {
   int cw = c->opts.col_block;
   rst_status s;
   if (cw == 0) {
-    // autotune: time every candidate on the costliest structure (2 energies)
+    // autotune: time every candidate on every structure at its first energy, a sample large
+    // enough to fill the device like the full launch does (timed on one structure alone, the
+    // half-empty device favoured wide column blocks that lose on the full batch)
     const long long key = ((long long)c->na << 40) ^ ((long long)c->nb << 24) ^ ((long long)c->rad << 8) ^
                           ((long long)c->opts.precond << 4) ^ c->opts.direction;
     auto it = c->tuned_cw.find(key);
@@ -1880,17 +1882,11 @@ rst_status rst_batch_run(rst_ctx* c, double* T_out, rst_stats* stats) {
     } else {
       int best = 1;
       double best_t = 1e300;
-      int worst = 0;
-      double cost = -1;
-      for (size_t i = 0; i < c->batch.size(); ++i) {
-        const double ci = (double)c->batch[i].nz * c->batch[i].en.size();
-        if (ci > cost) { cost = ci; worst = (int)i; }
-      }
       for (int cand : {1, 2, 4, 8}) {
         LaunchShape ls;
         if (choose_shape(c, cand, c->opts.threads, ls) != RST_OK) continue;
         BatchOut o;
-        if ((s = run_batch(c, {worst}, 2, cand, false, o)) != RST_OK) return s;
+        if ((s = run_batch(c, all, 1, cand, false, o)) != RST_OK) return s;
         const double per = o.ms / std::max<size_t>(1, o.its.size());
         if (per < best_t) { best_t = per; best = cand; }
       }
