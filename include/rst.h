@@ -280,7 +280,11 @@ rst_status rst_transmission_lowrank(rst_ctx *ctx, int n_e, const double *energie
  * BiCGSTAB, with or without the free-electron + CAP preconditioner).  With col_block = 0 the columns per workgroup are
  * chosen by timing the candidates on a sample of the batch (cached per lateral
  * shape); the launch is captured in a HIP graph and replayed while the batch is
- * unchanged. */
+ * unchanged.  When every structure alone has at least 64 column items per
+ * compute unit (columns x energies), the structures run instead as
+ * single-structure launches back to back on the context's stream (one column
+ * per workgroup unless col_block says otherwise): such work already fills the
+ * device, where the single-structure kernel is the faster one. */
 rst_status rst_batch_clear(rst_ctx *ctx);
 rst_status rst_batch_add(rst_ctx *ctx, const rst_problem *prob);
 rst_status rst_batch_run(rst_ctx *ctx, double *T_out, rst_stats *stats);

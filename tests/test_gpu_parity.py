@@ -436,6 +436,27 @@ def test_batch_equals_individual_launches(pc):
     np.testing.assert_allclose(tb2, tb, rtol=0, atol=1e-9)
 
 
+def test_batch_of_large_structures_runs_per_structure():
+    """Three slabs with 32 energies each (20,480 column items per slab, enough to
+    fill the device many times) take the per-structure launches: bitwise the T of
+    one rst_transmission call per slab, and a second run gives the same bits."""
+    torch = torch_cuda()
+    slabs = wl.batch_slabs(n_slabs=3, ne=32, cells=(6, 8))
+    ctx = _batch_ctx(slabs, precond=1)
+    tb, st, s = ctx.rst_batch_run()
+    _say("large batch stats", st)
+    assert s == rst.RST_OK and st["col_block"] == 1 and st["threads"] == 64
+    ti = []
+    for p in slabs:
+        c1 = make_ctx(torch, p, p.kpts[0], precond=1)
+        t, _, s1 = c1.rst_transmission(p.energies)
+        assert s1 == rst.RST_OK
+        ti.append(t)
+    assert np.array_equal(tb, np.concatenate(ti))
+    tb2, _, s2 = ctx.rst_batch_run()
+    assert s2 == rst.RST_OK and np.array_equal(tb2, tb)
+
+
 @pytest.mark.parametrize("pc", [0, 1])
 def test_batch_matches_oracle_and_graph_replay(pc):
     torch = torch_cuda()
