@@ -263,6 +263,7 @@ struct ColState {
   // since it last fell tenfold, the block's request
   double maxrr[CW_MAX], rr_upd[CW_MAX], rr_rec[CW_MAX], best_rr[CW_MAX];
   int updates[CW_MAX], fold[CW_MAX], stall[CW_MAX];
+  int it_upd[CW_MAX];  // mixed precision: iteration of the last FP64 residual replacement
   int upd_flag;
   int any_flag;
   int item;

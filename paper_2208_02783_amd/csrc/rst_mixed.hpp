@@ -23,7 +23,11 @@
 // (the FP32 increment was not reliable) and the block restarts.  A column
 // whose best true residual norm has not fallen tenfold over STALL_UPDATES
 // replacements is given up (status not converged): the library then solves it
-// again with the FP64 kernel.
+// again with the FP64 kernel.  So is a column whose FP32 recursion has gone
+// NOPROG_ITERS iterations without a replacement (it neither falls by delta nor
+// diverges, so the replacement count alone would never stop it): it gets a
+// replacement with its stall budget spent, and unless its true residual has
+// fallen a hundredfold below its best, it goes to the FP64 kernel.
 #pragma once
 #include "rst_precond.hpp"
 
@@ -32,6 +36,7 @@ namespace rst {
 constexpr double DIVERGE2 = 1e10;  // squared-norm growth that discards x32
 constexpr double GAP2 = 100.0;     // ||r_true||^2 / ||r_rec||^2 that takes a fold back
 constexpr int STALL_UPDATES = 30;  // replacements without a tenfold fall of the best residual
+constexpr int NOPROG_ITERS = 1000; // FP32 iterations without a replacement (a column replaces every ~25)
 
 // x64 += fold[c] * x32 (fold 1, 0 or -1) over all planes, with the gather of
 // the new x64 into C.acc and the transmission accumulator sum_z gdst(z) |x64|^2.
@@ -190,6 +195,7 @@ __device__ __forceinline__ void reliable_update(const SolveArgs& A, SweepCtx<dou
         }
         S.maxrr[c] = rr;
         S.rr_upd[c] = rr;
+        S.it_upd[c] = S.iters[c];
         if (restart) {
           S.j0[c] = S.rmax_idx[c];
           S.restarts[c] += 1;
@@ -247,6 +253,7 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
     S.updates[c] = 0;
     S.fold[c] = 1;
     S.stall[c] = 0;
+    S.it_upd[c] = 0;
     S.tacc[c] = 0.0;
     S.rr[c] = 0.0;
     if (col < A.ncols) {
@@ -461,6 +468,9 @@ __device__ __forceinline__ void mixed_solve_item(const SolveArgs& A, SweepCtx<do
             S.fold[c] = 0;
             atomicOr(&S.any_flag, 2);
           } else if (rr <= A.tol * A.tol * S.bb[c] || rr < d2max * S.maxrr[c]) {
+            atomicOr(&S.any_flag, 1);
+          } else if (S.iters[c] - S.it_upd[c] >= NOPROG_ITERS) {
+            S.stall[c] = STALL_UPDATES - 1;  // the replacement below decides: FP64 unless it fell 100x
             atomicOr(&S.any_flag, 1);
           } else if (rr > S.maxrr[c]) {
             S.maxrr[c] = rr;
