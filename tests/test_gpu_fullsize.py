@@ -8,13 +8,20 @@ any size: sampled Green's columns are verified with the oracle's own apply (the
 true residual recomputed in FP64 on the CPU), and T(E,k) over all 9826 columns
 against the independent low-rank route (random probes, Cholesky QR, adjoint
 solves at -k), against the left-CAP direction (T_LR = T_RL for any Hermitian
-H_k and real CAPs, transmission equation) and for positivity."""
+H_k and real CAPs, transmission equation) and for positivity.  The same column
+check runs for the FP32-apply / FP64-refinement mode.
+
+Config 4 at its full size (96 uneven free-electron slabs 8x8x48..160) in the
+batched launch the benchmark times: with V = 0 and no projectors, T(E,k) is the
+sum over the lateral modes of 1D chain transmissions at E - eps_perp, an
+identity that holds at any size and is computed here by an independent helper."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2208_02783_amd import rst
 from paper_2208_02783_amd import workloads as wl
+from tests import oracle_helpers as hp
 from tests.gpu_util import make_ctx, torch_cuda
 
 pytestmark = pytest.mark.gpu
@@ -77,3 +84,58 @@ def test_full_size_point_lowrank_and_rl_agree():
     assert srl == rst.RST_OK, strl
     assert strl["columns"] == p.l_columns().size
     assert abs(trl[0] - t[0]) <= bar, (trl[0], t[0])
+
+
+def test_full_size_mixed_sampled_columns_true_residual_by_oracle():
+    """FP32 BiCGSTAB with FP64 reliable updates on the same eight columns: the
+    oracle's FP64 residual meets the same bar as the FP64 path."""
+    torch = torch_cuda()
+    p, k, e = _problem()
+    ctx = _ctx(torch, p, k, precision=rst.RST_FP32_REFINE)
+    rc = p.r_columns()
+    cols = rc[np.linspace(0, rc.size - 1, 8).round().astype(int)]
+    _say("full-size mixed columns", cols.tolist())
+    x, st, s = rst.solve_columns(ctx, e, cols, p.n)
+    _say("mixed stats: iterations/column", st["iterations_total"] / st["columns"],
+         "FP64 replacements/column", st["updates_total"] / st["columns"])
+    assert s == rst.RST_OK, st
+    x = x.cpu().numpy()
+    b = np.zeros_like(x)
+    b[cols, np.arange(cols.size)] = 1.0
+    res = oracle.residual_norms(p, k, e, x, b)
+    _say("oracle-recomputed true residuals (mixed)", res)
+    assert np.all(res <= 2 * TOL), res
+
+
+def test_config4_full_batch_matches_separable_closed_form():
+    """All 96 config-4 slabs at the benchmark's two energies each, one batched
+    launch (autotuned column block, free-electron + CAP preconditioner), the
+    second run a HIP-graph replay of the first: bitwise equal runs, and every T
+    within 1e-6 max(1, T) of the sum of 1D chain transmissions."""
+    torch_cuda()
+    slabs = wl.batch_slabs(n_slabs=96, ne=128)
+    pick = np.linspace(0, 127, 2).round().astype(int)
+    p0 = slabs[0]
+    ctx = rst.Context(0)
+    ctx.rst_set_grid(p0.na, p0.nb, p0.nz, p0.ha, p0.hb, p0.hz, p0.order)
+    ctx.rst_set_solver(precond=rst.RST_PRECOND_FREE_CAP)
+    for p in slabs:
+        assert not p.v.any() and p.proj.nproj == 0
+        ctx.rst_batch_add(p.nz, p.v, p.gamma_l, p.gamma_r, p.kpts[0][0], p.kpts[0][1], p.energies[pick])
+    t1, st, s1 = ctx.rst_batch_run()
+    t2, _, s2 = ctx.rst_batch_run()
+    _say("config-4 batch: col_block", st["col_block"], "threads", st["threads"], "columns", st["columns"])
+    assert s1 == rst.RST_OK and s2 == rst.RST_OK
+    assert np.array_equal(t1, t2)
+    worst = 0.0
+    i = 0
+    for p in slabs:
+        ep = hp.lateral_energies(p.na, p.nb, p.ha, p.hb, p.kpts[0], p.order)
+        for e in p.energies[pick]:
+            ref = sum(hp.t1d(e - x, p.nz, p.hz, p.order, p.gamma_l, p.gamma_r) for x in ep)
+            d = abs(t1[i] - ref)
+            worst = max(worst, d)
+            assert d <= 1e-6 * max(1.0, ref), (p.name, e, t1[i], ref)
+            i += 1
+    assert i == t1.size == 192
+    _say("config-4 batch: max |T - separable sum|", worst)
