@@ -9,7 +9,8 @@ true residual recomputed in FP64 on the CPU), and T(E,k) over all 9826 columns
 against the independent low-rank route (random probes, Cholesky QR, adjoint
 solves at -k), against the left-CAP direction (T_LR = T_RL for any Hermitian
 H_k and real CAPs, transmission equation) and for positivity.  The same column
-check runs for the FP32-apply / FP64-refinement mode.
+check runs for the FP32-apply / FP64-refinement mode, for COCG at the Gamma
+point (where H_k is real) and for FGMRES, both with the same preconditioner.
 
 Config 4 at its full size (96 uneven free-electron slabs 8x8x48..160) in the
 batched launch the benchmark times: with V = 0 and no projectors, T(E,k) is the
@@ -139,3 +140,29 @@ def test_config4_full_batch_matches_separable_closed_form():
             i += 1
     assert i == t1.size == 192
     _say("config-4 batch: max |T - separable sum|", worst)
+
+
+@pytest.mark.parametrize("method", ["cocg_gamma", "fgmres"])
+def test_full_size_other_krylov_methods_sampled_columns(method):
+    """Four of the sampled columns by COCG at k = 0 (complex symmetric A) and by
+    FGMRES(m), both right-preconditioned by the free-electron + CAP operator:
+    the oracle's FP64 residual meets the same bar."""
+    torch = torch_cuda()
+    p, k, e = _problem()
+    if method == "cocg_gamma":
+        k = (0.0, 0.0)
+        ctx = _ctx(torch, p, k, method=rst.RST_COCG)
+    else:
+        ctx = _ctx(torch, p, k, method=rst.RST_FGMRES)
+    rc = p.r_columns()
+    cols = rc[np.linspace(0, rc.size - 1, 4).round().astype(int)]
+    _say(method, "full-size columns", cols.tolist(), "k", k)
+    x, st, s = rst.solve_columns(ctx, e, cols, p.n)
+    _say(method, "iterations/column", st["iterations_total"] / st["columns"], "restarts", st["restarts_total"])
+    assert s == rst.RST_OK, st
+    x = x.cpu().numpy()
+    b = np.zeros_like(x)
+    b[cols, np.arange(cols.size)] = 1.0
+    res = oracle.residual_norms(p, k, e, x, b)
+    _say(method, "oracle-recomputed true residuals", res)
+    assert np.all(res <= 2 * TOL), res
