@@ -84,7 +84,8 @@ typedef struct {
                         FP64 true residual b - A x64 whenever it has fallen by update_delta (reliable
                         updates, Sleijpen and van der Vorst 1996); convergence is decided on the FP64
                         true residual.  A column whose best FP64 residual has not fallen tenfold over
-                        30 replacements is solved again in FP64 (stats.fallback_columns) */
+                        30 replacements, or that ran 1000 FP32 iterations without a replacement, is
+                        solved again in FP64 (stats.fallback_columns) */
   double tol;        /* stop when the FP64 true residual ||b - A x|| <= tol ||b|| per column (default 1e-10) */
   int max_iter;      /* BiCGSTAB iterations per column (default 20000) */
   int col_block;     /* columns solved together by one workgroup; 0 = automatic */
@@ -144,19 +145,29 @@ typedef struct {
 
 void rst_default_solver(rst_solver_opts *opts);
 
-/* Creates a context on HIP device `hip_device`.  `hip_stream` (a hipStream_t)
- * may be NULL, in which case the context creates and owns a stream. */
+/* Creates a context on HIP device `hip_device` into *out.  `hip_stream` (a
+ * hipStream_t) may be NULL, in which case the context creates and owns a
+ * stream; a caller's stream stays the caller's.  RST_EINVAL for a null out,
+ * RST_EDEVICE for a device that does not exist or a failed stream creation
+ * (*out is then NULL). */
 rst_status rst_create(rst_ctx **out, int hip_device, void *hip_stream);
+/* Frees the context and every device buffer it allocated (NULL is ignored). */
 void rst_destroy(rst_ctx *ctx);
+/* Message of the last failed call on ctx, owned by the context and valid until
+ * its next call. */
 const char *rst_last_error(const rst_ctx *ctx);
 
 /* Grid of na x nb x nz points with spacings ha, hb, hz (bohr); fd_order even
- * in 2..12.  The GPU kernels require na > fd_order/2 and nb > fd_order/2
- * (RST_EUNSUPPORTED otherwise). */
+ * in 2..12 (the order-2M central Laplacian of the Bloch-form equation).
+ * RST_EINVAL for non-positive sizes or spacings, another order, or more than
+ * 2^31 - 1 points.  The GPU kernels require na > fd_order/2 and
+ * nb > fd_order/2 (RST_EUNSUPPORTED otherwise), and are built for orders 4
+ * and 12: the compute calls return RST_EUNSUPPORTED for the others. */
 rst_status rst_set_grid(rst_ctx *ctx, int na, int nb, int nz, double ha, double hb, double hz,
                         int fd_order);
 
-/* Local potential V, n = na*nb*nz doubles (Ha), host memory, copied. */
+/* Local potential V, n = na*nb*nz doubles (Ha), host memory, copied.
+ * RST_ESTATE before rst_set_grid; RST_EINVAL for NULL or a non-finite value. */
 rst_status rst_set_potential(rst_ctx *ctx, const double *v);
 
 /* Separable projectors in compressed rows over projectors: entries
@@ -166,14 +177,25 @@ rst_status rst_set_potential(rst_ctx *ctx, const double *v);
 rst_status rst_set_projectors(rst_ctx *ctx, int nproj, const int32_t *offs, const int32_t *pt,
                               const int8_t *img, const double *beta, const double *e_kb);
 
-/* CAP strengths Gamma_L(iz), Gamma_R(iz) >= 0 (nz doubles each, Ha), copied.
- * The solve columns of RST_DIR_LR are all grid points of the planes with
- * Gamma_R > 0 (RST_DIR_RL: Gamma_L > 0). */
+/* CAP strengths Gamma_L(iz), Gamma_R(iz) >= 0 (nz doubles each, Ha), copied
+ * (the absorbing terms of the retarded Green's function, Sec. II.A).  The
+ * solve columns of RST_DIR_LR are all grid points of the planes with
+ * Gamma_R > 0 (RST_DIR_RL: Gamma_L > 0).  RST_ESTATE before rst_set_grid;
+ * RST_EINVAL for NULL, a negative or a non-finite value. */
 rst_status rst_set_abc(rst_ctx *ctx, const double *gamma_l_z, const double *gamma_r_z);
 
-/* Lateral Bloch vector (bohr^-1) along a and b. */
+/* Lateral Bloch vector (bohr^-1) along a and b (the phases exp(i k_a L_a),
+ * exp(i k_b L_b) of the Bloch-form equation).  RST_ESTATE before
+ * rst_set_grid; RST_EINVAL for a non-finite component. */
 rst_status rst_set_k(rst_ctx *ctx, double ka, double kb);
 
+/* Copies the solver options (rst_solver_opts above).  RST_EINVAL for NULL, an
+ * unknown method, precision, direction or preconditioner, tol <= 0,
+ * max_iter < 1, a col_block other than 0 or a power of two <= 8, threads not 0
+ * or a multiple of 64 <= 512, update_delta outside (0, 1), restart outside
+ * 1..200 (FGMRES), fallback_ratio outside (0, 1] or the learned
+ * preconditioner with another method than FGMRES; RST_EUNSUPPORTED for
+ * FGMRES or COCG with RST_FP32_REFINE. */
 rst_status rst_set_solver(rst_ctx *ctx, const rst_solver_opts *opts);
 
 /* T(E_j, k) for j < n_e into T_out (host, caller-allocated, n_e doubles).
@@ -234,7 +256,11 @@ rst_status rst_apply_h_blocked(rst_ctx *ctx, double energy, const void *x_dev, v
 rst_status rst_apply_timing(const rst_ctx *ctx, double *proj_ms, double *stencil_ms);
 
 /* Green's function columns: x_dev[:, j] = G e_{col[j]} (complex128, n x ncol,
- * device).  col holds ncol grid indices (host). */
+ * column fastest, device, caller-allocated; the retarded G of Sec. II.A) with
+ * the context's solver options.  col holds ncol grid indices (host).
+ * RST_EINVAL for ncol < 0, NULL arguments, an index outside 0..n-1 or a
+ * non-finite energy; RST_ESTATE before the problem is set; RST_ENOCONV if a
+ * column missed the tolerance (x is still written). */
 rst_status rst_solve_columns(rst_ctx *ctx, double energy, int ncol, const int64_t *col,
                              void *x_dev, rst_stats *stats);
 
