@@ -41,3 +41,26 @@ def test_missing_library_fails_loudly(tmp_path):
             rst.load(str(tmp_path / "nope.so"))
     finally:
         rst._lib = saved
+
+
+@pytest.mark.skipif(not os.path.exists(rst.LIB_PATH), reason="librst.so not built")
+def test_host_side_argument_errors_and_defaults():
+    """Documented behaviour that needs no device: null contexts and outputs are
+    refused with RST_EINVAL before any HIP call, rst_destroy(NULL) is a no-op,
+    the network's weight count follows the documented layer layout and the
+    low-rank options have their documented defaults."""
+    lib = rst.load()
+    assert lib.rst_create(None, 0, None) == rst.RST_EINVAL
+    lib.rst_destroy(None)
+    assert lib.rst_last_error(None) == b"null context"
+    assert lib.rst_set_grid(None, 8, 8, 8, 0.5, 0.5, 0.5, 4) == rst.RST_EINVAL
+    assert lib.rst_set_k(None, 0.0, 0.0) == rst.RST_EINVAL
+    assert lib.rst_set_solver(None, None) == rst.RST_EINVAL
+    d = ctypes.c_double()
+    assert lib.rst_apply_timing(None, ctypes.byref(d), ctypes.byref(d)) == rst.RST_EINVAL
+    # layers W0..W8: (cout, cin) = (16, 4), (16, 16) x 7, (2, 16), 27 taps each
+    assert lib.rst_cnn_weight_count() == 27 * (16 * 4 + 7 * 16 * 16 + 2 * 16)
+    o = rst.rst_lowrank_opts()
+    lib.rst_default_lowrank(ctypes.byref(o))
+    assert (o.probes, o.heldout, o.max_probes, o.tail_tol) == (32, 8, 256, 1e-7)
+    lib.rst_default_lowrank(None)  # ignored
