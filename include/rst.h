@@ -220,14 +220,19 @@ rst_status rst_transmission_kavg(rst_ctx *ctx, int n_k, const double *kpts, int 
                                  const double *E, double *T_out, double *T_k, int *n_solved,
                                  rst_stats *stats);
 
-/* y = (E - H_k + i Gamma) x for an (n x ncol) complex128 block, column fastest
- * (element (gi, c) at gi*ncol + c): the FD Laplacian with Bloch-phase lateral
- * wraps, V, the CAPs and the KB projectors (Bloch-form and transmission
- * equations).  x_dev and y_dev are distinct device buffers of n*ncol*16 bytes;
- * a projection buffer of nproj*ncol*16 bytes is grown on demand.  Any lateral
- * size (one wavefront per grid point and 64 columns).  RST_EINVAL for x == y,
- * a negative ncol or a non-finite energy. */
-rst_status rst_apply_h(rst_ctx *ctx, double energy, const void *x_dev, void *y_dev, int ncol);
+/* y = (E - H_k + i Gamma) x for an (n x ncol) block, column fastest (element
+ * (gi, c) at gi*ncol + c): the FD Laplacian with Bloch-phase lateral wraps, V,
+ * the CAPs and the KB projectors (Bloch-form and transmission equations).
+ * precision RST_FP64: complex128 x and y (n*ncol*16 bytes each), FP64
+ * arithmetic.  RST_FP32_REFINE: complex64 x and y (n*ncol*8 bytes each), the
+ * stencil in FP32; the projections h^3 B^H x are formed in FP64 from the
+ * widened x, and the projector term is summed in FP64 and rounded once.
+ * x_dev and y_dev are distinct device buffers; a projection buffer of
+ * nproj*ncol*16 bytes is grown on demand.  Any lateral size (one wavefront
+ * per grid point and 64 columns).  RST_EINVAL for x == y, a negative ncol, a
+ * non-finite energy or another precision. */
+rst_status rst_apply_h(rst_ctx *ctx, double energy, const void *x_dev, void *y_dev, int ncol,
+                       int precision);
 
 /* Widest column block the blocked apply supports on the current grid (a power
  * of two <= 8: a lateral plane of col_block columns must fit one workgroup at

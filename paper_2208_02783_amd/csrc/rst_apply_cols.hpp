@@ -20,8 +20,14 @@
 // its own L2, so chunk c runs on XCD c mod 8 with all points of a segment
 // dispatched together and its segments in increasing z (whole groups of eight
 // chunks; a remainder keeps plain order).
+//
+// F is the arithmetic and storage type: double (complex128 x, y) or float
+// (complex64 x, y: the stencil in FP32; the projector sum, from the FP64
+// projections and tables, in FP64 and rounded once when subtracted).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "rst_kernels.hpp"
 
@@ -32,8 +38,8 @@ namespace rst {
 constexpr int APPLY_ZSEG = 16;
 
 struct ColApplyArgs {
-  const double2* x;
-  double2* y;
+  const void* x;      // n x ncol, complex128 or complex64 (the kernel's F)
+  void* y;
   int ncol;
   Geo g;
   const double* V;    // [n]
@@ -45,15 +51,27 @@ struct ColApplyArgs {
   int zseg;           // planes per wave (>= 1)
 };
 
-__device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <class V2>
+__device__ __forceinline__ V2 cmul2(V2 a, V2 b) {
+  return V2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
 // NMU: compile-time bound on the projectors per group (9 for l <= 2, else 16),
 // so a point's projection rows are all requested before the first is used.
-template <int RAD, int NMU>
-__global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
+// Occupancy request (minimum waves per SIMD): 4 for the complex64 instances with
+// up to 9 projectors per group (at most 128 VGPRs, a few spills); the others are
+// left free (the 16-projector one would spill heavily).
+template <class F, int NMU>
+struct ApplyMinWaves {
+  static constexpr int value = std::is_same<F, float>::value && NMU <= 9 ? 4 : 1;
+};
+
+template <int RAD, int NMU, class F>
+__global__ __launch_bounds__(64, (ApplyMinWaves<F, NMU>::value)) void k_apply_cols(ColApplyArgs A) {
+  using V2 = typename std::conditional<std::is_same<F, double>::value, double2, float2>::type;
   constexpr int NQ = 2 * RAD + 1;
+  const V2* X = (const V2*)A.x;
+  V2* Y = (V2*)A.y;
   const Geo& g = A.g;
   const int P = g.P, na = g.na, nb = g.nb, nz = g.nz, ncol = A.ncol;
   const int nchunk = (ncol + 63) / 64;
@@ -78,13 +96,14 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
   const int c = chunk * 64 + (int)threadIdx.x;
   const bool ok = c < ncol;
   const int ia = p % na, ib = p / na;
-  const double2 pha = make_double2(g.pha_x, g.pha_y), phac = make_double2(g.pha_x, -g.pha_y);
-  const double2 phb = make_double2(g.phb_x, g.phb_y), phbc = make_double2(g.phb_x, -g.phb_y);
-  const double2 zero = make_double2(0.0, 0.0);
+  const V2 pha{(F)g.pha_x, (F)g.pha_y}, phac{(F)g.pha_x, (F)-g.pha_y};
+  const V2 phb{(F)g.phb_x, (F)g.phb_y}, phbc{(F)g.phb_x, (F)-g.phb_y};
+  const V2 zero{(F)0, (F)0};
+  const double2 zero64 = make_double2(0.0, 0.0);
 
-  auto row = [&](long long gi) -> double2 { return ok ? A.x[gi * ncol + c] : zero; };
+  auto row = [&](long long gi) -> V2 { return ok ? X[gi * ncol + c] : zero; };
 
-  double2 q[NQ];  // q[RAD + d] = row of plane z + d
+  V2 q[NQ];  // q[RAD + d] = row of plane z + d
 #pragma unroll
   for (int s = 0; s < NQ; ++s) {
     const int zs = z0 - RAD + s;
@@ -93,30 +112,31 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
 
   for (int z = z0; z < z1; ++z) {
     const int zl = z + RAD + 1;
-    const double2 nxt = zl < nz ? row((long long)zl * P + p) : zero;
+    const V2 nxt = zl < nz ? row((long long)zl * P + p) : zero;
     const long long base = (long long)z * P;
     const long long gi = base + p;
-    const double2 u = q[RAD];
-    const double dr = A.energy - A.V[gi] + g.diag0;
-    const double gzz = A.gz[z];
-    double2 y = make_double2(dr * u.x - gzz * u.y, dr * u.y + gzz * u.x);
+    const V2 u = q[RAD];
+    const F dr = (F)(A.energy - A.V[gi] + g.diag0);
+    const F gzz = (F)A.gz[z];
+    V2 y{dr * u.x - gzz * u.y, dr * u.y + gzz * u.x};
 #pragma unroll
     for (int j = 1; j <= RAD; ++j) {
       // lateral neighbours: a wrap across the +face carries exp(+i k L), across the -face its conjugate
       int ap = ia + j, am = ia - j, bp = ib + j, bm = ib - j;
-      double2 xap = row(base + (long long)ib * na + (ap >= na ? ap - na : ap));
-      double2 xam = row(base + (long long)ib * na + (am < 0 ? am + na : am));
-      double2 xbp = row(base + (long long)(bp >= nb ? bp - nb : bp) * na + ia);
-      double2 xbm = row(base + (long long)(bm < 0 ? bm + nb : bm) * na + ia);
+      V2 xap = row(base + (long long)ib * na + (ap >= na ? ap - na : ap));
+      V2 xam = row(base + (long long)ib * na + (am < 0 ? am + na : am));
+      V2 xbp = row(base + (long long)(bp >= nb ? bp - nb : bp) * na + ia);
+      V2 xbm = row(base + (long long)(bm < 0 ? bm + nb : bm) * na + ia);
       if (ap >= na) xap = cmul2(xap, pha);
       if (am < 0) xam = cmul2(xam, phac);
       if (bp >= nb) xbp = cmul2(xbp, phb);
       if (bm < 0) xbm = cmul2(xbm, phbc);
-      const double2 zz = make_double2(q[RAD + j].x + q[RAD - j].x, q[RAD + j].y + q[RAD - j].y);
-      const double2 aa = make_double2(xap.x + xam.x, xap.y + xam.y);
-      const double2 bb = make_double2(xbp.x + xbm.x, xbp.y + xbm.y);
-      y.x += g.cz[j] * zz.x + g.ca[j] * aa.x + g.cb[j] * bb.x;
-      y.y += g.cz[j] * zz.y + g.ca[j] * aa.y + g.cb[j] * bb.y;
+      const V2 zz{q[RAD + j].x + q[RAD - j].x, q[RAD + j].y + q[RAD - j].y};
+      const V2 aa{xap.x + xam.x, xap.y + xam.y};
+      const V2 bb{xbp.x + xbm.x, xbp.y + xbm.y};
+      const F cz = (F)g.cz[j], ca = (F)g.ca[j], cb = (F)g.cb[j];
+      y.x += cz * zz.x + ca * aa.x + cb * bb.x;
+      y.y += cz * zz.y + ca * aa.y + cb * bb.y;
     }
     if (A.pj.nproj) {
       // sum over the point's (group, entry) pairs of exp(+i k.R_e) sum_m beta_e,m E_p P_p, p = first + m
@@ -135,7 +155,7 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
           const int mm = min(m, nv - 1);  // clamped: every load in bounds, the extra weights zero
           const double bw = pj.sc_beta[si * pj.nm + mm] * pj.ekb[pb + mm];
           w[m] = m < nv ? bw : 0.0;
-          pv[m] = ok ? A.P[(size_t)(pb + mm) * ncol + c] : zero;
+          pv[m] = ok ? A.P[(size_t)(pb + mm) * ncol + c] : zero64;
         }
         double tx = 0.0, ty = 0.0;
 #pragma unroll
@@ -156,7 +176,7 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
           double tx = 0.0, ty = 0.0;
           for (int m = 0; m < nmg; ++m) {
             const double w = pj.beta[(size_t)ge.y * pj.nm + m] * pj.ekb[pb + m];
-            const double2 pv = ok ? A.P[(size_t)(pb + m) * ncol + c] : zero;
+            const double2 pv = ok ? A.P[(size_t)(pb + m) * ncol + c] : zero64;
             tx += w * pv.x;
             ty += w * pv.y;
           }
@@ -164,10 +184,10 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
           sy += ph.x * ty + ph.y * tx;
         }
       }
-      y.x -= sx;
-      y.y -= sy;
+      y.x -= (F)sx;
+      y.y -= (F)sy;
     }
-    if (ok) A.y[gi * ncol + c] = y;
+    if (ok) Y[gi * ncol + c] = y;
 #pragma unroll
     for (int s = 0; s < NQ - 1; ++s) q[s] = q[s + 1];
     q[NQ - 1] = nxt;

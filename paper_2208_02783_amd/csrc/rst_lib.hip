@@ -2380,10 +2380,13 @@ rst_status rst_transmission_kavg(rst_ctx* c, int n_k, const double* kpts, int fo
   return worst;
 }
 
-rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev, int ncol) {
+rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev, int ncol, int precision) {
   rst_status s = check_ready(c);
   if (s != RST_OK) return s;
   if (ncol < 0 || (ncol > 0 && (!x_dev || !y_dev))) return fail(c, RST_EINVAL, "bad apply arguments");
+  if (precision != RST_FP64 && precision != RST_FP32_REFINE)
+    return fail(c, RST_EINVAL, "precision must be RST_FP64 or RST_FP32_REFINE");
+  const bool f32 = precision == RST_FP32_REFINE;
   if (x_dev == y_dev) return fail(c, RST_EINVAL, "x and y must be distinct buffers");
   if (!std::isfinite(energy)) return fail(c, RST_EINVAL, "non-finite energy");
   if (ncol == 0) return RST_OK;
@@ -2396,8 +2399,8 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
   if (nwg > 0x7fffffffLL) return fail(c, RST_EINVAL, "too many columns for one launch");
   rst::ColApplyArgs A;
   std::memset(&A, 0, sizeof(A));
-  A.x = (const double2*)x_dev;
-  A.y = (double2*)y_dev;
+  A.x = x_dev;
+  A.y = y_dev;
   A.ncol = ncol;
   A.g = make_geo(c);
   A.V = (const double*)c->d_v.p;
@@ -2412,7 +2415,7 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
     // all projections P = h^3 B^H x at once on the matrix cores; the apply kernel then scatters B E P
     if ((s = ensure(c, c->d_projP, (size_t)c->nproj * ncol * 16)) != RST_OK) return s;
     rst::ProjMMArgs M;
-    M.X = (const double2*)x_dev;
+    M.X = x_dev;
     M.P = (double2*)c->d_projP.p;
     M.grp_e0 = (const int*)c->d_grp_e0.p;
     M.grp_ne = (const int*)c->d_grp_ne.p;
@@ -2426,20 +2429,26 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
     M.ncol = ncol;
     M.h3 = c->ha * c->hb * c->hz;
     const long long tiles = (long long)c->ngroup * ((ncol + 63) / 64);  // one workgroup per (group, 64 columns)
-    hipLaunchKernelGGL(rst::k_proj_mm, dim3((unsigned)tiles), dim3(256), 0, c->stream, M);
+    if (f32)
+      hipLaunchKernelGGL(rst::k_proj_mm<float2>, dim3((unsigned)tiles), dim3(256), 0, c->stream, M);
+    else
+      hipLaunchKernelGGL(rst::k_proj_mm<double2>, dim3((unsigned)tiles), dim3(256), 0, c->stream, M);
     HIPCHK(c, hipGetLastError());
     A.P = (const double2*)c->d_projP.p;
   }
   HIPCHK(c, hipEventRecord(c->ev_apply[1], c->stream));
   const bool nm9 = c->nm <= 9;
-  if (c->rad == 6 && nm9)
-    hipLaunchKernelGGL((rst::k_apply_cols<6, 9>), dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
-  else if (c->rad == 6)
-    hipLaunchKernelGGL((rst::k_apply_cols<6, 16>), dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
-  else if (nm9)
-    hipLaunchKernelGGL((rst::k_apply_cols<2, 9>), dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
+  void* kern = nullptr;
+  if (f32)
+    kern = c->rad == 6 ? (nm9 ? (void*)rst::k_apply_cols<6, 9, float> : (void*)rst::k_apply_cols<6, 16, float>)
+                       : (nm9 ? (void*)rst::k_apply_cols<2, 9, float> : (void*)rst::k_apply_cols<2, 16, float>);
   else
-    hipLaunchKernelGGL((rst::k_apply_cols<2, 16>), dim3((unsigned)nwg), dim3(64), 0, c->stream, A);
+    kern = c->rad == 6 ? (nm9 ? (void*)rst::k_apply_cols<6, 9, double> : (void*)rst::k_apply_cols<6, 16, double>)
+                       : (nm9 ? (void*)rst::k_apply_cols<2, 9, double> : (void*)rst::k_apply_cols<2, 16, double>);
+  {
+    void* args[] = {&A};
+    HIPCHK(c, hipLaunchKernel(kern, dim3((unsigned)nwg), dim3(64), args, 0, c->stream));
+  }
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->ev_apply[2], c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

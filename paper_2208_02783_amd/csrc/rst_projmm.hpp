@@ -24,7 +24,7 @@ namespace rst {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct ProjMMArgs {
-  const double2* X;       // n x ncol
+  const void* X;          // n x ncol, complex128 or complex64 (the kernel's XT)
   double2* P;             // nproj x ncol: P[p*ncol + c]
   const int* grp_e0;      // [ngroup] first entry of the group (group-major entry order)
   const int* grp_ne;      // [ngroup] entries of the group
@@ -37,7 +37,10 @@ struct ProjMMArgs {
   double h3;
 };
 
+// XT: element type of X (double2, or float2 for a complex64 apply: widened to FP64 on load)
+template <class XT>
 __global__ __launch_bounds__(256) void k_proj_mm(ProjMMArgs A) {
+  const XT* X = (const XT*)A.X;
   __shared__ double red[3][32][64];  // partial products of waves 1..3: [wave-1][slot][lane]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int ntile = (A.ncol + 63) / 64;
@@ -67,7 +70,8 @@ __global__ __launch_bounds__(256) void k_proj_mm(ProjMMArgs A) {
       const int col = c0 + 16 * b + i16;
       double xr = 0.0, xi = 0.0;
       if (k < ne && col < A.ncol) {
-        const double2 x = A.X[gi * A.ncol + col];
+        const XT xv = X[gi * A.ncol + col];
+        const double2 x = make_double2((double)xv.x, (double)xv.y);
         xr = ph.x * x.x + ph.y * x.y;  // conj(ph) * x
         xi = ph.x * x.y - ph.y * x.x;
       }

@@ -120,7 +120,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.rst_set_k.argtypes = [P, C.c_double, C.c_double]
     lib.rst_set_solver.argtypes = [P, C.POINTER(rst_solver_opts)]
     lib.rst_transmission.argtypes = [P, C.c_int, P, P, C.POINTER(rst_stats)]
-    lib.rst_apply_h.argtypes = [P, C.c_double, P, P, C.c_int]
+    lib.rst_apply_h.argtypes = [P, C.c_double, P, P, C.c_int, C.c_int]
     lib.rst_transmission_kavg.argtypes = [P, C.c_int, P, C.c_int, C.c_int, P, P, P, C.POINTER(C.c_int),
                                           C.POINTER(rst_stats)]
     lib.rst_apply_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -255,9 +255,9 @@ class Context:
                       allow_noconv=True)
         return t, tk, ns.value, st.as_dict(), s
 
-    def rst_apply_h(self, energy, x_dev_ptr: int, y_dev_ptr: int, ncol: int):
+    def rst_apply_h(self, energy, x_dev_ptr: int, y_dev_ptr: int, ncol: int, precision: int = 0):
         return self._chk(self.lib.rst_apply_h(self.h, float(energy), C.c_void_p(x_dev_ptr),
-                                              C.c_void_p(y_dev_ptr), int(ncol)))
+                                              C.c_void_p(y_dev_ptr), int(ncol), int(precision)))
 
     def rst_apply_block_width(self):
         cw = C.c_int()
@@ -374,12 +374,14 @@ class Context:
 
 
 def apply_h(ctx: Context, energy: float, x):
-    """y = (E - H_k + i Gamma) x for a torch complex128 CUDA tensor x of shape (n, ncol)."""
+    """y = (E - H_k + i Gamma) x for a torch CUDA tensor x of shape (n, ncol):
+    complex128 (FP64 apply) or complex64 (FP32 stencil, FP64 projections)."""
     import torch
-    assert x.is_cuda and x.dtype == torch.complex128 and x.is_contiguous()
+    assert x.is_cuda and x.dtype in (torch.complex128, torch.complex64) and x.is_contiguous()
     y = torch.empty_like(x)
     torch.cuda.synchronize()
-    ctx.rst_apply_h(energy, x.data_ptr(), y.data_ptr(), x.shape[1])
+    prec = RST_FP32_REFINE if x.dtype == torch.complex64 else RST_FP64
+    ctx.rst_apply_h(energy, x.data_ptr(), y.data_ptr(), x.shape[1], prec)
     return y
 
 

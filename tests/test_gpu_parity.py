@@ -30,23 +30,39 @@ APPLY_CASES = [
 ]
 
 
+# The complex64 apply rounds each of its ~42 products and sums in FP32 (u = 6e-8);
+# the magnitudes summed are about ten times |y| on these grids (the order-12
+# Laplacian's weights), which bounds the error by ~2.5e-5 max|y|.  The input is
+# rounded to complex64 first and the oracle applied to those same values.
+APPLY_BAR = {"fp64": 1e-13, "fp32": 5e-5}
+
+
+def _apply_vs_oracle(torch, ctx, p, k, e, x, xd, prec):
+    if prec == "fp32":
+        xd = xd.to(torch.complex64)
+        x = xd.cpu().numpy().astype(np.complex128)
+    y = rst.apply_h(ctx, e, xd).cpu().numpy().astype(np.complex128)
+    ref = oracle.apply_system(p, k, e, x)
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    assert err <= APPLY_BAR[prec], (prec, err)
+    return err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", APPLY_CASES)
-def test_apply_matches_oracle(case):
+def test_apply_matches_oracle(case, prec):
     torch = torch_cuda()
-    _say("apply case", case)
+    _say("apply case", case, prec)
     rng = np.random.default_rng(13)
     p = hp.random_problem(rng, na=case["na"], nb=case["nb"], nz=case["nz"], order=case["order"],
                           nproj=case["nproj"], ramp=3)
     ctx = make_ctx(torch, p, case["k"])
     x, xd = rand_block(torch, p.n, case["ncol"], 1)
-    e = 0.731
-    y = rst.apply_h(ctx, e, xd).cpu().numpy()
-    ref = oracle.apply_system(p, case["k"], e, x)
-    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
-    assert err <= 1e-13, err
+    _apply_vs_oracle(torch, ctx, p, case["k"], 0.731, x, xd, prec)
 
 
-def test_apply_full_size_config2_columns():
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_full_size_config2_columns(prec):
     """Config 2 at its full size (17x17x170, order 12, 360 projectors), every
     output of a few columns against the oracle's factored apply."""
     torch = torch_cuda()
@@ -54,15 +70,12 @@ def test_apply_full_size_config2_columns():
     k = p.kpts[5]
     ctx = make_ctx(torch, p, k)
     x, xd = rand_block(torch, p.n, 3, 2)
-    e = float(p.energies[100])
-    y = rst.apply_h(ctx, e, xd).cpu().numpy()
-    ref = oracle.apply_system(p, k, e, x)
-    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
-    assert err <= 1e-13, err
+    _say("config-2 apply", prec, _apply_vs_oracle(torch, ctx, p, k, float(p.energies[100]), x, xd, prec))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("order,nproj", [(4, 3), (12, 4)])
-def test_apply_many_columns_matches_oracle(order, nproj):
+def test_apply_many_columns_matches_oracle(order, nproj, prec):
     """549 columns (eight full 64-column chunks placed per XCD plus a ragged
     ninth) over 40 planes (z segments of 16, 16 and 8): every output against
     the oracle."""
@@ -72,11 +85,21 @@ def test_apply_many_columns_matches_oracle(order, nproj):
     k = (0.31, -0.52)
     ctx = make_ctx(torch, p, k)
     x, xd = rand_block(torch, p.n, 549, 6)
-    e = 0.413
-    y = rst.apply_h(ctx, e, xd).cpu().numpy()
-    ref = oracle.apply_system(p, k, e, x)
-    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
-    assert err <= 1e-13, err
+    _apply_vs_oracle(torch, ctx, p, k, 0.413, x, xd, prec)
+
+
+def test_apply_precision_argument():
+    """An unknown precision is refused; both precisions accept zero columns."""
+    torch = torch_cuda()
+    p = wl.config(2, tiny=True)
+    ctx = make_ctx(torch, p, p.kpts[0])
+    x = torch.zeros((p.n, 2), dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_apply_h(0.5, x.data_ptr(), y.data_ptr(), 2, 7)
+    assert ei.value.status == rst.RST_EINVAL
+    for prec in (rst.RST_FP64, rst.RST_FP32_REFINE):
+        ctx.rst_apply_h(0.5, x.data_ptr(), y.data_ptr(), 0, prec)
 
 
 def test_apply_full_size_config3_columns():
