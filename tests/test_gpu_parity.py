@@ -102,7 +102,8 @@ def test_apply_precision_argument():
         ctx.rst_apply_h(0.5, x.data_ptr(), y.data_ptr(), 0, prec)
 
 
-def test_apply_full_size_config3_columns():
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_full_size_config3_columns(prec):
     """Config 3 at its full size (54x54x252 point contact, n = 734,832, 3420
     projectors): the column-fastest apply has no per-plane workgroup limit, so
     every output of a few columns is checked against the oracle's factored
@@ -114,10 +115,7 @@ def test_apply_full_size_config3_columns():
     ctx = make_ctx(torch, p, k, precond=rst.RST_PRECOND_FREE_CAP)
     x, xd = rand_block(torch, p.n, 3, 4)
     e = float(p.energies[40])
-    y = rst.apply_h(ctx, e, xd).cpu().numpy()
-    ref = oracle.apply_system(p, k, e, x)
-    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
-    assert err <= 1e-13, err
+    _say("config-3 apply", prec, _apply_vs_oracle(torch, ctx, p, k, e, x, xd, prec))
     with pytest.raises(rst.RstError) as ei:
         ctx.rst_transmission(np.array([e]))
     assert ei.value.status == rst.RST_EUNSUPPORTED
