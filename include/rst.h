@@ -244,8 +244,9 @@ rst_status rst_apply_block_width(rst_ctx *ctx, int *col_block);
  * vectors in: ncol columns in ncol/col_block blocks of col_block columns; block
  * j occupies elements [j*n*col_block, (j+1)*n*col_block) and holds column
  * j*col_block + c of grid point gi at j*n*col_block + gi*col_block + c
- * (complex128, device).  One workgroup streams z through each block, the
- * projector gather B^H x included (the operator of the transmission equation's
+ * (complex128, device).  The projections h^3 B^H x are formed first on the
+ * FP64 matrix cores, into per-block arrays; then one workgroup streams z
+ * through each block (the operator of the transmission equation's
  * G, with H_k the FD Laplacian with Bloch-phase lateral wraps, V and the KB
  * projectors).  RST_EINVAL if ncol is not a multiple of col_block, col_block is
  * not a power of two <= 8 or x == y; RST_EUNSUPPORTED if col_block exceeds
@@ -254,9 +255,8 @@ rst_status rst_apply_h_blocked(rst_ctx *ctx, double energy, const void *x_dev, v
                                int col_block);
 
 /* Kernel durations of the last rst_apply_h or rst_apply_h_blocked on this context, measured with HIP
- * events on the context's stream: the separate projector gather B^H x (0
- * without projectors and for the blocked apply, whose sweep gathers itself) and
- * the stencil sweep.
+ * events on the context's stream: the projector gather h^3 B^H x on the FP64
+ * matrix cores (0 without projectors) and the stencil sweep.
  * Both 0 before the first apply.  RST_EINVAL for a null argument. */
 rst_status rst_apply_timing(const rst_ctx *ctx, double *proj_ms, double *stencil_ms);
 

@@ -235,6 +235,7 @@ struct ApplyArgs {
   int ncol, cw, nblk;
   double2* pws;             // per-workgroup projection scratch (2 arrays nproj*cw)
   size_t pws_stride;
+  int proj_pre;             // the projections of x are already in pws (k_proj_mm): no gather sweep
 };
 
 // ---------------------------------------------------------------------------

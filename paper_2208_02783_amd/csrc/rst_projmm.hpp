@@ -35,6 +35,12 @@ struct ProjMMArgs {
   const double* beta;     // [nent*nm] beta[e*nm + m]
   int nm, ngroup, ncol;
   double h3;
+  // blocked layout (cw > 0): X holds blocks of cw columns, block b at b*n*cw with
+  // (gi, c) at gi*cw + c, and P is written per block at b*p_stride + p*cw + c
+  // (the solvers' per-workgroup projection arrays); cw == 0: column fastest
+  int cw;
+  long long n;
+  size_t p_stride;
 };
 
 // XT: element type of X (double2, or float2 for a complex64 apply: widened to FP64 on load)
@@ -70,7 +76,8 @@ __global__ __launch_bounds__(256) void k_proj_mm(ProjMMArgs A) {
       const int col = c0 + 16 * b + i16;
       double xr = 0.0, xi = 0.0;
       if (k < ne && col < A.ncol) {
-        const XT xv = X[gi * A.ncol + col];
+        const size_t xo = A.cw ? ((size_t)(col / A.cw) * A.n + gi) * A.cw + col % A.cw : (size_t)gi * A.ncol + col;
+        const XT xv = X[xo];
         const double2 x = make_double2((double)xv.x, (double)xv.y);
         xr = ph.x * x.x + ph.y * x.y;  // conj(ph) * x
         xi = ph.x * x.y - ph.y * x.x;
@@ -103,7 +110,11 @@ __global__ __launch_bounds__(256) void k_proj_mm(ProjMMArgs A) {
         si += red[w][16 + 4 * b + r][lane];
       }
       const int m = 4 * r + kq;
-      if (m < nmg && col < A.ncol) A.P[(size_t)(pb + m) * A.ncol + col] = make_double2(A.h3 * sr, A.h3 * si);
+      if (m < nmg && col < A.ncol) {
+        const size_t pi = A.cw ? (size_t)(col / A.cw) * A.p_stride + (size_t)(pb + m) * A.cw + col % A.cw
+                               : (size_t)(pb + m) * A.ncol + col;
+        A.P[pi] = make_double2(A.h3 * sr, A.h3 * si);
+      }
     }
   }
 }

@@ -526,7 +526,8 @@ __global__ __launch_bounds__(MAX_T) RST_WAVES_ATTR void k_bicgstab(const SolveAr
 }
 
 // y = (E - H_k + i Gamma) x on blocked vectors (the solvers' layout), one
-// workgroup per column block: a gather sweep forms B^H x of the block, then
+// workgroup per column block: a gather sweep forms B^H x of the block (unless
+// k_proj_mm has already put the projections in the block's pws array), then
 // the stencil sweep applies the rest and scatters the projector part.
 template <int RAD, int Q, class R>
 __global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ Ap) {
@@ -564,11 +565,11 @@ __global__ __launch_bounds__(MAX_T) void k_apply(const ApplyArgs* __restrict__ A
   }
   const size_t np = (size_t)A.pj.nproj * cw;
   cx<double>* Px = reinterpret_cast<cx<double>*>(A.pws) + (size_t)blockIdx.x * A.pws_stride;
-  zero_acc<R>(Px, (int)np);
+  if (!A.proj_pre) zero_acc<R>(Px, (int)np);
   __syncthreads();
   const Pos<Q> ps = make_pos<Q>(A.g, cw, RAD);
   double tacc = 0;
-  if (A.pj.nproj) {
+  if (A.pj.nproj && !A.proj_pre) {
     C.acc = Px;
     gather_sweep<Q, R, true>(C, ps, nullptr, tacc);
   }
