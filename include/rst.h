@@ -88,7 +88,7 @@ typedef struct {
                         solved again in FP64 (stats.fallback_columns) */
   double tol;        /* stop when the FP64 true residual ||b - A x|| <= tol ||b|| per column (default 1e-10) */
   int max_iter;      /* BiCGSTAB iterations per column (default 20000) */
-  int col_block;     /* columns solved together by one workgroup; 0 = automatic (FGMRES and COCG: 1) */
+  int col_block;     /* columns solved together by one workgroup; 0 = automatic (COCG: 1) */
   int threads;       /* workgroup size (multiple of 64, <= 512); 0 = automatic */
   int direction;     /* RST_DIR_LR: columns in the right CAP, T accumulated on the left (default);
                         RST_DIR_RL: the reverse.  Both give the same T (exact identity). */

@@ -914,9 +914,7 @@ rst_status run_fgmres(rst_ctx* c, int ne, const double* energies, const std::vec
   const int ncols = (int)cols.size();
   // launch shape shared by the apply and preconditioner kernels
   BlockedShape bs;
-  // automatic: one column per workgroup (config 2 at the Gamma point: COCG 9.2 s against 11.2 s with
-  // two, FGMRES 5.7 s against 6.0 s on 512 columns)
-  rst_status s = blocked_shape(c, c->opts.col_block > 0 ? c->opts.col_block : 1, c->opts.threads, bs);
+  rst_status s = blocked_shape(c, c->opts.col_block > 0 ? c->opts.col_block : 8, c->opts.threads, bs);
   if (s != RST_OK) return s;
   const LaunchShape ls = bs.ls;
   const int cw = ls.cw;
@@ -1279,8 +1277,7 @@ rst_status run_cocg(rst_ctx* c, int ne, const double* energies, const std::vecto
   const long long n = (long long)P * c->nz;
   const int ncols = (int)cols.size();
   BlockedShape bs;
-  // automatic: one column per workgroup (config 2 at the Gamma point: COCG 9.2 s against 11.2 s with
-  // two, FGMRES 5.7 s against 6.0 s on 512 columns)
+  // automatic: one column per workgroup (config 2 at the Gamma point: 9.2 s against 11.2 s with two)
   rst_status s = blocked_shape(c, c->opts.col_block > 0 ? c->opts.col_block : 1, c->opts.threads, bs);
   if (s != RST_OK) return s;
   const LaunchShape ls = bs.ls;
