@@ -113,6 +113,46 @@ def test_train_step_matches_oracle_and_lowers_the_loss():
     assert losses[-1] < 0.8 * losses[0], losses
 
 
+def test_three_adam_steps_match_oracle_elementwise():
+    """Three device training steps against the oracle's Adam (Kingma and Ba,
+    Algorithm 1) element by element.  Before each step the device's own weight
+    gradient of the mean squared loss is taken through rst_cnn_gradient (gout =
+    2 (f(x) - target) / ncol from the device forward pass); the oracle applies
+    adam_step with that gradient, at t = 1, 2, 3, to its FP64 copy of the weights
+    and moments.  Bar: |w_gpu - w_oracle| <= 1e-7 + 1e-6 |w| on every weight whose
+    gradient is above 1e-3 of the layer's largest at all three steps (elsewhere an
+    FP32 gradient of a few ulps can flip m_hat / sqrt(v_hat) by O(1), which is a
+    difference in the gradient, not in the optimiser)."""
+    torch = torch_cuda()
+    ncol, nz, nb, na = 2, 6, 5, 5
+    ws = rounded_weights(41, scale_last=0.1)
+    rng = np.random.default_rng(42)
+    x = rng.standard_normal((ncol, 4, nz, nb, na)).astype(np.float32).astype(np.float64)
+    tgt = (0.3 * x[:, :2] - 0.2 * x[:, 2:]).astype(np.float32).astype(np.float64)
+    ctx = rst.Context(0)
+    ctx.rst_cnn_set_weights(flat(ws))
+    xg, tg = to_gpu(torch, x), to_gpu(torch, tgt)
+    w_or = [w.copy() for w in ws]
+    m = [np.zeros_like(w) for w in ws]
+    v = [np.zeros_like(w) for w in ws]
+    big = [np.ones(w.shape, bool) for w in ws]
+    lr = 2e-3
+    for t in (1, 2, 3):
+        out = rst.cnn_forward(ctx, xg)
+        gout = ((out - tg) * (2.0 / ncol)).contiguous()
+        g = unflat(rst.cnn_gradient(ctx, xg, gout))
+        for b, gl in zip(big, g):
+            b &= np.abs(gl) > 1e-3 * np.max(np.abs(gl))
+        rst.cnn_train_step(ctx, xg, tg, lr)
+        cnn.adam_step(w_or, g, m, v, t, lr=lr)
+        w_gpu = unflat(ctx.rst_cnn_get_weights())
+        for li, (a, b, msk) in enumerate(zip(w_gpu, w_or, big)):
+            err = np.abs(a - b)[msk]
+            bar = (1e-7 + 1e-6 * np.abs(b))[msk]
+            assert np.all(err <= bar), (t, li, float(np.max(err - bar)))
+    assert sum(int(b.sum()) for b in big) > 0.5 * sum(b.size for b in big)
+
+
 def test_network_errors():
     torch = torch_cuda()
     ctx = rst.Context(0)

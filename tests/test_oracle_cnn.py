@@ -144,6 +144,51 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(w[0], w0 - 0.01 * g[0] / (np.abs(g[0]) + 1e-8), rtol=1e-12)
 
 
+def test_adam_constant_gradient_any_step():
+    """With the same gradient g at every step, both moment estimates are exactly
+    unbiased after the bias correction (m_hat = g, v_hat = g^2 for every t), so
+    step t moves each weight by -lr g / (|g| + eps) whatever t is: after T steps
+    w = w0 - T lr g / (|g| + eps).  A wrong correction exponent (beta^(t+1),
+    beta^1) or a missing correction breaks this from t = 2 on."""
+    rng = np.random.default_rng(18)
+    shape = (4, 5)
+    g = rng.standard_normal(shape) * np.exp(rng.uniform(-6, 2, shape))
+    w = [rng.standard_normal(shape)]
+    w0 = w[0].copy()
+    m, v = [np.zeros(shape)], [np.zeros(shape)]
+    lr = 0.003
+    for t in range(1, 8):
+        cnn.adam_step(w, [g], m, v, t, lr=lr)
+        np.testing.assert_allclose(w[0], w0 - t * lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_scale_invariance_and_zero_gradient_step():
+    """Two properties of the update that hold at every t: (1) with eps = 0 the
+    update is unchanged when every gradient is multiplied by c > 0 (m_hat scales
+    by c, sqrt(v_hat) by c); (2) a zero gradient after one nonzero g moves the
+    weight by -lr (b1/(1+b1)) / sqrt(b2/(1+b2)) sign(g) at t = 2: m_2 = b1(1-b1)g
+    and v_2 = b2(1-b2)g^2 over the corrections 1-b1^2 = (1-b1)(1+b1) and
+    1-b2^2 = (1-b2)(1+b2)."""
+    rng = np.random.default_rng(19)
+    shape = (3, 6)
+    gs = [rng.standard_normal(shape) for _ in range(5)]
+    runs = []
+    for c in (1.0, 37.0):
+        w, m, v = [np.zeros(shape)], [np.zeros(shape)], [np.zeros(shape)]
+        for t, g in enumerate(gs, start=1):
+            cnn.adam_step(w, [c * g], m, v, t, lr=0.01, eps=0.0)
+        runs.append(w[0])
+    np.testing.assert_allclose(runs[0], runs[1], rtol=1e-12, atol=1e-15)
+    b1, b2, lr = 0.9, 0.999, 0.01
+    g = gs[0]
+    w, m, v = [np.zeros(shape)], [np.zeros(shape)], [np.zeros(shape)]
+    cnn.adam_step(w, [g], m, v, 1, lr=lr, eps=0.0)
+    w1 = w[0].copy()
+    cnn.adam_step(w, [np.zeros(shape)], m, v, 2, lr=lr, eps=0.0)
+    step2 = lr * (b1 / (1 + b1)) / np.sqrt(b2 / (1 + b2)) * np.sign(g)
+    np.testing.assert_allclose(w[0] - w1, -step2, rtol=1e-12)
+
+
 def test_training_reduces_loss():
     """A few Adam steps on a fixed batch lower the loss (the optimiser and the
     gradients point the same way)."""
