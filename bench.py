@@ -1,23 +1,33 @@
 """Benchmark of the Bloch-CAP transmission hot path on one MI355X.
 
-One step = T(E, k) for one (energy, lateral k) point of the synthetic FCC bulk
-slab (17x17x170 grid, h = 0.401 bohr, 12th-order FD, 40 Gaussian wells, 360
-Kleinman-Bylander projectors, 34-plane quadratic CAP at each end): all 9826
-right-CAP columns solved to an FP64 true relative residual of 1e-10 by the
-persistent BiCGSTAB kernel (free-electron + CAP right preconditioner by
-default), and T accumulated over the left CAP.  Inputs are generated and
-uploaded before the timed region; the timed region is whole T(E,k) points.
+Headline (default, `--workload cfg3`): the point-contact slab (54x54x252 grid,
+h = 0.399 bohr, 12th-order FD, 380 Gaussian wells and 3420 Kleinman-Bylander
+projectors in a cylindrical constriction, 36-plane quadratic CAP at each end,
+104,976 right-CAP columns).  One step = T(E, k) at one lateral k-point of its
+4x4 Monkhorst-Pack grid for a block of energies, by the low-rank route: a
+randomised range finder over the CAP blocks (probe and held-out solves on the
+right CAP, adjoint solves at -k), every solve by the right-preconditioned FP64
+BiCGSTAB to a true relative residual of 1e-10, with an a-posteriori estimate of
+the neglected tail per energy.  `--workload cfg2` times instead whole
+full-column T(E, k) points of the FCC bulk slab (17x17x170, 9826 columns).
 
-Prints one JSON line (see the repository's measurement notes for the fields).
+Inputs are generated and uploaded before the timed region.  Every leg runs
+under a wall budget (the whole run stays inside `--budget` seconds from the
+start of the process); a leg that does not fit is recorded as skipped, and the
+timed loop stops early (reporting the steps it did time) when its share runs
+out.  Prints one JSON line.
 """
 from __future__ import annotations
 
-import argparse
-import json
-import math
-import os
-import sys
 import time
+
+T_START = time.time()
+
+import argparse  # noqa: E402
+import json  # noqa: E402
+import math  # noqa: E402
+import os  # noqa: E402
+import sys  # noqa: E402
 
 import numpy as np
 
@@ -55,31 +65,52 @@ def step_points(prob, i):
     return k, e
 
 
-def cpu_baseline(seconds_budget=20.0):
+def host_cpu():
+    """Host core count and CPU model (this machine's, where the oracle runs)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+def cpu_baseline(seconds_each=10.0):
     """The CPU oracle (dense LU, FP64) on a bounded sample: the tiny variant of
-    the same generator (8x8x48 grid, same order, wells and projector model,
-    512 right-CAP columns), as many energies as fit the budget."""
+    the FCC generator (8x8x48 grid, order 12, same wells and projector model,
+    512 right-CAP columns), as many (E, k) points as fit `seconds_each`, once
+    with one BLAS/LAPACK thread and once with all host threads."""
     import oracle
     from paper_2208_02783_amd import workloads as wl
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
+    nproc, model = host_cpu()
     p = wl.config(2, tiny=True)
-    done, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < seconds_budget:
-        k = p.kpts[done % len(p.kpts)]
-        oracle.transmission(p, [p.energies[(done // len(p.kpts)) % len(p.energies)]], k, both=False)
-        done += 1
-    dt = time.perf_counter() - t0
+
+    def run():
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds_each:
+            k = p.kpts[done % len(p.kpts)]
+            oracle.transmission(p, [p.energies[(done // len(p.kpts)) % len(p.energies)]], k, both=False)
+            done += 1
+        return done, time.perf_counter() - t0
+
+    with threadpool_limits(limits=1):
+        d1, t1 = run()
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    dn, tn = run()
     n_tiny, n_full = p.n, 17 * 17 * 170
-    per_point = dt / done
-    return {"value": done / dt, "unit": "T(E,k) points/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"dense-LU oracle on the 8x8x48 tiny variant of the same generator "
-                      f"(n={n_tiny}, 512 columns), {done} energies in {dt:.1f} s; "
-                      f"at the full 17x17x170 size (n={n_full}) the dense LU scales as n^3: "
-                      f"~{per_point * (n_full / n_tiny) ** 3 / 3600:.2f} h per point"}
+    return {"value": dn / tn, "unit": "T(E,k) points/s", "cores": int(threads), "kind": "oracle",
+            "host_nproc": nproc, "host_cpu_model": model,
+            "single_thread_points_per_s": d1 / t1, "all_threads_points_per_s": dn / tn,
+            "sample": f"dense-LU oracle (complex LU + 512 column solves per point) on the 8x8x48 tiny variant "
+                      f"of the FCC generator (n={n_tiny}): {d1} points in {t1:.1f} s on 1 thread, {dn} points in "
+                      f"{tn:.1f} s on {threads} threads; the dense LU grows as n^3, so a full 17x17x170 point "
+                      f"(n={n_full}) would take ~{tn / dn * (n_full / n_tiny) ** 3 / 3600:.2f} h on {threads} "
+                      f"threads"}
 
 
 def batched_comparison(n_slabs=96, ne=2, precond=1):
@@ -339,15 +370,80 @@ def cocg_comparison(prob2):
     return out
 
 
+class Budget:
+    """Wall-clock budget of the whole run, counted from the start of the process."""
+
+    def __init__(self, total_s):
+        self.total = total_s
+
+    def left(self):
+        return self.total - (time.time() - T_START)
+
+    def fits(self, estimate_s, reserve_s=0.0):
+        return self.left() - reserve_s >= estimate_s
+
+
+def run_leg(line, name, budget, estimate_s, reserve_s, fn):
+    """Runs one optional leg if its estimate fits the budget (else records it as skipped)."""
+    if not budget.fits(estimate_s, reserve_s):
+        line[name] = {"skipped": f"wall budget: {budget.left():.0f} s left, leg estimated at {estimate_s:.0f} s "
+                                 f"with {reserve_s:.0f} s reserved"}
+        print(f"leg {name}: skipped (budget)", file=sys.stderr, flush=True)
+        return
+    t0 = time.time()
+    print(f"leg {name}: start ({budget.left():.0f} s left)", file=sys.stderr, flush=True)
+    line[name] = fn()
+    line[name]["leg_wall_s"] = time.time() - t0
+    print(f"leg {name}: done in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
+
+CFG2_WORKLOAD = ("FCC bulk slab 17x17x170 (h=0.401 bohr, a=6.82, 10 cells), 12th-order FD, "
+                 "40 Gaussian wells (1.5 Ha, 1.2 bohr), 360 KB projectors (l<=2, rc=2.5), "
+                 "34-plane quadratic CAP peak 1 Ha, 9826 right-CAP columns per T(E,k) point")
+CFG3_WORKLOAD = ("point-contact slab 54x54x252 (h=0.399 bohr, 3x3x14 conventional FCC cells, a=7.19), "
+                 "12th-order FD, 380 Gaussian wells (1.5 Ha, 1.2 bohr) and 3420 KB projectors (l<=2, rc=2.5) "
+                 "with atoms outside a 5-bohr cylinder removed in cells 5-8, 36-plane quadratic CAP peak 1 Ha "
+                 "(104,976 right-CAP columns), 4x4 Monkhorst-Pack k-grid, 256 energies on [Vbar+0.05, Vbar+1.5]")
+
+
+def timed_loop(one, warmup, steps, budget, timed_share_s, warm_cap_s):
+    """W warm-up steps (stopping early past warm_cap_s), then up to K timed steps, stopping
+    after the step that crosses timed_share_s; returns (results, wall, warmups done)."""
+    import torch
+    t0 = time.time()
+    nw = 0
+    for i in range(warmup):
+        one(i)
+        nw += 1
+        if time.time() - t0 > warm_cap_s:
+            break
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for i in range(steps):
+        res.append(one(warmup + i))
+        if time.perf_counter() - t0 > timed_share_s or budget.left() < 60:
+            break
+    torch.cuda.synchronize()
+    return res, time.perf_counter() - t0, nw
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["cfg3", "cfg2"], default="cfg3",
+                    help="cfg3: point contact by the low-rank route (headline); cfg2: full-column FCC bulk points")
+    ap.add_argument("--energies-per-step", type=int, default=4, help="cfg3: energies per low-rank step")
+    ap.add_argument("--budget", type=float, default=450.0,
+                    help="wall seconds for the whole run, from process start (legs that do not fit are skipped)")
+    ap.add_argument("--timed-share", type=float, default=120.0,
+                    help="seconds after which the timed loop stops (reporting the steps it timed)")
     ap.add_argument("--precond", type=int, default=1, help="1: free-electron + CAP, 0: none")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
-                    help="fp64: FP64 throughout; mixed: FP32 applies inside FP64 refinement")
+                    help="cfg2 only. fp64: FP64 throughout; mixed: FP32 applies inside FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the plain-vs-batched comparison")
     ap.add_argument("--batched-energies", type=int, default=2,
@@ -357,6 +453,7 @@ def main():
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank transmission comparison")
     ap.add_argument("--no-stencil", action="store_true", help="skip the stand-alone operator apply")
     ap.add_argument("--no-cocg", action="store_true", help="skip the COCG comparison at k = 0")
+    ap.add_argument("--no-fullcol", action="store_true", help="skip the full-column config-2 point")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="before the run, copy this many GiB device-to-device (a reference "
                          "kernel of known traffic for hardware-counter scaling)")
@@ -366,12 +463,15 @@ def main():
               "MI355X (independent (k, E, column) units; see the design notes for how it shards). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    budget = Budget(args.budget)
 
     import torch
     from paper_2208_02783_amd import rst
     from paper_2208_02783_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    rst.load()
+    print(f"bench: imports done at {time.time() - T_START:.1f} s", file=sys.stderr, flush=True)
     if args.copy_calibration_gib > 0:
         nel = int(args.copy_calibration_gib * (1 << 30) // 8)
         a = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -379,7 +479,65 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    prob = wl.config(2)
+    prob2 = wl.config(2)
+    if args.workload == "cfg3":
+        line = headline_cfg3(args, budget)
+    else:
+        line = headline_cfg2(args, budget, prob2)
+    print(f"bench: headline done at {time.time() - T_START:.1f} s", file=sys.stderr, flush=True)
+    k_ref, e_ref = step_points(prob2, 0)
+    reserve = 0.0 if args.no_cpu_baseline else 30.0
+    if not args.no_cpu_baseline:
+        run_leg(line, "cpu_baseline", budget, 25.0, 0.0, lambda: cpu_baseline(10.0))
+    state = {}
+
+    def fullcol():
+        d = fullcol_point(prob2, k_ref, e_ref, args)
+        state["t_ref"] = d["T"]
+        return d
+    if args.workload == "cfg3" and not args.no_fullcol:
+        run_leg(line, "cfg2_full_column_point", budget, 35.0, reserve, fullcol)
+    elif args.workload == "cfg2":
+        state["t_ref"] = line["config"]["points"][0]["T"]
+        k_ref = line["config"]["points"][0]["k"]
+        e_ref = line["config"]["points"][0]["E"]
+    if not args.no_stencil:
+        run_leg(line, "stencil", budget, 15.0, reserve, lambda: stencil_apply(prob2, k_ref, e_ref))
+    if not args.no_lowrank and "t_ref" in state:
+        run_leg(line, "lowrank_cfg2", budget, 20.0, reserve,
+                lambda: lowrank_comparison(prob2, k_ref, e_ref, state["t_ref"]))
+    if not args.no_batched:
+        run_leg(line, "batched", budget, 30.0, reserve, lambda: batched_comparison(ne=args.batched_energies))
+    if not args.no_cocg:
+        run_leg(line, "cocg", budget, 45.0, reserve, lambda: cocg_comparison(prob2))
+    if not args.no_mixed and "t_ref" in state:
+        run_leg(line, "mixed", budget, 55.0, reserve, lambda: mixed_point(prob2, k_ref, e_ref, state["t_ref"]))
+    if not args.no_learned:
+        run_leg(line, "learned", budget, 50.0, reserve, lambda: learned_comparison(prob2))
+    line["wall_s_total"] = time.time() - T_START
+    print(json.dumps(line), flush=True)
+
+
+def fullcol_point(prob, k, e, args):
+    """One full-column T(E,k) point of the FCC bulk slab: all 9826 right-CAP
+    columns by the persistent preconditioned FP64 BiCGSTAB kernel."""
+    from paper_2208_02783_amd import rst
+    ctx = rst.Context(0)
+    ctx.load_problem(prob, k)
+    ctx.rst_set_solver(tol=args.tol, precond=1, max_iter=20000)
+    t0 = time.perf_counter()
+    t, st, s = ctx.rst_transmission(np.array([e]))
+    wall = time.perf_counter() - t0
+    return {"workload": CFG2_WORKLOAD, "k": [float(k[0]), float(k[1])], "E": e, "T": float(t[0]),
+            "status": int(s), "seconds": wall, "points_per_s": (s == rst.RST_OK) / wall,
+            "iterations_per_column": st["iterations_total"] / max(st["columns"], 1),
+            "kernel_ms": st["kernel_ms"], "algorithmic_GBps": st["bytes_algorithmic"] / (st["kernel_ms"] * 1e-3) / 1e9,
+            "frac_of_hbm_peak": st["bytes_algorithmic"] / (st["kernel_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS}
+
+
+def headline_cfg2(args, budget, prob):
+    import torch
+    from paper_2208_02783_amd import rst
     ctx = rst.Context(0)
     ctx.load_problem(prob, prob.kpts[0])
     ctx.rst_set_solver(tol=args.tol, precond=args.precond, max_iter=20000,
@@ -394,14 +552,7 @@ def main():
               file=sys.stderr, flush=True)
         return t[0], st, s, k, e
 
-    for i in range(args.warmup):
-        one(i)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = [one(args.warmup + i) for i in range(args.steps)]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
+    res, wall, nw = timed_loop(one, args.warmup, args.steps, budget, args.timed_share, 60.0)
     ok = all(r[2] == rst.RST_OK for r in res)
     kernel_ms = sum(r[1]["kernel_ms"] for r in res)
     bytes_alg = sum(r[1]["bytes_algorithmic"] for r in res)
@@ -409,60 +560,126 @@ def main():
     cols = sum(r[1]["columns"] for r in res)
     achieved = bytes_alg / (kernel_ms * 1e-3) / 1e9
     points_ok = sum(1 for r in res if r[2] == rst.RST_OK)
-    line = {
-        "metric": METRIC,
-        "value": points_ok / wall,
-        "unit": "T(E,k) points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
-        "data": "synthetic",
+    return {
+        "metric": METRIC, "value": points_ok / wall, "unit": "T(E,k) points/s", "n_gpus": 1,
+        "steps": len(res), "steps_requested": args.steps, "warmup": nw, "ms_per_step": wall * 1e3 / len(res),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
         "config": {
-            "workload": "FCC bulk slab 17x17x170 (h=0.401 bohr, a=6.82, 10 cells), 12th-order FD, "
-                        "40 Gaussian wells (1.5 Ha, 1.2 bohr), 360 KB projectors (l<=2, rc=2.5), "
-                        "34-plane quadratic CAP peak 1 Ha, 9826 right-CAP columns per T(E,k) point",
+            "workload": CFG2_WORKLOAD,
             "solver": ("right-preconditioned BiCGSTAB, free-electron + CAP preconditioner"
-                       if args.precond else "BiCGSTAB, no preconditioner"),
+                       if args.precond else "BiCGSTAB, no preconditioner") + ", every right-CAP column",
             "tol_true_rel_residual": args.tol,
             "precision": ("FP64 throughout" if args.precision == "fp64" else
                           "FP32 stencil/projector/preconditioner applies, FP64 refinement, "
                           "inner products and true residual"),
-            "points": [{"k": [float(r[3][0]), float(r[3][1])], "E": r[4], "T": r[0],
+            "points": [{"k": [float(r[3][0]), float(r[3][1])], "E": r[4], "T": float(r[0]),
                         "status": int(r[2])} for r in res],
-            "iterations_per_column_avg": iters / max(cols, 1),
-            "all_converged": ok,
+            "iterations_per_column_avg": iters / max(cols, 1), "all_converged": ok,
             "kernel_ms_total": kernel_ms,
         },
         "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
+            "kernel": "k_bicgstab_pc" if args.precond else "k_bicgstab",
+            "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": (measured_traffic(bytes_alg / args.steps, args.precond)
+            "traffic": (measured_traffic(bytes_alg / len(res), args.precond)
                         if args.precision == "fp64" else None),
         },
     }
-    if not args.no_stencil:
-        line["stencil"] = stencil_apply(prob, res[0][3], res[0][4])
-    if not args.no_batched:
-        line["batched"] = batched_comparison(ne=args.batched_energies)
-    if not args.no_cocg:
-        line["cocg"] = cocg_comparison(prob)
-    if not args.no_mixed and args.precision == "fp64":
-        line["mixed"] = mixed_point(prob, res[0][3], res[0][4], res[0][0])
-    if not args.no_learned:
-        line["learned"] = learned_comparison(prob)
-    if not args.no_lowrank and args.precision == "fp64":
-        line["lowrank"] = lowrank_comparison(prob, res[0][3], res[0][4], res[0][0])
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(line), flush=True)
+
+
+def headline_cfg3(args, budget):
+    """Config 3 by the low-rank route: step i = T(E, k) at k-point i mod 8 of the
+    4x4 Monkhorst-Pack grid (the eight k-points not related by k -> -k, which
+    gives the same T) for `energies_per_step` of the 256 energies, in one call.
+    A point counts when its solves converged and its tail estimate is within
+    tail_tol = 1e-7 (the neglected part of T, far inside the 1e-6 bar)."""
+    import torch
+    from paper_2208_02783_amd import rst
+    from paper_2208_02783_amd import workloads as wl
+    prob = wl.config(3)
+    ne = args.energies_per_step
+    tail_tol = 1e-7
+    ctx = rst.Context(0)
+    ctx.load_problem(prob, prob.kpts[0])
+    ctx.rst_set_solver(tol=args.tol, precond=1, max_iter=20000)
+    print(f"bench: config 3 loaded at {time.time() - T_START:.1f} s", file=sys.stderr, flush=True)
+
+    def one(i):
+        k = prob.kpts[i % 8]
+        sel = (np.arange(ne) * (256 // ne) + 37 * i) % len(prob.energies)
+        es = prob.energies[np.sort(sel)]
+        ctx.rst_set_k(k[0], k[1])
+        t, terr, st, s = ctx.rst_transmission_lowrank(es, probes=16, heldout=8, tail_tol=tail_tol, seed=1000 + i)
+        ok = int(np.sum(terr <= tail_tol)) if s in (rst.RST_OK, rst.RST_ENOCONV) and st["columns_unconverged"] == 0 \
+            else 0
+        print(f"step {i}: k={k} E={es[0]:.4f}..{es[-1]:.4f} T={np.round(t, 6)} max tail {np.max(terr):.1e} "
+              f"solves {st['columns']} its/solve {st['iterations_total'] / max(st['columns'], 1):.1f} "
+              f"kernel {st['kernel_ms']:.0f} ms status {s}", file=sys.stderr, flush=True)
+        return t, terr, st, s, k, es, ok
+
+    res, wall, nw = timed_loop(one, args.warmup, args.steps, budget, args.timed_share, 90.0)
+    points_ok = sum(r[6] for r in res)
+    kernel_ms = sum(r[2]["kernel_ms"] for r in res)
+    bytes_alg = sum(r[2]["bytes_algorithmic"] for r in res)
+    solves = sum(r[2]["columns"] for r in res)
+    its = sum(r[2]["iterations_total"] for r in res)
+    line = {
+        "metric": METRIC, "value": points_ok / wall, "unit": "T(E,k) points/s", "n_gpus": 1,
+        "steps": len(res), "steps_requested": args.steps, "warmup": nw, "ms_per_step": wall * 1e3 / len(res),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {
+            "workload": CFG3_WORKLOAD,
+            "solver": ("low-rank transmission (randomised range finder over the CAP blocks: 16 probes + 8 held-out "
+                       "solves on the right CAP, Cholesky QR, 16 adjoint solves at -k, probes doubled while the "
+                       "tail estimate exceeds 1e-7), each solve by the many-column right-preconditioned FP64 "
+                       "BiCGSTAB (free-electron + CAP preconditioner) to a true relative residual of 1e-10"),
+            "energies_per_step": ne, "tail_tol": tail_tol, "tol_true_rel_residual": args.tol,
+            "points": [{"k": [float(r[4][0]), float(r[4][1])], "E": [float(x) for x in r[5]],
+                        "T": [float(x) for x in r[0]], "tail_estimate": [float(x) for x in r[1]],
+                        "status": int(r[3])} for r in res],
+            "points_counted": points_ok, "points_computed": ne * len(res),
+            "solves": solves, "iterations_per_solve": its / max(solves, 1),
+            "kernel_ms_total": kernel_ms,
+            "solver_algorithmic_GBps": bytes_alg / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else None,
+        },
+    }
+    line["roofline"] = cfg3_roofline(ctx, prob, res[0][5][0], ncol=128)
+    return line
+
+
+def cfg3_roofline(ctx, prob, e, ncol=128, reps=5):
+    """Roofline of the dominant kernel of the config-3 solves, the many-column
+    apply k_apply_cols, at the block width the solver runs (128 columns: 24 probe
+    solves x 4 energies padded to whole 64-column chunks), timed live with HIP
+    events on the library's stream.  Algorithmic bytes per launch: read x and
+    write y, 32 B per grid point per column (V, the CAP and the projector tables
+    are read once per launch and not counted; the projections come from
+    k_proj_mm, timed separately)."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(11)
+    x = torch.randn((prob.n, ncol), dtype=torch.complex128, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    ctx.rst_apply_h(e, x.data_ptr(), y.data_ptr(), ncol)
+    pm, sm = [], []
+    for _ in range(reps):
+        ctx.rst_apply_h(e, x.data_ptr(), y.data_ptr(), ncol)
+        a, b = ctx.rst_apply_timing()
+        pm.append(a)
+        sm.append(b)
+    del x, y
+    alg = 32.0 * prob.n * ncol
+    ms = float(np.mean(sm))
+    achieved = alg / (ms * 1e-3) / 1e9
+    f = os.path.join(ROOT, "profiles", "k_apply_cols_cfg3_traffic.json")
+    traffic = None
+    if os.path.exists(f):
+        d = json.load(open(f))
+        if d.get("src_sha256") == src_hash() and d.get("ncol") == ncol:
+            traffic = d["traffic_bytes_per_launch"]
+    return {"kernel": "k_apply_cols", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "algorithmic_bytes_per_launch": alg,
+            "kernel_ms": ms, "projection_kernel_ms": float(np.mean(pm)), "columns": ncol}
 
 
 if __name__ == "__main__":

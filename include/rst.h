@@ -36,7 +36,9 @@
  *  - Status < 0: the call failed and wrote no output.  Status > 0: the call
  *    completed and wrote its outputs, with the condition recorded in rst_stats.
  *  - Setters invalidate dependent state: rst_set_grid clears potential,
- *    projectors, CAPs and k.  Calling out of order returns RST_ESTATE.
+ *    projectors, CAPs and k, and makes a batch built before it stale
+ *    (rst_batch_run then returns RST_ESTATE until rst_batch_clear).  Calling
+ *    out of order returns RST_ESTATE.
  *  - A context is not thread-safe.  rst_last_error() describes the last failure.
  */
 #ifndef RST_H
@@ -61,15 +63,27 @@ typedef enum {
   RST_EUNSUPPORTED = -5   /* valid but not supported by the GPU kernels */
 } rst_status;
 
-typedef enum { RST_BICGSTAB = 0, RST_FGMRES = 1, RST_COCG = 2 } rst_method;
+typedef enum { RST_BICGSTAB = 0, RST_FGMRES = 1, RST_COCG = 2, RST_BICGSTAB_MC = 3, RST_IDRS = 4 } rst_method;
 typedef enum { RST_FP64 = 0, RST_FP32_REFINE = 1 } rst_precision;
 typedef enum { RST_DIR_LR = 0, RST_DIR_RL = 1 } rst_direction;
 typedef enum { RST_PRECOND_NONE = 0, RST_PRECOND_FREE_CAP = 1, RST_PRECOND_LEARNED = 2 } rst_precond;
+typedef enum { RST_VREF_PLANE = 0, RST_VREF_CELL = 1 } rst_vref;
 
 /* Solver options.  rst_default_solver() fills the defaults. */
 typedef struct {
   int method;        /* rst_method.  RST_BICGSTAB: the persistent fused BiCGSTAB kernels (every precision
-                        and preconditioner except RST_PRECOND_LEARNED).  RST_FGMRES: restarted flexible
+                        and preconditioner except RST_PRECOND_LEARNED) for lateral planes of up to 1024
+                        points; wider planes (na*nb > 1024) are solved by RST_IDRS instead (FP64 only;
+                        col_block and threads must then be 0): BiCGSTAB stalls on long point-contact slabs.
+                        RST_BICGSTAB_MC: the same right-preconditioned BiCGSTAB over blocks of up to 1024
+                        columns in the column-fastest layout, one kernel per step (the many-column apply with
+                        per-column energies; the preconditioner as lateral DFT passes and one banded L D L^T
+                        solve of the operator's own order-2M z Laplacian per lateral mode and column), any
+                        plane size, FP64, preconditioner NONE or FREE_CAP, convergence on the FP64 true
+                        residual with restarts from it after a breakdown.  RST_IDRS: IDR(idr_s) with
+                        biorthogonalisation (Sonneveld and van Gijzen 2008; van Gijzen and Sonneveld 2011) on
+                        the same kernels and layout, right-preconditioned, a random shadow space shared by
+                        all columns; iterations_total then counts operator applies.  RST_FGMRES: restarted flexible
                         GMRES(restart) in FP64 over chunks of columns (classical Gram-Schmidt twice),
                         convergence on the FP64 true residual after each cycle; precision FP64 only.
                         RST_COCG: conjugate orthogonal conjugate gradients (van der Vorst and Melissen
@@ -88,23 +102,32 @@ typedef struct {
                         solved again in FP64 (stats.fallback_columns) */
   double tol;        /* stop when the FP64 true residual ||b - A x|| <= tol ||b|| per column (default 1e-10) */
   int max_iter;      /* BiCGSTAB iterations per column (default 20000) */
-  int col_block;     /* columns solved together by one workgroup; 0 = automatic (COCG: 1) */
+  int col_block;     /* columns solved together by one workgroup; 0 = automatic (FGMRES and COCG: 1) */
   int threads;       /* workgroup size (multiple of 64, <= 512); 0 = automatic */
   int direction;     /* RST_DIR_LR: columns in the right CAP, T accumulated on the left (default);
                         RST_DIR_RL: the reverse.  Both give the same T (exact identity). */
   double update_delta; /* RST_FP32_REFINE: the residual is replaced once its norm is below update_delta
                           times the largest since the last replacement (default 0.1, in (0, 1)) */
   int precond;       /* rst_precond.  RST_PRECOND_FREE_CAP: right preconditioner
-                        M = E - (-1/2 L_lat - 1/2 D2_z + Vbar) + i Gamma(z) with the exact
+                        M = E - (-1/2 L_lat - 1/2 D2_z + Vref(z)) + i Gamma(z) with the exact
                         lateral FD Laplacian (diagonal in the twisted lateral Fourier basis),
-                        the three-point z Laplacian and Vbar = mean(V); applied by lateral DFTs
-                        and one tridiagonal solve per lateral mode.  RST_PRECOND_LEARNED (RST_FGMRES
+                        the three-point z Laplacian and the reference potential Vref (pc_vref);
+                        applied by lateral DFTs and one tridiagonal solve per lateral mode.  RST_PRECOND_LEARNED (RST_FGMRES
                         only): z = M^-1 r + f(r, M^-1 r) with the context's network f (rst_cnn_*).
                         Default NONE. */
   int restart;       /* RST_FGMRES: Krylov steps per cycle (default 30, 1..200) */
   double fallback_ratio; /* RST_PRECOND_LEARNED: a column whose true residual after a cycle is above
                             fallback_ratio times the previous cycle's continues with M^-1 alone
                             (default 0.5, in (0, 1]) */
+  int pc_vref;       /* rst_vref, the preconditioner's reference potential.  RST_VREF_PLANE (default):
+                        Vref(z) = the mean of V over plane z, which keeps M separable (lateral modes
+                        still do not mix) and follows a potential that changes along the transport
+                        axis (a constriction, vacuum padding); RST_VREF_CELL: Vref = the mean of V
+                        over the cell. */
+  int idr_s;         /* RST_IDRS: dimension s of the shadow space (default 4, 1..8) */
+  double pc_shift;   /* imaginary shift eta >= 0 (Ha) added to the CAP inside the preconditioner only,
+                        M(eta) = M + i eta: damps the reference operator's standing waves between the
+                        CAPs of a long slab (a shifted-Laplacian preconditioner); default 0 */
 } rst_solver_opts;
 
 /* Statistics of the last rst_transmission / rst_solve_columns call. */
@@ -166,14 +189,24 @@ const char *rst_last_error(const rst_ctx *ctx);
 rst_status rst_set_grid(rst_ctx *ctx, int na, int nb, int nz, double ha, double hb, double hz,
                         int fd_order);
 
-/* Local potential V, n = na*nb*nz doubles (Ha), host memory, copied.
+/* Local potential V, n = na*nb*nz doubles (Ha), host memory, copied: the
+ * local part of the Kohn-Sham effective potential V_KS(x, y, z), periodic in
+ * the lateral plane (Sec. II.A, preliminaries), sampled on the grid and added
+ * to the diagonal of H_KS in G(E) = [E - H_KS + i Gamma]^-1 (ibid.).
  * RST_ESTATE before rst_set_grid; RST_EINVAL for NULL or a non-finite value. */
 rst_status rst_set_potential(rst_ctx *ctx, const double *v);
 
-/* Separable projectors in compressed rows over projectors: entries
+/* The nonlocal part of the norm-conserving pseudopotentials (s, p and d
+ * channels inside per-channel cutoff radii, Sec. IV.A bulk Cu and Sec. V.A
+ * bulk Rh), in separable Kleinman-Bylander form h^3 sum_p E_p |beta_p><beta_p|;
+ * the lateral images carry the Bloch phase exp(+i k.R) of the Bloch-form
+ * equation (Sec. II.A).  Compressed rows over projectors: entries
  * offs[p]..offs[p+1]-1 of projector p.  pt[e] is a grid index, img[2e],
  * img[2e+1] the lateral image (ia, ib) the entry comes from, beta[e] its real
- * value; e_kb[p] the projector energy (Ha).  nproj may be 0.  Copied. */
+ * value; e_kb[p] the projector energy (Ha).  nproj may be 0.  Host arrays,
+ * copied.  RST_ESTATE before rst_set_grid; RST_EINVAL for nproj < 0, a null
+ * array with nproj > 0, offs not non-decreasing from 0, a grid index outside
+ * 0..n-1, or a non-finite beta or e_kb. */
 rst_status rst_set_projectors(rst_ctx *ctx, int nproj, const int32_t *offs, const int32_t *pt,
                               const int8_t *img, const double *beta, const double *e_kb);
 
@@ -289,7 +322,9 @@ rst_status rst_solve_rhs(rst_ctx *ctx, int n_e, const double *energies, int ncol
  * probes, an estimate of the neglected part (T_true = T + neglected >= T); while
  * it exceeds tail_tol the probe count doubles (up to max_probes).  Returns
  * RST_ENOCONV when a solve missed the tolerance or an energy ended above tail_tol.
- * FP64 BiCGSTAB, direction LR. */
+ * FP64 BiCGSTAB (RST_BICGSTAB or RST_BICGSTAB_MC).  With direction RST_DIR_RL
+ * the two CAPs exchange roles: T_RL = 4 ||Gamma_R^1/2 G Gamma_L^1/2||_F^2, equal
+ * to T_LR for any Hermitian H_k and real CAPs. */
 typedef struct {
   int probes;        /* initial probe count s (default 32) */
   int heldout;       /* held-out probes p for the tail estimate (default 8) */

@@ -49,6 +49,8 @@ struct ColApplyArgs {
   Proj pj;
   const double2* P;   // [nproj*ncol]
   int zseg;           // planes per wave (>= 1)
+  const double* ecol; // [ncol] energy of each column (nullable: `energy` for all)
+  const int* mask;    // [ncol] columns to apply (nullable: all); others are left untouched
 };
 
 template <class V2>
@@ -94,7 +96,8 @@ __global__ __launch_bounds__(64, (ApplyMinWaves<F, NMU>::value)) void k_apply_co
   }
   const int z0 = seg * A.zseg, z1 = min(nz, z0 + A.zseg);
   const int c = chunk * 64 + (int)threadIdx.x;
-  const bool ok = c < ncol;
+  const bool ok = c < ncol && (A.mask == nullptr || A.mask[c] != 0);
+  const double ec = A.ecol != nullptr && c < ncol ? A.ecol[c] : A.energy;
   const int ia = p % na, ib = p / na;
   const V2 pha{(F)g.pha_x, (F)g.pha_y}, phac{(F)g.pha_x, (F)-g.pha_y};
   const V2 phb{(F)g.phb_x, (F)g.phb_y}, phbc{(F)g.phb_x, (F)-g.phb_y};
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(64, (ApplyMinWaves<F, NMU>::value)) void k_apply_co
     const long long base = (long long)z * P;
     const long long gi = base + p;
     const V2 u = q[RAD];
-    const F dr = (F)(A.energy - A.V[gi] + g.diag0);
+    const F dr = (F)(ec - A.V[gi] + g.diag0);
     const F gzz = (F)A.gz[z];
     V2 y{dr * u.x - gzz * u.y, dr * u.y + gzz * u.x};
 #pragma unroll

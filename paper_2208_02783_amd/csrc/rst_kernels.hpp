@@ -166,8 +166,10 @@ struct Proj {
 
 // Constants of the free-electron + CAP preconditioner (see rst_precond.hpp).
 struct PcConst {
-  double vbar;           // shift of the reference operator
+  double vbar;           // shift of the reference operator (when vz is null)
+  const double* vz;      // [nz] plane-dependent shift (the lateral mean of V per plane; nullable)
   double a;              // 1/2 / hz^2 (three-point z coupling)
+  double shift;          // imaginary shift added to the CAP in the preconditioner (Ha)
   const double* eps;     // [P] lateral mode energies eps_perp(m)
   const double2* steps;  // [3(na+nb)] DFT recurrence steps fa, fb, ia, ib and phases pa, pb
   const double2* inv;    // [ne*nz*P] reciprocal Thomas pivots per energy, plane, lateral mode

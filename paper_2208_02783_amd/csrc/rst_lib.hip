@@ -7,6 +7,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <map>
 #include <random>
 #include <string>
@@ -20,6 +21,8 @@
 #include "rst_projmm.hpp"
 #include "rst_apply_cols.hpp"
 #include "rst_mixed.hpp"
+#include "rst_mk.hpp"
+#include "rst_idr.hpp"
 
 using rst::cx;
 
@@ -32,7 +35,8 @@ __global__ void k_fill_int(int* p, int n, int v) {
 
 // Reciprocal Thomas pivots of the preconditioner for every (energy, lateral
 // mode): den_0 = b_0, den_z = b_z - a^2 / den_{z-1}, with
-// b_z = E - Vbar - eps_perp(m) - 2a + i Gamma(z).  One thread per (E, m).
+// b_z = E - Vref(z) - eps_perp(m) - 2a + i Gamma(z), Vref(z) the plane mean of V
+// (pc.vz) or the cell mean (pc.vbar).  One thread per (E, m).
 __global__ void k_pc_pivots(const SolveArgs* __restrict__ Ap) {
   const SolveArgs& A = *Ap;
   const int P = A.g.P, nz = A.g.nz;
@@ -40,11 +44,11 @@ __global__ void k_pc_pivots(const SolveArgs* __restrict__ Ap) {
   if (t >= (long long)A.ne * P) return;
   const int e = (int)(t / P), m = (int)(t % P);
   const double a = A.pc.a, a2 = a * a;
-  const double re0 = A.energies[e] - A.pc.vbar - A.pc.eps[m] - 2.0 * a;
+  const double re0 = A.energies[e] - A.pc.eps[m] - 2.0 * a;
   double2* inv = const_cast<double2*>(A.pc.inv) + (size_t)e * nz * P;
   cx<double> iv = mkc(0.0, 0.0);
   for (int z = 0; z < nz; ++z) {
-    cx<double> den = mkc(re0, A.gz[z]);
+    cx<double> den = mkc(re0 - (A.pc.vz ? A.pc.vz[z] : A.pc.vbar), A.gz[z] + A.pc.shift);
     if (z > 0) den = den - cscale(iv, a2);
     iv = cdiv(mkc(1.0, 0.0), den);
     double2 o;
@@ -105,7 +109,7 @@ struct rst_ctx {
   std::vector<double> sc_beta;
   int has_overflow = 0;
   // device copies
-  DevBuf d_v, d_gz, d_gl, d_gr;
+  DevBuf d_v, d_gz, d_gl, d_gr, d_vz;  // d_vz: plane means of V (preconditioner reference)
   DevBuf d_pc_eps, d_pc_twa, d_pc_twb;
   DevBuf d_grp_pbase, d_grp_nm, d_ekb, d_beta, d_eph, d_ent_p, d_zc, d_chunks, d_zg, d_zgroups,
       d_pe_offs, d_pe, d_sc_pb, d_sc_eph, d_sc_beta, d_g_ent_p, d_g_eph, d_g_beta;
@@ -123,6 +127,11 @@ struct rst_ctx {
   double last_cnn_flop = 0.0;     // FGMRES: network flops of the last solve
   double last_fg_bytes = 0.0;     // FGMRES: algorithmic vector bytes of the last solve
   double last_extra_bytes = 0.0;  // mixed precision: bytes of the FP64 re-solves
+  bool last_mk = false;           // the last solve ran the many-column BiCGSTAB
+  double last_mk_bytes = 0.0;     // its algorithmic bytes
+  // many-column BiCGSTAB (planes of any size): vectors, per-column state, partial sums, column tables,
+  // DFT matrices of the preconditioner
+  DevBuf d_mkv, d_mkst, d_mkact, d_mkmark, d_mkpart, d_mkcol, d_mkF, d_mkT, d_mkvref, d_mkidr, d_mkshadow;
   // COCG chunk buffers: R, P, Q vectors; per-column scalars and flags
   DevBuf d_cgR, d_cgP, d_cgQ, d_cgs, d_cgi;
   // flexible GMRES chunk buffers
@@ -130,15 +139,19 @@ struct rst_ctx {
       d_fgact, d_fgit, d_fguse, d_fgh1, d_fgh2, d_fgn2, d_fgy, d_fgsrc, d_fgbsc, d_fgt, d_fgaa, d_fgpa, d_fgsa;
   // batch of structures (rst_batch_add)
   struct HostProb {
+    long long grid_version;  // rst_set_grid calls made before the structure was added
     int nz;
     std::vector<double> v, gl, gr, en;
     double ka, kb;
   };
   std::vector<HostProb> batch;
   int batch_version = 0;
+  long long grid_version = 0;
   std::map<long long, int> tuned_cw;  // (lateral shape, order, direction) -> columns per workgroup
   hipGraphExec_t gexec = nullptr;
-  long long gexec_key = -1;
+  // what the captured launch depends on: batch contents, kernel, launch shape, LDS bytes and every
+  // device pointer baked into the graph (argument block, work counter, workspace)
+  std::array<long long, 9> gexec_key{};
   DevBuf d_bprob, d_bv, d_bgz, d_bgl, d_bgr, d_ben, d_bcols, d_bpc_eps, d_bpc_steps, d_bpargs;
   int last_cw = 0, last_threads = 0;
   // host copies of the last kernel-argument blocks (kept alive for async copies)
@@ -299,6 +312,77 @@ rst_status proj_blocked(rst_ctx* c, const rst::ApplyArgs& A) {
 // Builds the projector plan: groups of consecutive projectors with identical
 // (point, image) entry lists, entries sorted by plane, per-plane gather chunks,
 // and the point-centric scatter lists.
+// y = (E - H_k + i Gamma) x on an n x ncol column-fastest block: the projections
+// h^3 B^H x of every column on the FP64 matrix cores (k_proj_mm, into projP:
+// nproj*ncol complex128), then one wave per (64 columns, z segment, grid point)
+// (k_apply_cols).  ecol (nullable) gives each column its own energy, mask
+// (nullable) the columns to apply.  ev (nullable): three events recorded before,
+// between and after the two kernels.
+rst_status apply_cols(rst_ctx* c, const void* x, void* y, int ncol, double energy, const double* ecol,
+                      const int* mask, bool f32, double2* projP, hipEvent_t* ev) {
+  const int P = c->na * c->nb;  // rst_set_grid guarantees na, nb > rad: one wrap at most
+  // planes per wave: short segments keep the waves that share lateral rows close in z
+  const int zseg = std::min(c->nz, rst::APPLY_ZSEG);
+  const long long nseg = (c->nz + zseg - 1) / zseg;
+  const long long nwg = (long long)((ncol + 63) / 64) * nseg * P;  // one wave per (64 columns, segment, point)
+  if (nwg > 0x7fffffffLL) return fail(c, RST_EINVAL, "too many columns for one launch");
+  rst::ColApplyArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.x = x;
+  A.y = y;
+  A.ncol = ncol;
+  A.g = make_geo(c);
+  A.V = (const double*)c->d_v.p;
+  A.gz = (const double*)c->d_gz.p;
+  A.energy = energy;
+  A.pj = make_proj(c);
+  A.zseg = zseg;
+  A.ecol = ecol;
+  A.mask = mask;
+  if (ev) HIPCHK(c, hipEventRecord(ev[0], c->stream));
+  if (c->nproj > 0) {
+    // all projections P = h^3 B^H x at once on the matrix cores; the apply kernel then scatters B E P
+    rst::ProjMMArgs M;
+    std::memset(&M, 0, sizeof(M));
+    M.X = x;
+    M.P = projP;
+    M.grp_e0 = (const int*)c->d_grp_e0.p;
+    M.grp_ne = (const int*)c->d_grp_ne.p;
+    M.grp_pbase = (const int*)c->d_grp_pbase.p;
+    M.grp_nm = (const int*)c->d_grp_nm.p;
+    M.ent_gi = (const int*)c->d_ent_gi.p;
+    M.eph = (const double2*)c->d_eph.p;
+    M.beta = (const double*)c->d_beta.p;
+    M.nm = c->nm;
+    M.ngroup = c->ngroup;
+    M.ncol = ncol;
+    M.h3 = c->ha * c->hb * c->hz;
+    const long long tiles = (long long)c->ngroup * ((ncol + 63) / 64);  // one workgroup per (group, 64 columns)
+    if (f32)
+      hipLaunchKernelGGL(rst::k_proj_mm<float2>, dim3((unsigned)tiles), dim3(256), 0, c->stream, M);
+    else
+      hipLaunchKernelGGL(rst::k_proj_mm<double2>, dim3((unsigned)tiles), dim3(256), 0, c->stream, M);
+    HIPCHK(c, hipGetLastError());
+    A.P = projP;
+  }
+  if (ev) HIPCHK(c, hipEventRecord(ev[1], c->stream));
+  const bool nm9 = c->nm <= 9;
+  void* kern = nullptr;
+  if (f32)
+    kern = c->rad == 6 ? (nm9 ? (void*)rst::k_apply_cols<6, 9, float> : (void*)rst::k_apply_cols<6, 16, float>)
+                       : (nm9 ? (void*)rst::k_apply_cols<2, 9, float> : (void*)rst::k_apply_cols<2, 16, float>);
+  else
+    kern = c->rad == 6 ? (nm9 ? (void*)rst::k_apply_cols<6, 9, double> : (void*)rst::k_apply_cols<6, 16, double>)
+                       : (nm9 ? (void*)rst::k_apply_cols<2, 9, double> : (void*)rst::k_apply_cols<2, 16, double>);
+  {
+    void* args[] = {&A};
+    HIPCHK(c, hipLaunchKernel(kern, dim3((unsigned)nwg), dim3(64), args, 0, c->stream));
+  }
+  HIPCHK(c, hipGetLastError());
+  if (ev) HIPCHK(c, hipEventRecord(ev[2], c->stream));
+  return RST_OK;
+}
+
 rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t* pt, const int8_t* img,
                       const double* beta, const double* ekb) {
   const long long n = (long long)c->na * c->nb * c->nz;
@@ -498,6 +582,12 @@ void pc_tables(const rst_ctx* c, double ka, double kb, std::vector<double>& eps,
   for (int b = 0; b < nb; ++b) push(kb * b * c->hb);
 }
 
+// Reference potential of the preconditioner: the plane means of V (the default, pc_vref
+// RST_VREF_PLANE) or, with RST_VREF_CELL, none (the kernels then use the cell mean pc.vbar).
+const double* pc_vz(const rst_ctx* c) {
+  return c->opts.pc_vref == RST_VREF_CELL ? nullptr : (const double*)c->d_vz.p;
+}
+
 // Lateral mode energies and DFT steps of the free-electron + CAP
 // preconditioner for the current grid and k.
 rst_status upload_pc(rst_ctx* c) {
@@ -617,11 +707,18 @@ rst_status run_cocg(rst_ctx* c, int ne, const double* energies, const std::vecto
                     std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
                     std::vector<double>& res, std::vector<int>& st, double& ms);
 
+rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
+                           const double* d_gsrc, const double* d_gdst, double2* xout, std::vector<double>& Tcol,
+                           std::vector<int>& its, std::vector<int>& rss, std::vector<double>& res,
+                           std::vector<int>& st, double& ms, const double2* rhs, long long rhs_ld,
+                           long long rhs_estride);
+
 rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
                       const double* d_gsrc, const double* d_gdst, double2* xout,
                       std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
                       std::vector<double>& res, std::vector<int>& st, double& ms,
                       const double2* rhs = nullptr, long long rhs_ld = 0, long long rhs_estride = 0) {
+  c->last_mk = false;
   if (c->opts.method == RST_FGMRES) {
     const std::vector<double>* hsrc = d_gsrc == nullptr ? nullptr : (d_gsrc == c->d_gr.p ? &c->gr : &c->gl);
     return run_fgmres(c, ne, energies, cols, d_gdst, hsrc, xout, Tcol, its, rss, res, st, ms);
@@ -629,6 +726,15 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   if (c->opts.method == RST_COCG) {
     const std::vector<double>* hsrc = d_gsrc == nullptr ? nullptr : (d_gsrc == c->d_gr.p ? &c->gr : &c->gl);
     return run_cocg(c, ne, energies, cols, d_gdst, hsrc, xout, Tcol, its, rss, res, st, ms);
+  }
+  // the persistent kernels hold a whole lateral plane per workgroup; wider planes go to the
+  // many-column BiCGSTAB, one kernel per step
+  if (c->opts.method == RST_BICGSTAB_MC || c->opts.method == RST_IDRS || c->na * c->nb > 2 * rst::MAX_T) {
+    if (c->opts.col_block > 0 || c->opts.threads > 0)
+      return fail(c, RST_EUNSUPPORTED, "col_block and threads apply to the persistent kernels (planes of at most " +
+                                           std::to_string(2 * rst::MAX_T) + " points)");
+    return run_bicgstab_mk(c, ne, energies, cols, d_gsrc, d_gdst, xout, Tcol, its, rss, res, st, ms, rhs, rhs_ld,
+                           rhs_estride);
   }
   LaunchShape ls;
   rst_status s = choose_shape(c, c->opts.col_block, c->opts.threads, ls);
@@ -695,6 +801,8 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
     A.pc.vbar = vbar / (double)c->v.size();
     A.pc.a = 0.5 / (c->hz * c->hz);
     A.pc.eps = (const double*)c->d_pc_eps.p;
+    A.pc.vz = pc_vz(c);
+    A.pc.shift = c->opts.pc_shift;
     A.pc.steps = (const double2*)c->d_pc_twa.p;
     if ((s = ensure(c, c->d_pc_inv, (size_t)ne * n * 16)) != RST_OK) return s;
     A.pc.inv = (const double2*)c->d_pc_inv.p;
@@ -855,6 +963,8 @@ void fill_stats(rst_ctx* c, rst_stats* st, const std::vector<int>& its, const st
                           (double)s.updates_total * 72.0 * n + c->last_extra_bytes;
   else if (fgm)
     s.bytes_algorithmic = c->last_fg_bytes;
+  else if (c->last_mk)
+    s.bytes_algorithmic = c->last_mk_bytes;
   else
     s.bytes_algorithmic = (double)s.iterations_total * streams * 16.0 * n;
   if (st) *st = s;
@@ -914,7 +1024,9 @@ rst_status run_fgmres(rst_ctx* c, int ne, const double* energies, const std::vec
   const int ncols = (int)cols.size();
   // launch shape shared by the apply and preconditioner kernels
   BlockedShape bs;
-  rst_status s = blocked_shape(c, c->opts.col_block > 0 ? c->opts.col_block : 8, c->opts.threads, bs);
+  // automatic: one column per workgroup (config 2: 5.7 s against 6.0 s with the widest block on 512
+  // columns)
+  rst_status s = blocked_shape(c, c->opts.col_block > 0 ? c->opts.col_block : 1, c->opts.threads, bs);
   if (s != RST_OK) return s;
   const LaunchShape ls = bs.ls;
   const int cw = ls.cw;
@@ -1043,6 +1155,8 @@ rst_status run_fgmres(rst_ctx* c, int ne, const double* energies, const std::vec
       A.pc.vbar = vbar;
       A.pc.a = 0.5 / (c->hz * c->hz);
       A.pc.eps = (const double*)c->d_pc_eps.p;
+      A.pc.vz = pc_vz(c);
+      A.pc.shift = c->opts.pc_shift;
       A.pc.steps = (const double2*)c->d_pc_twa.p;
       A.pc.inv = (const double2*)c->d_pc_inv.p;
       std::vector<rst::SolveArgs> sa(1, A);
@@ -1262,6 +1376,532 @@ rst_status run_fgmres(rst_ctx* c, int ne, const double* energies, const std::vec
 // its FP64 true residual computed: below tol it is done, otherwise the
 // chunk's residual is replaced by the true one and that column restarts with
 // p = M^-1 r.  Columns still running at max_iter end unconverged.
+// Algorithmic bytes per grid point, iteration and column of the many-column BiCGSTAB: p update
+// 64, M^-1 p 192 (four DFT passes and the Thomas sweeps, each reading and writing the block),
+// apply 32, (r0h, v) 32, s update 48, M^-1 s 192, apply 32, (t, s) and (t, t) 32, x/r update and
+// dots 128; without the preconditioner the two M^-1 passes drop out.  Plus 16 B per projector
+// sphere entry per apply (the projections read x at the entries).
+double mk_bytes_per_point(bool pc) { return pc ? 752.0 : 368.0; }
+
+// Algorithmic bytes per grid point, operator apply and column of the many-column IDR(s), averaged over
+// a cycle of s + 1 applies: step k reads r and g_k..g_{s-1} and writes v (s - k + 2 streams), forms
+// u_k from u_k..u_{s-1} and M^-1 v (s - k + 2), applies M^-1 (12) and A (2), the dots read g_k (1),
+// the update reads and writes g_k, u_k, r, x and reads g_0..g_{k-1}, u_0..u_{k-1} (2k + 8); the
+// dimension-reduction step costs M^-1, A, the two dots (2), the r/x update (5) and the dots with P (1).
+// 16 B per stream.
+double idr_bytes_per_matvec(int s, bool pc) {
+  const double mpc = pc ? 12.0 : 0.0;
+  double streams = 0.0;
+  for (int k = 0; k < s; ++k) streams += (s - k + 2) + (s - k + 2) + mpc + 2 + 1 + (2 * k + 8);
+  streams += mpc + 2 + 2 + 5 + 1;
+  return 16.0 * streams / (s + 1);
+}
+
+// Many-column right-preconditioned BiCGSTAB (rst_mk.hpp) over the (energy, column) items, in blocks
+// of up to `ld` columns with one kernel per step; same inputs and outputs as the persistent solver.
+rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
+                           const double* d_gsrc, const double* d_gdst, double2* xout, std::vector<double>& Tcol,
+                           std::vector<int>& its, std::vector<int>& rss, std::vector<double>& res,
+                           std::vector<int>& st, double& ms, const double2* rhs, long long rhs_ld,
+                           long long rhs_estride) {
+  if (c->opts.precision != RST_FP64)
+    return fail(c, RST_EUNSUPPORTED, "the many-column solvers run in FP64 only");
+  const bool pc = c->opts.precond == RST_PRECOND_FREE_CAP;
+  const int na = c->na, nb = c->nb, nz = c->nz, P = na * nb;
+  const long long n = (long long)P * nz;
+  const int ncols = (int)cols.size();
+  const long long nitems = (long long)ne * ncols;
+  const std::vector<double>* hsrc = d_gsrc == nullptr ? nullptr : (d_gsrc == c->d_gr.p ? &c->gr : &c->gl);
+  c->last_cw = 0;
+  c->last_threads = 256;
+  // IDR(s) for RST_IDRS and for wide planes under RST_BICGSTAB (the method that converges on them)
+  const bool idr = c->opts.method == RST_IDRS || (c->opts.method == RST_BICGSTAB && P > 2 * rst::MAX_T);
+  const int sdim = idr ? c->opts.idr_s : 0;
+  // block width: vectors X R R0 P V T (+ PH SH W with the preconditioner); IDR(s): X R V T G_0..G_{s-1}
+  // U_0..U_{s-1} (+ VH W); at most a quarter of free memory
+  const int nvec = idr ? (4 + 2 * sdim + (pc ? 2 : 0)) : (pc ? 9 : 6);
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
+  const size_t per_col = (size_t)nvec * n * 16 + (size_t)c->nproj * 16;
+  long long ldmax = std::max<long long>(64, (long long)(free_b / 4 / per_col) / 64 * 64);
+  ldmax = std::min<long long>(ldmax, 1024);
+  const int ld = (int)std::min<long long>(ldmax, (nitems + 63) / 64 * 64);
+  rst::mk::Shape S;
+  S.n = n;
+  S.ld = ld;
+  int ncu = 0;
+  HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  // row ranges: about eight reducing workgroups per compute unit in all
+  S.nsplit = (int)std::max<long long>(1, std::min<long long>(n / 64, 8LL * ncu / (ld / 64)));
+  S.rows = (n + S.nsplit - 1) / S.nsplit;
+  const size_t vlen = (size_t)n * ld;
+  rst_status e;
+  if ((e = ensure(c, c->d_mkv, (size_t)nvec * vlen * 16)) != RST_OK) return e;
+  double2* X = (double2*)c->d_mkv.p;
+  double2* R = X + vlen;
+  double2* R0 = R + vlen;  // BiCGSTAB: shadow residual; IDR(s): v
+  double2* Pv = R0 + vlen; // BiCGSTAB: p; IDR(s): t
+  double2 *V, *T, *PH, *SH, *W, *Gb = nullptr, *Ub = nullptr;
+  if (!idr) {
+    V = Pv + vlen;
+    T = V + vlen;
+    PH = pc ? T + vlen : Pv;
+    SH = pc ? PH + vlen : R;
+    W = pc ? SH + vlen : nullptr;
+  } else {
+    V = R0;
+    T = Pv;
+    Gb = Pv + vlen;
+    Ub = Gb + (size_t)sdim * vlen;
+    PH = pc ? Ub + (size_t)sdim * vlen : V;  // M^-1 v
+    W = pc ? PH + vlen : nullptr;
+    SH = nullptr;
+  }
+  double2* Wres = idr ? T : V;  // the true residual's A x reuses a vector the next step rebuilds
+  if ((e = ensure(c, c->d_mkst, (size_t)ld * sizeof(rst::mk::ColSt))) != RST_OK) return e;
+  if ((e = ensure(c, c->d_mkact, (size_t)ld * 4)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_mkmark, (size_t)ld * 4)) != RST_OK) return e;
+  if ((e = ensure(c, c->d_mkpart, (size_t)(idr ? sdim + 1 : 2) * S.nsplit * ld * 16)) != RST_OK) return e;
+  if (idr) {
+    if ((e = ensure(c, c->d_mkidr, (size_t)ld * sizeof(rst::idr::IdrSt))) != RST_OK) return e;
+    if ((e = ensure(c, c->d_mkshadow, (size_t)n * sdim * 16)) != RST_OK) return e;
+    const long long ns = n * sdim;
+    hipLaunchKernelGGL(rst::idr::k_idr_shadow, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, c->stream, n, sdim,
+                       (unsigned long long)0x5EED1D25ULL, (double2*)c->d_mkshadow.p);
+    HIPCHK(c, hipGetLastError());
+  }
+  if ((e = ensure(c, c->d_mkT, (size_t)ld * 8)) != RST_OK) return e;
+  if (c->nproj > 0 && (e = ensure(c, c->d_projP, (size_t)c->nproj * ld * 16)) != RST_OK) return e;
+  rst::mk::ColSt* dst_ = (rst::mk::ColSt*)c->d_mkst.p;
+  int* act = (int*)c->d_mkact.p;
+  int* mark = (int*)c->d_mkmark.p;
+  double2* part = (double2*)c->d_mkpart.p;
+  // column tables: energy, pivot slice, point source, its value, dense offset
+  const size_t tab_bytes = (size_t)ld * (8 + 4 + 8 + 8 + 8);
+  if ((e = ensure(c, c->d_mkcol, tab_bytes)) != RST_OK) return e;
+  double* d_ecol = (double*)c->d_mkcol.p;
+  long long* d_src = (long long*)(d_ecol + ld);
+  double* d_bsc = (double*)(d_src + ld);
+  long long* d_doff = (long long*)(d_bsc + ld);
+  int* d_eidx = (int*)(d_doff + ld);
+  rst::mk::Rhs B;
+  B.src = d_src;
+  B.bsc = d_bsc;
+  B.dense = rhs;
+  B.dld = rhs_ld;
+  B.doff = d_doff;
+  // preconditioner: DFT passes: (w, post) tables of forward a, inverse a, forward b, inverse b; band factors
+  const double2 *band_L = nullptr, *band_dinv = nullptr;
+  const double2 *FAw = nullptr, *FAp = nullptr, *IAw = nullptr, *IAp = nullptr;
+  const double2 *FBw = nullptr, *FBp = nullptr, *IBw = nullptr, *IBp = nullptr;
+  if (pc) {
+    const double pi = 3.14159265358979323846;
+    std::vector<double2> F((size_t)4 * na + (size_t)4 * nb);
+    auto put = [](double2& d, double ph, double sc) { d = double2{sc * std::cos(ph), sc * std::sin(ph)}; };
+    double2* t = F.data();
+    for (int j = 0; j < na; ++j) {
+      put(t[j], -(2 * pi * j / na + c->ka * c->ha), 1.0);  // forward a: w
+      put(t[na + j], 0.0, 1.0);                             // forward a: post
+      put(t[2 * na + j], 2 * pi * j / na, 1.0);             // inverse a: w
+      put(t[3 * na + j], c->ka * c->ha * j, 1.0 / na);      // inverse a: post
+    }
+    t += 4 * na;
+    for (int j = 0; j < nb; ++j) {
+      put(t[j], -(2 * pi * j / nb + c->kb * c->hb), 1.0);
+      put(t[nb + j], 0.0, 1.0);
+      put(t[2 * nb + j], 2 * pi * j / nb, 1.0);
+      put(t[3 * nb + j], c->kb * c->hb * j, 1.0 / nb);
+    }
+    if ((e = upload(c, c->d_mkF, F)) != RST_OK) return e;
+    const double2* d = (const double2*)c->d_mkF.p;
+    FAw = d;
+    FAp = d + na;
+    IAw = d + 2 * na;
+    IAp = d + 3 * na;
+    FBw = d + 4 * na;
+    FBp = FBw + nb;
+    IBw = FBw + 2 * nb;
+    IBp = FBw + 3 * nb;
+    // banded L D L^T of the z operator per (energy, lateral mode)
+    std::vector<double> en(energies, energies + ne);
+    if ((e = upload(c, c->d_en, en)) != RST_OK) return e;
+    if ((e = ensure(c, c->d_pc_inv, (size_t)ne * n * 16 * (1 + c->rad))) != RST_OK) return e;
+    rst::mk::Band Bd;
+    std::memset(&Bd, 0, sizeof(Bd));
+    Bd.dinv = (double2*)c->d_pc_inv.p;
+    Bd.L = Bd.dinv + (size_t)ne * n;
+    Bd.energies = (const double*)c->d_en.p;
+    Bd.eps = (const double*)c->d_pc_eps.p;
+    Bd.gz = (const double*)c->d_gz.p;
+    // the reference potential per plane: the plane means, or the cell mean on every plane
+    std::vector<double> vref(nz, 0.0);
+    {
+      double vbar = 0.0;
+      for (double x : c->v) vbar += x;
+      vbar /= (double)c->v.size();
+      for (int z = 0; z < nz; ++z) {
+        double acc = 0.0;
+        for (int q = 0; q < P; ++q) acc += c->v[(size_t)z * P + q];
+        vref[z] = c->opts.pc_vref == RST_VREF_CELL ? vbar : acc / P;
+      }
+    }
+    if ((e = upload(c, c->d_mkvref, vref)) != RST_OK) return e;
+    Bd.vz = (const double*)c->d_mkvref.p;
+    for (int j = 0; j <= c->rad; ++j) Bd.cz[j] = 0.5 * c->fdw[j] / (c->hz * c->hz);
+    Bd.M = c->rad;
+    Bd.shift = c->opts.pc_shift;
+    Bd.P = P;
+    Bd.nz = nz;
+    Bd.ne = ne;
+    const long long nt = (long long)ne * P;
+    hipLaunchKernelGGL(rst::mk::k_mk_band_factor, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream, Bd);
+    HIPCHK(c, hipGetLastError());
+    band_L = Bd.L;
+    band_dinv = Bd.dinv;
+  }
+  // outputs per wave: the smallest instance with 4*RW >= N (N > 64 takes several rounds of 64)
+  auto dft_kernel = [](int N) -> const void* {
+    if (N <= 8) return (const void*)rst::mk::k_mk_dft<2>;
+    if (N <= 16) return (const void*)rst::mk::k_mk_dft<4>;
+    if (N <= 32) return (const void*)rst::mk::k_mk_dft<8>;
+    return (const void*)rst::mk::k_mk_dft<16>;
+  };
+  auto dft_lds = [](int N) -> size_t { return ((size_t)N * 64 + 2 * (size_t)N) * 16; };
+  for (int N : {na, nb})
+    if (dft_lds(N) > 64 * 1024)
+      HIPCHK(c, hipFuncSetAttribute(dft_kernel(N), hipFuncAttributeMaxDynamicSharedMemorySize, (int)dft_lds(N)));
+  // out = the DFT pass of `in` for the columns of `mask`
+  auto dft = [&](const double2* in, double2* out, const double2* w, const double2* post, bool axis_a,
+                 const int* mask) -> rst_status {
+    rst::mk::DftPass D;
+    D.in = in;
+    D.out = out;
+    D.w = w;
+    D.post = post;
+    D.act = mask;
+    D.N = axis_a ? na : nb;
+    D.stride = axis_a ? 1 : na;
+    D.nline_inner = axis_a ? nb : na;
+    D.inner_mul = axis_a ? na : 1;
+    D.P = P;
+    D.nz = nz;
+    D.ld = ld;
+    const long long nwg = (long long)nz * D.nline_inner * (ld / 64);
+    void* args[] = {&D};
+    HIPCHK(c, hipLaunchKernel(dft_kernel(D.N), dim3((unsigned)nwg), dim3(256), args, dft_lds(D.N), c->stream));
+    return RST_OK;
+  };
+  auto precondition = [&](const double2* in, double2* out, const int* mask) -> rst_status {
+    rst_status ps;
+    if ((ps = dft(in, W, FAw, FAp, true, mask)) != RST_OK) return ps;
+    if ((ps = dft(W, out, FBw, FBp, false, mask)) != RST_OK) return ps;
+    const long long nt = (long long)P * ld;
+    if (c->rad == 6)
+      hipLaunchKernelGGL(rst::mk::k_mk_band_solve<6>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
+                         out, W, band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
+    else
+      hipLaunchKernelGGL(rst::mk::k_mk_band_solve<2>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
+                         out, W, band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
+    HIPCHK(c, hipGetLastError());
+    if ((ps = dft(out, W, IBw, IBp, false, mask)) != RST_OK) return ps;
+    return dft(W, out, IAw, IAp, true, mask);
+  };
+  auto apply = [&](const double2* x, double2* y, const int* mask) -> rst_status {
+    return apply_cols(c, x, y, ld, 0.0, d_ecol, mask, false, (double2*)c->d_projP.p, nullptr);
+  };
+  const dim3 gred((unsigned)(ld / 64), (unsigned)S.nsplit);
+  const unsigned gsc = (unsigned)ld;  // one wavefront per column in the scalar and sum kernels
+  const unsigned gel = (unsigned)((vlen + 255) / 256);
+  auto scalar = [&](int step) -> rst_status {
+    hipLaunchKernelGGL(rst::mk::k_mk_scalar, dim3(gsc), dim3(64), 0, c->stream, S, step, dst_, act,
+                       (const double2*)part, c->opts.tol, c->opts.max_iter);
+    HIPCHK(c, hipGetLastError());
+    return RST_OK;
+  };
+  const size_t nout = (size_t)nitems;
+  Tcol.assign(nout, 0.0);
+  its.assign(nout, 0);
+  rss.assign(nout, 0);
+  res.assign(nout, 0.0);
+  st.assign(nout, 1);
+  c->last_updates.clear();
+  c->last_fallbacks = 0;
+  c->last_cnn_flop = 0.0;
+  long long nent = 0;
+  for (int g = 0; g < c->ngroup; ++g) nent += c->grp_ne[g];
+  double bytes = 0.0;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  std::vector<rst::mk::ColSt> hst(ld);
+  std::vector<rst::idr::IdrSt> hid(idr ? ld : 0);
+  rst::idr::IdrSt* did = (rst::idr::IdrSt*)c->d_mkidr.p;
+  const double2* Psh = (const double2*)c->d_mkshadow.p;
+  std::vector<int> hact(ld), hmark(ld);
+  std::vector<double2> hpart;
+  for (long long it0 = 0; it0 < nitems; it0 += ld) {
+    const int nc = (int)std::min<long long>(ld, nitems - it0);
+    std::vector<double> ecol(ld, energies[0]);
+    std::vector<long long> src(ld, -1), doff(ld, -1);
+    std::vector<double> bsc(ld, 0.0);
+    std::vector<int> eidx(ld, 0);
+    for (int j = 0; j < nc; ++j) {
+      const long long it = it0 + j;
+      const int ie = (int)(it / ncols), jc = (int)(it % ncols);
+      ecol[j] = energies[ie];
+      eidx[j] = ie;
+      if (rhs) {
+        doff[j] = (long long)ie * rhs_estride + jc;
+      } else {
+        src[j] = cols[jc];
+        bsc[j] = hsrc ? std::sqrt((*hsrc)[cols[jc] / P]) : 1.0;
+      }
+    }
+    HIPCHK(c, hipMemcpyAsync(d_ecol, ecol.data(), ld * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d_src, src.data(), ld * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d_bsc, bsc.data(), ld * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d_doff, doff.data(), ld * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d_eidx, eidx.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+    rst_status ps;
+    long long col_its = 0;
+    if (!idr) {
+      hipLaunchKernelGGL(rst::mk::k_mk_init, gred, dim3(256), 0, c->stream, S, B, X, R, R0, Pv, part);
+      HIPCHK(c, hipGetLastError());
+      if ((ps = scalar(rst::mk::SC_INIT)) != RST_OK) return ps;
+      for (int iter = 0;; ++iter) {
+        // one BiCGSTAB step of every iterating column
+        if (iter > 0)
+          hipLaunchKernelGGL(rst::mk::k_mk_p, dim3(gel), dim3(256), 0, c->stream, S, (const rst::mk::ColSt*)dst_,
+                             (const int*)act, Pv, (const double2*)R, (const double2*)V);
+        if (pc && (ps = precondition(Pv, PH, act)) != RST_OK) return ps;
+        if ((ps = apply(PH, V, act)) != RST_OK) return ps;
+        hipLaunchKernelGGL(rst::mk::k_mk_dots<1>, gred, dim3(256), 0, c->stream, S, (const int*)act,
+                           (const double2*)R0, (const double2*)V, (const double2*)nullptr, (const double2*)nullptr,
+                           part);
+        if ((ps = scalar(rst::mk::SC_ALPHA)) != RST_OK) return ps;
+        hipLaunchKernelGGL(rst::mk::k_mk_s, dim3(gel), dim3(256), 0, c->stream, S, (const rst::mk::ColSt*)dst_,
+                           (const int*)act, R, (const double2*)V);
+        if (pc && (ps = precondition(R, SH, act)) != RST_OK) return ps;
+        if ((ps = apply(SH, T, act)) != RST_OK) return ps;
+        hipLaunchKernelGGL(rst::mk::k_mk_dots<2>, gred, dim3(256), 0, c->stream, S, (const int*)act,
+                           (const double2*)T, (const double2*)R, (const double2*)T, (const double2*)T, part);
+        if ((ps = scalar(rst::mk::SC_OMEGA)) != RST_OK) return ps;
+        hipLaunchKernelGGL(rst::mk::k_mk_xr, gred, dim3(256), 0, c->stream, S, (const rst::mk::ColSt*)dst_,
+                           (const int*)act, X, R, (const double2*)R0, (const double2*)PH, (const double2*)SH,
+                           (const double2*)T, part);
+        if ((ps = scalar(rst::mk::SC_BETA)) != RST_OK) return ps;
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(hst.data(), dst_, ld * sizeof(rst::mk::ColSt), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(hact.data(), act, ld * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        // columns that stopped this step: true residual b - A x decides between done and restart
+        int nmark = 0, nact = 0;
+        for (int j = 0; j < ld; ++j) {
+          hmark[j] = (hst[j].done == 0 && !hact[j] && (hst[j].check || hst[j].brk)) ? 1 : 0;
+          nmark += hmark[j];
+          nact += hact[j];
+        }
+        if (nmark > 0) {
+          HIPCHK(c, hipMemcpyAsync(mark, hmark.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+          if ((ps = apply(X, Wres, mark)) != RST_OK) return ps;
+          hipLaunchKernelGGL(rst::mk::k_mk_resid, gred, dim3(256), 0, c->stream, S, B, (const int*)mark,
+                             (const double2*)Wres, R, part);
+          HIPCHK(c, hipGetLastError());
+          hpart.resize((size_t)S.nsplit * ld);
+          HIPCHK(c, hipMemcpyAsync(hpart.data(), part, hpart.size() * 16, hipMemcpyDeviceToHost, c->stream));
+          HIPCHK(c, hipStreamSynchronize(c->stream));
+          std::vector<int> rmark(ld, 0);
+          int nrestart = 0;
+          for (int j = 0; j < ld; ++j) {
+            if (!hmark[j]) continue;
+            double rr = 0.0;
+            for (int r = 0; r < S.nsplit; ++r) rr += hpart[(size_t)r * ld + j].x;
+            rst::mk::ColSt& q = hst[j];
+            const double rel = q.bb > 0 ? std::sqrt(rr / q.bb) : 0.0;
+            q.check = q.brk = 0;
+            if (rel <= c->opts.tol) {
+              q.done = 1;
+              q.rr = rel;
+            } else if (q.its >= c->opts.max_iter || !std::isfinite(rel) || q.restarts >= 1000) {
+              q.done = 2;
+              q.rr = rel;
+            } else {
+              // restart from the true residual (now in R): r0h = p = r, rho = ||r||^2
+              q.rho = double2{rr, 0.0};
+              q.r0n = rr;
+              q.rrmin = rr;
+              q.rr = rr;
+              q.alpha = q.omega = q.beta = double2{0.0, 0.0};
+              q.restarts += 1;
+              rmark[j] = 1;
+              hact[j] = 1;
+              ++nrestart;
+            }
+          }
+          HIPCHK(c, hipMemcpyAsync(dst_, hst.data(), ld * sizeof(rst::mk::ColSt), hipMemcpyHostToDevice, c->stream));
+          if (nrestart > 0) {
+            HIPCHK(c, hipMemcpyAsync(mark, rmark.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(act, hact.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+            hipLaunchKernelGGL(rst::mk::k_mk_restart, dim3(gel), dim3(256), 0, c->stream, S, (const int*)mark,
+                               (const double2*)R, R0, Pv);
+            HIPCHK(c, hipGetLastError());
+            nact += nrestart;
+          }
+          // a restarted column starts with p = r (no p update on its first step): the p kernel sees
+          // beta = 0, omega = 0 and recomputes p = r, which is the same
+        }
+        if (nact == 0) break;
+      }
+    } else {
+      // IDR(s) cycles: s steps of one apply each, then the dimension-reduction step
+      auto iscal = [&](int step, int k, const int* mk_) -> rst_status {
+        hipLaunchKernelGGL(rst::idr::k_idr_scalar, dim3((unsigned)ld), dim3(64), 0, c->stream, S, step, sdim, k, did,
+                           act, mk_, (const double2*)part, c->opts.tol, c->opts.max_iter);
+        HIPCHK(c, hipGetLastError());
+        return RST_OK;
+      };
+      double2* VH = pc ? PH : V;  // M^-1 v
+      hipLaunchKernelGGL(rst::idr::k_idr_init, dim3(gel), dim3(256), 0, c->stream, S, sdim, B, X, R, Gb, Ub);
+      hipLaunchKernelGGL(rst::idr::k_idr_pdots<true>, gred, dim3(256), 0, c->stream, S, sdim, (const int*)nullptr,
+                         Psh, (const double2*)R, part);
+      if ((ps = iscal(rst::idr::ID_INIT, 0, nullptr)) != RST_OK) return ps;
+      for (;;) {
+        for (int k = 0; k < sdim; ++k) {
+          double2* Gk = Gb + (size_t)k * vlen;
+          double2* Uk = Ub + (size_t)k * vlen;
+          if ((ps = iscal(rst::idr::ID_C, k, nullptr)) != RST_OK) return ps;
+          hipLaunchKernelGGL(rst::idr::k_idr_v, dim3(gel), dim3(256), 0, c->stream, S, sdim, k,
+                             (const rst::idr::IdrSt*)did, (const int*)act, (const double2*)R, (const double2*)Gb, V);
+          if (pc && (ps = precondition(V, PH, act)) != RST_OK) return ps;
+          hipLaunchKernelGGL(rst::idr::k_idr_u, dim3(gel), dim3(256), 0, c->stream, S, sdim, k,
+                             (const rst::idr::IdrSt*)did, (const int*)act, (const double2*)VH, Ub);
+          if ((ps = apply(Uk, Gk, act)) != RST_OK) return ps;
+          hipLaunchKernelGGL(rst::idr::k_idr_pdots<false>, gred, dim3(256), 0, c->stream, S, sdim, (const int*)act,
+                             Psh, (const double2*)Gk, part);
+          if ((ps = iscal(rst::idr::ID_D, k, nullptr)) != RST_OK) return ps;
+          hipLaunchKernelGGL(rst::idr::k_idr_upd, gred, dim3(256), 0, c->stream, S, k, (const rst::idr::IdrSt*)did,
+                             (const int*)act, Gb, Ub, R, X, part);
+          if ((ps = iscal(rst::idr::ID_CONV, k, nullptr)) != RST_OK) return ps;
+        }
+        // dimension reduction: v = M^-1 r, t = A v, omega from (t, r) and (t, t)
+        double2* vr = R;
+        if (pc) {
+          if ((ps = precondition(R, PH, act)) != RST_OK) return ps;
+          vr = PH;
+        }
+        if ((ps = apply(vr, T, act)) != RST_OK) return ps;
+        hipLaunchKernelGGL(rst::mk::k_mk_dots<2>, gred, dim3(256), 0, c->stream, S, (const int*)act,
+                           (const double2*)T, (const double2*)R, (const double2*)T, (const double2*)T, part);
+        if ((ps = iscal(rst::idr::ID_OMEGA, 0, nullptr)) != RST_OK) return ps;
+        hipLaunchKernelGGL(rst::idr::k_idr_rx, dim3(gel), dim3(256), 0, c->stream, S, (const rst::idr::IdrSt*)did,
+                           (const int*)act, R, X, (const double2*)T, (const double2*)vr);
+        hipLaunchKernelGGL(rst::idr::k_idr_pdots<true>, gred, dim3(256), 0, c->stream, S, sdim, (const int*)act,
+                           Psh, (const double2*)R, part);
+        if ((ps = iscal(rst::idr::ID_END, 0, nullptr)) != RST_OK) return ps;
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(hid.data(), did, ld * sizeof(rst::idr::IdrSt), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(hact.data(), act, ld * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        int nmark = 0, nact = 0;
+        for (int j = 0; j < ld; ++j) {
+          hmark[j] = (hid[j].done == 0 && !hact[j] && (hid[j].check || hid[j].brk)) ? 1 : 0;
+          nmark += hmark[j];
+          nact += hact[j];
+        }
+        if (nmark > 0) {
+          HIPCHK(c, hipMemcpyAsync(mark, hmark.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+          if ((ps = apply(X, Wres, mark)) != RST_OK) return ps;
+          hipLaunchKernelGGL(rst::mk::k_mk_resid, gred, dim3(256), 0, c->stream, S, B, (const int*)mark,
+                             (const double2*)Wres, R, part);
+          HIPCHK(c, hipGetLastError());
+          hpart.resize((size_t)S.nsplit * ld);
+          HIPCHK(c, hipMemcpyAsync(hpart.data(), part, hpart.size() * 16, hipMemcpyDeviceToHost, c->stream));
+          HIPCHK(c, hipStreamSynchronize(c->stream));
+          std::vector<int> rmark(ld, 0);
+          int nrestart = 0;
+          for (int j = 0; j < ld; ++j) {
+            if (!hmark[j]) continue;
+            double rr = 0.0;
+            for (int r = 0; r < S.nsplit; ++r) rr += hpart[(size_t)r * ld + j].x;
+            rst::idr::IdrSt& q = hid[j];
+            const double rel = q.bb > 0 ? std::sqrt(rr / q.bb) : 0.0;
+            q.check = q.brk = 0;
+            if (rel <= c->opts.tol) {
+              q.done = 1;
+              q.rr = rel;
+            } else if (q.its >= c->opts.max_iter || !std::isfinite(rel) || q.restarts >= 1000) {
+              q.done = 2;
+              q.rr = rel;
+            } else {
+              q.restarts += 1;  // restart from the true residual (now in R)
+              rmark[j] = 1;
+              hact[j] = 1;
+              ++nrestart;
+            }
+          }
+          HIPCHK(c, hipMemcpyAsync(did, hid.data(), ld * sizeof(rst::idr::IdrSt), hipMemcpyHostToDevice, c->stream));
+          if (nrestart > 0) {
+            HIPCHK(c, hipMemcpyAsync(mark, rmark.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+            hipLaunchKernelGGL(rst::idr::k_idr_zero, dim3(gel), dim3(256), 0, c->stream, S, sdim, (const int*)mark, Gb,
+                               Ub);
+            hipLaunchKernelGGL(rst::idr::k_idr_pdots<true>, gred, dim3(256), 0, c->stream, S, sdim, (const int*)mark,
+                               Psh, (const double2*)R, part);
+            if ((ps = iscal(rst::idr::ID_RESTART, 0, mark)) != RST_OK) return ps;
+            HIPCHK(c, hipMemcpyAsync(act, hact.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+            nact += nrestart;
+          }
+        }
+        if (nact == 0) break;
+      }
+      for (int j = 0; j < ld; ++j) {
+        hst[j].its = hid[j].its;
+        hst[j].restarts = hid[j].restarts;
+        hst[j].rr = hid[j].rr;
+        hst[j].done = hid[j].done;
+      }
+    }
+    // outputs of the block: T over the destination CAP, the exported solutions, per-column records
+    std::vector<double> tb(ld, 0.0);
+    if (d_gdst) {
+      hipLaunchKernelGGL(rst::mk::k_mk_tacc, gred, dim3(256), 0, c->stream, S, P, d_gdst, (const double2*)X, part);
+      hipLaunchKernelGGL(rst::mk::k_mk_sum, dim3(gsc), dim3(64), 0, c->stream, S, (const double2*)part,
+                         (double*)c->d_mkT.p);
+      HIPCHK(c, hipGetLastError());
+      HIPCHK(c, hipMemcpyAsync(tb.data(), c->d_mkT.p, ld * 8, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (xout) {
+      hipLaunchKernelGGL(rst::mk::k_mk_export, dim3(gel), dim3(256), 0, c->stream, S, nc, (const double2*)X, xout,
+                         nitems, it0);
+      HIPCHK(c, hipGetLastError());
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int j = 0; j < nc; ++j) {
+      const rst::mk::ColSt& q = hst[j];
+      const size_t o = (size_t)(it0 + j);
+      Tcol[o] = tb[j];
+      its[o] = q.its;
+      rss[o] = q.restarts;
+      res[o] = q.done == 0 ? 0.0 : q.rr;
+      st[o] = q.done == 1 ? 0 : 1;
+      col_its += q.its;
+    }
+    bytes += idr ? (double)col_its * (idr_bytes_per_matvec(sdim, pc) * (double)n + 16.0 * (double)nent)
+                 : (double)col_its * (mk_bytes_per_point(pc) * (double)n + 2.0 * 16.0 * (double)nent);
+  }
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float fms = 0;
+  HIPCHK(c, hipEventElapsedTime(&fms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  ms = fms;
+  c->last_mk = true;
+  c->last_mk_bytes = bytes;
+  c->last_cw = ld;
+  return RST_OK;
+}
+
 rst_status run_cocg(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
                     const double* d_gdst, const std::vector<double>* hsrc, double2* xout,
                     std::vector<double>& Tcol, std::vector<int>& its, std::vector<int>& rss,
@@ -1389,6 +2029,8 @@ rst_status run_cocg(rst_ctx* c, int ne, const double* energies, const std::vecto
       A.pc.vbar = vbar;
       A.pc.a = 0.5 / (c->hz * c->hz);
       A.pc.eps = (const double*)c->d_pc_eps.p;
+      A.pc.vz = pc_vz(c);
+      A.pc.shift = c->opts.pc_shift;
       A.pc.steps = (const double2*)c->d_pc_twa.p;
       A.pc.inv = (const double2*)c->d_pc_inv.p;
       std::vector<rst::SolveArgs> sa(1, A);
@@ -1769,6 +2411,7 @@ rst_status run_batch(rst_ctx* c, const std::vector<int>& sel, int ne_cap, int cw
     if ((s = ensure(c, c->d_pc_inv, (size_t)inv_total * 16)) != RST_OK) return s;
     A.pc.a = 0.5 / (c->hz * c->hz);
     A.pc.eps = (const double*)c->d_bpc_eps.p;
+    A.pc.shift = c->opts.pc_shift;
     A.pc.steps = (const double2*)c->d_bpc_steps.p;
     A.pc.inv = (const double2*)c->d_pc_inv.p;
     // Thomas pivots of every (structure, energy): one pivot launch per structure
@@ -1862,9 +2505,11 @@ rst_status run_batch(rst_ctx* c, const std::vector<int>& sel, int ne_cap, int cw
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
-  // graph key: batch contents, launch shape and buffers
-  const long long key = ((long long)c->batch_version << 32) ^ ((long long)ls.cw << 24) ^ (nwg << 1) ^
-                        (long long)(uintptr_t)c->d_ws.p ^ (long long)lds ^ ((long long)pc << 20);
+  // graph key: batch contents, kernel, launch shape and the device buffers the graph refers to
+  const std::array<long long, 9> key = {(long long)c->batch_version, (long long)(uintptr_t)kern,
+                                        (long long)ls.cw, (long long)ls.threads, nwg, (long long)lds,
+                                        (long long)(uintptr_t)c->d_args.p, (long long)(uintptr_t)c->d_counter.p,
+                                        (long long)(uintptr_t)c->d_ws.p};
   if (use_graph && (c->gexec == nullptr || c->gexec_key != key)) {
     if (c->gexec) {
       HIPCHK(c, hipGraphExecDestroy(c->gexec));
@@ -1947,6 +2592,7 @@ rst_status rst_batch_add(rst_ctx* c, const rst_problem* p) {
   if (!std::isfinite(p->ka) || !std::isfinite(p->kb)) return fail(c, RST_EINVAL, "non-finite k");
   const size_t n = (size_t)c->na * c->nb * p->nz;
   rst_ctx::HostProb hp;
+  hp.grid_version = c->grid_version;
   hp.nz = p->nz;
   hp.v.assign(p->v, p->v + n);
   hp.gl.assign(p->gamma_l, p->gamma_l + p->nz);
@@ -1974,6 +2620,9 @@ rst_status rst_batch_run(rst_ctx* c, double* T_out, rst_stats* stats) {
     return fail(c, RST_EUNSUPPORTED, "the batched launch runs FP64 BiCGSTAB");
   if (c->batch.empty()) return RST_OK;
   if (!T_out) return fail(c, RST_EINVAL, "null T_out");
+  for (const auto& hp : c->batch)
+    if (hp.grid_version != c->grid_version)
+      return fail(c, RST_ESTATE, "rst_set_grid was called after rst_batch_add (rst_batch_clear, then add again)");
   hipSetDevice(c->device);
   std::vector<int> all(c->batch.size());
   for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
@@ -2046,6 +2695,8 @@ void rst_default_solver(rst_solver_opts* o) {
   o->restart = 30;
   o->fallback_ratio = 0.5;
   o->precond = RST_PRECOND_NONE;
+  o->pc_vref = RST_VREF_PLANE;
+  o->idr_s = 4;
 }
 
 rst_status rst_create(rst_ctx** out, int hip_device, void* hip_stream) {
@@ -2105,6 +2756,14 @@ rst_status rst_set_grid(rst_ctx* c, int na, int nb, int nz, double ha, double hb
   c->fdw = fornberg_second_derivative(rad);
   c->has_grid = true;
   c->has_v = c->has_abc = c->has_k = false;
+  // structures added before this call carry potentials of the previous grid: rst_batch_run refuses
+  // them (RST_ESTATE) until the batch is rebuilt, and the launch captured for them is dropped
+  c->grid_version++;
+  c->batch_version++;
+  if (c->gexec) {
+    hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
   c->nproj = c->ngroup = 0;
   c->nm = 1;
   c->max_chunks = 0;
@@ -2138,6 +2797,15 @@ rst_status rst_set_potential(rst_ctx* c, const double* v) {
   c->v.assign(v, v + n);
   rst_status s = upload(c, c->d_v, c->v);
   if (s != RST_OK) return s;
+  // plane means: the preconditioner's default reference potential
+  const size_t P = (size_t)c->na * c->nb;
+  std::vector<double> vz(c->nz, 0.0);
+  for (int z = 0; z < c->nz; ++z) {
+    double acc = 0.0;
+    for (size_t p = 0; p < P; ++p) acc += c->v[(size_t)z * P + p];
+    vz[z] = acc / (double)P;
+  }
+  if ((s = upload(c, c->d_vz, vz)) != RST_OK) return s;
   c->has_v = true;
   return RST_OK;
 }
@@ -2211,8 +2879,13 @@ rst_status rst_set_k(rst_ctx* c, double ka, double kb) {
 
 rst_status rst_set_solver(rst_ctx* c, const rst_solver_opts* o) {
   if (!c || !o) return RST_EINVAL;
-  if (o->method != RST_BICGSTAB && o->method != RST_FGMRES && o->method != RST_COCG)
+  if (o->method != RST_BICGSTAB && o->method != RST_FGMRES && o->method != RST_COCG && o->method != RST_BICGSTAB_MC &&
+      o->method != RST_IDRS)
     return fail(c, RST_EINVAL, "unknown method");
+  if ((o->method == RST_BICGSTAB_MC || o->method == RST_IDRS) && o->precision != RST_FP64)
+    return fail(c, RST_EUNSUPPORTED, "the many-column solvers run in FP64 only");
+  if (o->idr_s < 1 || o->idr_s > rst::idr::SMAX) return fail(c, RST_EINVAL, "idr_s must be in 1..8");
+  if (!(o->pc_shift >= 0) || !std::isfinite(o->pc_shift)) return fail(c, RST_EINVAL, "pc_shift must be finite and >= 0");
   if (o->method == RST_COCG && o->precision != RST_FP64) return fail(c, RST_EUNSUPPORTED, "COCG runs in FP64 only");
   if (o->method == RST_FGMRES) {
     if (o->restart < 1 || o->restart > 200) return fail(c, RST_EINVAL, "restart must be in 1..200");
@@ -2234,6 +2907,8 @@ rst_status rst_set_solver(rst_ctx* c, const rst_solver_opts* o) {
   if (o->direction != RST_DIR_LR && o->direction != RST_DIR_RL) return fail(c, RST_EINVAL, "bad direction");
   if (o->precond != RST_PRECOND_NONE && o->precond != RST_PRECOND_FREE_CAP && o->precond != RST_PRECOND_LEARNED)
     return fail(c, RST_EINVAL, "unknown preconditioner");
+  if (o->pc_vref != RST_VREF_PLANE && o->pc_vref != RST_VREF_CELL)
+    return fail(c, RST_EINVAL, "unknown preconditioner reference potential");
   c->opts = *o;
   return RST_OK;
 }
@@ -2313,8 +2988,9 @@ rst_status rst_solve_rhs(rst_ctx* c, int n_e, const double* energies, int ncol, 
   if (rhs_estride != 0 && rhs_estride != ncol) return fail(c, RST_EINVAL, "rhs_estride must be 0 or ncol");
   for (int i = 0; i < n_e; ++i)
     if (!std::isfinite(energies[i])) return fail(c, RST_EINVAL, "non-finite energy");
-  if (c->opts.method != RST_BICGSTAB || c->opts.precision != RST_FP64)
-    return fail(c, RST_EUNSUPPORTED, "dense right-hand sides are solved by FP64 BiCGSTAB");
+  if ((c->opts.method != RST_BICGSTAB && c->opts.method != RST_BICGSTAB_MC && c->opts.method != RST_IDRS) ||
+      c->opts.precision != RST_FP64)
+    return fail(c, RST_EUNSUPPORTED, "dense right-hand sides are solved by FP64 BiCGSTAB or IDR(s)");
   if (n_e == 0 || ncol == 0) return RST_OK;
   hipSetDevice(c->device);
   std::vector<int64_t> cols(ncol, 0);
@@ -2429,67 +3105,12 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
   if (!std::isfinite(energy)) return fail(c, RST_EINVAL, "non-finite energy");
   if (ncol == 0) return RST_OK;
   hipSetDevice(c->device);
-  const int P = c->na * c->nb;  // rst_set_grid guarantees na, nb > rad: one wrap at most
-  // planes per wave: short segments keep the waves that share lateral rows close in z
-  const int zseg = std::min(c->nz, rst::APPLY_ZSEG);
-  const long long nseg = (c->nz + zseg - 1) / zseg;
-  const long long nwg = (long long)((ncol + 63) / 64) * nseg * P;  // one wave per (64 columns, segment, point)
-  if (nwg > 0x7fffffffLL) return fail(c, RST_EINVAL, "too many columns for one launch");
-  rst::ColApplyArgs A;
-  std::memset(&A, 0, sizeof(A));
-  A.x = x_dev;
-  A.y = y_dev;
-  A.ncol = ncol;
-  A.g = make_geo(c);
-  A.V = (const double*)c->d_v.p;
-  A.gz = (const double*)c->d_gz.p;
-  A.energy = energy;
-  A.pj = make_proj(c);
-  A.zseg = zseg;
   for (hipEvent_t& e : c->ev_apply)
     if (!e) HIPCHK(c, hipEventCreate(&e));
-  HIPCHK(c, hipEventRecord(c->ev_apply[0], c->stream));
-  if (c->nproj > 0) {
-    // all projections P = h^3 B^H x at once on the matrix cores; the apply kernel then scatters B E P
-    if ((s = ensure(c, c->d_projP, (size_t)c->nproj * ncol * 16)) != RST_OK) return s;
-    rst::ProjMMArgs M;
-    std::memset(&M, 0, sizeof(M));
-    M.X = x_dev;
-    M.P = (double2*)c->d_projP.p;
-    M.grp_e0 = (const int*)c->d_grp_e0.p;
-    M.grp_ne = (const int*)c->d_grp_ne.p;
-    M.grp_pbase = (const int*)c->d_grp_pbase.p;
-    M.grp_nm = (const int*)c->d_grp_nm.p;
-    M.ent_gi = (const int*)c->d_ent_gi.p;
-    M.eph = (const double2*)c->d_eph.p;
-    M.beta = (const double*)c->d_beta.p;
-    M.nm = c->nm;
-    M.ngroup = c->ngroup;
-    M.ncol = ncol;
-    M.h3 = c->ha * c->hb * c->hz;
-    const long long tiles = (long long)c->ngroup * ((ncol + 63) / 64);  // one workgroup per (group, 64 columns)
-    if (f32)
-      hipLaunchKernelGGL(rst::k_proj_mm<float2>, dim3((unsigned)tiles), dim3(256), 0, c->stream, M);
-    else
-      hipLaunchKernelGGL(rst::k_proj_mm<double2>, dim3((unsigned)tiles), dim3(256), 0, c->stream, M);
-    HIPCHK(c, hipGetLastError());
-    A.P = (const double2*)c->d_projP.p;
-  }
-  HIPCHK(c, hipEventRecord(c->ev_apply[1], c->stream));
-  const bool nm9 = c->nm <= 9;
-  void* kern = nullptr;
-  if (f32)
-    kern = c->rad == 6 ? (nm9 ? (void*)rst::k_apply_cols<6, 9, float> : (void*)rst::k_apply_cols<6, 16, float>)
-                       : (nm9 ? (void*)rst::k_apply_cols<2, 9, float> : (void*)rst::k_apply_cols<2, 16, float>);
-  else
-    kern = c->rad == 6 ? (nm9 ? (void*)rst::k_apply_cols<6, 9, double> : (void*)rst::k_apply_cols<6, 16, double>)
-                       : (nm9 ? (void*)rst::k_apply_cols<2, 9, double> : (void*)rst::k_apply_cols<2, 16, double>);
-  {
-    void* args[] = {&A};
-    HIPCHK(c, hipLaunchKernel(kern, dim3((unsigned)nwg), dim3(64), args, 0, c->stream));
-  }
-  HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipEventRecord(c->ev_apply[2], c->stream));
+  if (c->nproj > 0 && (s = ensure(c, c->d_projP, (size_t)c->nproj * ncol * 16)) != RST_OK) return s;
+  if ((s = apply_cols(c, x_dev, y_dev, ncol, energy, nullptr, nullptr, f32, (double2*)c->d_projP.p,
+                      c->ev_apply)) != RST_OK)
+    return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   float f0 = 0.f, f1 = 0.f;
   HIPCHK(c, hipEventElapsedTime(&f0, c->ev_apply[0], c->ev_apply[1]));
@@ -2756,6 +3377,8 @@ rst_status rst_precond_train(rst_ctx* c, const rst_train_opts* o, rst_train_stat
     A.pc.vbar = vbar;
     A.pc.a = 0.5 / (c->hz * c->hz);
     A.pc.eps = (const double*)c->d_pc_eps.p;
+    A.pc.vz = pc_vz(c);
+    A.pc.shift = c->opts.pc_shift;
     A.pc.steps = (const double2*)c->d_pc_twa.p;
     A.pc.inv = (const double2*)c->d_pc_inv.p;
     std::vector<rst::SolveArgs> sa(1, A);
@@ -2889,8 +3512,13 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
     return fail(c, RST_EINVAL, "bad low-rank options");
   for (int i = 0; i < n_e; ++i)
     if (!std::isfinite(E[i])) return fail(c, RST_EINVAL, "non-finite energy");
-  if (c->opts.method != RST_BICGSTAB || c->opts.precision != RST_FP64 || c->opts.direction != RST_DIR_LR)
-    return fail(c, RST_EUNSUPPORTED, "the low-rank transmission uses FP64 BiCGSTAB, direction LR");
+  if ((c->opts.method != RST_BICGSTAB && c->opts.method != RST_BICGSTAB_MC && c->opts.method != RST_IDRS) ||
+      c->opts.precision != RST_FP64)
+    return fail(c, RST_EUNSUPPORTED, "the low-rank transmission uses FP64 BiCGSTAB or IDR(s)");
+  // direction RL exchanges the roles of the two CAPs (T_RL = 4 ||Gamma_R^1/2 G Gamma_L^1/2||_F^2)
+  const bool rl = c->opts.direction == RST_DIR_RL;
+  const std::vector<double>& g_dst = rl ? c->gr : c->gl;
+  const std::vector<double>& g_src = rl ? c->gl : c->gr;
   if (n_e == 0) return RST_OK;
   hipSetDevice(c->device);
   const int P = c->na * c->nb;
@@ -2898,8 +3526,8 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
   std::vector<long long> Lh, Rh;
   for (int z = 0; z < c->nz; ++z)
     for (int p = 0; p < P; ++p) {
-      if (c->gl[z] > 0) Lh.push_back((long long)z * P + p);
-      if (c->gr[z] > 0) Rh.push_back((long long)z * P + p);
+      if (g_dst[z] > 0) Lh.push_back((long long)z * P + p);
+      if (g_src[z] > 0) Rh.push_back((long long)z * P + p);
     }
   rst_stats acc;
   std::memset(&acc, 0, sizeof(acc));
@@ -2914,8 +3542,8 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
   const int nL = (int)Lh.size(), nR = (int)Rh.size();
   if ((s = upload(c, c->d_lrL, Lh)) != RST_OK) return s;
   if ((s = upload(c, c->d_lrRc, Rh)) != RST_OK) return s;
-  const double* d_gl = (const double*)c->d_gl.p;
-  const double* d_gr = (const double*)c->d_gr.p;
+  const double* d_gl = (const double*)(rl ? c->d_gr.p : c->d_gl.p);
+  const double* d_gr = (const double*)(rl ? c->d_gl.p : c->d_gr.p);
   const long long* dL = (const long long*)c->d_lrL.p;
   const long long* dR = (const long long*)c->d_lrRc.p;
   std::vector<int> done(n_e, 0);

@@ -17,10 +17,11 @@ LIB_PATH = os.environ.get("RST_LIB") or os.path.join(_HERE, "librst.so")
 
 RST_OK, RST_ENOCONV = 0, 1
 RST_EINVAL, RST_ESTATE, RST_ENOMEM, RST_EDEVICE, RST_EUNSUPPORTED = -1, -2, -3, -4, -5
-RST_BICGSTAB, RST_FGMRES, RST_COCG = 0, 1, 2
+RST_BICGSTAB, RST_FGMRES, RST_COCG, RST_BICGSTAB_MC, RST_IDRS = 0, 1, 2, 3, 4
 RST_FP64, RST_FP32_REFINE = 0, 1
 RST_DIR_LR, RST_DIR_RL = 0, 1
 RST_PRECOND_NONE, RST_PRECOND_FREE_CAP, RST_PRECOND_LEARNED = 0, 1, 2
+RST_VREF_PLANE, RST_VREF_CELL = 0, 1
 
 EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error", "rst_set_grid",
             "rst_set_potential", "rst_set_projectors", "rst_set_abc", "rst_set_k", "rst_set_solver",
@@ -36,7 +37,8 @@ class rst_solver_opts(C.Structure):
     _fields_ = [("method", C.c_int), ("precision", C.c_int), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("col_block", C.c_int), ("threads", C.c_int),
                 ("direction", C.c_int), ("update_delta", C.c_double), ("precond", C.c_int),
-                ("restart", C.c_int), ("fallback_ratio", C.c_double)]
+                ("restart", C.c_int), ("fallback_ratio", C.c_double), ("pc_vref", C.c_int),
+                ("idr_s", C.c_int), ("pc_shift", C.c_double)]
 
 
 class rst_stats(C.Structure):

@@ -65,17 +65,20 @@ def test_fgmres_solve_columns_matches_oracle():
 
 def test_learned_preconditioner_untrained_still_converges():
     """With seeded, untrained weights the learned correction may hurt; the
-    per-column fallback to M^-1 keeps FGMRES convergent and T exact."""
+    per-column fallback to M^-1 keeps FGMRES convergent and T exact.  The
+    iteration cap (20000 Arnoldi steps) leaves the slowest column at most half of
+    it, so the outcome does not hang on the reduction order of a column block."""
     torch = torch_cuda()
     p = wl.config(2, tiny=True)
     k = p.kpts[2]
     es = p.energies[[4]]
     ref = oracle.transmission(p, es, k, both=False)["T_LR"]
-    ctx = make_ctx(torch, p, k, method=rst.RST_FGMRES, precond=rst.RST_PRECOND_LEARNED, restart=20, max_iter=3000)
+    ctx = make_ctx(torch, p, k, method=rst.RST_FGMRES, precond=rst.RST_PRECOND_LEARNED, restart=20, max_iter=20000)
     ctx.rst_cnn_seed(7)
     t, st, s = ctx.rst_transmission(es)
     _say("learned (untrained)", st)
     assert s == rst.RST_OK
+    assert st["iterations_max"] <= 10000, st
     assert st["cnn_flop"] > 0
     np.testing.assert_allclose(t, ref, atol=1e-6, rtol=0)
 

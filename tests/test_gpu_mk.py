@@ -1,0 +1,189 @@
+"""The many-column solvers (one kernel per step: BiCGSTAB as RST_BICGSTAB_MC,
+IDR(s) as RST_IDRS, the automatic route for lateral planes wider than one
+workgroup) against the oracle, through the C ABI.
+
+Small shapes (configs 1, 2-tiny and 3-tiny, forced onto the many-column path)
+are compared with the dense-LU oracle: T(E,k) to 1e-6 max(1, N_ch(E,k)) per
+energy, Green's columns and dense right-hand sides to 1e-9 relative.  The
+point-contact slab at its full size (54x54x252, 3420 projectors; the plane of
+2916 points takes the many-column path by itself) is checked by properties that
+hold at any size: sampled Green's columns by their true residual recomputed with
+the oracle's own FP64 apply, and the low-rank T(E,k) in both directions
+(T_LR = T_RL for any Hermitian H_k and real CAPs, transmission equation) and
+with two independent probe sets."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_02783_amd import rst
+from paper_2208_02783_amd import workloads as wl
+from tests.gpu_util import make_ctx, n_channels, torch_cuda
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+MC = rst.RST_BICGSTAB_MC
+IDR = rst.RST_IDRS
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("cfg,pc,method,s", [(2, 0, MC, 4), (2, 1, MC, 4), (3, 1, MC, 4), (2, 0, IDR, 4),
+                                             (2, 1, IDR, 4), (3, 1, IDR, 1), (3, 1, IDR, 8)])
+def test_mc_tiny_transmission_matches_oracle(cfg, pc, method, s):
+    torch = torch_cuda()
+    p = wl.config(cfg, tiny=True)
+    k = p.kpts[1]
+    es = p.energies[[1, 5]]
+    ctx = make_ctx(torch, p, k, method=method, precond=pc, idr_s=s)
+    t, st, s = ctx.rst_transmission(es)
+    _say(f"cfg{cfg}-tiny pc={pc}: T={t} its/col={st['iterations_total'] / st['columns']:.1f} "
+         f"restarts={st['restarts_total']}")
+    assert s == rst.RST_OK, st
+    assert st["columns"] == 2 * p.r_columns().size
+    ref = oracle.transmission(p, es, k, both=False)["T_LR"]
+    for e, a, b in zip(es, t, ref):
+        assert abs(a - b) <= 1e-6 * max(1, n_channels(p, e, k)), (e, a, b)
+
+
+def test_mc_config1_matches_stored_oracle_values():
+    torch = torch_cuda()
+    p = wl.config(1)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "config1_T.json")))
+    es = np.asarray(gold["energies"])
+    ctx = make_ctx(torch, p, (0.0, 0.0), method=MC, precond=1)
+    t, st, s = ctx.rst_transmission(es)
+    assert s == rst.RST_OK
+    ref = np.asarray(gold["T_LR"])
+    for e, a, b in zip(es, t, ref):
+        assert abs(a - b) <= 1e-6 * max(1, n_channels(p, e, (0.0, 0.0))), (e, a, b)
+
+
+@pytest.mark.parametrize("method", [MC, IDR])
+def test_mc_green_columns_rl_and_dense_rhs(method):
+    """Green's columns, the RL direction and dense right-hand sides on the tiny FCC
+    slab at a generic k (complex H_k), against LAPACK on the oracle's dense A."""
+    torch = torch_cuda()
+    import scipy.linalg as sla
+    p = wl.config(2, tiny=True)
+    k = p.kpts[2]
+    e = float(p.energies[3])
+    cols = np.array([0, 17, p.n // 2, p.n - 1])
+    ctx = make_ctx(torch, p, k, method=method, precond=1, tol=1e-12)
+    x, st, s = rst.solve_columns(ctx, e, cols, p.n)
+    assert s == rst.RST_OK, st
+    ref = oracle.green_columns(p, e, k, cols)
+    err = np.linalg.norm(x.cpu().numpy() - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert np.all(err <= 1e-9), err
+    ctx.rst_set_solver(method=method, precond=1, direction=rst.RST_DIR_RL)
+    es = p.energies[[2, 6]]
+    t_rl, _, s = ctx.rst_transmission(es)
+    assert s == rst.RST_OK
+    ref_t = oracle.transmission(p, es, k, both=True)
+    for ee, a, b in zip(es, t_rl, ref_t["T_RL"]):
+        assert abs(a - b) <= 1e-6 * max(1, n_channels(p, ee, k)), (ee, a, b)
+    rng = np.random.default_rng(78)
+    b = rng.standard_normal((p.n, 3)) + 1j * rng.standard_normal((p.n, 3))
+    b[:, 1] = 0.0
+    ctx.rst_set_solver(method=method, precond=1, tol=1e-12)
+    xr, st, s = rst.solve_rhs(ctx, es, torch.from_numpy(b).cuda())
+    assert s == rst.RST_OK, st
+    xr = xr.cpu().numpy()
+    for ie, ee in enumerate(es):
+        refb = sla.solve(oracle.system_matrix(p, k, ee), b)
+        got = xr[:, ie * 3:(ie + 1) * 3]
+        assert np.all(got[:, 1] == 0)
+        for j in (0, 2):
+            assert np.linalg.norm(got[:, j] - refb[:, j]) / np.linalg.norm(refb[:, j]) <= 1e-9
+
+
+def test_mc_equals_persistent_solver_on_tiny_config3():
+    """The persistent BiCGSTAB, the many-column BiCGSTAB and IDR(4) solve the same
+    systems to the same tolerance: T agrees far inside the accuracy bar."""
+    torch = torch_cuda()
+    p = wl.config(3, tiny=True)
+    k = p.kpts[3]
+    es = p.energies[[0, 4, 7]]
+    a = make_ctx(torch, p, k, precond=1)
+    b = make_ctx(torch, p, k, precond=1, method=MC)
+    c = make_ctx(torch, p, k, precond=1, method=IDR)
+    ta, _, sa = a.rst_transmission(es)
+    tb, _, sb = b.rst_transmission(es)
+    tc, stc, sc = c.rst_transmission(es)
+    _say("idr(4) applies per column", stc["iterations_total"] / stc["columns"])
+    assert sa == sb == sc == rst.RST_OK
+    assert np.max(np.abs(ta - tb)) <= 1e-8 * max(1.0, float(np.max(ta))), (ta, tb)
+    assert np.max(np.abs(ta - tc)) <= 1e-8 * max(1.0, float(np.max(ta))), (ta, tc)
+
+
+def test_mc_option_errors():
+    torch = torch_cuda()
+    p = wl.config(1)
+    ctx = make_ctx(torch, p, (0.0, 0.0))
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_set_solver(method=MC, precision=rst.RST_FP32_REFINE)
+    assert ei.value.status == rst.RST_EUNSUPPORTED
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_set_solver(method=IDR, idr_s=9)
+    assert ei.value.status == rst.RST_EINVAL
+    ctx.rst_set_solver(method=MC, col_block=2)
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_transmission(np.array([0.5]))
+    assert ei.value.status == rst.RST_EUNSUPPORTED
+    for m in (MC, IDR):
+        ctx.rst_set_solver(method=m, max_iter=2, precond=0)
+        t, st, s = ctx.rst_transmission(np.array([0.5]))
+        assert s == rst.RST_ENOCONV and st["columns_unconverged"] > 0
+        assert st["iterations_max"] <= 2 + 4 * (m == IDR)  # IDR stops at the end of a cycle
+
+
+# ------------------------------------------------------------ config 3, full size
+
+def _cfg3():
+    p = wl.config(3)
+    return p, p.kpts[5], float(p.energies[128])
+
+
+def test_full_config3_sampled_columns_true_residual_by_oracle():
+    torch = torch_cuda()
+    p, k, e = _cfg3()
+    ctx = make_ctx(torch, p, k, precond=1, tol=1e-10, max_iter=20000)
+    rc = p.r_columns()
+    cols = rc[np.linspace(0, rc.size - 1, 8).round().astype(int)]
+    _say("config-3 columns", cols.tolist(), "E", e, "k", k)
+    x, st, s = rst.solve_columns(ctx, e, cols, p.n)
+    _say(f"config-3 columns: its/col {st['iterations_total'] / st['columns']:.1f}, kernel {st['kernel_ms']:.0f} ms, "
+         f"restarts {st['restarts_total']}")
+    assert s == rst.RST_OK, st
+    x = x.cpu().numpy()
+    b = np.zeros_like(x)
+    b[cols, np.arange(cols.size)] = 1.0
+    res = oracle.residual_norms(p, k, e, x, b)
+    _say("oracle-recomputed true residuals", res)
+    assert np.all(res <= 2e-10), res
+    lz = np.repeat(p.gamma_l > 0, p.na * p.nb)
+    assert np.all(np.linalg.norm(x[lz], axis=0) > 0)
+
+
+def test_full_config3_lowrank_both_directions_and_probe_sets_agree():
+    torch = torch_cuda()
+    p, k, e = _cfg3()
+    ctx = make_ctx(torch, p, k, precond=1, tol=1e-10, max_iter=20000)
+    es = np.array([e])
+    t1, err1, st1, s1 = ctx.rst_transmission_lowrank(es, probes=16, heldout=8, tail_tol=1e-7, seed=1)
+    _say(f"config-3 low-rank T_LR {t1[0]:.9f} tail {err1[0]:.2e} solves {st1['columns']} "
+         f"kernel {st1['kernel_ms']:.0f} ms")
+    assert s1 == rst.RST_OK
+    t2, err2, _, s2 = ctx.rst_transmission_lowrank(es, probes=16, heldout=8, tail_tol=1e-7, seed=99)
+    ctx.rst_set_solver(precond=1, tol=1e-10, max_iter=20000, direction=rst.RST_DIR_RL)
+    t3, err3, _, s3 = ctx.rst_transmission_lowrank(es, probes=16, heldout=8, tail_tol=1e-7, seed=5)
+    _say(f"config-3 low-rank T_LR (second probes) {t2[0]:.9f}, T_RL {t3[0]:.9f}")
+    assert s2 == rst.RST_OK and s3 == rst.RST_OK
+    bar = 1e-6 * max(1.0, t1[0])
+    assert t1[0] >= 0.0
+    assert abs(t1[0] - t2[0]) <= bar + err1[0] + err2[0]
+    assert abs(t1[0] - t3[0]) <= bar + err1[0] + err3[0]
