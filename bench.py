@@ -436,6 +436,8 @@ def main():
     ap.add_argument("--workload", choices=["cfg3", "cfg2"], default="cfg3",
                     help="cfg3: point contact by the low-rank route (headline); cfg2: full-column FCC bulk points")
     ap.add_argument("--energies-per-step", type=int, default=4, help="cfg3: energies per low-rank step")
+    ap.add_argument("--idr-s", type=int, default=4, help="cfg3: shadow-space dimension of IDR(s)")
+    ap.add_argument("--pc-shift", type=float, default=0.1, help="cfg3: imaginary shift of the preconditioner (Ha)")
     ap.add_argument("--budget", type=float, default=450.0,
                     help="wall seconds for the whole run, from process start (legs that do not fit are skipped)")
     ap.add_argument("--timed-share", type=float, default=120.0,
@@ -602,7 +604,8 @@ def headline_cfg3(args, budget):
     tail_tol = 1e-7
     ctx = rst.Context(0)
     ctx.load_problem(prob, prob.kpts[0])
-    ctx.rst_set_solver(tol=args.tol, precond=1, max_iter=20000)
+    ctx.rst_set_solver(tol=args.tol, precond=1, max_iter=20000, method=rst.RST_IDRS, idr_s=args.idr_s,
+                       pc_shift=args.pc_shift)
     print(f"bench: config 3 loaded at {time.time() - T_START:.1f} s", file=sys.stderr, flush=True)
 
     def one(i):
@@ -614,11 +617,11 @@ def headline_cfg3(args, budget):
         ok = int(np.sum(terr <= tail_tol)) if s in (rst.RST_OK, rst.RST_ENOCONV) and st["columns_unconverged"] == 0 \
             else 0
         print(f"step {i}: k={k} E={es[0]:.4f}..{es[-1]:.4f} T={np.round(t, 6)} max tail {np.max(terr):.1e} "
-              f"solves {st['columns']} its/solve {st['iterations_total'] / max(st['columns'], 1):.1f} "
+              f"solves {st['columns']} applies/solve {st['iterations_total'] / max(st['columns'], 1):.1f} "
               f"kernel {st['kernel_ms']:.0f} ms status {s}", file=sys.stderr, flush=True)
         return t, terr, st, s, k, es, ok
 
-    res, wall, nw = timed_loop(one, args.warmup, args.steps, budget, args.timed_share, 90.0)
+    res, wall, nw = timed_loop(one, args.warmup, args.steps, budget, args.timed_share, 45.0)
     points_ok = sum(r[6] for r in res)
     kernel_ms = sum(r[2]["kernel_ms"] for r in res)
     bytes_alg = sum(r[2]["bytes_algorithmic"] for r in res)
@@ -633,13 +636,15 @@ def headline_cfg3(args, budget):
             "solver": ("low-rank transmission (randomised range finder over the CAP blocks: 16 probes + 8 held-out "
                        "solves on the right CAP, Cholesky QR, 16 adjoint solves at -k, probes doubled while the "
                        "tail estimate exceeds 1e-7), each solve by the many-column right-preconditioned FP64 "
-                       "BiCGSTAB (free-electron + CAP preconditioner) to a true relative residual of 1e-10"),
+                       f"IDR({args.idr_s}) (free-electron + CAP preconditioner with the plane-mean reference "
+                       f"potential, the operator's order-12 z Laplacian and an imaginary shift of "
+                       f"{args.pc_shift} Ha) to a true relative residual of 1e-10"),
             "energies_per_step": ne, "tail_tol": tail_tol, "tol_true_rel_residual": args.tol,
             "points": [{"k": [float(r[4][0]), float(r[4][1])], "E": [float(x) for x in r[5]],
                         "T": [float(x) for x in r[0]], "tail_estimate": [float(x) for x in r[1]],
                         "status": int(r[3])} for r in res],
             "points_counted": points_ok, "points_computed": ne * len(res),
-            "solves": solves, "iterations_per_solve": its / max(solves, 1),
+            "solves": solves, "operator_applies_per_solve": its / max(solves, 1),
             "kernel_ms_total": kernel_ms,
             "solver_algorithmic_GBps": bytes_alg / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else None,
         },
