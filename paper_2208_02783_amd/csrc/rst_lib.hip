@@ -117,7 +117,7 @@ struct rst_ctx {
   std::vector<int> grp_e0, grp_ne;
   DevBuf d_grp_e0, d_grp_ne, d_ent_gi, d_projP;
   // low-rank transmission buffers
-  DevBuf d_lrB, d_lrX, d_lrY, d_lrQ, d_lrQ2, d_lrG, d_lrR, d_lrW, d_lrL, d_lrRc, d_lrT;
+  DevBuf d_lrB, d_lrX, d_lrY, d_lrQ, d_lrQ2, d_lrG, d_lrR, d_lrW, d_lrL, d_lrRc, d_lrT, d_lrYacc, d_lrYacc2, d_lrQf;
   // solver
   rst_solver_opts opts;
   // work buffers (grown on demand)
@@ -3548,10 +3548,20 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
   const long long* dR = (const long long*)c->d_lrRc.p;
   std::vector<int> done(n_e, 0);
   std::vector<double> Tq(n_e, 0.0), tail(n_e, 0.0);
-  int sprobe = std::min(o->probes, nR);
+  const int smax = std::min(o->max_probes, nR);
+  int sprobe = std::min(o->probes, nR);  // probes in the basis after this round
   const int hp = o->heldout;
   uint64_t seed = o->seed;
   const double ka0 = c->ka, kb0 = c->kb;
+  // Y of the probes of earlier rounds, per open energy (compact over the open energies, in their
+  // order): Yacc[j][col][i], columns 0..s_prev-1, stride smax*nL per energy
+  const size_t ystride = (size_t)smax * nL;
+  if ((s = ensure(c, c->d_lrYacc, (size_t)n_e * ystride * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_lrYacc2, (size_t)n_e * ystride * 16)) != RST_OK) return s;
+  double2* Yacc = (double2*)c->d_lrYacc.p;
+  double2* Ynext = (double2*)c->d_lrYacc2.p;
+  std::vector<int> open_prev;  // open energies of the previous round, in Yacc order
+  int s_prev = 0;
   for (;;) {
     // energies still open
     std::vector<double> Eo;
@@ -3562,8 +3572,9 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
         idx.push_back(i);
       }
     const int ne = (int)Eo.size();
-    const int sc = sprobe + hp;
-    // (1) probes and forward solves
+    const int snew = sprobe - s_prev;  // probes added this round
+    const int sc = snew + hp;
+    // (1) new probes and held-out probes, forward solves
     if ((s = ensure(c, c->d_lrB, (size_t)n * sc * 16)) != RST_OK) return s;
     if ((s = ensure(c, c->d_lrX, (size_t)n * ne * sc * 16)) != RST_OK) return s;
     hipLaunchKernelGGL(rst::lr::k_lr_probes, dim3((unsigned)((n * sc + 255) / 256)), dim3(256), 0, c->stream, n, P, sc,
@@ -3572,24 +3583,40 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
     HIPCHK(c, hipMemsetAsync(c->d_lrX.p, 0, (size_t)n * ne * sc * 16, c->stream));
     if ((s = lr_solve(c, ne, Eo.data(), sc, (const double2*)c->d_lrB.p, 0, (double2*)c->d_lrX.p, acc)) != RST_OK)
       return s;
-    // (2) Y = Gamma_L^1/2 X on the left CAP; Q = orth(Y[:, :s]) by Cholesky QR twice
+    // (2) Y = Gamma_L^1/2 X on the left CAP for the new columns; the basis columns of every open
+    // energy are its earlier ones followed by the new ones
     const size_t ylen = (size_t)ne * sc * nL;
     if ((s = ensure(c, c->d_lrY, ylen * 16)) != RST_OK) return s;
-    if ((s = ensure(c, c->d_lrQ, (size_t)ne * sprobe * nL * 16)) != RST_OK) return s;
-    if ((s = ensure(c, c->d_lrQ2, (size_t)ne * sprobe * nL * 16)) != RST_OK) return s;
-    if ((s = ensure(c, c->d_lrG, (size_t)ne * sc * sc * 16)) != RST_OK) return s;
-    if ((s = ensure(c, c->d_lrR, (size_t)ne * sprobe * sprobe * 16)) != RST_OK) return s;
-    if ((s = ensure(c, c->d_lrW, (size_t)ne * sprobe * sprobe * 16)) != RST_OK) return s;
     hipLaunchKernelGGL(rst::lr::k_lr_gather_left, dim3((unsigned)((ylen + 255) / 256)), dim3(256), 0, c->stream,
                        (const double2*)c->d_lrX.p, ne, sc, dL, nL, P, d_gl, (double2*)c->d_lrY.p);
-    const double2* Y = (const double2*)c->d_lrY.p;
+    HIPCHK(c, hipGetLastError());
+    const double2* Ynew = (const double2*)c->d_lrY.p;
+    for (int j = 0; j < ne; ++j) {
+      double2* dstj = Ynext + (size_t)j * ystride;
+      if (s_prev > 0) {
+        const int jp = (int)(std::find(open_prev.begin(), open_prev.end(), idx[j]) - open_prev.begin());
+        HIPCHK(c, hipMemcpyAsync(dstj, Yacc + (size_t)jp * ystride, (size_t)s_prev * nL * 16,
+                                 hipMemcpyDeviceToDevice, c->stream));
+      }
+      HIPCHK(c, hipMemcpyAsync(dstj + (size_t)s_prev * nL, Ynew + (size_t)j * sc * nL, (size_t)snew * nL * 16,
+                               hipMemcpyDeviceToDevice, c->stream));
+    }
+    std::swap(Yacc, Ynext);
+    open_prev = idx;
+    s_prev = sprobe;
+    // Q = orth(Yacc[:, :sprobe]) by Cholesky QR twice
+    if ((s = ensure(c, c->d_lrQ, (size_t)ne * sprobe * nL * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_lrQ2, (size_t)ne * sprobe * nL * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_lrG, (size_t)ne * std::max(sprobe, hp) * std::max(sprobe, hp) * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_lrR, (size_t)ne * sprobe * sprobe * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_lrW, (size_t)ne * sprobe * sprobe * 16)) != RST_OK) return s;
     double2* Q = (double2*)c->d_lrQ.p;
     double2* Q2 = (double2*)c->d_lrQ2.p;
-    const long long sy = (long long)sc * nL, sq = (long long)sprobe * nL;
+    const long long sq = (long long)sprobe * nL;
     const unsigned gq = (unsigned)(((size_t)ne * sprobe * nL + 255) / 256);
     for (int pass = 0; pass < 2; ++pass) {
-      const double2* src = pass == 0 ? Y : Q;
-      const long long ss = pass == 0 ? sy : sq;
+      const double2* src = pass == 0 ? Yacc : Q;
+      const long long ss = pass == 0 ? (long long)ystride : sq;
       double2* dst = pass == 0 ? Q : Q2;
       hipLaunchKernelGGL(rst::lr::k_lr_gram, dim3(sprobe, sprobe, ne), dim3(256), 0, c->stream, src, ss, src, ss, nL,
                          sprobe, sprobe, (double2*)c->d_lrG.p);
@@ -3599,8 +3626,9 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
                          (const double2*)c->d_lrW.p, sprobe, nL, ne, dst);
       HIPCHK(c, hipGetLastError());
     }
-    // (3) tail of the held-out probes: ||y||^2 - ||Q^H y||^2
-    const double2* Yh = Y + (long long)sprobe * nL;
+    // (3) tail of the held-out probes (this round's last hp columns): ||y||^2 - ||Q^H y||^2
+    const double2* Yh = Ynew + (long long)snew * nL;
+    const long long sy = (long long)sc * nL;
     std::vector<double2> cq((size_t)ne * sprobe * hp), yy((size_t)ne * hp * hp);
     hipLaunchKernelGGL(rst::lr::k_lr_gram, dim3(sprobe, hp, ne), dim3(256), 0, c->stream, (const double2*)Q2, sq, Yh,
                        sy, nL, sprobe, hp, (double2*)c->d_lrG.p);
@@ -3609,7 +3637,7 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
                        (double2*)c->d_lrG.p);
     HIPCHK(c, hipMemcpyAsync(yy.data(), c->d_lrG.p, yy.size() * 16, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    std::vector<double> tl(ne, 0.0);
+    std::vector<int> fin;  // positions (in this round's order) of the energies that end this round
     for (int e = 0; e < ne; ++e) {
       double t = 0.0;
       for (int b = 0; b < hp; ++b) {
@@ -3620,45 +3648,53 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
         }
         t += std::max(r, 0.0);
       }
-      tl[e] = t / hp;
+      tail[idx[e]] = 4.0 * t / hp;
+      if (tail[idx[e]] <= o->tail_tol || sprobe >= smax) fin.push_back(e);
     }
-    // (4) adjoint solves at -k: Z = G_{-k} Gamma_L^1/2 conj(Q); T_Q = 4 ||Gamma_R^1/2 Z|_R||_F^2
-    if ((s = ensure(c, c->d_lrB, (size_t)n * ne * sprobe * 16)) != RST_OK) return s;
-    if ((s = ensure(c, c->d_lrX, (size_t)n * ne * sprobe * 16)) != RST_OK) return s;
-    HIPCHK(c, hipMemsetAsync(c->d_lrB.p, 0, (size_t)n * ne * sprobe * 16, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->d_lrX.p, 0, (size_t)n * ne * sprobe * 16, c->stream));
-    hipLaunchKernelGGL(rst::lr::k_lr_adjoint_rhs, dim3(gq), dim3(256), 0, c->stream, (const double2*)Q2, ne, sprobe, dL,
-                       nL, P, d_gl, n, (double2*)c->d_lrB.p);
-    HIPCHK(c, hipGetLastError());
-    c->ka = -ka0;
-    c->kb = -kb0;
-    if ((s = upload_k(c)) != RST_OK) return s;
-    if ((s = upload_pc(c)) != RST_OK) return s;
-    s = lr_solve(c, ne, Eo.data(), sprobe, (const double2*)c->d_lrB.p, sprobe, (double2*)c->d_lrX.p, acc);
-    c->ka = ka0;
-    c->kb = kb0;
-    rst_status s2 = upload_k(c);
-    if (s2 == RST_OK) s2 = upload_pc(c);
-    if (s != RST_OK) return s;
-    if (s2 != RST_OK) return s2;
-    if ((s = ensure(c, c->d_lrT, (size_t)ne * 8)) != RST_OK) return s;
-    hipLaunchKernelGGL(rst::lr::k_lr_tq, dim3(ne), dim3(256), 0, c->stream, (const double2*)c->d_lrX.p, ne, sprobe, dR,
-                       nR, P, d_gr, (double*)c->d_lrT.p);
-    HIPCHK(c, hipGetLastError());
-    std::vector<double> tq(ne);
-    HIPCHK(c, hipMemcpyAsync(tq.data(), c->d_lrT.p, (size_t)ne * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    bool more = false;
-    for (int e = 0; e < ne; ++e) {
-      Tq[idx[e]] = tq[e];
-      tail[idx[e]] = 4.0 * tl[e];
-      if (4.0 * tl[e] <= o->tail_tol || sprobe >= std::min(o->max_probes, nR))
-        done[idx[e]] = 1;
-      else
-        more = true;
+    // (4) for the energies that end here: adjoint solves at -k, Z = G_{-k} Gamma_L^1/2 conj(Q),
+    // T_Q = 4 ||Gamma_R^1/2 Z|_R||_F^2
+    if (!fin.empty()) {
+      const int nf = (int)fin.size();
+      std::vector<double> Ef(nf);
+      for (int f = 0; f < nf; ++f) Ef[f] = Eo[fin[f]];
+      if ((s = ensure(c, c->d_lrQf, (size_t)nf * sprobe * nL * 16)) != RST_OK) return s;
+      for (int f = 0; f < nf; ++f)
+        HIPCHK(c, hipMemcpyAsync((double2*)c->d_lrQf.p + (size_t)f * sq, Q2 + (size_t)fin[f] * sq, (size_t)sq * 16,
+                                 hipMemcpyDeviceToDevice, c->stream));
+      if ((s = ensure(c, c->d_lrB, (size_t)n * nf * sprobe * 16)) != RST_OK) return s;
+      if ((s = ensure(c, c->d_lrX, (size_t)n * nf * sprobe * 16)) != RST_OK) return s;
+      HIPCHK(c, hipMemsetAsync(c->d_lrB.p, 0, (size_t)n * nf * sprobe * 16, c->stream));
+      HIPCHK(c, hipMemsetAsync(c->d_lrX.p, 0, (size_t)n * nf * sprobe * 16, c->stream));
+      const unsigned gf = (unsigned)(((size_t)nf * sprobe * nL + 255) / 256);
+      hipLaunchKernelGGL(rst::lr::k_lr_adjoint_rhs, dim3(gf), dim3(256), 0, c->stream, (const double2*)c->d_lrQf.p, nf,
+                         sprobe, dL, nL, P, d_gl, n, (double2*)c->d_lrB.p);
+      HIPCHK(c, hipGetLastError());
+      c->ka = -ka0;
+      c->kb = -kb0;
+      if ((s = upload_k(c)) != RST_OK) return s;
+      if ((s = upload_pc(c)) != RST_OK) return s;
+      s = lr_solve(c, nf, Ef.data(), sprobe, (const double2*)c->d_lrB.p, sprobe, (double2*)c->d_lrX.p, acc);
+      c->ka = ka0;
+      c->kb = kb0;
+      rst_status s2 = upload_k(c);
+      if (s2 == RST_OK) s2 = upload_pc(c);
+      if (s != RST_OK) return s;
+      if (s2 != RST_OK) return s2;
+      if ((s = ensure(c, c->d_lrT, (size_t)nf * 8)) != RST_OK) return s;
+      hipLaunchKernelGGL(rst::lr::k_lr_tq, dim3(nf), dim3(256), 0, c->stream, (const double2*)c->d_lrX.p, nf, sprobe,
+                         dR, nR, P, d_gr, (double*)c->d_lrT.p);
+      HIPCHK(c, hipGetLastError());
+      std::vector<double> tq(nf);
+      HIPCHK(c, hipMemcpyAsync(tq.data(), c->d_lrT.p, (size_t)nf * 8, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      for (int f = 0; f < nf; ++f) {
+        Tq[idx[fin[f]]] = tq[f];
+        done[idx[fin[f]]] = 1;
+      }
     }
-    if (!more) break;
-    sprobe = std::min(2 * sprobe, std::min(o->max_probes, nR));
+    if ((int)fin.size() == ne) break;
+    // the energies left open double their basis with new probes
+    sprobe = std::min(2 * sprobe, smax);
     seed = seed * 0x9E3779B97F4A7C15ULL + 1;
   }
   bool within = true;
