@@ -267,6 +267,22 @@ rst_status rst_transmission_kavg(rst_ctx *ctx, int n_k, const double *kpts, int 
 rst_status rst_apply_h(rst_ctx *ctx, double energy, const void *x_dev, void *y_dev, int ncol,
                        int precision);
 
+/* rst_apply_h without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same operator, kernels, layouts, precisions and results as
+ * rst_apply_h, with the projections h^3 B^H x kept in a fixed 16 MiB scratch array
+ * that the library holds on each device until the process ends (nproj * ncol
+ * complex128 values must fit: with 360 projectors up to 2912 columns, with 3420
+ * up to 306; RST_EINVAL beyond, with the limit in rst_last_error).  Calls no
+ * hipMalloc or hipFree and records no timing (rst_apply_timing is not updated).
+ * Every call on one device shares that device's scratch array: calls that
+ * overlap in time on one GPU (other threads, other contexts, other streams) race
+ * and must be serialised by the caller.  Returns after the context's stream has
+ * finished.  Errors as rst_apply_h; RST_EDEVICE if the scratch address of the
+ * device could not be obtained. */
+rst_status rst_apply_h_noalloc(rst_ctx *ctx, double energy, const void *x_dev, void *y_dev, int ncol,
+                               int precision);
+
 /* Widest column block the blocked apply supports on the current grid (a power
  * of two <= 8: a lateral plane of col_block columns must fit one workgroup at
  * two positions per thread, its padded copy the LDS).  RST_ESTATE before the

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <array>
 #include <map>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -25,6 +26,20 @@
 #include "rst_idr.hpp"
 
 using rst::cx;
+
+// Scratch memory of rst_apply_h_noalloc: the projections h^3 B^H x of the applied
+// columns (nproj*ncol complex128).  One copy per device, held until the process
+// ends; its device address is looked up once per device by rst_create (with that
+// device current) and kept in scratch_dev[].  Host code never passes `scratch`
+// itself to a kernel: in host code the name is a host-side stand-in, not a device
+// address.
+constexpr size_t RST_SCRATCH_BYTES = (size_t)16 << 20;
+static __device__ __align__(256) double2 scratch[RST_SCRATCH_BYTES / sizeof(double2)];
+namespace {
+constexpr int RST_MAX_DEVICES = 64;
+double2* scratch_dev[RST_MAX_DEVICES] = {};
+std::mutex scratch_mu;
+}  // namespace
 
 namespace rst {
 // Fills n ints with v (used to reset the work-queue head without a memset node).
@@ -2705,6 +2720,15 @@ rst_status rst_create(rst_ctx** out, int hip_device, void* hip_stream) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return RST_EDEVICE;
   if (hipSetDevice(hip_device) != hipSuccess) return RST_EDEVICE;
+  if (hip_device < RST_MAX_DEVICES) {
+    // this device's copy of the no-allocation scratch array (looked up once, with the device current)
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[hip_device]) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RST_EDEVICE;
+      scratch_dev[hip_device] = (double2*)ptr;
+    }
+  }
   rst_ctx* c = new rst_ctx();
   c->device = hip_device;
   if (hip_stream) {
@@ -3117,6 +3141,31 @@ rst_status rst_apply_h(rst_ctx* c, double energy, const void* x_dev, void* y_dev
   HIPCHK(c, hipEventElapsedTime(&f1, c->ev_apply[1], c->ev_apply[2]));
   c->apply_ms[0] = f0;
   c->apply_ms[1] = f1;
+  return RST_OK;
+}
+
+rst_status rst_apply_h_noalloc(rst_ctx* c, double energy, const void* x_dev, void* y_dev, int ncol, int precision) {
+  rst_status s = check_ready(c);
+  if (s != RST_OK) return s;
+  if (ncol < 0 || (ncol > 0 && (!x_dev || !y_dev))) return fail(c, RST_EINVAL, "bad apply arguments");
+  if (precision != RST_FP64 && precision != RST_FP32_REFINE)
+    return fail(c, RST_EINVAL, "precision must be RST_FP64 or RST_FP32_REFINE");
+  if (x_dev == y_dev) return fail(c, RST_EINVAL, "x and y must be distinct buffers");
+  if (!std::isfinite(energy)) return fail(c, RST_EINVAL, "non-finite energy");
+  if (ncol == 0) return RST_OK;
+  if ((size_t)c->nproj * (size_t)ncol * sizeof(double2) > RST_SCRATCH_BYTES)
+    return fail(c, RST_EINVAL, "nproj x ncol projections exceed the " + std::to_string(RST_SCRATCH_BYTES >> 20) +
+                                   " MiB scratch of the no-allocation apply (at most " +
+                                   std::to_string(RST_SCRATCH_BYTES / sizeof(double2) / std::max(1, c->nproj)) +
+                                   " columns with these projectors)");
+  double2* sp = c->device < RST_MAX_DEVICES ? scratch_dev[c->device] : nullptr;
+  if (!sp) return fail(c, RST_EDEVICE, "no scratch address for this device");
+  hipSetDevice(c->device);
+  // the projections k_proj_mm writes cover every (projector, column) entry: nothing to clear
+  if ((s = apply_cols(c, x_dev, y_dev, ncol, energy, nullptr, nullptr, precision == RST_FP32_REFINE, sp, nullptr)) !=
+      RST_OK)
+    return s;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return RST_OK;
 }
 

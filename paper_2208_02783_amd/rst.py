@@ -30,7 +30,7 @@ EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error",
             "rst_batch_add", "rst_batch_run", "rst_cnn_weight_count", "rst_cnn_seed",
             "rst_cnn_set_weights", "rst_cnn_get_weights", "rst_cnn_forward", "rst_cnn_gradient",
             "rst_cnn_train_step", "rst_precond_train", "rst_solve_rhs", "rst_default_lowrank",
-            "rst_transmission_lowrank"]
+            "rst_transmission_lowrank", "rst_apply_h_noalloc"]
 
 
 class rst_solver_opts(C.Structure):
@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.rst_set_solver.argtypes = [P, C.POINTER(rst_solver_opts)]
     lib.rst_transmission.argtypes = [P, C.c_int, P, P, C.POINTER(rst_stats)]
     lib.rst_apply_h.argtypes = [P, C.c_double, P, P, C.c_int, C.c_int]
+    lib.rst_apply_h_noalloc.argtypes = [P, C.c_double, P, P, C.c_int, C.c_int]
     lib.rst_transmission_kavg.argtypes = [P, C.c_int, P, C.c_int, C.c_int, P, P, P, C.POINTER(C.c_int),
                                           C.POINTER(rst_stats)]
     lib.rst_apply_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -260,6 +261,10 @@ class Context:
     def rst_apply_h(self, energy, x_dev_ptr: int, y_dev_ptr: int, ncol: int, precision: int = 0):
         return self._chk(self.lib.rst_apply_h(self.h, float(energy), C.c_void_p(x_dev_ptr),
                                               C.c_void_p(y_dev_ptr), int(ncol), int(precision)))
+
+    def rst_apply_h_noalloc(self, energy, x_dev_ptr: int, y_dev_ptr: int, ncol: int, precision: int = 0):
+        return self._chk(self.lib.rst_apply_h_noalloc(self.h, float(energy), C.c_void_p(x_dev_ptr),
+                                                      C.c_void_p(y_dev_ptr), int(ncol), int(precision)))
 
     def rst_apply_block_width(self):
         cw = C.c_int()
