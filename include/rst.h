@@ -352,6 +352,36 @@ void rst_default_lowrank(rst_lowrank_opts *opts);
 rst_status rst_transmission_lowrank(rst_ctx *ctx, int n_e, const double *energies, const rst_lowrank_opts *opts,
                                     double *T_out, double *T_err, rst_stats *stats);
 
+/* Eigen route (paper Sec. II.A, the transmission trace in the eigenbasis of
+ * G^-1; Sec. II.B-II.D and the Appendix, the eigenpairs of +k and -k): the
+ * n_eig eigenpairs of K_k = H_k - i Gamma nearest sigma by shift-invert subspace
+ * iteration (blocks of solves with G(sigma) = (sigma - K_k)^-1 on the context's
+ * FP64 solver, orthonormalised by Cholesky QR twice) and Rayleigh-Ritz on the
+ * subspace (the small eigenproblem by Hessenberg reduction and shifted QR on the
+ * host), left eigenvectors as the conjugated right eigenvectors of K_{-k} matched
+ * by eigenvalue (K_k^T = K_{-k}; at a k equal to -k modulo a reciprocal vector
+ * the same run serves), normalised to L^H R = I; then for every energy
+ *     T(E) = 4 sum_{m,n} GtL[m,n] GtR[n,m] / ((E - lam_n)(E - lam_m)^*),
+ *     GtL = R^H Gamma_L R,  GtR = L^H Gamma_R L.
+ * With n_eig equal to the grid size the sum is T exactly; with fewer it is the
+ * paper's partial diagonalisation.  eig_out (nullable, 2*n_eig doubles) gets the
+ * eigenvalues (re, im), nearest sigma first.  stats->max_rel_residual is the
+ * largest relative eigenpair residual ||K x - lam x|| / max(1, |lam|),
+ * restarts_total the subspace iterations.  RST_ENOCONV if the residuals stay
+ * above tol after max_iter iterations (outputs written).  Solver options as for
+ * the transmission (FP64 BiCGSTAB or IDR(s)); the caller's k is restored. */
+typedef struct {
+  int n_eig;         /* eigenpairs in the trace (default 32, 1..min(512, n)) */
+  int subspace;      /* subspace dimension (0: min(n, 2 n_eig + 16); at most 1024) */
+  int max_iter;      /* subspace iterations per Bloch vector (default 40) */
+  double sigma;      /* target energy (Ha); the eigenvalues nearest it are taken (default 0) */
+  double tol;        /* relative eigenpair residual accepted (default 1e-8) */
+  uint64_t seed;     /* random start block */
+} rst_eig_opts;
+void rst_default_eig(rst_eig_opts *opts);
+rst_status rst_transmission_eigen(rst_ctx *ctx, int n_e, const double *energies, const rst_eig_opts *opts,
+                                  double *T_out, double *eig_out, rst_stats *stats);
+
 /* Batched transmission (paper Appendix: the (k, spin) calculations are
  * independent; here every (structure, energy, column block) is a work item of
  * one persistent launch).  rst_batch_clear empties the batch; rst_batch_add

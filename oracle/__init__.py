@@ -12,8 +12,12 @@ textbook 4th-order values; the lateral Laplacian spectrum in closed form; the
 free-electron separable identity against an independent 1D solve; the
 open-channel count for long CAPs; Bloch-mode counting in a periodic chain;
 supercell folding; T_LR = T_RL, T(k) = T(-k), T(k+G) = T(k), the CAP sum rule
-and T >= 0; a one-point projector reducing to a local potential.
+and T >= 0; a one-point projector reducing to a local potential.  The eigen
+route (oracle.eigen) is pinned by the LU route: with all eigenpairs both give
+the same T; by the +-k relation of left and right eigenvectors; by Im(lam) <= 0
+and by the complex-orthogonality of the eigenvectors where K is complex symmetric.
 """
+from . import eigen
 from .transport import (fd_second_derivative, fd_dispersion, hamiltonian_dense,
                         hamiltonian_sparse, bloch_projectors, system_matrix,
                         apply_system, transmission, green_columns, trace_forms,
@@ -21,4 +25,4 @@ from .transport import (fd_second_derivative, fd_dispersion, hamiltonian_dense,
 
 __all__ = ["fd_second_derivative", "fd_dispersion", "hamiltonian_dense",
            "hamiltonian_sparse", "bloch_projectors", "system_matrix", "apply_system",
-           "transmission", "green_columns", "trace_forms", "residual_norms"]
+           "transmission", "green_columns", "trace_forms", "residual_norms", "eigen"]

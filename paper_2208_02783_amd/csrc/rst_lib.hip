@@ -24,6 +24,8 @@
 #include "rst_mixed.hpp"
 #include "rst_mk.hpp"
 #include "rst_idr.hpp"
+#include "rst_eig.hpp"
+#include "rst_zeig.hpp"
 
 using rst::cx;
 
@@ -133,6 +135,8 @@ struct rst_ctx {
   DevBuf d_grp_e0, d_grp_ne, d_ent_gi, d_projP;
   // low-rank transmission buffers
   DevBuf d_lrB, d_lrX, d_lrY, d_lrQ, d_lrQ2, d_lrG, d_lrR, d_lrW, d_lrL, d_lrRc, d_lrT, d_lrYacc, d_lrYacc2, d_lrQf;
+  // eigen route: subspace blocks, Ritz vectors, small matrices
+  DevBuf d_egQ, d_egY, d_egW, d_egX, d_egKX, d_egS, d_egG, d_egR, d_egRm, d_egL, d_egTh, d_egRes, d_egMap, d_egSc;
   // solver
   rst_solver_opts opts;
   // work buffers (grown on demand)
@@ -3250,6 +3254,323 @@ rst_status rst_apply_timing(const rst_ctx* c, double* proj_ms, double* stencil_m
 }  // extern "C"
 
 // learned correction network ---------------------------------------------------
+
+// ---- eigen route -------------------------------------------------------------------------------
+
+// Cholesky of the m x m Hermitian Gram matrix g (column-major) and W = R^-1 with g = R^H R; a pivot
+// below 1e-24 of the largest diagonal drops its column (zero row of W).  Host, O(m^3).
+static void chol_inv(int m, const std::vector<double2>& g, std::vector<double2>& w) {
+  using cd = std::complex<double>;
+  std::vector<cd> R((size_t)m * m, cd(0.0)), W((size_t)m * m, cd(0.0));
+  auto G = [&](int i, int j) { return cd(g[i + (size_t)j * m].x, g[i + (size_t)j * m].y); };
+  double dmax = 0.0;
+  for (int i = 0; i < m; ++i) dmax = std::max(dmax, G(i, i).real());
+  for (int j = 0; j < m; ++j) {
+    double d = G(j, j).real();
+    for (int k = 0; k < j; ++k) d -= std::norm(R[k + (size_t)j * m]);
+    if (!(d > 1e-24 * dmax)) continue;
+    const double rjj = std::sqrt(d);
+    R[j + (size_t)j * m] = rjj;
+    for (int c2 = j + 1; c2 < m; ++c2) {
+      cd t = G(j, c2);
+      for (int k = 0; k < j; ++k) t -= std::conj(R[k + (size_t)j * m]) * R[k + (size_t)c2 * m];
+      R[j + (size_t)c2 * m] = t / rjj;
+    }
+  }
+  for (int b = 0; b < m; ++b)
+    for (int a = b; a >= 0; --a) {
+      const cd raa = R[a + (size_t)a * m];
+      if (raa == cd(0.0)) continue;
+      cd t = a == b ? cd(1.0) : cd(0.0);
+      for (int c2 = a + 1; c2 <= b; ++c2) t -= R[a + (size_t)c2 * m] * W[c2 + (size_t)b * m];
+      W[a + (size_t)b * m] = t / raa;
+    }
+  w.resize((size_t)m * m);
+  for (size_t i = 0; i < w.size(); ++i) w[i] = double2{W[i].real(), W[i].imag()};
+}
+
+// Right eigenpairs of K_k = H_k - i Gamma nearest sigma at the context's current k: shift-invert
+// subspace iteration (Y = G(sigma) Q, Q = orth(Y) by Cholesky QR twice) with Rayleigh-Ritz
+// (B = Q^H K Q from one apply, eigenpairs of B on the host, X = Q S).  Leaves the m Ritz vectors,
+// nearest sigma first, in c->d_egX (n x m) and their values in theta; resid gets the relative residuals
+// ||K x - theta x|| / max(1, |theta|) of the first p.
+static rst_status eig_right(rst_ctx* c, const rst_eig_opts* o, int m, int p, uint64_t seed,
+                            std::vector<std::complex<double>>& theta, std::vector<double>& resid, int& iters,
+                            rst_stats& acc) {
+  using cd = std::complex<double>;
+  const int P = c->na * c->nb;
+  const long long n = (long long)P * c->nz;
+  rst_status s;
+  if ((s = ensure(c, c->d_egQ, (size_t)n * m * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egY, (size_t)n * m * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egW, (size_t)n * m * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egX, (size_t)n * m * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egKX, (size_t)n * m * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egS, (size_t)m * m * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egG, (size_t)m * m * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egTh, (size_t)m * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egRes, (size_t)m * 8)) != RST_OK) return s;
+  if (c->nproj > 0 && (s = ensure(c, c->d_projP, (size_t)c->nproj * m * 16)) != RST_OK) return s;
+  double2* Q = (double2*)c->d_egQ.p;
+  double2* Y = (double2*)c->d_egY.p;
+  double2* W = (double2*)c->d_egW.p;
+  double2* X = (double2*)c->d_egX.p;
+  double2* KX = (double2*)c->d_egKX.p;
+  const unsigned gnm = (unsigned)((n * m + 255) / 256);
+  hipLaunchKernelGGL(rst::eig::k_eig_randn, dim3(gnm), dim3(256), 0, c->stream, n, m, (unsigned long long)seed, X);
+  HIPCHK(c, hipGetLastError());
+  std::vector<double2> hg((size_t)m * m), hw;
+  auto gram = [&](const double2* A, const double2* B, int cj) -> rst_status {
+    hipLaunchKernelGGL(rst::eig::k_eig_gram, dim3((unsigned)m * m), dim3(256), 0, c->stream, A, m, B, m, n, m, m, cj,
+                       (const double*)nullptr, P, (double2*)c->d_egG.p);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(hg.data(), c->d_egG.p, hg.size() * 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RST_OK;
+  };
+  auto rmul = [&](const double2* A, const std::vector<double2>& S, double alpha, double2* Z) -> rst_status {
+    HIPCHK(c, hipMemcpyAsync(c->d_egS.p, S.data(), S.size() * 16, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(rst::eig::k_eig_rmul, dim3(gnm), dim3(256), 0, c->stream, A, m, n, m,
+                       (const double2*)c->d_egS.p, m, alpha, Z, m);
+    HIPCHK(c, hipGetLastError());
+    return RST_OK;
+  };
+  std::vector<int64_t> zcols(m, 0);
+  theta.assign(m, cd(0.0));
+  resid.assign(p, 1e300);
+  iters = 0;
+  for (int it = 0; it < o->max_iter; ++it) {
+    iters = it + 1;
+    // Y = G(sigma) X  (dense right-hand sides, the context's solver)
+    std::vector<double> Tcol, res;
+    std::vector<int> its, rss, stv;
+    double ms = 0.0;
+    if (m == n) {
+      // the subspace is the whole space: Rayleigh-Ritz on any basis is exact, so the random block
+      // itself is orthonormalised (no solves, and no conditioning lost to G(sigma))
+      HIPCHK(c, hipMemcpyAsync(Y, X, (size_t)n * m * 16, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      HIPCHK(c, hipMemsetAsync(Y, 0, (size_t)n * m * 16, c->stream));
+      if ((s = run_solver(c, 1, &o->sigma, zcols, nullptr, nullptr, Y, Tcol, its, rss, res, stv, ms, X, m, 0)) !=
+          RST_OK)
+        return s;
+    }
+    int nbad = 0;
+    rst_stats st;
+    fill_stats(c, &st, its, rss, res, stv, ms, nbad, c->last_cw, c->last_threads);
+    acc.columns += st.columns;
+    acc.columns_unconverged += st.columns_unconverged;
+    acc.iterations_total += st.iterations_total;
+    acc.iterations_max = std::max(acc.iterations_max, st.iterations_max);
+    acc.kernel_ms += st.kernel_ms;
+    acc.bytes_algorithmic += st.bytes_algorithmic;
+    acc.max_rel_residual = std::max(acc.max_rel_residual, st.max_rel_residual);
+    // Q = orth(Y): Cholesky QR twice
+    if ((s = gram(Y, Y, 1)) != RST_OK) return s;
+    chol_inv(m, hg, hw);
+    if ((s = rmul(Y, hw, 1.0, Q)) != RST_OK) return s;
+    if ((s = gram(Q, Q, 1)) != RST_OK) return s;
+    chol_inv(m, hg, hw);
+    if ((s = rmul(Q, hw, 1.0, Y)) != RST_OK) return s;
+    std::swap(Q, Y);
+    // B = Q^H K Q with K Q = -A(0) Q
+    if ((s = apply_cols(c, Q, W, m, 0.0, nullptr, nullptr, false, (double2*)c->d_projP.p, nullptr)) != RST_OK)
+      return s;
+    if ((s = gram(Q, W, 1)) != RST_OK) return s;
+    std::vector<cd> B((size_t)m * m), w, v;
+    for (size_t i = 0; i < B.size(); ++i) B[i] = -cd(hg[i].x, hg[i].y);
+    if (!rst::zeig::eig(m, B, w, v)) return fail(c, RST_ENOCONV, "Rayleigh-Ritz eigensolver did not converge");
+    // Ritz pairs sorted by distance to sigma
+    std::vector<int> ord(m);
+    for (int i = 0; i < m; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return std::abs(w[a] - o->sigma) < std::abs(w[b] - o->sigma); });
+    std::vector<double2> S((size_t)m * m);
+    std::vector<double2> th(m);
+    for (int b = 0; b < m; ++b) {
+      theta[b] = w[ord[b]];
+      th[b] = double2{w[ord[b]].real(), w[ord[b]].imag()};
+      for (int a = 0; a < m; ++a) {
+        const cd x = v[a + (size_t)ord[b] * m];
+        S[a + (size_t)b * m] = double2{x.real(), x.imag()};
+      }
+    }
+    if ((s = rmul(Q, S, 1.0, X)) != RST_OK) return s;    // Ritz vectors (unit 2-norm: Q orthonormal)
+    if ((s = rmul(W, S, -1.0, KX)) != RST_OK) return s;  // K X
+    HIPCHK(c, hipMemcpyAsync(c->d_egTh.p, th.data(), m * 16, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(rst::eig::k_eig_resid, dim3((unsigned)p), dim3(256), 0, c->stream, (const double2*)KX,
+                       (const double2*)X, m, n, (const double2*)c->d_egTh.p, (double*)c->d_egRes.p);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> r2(p);
+    HIPCHK(c, hipMemcpyAsync(r2.data(), c->d_egRes.p, p * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool conv = true;
+    for (int i = 0; i < p; ++i) {
+      resid[i] = std::sqrt(r2[i]) / std::max(1.0, std::abs(theta[i]));
+      conv = conv && resid[i] <= o->tol;
+    }
+    if (conv || m == n) break;
+  }
+  return RST_OK;
+}
+
+extern "C" {
+
+void rst_default_eig(rst_eig_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->n_eig = 32;
+  o->subspace = 0;
+  o->max_iter = 40;
+  o->sigma = 0.0;
+  o->tol = 1e-8;
+  o->seed = 1;
+}
+
+rst_status rst_transmission_eigen(rst_ctx* c, int n_e, const double* E, const rst_eig_opts* o, double* T_out,
+                                  double* eig_out, rst_stats* stats) {
+  using cd = std::complex<double>;
+  rst_status s = check_ready(c);
+  if (s != RST_OK) return s;
+  if (!o || n_e < 0 || (n_e > 0 && (!E || !T_out))) return fail(c, RST_EINVAL, "bad eigen-route arguments");
+  for (int i = 0; i < n_e; ++i)
+    if (!std::isfinite(E[i])) return fail(c, RST_EINVAL, "non-finite energy");
+  const int P = c->na * c->nb;
+  const long long n = (long long)P * c->nz;
+  if (o->n_eig < 1 || o->n_eig > 512 || o->n_eig > n || o->max_iter < 1 || !(o->tol > 0) || !std::isfinite(o->sigma) ||
+      o->subspace < 0 || o->subspace > 1024)
+    return fail(c, RST_EINVAL, "bad eigen-route options (1 <= n_eig <= min(512, n), subspace <= 1024)");
+  if ((c->opts.method != RST_BICGSTAB && c->opts.method != RST_BICGSTAB_MC && c->opts.method != RST_IDRS) ||
+      c->opts.precision != RST_FP64)
+    return fail(c, RST_EUNSUPPORTED, "the eigen route solves with FP64 BiCGSTAB or IDR(s)");
+  hipSetDevice(c->device);
+  const int p = o->n_eig;
+  int m = o->subspace > 0 ? o->subspace : std::min<long long>(n, 2 * p + 16);
+  m = (int)std::min<long long>(std::max(m, p), n);
+  rst_stats acc;
+  std::memset(&acc, 0, sizeof(acc));
+  // right eigenvectors at +k (kept in d_egR) and at -k (in d_egX after the second run)
+  std::vector<cd> th_p, th_m;
+  std::vector<double> res_p, res_m;
+  int it_p = 0, it_m = 0;
+  if ((s = eig_right(c, o, m, p, o->seed, th_p, res_p, it_p, acc)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egR, (size_t)n * p * 16)) != RST_OK) return s;
+  // R = the first p Ritz vectors (n x p, column fastest)
+  {
+    std::vector<double2> sel((size_t)m * p, double2{0.0, 0.0});
+    for (int i = 0; i < p; ++i) sel[i + (size_t)i * m] = double2{1.0, 0.0};
+    HIPCHK(c, hipMemcpyAsync(c->d_egS.p, sel.data(), sel.size() * 16, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(rst::eig::k_eig_rmul, dim3((unsigned)((n * p + 255) / 256)), dim3(256), 0, c->stream,
+                       (const double2*)c->d_egX.p, m, n, m, (const double2*)c->d_egS.p, p, 1.0,
+                       (double2*)c->d_egR.p, p);
+    HIPCHK(c, hipGetLastError());
+  }
+  const double ka0 = c->ka, kb0 = c->kb;
+  const bool self = std::fabs(std::remainder(2 * ka0 * c->na * c->ha, 2 * M_PI)) < 1e-12 &&
+                    std::fabs(std::remainder(2 * kb0 * c->nb * c->hb, 2 * M_PI)) < 1e-12;
+  if (!self) {
+    c->ka = -ka0;
+    c->kb = -kb0;
+    if ((s = upload_k(c)) == RST_OK && (s = upload_pc(c)) == RST_OK)
+      s = eig_right(c, o, m, p, o->seed + 7919, th_m, res_m, it_m, acc);
+    c->ka = ka0;
+    c->kb = kb0;
+    rst_status s2 = upload_k(c);
+    if (s2 == RST_OK) s2 = upload_pc(c);
+    if (s != RST_OK) return s;
+    if (s2 != RST_OK) return s2;
+  }
+  // the -k Ritz vector of each +k eigenvalue (nearest eigenvalue; at a k equal to -k modulo a
+  // reciprocal vector the right vectors themselves), then L_i = conj(R'_j / d_i), d_i = R'_j . R_i
+  const double2* Rm = self ? (const double2*)c->d_egR.p : (const double2*)c->d_egX.p;
+  const int ldm = self ? p : m;
+  std::vector<int> map(p);
+  double mism = 0.0;
+  for (int i = 0; i < p; ++i) {
+    if (self) {
+      map[i] = i;
+      continue;
+    }
+    int best = 0;
+    for (int j = 1; j < m; ++j)
+      if (std::abs(th_m[j] - th_p[i]) < std::abs(th_m[best] - th_p[i])) best = j;
+    map[i] = best;
+    mism = std::max(mism, std::abs(th_m[best] - th_p[i]) / std::max(1.0, std::abs(th_p[i])));
+  }
+  if ((s = ensure(c, c->d_egL, (size_t)n * p * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egMap, (size_t)p * 4)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egSc, (size_t)p * 16)) != RST_OK) return s;
+  if ((s = ensure(c, c->d_egG, (size_t)std::max(m, p) * std::max(m, p) * 16)) != RST_OK) return s;
+  // d_i = sum_g R'_map(i)[g] R_i[g] (bilinear): the diagonal of a Gram block, one entry per workgroup
+  std::vector<double2> scale(p);
+  {
+    std::vector<double2> dv(1);
+    for (int i = 0; i < p; ++i) {
+      hipLaunchKernelGGL(rst::eig::k_eig_gram, dim3(1), dim3(256), 0, c->stream, Rm + map[i], ldm,
+                         (const double2*)c->d_egR.p + i, p, n, 1, 1, 0, (const double*)nullptr, P,
+                         (double2*)c->d_egG.p + i);
+    }
+    HIPCHK(c, hipGetLastError());
+    std::vector<double2> d(p);
+    HIPCHK(c, hipMemcpyAsync(d.data(), c->d_egG.p, p * 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < p; ++i) {
+      const cd inv = 1.0 / cd(d[i].x, d[i].y);
+      scale[i] = double2{inv.real(), inv.imag()};
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_egMap.p, map.data(), p * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_egSc.p, scale.data(), p * 16, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(rst::eig::k_eig_left, dim3((unsigned)((n * p + 255) / 256)), dim3(256), 0, c->stream, Rm, ldm, n,
+                     p, (const int*)c->d_egMap.p, (const double2*)c->d_egSc.p, (double2*)c->d_egL.p);
+  HIPCHK(c, hipGetLastError());
+  // transformed CAPs GtL = R^H Gamma_L R, GtR = L^H Gamma_R L (p x p, column-major)
+  std::vector<double2> gtl((size_t)p * p), gtr((size_t)p * p);
+  hipLaunchKernelGGL(rst::eig::k_eig_gram, dim3((unsigned)p * p), dim3(256), 0, c->stream,
+                     (const double2*)c->d_egR.p, p, (const double2*)c->d_egR.p, p, n, p, p, 1,
+                     (const double*)c->d_gl.p, P, (double2*)c->d_egG.p);
+  HIPCHK(c, hipMemcpyAsync(gtl.data(), c->d_egG.p, gtl.size() * 16, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  hipLaunchKernelGGL(rst::eig::k_eig_gram, dim3((unsigned)p * p), dim3(256), 0, c->stream,
+                     (const double2*)c->d_egL.p, p, (const double2*)c->d_egL.p, p, n, p, p, 1,
+                     (const double*)c->d_gr.p, P, (double2*)c->d_egG.p);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(gtr.data(), c->d_egG.p, gtr.size() * 16, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // T(E) = 4 sum_{m,n} GtL[m,n] GtR[n,m] / ((E - lam_n)(E - lam_m)^*)
+  for (int ie = 0; ie < n_e; ++ie) {
+    std::vector<cd> dd(p);
+    for (int i = 0; i < p; ++i) dd[i] = 1.0 / (E[ie] - th_p[i]);
+    cd t = 0.0;
+    for (int b = 0; b < p; ++b)
+      for (int a = 0; a < p; ++a) {
+        const cd l(gtl[a + (size_t)b * p].x, gtl[a + (size_t)b * p].y);   // GtL[a, b]
+        const cd r(gtr[b + (size_t)a * p].x, gtr[b + (size_t)a * p].y);   // GtR[b, a]
+        t += l * r * dd[b] * std::conj(dd[a]);
+      }
+    T_out[ie] = 4.0 * t.real();
+  }
+  if (eig_out)
+    for (int i = 0; i < p; ++i) {
+      eig_out[2 * i] = th_p[i].real();
+      eig_out[2 * i + 1] = th_p[i].imag();
+    }
+  double rmax = 0.0;
+  for (int i = 0; i < p; ++i) rmax = std::max(rmax, res_p[i]);
+  for (double r : res_m) rmax = std::max(rmax, r);
+  acc.restarts_total = it_p + it_m;  // subspace iterations (both Bloch vectors)
+  if (stats) {
+    *stats = acc;
+    stats->max_rel_residual = std::max(acc.max_rel_residual, rmax);
+  }
+  const bool ok = rmax <= o->tol && mism <= 1e3 * o->tol && acc.columns_unconverged == 0;
+  if (!ok && rmax > o->tol)
+    c->err = "eigenpairs not converged to tol: largest relative residual " + std::to_string(rmax) +
+             ", +k/-k eigenvalue mismatch " + std::to_string(mism);
+  return ok ? RST_OK : RST_ENOCONV;
+}
+
+}  // extern "C"
 
 static rst_status cnn_engine(rst_ctx* c, bool need_weights) {
   if (!c->cnn) c->cnn = rst::cnn::engine_create(c->stream);

@@ -30,7 +30,7 @@ EXPORTED = ["rst_default_solver", "rst_create", "rst_destroy", "rst_last_error",
             "rst_batch_add", "rst_batch_run", "rst_cnn_weight_count", "rst_cnn_seed",
             "rst_cnn_set_weights", "rst_cnn_get_weights", "rst_cnn_forward", "rst_cnn_gradient",
             "rst_cnn_train_step", "rst_precond_train", "rst_solve_rhs", "rst_default_lowrank",
-            "rst_transmission_lowrank", "rst_apply_h_noalloc"]
+            "rst_transmission_lowrank", "rst_apply_h_noalloc", "rst_default_eig", "rst_transmission_eigen"]
 
 
 class rst_solver_opts(C.Structure):
@@ -51,6 +51,11 @@ class rst_stats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rst_eig_opts(C.Structure):
+    _fields_ = [("n_eig", C.c_int), ("subspace", C.c_int), ("max_iter", C.c_int), ("sigma", C.c_double),
+                ("tol", C.c_double), ("seed", C.c_uint64)]
 
 
 class rst_train_opts(C.Structure):
@@ -124,6 +129,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.rst_transmission.argtypes = [P, C.c_int, P, P, C.POINTER(rst_stats)]
     lib.rst_apply_h.argtypes = [P, C.c_double, P, P, C.c_int, C.c_int]
     lib.rst_apply_h_noalloc.argtypes = [P, C.c_double, P, P, C.c_int, C.c_int]
+    lib.rst_default_eig.argtypes = [C.POINTER(rst_eig_opts)]
+    lib.rst_default_eig.restype = None
+    lib.rst_transmission_eigen.argtypes = [P, C.c_int, P, C.POINTER(rst_eig_opts), P, P, C.POINTER(rst_stats)]
     lib.rst_transmission_kavg.argtypes = [P, C.c_int, P, C.c_int, C.c_int, P, P, P, C.POINTER(C.c_int),
                                           C.POINTER(rst_stats)]
     lib.rst_apply_timing.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -147,7 +155,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.rst_cnn_train_step.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P, P, C.c_float,
                                        C.POINTER(C.c_double)]
     for name in EXPORTED:
-        if name not in ("rst_default_solver", "rst_destroy", "rst_last_error", "rst_default_lowrank"):
+        if name not in ("rst_default_solver", "rst_destroy", "rst_last_error", "rst_default_lowrank",
+                        "rst_default_eig"):
             getattr(lib, name).restype = C.c_int
     lib.rst_cnn_weight_count.restype = C.c_int64
     lib.rst_default_lowrank.restype = None
@@ -308,6 +317,20 @@ class Context:
         s = self._chk(self.lib.rst_transmission_lowrank(self.h, e.size, _ptr(e), C.byref(o), _ptr(t), _ptr(terr),
                                                         C.byref(st)), allow_noconv=True)
         return t, terr, st.as_dict(), s
+
+    def rst_transmission_eigen(self, energies, **kw):
+        """T(E) by the eigen route; returns (T, eigenvalues (complex, nearest sigma first), stats, status)."""
+        e = np.ascontiguousarray(np.atleast_1d(energies), np.float64)
+        o = rst_eig_opts()
+        self.lib.rst_default_eig(C.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        t = np.zeros(e.size)
+        ev = np.zeros(2 * o.n_eig)
+        st = rst_stats()
+        s = self._chk(self.lib.rst_transmission_eigen(self.h, e.size, _ptr(e), C.byref(o), _ptr(t), _ptr(ev),
+                                                      C.byref(st)), allow_noconv=True)
+        return t, ev[0::2] + 1j * ev[1::2], st.as_dict(), s
 
     # -- batches
     def rst_batch_clear(self):
