@@ -16,10 +16,15 @@
 // A wave covers one segment of zseg planes (its queue starts from the rows
 // below and above the segment), so the waves that share lateral rows stay
 // within a few planes of each other.  Workgroup b takes (chunk, segment,
-// point); the eight XCDs receive workgroups round robin (b mod 8) and each has
-// its own L2, so chunk c runs on XCD c mod 8 with all points of a segment
-// dispatched together and its segments in increasing z (whole groups of eight
-// chunks; a remainder keeps plain order).
+// point).  The eight XCDs receive workgroups round robin (b mod 8) and each has
+// its own L2, so the (chunk, segment) groups, segment fastest, are split into
+// eight contiguous runs, one per XCD: every lateral neighbour row a wave reads
+// was streamed on its own XCD, and consecutive segments of a chunk (which share
+// their z halo rows) run back to back (a remainder of fewer than eight groups
+// keeps plain order).  Inside a group the points go in strips of `strip`
+// a-columns, a fastest, so a point's b neighbours are dispatched within a few
+// strip widths of it and are still in L2 when it reads them (on wide planes a
+// plain row-major order puts them a whole b-row apart per step).
 //
 // F is the arithmetic and storage type: double (complex128 x, y) or float
 // (complex64 x, y: the stencil in FP32; the projector sum, from the FP64
@@ -36,6 +41,8 @@ namespace rst {
 // Planes per wave (measured on config 2 at 1024-4096 columns: 8 and 16 best,
 // 32 slightly and 170 (whole columns) 20-30% slower).
 constexpr int APPLY_ZSEG = 16;
+// a-columns per strip of the point order on planes wider than the waves in flight
+constexpr int APPLY_STRIP = 6;
 
 struct ColApplyArgs {
   const void* x;      // n x ncol, complex128 or complex64 (the kernel's F)
@@ -49,6 +56,7 @@ struct ColApplyArgs {
   Proj pj;
   const double2* P;   // [nproj*ncol]
   int zseg;           // planes per wave (>= 1)
+  int strip;          // a-columns per strip of the point order (1..na; na: row-major)
   const double* ecol; // [ncol] energy of each column (nullable: `energy` for all)
   const int* mask;    // [ncol] columns to apply (nullable: all); others are left untouched
 };
@@ -80,25 +88,29 @@ __global__ __launch_bounds__(64, (ApplyMinWaves<F, NMU>::value)) void k_apply_co
   const int nseg = (nz + A.zseg - 1) / A.zseg;
   // (chunk, segment, point) of this workgroup
   const long long b = blockIdx.x;
-  const long long full8 = (long long)(nchunk / 8) * 8;
-  int chunk, seg, p;
-  if (b < full8 * nseg * P) {
-    const long long i = b / 8;   // position in this XCD's sequence
-    const long long gl = i / P;  // (chunk on this XCD, segment), segment fastest
-    chunk = (int)((gl / nseg) * 8 + b % 8);
-    seg = (int)(gl % nseg);
-    p = (int)(i % P);
+  const long long g8 = (long long)nchunk * nseg / 8;  // groups per XCD in the balanced part
+  long long grp, pi;
+  if (b < g8 * 8 * P) {
+    const long long i = b / 8;  // position in this XCD's sequence
+    grp = (b % 8) * g8 + i / P;
+    pi = i % P;
   } else {
-    const long long r = b - full8 * nseg * P;
-    chunk = (int)(full8 + r / ((long long)nseg * P));
-    seg = (int)((r / P) % nseg);
-    p = (int)(r % P);
+    const long long r = b - g8 * 8 * P;
+    grp = g8 * 8 + r / P;
+    pi = r % P;
   }
+  const int chunk = (int)(grp / nseg), seg = (int)(grp % nseg);
+  // point pi of the group: strip s of W a-columns (the last one narrower), b-rows of w points
+  const int W = A.strip;
+  const int s0 = (int)(pi / ((long long)W * nb));
+  const int r0 = (int)(pi - (long long)s0 * W * nb);
+  const int w0 = min(W, na - s0 * W);
+  const int ib = r0 / w0, ia = s0 * W + r0 % w0;
+  const int p = ia + na * ib;
   const int z0 = seg * A.zseg, z1 = min(nz, z0 + A.zseg);
   const int c = chunk * 64 + (int)threadIdx.x;
   const bool ok = c < ncol && (A.mask == nullptr || A.mask[c] != 0);
   const double ec = A.ecol != nullptr && c < ncol ? A.ecol[c] : A.energy;
-  const int ia = p % na, ib = p / na;
   const V2 pha{(F)g.pha_x, (F)g.pha_y}, phac{(F)g.pha_x, (F)-g.pha_y};
   const V2 phb{(F)g.phb_x, (F)g.phb_y}, phbc{(F)g.phb_x, (F)-g.phb_y};
   const V2 zero{(F)0, (F)0};

@@ -117,32 +117,53 @@ __global__ __launch_bounds__(256) void k_idr_zero(Shape S, int s, const int* mar
   }
 }
 
+// The vector updates below run over a block's row range (grid (ld/64, nsplit),
+// four waves striding the rows) with each column's coefficients loaded once into
+// registers; columns that are not iterating are left untouched.
+
 // V = R - sum_{i=k}^{s-1} c_i G_i.
 __global__ __launch_bounds__(256) void k_idr_v(Shape S, int s, int k, const IdrSt* st, const int* act,
                                                const double2* R, const double2* G, double2* V) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long vlen = S.n * S.ld;
-  if (t >= vlen) return;
-  const int c = (int)(t % S.ld);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
   if (!act[c]) return;
-  const IdrSt& q = st[c];
-  double2 v = R[t];
-  for (int i = k; i < s; ++i) v = c_sub(v, c_mul(q.c[i], G[i * vlen + t]));
-  V[t] = v;
+  const long long r0 = (long long)blockIdx.y * S.rows;
+  const long long r1 = r0 + S.rows < S.n ? r0 + S.rows : S.n;
+  const long long vlen = S.n * S.ld;
+  double2 cf[SMAX];
+#pragma unroll
+  for (int i = 0; i < SMAX; ++i) cf[i] = i >= k && i < s ? st[c].c[i] : make_double2(0.0, 0.0);
+  for (long long gi = r0 + wv; gi < r1; gi += 4) {
+    const size_t o = (size_t)gi * S.ld + c;
+    double2 v = R[o];
+#pragma unroll
+    for (int i = 0; i < SMAX; ++i)
+      if (i >= k && i < s) v = c_sub(v, c_mul(cf[i], G[i * vlen + o]));
+    V[o] = v;
+  }
 }
 
 // U_k = sum_{i=k}^{s-1} c_i U_i + omega VH.
 __global__ __launch_bounds__(256) void k_idr_u(Shape S, int s, int k, const IdrSt* st, const int* act,
                                                const double2* VH, double2* U) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long vlen = S.n * S.ld;
-  if (t >= vlen) return;
-  const int c = (int)(t % S.ld);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
   if (!act[c]) return;
-  const IdrSt& q = st[c];
-  double2 u = c_mul(q.omega, VH[t]);
-  for (int i = k; i < s; ++i) u = c_add(u, c_mul(q.c[i], U[i * vlen + t]));
-  U[k * vlen + t] = u;
+  const long long r0 = (long long)blockIdx.y * S.rows;
+  const long long r1 = r0 + S.rows < S.n ? r0 + S.rows : S.n;
+  const long long vlen = S.n * S.ld;
+  double2 cf[SMAX];
+#pragma unroll
+  for (int i = 0; i < SMAX; ++i) cf[i] = i >= k && i < s ? st[c].c[i] : make_double2(0.0, 0.0);
+  const double2 om = st[c].omega;
+  for (long long gi = r0 + wv; gi < r1; gi += 4) {
+    const size_t o = (size_t)gi * S.ld + c;
+    double2 u = c_mul(om, VH[o]);
+#pragma unroll
+    for (int i = 0; i < SMAX; ++i)
+      if (i >= k && i < s) u = c_add(u, c_mul(cf[i], U[i * vlen + o]));
+    U[k * vlen + o] = u;
+  }
 }
 
 // G_k -= sum_{i<k} alpha_i G_i;  U_k -= sum_{i<k} alpha_i U_i;  R -= beta G_k;  X += beta U_k;
@@ -185,17 +206,45 @@ __global__ __launch_bounds__(256) void k_idr_upd(Shape S, int k, const IdrSt* st
   }
 }
 
-// R -= omega T;  X += omega VH  (dimension-reduction step).
-__global__ __launch_bounds__(256) void k_idr_rx(Shape S, const IdrSt* st, const int* act, double2* R, double2* X,
-                                                const double2* T, const double2* VH) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= S.n * S.ld) return;
-  const int c = (int)(t % S.ld);
-  if (!act[c]) return;
-  const double2 om = st[c].omega;
-  const double2 vh = VH[t];  // read before R is written: VH may be R itself (no preconditioner)
-  R[t] = c_sub(R[t], c_mul(om, T[t]));
-  X[t] = c_add(X[t], c_mul(om, vh));
+// R -= omega T;  X += omega VH  (dimension-reduction step), with the partials of
+// ||R||^2 (product 0) and P^H R (products 1..s) of the new residual, as k_idr_pdots<true>.
+__global__ __launch_bounds__(256) void k_idr_rx(Shape S, int s, const IdrSt* st, const int* act, double2* R,
+                                                double2* X, const double2* T, const double2* VH, const double2* Pm,
+                                                double2* part) {
+  __shared__ double2 red[SMAX + 1][4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  const long long r0 = (long long)blockIdx.y * S.rows;
+  const long long r1 = r0 + S.rows < S.n ? r0 + S.rows : S.n;
+  double2 acc[SMAX + 1];
+#pragma unroll
+  for (int d = 0; d <= SMAX; ++d) acc[d] = make_double2(0.0, 0.0);
+  if (act[c]) {
+    const double2 om = st[c].omega;
+    for (long long gi = r0 + wv; gi < r1; gi += 4) {
+      const size_t o = (size_t)gi * S.ld + c;
+      const double2 vh = VH[o];  // read before R is written: VH may be R itself (no preconditioner)
+      const double2 r = c_sub(R[o], c_mul(om, T[o]));
+      R[o] = r;
+      X[o] = c_add(X[o], c_mul(om, vh));
+      acc[0].x += r.x * r.x + r.y * r.y;
+#pragma unroll
+      for (int j = 0; j < SMAX; ++j)
+        if (j < s) acc[1 + j] = c_add(acc[1 + j], c_mulc(Pm[(size_t)gi * s + j], r));
+    }
+  }
+#pragma unroll
+  for (int d = 0; d <= SMAX; ++d) red[d][wv][lane] = acc[d];
+  __syncthreads();
+  if (wv == 0) {
+    for (int d = 0; d <= s; ++d) {
+      double2 t = red[d][0][lane];
+      t = c_add(t, red[d][1][lane]);
+      t = c_add(t, red[d][2][lane]);
+      t = c_add(t, red[d][3][lane]);
+      part[((size_t)d * S.nsplit + blockIdx.y) * S.ld + c] = t;
+    }
+  }
 }
 
 // Per-column scalar work after each reduction; one wavefront per column sums the

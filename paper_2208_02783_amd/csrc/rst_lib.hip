@@ -328,9 +328,11 @@ rst_status proj_blocked(rst_ctx* c, const rst::ApplyArgs& A) {
   return RST_OK;
 }
 
-// Builds the projector plan: groups of consecutive projectors with identical
-// (point, image) entry lists, entries sorted by plane, per-plane gather chunks,
-// and the point-centric scatter lists.
+// Strip width of k_apply_cols' point order.  A plane that the waves in flight on
+// one XCD cover whole (about 32 CUs x 12 waves) keeps row-major order; on wider
+// planes strips of APPLY_STRIP a-columns keep the b neighbours a few strips apart.
+int apply_strip(int na, int P) { return P <= 512 ? na : std::min(na, rst::APPLY_STRIP); }
+
 // y = (E - H_k + i Gamma) x on an n x ncol column-fastest block: the projections
 // h^3 B^H x of every column on the FP64 matrix cores (k_proj_mm, into projP:
 // nproj*ncol complex128), then one wave per (64 columns, z segment, grid point)
@@ -356,6 +358,7 @@ rst_status apply_cols(rst_ctx* c, const void* x, void* y, int ncol, double energ
   A.energy = energy;
   A.pj = make_proj(c);
   A.zseg = zseg;
+  A.strip = apply_strip(c->na, P);
   A.ecol = ecol;
   A.mask = mask;
   if (ev) HIPCHK(c, hipEventRecord(ev[0], c->stream));
@@ -402,6 +405,9 @@ rst_status apply_cols(rst_ctx* c, const void* x, void* y, int ncol, double energ
   return RST_OK;
 }
 
+// Builds the projector plan: groups of consecutive projectors with identical
+// (point, image) entry lists, entries sorted by plane, per-plane gather chunks,
+// and the point-centric scatter lists.
 rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t* pt, const int8_t* img,
                       const double* beta, const double* ekb) {
   const long long n = (long long)c->na * c->nb * c->nz;
@@ -1418,6 +1424,29 @@ double idr_bytes_per_matvec(int s, bool pc) {
 
 // Many-column right-preconditioned BiCGSTAB (rst_mk.hpp) over the (energy, column) items, in blocks
 // of up to `ld` columns with one kernel per step; same inputs and outputs as the persistent solver.
+// Factored lateral DFT instances (k_mk_fft<N1, N2, NW>, N = N1 N2); other N use the direct
+// evaluation (k_mk_dft).
+struct FftInstance {
+  const void* kern;
+  int nw;
+};
+FftInstance fft_instance(int N) {
+  switch (N) {
+    case 8: return {(const void*)rst::mk::k_mk_fft<2, 4, 2, 1>, 2};
+    case 12: return {(const void*)rst::mk::k_mk_fft<3, 4, 2, 1>, 2};
+    case 16: return {(const void*)rst::mk::k_mk_fft<4, 4, 4, 1>, 4};
+    case 18: return {(const void*)rst::mk::k_mk_fft<3, 6, 3, 1>, 3};
+    case 24: return {(const void*)rst::mk::k_mk_fft<4, 6, 2, 1>, 2};
+    case 27: return {(const void*)rst::mk::k_mk_fft<3, 9, 3, 1>, 3};
+    case 32: return {(const void*)rst::mk::k_mk_fft<4, 8, 4, 1>, 4};
+    case 36: return {(const void*)rst::mk::k_mk_fft<6, 6, 3, 1>, 3};
+    case 48: return {(const void*)rst::mk::k_mk_fft<6, 8, 2, 1>, 2};
+    case 54: return {(const void*)rst::mk::k_mk_fft<6, 9, 3, 1>, 3};
+    case 64: return {(const void*)rst::mk::k_mk_fft<8, 8, 4, 1>, 4};
+    default: return {nullptr, 0};
+  }
+}
+
 rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
                            const double* d_gsrc, const double* d_gdst, double2* xout, std::vector<double>& Tcol,
                            std::vector<int>& its, std::vector<int>& rss, std::vector<double>& res,
@@ -1511,36 +1540,42 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
   B.doff = d_doff;
   // preconditioner: DFT passes: (w, post) tables of forward a, inverse a, forward b, inverse b; band factors
   const double2 *band_L = nullptr, *band_dinv = nullptr;
-  const double2 *FAw = nullptr, *FAp = nullptr, *IAw = nullptr, *IAp = nullptr;
-  const double2 *FBw = nullptr, *FBp = nullptr, *IBw = nullptr, *IBp = nullptr;
+  struct DftTabs {
+    const double2 *w = nullptr, *post = nullptr, *pre = nullptr, *root = nullptr;
+  } FA, IA, FB, IB;
   if (pc) {
     const double pi = 3.14159265358979323846;
-    std::vector<double2> F((size_t)4 * na + (size_t)4 * nb);
+    // per axis (N points, Bloch phase kh per point): w and post of the forward and inverse
+    // passes, then the factored form's tables: the forward twist pre[i] = exp(-i kh i), ones
+    // (no twist on the inverse), and the roots exp(-+2 pi i m/N)
+    std::vector<double2> F((size_t)8 * na + (size_t)8 * nb);
     auto put = [](double2& d, double ph, double sc) { d = double2{sc * std::cos(ph), sc * std::sin(ph)}; };
-    double2* t = F.data();
-    for (int j = 0; j < na; ++j) {
-      put(t[j], -(2 * pi * j / na + c->ka * c->ha), 1.0);  // forward a: w
-      put(t[na + j], 0.0, 1.0);                             // forward a: post
-      put(t[2 * na + j], 2 * pi * j / na, 1.0);             // inverse a: w
-      put(t[3 * na + j], c->ka * c->ha * j, 1.0 / na);      // inverse a: post
-    }
-    t += 4 * na;
-    for (int j = 0; j < nb; ++j) {
-      put(t[j], -(2 * pi * j / nb + c->kb * c->hb), 1.0);
-      put(t[nb + j], 0.0, 1.0);
-      put(t[2 * nb + j], 2 * pi * j / nb, 1.0);
-      put(t[3 * nb + j], c->kb * c->hb * j, 1.0 / nb);
-    }
+    auto axis = [&](double2* t, int N, double kh) {
+      for (int j = 0; j < N; ++j) {
+        put(t[j], -(2 * pi * j / N + kh), 1.0);  // forward: w
+        put(t[N + j], 0.0, 1.0);                 // forward: post
+        put(t[2 * N + j], 2 * pi * j / N, 1.0);  // inverse: w
+        put(t[3 * N + j], kh * j, 1.0 / N);      // inverse: post
+        put(t[4 * N + j], -kh * j, 1.0);         // forward: pre
+        put(t[5 * N + j], 0.0, 1.0);             // inverse: pre
+        put(t[6 * N + j], -2 * pi * j / N, 1.0); // forward: root^j
+        put(t[7 * N + j], 2 * pi * j / N, 1.0);  // inverse: root^j
+      }
+    };
+    axis(F.data(), na, c->ka * c->ha);
+    axis(F.data() + 8 * na, nb, c->kb * c->hb);
     if ((e = upload(c, c->d_mkF, F)) != RST_OK) return e;
     const double2* d = (const double2*)c->d_mkF.p;
-    FAw = d;
-    FAp = d + na;
-    IAw = d + 2 * na;
-    IAp = d + 3 * na;
-    FBw = d + 4 * na;
-    FBp = FBw + nb;
-    IBw = FBw + 2 * nb;
-    IBp = FBw + 3 * nb;
+    auto tabs = [](const double2* t, int N, bool inv, DftTabs& o) {
+      o.w = t + (inv ? 2 : 0) * N;
+      o.post = t + (inv ? 3 : 1) * N;
+      o.pre = t + (inv ? 5 : 4) * N;
+      o.root = t + (inv ? 7 : 6) * N;
+    };
+    tabs(d, na, false, FA);
+    tabs(d, na, true, IA);
+    tabs(d + 8 * na, nb, false, FB);
+    tabs(d + 8 * na, nb, true, IB);
     // banded L D L^T of the z operator per (energy, lateral mode)
     std::vector<double> en(energies, energies + ne);
     if ((e = upload(c, c->d_en, en)) != RST_OK) return e;
@@ -1578,7 +1613,7 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     band_L = Bd.L;
     band_dinv = Bd.dinv;
   }
-  // outputs per wave: the smallest instance with 4*RW >= N (N > 64 takes several rounds of 64)
+  // direct evaluation: the smallest instance with 4*RW >= N (N > 64 takes several rounds of 64)
   auto dft_kernel = [](int N) -> const void* {
     if (N <= 8) return (const void*)rst::mk::k_mk_dft<2>;
     if (N <= 16) return (const void*)rst::mk::k_mk_dft<4>;
@@ -1587,16 +1622,17 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
   };
   auto dft_lds = [](int N) -> size_t { return ((size_t)N * 64 + 2 * (size_t)N) * 16; };
   for (int N : {na, nb})
-    if (dft_lds(N) > 64 * 1024)
+    if (!fft_instance(N).kern && dft_lds(N) > 64 * 1024)
       HIPCHK(c, hipFuncSetAttribute(dft_kernel(N), hipFuncAttributeMaxDynamicSharedMemorySize, (int)dft_lds(N)));
-  // out = the DFT pass of `in` for the columns of `mask`
-  auto dft = [&](const double2* in, double2* out, const double2* w, const double2* post, bool axis_a,
-                 const int* mask) -> rst_status {
+  // out = the DFT pass of `in` for the columns of `mask` (factored where N has an instance)
+  auto dft = [&](const double2* in, double2* out, const DftTabs& tb, bool axis_a, const int* mask) -> rst_status {
     rst::mk::DftPass D;
     D.in = in;
     D.out = out;
-    D.w = w;
-    D.post = post;
+    D.w = tb.w;
+    D.post = tb.post;
+    D.pre = tb.pre;
+    D.root = tb.root;
     D.act = mask;
     D.N = axis_a ? na : nb;
     D.stride = axis_a ? 1 : na;
@@ -1607,13 +1643,17 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     D.ld = ld;
     const long long nwg = (long long)nz * D.nline_inner * (ld / 64);
     void* args[] = {&D};
-    HIPCHK(c, hipLaunchKernel(dft_kernel(D.N), dim3((unsigned)nwg), dim3(256), args, dft_lds(D.N), c->stream));
+    const FftInstance fi = fft_instance(D.N);
+    if (fi.kern)
+      HIPCHK(c, hipLaunchKernel(fi.kern, dim3((unsigned)nwg), dim3(64 * fi.nw), args, 0, c->stream));
+    else
+      HIPCHK(c, hipLaunchKernel(dft_kernel(D.N), dim3((unsigned)nwg), dim3(256), args, dft_lds(D.N), c->stream));
     return RST_OK;
   };
   auto precondition = [&](const double2* in, double2* out, const int* mask) -> rst_status {
     rst_status ps;
-    if ((ps = dft(in, W, FAw, FAp, true, mask)) != RST_OK) return ps;
-    if ((ps = dft(W, out, FBw, FBp, false, mask)) != RST_OK) return ps;
+    if ((ps = dft(in, W, FA, true, mask)) != RST_OK) return ps;
+    if ((ps = dft(W, out, FB, false, mask)) != RST_OK) return ps;
     const long long nt = (long long)P * ld;
     if (c->rad == 6)
       hipLaunchKernelGGL(rst::mk::k_mk_band_solve<6>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
@@ -1622,8 +1662,8 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
       hipLaunchKernelGGL(rst::mk::k_mk_band_solve<2>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
                          out, W, band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
     HIPCHK(c, hipGetLastError());
-    if ((ps = dft(out, W, IBw, IBp, false, mask)) != RST_OK) return ps;
-    return dft(W, out, IAw, IAp, true, mask);
+    if ((ps = dft(out, W, IB, false, mask)) != RST_OK) return ps;
+    return dft(W, out, IA, true, mask);
   };
   auto apply = [&](const double2* x, double2* y, const int* mask) -> rst_status {
     return apply_cols(c, x, y, ld, 0.0, d_ecol, mask, false, (double2*)c->d_projP.p, nullptr);
@@ -1691,7 +1731,7 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
       for (int iter = 0;; ++iter) {
         // one BiCGSTAB step of every iterating column
         if (iter > 0)
-          hipLaunchKernelGGL(rst::mk::k_mk_p, dim3(gel), dim3(256), 0, c->stream, S, (const rst::mk::ColSt*)dst_,
+          hipLaunchKernelGGL(rst::mk::k_mk_p, gred, dim3(256), 0, c->stream, S, (const rst::mk::ColSt*)dst_,
                              (const int*)act, Pv, (const double2*)R, (const double2*)V);
         if (pc && (ps = precondition(Pv, PH, act)) != RST_OK) return ps;
         if ((ps = apply(PH, V, act)) != RST_OK) return ps;
@@ -1699,7 +1739,7 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
                            (const double2*)R0, (const double2*)V, (const double2*)nullptr, (const double2*)nullptr,
                            part);
         if ((ps = scalar(rst::mk::SC_ALPHA)) != RST_OK) return ps;
-        hipLaunchKernelGGL(rst::mk::k_mk_s, dim3(gel), dim3(256), 0, c->stream, S, (const rst::mk::ColSt*)dst_,
+        hipLaunchKernelGGL(rst::mk::k_mk_s, gred, dim3(256), 0, c->stream, S, (const rst::mk::ColSt*)dst_,
                            (const int*)act, R, (const double2*)V);
         if (pc && (ps = precondition(R, SH, act)) != RST_OK) return ps;
         if ((ps = apply(SH, T, act)) != RST_OK) return ps;
@@ -1790,10 +1830,10 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
           double2* Gk = Gb + (size_t)k * vlen;
           double2* Uk = Ub + (size_t)k * vlen;
           if ((ps = iscal(rst::idr::ID_C, k, nullptr)) != RST_OK) return ps;
-          hipLaunchKernelGGL(rst::idr::k_idr_v, dim3(gel), dim3(256), 0, c->stream, S, sdim, k,
+          hipLaunchKernelGGL(rst::idr::k_idr_v, gred, dim3(256), 0, c->stream, S, sdim, k,
                              (const rst::idr::IdrSt*)did, (const int*)act, (const double2*)R, (const double2*)Gb, V);
           if (pc && (ps = precondition(V, PH, act)) != RST_OK) return ps;
-          hipLaunchKernelGGL(rst::idr::k_idr_u, dim3(gel), dim3(256), 0, c->stream, S, sdim, k,
+          hipLaunchKernelGGL(rst::idr::k_idr_u, gred, dim3(256), 0, c->stream, S, sdim, k,
                              (const rst::idr::IdrSt*)did, (const int*)act, (const double2*)VH, Ub);
           if ((ps = apply(Uk, Gk, act)) != RST_OK) return ps;
           hipLaunchKernelGGL(rst::idr::k_idr_pdots<false>, gred, dim3(256), 0, c->stream, S, sdim, (const int*)act,
@@ -1813,10 +1853,9 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
         hipLaunchKernelGGL(rst::mk::k_mk_dots<2>, gred, dim3(256), 0, c->stream, S, (const int*)act,
                            (const double2*)T, (const double2*)R, (const double2*)T, (const double2*)T, part);
         if ((ps = iscal(rst::idr::ID_OMEGA, 0, nullptr)) != RST_OK) return ps;
-        hipLaunchKernelGGL(rst::idr::k_idr_rx, dim3(gel), dim3(256), 0, c->stream, S, (const rst::idr::IdrSt*)did,
-                           (const int*)act, R, X, (const double2*)T, (const double2*)vr);
-        hipLaunchKernelGGL(rst::idr::k_idr_pdots<true>, gred, dim3(256), 0, c->stream, S, sdim, (const int*)act,
-                           Psh, (const double2*)R, part);
+        hipLaunchKernelGGL(rst::idr::k_idr_rx, gred, dim3(256), 0, c->stream, S, sdim,
+                           (const rst::idr::IdrSt*)did, (const int*)act, R, X, (const double2*)T, (const double2*)vr,
+                           Psh, part);
         if ((ps = iscal(rst::idr::ID_END, 0, nullptr)) != RST_OK) return ps;
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(hid.data(), did, ld * sizeof(rst::idr::IdrSt), hipMemcpyDeviceToHost, c->stream));

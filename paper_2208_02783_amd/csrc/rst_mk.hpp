@@ -131,23 +131,34 @@ __global__ __launch_bounds__(256) void k_mk_init(Shape S, Rhs B, double2* X, dou
 }
 
 // P = R + beta (P - omega V) for iterating columns.
+// (Grid (ld/64, nsplit), four waves striding the block's rows, the column's scalars
+// loaded once.)
 __global__ __launch_bounds__(256) void k_mk_p(Shape S, const ColSt* st, const int* act, double2* P, const double2* R,
                                               const double2* V) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= S.n * S.ld) return;
-  const int c = (int)(t % S.ld);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
   if (!act[c]) return;
-  const ColSt& q = st[c];
-  P[t] = c_add(R[t], c_mul(q.beta, c_sub(P[t], c_mul(q.omega, V[t]))));
+  const long long r0 = (long long)blockIdx.y * S.rows;
+  const long long r1 = r0 + S.rows < S.n ? r0 + S.rows : S.n;
+  const double2 be = st[c].beta, om = st[c].omega;
+  for (long long gi = r0 + wv; gi < r1; gi += 4) {
+    const size_t o = (size_t)gi * S.ld + c;
+    P[o] = c_add(R[o], c_mul(be, c_sub(P[o], c_mul(om, V[o]))));
+  }
 }
 
-// R = R - alpha V (s overwrites r) for iterating columns.
+// R = R - alpha V (s overwrites r) for iterating columns (grid as k_mk_p).
 __global__ __launch_bounds__(256) void k_mk_s(Shape S, const ColSt* st, const int* act, double2* R, const double2* V) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= S.n * S.ld) return;
-  const int c = (int)(t % S.ld);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
   if (!act[c]) return;
-  R[t] = c_sub(R[t], c_mul(st[c].alpha, V[t]));
+  const long long r0 = (long long)blockIdx.y * S.rows;
+  const long long r1 = r0 + S.rows < S.n ? r0 + S.rows : S.n;
+  const double2 al = st[c].alpha;
+  for (long long gi = r0 + wv; gi < r1; gi += 4) {
+    const size_t o = (size_t)gi * S.ld + c;
+    R[o] = c_sub(R[o], c_mul(al, V[o]));
+  }
 }
 
 // Partial (U0, V0) and, with NDOT = 2, (U1, V1) over iterating columns.
@@ -341,8 +352,10 @@ __global__ __launch_bounds__(64) void k_mk_scalar(Shape S, int step, ColSt* st, 
 struct DftPass {
   const double2* in;
   double2* out;
-  const double2* w;    // [N]
+  const double2* w;    // [N] (direct evaluation)
   const double2* post; // [N]
+  const double2* pre;  // [N] (factored evaluation): pre[i] = (w[j] / root^j)^i, the twist
+  const double2* root; // [N] (factored evaluation): root^m, root = w[1] / w[0]
   const int* act;      // [ld] columns to transform (others untouched); nullable = all
   int N;               // points along the axis
   int stride;          // grid-index stride along the axis
@@ -396,6 +409,87 @@ __global__ __launch_bounds__(256) void k_mk_dft(DftPass D) {
     for (int r = 0; r < RW; ++r) {
       const int j = jb + wv + 4 * r;
       if (j < N) D.out[(size_t)(base + (long long)j * D.stride) * D.ld + c] = c_mul(tp[j], acc[r]);
+    }
+  }
+}
+
+// The same pass factored (Cooley-Tukey, one twiddle stage) for N = N1 N2, where
+// w[j] = w[0] root^j with root an N-th root of unity: then w[j]^i = pre[i] root^(ij)
+// with pre[i] = w[0]^i, and with i = N2 n1 + n2 (n1 < N1, n2 < N2), j = k1 + N1 k2,
+//   Y[k1][n2]      = root^(n2 k1) sum_n1 pre[i] in[i] root^(N2 n1 k1)   (N2 transforms of length N1)
+//   out[k1 + N1 k2] = post[j] sum_n2 Y[k1][n2] root^(N1 n2 k2)          (N1 transforms of length N2)
+// N1 + N2 + 2 complex products per point instead of N.  The first stage reads its
+// inputs straight from global memory (all of a wave's rows requested before the
+// first is used) and leaves Y[k1][n2] in LDS slot N2 k1 + n2; after one barrier
+// the second stage reads N2 consecutive slots and writes the outputs.  Workgroup:
+// one (line, 64-column chunk), NW waves; wave q takes n2 = q, q + NW, ... in the
+// first stage and k1 = q, q + NW, ... in the second.  MINW: waves per SIMD asked of
+// the register allocator.
+template <int N1, int N2, int NW, int MINW>
+__global__ __launch_bounds__(64 * NW, MINW) void k_mk_fft(DftPass D) {
+  constexpr int N = N1 * N2;
+  __shared__ double2 ys[N * 64];
+  __shared__ double2 troot[N], tpre[N], tpost[N];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nchunk = D.ld / 64;
+  const long long line = blockIdx.x / nchunk;
+  const int chunk = (int)(blockIdx.x % nchunk);
+  const int c = chunk * 64 + lane;
+  const int z = (int)(line / D.nline_inner), li = (int)(line % D.nline_inner);
+  const long long base = (long long)z * D.P + (long long)li * D.inner_mul;
+  const bool on = D.act == nullptr || D.act[c];
+  for (int i = threadIdx.x; i < N; i += 64 * NW) {
+    troot[i] = D.root[i];
+    tpre[i] = D.pre[i];
+    tpost[i] = D.post[i];
+  }
+  __syncthreads();
+  constexpr int G1 = (N2 + NW - 1) / NW;  // first-stage transforms per wave
+  double2 v[G1][N1];
+#pragma unroll
+  for (int g = 0; g < G1; ++g) {
+    const int n2 = wv + g * NW;
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1)
+      v[g][n1] = on && n2 < N2 ? D.in[(size_t)(base + (long long)(N2 * n1 + n2) * D.stride) * D.ld + c]
+                               : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int g = 0; g < G1; ++g) {
+    const int n2 = wv + g * NW;
+    if (n2 >= N2) break;
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) v[g][n1] = c_mul(v[g][n1], tpre[N2 * n1 + n2]);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      double2 acc = v[g][0];
+#pragma unroll
+      for (int n1 = 1; n1 < N1; ++n1) {
+        const double2 r = troot[(N2 * n1 * k1) % N];
+        acc.x = fma(v[g][n1].x, r.x, fma(-v[g][n1].y, r.y, acc.x));
+        acc.y = fma(v[g][n1].x, r.y, fma(v[g][n1].y, r.x, acc.y));
+      }
+      ys[(N2 * k1 + n2) * 64 + lane] = c_mul(acc, troot[(n2 * k1) % N]);
+    }
+  }
+  __syncthreads();
+  if (!on) return;
+  for (int k1 = wv; k1 < N1; k1 += NW) {
+    double2 u[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) u[n2] = ys[(N2 * k1 + n2) * 64 + lane];
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      double2 acc = u[0];
+#pragma unroll
+      for (int n2 = 1; n2 < N2; ++n2) {
+        const double2 r = troot[(N1 * n2 * k2) % N];
+        acc.x = fma(u[n2].x, r.x, fma(-u[n2].y, r.y, acc.x));
+        acc.y = fma(u[n2].x, r.y, fma(u[n2].y, r.x, acc.y));
+      }
+      const int j = k1 + N1 * k2;
+      D.out[(size_t)(base + (long long)j * D.stride) * D.ld + c] = c_mul(tpost[j], acc);
     }
   }
 }
@@ -477,29 +571,61 @@ __global__ __launch_bounds__(256) void k_mk_band_solve(double2* io, double2* W, 
   double2 win[RM];  // win[k-1] = y_{z-k} (forward), x_{z+k} (backward)
 #pragma unroll
   for (int k = 0; k < RM; ++k) win[k] = make_double2(0.0, 0.0);
-  size_t o = (size_t)m * ld + c;
-  for (int z = 0; z < nz; ++z, o += zs) {
-    const double2* Lr = L + ((size_t)z * P + m) * RM;
-    double2 y = io[o];
+  // both sweeps go BZ planes at a time, the block's loads (vector rows, factor rows, pivots)
+  // requested before the first is used
+  constexpr int BZ = 4;
+  const size_t o0 = (size_t)m * ld + c;
+  for (int zb = 0; zb < nz; zb += BZ) {
+    double2 xin[BZ], dv[BZ], Lz[BZ][RM];
 #pragma unroll
-    for (int k = 1; k <= RM; ++k) y = c_sub(y, c_mul(Lr[k - 1], win[k - 1]));
+    for (int q = 0; q < BZ; ++q) {
+      const int z = zb + q < nz ? zb + q : nz - 1;
+      xin[q] = io[o0 + (size_t)z * zs];
+      dv[q] = di[(size_t)z * P + m];
 #pragma unroll
-    for (int k = RM - 1; k >= 1; --k) win[k] = win[k - 1];
-    win[0] = y;
-    W[o] = c_mul(y, di[(size_t)z * P + m]);
+      for (int k = 0; k < RM; ++k) Lz[q][k] = L[((size_t)z * P + m) * RM + k];
+    }
+#pragma unroll
+    for (int q = 0; q < BZ; ++q) {
+      if (zb + q >= nz) break;
+      double2 y = xin[q];
+#pragma unroll
+      for (int k = 1; k <= RM; ++k) y = c_sub(y, c_mul(Lz[q][k - 1], win[k - 1]));
+#pragma unroll
+      for (int k = RM - 1; k >= 1; --k) win[k] = win[k - 1];
+      win[0] = y;
+      W[o0 + (size_t)(zb + q) * zs] = c_mul(y, dv[q]);
+    }
   }
 #pragma unroll
   for (int k = 0; k < RM; ++k) win[k] = make_double2(0.0, 0.0);
-  for (int z = nz - 1; z >= 0; --z) {
-    o -= zs;
-    double2 x = W[o];
+  // backward: x_z = W_z - sum_j L[z+j][j] x_{z+j}; the block z = zt, zt-1, ..., zt-BZ+1 needs the
+  // factor rows z+1 .. z+RM, i.e. rows zt-BZ+2 .. zt+RM (clamped; entries past nz-1 unused)
+  for (int zt = nz - 1; zt >= 0; zt -= BZ) {
+    double2 w[BZ], Lz[BZ][RM];
 #pragma unroll
-    for (int j = 1; j <= RM; ++j)
-      if (z + j < nz) x = c_sub(x, c_mul(L[((size_t)(z + j) * P + m) * RM + (j - 1)], win[j - 1]));
+    for (int q = 0; q < BZ; ++q) {
+      const int z = zt - q >= 0 ? zt - q : 0;
+      w[q] = W[o0 + (size_t)z * zs];
 #pragma unroll
-    for (int k = RM - 1; k >= 1; --k) win[k] = win[k - 1];
-    win[0] = x;
-    io[o] = x;
+      for (int j = 1; j <= RM; ++j) {
+        const int zr = z + j < nz ? z + j : nz - 1;
+        Lz[q][j - 1] = L[((size_t)zr * P + m) * RM + (j - 1)];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < BZ; ++q) {
+      const int z = zt - q;
+      if (z < 0) break;
+      double2 x = w[q];
+#pragma unroll
+      for (int j = 1; j <= RM; ++j)
+        if (z + j < nz) x = c_sub(x, c_mul(Lz[q][j - 1], win[j - 1]));
+#pragma unroll
+      for (int k = RM - 1; k >= 1; --k) win[k] = win[k - 1];
+      win[0] = x;
+      io[o0 + (size_t)z * zs] = x;
+    }
   }
 }
 

@@ -88,6 +88,22 @@ def test_apply_many_columns_matches_oracle(order, nproj, prec):
     _apply_vs_oracle(torch, ctx, p, k, 0.413, x, xd, prec)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_wide_plane_strips_matches_oracle(prec):
+    """A 29x23 plane (667 points: wider than one XCD's waves in flight, so the
+    points go in strips of 6 a-columns and a ragged strip of 5) with 600
+    columns (ten 64-column chunks: eight (chunk, segment) groups per XCD run and
+    a remainder) over 21 planes (segments of 16 and 5): every output against
+    the oracle."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(31)
+    p = hp.random_problem(rng, na=29, nb=23, nz=21, order=12, nproj=5, ramp=4)
+    k = (0.27, -0.44)
+    ctx = make_ctx(torch, p, k)
+    x, xd = rand_block(torch, p.n, 600, 8)
+    _apply_vs_oracle(torch, ctx, p, k, 0.377, x, xd, prec)
+
+
 def test_apply_precision_argument():
     """An unknown precision is refused; both precisions accept zero columns."""
     torch = torch_cuda()
