@@ -99,7 +99,13 @@ typedef struct {
                         updates, Sleijpen and van der Vorst 1996); convergence is decided on the FP64
                         true residual.  A column whose best FP64 residual has not fallen tenfold over
                         30 replacements, or that ran 1000 FP32 iterations without a replacement, is
-                        solved again in FP64 (stats.fallback_columns) */
+                        solved again in FP64 (stats.fallback_columns).  With RST_IDRS (and wide planes
+                        under RST_BICGSTAB): FP64 iterative refinement, x += d where d comes from an
+                        IDR(s) run on complex64 vectors (FP64 arithmetic, FP32 stencil) for the current
+                        FP64 residual r = b - A x to the relative tolerance update_delta; stats
+                        updates_total counts the cycles, iterations_total all inner applies.  A column
+                        ends unconverged when three cycles in a row fail to halve its FP64 residual.
+                        RST_BICGSTAB_MC refuses it (RST_EUNSUPPORTED) */
   double tol;        /* stop when the FP64 true residual ||b - A x|| <= tol ||b|| per column (default 1e-10) */
   int max_iter;      /* BiCGSTAB iterations per column (default 20000) */
   int col_block;     /* columns solved together by one workgroup; 0 = automatic (FGMRES and COCG: 1) */
@@ -107,7 +113,9 @@ typedef struct {
   int direction;     /* RST_DIR_LR: columns in the right CAP, T accumulated on the left (default);
                         RST_DIR_RL: the reverse.  Both give the same T (exact identity). */
   double update_delta; /* RST_FP32_REFINE: the residual is replaced once its norm is below update_delta
-                          times the largest since the last replacement (default 0.1, in (0, 1)) */
+                          times the largest since the last replacement (default 0.1, in (0, 1)); under
+                          RST_IDRS the relative tolerance of each complex64 correction solve (values
+                          near 1e-4 to 1e-5 take the fewest cycles) */
   int precond;       /* rst_precond.  RST_PRECOND_FREE_CAP: right preconditioner
                         M = E - (-1/2 L_lat - 1/2 D2_z + Vref(z)) + i Gamma(z) with the exact
                         lateral FD Laplacian (diagonal in the twisted lateral Fourier basis),

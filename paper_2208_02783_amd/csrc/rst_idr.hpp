@@ -37,6 +37,8 @@ using mk::c_mul;
 using mk::c_mulc;
 using mk::c_div;
 using mk::c_finite;
+using mk::vld;
+using mk::vst;
 
 constexpr int SMAX = 8;
 
@@ -55,9 +57,9 @@ enum IdrStep { ID_INIT = 0, ID_C = 1, ID_D = 2, ID_CONV = 3, ID_OMEGA = 4, ID_EN
 // Partials of the s products (P_j, y) (conj(P_j) y) for j < s, stored as products
 // 1..s of the partial array (product 0 is left to the caller); with NORM also
 // ||y||^2 as product 0.
-template <bool NORM>
+template <bool NORM, class VT = double2>
 __global__ __launch_bounds__(256) void k_idr_pdots(Shape S, int s, const int* act, const double2* Pm,
-                                                   const double2* Y, double2* part) {
+                                                   const VT* Y, double2* part) {
   __shared__ double2 red[SMAX + 1][4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + lane;
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(256) void k_idr_pdots(Shape S, int s, const int* ac
   for (int d = 0; d <= SMAX; ++d) acc[d] = make_double2(0.0, 0.0);
   if (act == nullptr || act[c]) {
     for (long long gi = r0 + wv; gi < r1; gi += 4) {
-      const double2 y = Y[(size_t)gi * S.ld + c];
+      const double2 y = vld(Y, (size_t)gi * S.ld + c);
       if (NORM) acc[0].x += y.x * y.x + y.y * y.y;
 #pragma unroll
       for (int j = 0; j < SMAX; ++j)
@@ -90,30 +92,32 @@ __global__ __launch_bounds__(256) void k_idr_pdots(Shape S, int s, const int* ac
 }
 
 // X = 0, R = b; G_i = U_i = 0 (all columns).
-__global__ __launch_bounds__(256) void k_idr_init(Shape S, int s, mk::Rhs B, double2* X, double2* R, double2* G,
-                                                  double2* U) {
+template <class VT = double2>
+__global__ __launch_bounds__(256) void k_idr_init(Shape S, int s, mk::Rhs B, VT* X, VT* R, VT* G, VT* U) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long vlen = S.n * S.ld;
   if (t >= vlen) return;
   const int c = (int)(t % S.ld);
   const long long gi = t / S.ld;
-  X[t] = make_double2(0.0, 0.0);
-  R[t] = mk::rhs_at(B, gi, c);
+  const double2 z = make_double2(0.0, 0.0);
+  vst(X, t, z);
+  vst(R, t, mk::rhs_at(B, gi, c));
   for (int i = 0; i < s; ++i) {
-    G[i * vlen + t] = make_double2(0.0, 0.0);
-    U[i * vlen + t] = make_double2(0.0, 0.0);
+    vst(G, i * vlen + t, z);
+    vst(U, i * vlen + t, z);
   }
 }
 
 // G_i = U_i = 0 for the marked columns (restart).
-__global__ __launch_bounds__(256) void k_idr_zero(Shape S, int s, const int* mark, double2* G, double2* U) {
+template <class VT = double2>
+__global__ __launch_bounds__(256) void k_idr_zero(Shape S, int s, const int* mark, VT* G, VT* U) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long vlen = S.n * S.ld;
   if (t >= vlen) return;
   if (!mark[(int)(t % S.ld)]) return;
   for (int i = 0; i < s; ++i) {
-    G[i * vlen + t] = make_double2(0.0, 0.0);
-    U[i * vlen + t] = make_double2(0.0, 0.0);
+    vst(G, i * vlen + t, make_double2(0.0, 0.0));
+    vst(U, i * vlen + t, make_double2(0.0, 0.0));
   }
 }
 
@@ -122,8 +126,9 @@ __global__ __launch_bounds__(256) void k_idr_zero(Shape S, int s, const int* mar
 // registers; columns that are not iterating are left untouched.
 
 // V = R - sum_{i=k}^{s-1} c_i G_i.
-__global__ __launch_bounds__(256) void k_idr_v(Shape S, int s, int k, const IdrSt* st, const int* act,
-                                               const double2* R, const double2* G, double2* V) {
+template <class VT = double2>
+__global__ __launch_bounds__(256) void k_idr_v(Shape S, int s, int k, const IdrSt* st, const int* act, const VT* R,
+                                               const VT* G, VT* V) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + lane;
   if (!act[c]) return;
@@ -135,17 +140,18 @@ __global__ __launch_bounds__(256) void k_idr_v(Shape S, int s, int k, const IdrS
   for (int i = 0; i < SMAX; ++i) cf[i] = i >= k && i < s ? st[c].c[i] : make_double2(0.0, 0.0);
   for (long long gi = r0 + wv; gi < r1; gi += 4) {
     const size_t o = (size_t)gi * S.ld + c;
-    double2 v = R[o];
+    double2 v = vld(R, o);
 #pragma unroll
     for (int i = 0; i < SMAX; ++i)
-      if (i >= k && i < s) v = c_sub(v, c_mul(cf[i], G[i * vlen + o]));
-    V[o] = v;
+      if (i >= k && i < s) v = c_sub(v, c_mul(cf[i], vld(G, i * vlen + o)));
+    vst(V, o, v);
   }
 }
 
 // U_k = sum_{i=k}^{s-1} c_i U_i + omega VH.
-__global__ __launch_bounds__(256) void k_idr_u(Shape S, int s, int k, const IdrSt* st, const int* act,
-                                               const double2* VH, double2* U) {
+template <class VT = double2>
+__global__ __launch_bounds__(256) void k_idr_u(Shape S, int s, int k, const IdrSt* st, const int* act, const VT* VH,
+                                               VT* U) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + lane;
   if (!act[c]) return;
@@ -158,18 +164,19 @@ __global__ __launch_bounds__(256) void k_idr_u(Shape S, int s, int k, const IdrS
   const double2 om = st[c].omega;
   for (long long gi = r0 + wv; gi < r1; gi += 4) {
     const size_t o = (size_t)gi * S.ld + c;
-    double2 u = c_mul(om, VH[o]);
+    double2 u = c_mul(om, vld(VH, o));
 #pragma unroll
     for (int i = 0; i < SMAX; ++i)
-      if (i >= k && i < s) u = c_add(u, c_mul(cf[i], U[i * vlen + o]));
-    U[k * vlen + o] = u;
+      if (i >= k && i < s) u = c_add(u, c_mul(cf[i], vld(U, i * vlen + o)));
+    vst(U, k * vlen + o, u);
   }
 }
 
 // G_k -= sum_{i<k} alpha_i G_i;  U_k -= sum_{i<k} alpha_i U_i;  R -= beta G_k;  X += beta U_k;
 // partial ||R||^2 (product 0).
-__global__ __launch_bounds__(256) void k_idr_upd(Shape S, int k, const IdrSt* st, const int* act, double2* G,
-                                                 double2* U, double2* R, double2* X, double2* part) {
+template <class VT = double2>
+__global__ __launch_bounds__(256) void k_idr_upd(Shape S, int k, const IdrSt* st, const int* act, VT* G, VT* U, VT* R,
+                                                 VT* X, double2* part) {
   __shared__ double2 red[4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + lane;
@@ -182,16 +189,16 @@ __global__ __launch_bounds__(256) void k_idr_upd(Shape S, int k, const IdrSt* st
     const double2 be = q.beta;
     for (long long gi = r0 + wv; gi < r1; gi += 4) {
       const size_t o = (size_t)gi * S.ld + c;
-      double2 g = G[k * vlen + o], u = U[k * vlen + o];
+      double2 g = vld(G, k * vlen + o), u = vld(U, k * vlen + o);
       for (int i = 0; i < k; ++i) {
-        g = c_sub(g, c_mul(q.al[i], G[i * vlen + o]));
-        u = c_sub(u, c_mul(q.al[i], U[i * vlen + o]));
+        g = c_sub(g, c_mul(q.al[i], vld(G, i * vlen + o)));
+        u = c_sub(u, c_mul(q.al[i], vld(U, i * vlen + o)));
       }
-      G[k * vlen + o] = g;
-      U[k * vlen + o] = u;
-      const double2 r = c_sub(R[o], c_mul(be, g));
-      R[o] = r;
-      X[o] = c_add(X[o], c_mul(be, u));
+      vst(G, k * vlen + o, g);
+      vst(U, k * vlen + o, u);
+      const double2 r = c_sub(vld(R, o), c_mul(be, g));
+      vst(R, o, r);
+      vst(X, o, c_add(vld(X, o), c_mul(be, u)));
       rr += r.x * r.x + r.y * r.y;
     }
   }
@@ -208,9 +215,9 @@ __global__ __launch_bounds__(256) void k_idr_upd(Shape S, int k, const IdrSt* st
 
 // R -= omega T;  X += omega VH  (dimension-reduction step), with the partials of
 // ||R||^2 (product 0) and P^H R (products 1..s) of the new residual, as k_idr_pdots<true>.
-__global__ __launch_bounds__(256) void k_idr_rx(Shape S, int s, const IdrSt* st, const int* act, double2* R,
-                                                double2* X, const double2* T, const double2* VH, const double2* Pm,
-                                                double2* part) {
+template <class VT = double2>
+__global__ __launch_bounds__(256) void k_idr_rx(Shape S, int s, const IdrSt* st, const int* act, VT* R, VT* X,
+                                                const VT* T, const VT* VH, const double2* Pm, double2* part) {
   __shared__ double2 red[SMAX + 1][4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + lane;
@@ -223,10 +230,10 @@ __global__ __launch_bounds__(256) void k_idr_rx(Shape S, int s, const IdrSt* st,
     const double2 om = st[c].omega;
     for (long long gi = r0 + wv; gi < r1; gi += 4) {
       const size_t o = (size_t)gi * S.ld + c;
-      const double2 vh = VH[o];  // read before R is written: VH may be R itself (no preconditioner)
-      const double2 r = c_sub(R[o], c_mul(om, T[o]));
-      R[o] = r;
-      X[o] = c_add(X[o], c_mul(om, vh));
+      const double2 vh = vld(VH, o);  // read before R is written: VH may be R itself (no preconditioner)
+      const double2 r = c_sub(vld(R, o), c_mul(om, vld(T, o)));
+      vst(R, o, r);
+      vst(X, o, c_add(vld(X, o), c_mul(om, vh)));
       acc[0].x += r.x * r.x + r.y * r.y;
 #pragma unroll
       for (int j = 0; j < SMAX; ++j)
@@ -261,9 +268,12 @@ __global__ __launch_bounds__(256) void k_idr_rx(Shape S, int s, const IdrSt* st,
 //              smallest rr since the last restart.
 //  ID_OMEGA  : omega = (t, r)/(t, t) from products 0 and 1, enlarged to an angle of 0.7.
 //  ID_END    : as ID_CONV with f = P^H r (products 1..s).
+// cap (nullable): per-column iteration limits in place of max_iter.
 __global__ __launch_bounds__(64) void k_idr_scalar(Shape S, int step, int s, int k, IdrSt* st, int* act,
-                                                   const int* mark, const double2* part, double tol, int max_iter) {
+                                                   const int* mark, const double2* part, double tol, int max_iter,
+                                                   const int* cap) {
   const int c = blockIdx.x;
+  if (cap != nullptr) max_iter = cap[c];  // per-column iteration budget (inner solves of the refinement)
   if (step == ID_RESTART) {
     if (!mark[c]) return;
   } else if (step != ID_INIT && !act[c]) {

@@ -137,6 +137,8 @@ struct rst_ctx {
   DevBuf d_lrB, d_lrX, d_lrY, d_lrQ, d_lrQ2, d_lrG, d_lrR, d_lrW, d_lrL, d_lrRc, d_lrT, d_lrYacc, d_lrYacc2, d_lrQf;
   // eigen route: subspace blocks, Ritz vectors, small matrices
   DevBuf d_egQ, d_egY, d_egW, d_egX, d_egKX, d_egS, d_egG, d_egR, d_egRm, d_egL, d_egTh, d_egRes, d_egMap, d_egSc;
+  // many-column solvers, mixed mode: FP64 x and r; per-column right-hand-side offsets and budgets
+  DevBuf d_mkv64, d_mkref;
   // solver
   rst_solver_opts opts;
   // work buffers (grown on demand)
@@ -1412,25 +1414,31 @@ double mk_bytes_per_point(bool pc) { return pc ? 752.0 : 368.0; }
 // a cycle of s + 1 applies: step k reads r and g_k..g_{s-1} and writes v (s - k + 2 streams), forms
 // u_k from u_k..u_{s-1} and M^-1 v (s - k + 2), applies M^-1 (12) and A (2), the dots read g_k (1),
 // the update reads and writes g_k, u_k, r, x and reads g_0..g_{k-1}, u_0..u_{k-1} (2k + 8); the
-// dimension-reduction step costs M^-1, A, the two dots (2), the r/x update (5) and the dots with P (1).
+// dimension-reduction step costs M^-1, A, the two dots (2) and the r/x update with the dots with P (5).
 // 16 B per stream.
 double idr_bytes_per_matvec(int s, bool pc) {
   const double mpc = pc ? 12.0 : 0.0;
   double streams = 0.0;
   for (int k = 0; k < s; ++k) streams += (s - k + 2) + (s - k + 2) + mpc + 2 + 1 + (2 * k + 8);
-  streams += mpc + 2 + 2 + 5 + 1;
+  streams += mpc + 2 + 2 + 5;
   return 16.0 * streams / (s + 1);
 }
 
-// Many-column right-preconditioned BiCGSTAB (rst_mk.hpp) over the (energy, column) items, in blocks
-// of up to `ld` columns with one kernel per step; same inputs and outputs as the persistent solver.
 // Factored lateral DFT instances (k_mk_fft<N1, N2, NW>, N = N1 N2); other N use the direct
 // evaluation (k_mk_dft).
 struct FftInstance {
   const void* kern;
   int nw;
 };
-FftInstance fft_instance(int N) {
+FftInstance fft_instance(int N, bool f32) {
+  if (f32) {
+    switch (N) {
+      case 8: return {(const void*)rst::mk::k_mk_fft<2, 4, 2, 1, float2>, 2};
+      case 16: return {(const void*)rst::mk::k_mk_fft<4, 4, 4, 1, float2>, 4};
+      case 54: return {(const void*)rst::mk::k_mk_fft<6, 9, 3, 1, float2>, 3};
+      default: return {nullptr, 0};
+    }
+  }
   switch (N) {
     case 8: return {(const void*)rst::mk::k_mk_fft<2, 4, 2, 1>, 2};
     case 12: return {(const void*)rst::mk::k_mk_fft<3, 4, 2, 1>, 2};
@@ -1447,13 +1455,16 @@ FftInstance fft_instance(int N) {
   }
 }
 
+// Many-column right-preconditioned BiCGSTAB and IDR(s) (rst_mk.hpp, rst_idr.hpp) over the (energy,
+// column) items, in blocks of up to `ld` columns with one kernel per step; same inputs and outputs as
+// the persistent solver.  RST_FP32_REFINE (IDR(s) only): FP64 iterative refinement, x += d with d
+// from an IDR(s) run on complex64 vectors (FP64 arithmetic, the complex64 operator apply) for the
+// current FP64 residual r = b - A x, until the FP64 true residual meets the tolerance.
 rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std::vector<int64_t>& cols,
                            const double* d_gsrc, const double* d_gdst, double2* xout, std::vector<double>& Tcol,
                            std::vector<int>& its, std::vector<int>& rss, std::vector<double>& res,
                            std::vector<int>& st, double& ms, const double2* rhs, long long rhs_ld,
                            long long rhs_estride) {
-  if (c->opts.precision != RST_FP64)
-    return fail(c, RST_EUNSUPPORTED, "the many-column solvers run in FP64 only");
   const bool pc = c->opts.precond == RST_PRECOND_FREE_CAP;
   const int na = c->na, nb = c->nb, nz = c->nz, P = na * nb;
   const long long n = (long long)P * nz;
@@ -1465,12 +1476,17 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
   // IDR(s) for RST_IDRS and for wide planes under RST_BICGSTAB (the method that converges on them)
   const bool idr = c->opts.method == RST_IDRS || (c->opts.method == RST_BICGSTAB && P > 2 * rst::MAX_T);
   const int sdim = idr ? c->opts.idr_s : 0;
+  const bool mixed = c->opts.precision == RST_FP32_REFINE;
+  if (mixed && !idr)
+    return fail(c, RST_EUNSUPPORTED, "the many-column BiCGSTAB runs in FP64 only (mixed precision: RST_IDRS)");
   // block width: vectors X R R0 P V T (+ PH SH W with the preconditioner); IDR(s): X R V T G_0..G_{s-1}
-  // U_0..U_{s-1} (+ VH W); at most a quarter of free memory
+  // U_0..U_{s-1} (+ VH W), complex64 in the mixed mode, which adds the FP64 x and r; at most a quarter
+  // of free memory
   const int nvec = idr ? (4 + 2 * sdim + (pc ? 2 : 0)) : (pc ? 9 : 6);
+  const size_t esz = mixed ? 8 : 16;
   size_t free_b = 0, total_b = 0;
   HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
-  const size_t per_col = (size_t)nvec * n * 16 + (size_t)c->nproj * 16;
+  const size_t per_col = (size_t)nvec * n * esz + (mixed ? (size_t)2 * n * 16 : 0) + (size_t)c->nproj * 16;
   long long ldmax = std::max<long long>(64, (long long)(free_b / 4 / per_col) / 64 * 64);
   ldmax = std::min<long long>(ldmax, 1024);
   const int ld = (int)std::min<long long>(ldmax, (nitems + 63) / 64 * 64);
@@ -1484,8 +1500,12 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
   S.rows = (n + S.nsplit - 1) / S.nsplit;
   const size_t vlen = (size_t)n * ld;
   rst_status e;
-  if ((e = ensure(c, c->d_mkv, (size_t)nvec * vlen * 16)) != RST_OK) return e;
-  double2* X = (double2*)c->d_mkv.p;
+  if ((e = ensure(c, c->d_mkv, (size_t)nvec * vlen * esz)) != RST_OK) return e;
+  if (mixed && (e = ensure(c, c->d_mkv64, (size_t)2 * vlen * 16)) != RST_OK) return e;
+  double2* X = (double2*)c->d_mkv.p;  // the FP64 vectors (BiCGSTAB; IDR(s) in FP64 lays them out itself)
+  double2* X64 = mixed ? (double2*)c->d_mkv64.p : nullptr;  // mixed mode: FP64 x and r
+  double2* R64 = mixed ? X64 + vlen : nullptr;
+  const double2* Xres = mixed ? X64 : X;  // the block's solutions
   double2* R = X + vlen;
   double2* R0 = R + vlen;  // BiCGSTAB: shadow residual; IDR(s): v
   double2* Pv = R0 + vlen; // BiCGSTAB: p; IDR(s): t
@@ -1614,7 +1634,13 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     band_dinv = Bd.dinv;
   }
   // direct evaluation: the smallest instance with 4*RW >= N (N > 64 takes several rounds of 64)
-  auto dft_kernel = [](int N) -> const void* {
+  auto dft_kernel = [](int N, bool f32) -> const void* {
+    if (f32) {
+      if (N <= 8) return (const void*)rst::mk::k_mk_dft<2, float2>;
+      if (N <= 16) return (const void*)rst::mk::k_mk_dft<4, float2>;
+      if (N <= 32) return (const void*)rst::mk::k_mk_dft<8, float2>;
+      return (const void*)rst::mk::k_mk_dft<16, float2>;
+    }
     if (N <= 8) return (const void*)rst::mk::k_mk_dft<2>;
     if (N <= 16) return (const void*)rst::mk::k_mk_dft<4>;
     if (N <= 32) return (const void*)rst::mk::k_mk_dft<8>;
@@ -1622,10 +1648,14 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
   };
   auto dft_lds = [](int N) -> size_t { return ((size_t)N * 64 + 2 * (size_t)N) * 16; };
   for (int N : {na, nb})
-    if (!fft_instance(N).kern && dft_lds(N) > 64 * 1024)
-      HIPCHK(c, hipFuncSetAttribute(dft_kernel(N), hipFuncAttributeMaxDynamicSharedMemorySize, (int)dft_lds(N)));
-  // out = the DFT pass of `in` for the columns of `mask` (factored where N has an instance)
-  auto dft = [&](const double2* in, double2* out, const DftTabs& tb, bool axis_a, const int* mask) -> rst_status {
+    for (bool f32 : {false, true})
+      if (!fft_instance(N, f32).kern && dft_lds(N) > 64 * 1024)
+        HIPCHK(c, hipFuncSetAttribute(dft_kernel(N, f32), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)dft_lds(N)));
+  // out = the DFT pass of `in` for the columns of `mask` (factored where N has an instance); f32:
+  // complex64 vectors
+  auto dft = [&](const void* in, void* out, const DftTabs& tb, bool axis_a, const int* mask,
+                 bool f32) -> rst_status {
     rst::mk::DftPass D;
     D.in = in;
     D.out = out;
@@ -1643,30 +1673,43 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     D.ld = ld;
     const long long nwg = (long long)nz * D.nline_inner * (ld / 64);
     void* args[] = {&D};
-    const FftInstance fi = fft_instance(D.N);
+    const FftInstance fi = fft_instance(D.N, f32);
     if (fi.kern)
       HIPCHK(c, hipLaunchKernel(fi.kern, dim3((unsigned)nwg), dim3(64 * fi.nw), args, 0, c->stream));
     else
-      HIPCHK(c, hipLaunchKernel(dft_kernel(D.N), dim3((unsigned)nwg), dim3(256), args, dft_lds(D.N), c->stream));
+      HIPCHK(c, hipLaunchKernel(dft_kernel(D.N, f32), dim3((unsigned)nwg), dim3(256), args, dft_lds(D.N),
+                                c->stream));
     return RST_OK;
   };
-  auto precondition = [&](const double2* in, double2* out, const int* mask) -> rst_status {
+  // out = M^-1 in (Wp: a work vector of the same type)
+  auto precondition = [&](const void* in, void* out, void* Wp, const int* mask, bool f32) -> rst_status {
     rst_status ps;
-    if ((ps = dft(in, W, FA, true, mask)) != RST_OK) return ps;
-    if ((ps = dft(W, out, FB, false, mask)) != RST_OK) return ps;
+    if ((ps = dft(in, Wp, FA, true, mask, f32)) != RST_OK) return ps;
+    if ((ps = dft(Wp, out, FB, false, mask, f32)) != RST_OK) return ps;
     const long long nt = (long long)P * ld;
-    if (c->rad == 6)
-      hipLaunchKernelGGL(rst::mk::k_mk_band_solve<6>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
-                         out, W, band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
-    else
-      hipLaunchKernelGGL(rst::mk::k_mk_band_solve<2>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
-                         out, W, band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
+    const dim3 gb((unsigned)((nt + 255) / 256));
+    if (f32) {
+      if (c->rad == 6)
+        hipLaunchKernelGGL((rst::mk::k_mk_band_solve<6, float2>), gb, dim3(256), 0, c->stream, (float2*)out,
+                           (float2*)Wp, band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
+      else
+        hipLaunchKernelGGL((rst::mk::k_mk_band_solve<2, float2>), gb, dim3(256), 0, c->stream, (float2*)out,
+                           (float2*)Wp, band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
+    } else {
+      if (c->rad == 6)
+        hipLaunchKernelGGL(rst::mk::k_mk_band_solve<6>, gb, dim3(256), 0, c->stream, (double2*)out, (double2*)Wp,
+                           band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
+      else
+        hipLaunchKernelGGL(rst::mk::k_mk_band_solve<2>, gb, dim3(256), 0, c->stream, (double2*)out, (double2*)Wp,
+                           band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
+    }
     HIPCHK(c, hipGetLastError());
-    if ((ps = dft(out, W, IB, false, mask)) != RST_OK) return ps;
-    return dft(W, out, IA, true, mask);
+    if ((ps = dft(out, Wp, IB, false, mask, f32)) != RST_OK) return ps;
+    return dft(Wp, out, IA, true, mask, f32);
   };
-  auto apply = [&](const double2* x, double2* y, const int* mask) -> rst_status {
-    return apply_cols(c, x, y, ld, 0.0, d_ecol, mask, false, (double2*)c->d_projP.p, nullptr);
+  // y = A x on the block (f32: complex64 vectors, the FP32 stencil)
+  auto apply = [&](const void* x, void* y, const int* mask, bool f32) -> rst_status {
+    return apply_cols(c, x, y, ld, 0.0, d_ecol, mask, f32, (double2*)c->d_projP.p, nullptr);
   };
   const dim3 gred((unsigned)(ld / 64), (unsigned)S.nsplit);
   const unsigned gsc = (unsigned)ld;  // one wavefront per column in the scalar and sum kernels
@@ -1684,6 +1727,7 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
   res.assign(nout, 0.0);
   st.assign(nout, 1);
   c->last_updates.clear();
+  if (mixed) c->last_updates.assign((size_t)nitems, 0);  // refinement cycles per item
   c->last_fallbacks = 0;
   c->last_cnn_flop = 0.0;
   long long nent = 0;
@@ -1723,7 +1767,7 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     HIPCHK(c, hipMemcpyAsync(d_doff, doff.data(), ld * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(d_eidx, eidx.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
     rst_status ps;
-    long long col_its = 0;
+    long long col_its = 0, col_cyc = 0;
     if (!idr) {
       hipLaunchKernelGGL(rst::mk::k_mk_init, gred, dim3(256), 0, c->stream, S, B, X, R, R0, Pv, part);
       HIPCHK(c, hipGetLastError());
@@ -1733,16 +1777,16 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
         if (iter > 0)
           hipLaunchKernelGGL(rst::mk::k_mk_p, gred, dim3(256), 0, c->stream, S, (const rst::mk::ColSt*)dst_,
                              (const int*)act, Pv, (const double2*)R, (const double2*)V);
-        if (pc && (ps = precondition(Pv, PH, act)) != RST_OK) return ps;
-        if ((ps = apply(PH, V, act)) != RST_OK) return ps;
+        if (pc && (ps = precondition(Pv, PH, W, act, false)) != RST_OK) return ps;
+        if ((ps = apply(PH, V, act, false)) != RST_OK) return ps;
         hipLaunchKernelGGL(rst::mk::k_mk_dots<1>, gred, dim3(256), 0, c->stream, S, (const int*)act,
                            (const double2*)R0, (const double2*)V, (const double2*)nullptr, (const double2*)nullptr,
                            part);
         if ((ps = scalar(rst::mk::SC_ALPHA)) != RST_OK) return ps;
         hipLaunchKernelGGL(rst::mk::k_mk_s, gred, dim3(256), 0, c->stream, S, (const rst::mk::ColSt*)dst_,
                            (const int*)act, R, (const double2*)V);
-        if (pc && (ps = precondition(R, SH, act)) != RST_OK) return ps;
-        if ((ps = apply(SH, T, act)) != RST_OK) return ps;
+        if (pc && (ps = precondition(R, SH, W, act, false)) != RST_OK) return ps;
+        if ((ps = apply(SH, T, act, false)) != RST_OK) return ps;
         hipLaunchKernelGGL(rst::mk::k_mk_dots<2>, gred, dim3(256), 0, c->stream, S, (const int*)act,
                            (const double2*)T, (const double2*)R, (const double2*)T, (const double2*)T, part);
         if ((ps = scalar(rst::mk::SC_OMEGA)) != RST_OK) return ps;
@@ -1763,7 +1807,7 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
         }
         if (nmark > 0) {
           HIPCHK(c, hipMemcpyAsync(mark, hmark.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
-          if ((ps = apply(X, Wres, mark)) != RST_OK) return ps;
+          if ((ps = apply(X, Wres, mark, false)) != RST_OK) return ps;
           hipLaunchKernelGGL(rst::mk::k_mk_resid, gred, dim3(256), 0, c->stream, S, B, (const int*)mark,
                              (const double2*)Wres, R, part);
           HIPCHK(c, hipGetLastError());
@@ -1813,124 +1857,225 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
         if (nact == 0) break;
       }
     } else {
-      // IDR(s) cycles: s steps of one apply each, then the dimension-reduction step
-      auto iscal = [&](int step, int k, const int* mk_) -> rst_status {
-        hipLaunchKernelGGL(rst::idr::k_idr_scalar, dim3((unsigned)ld), dim3(64), 0, c->stream, S, step, sdim, k, did,
-                           act, mk_, (const double2*)part, c->opts.tol, c->opts.max_iter);
-        HIPCHK(c, hipGetLastError());
-        return RST_OK;
-      };
-      double2* VH = pc ? PH : V;  // M^-1 v
-      hipLaunchKernelGGL(rst::idr::k_idr_init, dim3(gel), dim3(256), 0, c->stream, S, sdim, B, X, R, Gb, Ub);
-      hipLaunchKernelGGL(rst::idr::k_idr_pdots<true>, gred, dim3(256), 0, c->stream, S, sdim, (const int*)nullptr,
-                         Psh, (const double2*)R, part);
-      if ((ps = iscal(rst::idr::ID_INIT, 0, nullptr)) != RST_OK) return ps;
-      for (;;) {
-        for (int k = 0; k < sdim; ++k) {
-          double2* Gk = Gb + (size_t)k * vlen;
-          double2* Uk = Ub + (size_t)k * vlen;
-          if ((ps = iscal(rst::idr::ID_C, k, nullptr)) != RST_OK) return ps;
-          hipLaunchKernelGGL(rst::idr::k_idr_v, gred, dim3(256), 0, c->stream, S, sdim, k,
-                             (const rst::idr::IdrSt*)did, (const int*)act, (const double2*)R, (const double2*)Gb, V);
-          if (pc && (ps = precondition(V, PH, act)) != RST_OK) return ps;
-          hipLaunchKernelGGL(rst::idr::k_idr_u, gred, dim3(256), 0, c->stream, S, sdim, k,
-                             (const rst::idr::IdrSt*)did, (const int*)act, (const double2*)VH, Ub);
-          if ((ps = apply(Uk, Gk, act)) != RST_OK) return ps;
-          hipLaunchKernelGGL(rst::idr::k_idr_pdots<false>, gred, dim3(256), 0, c->stream, S, sdim, (const int*)act,
-                             Psh, (const double2*)Gk, part);
-          if ((ps = iscal(rst::idr::ID_D, k, nullptr)) != RST_OK) return ps;
-          hipLaunchKernelGGL(rst::idr::k_idr_upd, gred, dim3(256), 0, c->stream, S, k, (const rst::idr::IdrSt*)did,
-                             (const int*)act, Gb, Ub, R, X, part);
-          if ((ps = iscal(rst::idr::ID_CONV, k, nullptr)) != RST_OK) return ps;
-        }
-        // dimension reduction: v = M^-1 r, t = A v, omega from (t, r) and (t, t)
-        double2* vr = R;
-        if (pc) {
-          if ((ps = precondition(R, PH, act)) != RST_OK) return ps;
-          vr = PH;
-        }
-        if ((ps = apply(vr, T, act)) != RST_OK) return ps;
-        hipLaunchKernelGGL(rst::mk::k_mk_dots<2>, gred, dim3(256), 0, c->stream, S, (const int*)act,
-                           (const double2*)T, (const double2*)R, (const double2*)T, (const double2*)T, part);
-        if ((ps = iscal(rst::idr::ID_OMEGA, 0, nullptr)) != RST_OK) return ps;
-        hipLaunchKernelGGL(rst::idr::k_idr_rx, gred, dim3(256), 0, c->stream, S, sdim,
-                           (const rst::idr::IdrSt*)did, (const int*)act, R, X, (const double2*)T, (const double2*)vr,
-                           Psh, part);
-        if ((ps = iscal(rst::idr::ID_END, 0, nullptr)) != RST_OK) return ps;
-        HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipMemcpyAsync(hid.data(), did, ld * sizeof(rst::idr::IdrSt), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipMemcpyAsync(hact.data(), act, ld * 4, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        int nmark = 0, nact = 0;
-        for (int j = 0; j < ld; ++j) {
-          hmark[j] = (hid[j].done == 0 && !hact[j] && (hid[j].check || hid[j].brk)) ? 1 : 0;
-          nmark += hmark[j];
-          nact += hact[j];
-        }
-        if (nmark > 0) {
-          HIPCHK(c, hipMemcpyAsync(mark, hmark.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
-          if ((ps = apply(X, Wres, mark)) != RST_OK) return ps;
-          hipLaunchKernelGGL(rst::mk::k_mk_resid, gred, dim3(256), 0, c->stream, S, B, (const int*)mark,
-                             (const double2*)Wres, R, part);
+      // IDR(s) cycles: s steps of one apply each, then the dimension-reduction step.  `run_idr` runs
+      // them on vectors of storage type VT (complex128, or complex64 for the corrections of the mixed
+      // mode) from the right-hand sides Bv to the relative tolerance tol.  inner: a column that stops
+      // (tolerance, iteration budget cap[c], breakdown) is finished for this run; the FP64 refinement
+      // around it checks the true residual.  Otherwise a stopped column's true residual b - A x decides
+      // between done and a restart from it.
+      auto run_idr = [&](auto tag, const rst::mk::Rhs& Bv, double tol, bool inner, const int* capd) -> rst_status {
+        using VT = typename std::remove_pointer<decltype(tag)>::type;
+        constexpr bool f32 = std::is_same<VT, float2>::value;
+        VT* Xv = (VT*)c->d_mkv.p;
+        VT* Rv = Xv + vlen;
+        VT* Vv = Rv + vlen;
+        VT* Tv = Vv + vlen;
+        VT* Gv = Tv + vlen;
+        VT* Uv = Gv + (size_t)sdim * vlen;
+        VT* PHv = pc ? Uv + (size_t)sdim * vlen : Vv;  // M^-1 v
+        VT* Wv = pc ? PHv + vlen : nullptr;
+        VT* VH = pc ? PHv : Vv;
+        rst_status rs;
+        auto iscal = [&](int step, int k, const int* mk_) -> rst_status {
+          hipLaunchKernelGGL(rst::idr::k_idr_scalar, dim3((unsigned)ld), dim3(64), 0, c->stream, S, step, sdim, k,
+                             did, act, mk_, (const double2*)part, tol, c->opts.max_iter, capd);
           HIPCHK(c, hipGetLastError());
-          hpart.resize((size_t)S.nsplit * ld);
-          HIPCHK(c, hipMemcpyAsync(hpart.data(), part, hpart.size() * 16, hipMemcpyDeviceToHost, c->stream));
+          return RST_OK;
+        };
+        hipLaunchKernelGGL(rst::idr::k_idr_init<VT>, dim3(gel), dim3(256), 0, c->stream, S, sdim, Bv, Xv, Rv, Gv,
+                           Uv);
+        hipLaunchKernelGGL((rst::idr::k_idr_pdots<true, VT>), gred, dim3(256), 0, c->stream, S, sdim,
+                           (const int*)nullptr, Psh, (const VT*)Rv, part);
+        if ((rs = iscal(rst::idr::ID_INIT, 0, nullptr)) != RST_OK) return rs;
+        for (;;) {
+          for (int k = 0; k < sdim; ++k) {
+            VT* Gk = Gv + (size_t)k * vlen;
+            VT* Uk = Uv + (size_t)k * vlen;
+            if ((rs = iscal(rst::idr::ID_C, k, nullptr)) != RST_OK) return rs;
+            hipLaunchKernelGGL(rst::idr::k_idr_v<VT>, gred, dim3(256), 0, c->stream, S, sdim, k,
+                               (const rst::idr::IdrSt*)did, (const int*)act, (const VT*)Rv, (const VT*)Gv, Vv);
+            if (pc && (rs = precondition(Vv, PHv, Wv, act, f32)) != RST_OK) return rs;
+            hipLaunchKernelGGL(rst::idr::k_idr_u<VT>, gred, dim3(256), 0, c->stream, S, sdim, k,
+                               (const rst::idr::IdrSt*)did, (const int*)act, (const VT*)VH, Uv);
+            if ((rs = apply(Uk, Gk, act, f32)) != RST_OK) return rs;
+            hipLaunchKernelGGL((rst::idr::k_idr_pdots<false, VT>), gred, dim3(256), 0, c->stream, S, sdim,
+                               (const int*)act, Psh, (const VT*)Gk, part);
+            if ((rs = iscal(rst::idr::ID_D, k, nullptr)) != RST_OK) return rs;
+            hipLaunchKernelGGL(rst::idr::k_idr_upd<VT>, gred, dim3(256), 0, c->stream, S, k,
+                               (const rst::idr::IdrSt*)did, (const int*)act, Gv, Uv, Rv, Xv, part);
+            if ((rs = iscal(rst::idr::ID_CONV, k, nullptr)) != RST_OK) return rs;
+          }
+          // dimension reduction: v = M^-1 r, t = A v, omega from (t, r) and (t, t)
+          VT* vr = Rv;
+          if (pc) {
+            if ((rs = precondition(Rv, PHv, Wv, act, f32)) != RST_OK) return rs;
+            vr = PHv;
+          }
+          if ((rs = apply(vr, Tv, act, f32)) != RST_OK) return rs;
+          hipLaunchKernelGGL((rst::mk::k_mk_dots<2, VT>), gred, dim3(256), 0, c->stream, S, (const int*)act,
+                             (const VT*)Tv, (const VT*)Rv, (const VT*)Tv, (const VT*)Tv, part);
+          if ((rs = iscal(rst::idr::ID_OMEGA, 0, nullptr)) != RST_OK) return rs;
+          hipLaunchKernelGGL(rst::idr::k_idr_rx<VT>, gred, dim3(256), 0, c->stream, S, sdim,
+                             (const rst::idr::IdrSt*)did, (const int*)act, Rv, Xv, (const VT*)Tv, (const VT*)vr,
+                             Psh, part);
+          if ((rs = iscal(rst::idr::ID_END, 0, nullptr)) != RST_OK) return rs;
+          HIPCHK(c, hipGetLastError());
+          HIPCHK(c, hipMemcpyAsync(hid.data(), did, ld * sizeof(rst::idr::IdrSt), hipMemcpyDeviceToHost, c->stream));
+          HIPCHK(c, hipMemcpyAsync(hact.data(), act, ld * 4, hipMemcpyDeviceToHost, c->stream));
           HIPCHK(c, hipStreamSynchronize(c->stream));
-          std::vector<int> rmark(ld, 0);
-          int nrestart = 0;
+          int nmark = 0, nact = 0;
           for (int j = 0; j < ld; ++j) {
-            if (!hmark[j]) continue;
-            double rr = 0.0;
-            for (int r = 0; r < S.nsplit; ++r) rr += hpart[(size_t)r * ld + j].x;
-            rst::idr::IdrSt& q = hid[j];
-            const double rel = q.bb > 0 ? std::sqrt(rr / q.bb) : 0.0;
-            q.check = q.brk = 0;
-            if (rel <= c->opts.tol) {
-              q.done = 1;
-              q.rr = rel;
-            } else if (q.its >= c->opts.max_iter || !std::isfinite(rel) || q.restarts >= 1000) {
-              q.done = 2;
-              q.rr = rel;
-            } else {
-              q.restarts += 1;  // restart from the true residual (now in R)
-              rmark[j] = 1;
-              hact[j] = 1;
-              ++nrestart;
+            hmark[j] = (hid[j].done == 0 && !hact[j] && (hid[j].check || hid[j].brk)) ? 1 : 0;
+            nmark += hmark[j];
+            nact += hact[j];
+          }
+          if (inner) {
+            for (int j = 0; j < ld; ++j)
+              if (hmark[j]) hid[j].done = hid[j].check ? 1 : 2;
+            if (nmark > 0)
+              HIPCHK(c, hipMemcpyAsync(did, hid.data(), ld * sizeof(rst::idr::IdrSt), hipMemcpyHostToDevice,
+                                       c->stream));
+          } else if constexpr (!f32) {
+            if (nmark > 0) {
+              HIPCHK(c, hipMemcpyAsync(mark, hmark.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+              if ((rs = apply(Xv, Tv, mark, false)) != RST_OK) return rs;  // t is rebuilt by the next cycle
+              hipLaunchKernelGGL(rst::mk::k_mk_resid, gred, dim3(256), 0, c->stream, S, Bv, (const int*)mark,
+                                 (const double2*)Tv, Rv, part);
+              HIPCHK(c, hipGetLastError());
+              hpart.resize((size_t)S.nsplit * ld);
+              HIPCHK(c, hipMemcpyAsync(hpart.data(), part, hpart.size() * 16, hipMemcpyDeviceToHost, c->stream));
+              HIPCHK(c, hipStreamSynchronize(c->stream));
+              std::vector<int> rmark(ld, 0);
+              int nrestart = 0;
+              for (int j = 0; j < ld; ++j) {
+                if (!hmark[j]) continue;
+                double rr = 0.0;
+                for (int r = 0; r < S.nsplit; ++r) rr += hpart[(size_t)r * ld + j].x;
+                rst::idr::IdrSt& q = hid[j];
+                const double rel = q.bb > 0 ? std::sqrt(rr / q.bb) : 0.0;
+                q.check = q.brk = 0;
+                if (rel <= tol) {
+                  q.done = 1;
+                  q.rr = rel;
+                } else if (q.its >= c->opts.max_iter || !std::isfinite(rel) || q.restarts >= 1000) {
+                  q.done = 2;
+                  q.rr = rel;
+                } else {
+                  q.restarts += 1;  // restart from the true residual (now in R)
+                  rmark[j] = 1;
+                  hact[j] = 1;
+                  ++nrestart;
+                }
+              }
+              HIPCHK(c, hipMemcpyAsync(did, hid.data(), ld * sizeof(rst::idr::IdrSt), hipMemcpyHostToDevice,
+                                       c->stream));
+              if (nrestart > 0) {
+                HIPCHK(c, hipMemcpyAsync(mark, rmark.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+                hipLaunchKernelGGL(rst::idr::k_idr_zero<VT>, dim3(gel), dim3(256), 0, c->stream, S, sdim,
+                                   (const int*)mark, Gv, Uv);
+                hipLaunchKernelGGL((rst::idr::k_idr_pdots<true, VT>), gred, dim3(256), 0, c->stream, S, sdim,
+                                   (const int*)mark, Psh, (const VT*)Rv, part);
+                if ((rs = iscal(rst::idr::ID_RESTART, 0, mark)) != RST_OK) return rs;
+                HIPCHK(c, hipMemcpyAsync(act, hact.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+                nact += nrestart;
+              }
             }
           }
-          HIPCHK(c, hipMemcpyAsync(did, hid.data(), ld * sizeof(rst::idr::IdrSt), hipMemcpyHostToDevice, c->stream));
-          if (nrestart > 0) {
-            HIPCHK(c, hipMemcpyAsync(mark, rmark.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
-            hipLaunchKernelGGL(rst::idr::k_idr_zero, dim3(gel), dim3(256), 0, c->stream, S, sdim, (const int*)mark, Gb,
-                               Ub);
-            hipLaunchKernelGGL(rst::idr::k_idr_pdots<true>, gred, dim3(256), 0, c->stream, S, sdim, (const int*)mark,
-                               Psh, (const double2*)R, part);
-            if ((ps = iscal(rst::idr::ID_RESTART, 0, mark)) != RST_OK) return ps;
-            HIPCHK(c, hipMemcpyAsync(act, hact.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
-            nact += nrestart;
+          if (nact == 0) break;
+        }
+        return RST_OK;
+      };
+      if (!mixed) {
+        if ((ps = run_idr((double2*)nullptr, B, c->opts.tol, false, nullptr)) != RST_OK) return ps;
+        for (int j = 0; j < ld; ++j) {
+          hst[j].its = hid[j].its;
+          hst[j].restarts = hid[j].restarts;
+          hst[j].rr = hid[j].rr;
+          hst[j].done = hid[j].done;
+        }
+      } else {
+        // FP64 refinement: x = 0, r = b; each cycle solves A d = r in complex64 to the relative
+        // tolerance update_delta for the columns not yet done, x += d, r = b - A x in FP64
+        hipLaunchKernelGGL(rst::mk::k_mk_rhs, gred, dim3(256), 0, c->stream, S, B, X64, R64, part);
+        HIPCHK(c, hipGetLastError());
+        hpart.resize((size_t)S.nsplit * ld);
+        HIPCHK(c, hipMemcpyAsync(hpart.data(), part, hpart.size() * 16, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        std::vector<double> bb(ld, 0.0), rel(ld, 0.0);
+        std::vector<int> cum(ld, 0), cyc(ld, 0), fin(ld, 0), stall(ld, 0), cap(ld, 0), open(ld, 0);
+        std::vector<long long> doff2(ld, -1);
+        for (int j = 0; j < ld; ++j) {
+          for (int r = 0; r < S.nsplit; ++r) bb[j] += hpart[(size_t)r * ld + j].x;
+          fin[j] = bb[j] > 0.0 ? 0 : 1;  // a zero right-hand side (or a padding column) is solved by x = 0
+          rel[j] = bb[j] > 0.0 ? 1.0 : 0.0;
+        }
+        if ((e = ensure(c, c->d_mkref, (size_t)ld * (8 + 4))) != RST_OK) return e;
+        long long* d_doff2 = (long long*)c->d_mkref.p;
+        int* d_cap = (int*)(d_doff2 + ld);
+        rst::mk::Rhs Bi;
+        Bi.src = d_src;
+        Bi.bsc = d_bsc;
+        Bi.dense = R64;
+        Bi.dld = ld;
+        Bi.doff = d_doff2;
+        for (;;) {
+          int nopen = 0;
+          for (int j = 0; j < ld; ++j) {
+            open[j] = fin[j] == 0 ? 1 : 0;
+            doff2[j] = open[j] ? j : -1;
+            cap[j] = open[j] ? c->opts.max_iter - cum[j] : 0;
+            nopen += open[j];
+          }
+          if (nopen == 0) break;
+          HIPCHK(c, hipMemcpyAsync(d_doff2, doff2.data(), ld * 8, hipMemcpyHostToDevice, c->stream));
+          HIPCHK(c, hipMemcpyAsync(d_cap, cap.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+          HIPCHK(c, hipMemcpyAsync(mark, open.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+          if ((ps = run_idr((float2*)nullptr, Bi, c->opts.update_delta, true, d_cap)) != RST_OK) return ps;
+          hipLaunchKernelGGL(rst::mk::k_mk_addx, gred, dim3(256), 0, c->stream, S, (const int*)mark, X64,
+                             (const float2*)c->d_mkv.p);
+          if ((ps = apply(X64, R64, mark, false)) != RST_OK) return ps;
+          hipLaunchKernelGGL(rst::mk::k_mk_resid, gred, dim3(256), 0, c->stream, S, B, (const int*)mark,
+                             (const double2*)R64, R64, part);
+          HIPCHK(c, hipGetLastError());
+          HIPCHK(c, hipMemcpyAsync(hpart.data(), part, hpart.size() * 16, hipMemcpyDeviceToHost, c->stream));
+          HIPCHK(c, hipStreamSynchronize(c->stream));
+          for (int j = 0; j < ld; ++j) {
+            if (!open[j]) continue;
+            double rr = 0.0;
+            for (int r = 0; r < S.nsplit; ++r) rr += hpart[(size_t)r * ld + j].x;
+            const double rn = std::sqrt(rr / bb[j]);
+            cum[j] += hid[j].its;
+            cyc[j] += 1;
+            // a cycle that does not halve the residual counts as a stall; three in a row end the column
+            stall[j] = rn > 0.5 * rel[j] ? stall[j] + 1 : 0;
+            rel[j] = rn;
+            if (rn <= c->opts.tol)
+              fin[j] = 1;
+            else if (cum[j] >= c->opts.max_iter || !std::isfinite(rn) || stall[j] >= 3)
+              fin[j] = 2;
           }
         }
-        if (nact == 0) break;
-      }
-      for (int j = 0; j < ld; ++j) {
-        hst[j].its = hid[j].its;
-        hst[j].restarts = hid[j].restarts;
-        hst[j].rr = hid[j].rr;
-        hst[j].done = hid[j].done;
+        for (int j = 0; j < ld; ++j) {
+          hst[j].its = cum[j];
+          hst[j].restarts = std::max(0, cyc[j] - 1);
+          hst[j].rr = rel[j];
+          hst[j].done = fin[j];
+          if (j < nc) c->last_updates[(size_t)(it0 + j)] = cyc[j];
+        }
       }
     }
     // outputs of the block: T over the destination CAP, the exported solutions, per-column records
     std::vector<double> tb(ld, 0.0);
     if (d_gdst) {
-      hipLaunchKernelGGL(rst::mk::k_mk_tacc, gred, dim3(256), 0, c->stream, S, P, d_gdst, (const double2*)X, part);
+      hipLaunchKernelGGL(rst::mk::k_mk_tacc, gred, dim3(256), 0, c->stream, S, P, d_gdst, Xres, part);
       hipLaunchKernelGGL(rst::mk::k_mk_sum, dim3(gsc), dim3(64), 0, c->stream, S, (const double2*)part,
                          (double*)c->d_mkT.p);
       HIPCHK(c, hipGetLastError());
       HIPCHK(c, hipMemcpyAsync(tb.data(), c->d_mkT.p, ld * 8, hipMemcpyDeviceToHost, c->stream));
     }
     if (xout) {
-      hipLaunchKernelGGL(rst::mk::k_mk_export, dim3(gel), dim3(256), 0, c->stream, S, nc, (const double2*)X, xout,
-                         nitems, it0);
+      hipLaunchKernelGGL(rst::mk::k_mk_export, dim3(gel), dim3(256), 0, c->stream, S, nc, Xres, xout, nitems,
+                         it0);
       HIPCHK(c, hipGetLastError());
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1943,8 +2088,13 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
       res[o] = q.done == 0 ? 0.0 : q.rr;
       st[o] = q.done == 1 ? 0 : 1;
       col_its += q.its;
+      col_cyc += mixed && q.its > 0 ? q.restarts + 1 : 0;
     }
-    bytes += idr ? (double)col_its * (idr_bytes_per_matvec(sdim, pc) * (double)n + 16.0 * (double)nent)
+    // mixed: complex64 vectors in the inner solves (half the bytes), and per cycle the FP64 apply,
+    // residual and correction (x, r: 104 B per point)
+    bytes += idr ? (double)col_its * ((mixed ? 0.5 : 1.0) * idr_bytes_per_matvec(sdim, pc) * (double)n +
+                                      16.0 * (double)nent) +
+                       (double)col_cyc * (104.0 * (double)n + 16.0 * (double)nent)
                  : (double)col_its * (mk_bytes_per_point(pc) * (double)n + 2.0 * 16.0 * (double)nent);
   }
   HIPCHK(c, hipEventRecord(e1, c->stream));
@@ -2949,8 +3099,8 @@ rst_status rst_set_solver(rst_ctx* c, const rst_solver_opts* o) {
   if (o->method != RST_BICGSTAB && o->method != RST_FGMRES && o->method != RST_COCG && o->method != RST_BICGSTAB_MC &&
       o->method != RST_IDRS)
     return fail(c, RST_EINVAL, "unknown method");
-  if ((o->method == RST_BICGSTAB_MC || o->method == RST_IDRS) && o->precision != RST_FP64)
-    return fail(c, RST_EUNSUPPORTED, "the many-column solvers run in FP64 only");
+  if (o->method == RST_BICGSTAB_MC && o->precision != RST_FP64)
+    return fail(c, RST_EUNSUPPORTED, "the many-column BiCGSTAB runs in FP64 only (mixed precision: RST_IDRS)");
   if (o->idr_s < 1 || o->idr_s > rst::idr::SMAX) return fail(c, RST_EINVAL, "idr_s must be in 1..8");
   if (!(o->pc_shift >= 0) || !std::isfinite(o->pc_shift)) return fail(c, RST_EINVAL, "pc_shift must be finite and >= 0");
   if (o->method == RST_COCG && o->precision != RST_FP64) return fail(c, RST_EUNSUPPORTED, "COCG runs in FP64 only");

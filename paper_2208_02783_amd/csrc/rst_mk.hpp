@@ -77,6 +77,16 @@ __device__ __forceinline__ double2 c_div(double2 a, double2 b) {
 }
 __device__ __forceinline__ bool c_finite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
 
+// Vector storage: complex128 (double2) or, for the inner solves of the mixed-precision
+// refinement, complex64 (float2); arithmetic is FP64 either way.
+__device__ __forceinline__ double2 vld(const double2* p, size_t i) { return p[i]; }
+__device__ __forceinline__ double2 vld(const float2* p, size_t i) {
+  const float2 v = p[i];
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void vst(double2* p, size_t i, double2 v) { p[i] = v; }
+__device__ __forceinline__ void vst(float2* p, size_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
+
 __device__ __forceinline__ double2 rhs_at(const Rhs& B, long long gi, int c) {
   if (B.dense) {
     const long long o = B.doff[c];
@@ -162,9 +172,9 @@ __global__ __launch_bounds__(256) void k_mk_s(Shape S, const ColSt* st, const in
 }
 
 // Partial (U0, V0) and, with NDOT = 2, (U1, V1) over iterating columns.
-template <int NDOT>
-__global__ __launch_bounds__(256) void k_mk_dots(Shape S, const int* act, const double2* U0, const double2* V0,
-                                                 const double2* U1, const double2* V1, double2* part) {
+template <int NDOT, class VT = double2>
+__global__ __launch_bounds__(256) void k_mk_dots(Shape S, const int* act, const VT* U0, const VT* V0,
+                                                 const VT* U1, const VT* V1, double2* part) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + lane;
   const long long r0 = (long long)blockIdx.y * S.rows;
@@ -175,8 +185,8 @@ __global__ __launch_bounds__(256) void k_mk_dots(Shape S, const int* act, const 
   if (act[c]) {
     for (long long gi = r0 + wv; gi < r1; gi += 4) {
       const size_t o = (size_t)gi * S.ld + c;
-      acc[0] = c_add(acc[0], c_mulc(U0[o], V0[o]));
-      if (NDOT > 1) acc[NDOT - 1] = c_add(acc[NDOT - 1], c_mulc(U1[o], V1[o]));
+      acc[0] = c_add(acc[0], c_mulc(vld(U0, o), vld(V0, o)));
+      if (NDOT > 1) acc[NDOT - 1] = c_add(acc[NDOT - 1], c_mulc(vld(U1, o), vld(V1, o)));
     }
   }
   store_partials<NDOT>(S, acc, part);
@@ -223,6 +233,36 @@ __global__ __launch_bounds__(256) void k_mk_resid(Shape S, Rhs B, const int* mar
     }
   }
   store_partials<1>(S, acc, part);
+}
+
+// Mixed-precision refinement: X = 0, R = b for all columns; partial ||b||^2.
+__global__ __launch_bounds__(256) void k_mk_rhs(Shape S, Rhs B, double2* X, double2* R, double2* part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  const long long r0 = (long long)blockIdx.y * S.rows;
+  const long long r1 = r0 + S.rows < S.n ? r0 + S.rows : S.n;
+  double2 acc[1] = {make_double2(0.0, 0.0)};
+  for (long long gi = r0 + wv; gi < r1; gi += 4) {
+    const size_t o = (size_t)gi * S.ld + c;
+    const double2 b = rhs_at(B, gi, c);
+    X[o] = make_double2(0.0, 0.0);
+    R[o] = b;
+    acc[0].x += b.x * b.x + b.y * b.y;
+  }
+  store_partials<1>(S, acc, part);
+}
+
+// Mixed-precision refinement: X += D (the complex64 correction) for the marked columns.
+__global__ __launch_bounds__(256) void k_mk_addx(Shape S, const int* mark, double2* X, const float2* D) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  if (!mark[c]) return;
+  const long long r0 = (long long)blockIdx.y * S.rows;
+  const long long r1 = r0 + S.rows < S.n ? r0 + S.rows : S.n;
+  for (long long gi = r0 + wv; gi < r1; gi += 4) {
+    const size_t o = (size_t)gi * S.ld + c;
+    X[o] = c_add(X[o], vld(D, o));
+  }
 }
 
 // Restart of the marked columns from their true residual: R0 = P = R.
@@ -350,8 +390,8 @@ __global__ __launch_bounds__(64) void k_mk_scalar(Shape S, int step, ColSt* st, 
 // q forms outputs j = q, q + 4, ..., q + 4(R-1) (R = ceil(N/4) <= RW, the rest
 // of a block of 4*RW outputs in later rounds).
 struct DftPass {
-  const double2* in;
-  double2* out;
+  const void* in;      // n x ld vectors of the kernel's storage type
+  void* out;
   const double2* w;    // [N] (direct evaluation)
   const double2* post; // [N]
   const double2* pre;  // [N] (factored evaluation): pre[i] = (w[j] / root^j)^i, the twist
@@ -364,8 +404,10 @@ struct DftPass {
   int P, nz, ld;
 };
 
-template <int RW>
+template <int RW, class VT = double2>
 __global__ __launch_bounds__(256) void k_mk_dft(DftPass D) {
+  const VT* in = (const VT*)D.in;
+  VT* out = (VT*)D.out;
   extern __shared__ double2 lds_dft[];  // [N][64] line, then w[N], post[N]
   double2* lin = lds_dft;
   double2* tw = lds_dft + (size_t)D.N * 64;
@@ -381,7 +423,7 @@ __global__ __launch_bounds__(256) void k_mk_dft(DftPass D) {
   const long long base = (long long)z * D.P + (long long)li * D.inner_mul;
   const bool on = D.act == nullptr || D.act[c];
   for (int i = wv; i < N; i += 4)
-    lin[i * 64 + lane] = on ? D.in[(size_t)(base + (long long)i * D.stride) * D.ld + c] : make_double2(0.0, 0.0);
+    lin[i * 64 + lane] = on ? vld(in, (size_t)(base + (long long)i * D.stride) * D.ld + c) : make_double2(0.0, 0.0);
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     tw[i] = D.w[i];
     tp[i] = D.post[i];
@@ -408,7 +450,7 @@ __global__ __launch_bounds__(256) void k_mk_dft(DftPass D) {
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
       const int j = jb + wv + 4 * r;
-      if (j < N) D.out[(size_t)(base + (long long)j * D.stride) * D.ld + c] = c_mul(tp[j], acc[r]);
+      if (j < N) vst(out, (size_t)(base + (long long)j * D.stride) * D.ld + c, c_mul(tp[j], acc[r]));
     }
   }
 }
@@ -425,9 +467,11 @@ __global__ __launch_bounds__(256) void k_mk_dft(DftPass D) {
 // one (line, 64-column chunk), NW waves; wave q takes n2 = q, q + NW, ... in the
 // first stage and k1 = q, q + NW, ... in the second.  MINW: waves per SIMD asked of
 // the register allocator.
-template <int N1, int N2, int NW, int MINW>
+template <int N1, int N2, int NW, int MINW, class VT = double2>
 __global__ __launch_bounds__(64 * NW, MINW) void k_mk_fft(DftPass D) {
   constexpr int N = N1 * N2;
+  const VT* in = (const VT*)D.in;
+  VT* out = (VT*)D.out;
   __shared__ double2 ys[N * 64];
   __shared__ double2 troot[N], tpre[N], tpost[N];
   const int lane = threadIdx.x & 63;
@@ -452,7 +496,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void k_mk_fft(DftPass D) {
     const int n2 = wv + g * NW;
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1)
-      v[g][n1] = on && n2 < N2 ? D.in[(size_t)(base + (long long)(N2 * n1 + n2) * D.stride) * D.ld + c]
+      v[g][n1] = on && n2 < N2 ? vld(in, (size_t)(base + (long long)(N2 * n1 + n2) * D.stride) * D.ld + c)
                                : make_double2(0.0, 0.0);
   }
 #pragma unroll
@@ -489,7 +533,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void k_mk_fft(DftPass D) {
         acc.y = fma(u[n2].x, r.y, fma(u[n2].y, r.x, acc.y));
       }
       const int j = k1 + N1 * k2;
-      D.out[(size_t)(base + (long long)j * D.stride) * D.ld + c] = c_mul(tpost[j], acc);
+      vst(out, (size_t)(base + (long long)j * D.stride) * D.ld + c, c_mul(tpost[j], acc));
     }
   }
 }
@@ -555,8 +599,8 @@ __global__ __launch_bounds__(256) void k_mk_band_factor(Band B) {
 // w_z = y_z / D_z (into W), backward x_z = w_z - sum_j L[z+j][j] x_{z+j} (into io,
 // which held f).  The last M values of y (forward) and x (backward) stay in
 // registers.  RM: the stencil radius.
-template <int RM>
-__global__ __launch_bounds__(256) void k_mk_band_solve(double2* io, double2* W, const double2* Lb,
+template <int RM, class VT = double2>
+__global__ __launch_bounds__(256) void k_mk_band_solve(VT* io, VT* W, const double2* Lb,
                                                        const double2* dinv, const int* eidx, const int* act, int P,
                                                        int nz, int ld) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -580,7 +624,7 @@ __global__ __launch_bounds__(256) void k_mk_band_solve(double2* io, double2* W, 
 #pragma unroll
     for (int q = 0; q < BZ; ++q) {
       const int z = zb + q < nz ? zb + q : nz - 1;
-      xin[q] = io[o0 + (size_t)z * zs];
+      xin[q] = vld(io, o0 + (size_t)z * zs);
       dv[q] = di[(size_t)z * P + m];
 #pragma unroll
       for (int k = 0; k < RM; ++k) Lz[q][k] = L[((size_t)z * P + m) * RM + k];
@@ -594,7 +638,7 @@ __global__ __launch_bounds__(256) void k_mk_band_solve(double2* io, double2* W, 
 #pragma unroll
       for (int k = RM - 1; k >= 1; --k) win[k] = win[k - 1];
       win[0] = y;
-      W[o0 + (size_t)(zb + q) * zs] = c_mul(y, dv[q]);
+      vst(W, o0 + (size_t)(zb + q) * zs, c_mul(y, dv[q]));
     }
   }
 #pragma unroll
@@ -606,7 +650,7 @@ __global__ __launch_bounds__(256) void k_mk_band_solve(double2* io, double2* W, 
 #pragma unroll
     for (int q = 0; q < BZ; ++q) {
       const int z = zt - q >= 0 ? zt - q : 0;
-      w[q] = W[o0 + (size_t)z * zs];
+      w[q] = vld(W, o0 + (size_t)z * zs);
 #pragma unroll
       for (int j = 1; j <= RM; ++j) {
         const int zr = z + j < nz ? z + j : nz - 1;
@@ -624,7 +668,7 @@ __global__ __launch_bounds__(256) void k_mk_band_solve(double2* io, double2* W, 
 #pragma unroll
       for (int k = RM - 1; k >= 1; --k) win[k] = win[k - 1];
       win[0] = x;
-      io[o0 + (size_t)z * zs] = x;
+      vst(io, o0 + (size_t)z * zs, x);
     }
   }
 }

@@ -120,6 +120,32 @@ def test_mc_equals_persistent_solver_on_tiny_config3():
     assert np.max(np.abs(ta - tc)) <= 1e-8 * max(1.0, float(np.max(ta))), (ta, tc)
 
 
+@pytest.mark.parametrize("cfg,pc", [(2, 0), (2, 1), (3, 1)])
+def test_idr_mixed_tiny_transmission_matches_oracle(cfg, pc):
+    """IDR(4) in the mixed mode (FP64 refinement around complex64 correction
+    solves): T(E,k) on the tiny slabs against the oracle at the same bar as
+    FP64, and Green's columns to 1e-9."""
+    torch = torch_cuda()
+    p = wl.config(cfg, tiny=True)
+    k = p.kpts[1]
+    es = p.energies[[1, 5]]
+    ctx = make_ctx(torch, p, k, method=IDR, precond=pc, precision=rst.RST_FP32_REFINE, update_delta=1e-4)
+    t, st, s = ctx.rst_transmission(es)
+    _say(f"cfg{cfg}-tiny mixed pc={pc}: T={t} applies/col={st['iterations_total'] / st['columns']:.1f} "
+         f"cycles={st['updates_total']} fallbacks={st['fallback_columns']}")
+    assert s == rst.RST_OK, st
+    assert st["updates_total"] >= st["columns"]  # at least one refinement cycle per column
+    ref = oracle.transmission(p, es, k, both=False)["T_LR"]
+    for e, a, b in zip(es, t, ref):
+        assert abs(a - b) <= 1e-6 * max(1, n_channels(p, e, k)), (e, a, b)
+    cols = p.r_columns()[:7]
+    x, st, s = rst.solve_columns(ctx, float(es[0]), cols, p.n)
+    assert s == rst.RST_OK
+    g = oracle.green_columns(p, float(es[0]), k, cols)
+    err = np.max(np.abs(x.cpu().numpy() - g)) / np.max(np.abs(g))
+    assert err <= 1e-9, err
+
+
 def test_mc_option_errors():
     torch = torch_cuda()
     p = wl.config(1)
@@ -170,6 +196,28 @@ def test_full_config3_sampled_columns_true_residual_by_oracle():
     assert np.all(res <= 2e-10), res
     lz = np.repeat(p.gamma_l > 0, p.na * p.nb)
     assert np.all(np.linalg.norm(x[lz], axis=0) > 0)
+
+
+def test_full_config3_sampled_columns_mixed_precision_true_residual_by_oracle():
+    """The same eight config-3 columns in the mixed mode: the FP64 refinement's
+    answer passes the oracle's own FP64 residual at the same 2e-10."""
+    torch = torch_cuda()
+    p, k, e = _cfg3()
+    ctx = make_ctx(torch, p, k, precond=1, tol=1e-10, max_iter=20000, pc_shift=SHIFT, method=IDR,
+                   precision=rst.RST_FP32_REFINE, update_delta=1e-4)
+    rc = p.r_columns()
+    cols = rc[np.linspace(0, rc.size - 1, 8).round().astype(int)]
+    x, st, s = rst.solve_columns(ctx, e, cols, p.n)
+    _say(f"config-3 mixed columns: applies/col {st['iterations_total'] / st['columns']:.1f}, cycles "
+         f"{st['updates_total']}, kernel {st['kernel_ms']:.0f} ms, fallbacks {st['fallback_columns']}")
+    assert s == rst.RST_OK, st
+    assert st["fallback_columns"] == 0
+    x = x.cpu().numpy()
+    b = np.zeros_like(x)
+    b[cols, np.arange(cols.size)] = 1.0
+    res = oracle.residual_norms(p, k, e, x, b)
+    _say("oracle-recomputed true residuals (mixed)", res)
+    assert np.all(res <= 2e-10), res
 
 
 def test_full_config3_lowrank_both_directions_and_probe_sets_agree():
