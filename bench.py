@@ -534,10 +534,10 @@ def main():
         run_leg(line, "batched", budget, 30.0, reserve, lambda: batched_comparison(ne=args.batched_energies))
     if not args.no_cocg:
         run_leg(line, "cocg", budget, 45.0, reserve, lambda: cocg_comparison(prob2))
-    if not args.no_mixed and "t_ref" in state:
-        run_leg(line, "mixed", budget, 55.0, reserve, lambda: mixed_point(prob2, k_ref, e_ref, state["t_ref"]))
     if not args.no_learned:
         run_leg(line, "learned", budget, 50.0, reserve, lambda: learned_comparison(prob2))
+    if not args.no_mixed and "t_ref" in state:
+        run_leg(line, "mixed", budget, 90.0, reserve, lambda: mixed_point(prob2, k_ref, e_ref, state["t_ref"]))
     line["wall_s_total"] = time.time() - T_START
     print(json.dumps(line), flush=True)
 

@@ -192,8 +192,11 @@ const char *rst_last_error(const rst_ctx *ctx);
  * in 2..12 (the order-2M central Laplacian of the Bloch-form equation).
  * RST_EINVAL for non-positive sizes or spacings, another order, or more than
  * 2^31 - 1 points.  The GPU kernels require na > fd_order/2 and
- * nb > fd_order/2 (RST_EUNSUPPORTED otherwise), and are built for orders 4
- * and 12: the compute calls return RST_EUNSUPPORTED for the others. */
+ * nb > fd_order/2 (RST_EUNSUPPORTED otherwise).  Every order runs on the
+ * many-column apply and solvers (rst_apply_h, rst_transmission and the calls
+ * built on it route orders other than 4 and 12 there); the persistent
+ * kernels (the blocked apply, FGMRES, COCG, the batched launch) are built for
+ * orders 4 and 12 and return RST_EUNSUPPORTED for the others. */
 rst_status rst_set_grid(rst_ctx *ctx, int na, int nb, int nz, double ha, double hb, double hz,
                         int fd_order);
 

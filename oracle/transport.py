@@ -27,6 +27,7 @@ import math
 
 import numpy as np
 import scipy.linalg as sla
+from scipy.linalg import lapack
 import scipy.sparse as sp
 
 
@@ -178,7 +179,13 @@ def transmission(prob, energies, k, both=True):
 
     T_LR = 4 sum_{i in R} sum_{j in L} Gamma_L,j |x_i[j]|^2 with
     x_i = A^-1 (sqrt(Gamma_R,i) e_i); T_RL the same with L and R exchanged.
-    Returns dict(T_LR, T_RL) of arrays over energies."""
+    Returns dict(T_LR, T_RL, rcond, near_singular) of arrays over energies.
+
+    Near-singular energies (a state decoupled from both CAPs makes A almost
+    singular there, so T is ill-conditioned) are flagged: rcond is LAPACK's
+    1-norm reciprocal condition estimate of A from its LU factors, and an energy
+    is flagged when rcond < 1e-12 or, with both directions, when |T_LR - T_RL|
+    exceeds 1e-9 max(1, T_LR) (the two are equal for any nonsingular A)."""
     energies = np.atleast_1d(np.asarray(energies, float))
     gl, gr = _gz(prob, "L"), _gz(prob, "R")
     rcols, lcols = prob.r_columns(), prob.l_columns()
@@ -186,10 +193,13 @@ def transmission(prob, energies, k, both=True):
     base[np.diag_indices(prob.n)] += 1j * (gl + gr)
     t_lr = np.zeros(energies.size)
     t_rl = np.zeros(energies.size)
+    rcond = np.zeros(energies.size)
     for ie, e in enumerate(energies):
         a = base.copy()
         a[np.diag_indices(prob.n)] += e
+        anorm = float(np.max(np.sum(np.abs(a), axis=0)))
         lu = sla.lu_factor(a, overwrite_a=True, check_finite=False)
+        rcond[ie] = float(lapack.zgecon(lu[0], anorm, norm="1")[0])
         b = np.zeros((prob.n, rcols.size), complex)
         b[rcols, np.arange(rcols.size)] = np.sqrt(gr[rcols])
         x = sla.lu_solve(lu, b, check_finite=False)
@@ -199,7 +209,10 @@ def transmission(prob, energies, k, both=True):
             b[lcols, np.arange(lcols.size)] = np.sqrt(gl[lcols])
             x = sla.lu_solve(lu, b, check_finite=False)
             t_rl[ie] = 4.0 * float(np.sum(gr[:, None] * np.abs(x) ** 2))
-    return dict(T_LR=t_lr, T_RL=t_rl if both else None)
+    flag = rcond < 1e-12
+    if both:
+        flag |= np.abs(t_lr - t_rl) > 1e-9 * np.maximum(1.0, t_lr)
+    return dict(T_LR=t_lr, T_RL=t_rl if both else None, rcond=rcond, near_singular=flag)
 
 
 def green_columns(prob, e, k, cols) -> np.ndarray:

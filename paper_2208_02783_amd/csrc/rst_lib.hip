@@ -330,6 +330,23 @@ rst_status proj_blocked(rst_ctx* c, const rst::ApplyArgs& A) {
   return RST_OK;
 }
 
+// k_apply_cols instance for a stencil radius (FD order 2..12), projector group size and precision.
+void* apply_cols_kernel(int rad, bool nm9, bool f32) {
+#define RST_APPLY_PICK(R)                                                                          \
+  if (rad == R) {                                                                                  \
+    if (f32) return nm9 ? (void*)rst::k_apply_cols<R, 9, float> : (void*)rst::k_apply_cols<R, 16, float>; \
+    return nm9 ? (void*)rst::k_apply_cols<R, 9, double> : (void*)rst::k_apply_cols<R, 16, double>; \
+  }
+  RST_APPLY_PICK(1)
+  RST_APPLY_PICK(2)
+  RST_APPLY_PICK(3)
+  RST_APPLY_PICK(4)
+  RST_APPLY_PICK(5)
+  RST_APPLY_PICK(6)
+#undef RST_APPLY_PICK
+  return nullptr;
+}
+
 // Strip width of k_apply_cols' point order.  A plane that the waves in flight on
 // one XCD cover whole (about 32 CUs x 12 waves) keeps row-major order; on wider
 // planes strips of APPLY_STRIP a-columns keep the b neighbours a few strips apart.
@@ -390,14 +407,8 @@ rst_status apply_cols(rst_ctx* c, const void* x, void* y, int ncol, double energ
     A.P = projP;
   }
   if (ev) HIPCHK(c, hipEventRecord(ev[1], c->stream));
-  const bool nm9 = c->nm <= 9;
-  void* kern = nullptr;
-  if (f32)
-    kern = c->rad == 6 ? (nm9 ? (void*)rst::k_apply_cols<6, 9, float> : (void*)rst::k_apply_cols<6, 16, float>)
-                       : (nm9 ? (void*)rst::k_apply_cols<2, 9, float> : (void*)rst::k_apply_cols<2, 16, float>);
-  else
-    kern = c->rad == 6 ? (nm9 ? (void*)rst::k_apply_cols<6, 9, double> : (void*)rst::k_apply_cols<6, 16, double>)
-                       : (nm9 ? (void*)rst::k_apply_cols<2, 9, double> : (void*)rst::k_apply_cols<2, 16, double>);
+  void* kern = apply_cols_kernel(c->rad, c->nm <= 9, f32);
+  if (!kern) return fail(c, RST_EUNSUPPORTED, "no many-column apply for this FD order");
   {
     void* args[] = {&A};
     HIPCHK(c, hipLaunchKernel(kern, dim3((unsigned)nwg), dim3(64), args, 0, c->stream));
@@ -669,6 +680,10 @@ RST_KINST(6)
 RST_KINST(7)
 #undef RST_KINST
 
+// The persistent kernels are built for FD orders 4 and 12; the other even orders 2..12 run on
+// the many-column solvers.
+bool persistent_order(int rad) { return rad == 2 || rad == 6; }
+
 void* pick_kernel(int rad, int q, int w) {
 #define RST_KPICK(K)                                                \
   if (w == K) {                                                     \
@@ -718,8 +733,6 @@ rst_status check_ready(rst_ctx* c) {
   if (!c->has_v) return fail(c, RST_ESTATE, "rst_set_potential not called");
   if (!c->has_abc) return fail(c, RST_ESTATE, "rst_set_abc not called");
   if (!c->has_k) return fail(c, RST_ESTATE, "rst_set_k not called");
-  if (c->rad != 2 && c->rad != 6)
-    return fail(c, RST_EUNSUPPORTED, "GPU kernels are built for FD orders 4 and 12");
   return RST_OK;
 }
 
@@ -756,7 +769,8 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
   }
   // the persistent kernels hold a whole lateral plane per workgroup; wider planes go to the
   // many-column BiCGSTAB, one kernel per step
-  if (c->opts.method == RST_BICGSTAB_MC || c->opts.method == RST_IDRS || c->na * c->nb > 2 * rst::MAX_T) {
+  if (c->opts.method == RST_BICGSTAB_MC || c->opts.method == RST_IDRS || c->na * c->nb > 2 * rst::MAX_T ||
+      !persistent_order(c->rad)) {
     if (c->opts.col_block > 0 || c->opts.threads > 0)
       return fail(c, RST_EUNSUPPORTED, "col_block and threads apply to the persistent kernels (planes of at most " +
                                            std::to_string(2 * rst::MAX_T) + " points)");
@@ -1424,6 +1438,21 @@ double idr_bytes_per_matvec(int s, bool pc) {
   return 16.0 * streams / (s + 1);
 }
 
+// Banded z solve instance for a stencil radius (the band's half width) and vector storage.
+const void* band_solve_kernel(int rad, bool f32) {
+#define RST_BAND_PICK(R)                                                                        \
+  if (rad == R) return f32 ? (const void*)rst::mk::k_mk_band_solve<R, float2>                   \
+                           : (const void*)rst::mk::k_mk_band_solve<R, double2>;
+  RST_BAND_PICK(1)
+  RST_BAND_PICK(2)
+  RST_BAND_PICK(3)
+  RST_BAND_PICK(4)
+  RST_BAND_PICK(5)
+  RST_BAND_PICK(6)
+#undef RST_BAND_PICK
+  return nullptr;
+}
+
 // Factored lateral DFT instances (k_mk_fft<N1, N2, NW>, N = N1 N2); other N use the direct
 // evaluation (k_mk_dft).
 struct FftInstance {
@@ -1688,22 +1717,13 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     if ((ps = dft(Wp, out, FB, false, mask, f32)) != RST_OK) return ps;
     const long long nt = (long long)P * ld;
     const dim3 gb((unsigned)((nt + 255) / 256));
-    if (f32) {
-      if (c->rad == 6)
-        hipLaunchKernelGGL((rst::mk::k_mk_band_solve<6, float2>), gb, dim3(256), 0, c->stream, (float2*)out,
-                           (float2*)Wp, band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
-      else
-        hipLaunchKernelGGL((rst::mk::k_mk_band_solve<2, float2>), gb, dim3(256), 0, c->stream, (float2*)out,
-                           (float2*)Wp, band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
-    } else {
-      if (c->rad == 6)
-        hipLaunchKernelGGL(rst::mk::k_mk_band_solve<6>, gb, dim3(256), 0, c->stream, (double2*)out, (double2*)Wp,
-                           band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
-      else
-        hipLaunchKernelGGL(rst::mk::k_mk_band_solve<2>, gb, dim3(256), 0, c->stream, (double2*)out, (double2*)Wp,
-                           band_L, band_dinv, (const int*)d_eidx, mask, P, nz, ld);
+    {
+      const void* kb = band_solve_kernel(c->rad, f32);
+      const int* eix = d_eidx;
+      void* args[] = {&out, &Wp, (void*)&band_L, (void*)&band_dinv, (void*)&eix, (void*)&mask, (void*)&P,
+                      (void*)&nz, (void*)&ld};
+      HIPCHK(c, hipLaunchKernel(kb, gb, dim3(256), args, 0, c->stream));
     }
-    HIPCHK(c, hipGetLastError());
     if ((ps = dft(out, Wp, IB, false, mask, f32)) != RST_OK) return ps;
     return dft(Wp, out, IA, true, mask, f32);
   };

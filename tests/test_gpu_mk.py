@@ -146,6 +146,41 @@ def test_idr_mixed_tiny_transmission_matches_oracle(cfg, pc):
     assert err <= 1e-9, err
 
 
+@pytest.mark.parametrize("order", [2, 6, 8, 10])
+def test_other_fd_orders_run_on_the_many_column_path(order):
+    """FD orders other than 4 and 12 (no persistent-kernel instances): the apply
+    in both precisions element by element, T(E,k) through rst_transmission (routed
+    to the many-column solvers, with and without M^-1) against the oracle; the
+    persistent-only calls refuse the order."""
+    from tests import oracle_helpers as hp
+    torch = torch_cuda()
+    rng = np.random.default_rng(50 + order)
+    p = hp.random_problem(rng, na=7, nb=6, nz=30, order=order, nproj=3, ramp=5)
+    k = (0.29, -0.47)
+    ctx = make_ctx(torch, p, k)
+    x = rng.standard_normal((p.n, 70)) + 1j * rng.standard_normal((p.n, 70))
+    ref = oracle.apply_system(p, k, 0.41, x)
+    y = rst.apply_h(ctx, 0.41, torch.from_numpy(x).to("cuda")).cpu().numpy()
+    assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
+    x32 = torch.from_numpy(x).to("cuda").to(torch.complex64)
+    ref32 = oracle.apply_system(p, k, 0.41, x32.cpu().numpy().astype(np.complex128))
+    y32 = rst.apply_h(ctx, 0.41, x32).cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(y32 - ref32)) <= 5e-5 * np.max(np.abs(ref32))
+    es = np.array([0.3, 0.9])
+    tref = oracle.transmission(p, es, k, both=False)["T_LR"]
+    for pc in (0, 1):
+        ctx.rst_set_solver(precond=pc, tol=1e-11)
+        t, st, s = ctx.rst_transmission(es)
+        _say(f"order {order} pc={pc}: T={t} ref={tref} its/col={st['iterations_total'] / st['columns']:.1f}")
+        assert s == rst.RST_OK, st
+        for e, a, b in zip(es, t, tref):
+            assert abs(a - b) <= 1e-6 * max(1, n_channels(p, e, k)), (e, a, b)
+    ctx.rst_set_solver(method=rst.RST_FGMRES)
+    with pytest.raises(rst.RstError) as ei:
+        ctx.rst_transmission(es)
+    assert ei.value.status == rst.RST_EUNSUPPORTED
+
+
 def test_mc_option_errors():
     torch = torch_cuda()
     p = wl.config(1)

@@ -308,3 +308,28 @@ def test_bulk_mode_count_3d_with_projectors():
         assert abs(tt - m) < 1e-2 * max(1, m), (e, tt, m)
         checked += 1
     assert checked >= 4
+
+
+def test_near_singular_energy_is_flagged():
+    """A box sealed by two tall barriers holds a state that barely couples to
+    the CAPs: at its energy A = E - H + i Gamma is numerically singular and the
+    oracle flags the energy (rcond < 1e-12); a regular energy of the same slab
+    and every energy of an open slab are not flagged (reading of the
+    uniqueness requirement: flag near-singular energies instead of trusting T)."""
+    import dataclasses
+    from oracle import eigen
+    rng = np.random.default_rng(7)
+    p = hp.random_problem(rng, na=3, nb=3, nz=40, order=4, nproj=0, ramp=6, vscale=0.0)
+    k = (0.0, 0.0)
+    v = np.zeros((p.nz, p.nb * p.na))
+    v[12:17] = 60.0  # barriers of 5 planes (2.5 bohr) at 60 Ha: tunnelling ~ exp(-27)
+    v[23:28] = 60.0
+    sealed = dataclasses.replace(p, v=v.reshape(-1))
+    lam = np.linalg.eigvals(eigen.k_matrix(sealed, k))
+    trapped = lam[np.argmin(np.abs(lam.imag) + 10.0 * (np.abs(lam.real) > 3.0))]
+    assert abs(trapped.imag) < 1e-10
+    out = oracle.transmission(sealed, [trapped.real, trapped.real + 0.05], k)
+    assert out["near_singular"][0] and out["rcond"][0] < 1e-12, out["rcond"]
+    assert not out["near_singular"][1], out["rcond"]
+    open_slab = oracle.transmission(p, [0.2, 0.7, 1.3], k)
+    assert not np.any(open_slab["near_singular"]), open_slab["rcond"]
