@@ -168,7 +168,9 @@ struct rst_ctx {
   std::vector<HostProb> batch;
   int batch_version = 0;
   long long grid_version = 0;
-  std::map<long long, int> tuned_cw;  // (lateral shape, order, direction) -> columns per workgroup
+  // (lateral shape, order, preconditioner, direction, launch mode, caller's requests) -> tuned
+  // (columns per workgroup, workgroup size) of the batched launch
+  std::map<long long, std::pair<int, int>> tuned_shape;
   hipGraphExec_t gexec = nullptr;
   // what the captured launch depends on: batch contents, kernel, launch shape, LDS bytes and every
   // device pointer baked into the graph (argument block, work counter, workspace)
@@ -2483,9 +2485,9 @@ rst_status batch_collect(rst_ctx* c, const std::vector<int>& sel, const std::vec
                          int P, BatchOut& out);
 
 rst_status run_batch(rst_ctx* c, const std::vector<int>& sel, int ne_cap, int cw, bool use_graph,
-                     BatchOut& out, bool per_structure = false) {
+                     BatchOut& out, bool per_structure = false, int threads = -1) {
   LaunchShape ls;
-  rst_status s = choose_shape(c, cw, c->opts.threads, ls);
+  rst_status s = choose_shape(c, cw, threads >= 0 ? threads : c->opts.threads, ls);
   if (s != RST_OK) return s;
   const int P = c->na * c->nb;
   const bool lr = c->opts.direction == RST_DIR_LR;
@@ -2707,14 +2709,44 @@ rst_status run_batch(rst_ctx* c, const std::vector<int>& sel, int ne_cap, int cw
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
+    // the launches, back to back (captured once into a HIP graph and replayed with use_graph)
+    auto launch_all = [&]() -> rst_status {
+      for (size_t i = 0; i < qs.size(); ++i) {
+        if (nit[i] == 0) continue;
+        void* qarg = (char*)c->d_args.p + i * sizeof(rst::SolveArgs);
+        void* qargs[] = {&qarg};
+        hipLaunchKernelGGL(rst::k_fill_int, dim3(1), dim3(64), 0, c->stream, (int*)c->d_counter.p, 16, 0);
+        HIPCHK(c, hipLaunchKernel(kern, dim3((unsigned)std::min<long long>(nwg, nit[i])), dim3(ls.threads), qargs,
+                                  lds, c->stream));
+      }
+      return RST_OK;
+    };
+    const std::array<long long, 9> key = {(long long)c->batch_version, (long long)(uintptr_t)kern,
+                                          (long long)ls.cw, (long long)ls.threads, -(long long)qs.size(),
+                                          (long long)lds, (long long)(uintptr_t)c->d_args.p,
+                                          (long long)(uintptr_t)c->d_counter.p, (long long)(uintptr_t)c->d_ws.p};
+    if (use_graph && (c->gexec == nullptr || c->gexec_key != key)) {
+      if (c->gexec) {
+        HIPCHK(c, hipGraphExecDestroy(c->gexec));
+        c->gexec = nullptr;
+      }
+      hipGraph_t graph;
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      rst_status ls_ = launch_all();
+      HIPCHK(c, hipStreamEndCapture(c->stream, &graph));
+      if (ls_ != RST_OK) {
+        hipGraphDestroy(graph);
+        return ls_;
+      }
+      HIPCHK(c, hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0));
+      HIPCHK(c, hipGraphDestroy(graph));
+      c->gexec_key = key;
+    }
     HIPCHK(c, hipEventRecord(e0, c->stream));
-    for (size_t i = 0; i < qs.size(); ++i) {
-      if (nit[i] == 0) continue;
-      void* qarg = (char*)c->d_args.p + i * sizeof(rst::SolveArgs);
-      void* qargs[] = {&qarg};
-      hipLaunchKernelGGL(rst::k_fill_int, dim3(1), dim3(64), 0, c->stream, (int*)c->d_counter.p, 16, 0);
-      HIPCHK(c, hipLaunchKernel(kern, dim3((unsigned)std::min<long long>(nwg, nit[i])), dim3(ls.threads), qargs,
-                                lds, c->stream));
+    if (use_graph) {
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    } else if ((s = launch_all()) != RST_OK) {
+      return s;
     }
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -2872,33 +2904,58 @@ rst_status rst_batch_run(rst_ctx* c, double* T_out, rst_stats* stats) {
     if (it > 0) min_items = min_items < 0 ? it : std::min(min_items, it);
   }
   const bool per_structure = min_items >= 4LL * 16 * ncu;
-  if (per_structure && cw == 0) cw = 1;
-  if (cw == 0) {
-    // autotune: time every candidate on every structure at its first energy, a sample large
+  if (per_structure && cw == 0) cw = 1;  // measured best for launches that each fill the device
+  int threads = c->opts.threads;
+  if (cw == 0 || threads == 0) {
+    // autotune the launch shape: columns per workgroup (1, 2, 4, 8, or the caller's) times the
+    // positions per thread (one or two, i.e. the workgroup size), each candidate timed on every
+    // structure at its first energy in the launch mode the full batch uses: a sample large
     // enough to fill the device like the full launch does (timed on one structure alone, the
     // half-empty device favoured wide column blocks that lose on the full batch)
     const long long key = ((long long)c->na << 40) ^ ((long long)c->nb << 24) ^ ((long long)c->rad << 8) ^
-                          ((long long)c->opts.precond << 4) ^ c->opts.direction;
-    auto it = c->tuned_cw.find(key);
-    if (it != c->tuned_cw.end()) {
-      cw = it->second;
+                          ((long long)c->opts.precond << 4) ^ ((long long)c->opts.direction << 2) ^
+                          ((long long)per_structure << 1) ^ ((long long)cw << 48) ^ ((long long)threads << 52);
+    auto it = c->tuned_shape.find(key);
+    if (it != c->tuned_shape.end()) {
+      cw = it->second.first;
+      threads = it->second.second;
     } else {
-      int best = 1;
-      double best_t = 1e300;
-      for (int cand : {1, 2, 4, 8}) {
-        LaunchShape ls;
-        if (choose_shape(c, cand, c->opts.threads, ls) != RST_OK) continue;
-        BatchOut o;
-        if ((s = run_batch(c, all, 1, cand, false, o)) != RST_OK) return s;
-        const double per = o.ms / std::max<size_t>(1, o.its.size());
-        if (per < best_t) { best_t = per; best = cand; }
+      std::vector<int> cws = cw > 0 ? std::vector<int>{cw} : std::vector<int>{1, 2, 4, 8};
+      int best_cw = cws[0], best_t = threads;
+      double best_ms = 1e300;
+      for (int cand : cws) {
+        std::vector<int> tcands;
+        if (threads > 0) {
+          tcands.push_back(threads);
+        } else {
+          const int pos = P * cand;
+          for (int q : {1, 2}) {
+            const int t = std::max(64, ((pos + q - 1) / q + 63) / 64 * 64);
+            if (t <= rst::MAX_T && t % cand == 0 && (long long)t * 2 >= pos &&
+                std::find(tcands.begin(), tcands.end(), t) == tcands.end())
+              tcands.push_back(t);
+          }
+        }
+        for (int t : tcands) {
+          LaunchShape ls;
+          if (choose_shape(c, cand, t, ls) != RST_OK) continue;
+          BatchOut o;
+          if ((s = run_batch(c, all, 1, cand, false, o, per_structure, t)) != RST_OK) return s;
+          const double per = o.ms / std::max<size_t>(1, o.its.size());
+          if (per < best_ms) {
+            best_ms = per;
+            best_cw = cand;
+            best_t = t;
+          }
+        }
       }
-      c->tuned_cw[key] = best;
-      cw = best;
+      c->tuned_shape[key] = {best_cw, best_t};
+      cw = best_cw;
+      threads = best_t;
     }
   }
   BatchOut o;
-  if ((s = run_batch(c, all, 0, cw, true, o, per_structure)) != RST_OK) return s;
+  if ((s = run_batch(c, all, 0, cw, true, o, per_structure, threads)) != RST_OK) return s;
   size_t k = 0;
   for (size_t i = 0; i < all.size(); ++i)
     for (double t : o.T[i]) T_out[k++] = t;
