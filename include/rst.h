@@ -87,11 +87,17 @@ typedef struct {
                         GMRES(restart) in FP64 over chunks of columns (classical Gram-Schmidt twice),
                         convergence on the FP64 true residual after each cycle; precision FP64 only.
                         RST_COCG: conjugate orthogonal conjugate gradients (van der Vorst and Melissen
-                        1990) for a real H_k (k_a L_a and k_b L_b multiples of pi, e.g. the Gamma
-                        point: A = E - H_k + i Gamma is then complex symmetric), one operator apply per
-                        step, preconditioner NONE or FREE_CAP, FP64 only, convergence on the FP64 true
-                        residual; a transmission or column solve at any other k returns
-                        RST_EUNSUPPORTED */
+                        1990), FP64, preconditioner NONE or FREE_CAP, convergence on the FP64 true
+                        residual.  For a real H_k (k_a L_a and k_b L_b multiples of pi, e.g. the Gamma
+                        point: A = E - H_k + i Gamma is then complex symmetric) on planes of up to 1024
+                        points: the blocked COCG, one operator apply per step.  At any other k (and on
+                        wider planes or other FD orders): COCG on the doubled system
+                        B = [[0, A_k], [A_-k, 0]], complex symmetric because A_k^T = A_-k (paper
+                        Sec. II.B: the doubled operator of k and -k), with the preconditioner
+                        [[0, M_k], [M_-k, 0]]^-1; it solves each column at k and at -k together (one
+                        step: one apply at k and one at -k; iterations_total counts steps) and
+                        reports the k solution.  col_block and threads are refused there, and dense
+                        right-hand sides stay BiCGSTAB / IDR(s) */
   int precision;     /* rst_precision; RST_FP32_REFINE: BiCGSTAB on complex64 vectors with FP32 stencil,
                         projector and preconditioner applies (inner products, scalars and projections
                         FP64), the solution kept as x64 + x32 and the recursive residual replaced by the

@@ -59,6 +59,8 @@ struct ColApplyArgs {
   int strip;          // a-columns per strip of the point order (1..na; na: row-major)
   const double* ecol; // [ncol] energy of each column (nullable: `energy` for all)
   const int* mask;    // [ncol] columns to apply (nullable: all); others are left untouched
+  const int* cfl;     // [ncol] (nullable) columns given as conj(x) of a -k system: y = conj((E - H_k - i Gamma)
+                      // conj(x)) = (E - H_-k + i Gamma) x for real V and projectors, i.e. A_-k x
 };
 
 template <class V2>
@@ -111,12 +113,18 @@ __global__ __launch_bounds__(64, (ApplyMinWaves<F, NMU>::value)) void k_apply_co
   const int c = chunk * 64 + (int)threadIdx.x;
   const bool ok = c < ncol && (A.mask == nullptr || A.mask[c] != 0);
   const double ec = A.ecol != nullptr && c < ncol ? A.ecol[c] : A.energy;
+  const bool cj = A.cfl != nullptr && c < ncol && A.cfl[c] != 0;
   const V2 pha{(F)g.pha_x, (F)g.pha_y}, phac{(F)g.pha_x, (F)-g.pha_y};
   const V2 phb{(F)g.phb_x, (F)g.phb_y}, phbc{(F)g.phb_x, (F)-g.phb_y};
   const V2 zero{(F)0, (F)0};
   const double2 zero64 = make_double2(0.0, 0.0);
 
-  auto row = [&](long long gi) -> V2 { return ok ? X[gi * ncol + c] : zero; };
+  auto row = [&](long long gi) -> V2 {
+    if (!ok) return zero;
+    V2 v = X[gi * ncol + c];
+    if (cj) v.y = -v.y;
+    return v;
+  };
 
   V2 q[NQ];  // q[RAD + d] = row of plane z + d
 #pragma unroll
@@ -132,7 +140,7 @@ __global__ __launch_bounds__(64, (ApplyMinWaves<F, NMU>::value)) void k_apply_co
     const long long gi = base + p;
     const V2 u = q[RAD];
     const F dr = (F)(ec - A.V[gi] + g.diag0);
-    const F gzz = (F)A.gz[z];
+    const F gzz = (F)(cj ? -A.gz[z] : A.gz[z]);
     V2 y{dr * u.x - gzz * u.y, dr * u.y + gzz * u.x};
 #pragma unroll
     for (int j = 1; j <= RAD; ++j) {
@@ -202,6 +210,7 @@ __global__ __launch_bounds__(64, (ApplyMinWaves<F, NMU>::value)) void k_apply_co
       y.x -= (F)sx;
       y.y -= (F)sy;
     }
+    if (cj) y.y = -y.y;
     if (ok) Y[gi * ncol + c] = y;
 #pragma unroll
     for (int s = 0; s < NQ - 1; ++s) q[s] = q[s + 1];

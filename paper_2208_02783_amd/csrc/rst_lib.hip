@@ -24,6 +24,7 @@
 #include "rst_mixed.hpp"
 #include "rst_mk.hpp"
 #include "rst_idr.hpp"
+#include "rst_cocg2.hpp"
 #include "rst_eig.hpp"
 #include "rst_zeig.hpp"
 
@@ -137,8 +138,9 @@ struct rst_ctx {
   DevBuf d_lrB, d_lrX, d_lrY, d_lrQ, d_lrQ2, d_lrG, d_lrR, d_lrW, d_lrL, d_lrRc, d_lrT, d_lrYacc, d_lrYacc2, d_lrQf;
   // eigen route: subspace blocks, Ritz vectors, small matrices
   DevBuf d_egQ, d_egY, d_egW, d_egX, d_egKX, d_egS, d_egG, d_egR, d_egRm, d_egL, d_egTh, d_egRes, d_egMap, d_egSc;
-  // many-column solvers, mixed mode: FP64 x and r; per-column right-hand-side offsets and budgets
-  DevBuf d_mkv64, d_mkref;
+  // many-column solvers, mixed mode: FP64 x and r; per-column right-hand-side offsets and budgets;
+  // doubled COCG: per-column conjugation flags and per-pair state
+  DevBuf d_mkv64, d_mkref, d_mkcfl, d_mkcd;
   // solver
   rst_solver_opts opts;
   // work buffers (grown on demand)
@@ -361,7 +363,7 @@ int apply_strip(int na, int P) { return P <= 512 ? na : std::min(na, rst::APPLY_
 // (nullable) the columns to apply.  ev (nullable): three events recorded before,
 // between and after the two kernels.
 rst_status apply_cols(rst_ctx* c, const void* x, void* y, int ncol, double energy, const double* ecol,
-                      const int* mask, bool f32, double2* projP, hipEvent_t* ev) {
+                      const int* mask, bool f32, double2* projP, hipEvent_t* ev, const int* cfl = nullptr) {
   const int P = c->na * c->nb;  // rst_set_grid guarantees na, nb > rad: one wrap at most
   // planes per wave: short segments keep the waves that share lateral rows close in z
   const int zseg = std::min(c->nz, rst::APPLY_ZSEG);
@@ -382,6 +384,7 @@ rst_status apply_cols(rst_ctx* c, const void* x, void* y, int ncol, double energ
   A.strip = apply_strip(c->na, P);
   A.ecol = ecol;
   A.mask = mask;
+  A.cfl = cfl;
   if (ev) HIPCHK(c, hipEventRecord(ev[0], c->stream));
   if (c->nproj > 0) {
     // all projections P = h^3 B^H x at once on the matrix cores; the apply kernel then scatters B E P
@@ -399,6 +402,7 @@ rst_status apply_cols(rst_ctx* c, const void* x, void* y, int ncol, double energ
     M.nm = c->nm;
     M.ngroup = c->ngroup;
     M.ncol = ncol;
+    M.cfl = cfl;
     M.h3 = c->ha * c->hb * c->hz;
     const long long tiles = (long long)c->ngroup * ((ncol + 63) / 64);  // one workgroup per (group, 64 columns)
     if (f32)
@@ -766,8 +770,18 @@ rst_status run_solver(rst_ctx* c, int ne, const double* energies, const std::vec
     return run_fgmres(c, ne, energies, cols, d_gdst, hsrc, xout, Tcol, its, rss, res, st, ms);
   }
   if (c->opts.method == RST_COCG) {
-    const std::vector<double>* hsrc = d_gsrc == nullptr ? nullptr : (d_gsrc == c->d_gr.p ? &c->gr : &c->gl);
-    return run_cocg(c, ne, energies, cols, d_gdst, hsrc, xout, Tcol, its, rss, res, st, ms);
+    // a real H_k (A complex symmetric) on a plane the persistent kernels hold: the blocked COCG;
+    // otherwise COCG on the doubled k / -k system over many columns
+    const rst::Geo g0 = make_geo(c);
+    const bool real_hk = std::fabs(g0.pha_y) <= 1e-12 && std::fabs(g0.phb_y) <= 1e-12;
+    if (real_hk && c->na * c->nb <= 2 * rst::MAX_T && persistent_order(c->rad) && rhs == nullptr) {
+      const std::vector<double>* hsrc = d_gsrc == nullptr ? nullptr : (d_gsrc == c->d_gr.p ? &c->gr : &c->gl);
+      return run_cocg(c, ne, energies, cols, d_gdst, hsrc, xout, Tcol, its, rss, res, st, ms);
+    }
+    if (c->opts.col_block > 0 || c->opts.threads > 0)
+      return fail(c, RST_EUNSUPPORTED, "col_block and threads apply to the blocked COCG (a real H_k)");
+    return run_bicgstab_mk(c, ne, energies, cols, d_gsrc, d_gdst, xout, Tcol, its, rss, res, st, ms, rhs, rhs_ld,
+                           rhs_estride);
   }
   // the persistent kernels hold a whole lateral plane per workgroup; wider planes go to the
   // many-column BiCGSTAB, one kernel per step
@@ -1508,19 +1522,23 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
   const bool idr = c->opts.method == RST_IDRS || (c->opts.method == RST_BICGSTAB && P > 2 * rst::MAX_T);
   const int sdim = idr ? c->opts.idr_s : 0;
   const bool mixed = c->opts.precision == RST_FP32_REFINE;
+  // COCG on the doubled k / -k system (generic k; run_solver sends the real-H_k points to the
+  // persistent COCG): a block of ld columns holds ld/2 (energy, column) pairs
+  const bool cocg2 = c->opts.method == RST_COCG;
   if (mixed && !idr)
     return fail(c, RST_EUNSUPPORTED, "the many-column BiCGSTAB runs in FP64 only (mixed precision: RST_IDRS)");
   // block width: vectors X R R0 P V T (+ PH SH W with the preconditioner); IDR(s): X R V T G_0..G_{s-1}
   // U_0..U_{s-1} (+ VH W), complex64 in the mixed mode, which adds the FP64 x and r; at most a quarter
   // of free memory
-  const int nvec = idr ? (4 + 2 * sdim + (pc ? 2 : 0)) : (pc ? 9 : 6);
+  const int nvec = cocg2 ? (pc ? 6 : 5) : idr ? (4 + 2 * sdim + (pc ? 2 : 0)) : (pc ? 9 : 6);
   const size_t esz = mixed ? 8 : 16;
   size_t free_b = 0, total_b = 0;
   HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
   const size_t per_col = (size_t)nvec * n * esz + (mixed ? (size_t)2 * n * 16 : 0) + (size_t)c->nproj * 16;
   long long ldmax = std::max<long long>(64, (long long)(free_b / 4 / per_col) / 64 * 64);
   ldmax = std::min<long long>(ldmax, 1024);
-  const int ld = (int)std::min<long long>(ldmax, (nitems + 63) / 64 * 64);
+  const int ld = (int)std::min<long long>(ldmax, ((cocg2 ? 2 : 1) * nitems + 63) / 64 * 64);
+  const int per_blk = cocg2 ? ld / 2 : ld;  // items per block
   rst::mk::Shape S;
   S.n = n;
   S.ld = ld;
@@ -1628,13 +1646,16 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     tabs(d + 8 * na, nb, false, FB);
     tabs(d + 8 * na, nb, true, IB);
     // banded L D L^T of the z operator per (energy, lateral mode)
+    // (the doubled COCG adds the conjugate-space factors of every energy as entries ne..2ne-1)
+    const int nef = cocg2 ? 2 * ne : ne;
     std::vector<double> en(energies, energies + ne);
+    if (cocg2) en.insert(en.end(), energies, energies + ne);
     if ((e = upload(c, c->d_en, en)) != RST_OK) return e;
-    if ((e = ensure(c, c->d_pc_inv, (size_t)ne * n * 16 * (1 + c->rad))) != RST_OK) return e;
+    if ((e = ensure(c, c->d_pc_inv, (size_t)nef * n * 16 * (1 + c->rad))) != RST_OK) return e;
     rst::mk::Band Bd;
     std::memset(&Bd, 0, sizeof(Bd));
     Bd.dinv = (double2*)c->d_pc_inv.p;
-    Bd.L = Bd.dinv + (size_t)ne * n;
+    Bd.L = Bd.dinv + (size_t)nef * n;
     Bd.energies = (const double*)c->d_en.p;
     Bd.eps = (const double*)c->d_pc_eps.p;
     Bd.gz = (const double*)c->d_gz.p;
@@ -1657,8 +1678,9 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     Bd.shift = c->opts.pc_shift;
     Bd.P = P;
     Bd.nz = nz;
-    Bd.ne = ne;
-    const long long nt = (long long)ne * P;
+    Bd.ne = nef;
+    Bd.neg_from = ne;
+    const long long nt = (long long)nef * P;
     hipLaunchKernelGGL(rst::mk::k_mk_band_factor, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream, Bd);
     HIPCHK(c, hipGetLastError());
     band_L = Bd.L;
@@ -1685,9 +1707,13 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
                                       (int)dft_lds(N)));
   // out = the DFT pass of `in` for the columns of `mask` (factored where N has an instance); f32:
   // complex64 vectors
-  auto dft = [&](const void* in, void* out, const DftTabs& tb, bool axis_a, const int* mask,
-                 bool f32) -> rst_status {
+  const int* pc_cfl = nullptr;  // columns preconditioned in the conjugate space (doubled COCG)
+  auto dft = [&](const void* in, void* out, const DftTabs& tb, bool axis_a, const int* mask, bool f32, int cin,
+                 int cout) -> rst_status {
     rst::mk::DftPass D;
+    D.cfl = pc_cfl;
+    D.cin = cin;
+    D.cout = cout;
     D.in = in;
     D.out = out;
     D.w = tb.w;
@@ -1715,8 +1741,8 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
   // out = M^-1 in (Wp: a work vector of the same type)
   auto precondition = [&](const void* in, void* out, void* Wp, const int* mask, bool f32) -> rst_status {
     rst_status ps;
-    if ((ps = dft(in, Wp, FA, true, mask, f32)) != RST_OK) return ps;
-    if ((ps = dft(Wp, out, FB, false, mask, f32)) != RST_OK) return ps;
+    if ((ps = dft(in, Wp, FA, true, mask, f32, 1, 0)) != RST_OK) return ps;
+    if ((ps = dft(Wp, out, FB, false, mask, f32, 0, 0)) != RST_OK) return ps;
     const long long nt = (long long)P * ld;
     const dim3 gb((unsigned)((nt + 255) / 256));
     {
@@ -1726,12 +1752,12 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
                       (void*)&nz, (void*)&ld};
       HIPCHK(c, hipLaunchKernel(kb, gb, dim3(256), args, 0, c->stream));
     }
-    if ((ps = dft(out, Wp, IB, false, mask, f32)) != RST_OK) return ps;
-    return dft(Wp, out, IA, true, mask, f32);
+    if ((ps = dft(out, Wp, IB, false, mask, f32, 0, 0)) != RST_OK) return ps;
+    return dft(Wp, out, IA, true, mask, f32, 0, 1);
   };
   // y = A x on the block (f32: complex64 vectors, the FP32 stencil)
-  auto apply = [&](const void* x, void* y, const int* mask, bool f32) -> rst_status {
-    return apply_cols(c, x, y, ld, 0.0, d_ecol, mask, f32, (double2*)c->d_projP.p, nullptr);
+  auto apply = [&](const void* x, void* y, const int* mask, bool f32, const int* cfl = nullptr) -> rst_status {
+    return apply_cols(c, x, y, ld, 0.0, d_ecol, mask, f32, (double2*)c->d_projP.p, nullptr, cfl);
   };
   const dim3 gred((unsigned)(ld / 64), (unsigned)S.nsplit);
   const unsigned gsc = (unsigned)ld;  // one wavefront per column in the scalar and sum kernels
@@ -1765,22 +1791,162 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
   const double2* Psh = (const double2*)c->d_mkshadow.p;
   std::vector<int> hact(ld), hmark(ld);
   std::vector<double2> hpart;
-  for (long long it0 = 0; it0 < nitems; it0 += ld) {
-    const int nc = (int)std::min<long long>(ld, nitems - it0);
+  // doubled COCG on one block of m = ld/2 pairs (rst_cocg2.hpp): X, R, P, Q, Z (+ W) in d_mkv;
+  // columns cc < m run the operator as A_-k (conjugated), columns cc >= m the preconditioner as
+  // M_-k^-1 (conjugated, the factor entries ne..2ne-1)
+  auto run_cocg2 = [&](int nc) -> rst_status {
+    const int m = per_blk;
+    double2* Xc = (double2*)c->d_mkv.p;
+    double2* Rc = Xc + vlen;
+    double2* Pc = Rc + vlen;
+    double2* Qc = Pc + vlen;
+    double2* Zc = pc ? Qc + vlen : Rc;  // M^-1 r (swapped halves), or r itself without M^-1
+    double2* Wc = pc ? Zc + vlen : nullptr;
+    const int zsw = pc ? 1 : 0;
+    rst_status rs;
+    if ((rs = ensure(c, c->d_mkcfl, (size_t)2 * ld * 4)) != RST_OK) return rs;
+    if ((rs = ensure(c, c->d_mkcd, (size_t)m * sizeof(rst::cd::CdSt))) != RST_OK) return rs;
+    int* cfl_ap = (int*)c->d_mkcfl.p;
+    int* cfl_pc = cfl_ap + ld;
+    {
+      std::vector<int> fl(2 * (size_t)ld, 0);
+      for (int cc = 0; cc < ld; ++cc) {
+        fl[cc] = cc < m ? 1 : 0;
+        fl[ld + cc] = cc >= m ? 1 : 0;
+      }
+      HIPCHK(c, hipMemcpyAsync(cfl_ap, fl.data(), fl.size() * 4, hipMemcpyHostToDevice, c->stream));
+    }
+    rst::cd::CdSt* dcd = (rst::cd::CdSt*)c->d_mkcd.p;
+    std::vector<rst::cd::CdSt> hcd(m);
+    auto cscal = [&](int step, int* actp, const int* mk_) -> rst_status {
+      hipLaunchKernelGGL(rst::cd::k_cd_scalar, dim3((unsigned)m), dim3(64), 0, c->stream, S, m, step, dcd, actp, mk_,
+                         (const double2*)part, c->opts.tol, c->opts.max_iter);
+      HIPCHK(c, hipGetLastError());
+      return RST_OK;
+    };
+    auto zstep = [&](const int* msk) -> rst_status {  // Z = K r (swapped), or r itself
+      if (!pc) return RST_OK;
+      pc_cfl = cfl_pc;
+      rst_status r2 = precondition(Rc, Zc, Wc, msk, false);
+      pc_cfl = nullptr;
+      return r2;
+    };
+    // start: x = p = 0, r = b, z = K r, rho = r^T z, p = z
+    hipLaunchKernelGGL(rst::cd::k_cd_init, gred, dim3(256), 0, c->stream, S, B, Xc, Rc, Pc, part);
+    if ((rs = cscal(rst::cd::CD_INIT, act, nullptr)) != RST_OK) return rs;
+    if ((rs = zstep(act)) != RST_OK) return rs;
+    hipLaunchKernelGGL(rst::cd::k_cd_dot, gred, dim3(256), 0, c->stream, S, m, (const int*)act, (const double2*)Rc,
+                       (const double2*)Zc, zsw, part);
+    if ((rs = cscal(rst::cd::CD_RHO, act, nullptr)) != RST_OK) return rs;
+    hipLaunchKernelGGL(rst::cd::k_cd_p, gred, dim3(256), 0, c->stream, S, m, (const rst::cd::CdSt*)dcd,
+                       (const int*)act, Pc, (const double2*)Zc, zsw);
+    HIPCHK(c, hipGetLastError());
+    for (;;) {
+      // q = B p (Q holds its halves swapped), alpha = rho / p^T q, x += alpha p, r -= alpha q
+      if ((rs = apply(Pc, Qc, act, false, cfl_ap)) != RST_OK) return rs;
+      hipLaunchKernelGGL(rst::cd::k_cd_dot, gred, dim3(256), 0, c->stream, S, m, (const int*)act,
+                         (const double2*)Pc, (const double2*)Qc, 1, part);
+      if ((rs = cscal(rst::cd::CD_ALPHA, act, nullptr)) != RST_OK) return rs;
+      hipLaunchKernelGGL(rst::cd::k_cd_xr, gred, dim3(256), 0, c->stream, S, m, (const rst::cd::CdSt*)dcd,
+                         (const int*)act, Xc, Rc, (const double2*)Pc, (const double2*)Qc, part);
+      if ((rs = cscal(rst::cd::CD_CONV, act, nullptr)) != RST_OK) return rs;
+      // z = K r, beta = r^T z / rho, p = z + beta p
+      if ((rs = zstep(act)) != RST_OK) return rs;
+      hipLaunchKernelGGL(rst::cd::k_cd_dot, gred, dim3(256), 0, c->stream, S, m, (const int*)act,
+                         (const double2*)Rc, (const double2*)Zc, zsw, part);
+      if ((rs = cscal(rst::cd::CD_BETA, act, nullptr)) != RST_OK) return rs;
+      hipLaunchKernelGGL(rst::cd::k_cd_p, gred, dim3(256), 0, c->stream, S, m, (const rst::cd::CdSt*)dcd,
+                         (const int*)act, Pc, (const double2*)Zc, zsw);
+      HIPCHK(c, hipGetLastError());
+      HIPCHK(c, hipMemcpyAsync(hcd.data(), dcd, m * sizeof(rst::cd::CdSt), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(hact.data(), act, ld * 4, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      int nmark = 0, nact = 0;
+      for (int j = 0; j < ld; ++j) hmark[j] = 0;
+      for (int j = 0; j < m; ++j) {
+        const bool stop = hcd[j].done == 0 && !hact[j] && (hcd[j].check || hcd[j].brk);
+        hmark[j] = hmark[j + m] = stop ? 1 : 0;
+        nmark += stop;
+        nact += hact[j];
+      }
+      if (nmark > 0) {
+        // stopped pairs: the true residual b - B x decides between done and a restart from it
+        HIPCHK(c, hipMemcpyAsync(mark, hmark.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+        if ((rs = apply(Xc, Qc, mark, false, cfl_ap)) != RST_OK) return rs;
+        hipLaunchKernelGGL(rst::cd::k_cd_resid, gred, dim3(256), 0, c->stream, S, m, B, (const int*)mark,
+                           (const double2*)Qc, Rc, part);
+        HIPCHK(c, hipGetLastError());
+        hpart.resize((size_t)S.nsplit * ld);
+        HIPCHK(c, hipMemcpyAsync(hpart.data(), part, hpart.size() * 16, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        std::vector<int> rmark(ld, 0);
+        int nrestart = 0;
+        for (int j = 0; j < m; ++j) {
+          if (!hmark[j]) continue;
+          double rr = 0.0;
+          for (int r = 0; r < S.nsplit; ++r) rr += hpart[(size_t)r * ld + j].x + hpart[(size_t)r * ld + j + m].x;
+          rst::cd::CdSt& q = hcd[j];
+          const double rel = q.bb > 0 ? std::sqrt(rr / q.bb) : 0.0;
+          q.check = q.brk = 0;
+          if (rel <= c->opts.tol) {
+            q.done = 1;
+            q.rr = rel;
+          } else if (q.its >= c->opts.max_iter || !std::isfinite(rel) || q.restarts >= 1000) {
+            q.done = 2;
+            q.rr = rel;
+          } else {
+            q.restarts += 1;
+            q.rr = q.rrmin = rr;
+            rmark[j] = rmark[j + m] = 1;
+            hact[j] = hact[j + m] = 1;
+            ++nrestart;
+          }
+        }
+        HIPCHK(c, hipMemcpyAsync(dcd, hcd.data(), m * sizeof(rst::cd::CdSt), hipMemcpyHostToDevice, c->stream));
+        if (nrestart > 0) {
+          // restart the marked pairs from their true residual (now in R): z = K r, rho, p = z
+          HIPCHK(c, hipMemcpyAsync(mark, rmark.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+          if ((rs = zstep(mark)) != RST_OK) return rs;
+          hipLaunchKernelGGL(rst::cd::k_cd_dot, gred, dim3(256), 0, c->stream, S, m, (const int*)mark,
+                             (const double2*)Rc, (const double2*)Zc, zsw, part);
+          if ((rs = cscal(rst::cd::CD_RHO, mark, nullptr)) != RST_OK) return rs;
+          hipLaunchKernelGGL(rst::cd::k_cd_p, gred, dim3(256), 0, c->stream, S, m, (const rst::cd::CdSt*)dcd,
+                             (const int*)mark, Pc, (const double2*)Zc, zsw);
+          HIPCHK(c, hipGetLastError());
+          HIPCHK(c, hipMemcpyAsync(act, hact.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
+          nact += nrestart;
+        }
+      }
+      if (nact == 0) break;
+    }
+    for (int j = 0; j < nc; ++j) {
+      hst[j].its = hcd[j].its;
+      hst[j].restarts = hcd[j].restarts;
+      hst[j].rr = hcd[j].rr;
+      hst[j].done = hcd[j].done;
+    }
+    return RST_OK;
+  };
+  for (long long it0 = 0; it0 < nitems; it0 += per_blk) {
+    const int nc = (int)std::min<long long>(per_blk, nitems - it0);
     std::vector<double> ecol(ld, energies[0]);
     std::vector<long long> src(ld, -1), doff(ld, -1);
     std::vector<double> bsc(ld, 0.0);
     std::vector<int> eidx(ld, 0);
-    for (int j = 0; j < nc; ++j) {
+    // column cc of the block holds item it0 + cc (doubled COCG: item it0 + cc mod m in both halves,
+    // the second half's preconditioner factors at entries ne + e)
+    for (int cc = 0; cc < ld; ++cc) {
+      const int j = cocg2 ? cc % per_blk : cc;
+      if (j >= nc) continue;
       const long long it = it0 + j;
       const int ie = (int)(it / ncols), jc = (int)(it % ncols);
-      ecol[j] = energies[ie];
-      eidx[j] = ie;
+      ecol[cc] = energies[ie];
+      eidx[cc] = cocg2 && cc >= per_blk ? ne + ie : ie;
       if (rhs) {
-        doff[j] = (long long)ie * rhs_estride + jc;
+        doff[cc] = (long long)ie * rhs_estride + jc;
       } else {
-        src[j] = cols[jc];
-        bsc[j] = hsrc ? std::sqrt((*hsrc)[cols[jc] / P]) : 1.0;
+        src[cc] = cols[jc];
+        bsc[cc] = hsrc ? std::sqrt((*hsrc)[cols[jc] / P]) : 1.0;
       }
     }
     HIPCHK(c, hipMemcpyAsync(d_ecol, ecol.data(), ld * 8, hipMemcpyHostToDevice, c->stream));
@@ -1790,7 +1956,9 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     HIPCHK(c, hipMemcpyAsync(d_eidx, eidx.data(), ld * 4, hipMemcpyHostToDevice, c->stream));
     rst_status ps;
     long long col_its = 0, col_cyc = 0;
-    if (!idr) {
+    if (cocg2) {
+      if ((ps = run_cocg2(nc)) != RST_OK) return ps;
+    } else if (!idr) {
       hipLaunchKernelGGL(rst::mk::k_mk_init, gred, dim3(256), 0, c->stream, S, B, X, R, R0, Pv, part);
       HIPCHK(c, hipGetLastError());
       if ((ps = scalar(rst::mk::SC_INIT)) != RST_OK) return ps;
@@ -2088,6 +2256,7 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     }
     // outputs of the block: T over the destination CAP, the exported solutions, per-column records
     std::vector<double> tb(ld, 0.0);
+    const int xc0 = cocg2 ? per_blk : 0;  // the +k solutions of the doubled COCG
     if (d_gdst) {
       hipLaunchKernelGGL(rst::mk::k_mk_tacc, gred, dim3(256), 0, c->stream, S, P, d_gdst, Xres, part);
       hipLaunchKernelGGL(rst::mk::k_mk_sum, dim3(gsc), dim3(64), 0, c->stream, S, (const double2*)part,
@@ -2097,14 +2266,14 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     }
     if (xout) {
       hipLaunchKernelGGL(rst::mk::k_mk_export, dim3(gel), dim3(256), 0, c->stream, S, nc, Xres, xout, nitems,
-                         it0);
+                         it0, xc0);
       HIPCHK(c, hipGetLastError());
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int j = 0; j < nc; ++j) {
       const rst::mk::ColSt& q = hst[j];
       const size_t o = (size_t)(it0 + j);
-      Tcol[o] = tb[j];
+      Tcol[o] = tb[xc0 + j];
       its[o] = q.its;
       rss[o] = q.restarts;
       res[o] = q.done == 0 ? 0.0 : q.rr;
@@ -2114,7 +2283,12 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     }
     // mixed: complex64 vectors in the inner solves (half the bytes), and per cycle the FP64 apply,
     // residual and correction (x, r: 104 B per point)
-    bytes += idr ? (double)col_its * ((mixed ? 0.5 : 1.0) * idr_bytes_per_matvec(sdim, pc) * (double)n +
+    // doubled COCG: per step one apply and one M^-1 over both halves and the vector work (x, r, p
+    // updates, two dots): 2 x (apply 32 + M^-1 192 + 160) B per point
+    if (cocg2)
+      bytes += (double)col_its * (2.0 * ((pc ? 224.0 : 32.0) + 160.0) * (double)n + 2.0 * 16.0 * (double)nent);
+    else
+      bytes += idr ? (double)col_its * ((mixed ? 0.5 : 1.0) * idr_bytes_per_matvec(sdim, pc) * (double)n +
                                       16.0 * (double)nent) +
                        (double)col_cyc * (104.0 * (double)n + 16.0 * (double)nent)
                  : (double)col_its * (mk_bytes_per_point(pc) * (double)n + 2.0 * 16.0 * (double)nent);

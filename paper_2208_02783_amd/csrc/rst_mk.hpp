@@ -87,6 +87,8 @@ __device__ __forceinline__ double2 vld(const float2* p, size_t i) {
 __device__ __forceinline__ void vst(double2* p, size_t i, double2 v) { p[i] = v; }
 __device__ __forceinline__ void vst(float2* p, size_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
 
+__device__ __forceinline__ double2 cflip(double2 a, bool cj) { return cj ? make_double2(a.x, -a.y) : a; }
+
 __device__ __forceinline__ double2 rhs_at(const Rhs& B, long long gi, int c) {
   if (B.dense) {
     const long long o = B.doff[c];
@@ -397,6 +399,8 @@ struct DftPass {
   const double2* pre;  // [N] (factored evaluation): pre[i] = (w[j] / root^j)^i, the twist
   const double2* root; // [N] (factored evaluation): root^m, root = w[1] / w[0]
   const int* act;      // [ld] columns to transform (others untouched); nullable = all
+  const int* cfl;      // [ld] (nullable) flagged columns: conjugated on load (cin) and on store (cout)
+  int cin, cout;
   int N;               // points along the axis
   int stride;          // grid-index stride along the axis
   int nline_inner;     // lines per plane (axis a: nb; axis b: na)
@@ -422,8 +426,11 @@ __global__ __launch_bounds__(256) void k_mk_dft(DftPass D) {
   const int z = (int)(line / D.nline_inner), li = (int)(line % D.nline_inner);
   const long long base = (long long)z * D.P + (long long)li * D.inner_mul;
   const bool on = D.act == nullptr || D.act[c];
+  const bool cfc = D.cfl != nullptr && D.cfl[c] != 0;
+  const bool cjin = cfc && D.cin, cjout = cfc && D.cout;
   for (int i = wv; i < N; i += 4)
-    lin[i * 64 + lane] = on ? vld(in, (size_t)(base + (long long)i * D.stride) * D.ld + c) : make_double2(0.0, 0.0);
+    lin[i * 64 + lane] = on ? cflip(vld(in, (size_t)(base + (long long)i * D.stride) * D.ld + c), cjin)
+                            : make_double2(0.0, 0.0);
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     tw[i] = D.w[i];
     tp[i] = D.post[i];
@@ -450,7 +457,7 @@ __global__ __launch_bounds__(256) void k_mk_dft(DftPass D) {
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
       const int j = jb + wv + 4 * r;
-      if (j < N) vst(out, (size_t)(base + (long long)j * D.stride) * D.ld + c, c_mul(tp[j], acc[r]));
+      if (j < N) vst(out, (size_t)(base + (long long)j * D.stride) * D.ld + c, cflip(c_mul(tp[j], acc[r]), cjout));
     }
   }
 }
@@ -483,6 +490,8 @@ __global__ __launch_bounds__(64 * NW, MINW) void k_mk_fft(DftPass D) {
   const int z = (int)(line / D.nline_inner), li = (int)(line % D.nline_inner);
   const long long base = (long long)z * D.P + (long long)li * D.inner_mul;
   const bool on = D.act == nullptr || D.act[c];
+  const bool cfc = D.cfl != nullptr && D.cfl[c] != 0;
+  const bool cjin = cfc && D.cin, cjout = cfc && D.cout;
   for (int i = threadIdx.x; i < N; i += 64 * NW) {
     troot[i] = D.root[i];
     tpre[i] = D.pre[i];
@@ -496,7 +505,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void k_mk_fft(DftPass D) {
     const int n2 = wv + g * NW;
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1)
-      v[g][n1] = on && n2 < N2 ? vld(in, (size_t)(base + (long long)(N2 * n1 + n2) * D.stride) * D.ld + c)
+      v[g][n1] = on && n2 < N2 ? cflip(vld(in, (size_t)(base + (long long)(N2 * n1 + n2) * D.stride) * D.ld + c), cjin)
                                : make_double2(0.0, 0.0);
   }
 #pragma unroll
@@ -533,7 +542,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void k_mk_fft(DftPass D) {
         acc.y = fma(u[n2].x, r.y, fma(u[n2].y, r.x, acc.y));
       }
       const int j = k1 + N1 * k2;
-      vst(out, (size_t)(base + (long long)j * D.stride) * D.ld + c, c_mul(tpost[j], acc));
+      vst(out, (size_t)(base + (long long)j * D.stride) * D.ld + c, cflip(c_mul(tpost[j], acc), cjout));
     }
   }
 }
@@ -557,6 +566,8 @@ struct Band {
   double cz[7];        // c_j / (2 hz^2), j = 0..M
   double shift;        // imaginary shift added to the CAP (Ha)
   int M, P, nz, ne;
+  int neg_from;        // energy entries e >= neg_from factor the conjugate-space operator: imaginary
+                       // part -(Gamma + shift) (the -k half of the doubled COCG); ne: none
 };
 
 __global__ __launch_bounds__(256) void k_mk_band_factor(Band B) {
@@ -584,7 +595,7 @@ __global__ __launch_bounds__(256) void k_mk_band_factor(Band B) {
       }
       Lr[k] = c_div(acc, D[k]);
     }
-    double2 dz = make_double2(d0 - B.vz[z], B.gz[z] + B.shift);
+    double2 dz = make_double2(d0 - B.vz[z], (e >= B.neg_from ? -1.0 : 1.0) * (B.gz[z] + B.shift));
     for (int k = 1; k <= M; ++k)
       if (z - k >= 0) dz = c_sub(dz, c_mul(c_mul(Lr[k], Lr[k]), D[k]));
     double2* Lo = L + ((size_t)z * P + m) * M;
@@ -698,13 +709,13 @@ __global__ __launch_bounds__(64) void k_mk_sum(Shape S, const double2* part, dou
   if (threadIdx.x == 0) out[blockIdx.x] = s.x;
 }
 
-// Export of the block's first nc columns: xout[gi*xld + it0 + c] = X[gi*ld + c].
+// Export of nc columns from column c0 on: xout[gi*xld + it0 + c] = X[gi*ld + c0 + c].
 __global__ __launch_bounds__(256) void k_mk_export(Shape S, int nc, const double2* X, double2* xout, long long xld,
-                                                   long long it0) {
+                                                   long long it0, int c0) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= S.n * S.ld) return;
-  const int c = (int)(t % S.ld);
-  if (c >= nc) return;
+  const int c = (int)(t % S.ld) - c0;
+  if (c < 0 || c >= nc) return;
   const long long gi = t / S.ld;
   xout[gi * xld + it0 + c] = X[t];
 }

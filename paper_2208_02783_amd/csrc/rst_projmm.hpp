@@ -41,6 +41,7 @@ struct ProjMMArgs {
   int cw;
   long long n;
   size_t p_stride;
+  const int* cfl;         // [ncol] (nullable, column-fastest only): the column's x enters conjugated
 };
 
 // XT: element type of X (double2, or float2 for a complex64 apply: widened to FP64 on load)
@@ -78,7 +79,8 @@ __global__ __launch_bounds__(256) void k_proj_mm(ProjMMArgs A) {
       if (k < ne && col < A.ncol) {
         const size_t xo = A.cw ? ((size_t)(col / A.cw) * A.n + gi) * A.cw + col % A.cw : (size_t)gi * A.ncol + col;
         const XT xv = X[xo];
-        const double2 x = make_double2((double)xv.x, (double)xv.y);
+        const bool cj = A.cfl != nullptr && A.cfl[col] != 0;
+        const double2 x = make_double2((double)xv.x, cj ? -(double)xv.y : (double)xv.y);
         xr = ph.x * x.x + ph.y * x.y;  // conj(ph) * x
         xi = ph.x * x.y - ph.y * x.x;
       }
