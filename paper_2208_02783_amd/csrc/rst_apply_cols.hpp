@@ -78,7 +78,9 @@ struct ApplyMinWaves {
   static constexpr int value = std::is_same<F, float>::value && NMU <= 9 ? 4 : 1;
 };
 
-template <int RAD, int NMU, class F>
+// CJ: the instance honours the conjugate-space flags (cfl); the others ignore them, so the hot
+// instances carry no extra work.
+template <int RAD, int NMU, class F, bool CJ = false>
 __global__ __launch_bounds__(64, (ApplyMinWaves<F, NMU>::value)) void k_apply_cols(ColApplyArgs A) {
   using V2 = typename std::conditional<std::is_same<F, double>::value, double2, float2>::type;
   constexpr int NQ = 2 * RAD + 1;
@@ -113,16 +115,17 @@ __global__ __launch_bounds__(64, (ApplyMinWaves<F, NMU>::value)) void k_apply_co
   const int c = chunk * 64 + (int)threadIdx.x;
   const bool ok = c < ncol && (A.mask == nullptr || A.mask[c] != 0);
   const double ec = A.ecol != nullptr && c < ncol ? A.ecol[c] : A.energy;
-  const bool cj = A.cfl != nullptr && c < ncol && A.cfl[c] != 0;
+  // conjugate-space columns: sign of the imaginary parts of the loaded and stored rows and of the CAP
+  // (a multiply, no branch, so the row loads below stay one unconditional group)
+  const F ysg = CJ && A.cfl != nullptr && c < ncol && A.cfl[c] != 0 ? (F)-1 : (F)1;
   const V2 pha{(F)g.pha_x, (F)g.pha_y}, phac{(F)g.pha_x, (F)-g.pha_y};
   const V2 phb{(F)g.phb_x, (F)g.phb_y}, phbc{(F)g.phb_x, (F)-g.phb_y};
   const V2 zero{(F)0, (F)0};
   const double2 zero64 = make_double2(0.0, 0.0);
 
   auto row = [&](long long gi) -> V2 {
-    if (!ok) return zero;
-    V2 v = X[gi * ncol + c];
-    if (cj) v.y = -v.y;
+    V2 v = ok ? X[gi * ncol + c] : zero;
+    if (CJ) v.y *= ysg;
     return v;
   };
 
@@ -140,7 +143,7 @@ __global__ __launch_bounds__(64, (ApplyMinWaves<F, NMU>::value)) void k_apply_co
     const long long gi = base + p;
     const V2 u = q[RAD];
     const F dr = (F)(ec - A.V[gi] + g.diag0);
-    const F gzz = (F)(cj ? -A.gz[z] : A.gz[z]);
+    const F gzz = CJ ? (F)A.gz[z] * ysg : (F)A.gz[z];
     V2 y{dr * u.x - gzz * u.y, dr * u.y + gzz * u.x};
 #pragma unroll
     for (int j = 1; j <= RAD; ++j) {
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(64, (ApplyMinWaves<F, NMU>::value)) void k_apply_co
       y.x -= (F)sx;
       y.y -= (F)sy;
     }
-    if (cj) y.y = -y.y;
+    if (CJ) y.y *= ysg;
     if (ok) Y[gi * ncol + c] = y;
 #pragma unroll
     for (int s = 0; s < NQ - 1; ++s) q[s] = q[s + 1];

@@ -335,9 +335,12 @@ rst_status proj_blocked(rst_ctx* c, const rst::ApplyArgs& A) {
 }
 
 // k_apply_cols instance for a stencil radius (FD order 2..12), projector group size and precision.
-void* apply_cols_kernel(int rad, bool nm9, bool f32) {
+void* apply_cols_kernel(int rad, bool nm9, bool f32, bool cj) {
 #define RST_APPLY_PICK(R)                                                                          \
   if (rad == R) {                                                                                  \
+    if (cj && !f32)                                                                                \
+      return nm9 ? (void*)rst::k_apply_cols<R, 9, double, true> : (void*)rst::k_apply_cols<R, 16, double, true>; \
+    if (cj) return nullptr;                                                                        \
     if (f32) return nm9 ? (void*)rst::k_apply_cols<R, 9, float> : (void*)rst::k_apply_cols<R, 16, float>; \
     return nm9 ? (void*)rst::k_apply_cols<R, 9, double> : (void*)rst::k_apply_cols<R, 16, double>; \
   }
@@ -413,7 +416,7 @@ rst_status apply_cols(rst_ctx* c, const void* x, void* y, int ncol, double energ
     A.P = projP;
   }
   if (ev) HIPCHK(c, hipEventRecord(ev[1], c->stream));
-  void* kern = apply_cols_kernel(c->rad, c->nm <= 9, f32);
+  void* kern = apply_cols_kernel(c->rad, c->nm <= 9, f32, cfl != nullptr);
   if (!kern) return fail(c, RST_EUNSUPPORTED, "no many-column apply for this FD order");
   {
     void* args[] = {&A};
@@ -1475,7 +1478,15 @@ struct FftInstance {
   const void* kern;
   int nw;
 };
-FftInstance fft_instance(int N, bool f32) {
+FftInstance fft_instance(int N, bool f32, bool cj = false) {
+  if (cj) {  // conjugate-space columns (the doubled COCG, FP64)
+    switch (N) {
+      case 8: return {(const void*)rst::mk::k_mk_fft<2, 4, 2, 1, double2, true>, 2};
+      case 16: return {(const void*)rst::mk::k_mk_fft<4, 4, 4, 1, double2, true>, 4};
+      case 54: return {(const void*)rst::mk::k_mk_fft<6, 9, 3, 1, double2, true>, 3};
+      default: return {nullptr, 0};
+    }
+  }
   if (f32) {
     switch (N) {
       case 8: return {(const void*)rst::mk::k_mk_fft<2, 4, 2, 1, float2>, 2};
@@ -1687,7 +1698,13 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     band_dinv = Bd.dinv;
   }
   // direct evaluation: the smallest instance with 4*RW >= N (N > 64 takes several rounds of 64)
-  auto dft_kernel = [](int N, bool f32) -> const void* {
+  auto dft_kernel = [](int N, bool f32, bool cj) -> const void* {
+    if (cj) {
+      if (N <= 8) return (const void*)rst::mk::k_mk_dft<2, double2, true>;
+      if (N <= 16) return (const void*)rst::mk::k_mk_dft<4, double2, true>;
+      if (N <= 32) return (const void*)rst::mk::k_mk_dft<8, double2, true>;
+      return (const void*)rst::mk::k_mk_dft<16, double2, true>;
+    }
     if (f32) {
       if (N <= 8) return (const void*)rst::mk::k_mk_dft<2, float2>;
       if (N <= 16) return (const void*)rst::mk::k_mk_dft<4, float2>;
@@ -1701,9 +1718,9 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
   };
   auto dft_lds = [](int N) -> size_t { return ((size_t)N * 64 + 2 * (size_t)N) * 16; };
   for (int N : {na, nb})
-    for (bool f32 : {false, true})
-      if (!fft_instance(N, f32).kern && dft_lds(N) > 64 * 1024)
-        HIPCHK(c, hipFuncSetAttribute(dft_kernel(N, f32), hipFuncAttributeMaxDynamicSharedMemorySize,
+    for (int v = 0; v < 3; ++v)  // complex128, complex64, conjugate-space complex128
+      if (!fft_instance(N, v == 1, v == 2).kern && dft_lds(N) > 64 * 1024)
+        HIPCHK(c, hipFuncSetAttribute(dft_kernel(N, v == 1, v == 2), hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)dft_lds(N)));
   // out = the DFT pass of `in` for the columns of `mask` (factored where N has an instance); f32:
   // complex64 vectors
@@ -1730,11 +1747,12 @@ rst_status run_bicgstab_mk(rst_ctx* c, int ne, const double* energies, const std
     D.ld = ld;
     const long long nwg = (long long)nz * D.nline_inner * (ld / 64);
     void* args[] = {&D};
-    const FftInstance fi = fft_instance(D.N, f32);
+    const bool cj = pc_cfl != nullptr && (cin || cout);
+    const FftInstance fi = fft_instance(D.N, f32, cj);
     if (fi.kern)
       HIPCHK(c, hipLaunchKernel(fi.kern, dim3((unsigned)nwg), dim3(64 * fi.nw), args, 0, c->stream));
     else
-      HIPCHK(c, hipLaunchKernel(dft_kernel(D.N, f32), dim3((unsigned)nwg), dim3(256), args, dft_lds(D.N),
+      HIPCHK(c, hipLaunchKernel(dft_kernel(D.N, f32, cj), dim3((unsigned)nwg), dim3(256), args, dft_lds(D.N),
                                 c->stream));
     return RST_OK;
   };

@@ -87,7 +87,7 @@ __device__ __forceinline__ double2 vld(const float2* p, size_t i) {
 __device__ __forceinline__ void vst(double2* p, size_t i, double2 v) { p[i] = v; }
 __device__ __forceinline__ void vst(float2* p, size_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
 
-__device__ __forceinline__ double2 cflip(double2 a, bool cj) { return cj ? make_double2(a.x, -a.y) : a; }
+__device__ __forceinline__ double2 cflip(double2 a, double sg) { return make_double2(a.x, sg * a.y); }
 
 __device__ __forceinline__ double2 rhs_at(const Rhs& B, long long gi, int c) {
   if (B.dense) {
@@ -408,7 +408,9 @@ struct DftPass {
   int P, nz, ld;
 };
 
-template <int RW, class VT = double2>
+// CJ: the instance honours the conjugation flags (cfl, cin, cout); the others ignore them (reading
+// them measurably slowed the pass).
+template <int RW, class VT = double2, bool CJ = false>
 __global__ __launch_bounds__(256) void k_mk_dft(DftPass D) {
   const VT* in = (const VT*)D.in;
   VT* out = (VT*)D.out;
@@ -426,8 +428,8 @@ __global__ __launch_bounds__(256) void k_mk_dft(DftPass D) {
   const int z = (int)(line / D.nline_inner), li = (int)(line % D.nline_inner);
   const long long base = (long long)z * D.P + (long long)li * D.inner_mul;
   const bool on = D.act == nullptr || D.act[c];
-  const bool cfc = D.cfl != nullptr && D.cfl[c] != 0;
-  const bool cjin = cfc && D.cin, cjout = cfc && D.cout;
+  const bool cfc = CJ && D.cfl != nullptr && D.cfl[c] != 0;
+  const double cjin = cfc && D.cin ? -1.0 : 1.0, cjout = cfc && D.cout ? -1.0 : 1.0;  // imaginary-part signs
   for (int i = wv; i < N; i += 4)
     lin[i * 64 + lane] = on ? cflip(vld(in, (size_t)(base + (long long)i * D.stride) * D.ld + c), cjin)
                             : make_double2(0.0, 0.0);
@@ -474,7 +476,7 @@ __global__ __launch_bounds__(256) void k_mk_dft(DftPass D) {
 // one (line, 64-column chunk), NW waves; wave q takes n2 = q, q + NW, ... in the
 // first stage and k1 = q, q + NW, ... in the second.  MINW: waves per SIMD asked of
 // the register allocator.
-template <int N1, int N2, int NW, int MINW, class VT = double2>
+template <int N1, int N2, int NW, int MINW, class VT = double2, bool CJ = false>
 __global__ __launch_bounds__(64 * NW, MINW) void k_mk_fft(DftPass D) {
   constexpr int N = N1 * N2;
   const VT* in = (const VT*)D.in;
@@ -490,8 +492,8 @@ __global__ __launch_bounds__(64 * NW, MINW) void k_mk_fft(DftPass D) {
   const int z = (int)(line / D.nline_inner), li = (int)(line % D.nline_inner);
   const long long base = (long long)z * D.P + (long long)li * D.inner_mul;
   const bool on = D.act == nullptr || D.act[c];
-  const bool cfc = D.cfl != nullptr && D.cfl[c] != 0;
-  const bool cjin = cfc && D.cin, cjout = cfc && D.cout;
+  const bool cfc = CJ && D.cfl != nullptr && D.cfl[c] != 0;
+  const double cjin = cfc && D.cin ? -1.0 : 1.0, cjout = cfc && D.cout ? -1.0 : 1.0;  // imaginary-part signs
   for (int i = threadIdx.x; i < N; i += 64 * NW) {
     troot[i] = D.root[i];
     tpre[i] = D.pre[i];

@@ -56,10 +56,13 @@ __global__ __launch_bounds__(256) void k_proj_mm(ProjMMArgs A) {
   const int e0 = A.grp_e0[g], ne = A.grp_ne[g], nmg = A.grp_nm[g];
   const int i16 = lane & 15, kq = lane >> 4;
   v4d re[4], im[4];
+  double ysg[4];  // -1 for conjugate-space columns (their x enters conjugated)
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     re[b] = v4d{0.0, 0.0, 0.0, 0.0};
     im[b] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int col = c0 + 16 * b + i16;
+    ysg[b] = A.cfl != nullptr && col < A.ncol && A.cfl[col] != 0 ? -1.0 : 1.0;
   }
   for (int k0 = 4 * wv; k0 < ne; k0 += 16) {
     const int k = k0 + kq;
@@ -79,8 +82,7 @@ __global__ __launch_bounds__(256) void k_proj_mm(ProjMMArgs A) {
       if (k < ne && col < A.ncol) {
         const size_t xo = A.cw ? ((size_t)(col / A.cw) * A.n + gi) * A.cw + col % A.cw : (size_t)gi * A.ncol + col;
         const XT xv = X[xo];
-        const bool cj = A.cfl != nullptr && A.cfl[col] != 0;
-        const double2 x = make_double2((double)xv.x, cj ? -(double)xv.y : (double)xv.y);
+        const double2 x = make_double2((double)xv.x, ysg[b] * (double)xv.y);
         xr = ph.x * x.x + ph.y * x.y;  // conj(ph) * x
         xi = ph.x * x.y - ph.y * x.x;
       }
