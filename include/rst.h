@@ -449,11 +449,19 @@ rst_status rst_cnn_train_step(rst_ctx *ctx, int ncol, int nz, int nb, int na, co
 
 /* Training of the network (Adam on FP32 weights).  Each step draws one energy
  * from `energies` and one lateral k from `kpts` (n_k pairs (ka, kb)), then
- * `batch` pairs: xi complex normal (SplitMix64 counter-based, Box-Muller),
- * e = M^-1 xi, r = A e with A = E - H_k + i Gamma, both scaled so that
- * ||r|| = 1; input (r, M^-1 r), target e - M^-1 r.  steps = ceil(pairs / batch).
- * Starts from the context's weights (seeded from `seed` if it has none); the
- * context's k is restored on return. */
+ * `batch` pairs (r, e) with A e = r, A = E - H_k + i Gamma; input (r, M^-1 r),
+ * target e - M^-1 r, both scaled so that ||r|| = 1 (synthetic pairs) or
+ * ||e|| = 1 (solver pairs).
+ * source 0 (synthetic): xi complex normal (SplitMix64 counter-based,
+ * Box-Muller), e = M^-1 xi, r = A e.
+ * source 1 (solver): `batch` right-CAP columns b = e_c drawn at random; x* from
+ * the FP64 preconditioned BiCGSTAB to 1e-10, then the iterates x_j after j =
+ * 2, 4, 8, ..., 64 iterations of the same solver; pairs r_j = b - A x_j,
+ * e_j = x* - x_j (the residuals and errors the solver actually leaves), one
+ * Adam step per iterate.
+ * steps = ceil(pairs / batch).  Starts from the context's weights (seeded from
+ * `seed` if it has none); the context's k and solver options are restored on
+ * return. */
 typedef struct {
   int pairs;               /* training pairs */
   int batch;               /* pairs per Adam step, 1..64 */
@@ -463,6 +471,7 @@ typedef struct {
   const double *energies;  /* host, n_e (Ha) */
   int n_k;
   const double *kpts;      /* host, 2*n_k (bohr^-1) */
+  int source;              /* 0: synthetic pairs (default), 1: pairs from solver runs */
 } rst_train_opts;
 typedef struct {
   int steps;

@@ -302,6 +302,41 @@ __global__ void k_fg_target(Shape S, const double2* E, const double2* Ms, const 
   tgt[2 * j + 1] = (float)(s[c] * E[e].y - Ms[e].y);
 }
 
+// Solver-generated training pairs: from the column-fastest n x B blocks of an iterate x_j and the
+// converged x*, the blocked x_j (into Xb) and error e_j = x* - x_j (into Eb); padding columns zero.
+__global__ void k_fg_pairs(Shape S, int B, const double2* Xs, const double2* Xj, double2* Xb, double2* Eb) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = (long long)S.nblk * S.cw * S.n;
+  if (t >= tot) return;
+  const int c = (int)(t / S.n);
+  const long long p = t % S.n;
+  const size_t e = ((size_t)(c / S.cw) * S.n + p) * S.cw + c % S.cw;
+  if (c >= B) {
+    Xb[e] = make_double2(0.0, 0.0);
+    Eb[e] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double2 xj = Xj[(size_t)p * B + c], xs = Xs[(size_t)p * B + c];
+  Xb[e] = xj;
+  Eb[e] = make_double2(xs.x - xj.x, xs.y - xj.y);
+}
+
+// R = b - R for unit right-hand sides b = e_{cols[c]} (blocked layout); padding columns zero.
+__global__ void k_fg_bsub(Shape S, int B, const long long* cols, double2* R) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = (long long)S.nblk * S.cw * S.n;
+  if (t >= tot) return;
+  const int c = (int)(t / S.n);
+  const long long p = t % S.n;
+  const size_t e = ((size_t)(c / S.cw) * S.n + p) * S.cw + c % S.cw;
+  if (c >= B) {
+    R[e] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double2 ax = R[e];
+  R[e] = make_double2((p == cols[c] ? 1.0 : 0.0) - ax.x, -ax.y);
+}
+
 // s[c] = 1 / sqrt(nrm2[c]) (0 for a zero column)
 __global__ void k_fg_rsqrt(const double2* nrm2, double* s, int ncolp) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;

@@ -141,6 +141,8 @@ struct rst_ctx {
   // many-column solvers, mixed mode: FP64 x and r; per-column right-hand-side offsets and budgets;
   // doubled COCG: per-column conjugation flags and per-pair state
   DevBuf d_mkv64, d_mkref, d_mkcfl, d_mkcd;
+  // training of the network: its energies, solver pairs (x*, x_j) and their columns
+  DevBuf d_tren, d_trX, d_trcols;
   // solver
   rst_solver_opts opts;
   // work buffers (grown on demand)
@@ -4127,8 +4129,9 @@ rst_status rst_precond_train(rst_ctx* c, const rst_train_opts* o, rst_train_stat
   rst_status s = check_ready(c);
   if (s != RST_OK) return s;
   if (!o || o->pairs < 1 || o->batch < 1 || o->batch > 64 || !(o->lr > 0.f) || o->n_e < 1 || !o->energies ||
-      o->n_k < 1 || !o->kpts)
+      o->n_k < 1 || !o->kpts || (o->source != 0 && o->source != 1))
     return fail(c, RST_EINVAL, "bad training options");
+  const bool from_solver = o->source == 1;
   for (int i = 0; i < o->n_e; ++i)
     if (!std::isfinite(o->energies[i])) return fail(c, RST_EINVAL, "non-finite energy");
   for (int i = 0; i < 2 * o->n_k; ++i)
@@ -4163,7 +4166,18 @@ rst_status rst_precond_train(rst_ctx* c, const rst_train_opts* o, rst_train_stat
   if ((s = ensure(c, c->d_pws, (size_t)nblk * pws_stride * 16)) != RST_OK) return s;
   const double ka0 = c->ka, kb0 = c->kb;
   std::vector<double> en(o->energies, o->energies + o->n_e);
-  if ((s = upload(c, c->d_en, en)) != RST_OK) return s;
+  if ((s = upload(c, c->d_tren, en)) != RST_OK) return s;
+  // solver pairs: the right-CAP columns to draw from, x* and x_j (column-fastest n x B), the columns
+  std::vector<int64_t> rcols;
+  const rst_solver_opts opts0 = c->opts;
+  if (from_solver) {
+    for (int z = 0; z < c->nz; ++z)
+      if (c->gr[z] > 0)
+        for (int q = 0; q < P; ++q) rcols.push_back((int64_t)z * P + q);
+    if (rcols.empty()) return fail(c, RST_EINVAL, "solver pairs need a right CAP");
+    if ((s = ensure(c, c->d_trX, (size_t)2 * n * B * 16)) != RST_OK) return s;
+    if ((s = ensure(c, c->d_trcols, (size_t)B * 8)) != RST_OK) return s;
+  }
   if ((s = ensure(c, c->d_pc_inv, (size_t)n * 16)) != RST_OK) return s;
   double vbar = 0;
   for (double x : c->v) vbar += x;
@@ -4180,9 +4194,14 @@ rst_status rst_precond_train(rst_ctx* c, const rst_train_opts* o, rst_train_stat
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   HIPCHK(c, hipEventRecord(e0, c->stream));
+  int jcheck = 0;  // solver pairs: the next iterate of the current draw (iterations 2^jcheck)
+  std::vector<int64_t> dcols(B);
+  int ie = 0, ik = 0;
   for (int st = 0; st < steps; ++st) {
-    const int ie = (int)(gen() % (uint64_t)o->n_e);
-    const int ik = (int)(gen() % (uint64_t)o->n_k);
+    if (!from_solver || jcheck == 0) {
+      ie = (int)(gen() % (uint64_t)o->n_e);
+      ik = (int)(gen() % (uint64_t)o->n_k);
+    }
     if (ik != cur_k) {
       c->ka = o->kpts[2 * ik];
       c->kb = o->kpts[2 * ik + 1];
@@ -4200,7 +4219,7 @@ rst_status rst_precond_train(rst_ctx* c, const rst_train_opts* o, rst_train_stat
     std::memset(&A, 0, sizeof(A));
     A.g = g;
     A.gz = (const double*)c->d_gz.p;
-    A.energies = (const double*)c->d_en.p + ie;
+    A.energies = (const double*)c->d_tren.p + ie;
     A.ne = 1;
     A.pc.vbar = vbar;
     A.pc.a = 0.5 / (c->hz * c->hz);
@@ -4233,7 +4252,7 @@ rst_status rst_precond_train(rst_ctx* c, const rst_train_opts* o, rst_train_stat
     aa[0].V = (const double*)c->d_v.p;
     aa[0].gz = (const double*)c->d_gz.p;
     aa[0].energy = o->energies[ie];
-    aa[0].x = Ev;
+    aa[0].x = from_solver ? Xi : Ev;
     aa[0].y = Rv;
     aa[0].ncol = ncolp;
     aa[0].cw = cw;
@@ -4242,19 +4261,64 @@ rst_status rst_precond_train(rst_ctx* c, const rst_train_opts* o, rst_train_stat
     aa[0].pws_stride = pws_stride;
     aa[0].proj_pre = c->nproj > 0;
     if ((s = upload(c, c->d_fgaa, aa)) != RST_OK) return s;
-    // xi -> e = M^-1 xi -> r = A e; scale to ||r|| = 1; m = M^-1 r; (features, target)
-    hipLaunchKernelGGL(rst::fg::k_fg_randn, dim3(gv), dim3(256), 0, c->stream, S,
-                       (unsigned long long)(o->seed * 0x9E3779B97F4A7C15ULL + (uint64_t)st), Xi);
     void* p0 = c->d_fgpa.p;
     void* p1 = (char*)c->d_fgpa.p + sizeof(rst::PcApplyArgs);
     void* a0 = c->d_fgaa.p;
-    void* args0[] = {&p0};
-    HIPCHK(c, hipLaunchKernel(kpc, dim3(nblk), dim3(ls.threads), args0, lds_pc, c->stream));
     void* argsa[] = {&a0};
-    if ((s = proj_blocked(c, aa[0])) != RST_OK) return s;
-    HIPCHK(c, hipLaunchKernel(kapply, dim3(nblk), dim3(ls.threads), argsa, lds_apply, c->stream));
-    hipLaunchKernelGGL(rst::fg::k_fg_dots, dim3(nblk, 1), dim3(256), 0, c->stream, S, (const double2*)Rv,
-                       (long long)vlen, 1, (const double2*)Rv, (double2*)c->d_fgn2.p, ncolp);
+    if (!from_solver) {
+      // xi -> e = M^-1 xi -> r = A e; scale to ||r|| = 1; m = M^-1 r; (features, target)
+      hipLaunchKernelGGL(rst::fg::k_fg_randn, dim3(gv), dim3(256), 0, c->stream, S,
+                         (unsigned long long)(o->seed * 0x9E3779B97F4A7C15ULL + (uint64_t)st), Xi);
+      void* args0[] = {&p0};
+      HIPCHK(c, hipLaunchKernel(kpc, dim3(nblk), dim3(ls.threads), args0, lds_pc, c->stream));
+      if ((s = proj_blocked(c, aa[0])) != RST_OK) return s;
+      HIPCHK(c, hipLaunchKernel(kapply, dim3(nblk), dim3(ls.threads), argsa, lds_apply, c->stream));
+    } else {
+      // x* (on a new draw), then the iterate x_j of the same solver after 2^(jcheck+1) iterations:
+      // e = x* - x_j, r = b - A x_j; scale to ||r|| = 1; m = M^-1 r; (features, target)
+      double2* Xs = (double2*)c->d_trX.p;
+      double2* Xj = Xs + (size_t)n * B;
+      std::vector<double> Tc, rs_;
+      std::vector<int> itc, rsc, stc;
+      double msc = 0;
+      c->opts = opts0;
+      c->opts.method = RST_BICGSTAB;
+      c->opts.precond = RST_PRECOND_FREE_CAP;
+      c->opts.precision = RST_FP64;
+      c->opts.col_block = 0;
+      c->opts.threads = 0;
+      c->opts.tol = 1e-10;
+      rst_status sv = RST_OK;
+      if (jcheck == 0) {
+        for (int b = 0; b < B; ++b) dcols[b] = rcols[gen() % (uint64_t)rcols.size()];
+        c->opts.max_iter = 20000;
+        sv = run_solver(c, 1, o->energies + ie, dcols, nullptr, nullptr, Xs, Tc, itc, rsc, rs_, stc, msc);
+      }
+      if (sv == RST_OK) {
+        c->opts.max_iter = 2 << jcheck;
+        sv = run_solver(c, 1, o->energies + ie, dcols, nullptr, nullptr, Xj, Tc, itc, rsc, rs_, stc, msc);
+      }
+      c->opts = opts0;
+      if (sv != RST_OK) return sv;
+      jcheck = jcheck + 1 < 6 ? jcheck + 1 : 0;  // iterates after 2, 4, ..., 64 iterations per draw
+      HIPCHK(c, hipMemcpyAsync(c->d_trcols.p, dcols.data(), (size_t)B * 8, hipMemcpyHostToDevice, c->stream));
+      hipLaunchKernelGGL(rst::fg::k_fg_pairs, dim3(gv), dim3(256), 0, c->stream, S, B, (const double2*)Xs,
+                         (const double2*)Xj, Xi, Ev);
+      // the solves above may have regrown the projection scratch: the apply's arguments again
+      aa[0].pws = (double2*)c->d_pws.p;
+      if ((s = upload(c, c->d_fgaa, aa)) != RST_OK) return s;
+      a0 = c->d_fgaa.p;
+      if ((s = proj_blocked(c, aa[0])) != RST_OK) return s;
+      HIPCHK(c, hipLaunchKernel(kapply, dim3(nblk), dim3(ls.threads), argsa, lds_apply, c->stream));
+      hipLaunchKernelGGL(rst::fg::k_fg_bsub, dim3(gv), dim3(256), 0, c->stream, S, B,
+                         (const long long*)c->d_trcols.p, Rv);
+    }
+    // pair scale: 1/||r|| (synthetic pairs), 1/||e|| (solver pairs, whose errors exceed their residuals
+    // by up to the condition number: every pair then weighs the same in the loss; the bias-free ReLU
+    // network is positively homogeneous, so a common scale of input and target changes nothing else)
+    const double2* Sv = from_solver ? (const double2*)Ev : (const double2*)Rv;
+    hipLaunchKernelGGL(rst::fg::k_fg_dots, dim3(nblk, 1), dim3(256), 0, c->stream, S, Sv, (long long)vlen, 1, Sv,
+                       (double2*)c->d_fgn2.p, ncolp);
     hipLaunchKernelGGL(rst::fg::k_fg_rsqrt, dim3((ncolp + 63) / 64), dim3(64), 0, c->stream,
                        (const double2*)c->d_fgn2.p, (double*)c->d_fginv.p, ncolp);
     hipLaunchKernelGGL(rst::fg::k_fg_scale, dim3(gv), dim3(256), 0, c->stream, S, Rv, (const double2*)Rv,
@@ -4277,7 +4341,8 @@ rst_status rst_precond_train(rst_ctx* c, const rst_train_opts* o, rst_train_stat
   HIPCHK(c, hipEventElapsedTime(&fms, e0, e1));
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  // restore the context's k
+  // restore the context's k (and options)
+  c->opts = opts0;
   c->ka = ka0;
   c->kb = kb0;
   if ((s = upload_k(c)) != RST_OK) return s;

@@ -60,7 +60,8 @@ class rst_eig_opts(C.Structure):
 
 class rst_train_opts(C.Structure):
     _fields_ = [("pairs", C.c_int), ("batch", C.c_int), ("lr", C.c_float), ("seed", C.c_uint64),
-                ("n_e", C.c_int), ("energies", C.c_void_p), ("n_k", C.c_int), ("kpts", C.c_void_p)]
+                ("n_e", C.c_int), ("energies", C.c_void_p), ("n_k", C.c_int), ("kpts", C.c_void_p),
+                ("source", C.c_int)]
 
 
 class rst_train_stats(C.Structure):
@@ -381,11 +382,11 @@ class Context:
                                               float(lr), C.byref(loss)))
         return loss.value
 
-    def rst_precond_train(self, energies, kpts, pairs, batch=8, lr=1e-3, seed=0):
+    def rst_precond_train(self, energies, kpts, pairs, batch=8, lr=1e-3, seed=0, source=0):
         e = np.ascontiguousarray(np.atleast_1d(energies), np.float64)
         k = np.ascontiguousarray(np.asarray(kpts, np.float64).reshape(-1, 2))
         o = rst_train_opts(int(pairs), int(batch), float(lr), int(seed), e.size, _ptr(e).value,
-                           k.shape[0], _ptr(k).value)
+                           k.shape[0], _ptr(k).value, int(source))
         st = rst_train_stats()
         self._chk(self.lib.rst_precond_train(self.h, C.byref(o), C.byref(st)))
         return st.as_dict()
