@@ -41,11 +41,9 @@ __global__ __launch_bounds__(256) void k_cg_dot(Shape S, const double2* U, const
     acc.x += a.x * b.x - ay * b.y;
     acc.y += a.x * b.y + ay * b.x;
   }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  if ((int)threadIdx.x < S.cw) {  // thread t met column t % cw only (256 is a multiple of cw)
-    double2 s = make_double2(0.0, 0.0);
-    for (int k = threadIdx.x; k < (int)blockDim.x; k += S.cw) s = fg::cadd(s, red[k]);
+  // thread t met column t % cw only (256 is a multiple of cw)
+  const double2 s = rst::col_reduce_c(red, S.cw, acc);
+  if ((int)threadIdx.x < S.cw) {
     const int c = blk * S.cw + threadIdx.x;
     if (c < ncolp) out[c] = s;
   }

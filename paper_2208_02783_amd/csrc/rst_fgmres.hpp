@@ -13,6 +13,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "rst_kernels.hpp"
+
 namespace rst {
 namespace fg {
 
@@ -55,11 +57,9 @@ __global__ __launch_bounds__(256) void k_fg_dots(Shape S, const double2* V, long
   const long long tot = S.n * S.cw;
   double2 acc = make_double2(0.0, 0.0);
   for (long long t = threadIdx.x; t < tot; t += blockDim.x) acc = cadd(acc, cmulc_(v[t], w[t]));
-  red[threadIdx.x] = acc;
-  __syncthreads();
+  // thread t met column t % cw only (256 is a multiple of cw)
+  const double2 s = rst::col_reduce_c(red, S.cw, acc);
   if ((int)threadIdx.x < S.cw) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int k = threadIdx.x; k < (int)blockDim.x; k += S.cw) s = cadd(s, red[k]);
     const int c = blk * S.cw + threadIdx.x;
     if (c < ncolp) out[(size_t)i * ncolp + c] = s;
   }

@@ -472,21 +472,51 @@ __device__ __forceinline__ void pacc_flush(const Proj& pj, const Lds<R>& L, int 
   for (int w = threadIdx.x; w < pj.nproj * cw; w += blockDim.x) dst[w] = L.pacc[w];
 }
 
-// Workgroup reduction of four per-thread doubles per column into out[k][c].
+// Workgroup reduction of four per-thread doubles per column into out[k][c]; thread t
+// holds column t % cw.  Within a wavefront a shuffle butterfly over lane offsets
+// 32, 16, ..., cw (each keeps the lane's column) leaves every lane with its
+// column's wave sum; lanes 0..cw-1 write those to LDS and threads (k, c) add the
+// waves in order (deterministic).  red: at least 4 * waves * cw doubles.
 __device__ __forceinline__ void col_reduce4(double* red, int cw, const double (&v)[4],
                                             double (*out)[CW_MAX]) {
-  const int tid = threadIdx.x, T = blockDim.x;
-  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  double s[4] = {v[0], v[1], v[2], v[3]};
+  for (int off = 32; off >= cw; off >>= 1) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) red[k * T + tid] = v[k];
+    for (int k = 0; k < 4; ++k) s[k] += __shfl_xor(s[k], off, 64);
+  }
+  __syncthreads();
+  if (lane < cw) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[(k * nw + wv) * cw + lane] = s[k];
+  }
   __syncthreads();
   if (tid < 4 * cw) {
     const int k = tid / cw, c = tid % cw;
-    double s = 0.0;
-    for (int i = c; i < T; i += cw) s += red[k * T + i];
-    out[k][c] = s;
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[(k * nw + w) * cw + c];
+    out[k][c] = t;
   }
   __syncthreads();
+}
+
+// The same for one complex value per thread over a 256-thread workgroup: returns the
+// column sum (valid in threads 0..cw-1).  red: 4 * cw double2.
+__device__ __forceinline__ double2 col_reduce_c(double2* red, int cw, double2 v) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  for (int off = 32; off >= cw; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  if (lane < cw) red[wv * cw + lane] = v;
+  __syncthreads();
+  double2 t = make_double2(0.0, 0.0);
+  if (tid < cw)
+    for (int w = 0; w < nw; ++w) {
+      t.x += red[w * cw + tid].x;
+      t.y += red[w * cw + tid].y;
+    }
+  return t;
 }
 
 }  // namespace rst
