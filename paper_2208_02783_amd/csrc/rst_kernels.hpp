@@ -159,6 +159,8 @@ struct Proj {
   const int* sc_pb;                // [n*SC_SLOTS] first projector of the slot's group, -1 if empty
   const double2* sc_eph;           // [n*SC_SLOTS] exp(+i k.R) of the slot's entry
   const double* sc_beta;           // [n*SC_SLOTS*nm] projector values of the slot (zero-padded)
+  const double* sc_w;              // [n*SC_SLOTS*(nm <= 9 ? 9 : 16)] beta_m E_{pb+m} of the slot, zero past
+                                   // the group (rows as wide as the many-column apply's projector bound)
   int has_overflow;                // points touched by more than SC_SLOTS entries exist
   const int* pe_offs;              // [n+1] overflow entries of each grid point
   const int2* pe;                  // (group, entry)

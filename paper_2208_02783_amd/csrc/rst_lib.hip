@@ -124,13 +124,13 @@ struct rst_ctx {
   // gather order: plane-major, each (plane, group) run padded to whole chunks
   std::vector<int> g_ent_p, g_src;  // in-plane point and source entry (-1: padding)
   std::vector<double> g_beta;
-  std::vector<double> sc_beta;
+  std::vector<double> sc_beta, sc_w;
   int has_overflow = 0;
   // device copies
   DevBuf d_v, d_gz, d_gl, d_gr, d_vz;  // d_vz: plane means of V (preconditioner reference)
   DevBuf d_pc_eps, d_pc_twa, d_pc_twb;
   DevBuf d_grp_pbase, d_grp_nm, d_ekb, d_beta, d_eph, d_ent_p, d_zc, d_chunks, d_zg, d_zgroups,
-      d_pe_offs, d_pe, d_sc_pb, d_sc_eph, d_sc_beta, d_g_ent_p, d_g_eph, d_g_beta;
+      d_pe_offs, d_pe, d_sc_pb, d_sc_eph, d_sc_beta, d_sc_w, d_g_ent_p, d_g_eph, d_g_beta;
   // batched projector gather (many-column apply): group entry ranges, entry grid indices, projections
   std::vector<int> grp_e0, grp_ne;
   DevBuf d_grp_e0, d_grp_ne, d_ent_gi, d_projP;
@@ -303,6 +303,7 @@ rst::Proj make_proj(const rst_ctx* c) {
   p.g_eph = (const double2*)c->d_g_eph.p;
   p.g_beta = (const double*)c->d_g_beta.p;
   p.sc_beta = (const double*)c->d_sc_beta.p;
+  p.sc_w = (const double*)c->d_sc_w.p;
   p.has_overflow = c->has_overflow;
   return p;
 }
@@ -336,22 +337,32 @@ rst_status proj_blocked(rst_ctx* c, const rst::ApplyArgs& A) {
   return RST_OK;
 }
 
-// k_apply_cols instance for a stencil radius (FD order 2..12), projector group size and precision.
-void* apply_cols_kernel(int rad, bool nm9, bool f32, bool cj) {
-#define RST_APPLY_PICK(R)                                                                          \
+// k_apply_cols instance for a stencil radius (FD order 2..12), projector group size and
+// precision; wide: the 64-bit addressed kernel for planes or projection arrays past the
+// buffer path's offsets.
+void* apply_cols_kernel(int rad, bool nm9, bool f32, bool cj, bool wide) {
+#define RST_APPLY_PICK(K, R)                                                                       \
   if (rad == R) {                                                                                  \
-    if (cj && !f32)                                                                                \
-      return nm9 ? (void*)rst::k_apply_cols<R, 9, double, true> : (void*)rst::k_apply_cols<R, 16, double, true>; \
+    if (cj && !f32) return nm9 ? (void*)rst::K<R, 9, double, true> : (void*)rst::K<R, 16, double, true>; \
     if (cj) return nullptr;                                                                        \
-    if (f32) return nm9 ? (void*)rst::k_apply_cols<R, 9, float> : (void*)rst::k_apply_cols<R, 16, float>; \
-    return nm9 ? (void*)rst::k_apply_cols<R, 9, double> : (void*)rst::k_apply_cols<R, 16, double>; \
+    if (f32) return nm9 ? (void*)rst::K<R, 9, float> : (void*)rst::K<R, 16, float>;                \
+    return nm9 ? (void*)rst::K<R, 9, double> : (void*)rst::K<R, 16, double>;                       \
   }
-  RST_APPLY_PICK(1)
-  RST_APPLY_PICK(2)
-  RST_APPLY_PICK(3)
-  RST_APPLY_PICK(4)
-  RST_APPLY_PICK(5)
-  RST_APPLY_PICK(6)
+  if (wide) {
+    RST_APPLY_PICK(k_apply_cols_wide, 1)
+    RST_APPLY_PICK(k_apply_cols_wide, 2)
+    RST_APPLY_PICK(k_apply_cols_wide, 3)
+    RST_APPLY_PICK(k_apply_cols_wide, 4)
+    RST_APPLY_PICK(k_apply_cols_wide, 5)
+    RST_APPLY_PICK(k_apply_cols_wide, 6)
+    return nullptr;
+  }
+  RST_APPLY_PICK(k_apply_cols, 1)
+  RST_APPLY_PICK(k_apply_cols, 2)
+  RST_APPLY_PICK(k_apply_cols, 3)
+  RST_APPLY_PICK(k_apply_cols, 4)
+  RST_APPLY_PICK(k_apply_cols, 5)
+  RST_APPLY_PICK(k_apply_cols, 6)
 #undef RST_APPLY_PICK
   return nullptr;
 }
@@ -418,7 +429,11 @@ rst_status apply_cols(rst_ctx* c, const void* x, void* y, int ncol, double energ
     A.P = projP;
   }
   if (ev) HIPCHK(c, hipEventRecord(ev[1], c->stream));
-  void* kern = apply_cols_kernel(c->rad, c->nm <= 9, f32, cfl != nullptr);
+  // the buffer path addresses a plane of rows and the projection array with 32-bit offsets
+  const long long esz = f32 ? 8 : 16;
+  const bool wide = (long long)P * ncol * esz > rst::APPLY_BUF_MAX ||
+                    (long long)c->nproj * ncol * 16 > rst::APPLY_BUF_MAX;
+  void* kern = apply_cols_kernel(c->rad, c->nm <= 9, f32, cfl != nullptr, wide);
   if (!kern) return fail(c, RST_EUNSUPPORTED, "no many-column apply for this FD order");
   {
     void* args[] = {&A};
@@ -554,6 +569,8 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
   c->sc_pb.assign((size_t)n * K, -1);
   c->sc_ent.assign((size_t)n * K, -1);
   c->sc_beta.assign((size_t)n * K * nm, 0.0);
+  const int wn = nm <= 9 ? 9 : 16;  // the many-column apply's compile-time projector bound
+  c->sc_w.assign((size_t)n * K * wn, 0.0);
   std::vector<int> used(n, 0);
   std::vector<int> cnt(n + 1, 0);
   std::vector<std::pair<long long, int2>> ovf;
@@ -565,6 +582,8 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
         c->sc_pb[si] = c->grp_pbase[gi];
         c->sc_ent[si] = e;
         for (int m = 0; m < nm; ++m) c->sc_beta[si * nm + m] = c->beta[(size_t)e * nm + m];
+        for (int m = 0; m < c->grp_nm[gi]; ++m)
+          c->sc_w[si * wn + m] = c->beta[(size_t)e * nm + m] * c->ekb[c->grp_pbase[gi] + m];
         used[i]++;
       } else {
         int2 v;
@@ -600,6 +619,7 @@ rst_status build_plan(rst_ctx* c, int nproj, const int32_t* offs, const int32_t*
   if ((s = upload(c, c->d_pe, c->pe)) != RST_OK) return s;
   if ((s = upload(c, c->d_sc_pb, c->sc_pb)) != RST_OK) return s;
   if ((s = upload(c, c->d_sc_beta, c->sc_beta)) != RST_OK) return s;
+  if ((s = upload(c, c->d_sc_w, c->sc_w)) != RST_OK) return s;
   return RST_OK;
 }
 

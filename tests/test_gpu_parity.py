@@ -104,6 +104,34 @@ def test_apply_wide_plane_strips_matches_oracle(prec):
     _apply_vs_oracle(torch, ctx, p, k, 0.377, x, xd, prec)
 
 
+def test_apply_plane_beyond_32bit_offsets_matches_oracle():
+    """A launch whose plane of rows exceeds 2^31 bytes (16 points x 8,388,645
+    columns x 16 B, 12.9 GB per vector; the last 64-column chunk ragged) runs
+    the 64-bit addressed kernel instead of the buffer-load one; sampled columns,
+    first, middle and ragged last chunk, against the oracle."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(37)
+    p = hp.random_problem(rng, na=4, nb=4, nz=6, order=4, nproj=2, ramp=2)
+    k = (0.23, -0.61)
+    ncol = (1 << 31) // (p.na * p.nb * 16) + 37
+    assert p.na * p.nb * ncol * 16 > (1 << 31) - 1
+    ctx = make_ctx(torch, p, k)
+    g = torch.Generator(device="cuda").manual_seed(41)
+    xd = torch.randn((p.n, ncol), dtype=torch.complex128, device="cuda", generator=g)
+    _say("apply past 32-bit plane offsets: ncol", ncol, "GB per vector", xd.numel() * 16 / 1e9)
+    yd = rst.apply_h(ctx, 0.517, xd)
+    torch.cuda.synchronize()
+    cols = np.array([0, 1, 63, 64, 4_194_301, ncol - 38, ncol - 37, ncol - 20, ncol - 1])
+    ci = torch.from_numpy(cols).to("cuda")
+    xs = xd.index_select(1, ci).cpu().numpy()
+    ys = yd.index_select(1, ci).cpu().numpy()
+    del xd, yd
+    torch.cuda.empty_cache()
+    ref = oracle.apply_system(p, k, 0.517, xs)
+    err = np.max(np.abs(ys - ref)) / np.max(np.abs(ref))
+    assert err <= APPLY_BAR["fp64"], err
+
+
 def test_apply_precision_argument():
     """An unknown precision is refused; both precisions accept zero columns."""
     torch = torch_cuda()
