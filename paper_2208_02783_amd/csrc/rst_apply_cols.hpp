@@ -118,11 +118,12 @@ __device__ __forceinline__ void apply_place(const ColApplyArgs& A, long long b, 
   ia = s0 * W + r0 % w0;
 }
 
-// Raw buffer loads: the descriptor holds a (uniform) base address, the lane
-// adds its column offset (VGPR) and the row offset comes from an SGPR, so a row
-// request costs no address arithmetic.  Descriptor word 3 for gfx9-family
-// chips (32-bit data format, no swizzle); the record count is left at its
-// maximum, every offset being in range by construction.
+// Raw buffer loads: the descriptor holds a (uniform) base address and the
+// request adds a 32-bit VGPR offset (the row's and the lane's column offset,
+// fixed for the wave) and an SGPR offset, so a row request costs no address
+// arithmetic.  Descriptor word 3 for gfx9-family chips (32-bit data format, no
+// swizzle); the record count is left at its maximum, every offset being in range
+// by construction.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
 }
@@ -158,8 +159,8 @@ __device__ __forceinline__ int2 sld(const int2* p, long long i) {
 }
 
 // Largest byte offset the buffer path addresses: a lateral plane of rows and the
-// projection array must each stay below 2^31 bytes (one SGPR offset plus the
-// lane's column offset); larger launches take k_apply_cols_wide.
+// projection array must each stay below 2^31 bytes (offsets from one descriptor
+// base are 32-bit); larger launches take k_apply_cols_wide.
 constexpr long long APPLY_BUF_MAX = 0x7fffffffLL;
 
 // CJ: the instance honours the conjugate-space flags (cfl); the others ignore them, so the hot
