@@ -166,9 +166,10 @@ constexpr long long APPLY_BUF_MAX = 0x7fffffffLL;
 // CJ: the instance honours the conjugate-space flags (cfl); the others ignore them, so the hot
 // instances carry no extra work.
 //
-// Every lane loads (columns past ncol read the last column; masked columns are
-// computed and not stored), so the row requests of a plane are one unconditional
-// group.  The 4M lateral neighbour offsets and their wrap flags depend only on
+// Every lane of a wave with at least one column to apply loads (columns past
+// ncol read the last column; masked columns are computed and not stored), so the
+// row requests of a plane are one unconditional group; a wave whose 64 columns are
+// all masked returns at once.  The 4M lateral neighbour offsets and their wrap flags depend only on
 // the wave's point and are computed once; per plane the kernel advances one
 // descriptor base.  The point's projector slot is read one plane ahead, so the
 // projection rows are requested together with the stencil rows.
@@ -189,6 +190,7 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
   const int c = chunk * 64 + (int)threadIdx.x;
   const int cc = c < ncol ? c : ncol - 1;
   const bool ok = c < ncol && (A.mask == nullptr || A.mask[c] != 0);
+  if (__builtin_amdgcn_ballot_w64(ok) == 0) return;  // no column of this chunk to apply
   const double ec = A.ecol != nullptr ? A.ecol[cc] : A.energy;
   const F ysg = CJ && A.cfl != nullptr && A.cfl[cc] != 0 ? (F)-1 : (F)1;
   const V2 pha{(F)g.pha_x, (F)g.pha_y}, phac{(F)g.pha_x, (F)-g.pha_y};
