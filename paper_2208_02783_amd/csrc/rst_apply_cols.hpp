@@ -118,14 +118,15 @@ __device__ __forceinline__ void apply_place(const ColApplyArgs& A, long long b, 
   ia = s0 * W + r0 % w0;
 }
 
-// Raw buffer loads: the descriptor holds a (uniform) base address and the
-// request adds a 32-bit VGPR offset (the row's and the lane's column offset,
-// fixed for the wave) and an SGPR offset, so a row request costs no address
-// arithmetic.  Descriptor word 3 for gfx9-family chips (32-bit data format, no
-// swizzle); the record count is left at its maximum, every offset being in range
-// by construction.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
+// Raw buffer loads: the descriptor holds a (uniform) base address and a record
+// count in bytes, and the request adds a 32-bit VGPR offset (the row's and the
+// lane's column offset, fixed for the wave) and an SGPR offset, so a row request
+// costs no address arithmetic.  A lane whose VGPR offset is at or past the record
+// count reads zero without a memory access (offset = the record count itself,
+// so the address would be the first byte past the described range).  Descriptor
+// word 3 for gfx9-family chips (32-bit data format, no swizzle).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
 }
 template <class V2>
 __device__ __forceinline__ V2 buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff);
@@ -158,6 +159,9 @@ __device__ __forceinline__ int2 sld(const int2* p, long long i) {
   return make_int2(sld((const int*)p, 2 * i), sld((const int*)p, 2 * i + 1));
 }
 
+// Bytes of the projection array P (nproj x ncol complex128).
+__device__ __forceinline__ int pj_bytes(const Proj& pj, int ncol) { return pj.nproj * ncol * 16; }
+
 // Largest byte offset the buffer path addresses: a lateral plane of rows and the
 // projection array must each stay below 2^31 bytes (offsets from one descriptor
 // base are 32-bit); larger launches take k_apply_cols_wide.
@@ -166,10 +170,10 @@ constexpr long long APPLY_BUF_MAX = 0x7fffffffLL;
 // CJ: the instance honours the conjugate-space flags (cfl); the others ignore them, so the hot
 // instances carry no extra work.
 //
-// Every lane of a wave with at least one column to apply loads (columns past
-// ncol read the last column; masked columns are computed and not stored), so the
-// row requests of a plane are one unconditional group; a wave whose 64 columns are
-// all masked returns at once.  The 4M lateral neighbour offsets and their wrap flags depend only on
+// The row requests of a plane are one unconditional group: a masked lane (or one
+// past ncol, which uses the last column's addresses) has its stencil row offsets
+// set to the record count, so it reads zeros without memory traffic, and stores
+// nothing; a wave whose 64 columns are all masked returns at once.  The 4M lateral neighbour offsets and their wrap flags depend only on
 // the wave's point and are computed once; per plane the kernel advances one
 // descriptor base.  The point's projector slot is read one plane ahead, so the
 // projection rows are requested together with the stencil rows.
@@ -201,6 +205,8 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
   // offsets of their rows within a plane, and which of them wrap
   const int rowb = ncol * (int)ESZ;
   const unsigned voff = (unsigned)cc * ESZ;
+  const int plane_bytes = P * rowb;                             // at most APPLY_BUF_MAX (host check)
+  const unsigned oob = (unsigned)plane_bytes;
   unsigned off[4 * RAD];  // lane byte offset of each neighbour row within a plane
   unsigned wrap = 0;
 #pragma unroll
@@ -211,12 +217,13 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
     if (am < 0) { am += na; wrap |= 2u << k; }
     if (bp >= nb) { bp -= nb; wrap |= 4u << k; }
     if (bm < 0) { bm += nb; wrap |= 8u << k; }
-    off[k] = (unsigned)((ib * na + ap) * rowb) + voff;
-    off[k + 1] = (unsigned)((ib * na + am) * rowb) + voff;
-    off[k + 2] = (unsigned)((bp * na + ia) * rowb) + voff;
-    off[k + 3] = (unsigned)((bm * na + ia) * rowb) + voff;
+    // a masked lane's requests fall past the record count: zeros, no memory traffic
+    off[k] = ok ? (unsigned)((ib * na + ap) * rowb) + voff : oob;
+    off[k + 1] = ok ? (unsigned)((ib * na + am) * rowb) + voff : oob;
+    off[k + 2] = ok ? (unsigned)((bp * na + ia) * rowb) + voff : oob;
+    off[k + 3] = ok ? (unsigned)((bm * na + ia) * rowb) + voff : oob;
   }
-  const unsigned voffp = (unsigned)cc * (unsigned)sizeof(double2);
+  const unsigned voffp = (unsigned)cc * (unsigned)sizeof(double2);  // projection rows: every lane reads
   const size_t plane = (size_t)P * ncol;  // elements per plane
 
   V2 q[NQ];  // q[RAD + d] = row of plane z + d
@@ -229,7 +236,7 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
   }
 
   const Proj& pj = A.pj;
-  const __amdgpu_buffer_rsrc_t rP = buf_rsrc(A.P);
+  const __amdgpu_buffer_rsrc_t rP = buf_rsrc(A.P, pj_bytes(pj, ncol));
   const char* xz = (const char*)A.x + (size_t)z0 * plane * ESZ;
   const V2* xn = X + ((size_t)(z0 + RAD + 1) * P + p) * ncol + cc;  // z-queue row of plane z + M + 1
   V2* yp = Y + ((size_t)z0 * P + p) * ncol + cc;
@@ -239,7 +246,7 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
     const long long gi = (long long)z * P + p;
     const int pb = pbn;
     if (pj.nproj) pbn = z + 1 < z1 ? sld(pj.sc_pb, gi + P) : -1;
-    const __amdgpu_buffer_rsrc_t rx = buf_rsrc(xz);
+    const __amdgpu_buffer_rsrc_t rx = buf_rsrc(xz, plane_bytes);
     V2 xl[4 * RAD];
 #pragma unroll
     for (int k = 0; k < 4 * RAD; ++k) xl[k] = buf_ld<V2>(rx, off[k], 0);
