@@ -115,6 +115,9 @@ def test_apply_plane_beyond_32bit_offsets_matches_oracle():
     k = (0.23, -0.61)
     ncol = (1 << 31) // (p.na * p.nb * 16) + 37
     assert p.na * p.nb * ncol * 16 > (1 << 31) - 1
+    need = 2 * p.n * ncol * 16 + p.proj.nproj * ncol * 16
+    if torch.cuda.mem_get_info()[0] < need + (4 << 30):
+        pytest.skip(f"needs {need / 1e9:.1f} GB of free device memory")
     ctx = make_ctx(torch, p, k)
     g = torch.Generator(device="cuda").manual_seed(41)
     xd = torch.randn((p.n, ncol), dtype=torch.complex128, device="cuda", generator=g)
