@@ -324,7 +324,10 @@ __global__ __launch_bounds__(64) void k_apply_cols(ColApplyArgs A) {
     y.x -= (F)sx;
     y.y -= (F)sy;
     if (CJ) y.y *= ysg;
-    if (ok) *yp = y;
+    if (ok) {  // streaming store: the output row is not read again by this launch
+      __builtin_nontemporal_store(y.x, &yp->x);
+      __builtin_nontemporal_store(y.y, &yp->y);
+    }
     if (CJ) nxt.y *= ysg;
 #pragma unroll
     for (int s = 0; s < NQ - 1; ++s) q[s] = q[s + 1];
