@@ -78,14 +78,23 @@ __device__ __forceinline__ double2 c_div(double2 a, double2 b) {
 __device__ __forceinline__ bool c_finite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
 
 // Vector storage: complex128 (double2) or, for the inner solves of the mixed-precision
-// refinement, complex64 (float2); arithmetic is FP64 either way.
-__device__ __forceinline__ double2 vld(const double2* p, size_t i) { return p[i]; }
-__device__ __forceinline__ double2 vld(const float2* p, size_t i) {
-  const float2 v = p[i];
-  return make_double2(v.x, v.y);
+// refinement, complex64 (float2); arithmetic is FP64 either way.  The Krylov vectors are
+// streamed once per kernel, so their loads and stores are non-temporal (the two halves of
+// an element merge into one 16-byte or 8-byte access).
+__device__ __forceinline__ double2 vld(const double2* p, size_t i) {
+  return make_double2(__builtin_nontemporal_load(&p[i].x), __builtin_nontemporal_load(&p[i].y));
 }
-__device__ __forceinline__ void vst(double2* p, size_t i, double2 v) { p[i] = v; }
-__device__ __forceinline__ void vst(float2* p, size_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ double2 vld(const float2* p, size_t i) {
+  return make_double2(__builtin_nontemporal_load(&p[i].x), __builtin_nontemporal_load(&p[i].y));
+}
+__device__ __forceinline__ void vst(double2* p, size_t i, double2 v) {
+  __builtin_nontemporal_store(v.x, &p[i].x);
+  __builtin_nontemporal_store(v.y, &p[i].y);
+}
+__device__ __forceinline__ void vst(float2* p, size_t i, double2 v) {
+  __builtin_nontemporal_store((float)v.x, &p[i].x);
+  __builtin_nontemporal_store((float)v.y, &p[i].y);
+}
 
 __device__ __forceinline__ double2 cflip(double2 a, double sg) { return make_double2(a.x, sg * a.y); }
 
