@@ -4462,7 +4462,7 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
   std::vector<int> done(n_e, 0);
   std::vector<double> Tq(n_e, 0.0), tail(n_e, 0.0);
   const int smax = std::min(o->max_probes, nR);
-  int sprobe = std::min(o->probes, nR);  // probes in the basis after this round
+  int sprobe = std::min(o->probes, nR);  // probes in the basis after this doubling step
   const int hp = o->heldout;
   uint64_t seed = o->seed;
   const double ka0 = c->ka, kb0 = c->kb;
@@ -4485,7 +4485,7 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
         idx.push_back(i);
       }
     const int ne = (int)Eo.size();
-    const int snew = sprobe - s_prev;  // probes added this round
+    const int snew = sprobe - s_prev;  // probes added by this doubling step
     const int sc = snew + hp;
     // (1) new probes and held-out probes, forward solves
     if ((s = ensure(c, c->d_lrB, (size_t)n * sc * 16)) != RST_OK) return s;
@@ -4539,7 +4539,7 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
                          (const double2*)c->d_lrW.p, sprobe, nL, ne, dst);
       HIPCHK(c, hipGetLastError());
     }
-    // (3) tail of the held-out probes (this round's last hp columns): ||y||^2 - ||Q^H y||^2
+    // (3) tail of the held-out probes (the last hp columns of this doubling step): ||y||^2 - ||Q^H y||^2
     const double2* Yh = Ynew + (long long)snew * nL;
     const long long sy = (long long)sc * nL;
     std::vector<double2> cq((size_t)ne * sprobe * hp), yy((size_t)ne * hp * hp);
@@ -4550,7 +4550,7 @@ rst_status rst_transmission_lowrank(rst_ctx* c, int n_e, const double* E, const 
                        (double2*)c->d_lrG.p);
     HIPCHK(c, hipMemcpyAsync(yy.data(), c->d_lrG.p, yy.size() * 16, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    std::vector<int> fin;  // positions (in this round's order) of the energies that end this round
+    std::vector<int> fin;  // positions (in this doubling step's order) of the energies that end in this doubling step
     for (int e = 0; e < ne; ++e) {
       double t = 0.0;
       for (int b = 0; b < hp; ++b) {
